@@ -1,0 +1,156 @@
+"""Pins of the oracle's Nesterov step, perturbation, best-of selection and placer loop."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+from helpers import GOLDEN, cells_only
+from paper_2402_18311_amd import netgen
+
+
+def test_splitmix64_published_vector(orc):
+    with open(f"{GOLDEN}/splitmix64_seed1234567.txt") as f:
+        want = [int(l) for l in f if l.strip() and not l.startswith("#")]
+    assert [orc.splitmix(1234567, i) for i in range(5)] == want
+
+
+def _quad_setup(orc, n=50, seed=0):
+    # cells without pins: the preconditioner is max(1, 0 + 0 * area) = 1 at lambda = 0
+    rng = np.random.default_rng(seed)
+    W = 100.0
+    nl = cells_only(np.ones(n), np.ones(n), W, W, 8, rng.uniform(10, 80, n), rng.uniform(10, 80, n))
+    return orc.Oracle(nl), nl, np.concatenate([rng.uniform(20, 70, n), rng.uniform(20, 70, n)])
+
+
+def test_nesterov_first_step_and_bb_exact_on_quadratic(orc):
+    # f = c/2 |x - t|^2: g = c (v - t).  Step 0 moves by alpha_0 = 0.1 wb / max|g| with no
+    # momentum ((a_0 - 1)/a_1 = 0).  Step 1's Barzilai-Borwein length is |dv| / |dg| = 1/c,
+    # so u_2 = v_1 - (1/c) c (v_1 - t) = t exactly (the textbook property of BB on a
+    # quadratic with a scalar Hessian).
+    o, nl, t = _quad_setup(orc)
+    c = 0.37
+    st = o.new_state(nl.x0, nl.y0)
+    v0 = st["v"].copy()
+    g = c * (st["v"] - t)
+    o.nesterov_step(0.0, g, st)
+    a1 = (1 + math.sqrt(5)) / 2
+    alpha0 = 0.1 * nl.bin_w / np.abs(g).max()
+    assert st["k"] == 1 and st["a"] == pytest.approx(a1) and st["alpha"] == pytest.approx(alpha0)
+    assert np.allclose(st["u"], v0 - alpha0 * g, rtol=1e-15, atol=1e-12)
+    assert np.allclose(st["v"], st["u"])  # no momentum on the first step
+    assert np.array_equal(st["v_prev"], v0) and np.allclose(st["gp_prev"], g)
+    u1 = st["u"].copy()
+    g = c * (st["v"] - t)
+    o.nesterov_step(0.0, g, st)
+    assert st["alpha"] == pytest.approx(1 / c, rel=1e-12)
+    assert np.allclose(st["u"], t, atol=1e-10)
+    a2 = (1 + math.sqrt(4 * a1 * a1 + 1)) / 2
+    assert np.allclose(st["v"], t + (a1 - 1) / a2 * (t - u1), atol=1e-10)
+
+
+def test_nesterov_preconditioner_and_clamp(orc):
+    # a cell with 3 pins and area 2: P = max(1, 3 + lambda * 2); at lambda = 1, P = 5
+    nl = cells_only([2.0, 1.0], [1.0, 1.0], 16.0, 16.0, 4, [5.0, 1.0], [5.0, 0.5],
+                    nets=[[(0, 0, 0), (1, 0, 0)], [(0, 1, 0), (1, 0, 0)], [(0, 0, 0), (1, 0, 0)]])
+    o = orc.Oracle(nl)
+    st = o.new_state(nl.x0, nl.y0)
+    g = np.array([10.0, 2.0, 5.0, 40.0])  # gx0, gx1, gy0, gy1
+    o.nesterov_step(1.0, g, st)
+    gt = g / np.array([5.0, 4.0, 5.0, 4.0])  # cell 1: 3 pins + 1 * area 1
+    alpha = 0.1 * 4.0 / np.abs(gt).max()
+    assert st["alpha"] == pytest.approx(alpha)
+    want = np.array([5.0, 1.0, 5.0, 0.5]) - alpha * gt
+    want = np.clip(want, 0, [14.0, 15.0, 15.0, 15.0])
+    assert np.allclose(st["u"], want)
+    # near the walls, the first step (0.1 bin = 0.4 here) is clamped into the die
+    st = o.new_state(np.array([13.9, 0.1]), np.array([14.8, 0.2]))
+    o.nesterov_step(0.0, np.array([-1.0, 1.0, -1.0, 1.0]), st)
+    assert np.array_equal(st["u"], [14.0, 0.0, 15.0, 0.0])
+    assert np.array_equal(st["v"], [14.0, 0.0, 15.0, 0.0])
+
+
+@pytest.fixture(scope="module")
+def tiny(orc):
+    nl = netgen.make_netlist("tiny", 0)
+    return nl, orc.Oracle(nl)
+
+
+def test_perturb_selection_is_m_smallest_keys(orc, tiny):
+    nl, o = tiny
+    for frac, seed in [(0.5, 7), (0.05, 123), (0.0, 1), (1.0, 2), (0.3333, 2**63 + 5)]:
+        x, y, idx = o.perturb(nl.x0, nl.y0, orc.GAUSS, frac, 8.0, seed)
+        m = int(math.floor(frac * nl.n_movable + 0.5))
+        keys = np.array([orc.splitmix(seed, i) for i in range(nl.n_movable)], dtype=np.uint64)
+        order = np.lexsort((np.arange(nl.n_movable), keys))  # by key, then index
+        assert len(idx) == m
+        assert np.array_equal(idx, np.sort(order[:m]))
+        moved = (x != nl.x0) | (y != nl.y0)
+        assert not moved[np.setdiff1d(np.arange(nl.n_movable), idx)].any()
+    # deterministic by seed, different across seeds
+    a = o.perturb(nl.x0, nl.y0, orc.GAUSS, 0.5, 8.0, 9)
+    b = o.perturb(nl.x0, nl.y0, orc.GAUSS, 0.5, 8.0, 9)
+    c = o.perturb(nl.x0, nl.y0, orc.GAUSS, 0.5, 8.0, 10)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    assert not np.array_equal(a[2], c[2])
+
+
+def test_gauss_displacements_are_normal(orc):
+    n = 100_000
+    W = 1e6
+    nl = cells_only(np.ones(n), np.ones(n), W, W, 1024, np.full(n, W / 2), np.full(n, W / 2))
+    o = orc.Oracle(nl)
+    x, y, idx = o.perturb(nl.x0, nl.y0, orc.GAUSS, 1.0, 8.0, 42)
+    sigma = 8.0 * nl.bin_w
+    for d in ((x - nl.x0) / sigma, (y - nl.y0) / sigma):
+        assert scipy.stats.kstest(d, "norm").pvalue > 0.01
+    r = np.corrcoef((x - nl.x0), (y - nl.y0))[0, 1]
+    assert abs(r) < 0.02
+
+
+def test_shuffle_permutes_centres(orc):
+    for m in [1, 2, 3, 5, 100, 1000, 4097]:
+        p = [orc.shuffle_perm(j, m, 77) for j in range(m)]
+        assert sorted(p) == list(range(m))
+    n = 2000
+    rng = np.random.default_rng(3)
+    W = 200.0
+    snap = lambda v: np.round(v * 256) / 256  # centre +- w/2 is then exact
+    nl = cells_only(np.full(n, 2.0), np.ones(n), W, W, 64, snap(rng.uniform(0, W - 2, n)),
+                    snap(rng.uniform(0, W - 1, n)))
+    o = orc.Oracle(nl)
+    x, y, idx = o.perturb(nl.x0, nl.y0, orc.SHUFFLE, 0.5, 0.0, 11)
+    assert len(idx) == 1000
+    before = sorted(zip(nl.x0[idx], nl.y0[idx]))
+    after = sorted(zip(x[idx], y[idx]))
+    assert before == after  # equal widths: the multiset of locations is preserved exactly
+    assert np.mean(x[idx] != nl.x0[idx]) > 0.99
+    rest = np.setdiff1d(np.arange(n), idx)
+    assert np.array_equal(x[rest], nl.x0[rest])
+
+
+def test_uniform_restart_covers_die(orc, tiny):
+    nl, o = tiny
+    x, y, idx = o.perturb(nl.x0, nl.y0, orc.UNIFORM, 0.0, 0.0, 5)
+    assert len(idx) == nl.n_movable
+    w = nl.cell_w[: nl.n_movable]
+    assert np.all(x >= 0) and np.all(x <= nl.W - w)
+    assert scipy.stats.kstest(x / (nl.W - w), "uniform").pvalue > 0.01
+
+
+def test_argmin_ties_to_lowest(orc):
+    assert orc.argmin_i64([5, 3, 3, 9]) == 1
+    assert orc.argmin_i64([2]) == 0
+    v = np.random.default_rng(0).integers(0, 5, 100)
+    assert orc.argmin_i64(v) == int(np.argmin(v))
+
+
+def test_placer_reduces_hpwl_and_spreads(orc, tiny):
+    nl, o = tiny
+    x, y, tr = o.place(nl.x0, nl.y0, 200, 4 * nl.bin_w, 1e-4, 4.0)
+    h0 = o.hpwl_q(nl.x0, nl.y0)
+    assert tr["hpwl_q"][-1] == o.hpwl_q(x, y)
+    assert tr["hpwl_q"][-1] < 0.4 * h0
+    assert tr["overflow"][-1] <= 0.10  # the density constraint D(s) <= eps of Eq. 1
+    w = nl.cell_w[: nl.n_movable]
+    assert np.all(x >= 0) and np.all(x <= nl.W - w)
