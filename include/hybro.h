@@ -1,0 +1,177 @@
+/*
+ * libhybro -- the data-parallel hot path of the Hybro hybrid global placer on one AMD
+ * Instinct MI355X (gfx950), as a C ABI.
+ *
+ * Paper: "Escaping Local Optima in Global Placement" (Hybro).  The placer minimises the
+ * penalised objective of Eq. 2, sum_e WL_e(s) + lambda * D(s), with WL_e the weighted-average
+ * wirelength of Eq. 3 and D the density term, by repeated gradient steps (Sec. 3.1); Hybro
+ * (Alg. 1) perturbs the result (Sec. 4.2) and re-runs the placer, keeping the solution with
+ * the smallest HPWL (Eq. 1).  D, the optimiser and the lambda schedule are only named by the
+ * paper; this library uses the ePlace electrostatic system the paper builds on: an integer
+ * charge map on a bin grid, a cosine-basis Poisson solve, field forces, and a preconditioned
+ * Nesterov method with a Barzilai-Borwein step.
+ *
+ * Conventions
+ *   - Cells [0, n_movable) are movable, [n_movable, n_cells) fixed.  Positions are lower-left
+ *     corners on the die [0, W] x [0, H] (xl = yl = 0).  Pin p of net e sits at the cell's
+ *     position plus (pin_ox[p], pin_oy[p]).
+ *   - A context computes in FP32 or FP64 ("precision").  Position/gradient arrays are of
+ *     that type ("real" below).  Reductions are accumulated in FP64; HPWL, the density map
+ *     and perturbation indices are integers and therefore exact and run-to-run identical.
+ *   - The library never allocates device memory: the caller allocates the byte sizes that
+ *     hp_netlist_bytes / hp_slot_bytes return (e.g. as torch uint8 tensors) and lends them
+ *     until hp_slot_free / hp_destroy.  Buffers must be 256-byte aligned.
+ *   - Every call enqueues on the context's HIP stream.  Calls that return values to host
+ *     memory synchronise that stream; calls whose outputs stay on the device do not.
+ *   - Errors: a negative return code; hp_last_error gives a message (per thread, valid until
+ *     that thread's next call).  On error nothing has been written to outputs.
+ *   - A "slot" is one placement instance (its positions, optimiser state and scratch) on a
+ *     loaded netlist.  Calls taking a slot list process all of them in one set of launches;
+ *     all slots of one call must belong to the same netlist.
+ */
+#ifndef HYBRO_H
+#define HYBRO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp_ctx hp_ctx;
+
+enum {
+    HP_OK = 0,
+    HP_EINVAL = -1,   /* bad argument or netlist */
+    HP_ENOMEM = -2,   /* a lent buffer is too small */
+    HP_EDEVICE = -3,  /* a HIP call failed */
+    HP_ESTATE = -4,   /* unknown slot / netlist, or slots of different netlists */
+    HP_ENOTIMPL = -5
+};
+
+/* Die and bin grid.  mx, my: number of bins, powers of two in [8, 4096]; the bin width W/mx
+ * and height H/my must be multiples of 2^-12 (so bin edges are exact in the 2^-12 integer
+ * coordinates of the density map).  target_density: the rho_t of the overflow measure.
+ * stretch: 1 spreads a small cell's charge over at least sqrt(2) bins per side (ePlace local
+ * smoothing), 0 uses the cell's own rectangle.  fd5: 1 uses the 5-point Laplacian's
+ * eigenvalues in the Poisson solve instead of the continuous ones. */
+typedef struct {
+    double W, H;
+    int32_t mx, my;
+    double target_density;
+    int32_t stretch;
+    int32_t fd5;
+} hp_die;
+
+typedef struct {
+    int32_t n_cells, n_movable, n_nets, n_pins;
+} hp_shape;
+
+/* precision: 32 or 64.  hip_stream: a hipStream_t (NULL = the null stream). */
+int hp_create(hp_ctx **out, int device, void *hip_stream, int precision);
+int hp_destroy(hp_ctx *ctx);
+const char *hp_last_error(void);
+
+/* Sizes of the device buffers the caller lends (bytes, upper bounds from the shape). */
+size_t hp_netlist_bytes(const hp_ctx *ctx, const hp_shape *shape, const hp_die *die);
+size_t hp_slot_bytes(const hp_ctx *ctx, const hp_shape *shape, const hp_die *die);
+
+/* Netlist N = (V, E) of Sec. 3 as a net -> pin CSR.  Host arrays are read during the call
+ * and not kept.  cell_w/cell_h [n_cells] (> 0 for movable cells, >= 0 for fixed; zero-area
+ * fixed cells are pads); fixed_x/fixed_y [n_cells - n_movable] lower-left of fixed cells;
+ * net_start [n_nets + 1] non-decreasing, net_start[0] = 0, net_start[n_nets] = n_pins;
+ * pin_cell [n_pins] in [0, n_cells); pin_ox/pin_oy [n_pins]; net_weight [n_nets] or NULL
+ * (all 1).  Nets with fewer than two pins add nothing to Eq. 1 or Eq. 3.  Validates
+ * everything above (HP_EINVAL) and dev_bytes (HP_ENOMEM).  Synchronises the stream. */
+int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die,
+                        const double *cell_w, const double *cell_h,
+                        const double *fixed_x, const double *fixed_y,
+                        const int32_t *net_start, const int32_t *pin_cell,
+                        const double *pin_ox, const double *pin_oy,
+                        const double *net_weight, void *dev_buf, size_t dev_bytes,
+                        int32_t *out_netlist);
+
+/* A placement instance on a netlist, in a lent buffer of hp_slot_bytes bytes. */
+int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
+                  int32_t *out_slot);
+int hp_slot_free(hp_ctx *ctx, int32_t slot);
+
+/* Set the movable cells' positions (real [n_movable] each; host or device memory) and
+ * restart the optimiser there: u = v = v_prev = (x, y), k = 0, a = 1, lambda re-derived at
+ * the next evaluation.  hp_get_positions copies out the major solution u. */
+int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, int on_device);
+int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device);
+
+/* lambda schedule of Eq. 2 ("small at the beginning", Sec. 3): at the first evaluation after
+ * hp_set_positions / hp_perturb, lambda_0 = lambda0_scale * |grad WL|_1 / |grad N|_1; every
+ * Nesterov step multiplies it by 10^(decades / total_iters).  Defaults: 1e-4, 4, 1000. */
+int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double decades,
+                    int32_t total_iters);
+
+/* Objective of Eq. 2 and its gradient at the slots' reference points v:
+ *   wl = sum_e w_e WL_e (Eq. 3, both axes), energy = electrostatic energy N of the charge
+ *   map, overflow = sum_b max(0, movable charge - target * free area) / total movable charge
+ *   (the D(s) <= eps measure of Eq. 1), gradient = grad WL + lambda * grad N over movable
+ *   cells.  gamma: the smoothing length of Eq. 3 (same units as positions).  lambda >= 0 is
+ *   used as given; lambda < 0 uses each slot's scheduled lambda.  grad_mode 0: field force
+ *   (the only mode on the device; 1 returns HP_ENOTIMPL).  keep_maps 1 keeps the charge,
+ *   potential and field maps for hp_get_map.  wl/energy/overflow: host double [n_slots] or
+ *   NULL (then nothing is synchronised).  grad_x/grad_y: device real [n_slots][n_movable] or
+ *   NULL (the gradient always stays in the slot for hp_nesterov_step). */
+typedef struct {
+    double gamma;
+    double lambda;
+    int32_t grad_mode;
+    int32_t keep_maps;
+} hp_eval_params;
+int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n_slots,
+                           const hp_eval_params *p, double *wl, double *energy,
+                           double *overflow, void *grad_x, void *grad_y);
+
+/* One preconditioned Nesterov step per slot from the gradient of the last evaluation:
+ * P_i = max(1, pins_i + lambda area_i), g~ = g / P, step alpha_0 = 0.1 bin / max|g~| then
+ * Barzilai-Borwein |v - v_prev| / |g~ - g~_prev|, u' = clamp(v - alpha g~),
+ * a' = (1 + sqrt(4 a^2 + 1)) / 2, v' = clamp(u' + (a - 1)/a' (u' - u)).  Device only. */
+int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n_slots);
+
+/* Perturbation of Alg. 1 / Sec. 4.2 on slot's major solution u, which also restarts the
+ * optimiser there.  mode HP_PERTURB_GAUSS: the round(fraction * n_movable) cells with the
+ * smallest SplitMix64 keys move by a Gaussian of sigma_bins bins per axis; SHUFFLE: those
+ * cells exchange centres by a keyed permutation ("Shuffle (all)"); UNIFORM: every movable
+ * cell is redrawn uniformly (random restart).  Moved cells are clamped into the die.
+ * out_idx: host int32 [count] of moved cells in ascending order, or NULL; out_count: host or
+ * NULL.  Either output synchronises. */
+enum { HP_PERTURB_GAUSS = 0, HP_PERTURB_SHUFFLE = 1, HP_PERTURB_UNIFORM = 2 };
+int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins,
+               uint64_t seed, int32_t *out_idx, int32_t *out_count);
+
+/* Exact HPWL (Eq. 1) of the slots' major solutions u on pin coordinates quantized to 2^-16:
+ * out_q (host int64 [n_slots], units of 2^-16) and/or out (host double) or both NULL (the
+ * value stays in the slot for hp_select_best). */
+int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, int64_t *out_q, double *out);
+
+/* Best solution of Alg. 1: among the slots' last hp_hpwl values (and the incumbent's, if
+ * incumbent >= 0 and it has one), the smallest wins, ties to the lowest list position and
+ * then to the incumbent; the winner's u is copied into the incumbent's u and v (incumbent
+ * restarts there).  out_best: host, list position of the winner or -1 if the incumbent
+ * stayed; NULL keeps everything on the device. */
+int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, int32_t incumbent,
+                   int32_t *out_best);
+
+/* Inspection (synchronises).  hp_get_map copies a bin map of the last evaluation that ran
+ * with keep_maps: HP_MAP_RHO_MOV (int64 charge, 2^-40 area units), HP_MAP_RHO_FIXED (int64),
+ * HP_MAP_PSI / HP_MAP_EX / HP_MAP_EY (real; potential and field).  Layout [my][mx]. */
+enum { HP_MAP_RHO_MOV = 0, HP_MAP_RHO_FIXED = 1, HP_MAP_PSI = 2, HP_MAP_EX = 3, HP_MAP_EY = 4 };
+int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *host_dst);
+
+typedef struct {
+    int64_t k, hpwl_q, overflow_num;
+    double a, alpha, lambda, wl, energy, overflow;
+} hp_slot_state;
+int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYBRO_H */

@@ -1,0 +1,887 @@
+// Host side of libhybro: argument validation, netlist preprocessing (degree buckets, cell ->
+// pin CSR, quantized per-cell charge constants, spectral tables), buffer layouts, and the
+// launch sequences of every C-ABI entry point.  No device memory is allocated here: all of
+// it lives in buffers the caller lends.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hp_internal.h"
+#include "hybro.h"
+
+using namespace hp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HP_CHECK(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(HP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct NetBuf {
+    size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
+        cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh, total;
+};
+
+NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
+    NetBuf b{};
+    size_t o = 0;
+    auto put = [&](size_t &f, size_t bytes) {
+        f = o;
+        o = align256(o + bytes);
+    };
+    const size_t E = s.n_nets, P = s.n_pins, Nm = s.n_movable, Nf = s.n_cells - s.n_movable;
+    const size_t mx = d.mx, my = d.my;
+    put(b.net_start, 4 * (E + 1));
+    put(b.pin_cell, 4 * P);
+    put(b.pin_off, 2 * rs * P);
+    put(b.pin_offq, 8 * P);
+    put(b.net_w, rs * E);
+    put(b.cell_pin_start, 4 * (Nm + 1));
+    put(b.cell_pins, 4 * P);
+    put(b.cq, 16 * Nm);
+    put(b.rq, 4 * Nm);
+    put(b.cstep, 4 * rs * Nm);
+    put(b.cell_wh, 2 * rs * Nm);
+    put(b.rho_fixed, 8 * mx * my);
+    put(b.tw_x, 2 * rs * (mx / 2));
+    put(b.tw_y, 2 * rs * (my / 2));
+    put(b.ph_x, 2 * rs * mx);
+    put(b.ph_y, 2 * rs * my);
+    put(b.omega, 8 * (mx + my));
+    put(b.den1, 8 * (mx + my));
+    put(b.fixed_pos, 2 * rs * Nf);
+    put(b.fxy, 16 * Nf);
+    put(b.fwh, 16 * Nf);
+    b.total = o;
+    return b;
+}
+
+// Upper bound of the blocks of any per-slot reduction (sweep, cells, spectral columns).
+size_t part_stride(const hp_shape &s, const hp_die &d) {
+    const size_t sweep = (size_t)s.n_pins / 65 + (size_t)s.n_nets / 4 + 8 * kMaxBuckets + 8;
+    const size_t cells = ((size_t)s.n_movable + kBlock - 1) / kBlock;
+    return std::max<size_t>({sweep, cells, (size_t)d.mx, 1});
+}
+
+SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs) {
+    SlotLayout L{};
+    size_t o = 0;
+    auto put = [&](size_t &f, size_t bytes) {
+        f = o;
+        o = align256(o + bytes);
+    };
+    const size_t Nc = s.n_cells, Nm = s.n_movable, P = s.n_pins, nb = (size_t)d.mx * d.my;
+    put(L.u, 2 * rs * Nc);
+    put(L.v, 2 * rs * Nc);
+    put(L.vprev, 2 * rs * Nm);
+    put(L.gprev, 2 * rs * Nm);
+    put(L.g, 2 * rs * Nm);
+    put(L.gd, 2 * rs * Nm);
+    put(L.pin_grad, 2 * rs * P);
+    put(L.rho, 8 * nb);
+    put(L.t1, rs * nb);
+    put(L.bx, rs * nb);
+    put(L.by, rs * nb);
+    put(L.bp, rs * nb);
+    put(L.psi, rs * nb);
+    put(L.ex, rs * nb);
+    put(L.ey, rs * nb);
+    put(L.scal, sizeof(Scalars));
+    L.pstride = part_stride(s, d);
+    put(L.part, 8 * PART_COUNT * L.pstride);
+    put(L.keys, 8 * Nm);
+    put(L.sel, 4 * Nm);
+    put(L.work, perturb_work_bytes((int)Nm));
+    L.total = o;
+    return L;
+}
+
+struct Netlist {
+    bool alive = false;
+    hp_shape shape{};
+    hp_die die{};
+    NetDev nd{};
+    Buckets bk{};
+    SlotLayout L{};
+    char *buf = nullptr;
+    int e_parts = 0;
+};
+
+struct Slot {
+    bool alive = false;
+    int netlist = -1;
+    char *base = nullptr;
+    bool lambda_valid = false;  // host mirror of the device flag
+    bool map_dirty = false;     // the movable map was kept by the last evaluation
+    bool maps_valid = false;
+};
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct hp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int precision = 32;
+    std::vector<Netlist> nets;
+    std::vector<Slot> slots;
+};
+
+namespace {
+
+size_t rsize(const hp_ctx *c) { return c->precision == 64 ? 8 : 4; }
+
+int max_bins(const hp_ctx *c) { return c->precision == 64 ? 1024 : 2048; }
+
+int check_die(const hp_ctx *ctx, const hp_die *d) {
+    if (!d) return fail(HP_EINVAL, "die is NULL");
+    if (!(std::isfinite(d->W) && std::isfinite(d->H) && d->W > 0 && d->H > 0))
+        return fail(HP_EINVAL, "die W/H must be finite and positive");
+    if (!is_pow2(d->mx) || !is_pow2(d->my) || d->mx < 8 || d->my < 8 || d->mx > max_bins(ctx) ||
+        d->my > max_bins(ctx))
+        return fail(HP_EINVAL, "bins mx/my must be powers of two in [8, " +
+                                   std::to_string(max_bins(ctx)) + "]");
+    const double bq = d->W / d->mx * 4096.0, hq = d->H / d->my * 4096.0;
+    if (bq != std::floor(bq) || hq != std::floor(hq) || bq < 1 || hq < 1)
+        return fail(HP_EINVAL, "bin width and height must be multiples of 2^-12");
+    if (d->W * 4096.0 >= 2147483647.0 || d->H * 4096.0 >= 2147483647.0)
+        return fail(HP_EINVAL, "die too large for 2^-12 integer coordinates");
+    if (!(d->target_density > 0 && d->target_density <= 1e6))
+        return fail(HP_EINVAL, "target_density must be positive");
+    return HP_OK;
+}
+
+int check_shape(const hp_shape *s) {
+    if (!s) return fail(HP_EINVAL, "shape is NULL");
+    if (s->n_cells < 0 || s->n_movable < 0 || s->n_movable > s->n_cells || s->n_nets < 0 ||
+        s->n_pins < 0)
+        return fail(HP_EINVAL, "bad shape counts");
+    return HP_OK;
+}
+
+template <typename T>
+int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *cell_w,
+                 const double *cell_h, const double *fixed_x, const double *fixed_y,
+                 const int32_t *net_start, const int32_t *pin_cell, const double *pin_ox,
+                 const double *pin_oy, const double *net_weight, char *buf, Netlist &NL) {
+    const int Nc = S.n_cells, Nm = S.n_movable, Nf = Nc - Nm, E = S.n_nets, P = S.n_pins;
+    // ---- validation (host) ----------------------------------------------------------------
+    if ((Nc && (!cell_w || !cell_h)) || (Nf && (!fixed_x || !fixed_y)) || !net_start ||
+        (P && (!pin_cell || !pin_ox || !pin_oy)))
+        return fail(HP_EINVAL, "required netlist array is NULL");
+    if (net_start[0] != 0 || net_start[E] != P) return fail(HP_EINVAL, "net_start[0] must be 0 and net_start[n_nets] == n_pins");
+    for (int e = 0; e < E; ++e)
+        if (net_start[e + 1] < net_start[e]) return fail(HP_EINVAL, "net_start must be non-decreasing");
+    for (int p = 0; p < P; ++p) {
+        if (pin_cell[p] < 0 || pin_cell[p] >= Nc)
+            return fail(HP_EINVAL, "pin_cell[" + std::to_string(p) + "] out of range");
+        if (!std::isfinite(pin_ox[p]) || !std::isfinite(pin_oy[p]))
+            return fail(HP_EINVAL, "pin offsets must be finite");
+        if (std::fabs(pin_ox[p]) * 65536.0 >= 2147483647.0 || std::fabs(pin_oy[p]) * 65536.0 >= 2147483647.0)
+            return fail(HP_EINVAL, "pin offset too large");
+    }
+    for (int i = 0; i < Nc; ++i) {
+        const double w = cell_w[i], h = cell_h[i];
+        if (!std::isfinite(w) || !std::isfinite(h) || w < 0 || h < 0)
+            return fail(HP_EINVAL, "cell sizes must be finite and >= 0");
+        if (i < Nm && (w <= 0 || h <= 0 || w > D.W || h > D.H))
+            return fail(HP_EINVAL, "movable cell " + std::to_string(i) + " must have 0 < size <= die");
+    }
+    for (int i = 0; i < Nf; ++i)
+        if (!std::isfinite(fixed_x[i]) || !std::isfinite(fixed_y[i]))
+            return fail(HP_EINVAL, "fixed positions must be finite");
+    if (net_weight)
+        for (int e = 0; e < E; ++e)
+            if (!std::isfinite(net_weight[e])) return fail(HP_EINVAL, "net weights must be finite");
+
+    const NetBuf B = net_layout(S, D, sizeof(T));
+    NetDev &nd = NL.nd;
+    nd = NetDev{};
+    nd.n_cells = Nc;
+    nd.n_mov = Nm;
+    nd.n_fixed = Nf;
+    nd.mx = D.mx;
+    nd.my = D.my;
+    nd.logmx = ilog2(D.mx);
+    nd.logmy = ilog2(D.my);
+    nd.W = D.W;
+    nd.H = D.H;
+    nd.wb = D.W / D.mx;
+    nd.hb = D.H / D.my;
+    nd.bq = (int)std::llrint(nd.wb * 4096.0);
+    nd.hq = (int)std::llrint(nd.hb * 4096.0);
+    nd.wq_die = nd.bq * D.mx;
+    nd.hq_die = nd.hq * D.my;
+    nd.density_unit = std::ldexp(1.0, -40) / (nd.wb * nd.hb);
+    nd.area_q = (int64_t)nd.bq * nd.hq * 65536;
+    nd.target_density = D.target_density;
+
+    // ---- degree buckets -------------------------------------------------------------------
+    // order: block-per-net (largest first), then groups of 64, 32, ..., 2 lanes
+    const int Gs[7] = {0, 64, 32, 16, 8, 4, 2};
+    std::vector<std::vector<int>> members(7);
+    for (int e = 0; e < E; ++e) {
+        const int d = net_start[e + 1] - net_start[e];
+        if (d < 2) continue;
+        int b = 0;
+        if (d <= 64) {
+            int G = 2;
+            while (G < d) G <<= 1;
+            b = 1 + (6 - ilog2(G));
+        }
+        members[b].push_back(e);
+    }
+    std::stable_sort(members[0].begin(), members[0].end(), [&](int a, int b) {
+        return net_start[a + 1] - net_start[a] > net_start[b + 1] - net_start[b];
+    });
+    std::vector<int> order;
+    Buckets bk{};
+    int blk = 0;
+    for (int b = 0; b < 7; ++b) {
+        if (members[b].empty()) continue;
+        const int G = Gs[b];
+        const int npb = G ? kBlock / G : 1;
+        int nblk = ((int)members[b].size() + npb - 1) / npb;
+        nblk = (nblk + kXcds - 1) / kXcds * kXcds;
+        bk.G[bk.n] = G;
+        bk.net0[bk.n] = (int)order.size();
+        order.insert(order.end(), members[b].begin(), members[b].end());
+        bk.net1[bk.n] = (int)order.size();
+        bk.blk0[bk.n] = blk;
+        bk.nblk[bk.n] = nblk;
+        blk += nblk;
+        ++bk.n;
+    }
+    bk.total_blocks = blk;
+    if ((size_t)blk > part_stride(S, D)) return fail(HP_EINVAL, "internal: sweep block bound");
+    const int ns = (int)order.size();
+    nd.ns = ns;
+
+    std::vector<int32_t> h_ns(ns + 1), h_pc;
+    std::vector<T> h_po, h_w;
+    std::vector<int32_t> h_pq;
+    std::vector<int32_t> orig_to_sweep(P, -1);
+    h_pc.reserve(P);
+    h_po.reserve(2 * (size_t)P);
+    h_pq.reserve(2 * (size_t)P);
+    bool any_w = false;
+    if (net_weight)
+        for (int e = 0; e < E; ++e) any_w |= net_weight[e] != 1.0;
+    for (int i = 0; i < ns; ++i) {
+        const int e = order[i];
+        h_ns[i] = (int32_t)h_pc.size();
+        for (int p = net_start[e]; p < net_start[e + 1]; ++p) {
+            orig_to_sweep[p] = (int32_t)h_pc.size();
+            h_pc.push_back(pin_cell[p]);
+            h_po.push_back((T)pin_ox[p]);
+            h_po.push_back((T)pin_oy[p]);
+            h_pq.push_back((int32_t)std::llrint(pin_ox[p] * 65536.0));
+            h_pq.push_back((int32_t)std::llrint(pin_oy[p] * 65536.0));
+        }
+        if (any_w) h_w.push_back((T)net_weight[e]);
+    }
+    h_ns[ns] = (int32_t)h_pc.size();
+    const int ps = (int)h_pc.size();
+    nd.ps = ps;
+
+    // cell -> sweep-pin CSR (movable cells), and pin counts over all nets for the
+    // preconditioner
+    std::vector<int32_t> h_cps(Nm + 1, 0), cnt_all(Nm, 0);
+    for (int p = 0; p < P; ++p)
+        if (pin_cell[p] < Nm) cnt_all[pin_cell[p]]++;
+    for (int q = 0; q < ps; ++q)
+        if (h_pc[q] < Nm) h_cps[h_pc[q] + 1]++;
+    for (int i = 0; i < Nm; ++i) h_cps[i + 1] += h_cps[i];
+    std::vector<int32_t> h_cp(h_cps[Nm]);
+    {
+        std::vector<int32_t> fill(h_cps.begin(), h_cps.end() - 1);
+        for (int q = 0; q < ps; ++q)
+            if (h_pc[q] < Nm) h_cp[fill[h_pc[q]]++] = q;
+    }
+
+    // per-cell charge constants (2^-12 / 2^-16 integers, computed in FP64 once)
+    std::vector<int32_t> h_cq(4 * (size_t)Nm), h_rq(Nm);
+    std::vector<T> h_cs(4 * (size_t)Nm), h_wh(2 * (size_t)Nm);
+    int64_t total_charge = 0;
+    {
+#pragma clang fp contract(off)
+        for (int i = 0; i < Nm; ++i) {
+            const double w = cell_w[i], h = cell_h[i];
+            double ws = w, hs = h, r = 1.0;
+            if (D.stretch) {
+                ws = std::fmax(w, M_SQRT2 * nd.wb);
+                hs = std::fmax(h, M_SQRT2 * nd.hb);
+                r = (w * h) / (ws * hs);
+            }
+            const long long wq = std::llrint(ws * 4096.0), hq = std::llrint(hs * 4096.0);
+            const long long dxq = std::llrint((w - ws) * 0.5 * 4096.0);
+            const long long dyq = std::llrint((h - hs) * 0.5 * 4096.0);
+            const long long rq = std::llrint(r * 65536.0);
+            h_cq[4 * (size_t)i + 0] = (int32_t)wq;
+            h_cq[4 * (size_t)i + 1] = (int32_t)hq;
+            h_cq[4 * (size_t)i + 2] = (int32_t)dxq;
+            h_cq[4 * (size_t)i + 3] = (int32_t)dyq;
+            h_rq[i] = (int32_t)rq;
+            total_charge += rq * wq * hq;
+            h_cs[i] = (T)cnt_all[i];
+            h_cs[(size_t)Nm + i] = (T)(w * h);
+            h_cs[2 * (size_t)Nm + i] = (T)(D.W - w);
+            h_cs[3 * (size_t)Nm + i] = (T)(D.H - h);
+            h_wh[i] = (T)w;
+            h_wh[(size_t)Nm + i] = (T)h;
+        }
+    }
+    nd.total_charge = total_charge > 0 ? total_charge : 1;
+
+    // spectral tables: FFT twiddles exp(-2 pi i k / M), DCT phases (cos, sin)(pi u / 2M),
+    // w_u = pi u / W and the per-axis Laplacian symbol
+    auto twid = [](int M) {
+        std::vector<T> t(M);
+        for (int k = 0; k < M / 2; ++k) {
+            t[2 * k] = (T)std::cos(2.0 * M_PI * k / M);
+            t[2 * k + 1] = (T)(-std::sin(2.0 * M_PI * k / M));
+        }
+        return t;
+    };
+    auto phase = [](int M) {
+        std::vector<T> t(2 * (size_t)M);
+        for (int u = 0; u < M; ++u) {
+            t[2 * u] = (T)std::cos(M_PI * u / (2.0 * M));
+            t[2 * u + 1] = (T)std::sin(M_PI * u / (2.0 * M));
+        }
+        return t;
+    };
+    std::vector<double> h_om(D.mx + D.my), h_den(D.mx + D.my);
+    for (int u = 0; u < D.mx; ++u) {
+        h_om[u] = M_PI * u / D.W;
+        h_den[u] = D.fd5 ? (4.0 / (nd.wb * nd.wb)) * std::pow(std::sin(M_PI * u / (2.0 * D.mx)), 2)
+                         : std::pow(M_PI * u / D.W, 2);
+    }
+    for (int v = 0; v < D.my; ++v) {
+        h_om[D.mx + v] = M_PI * v / D.H;
+        h_den[D.mx + v] = D.fd5 ? (4.0 / (nd.hb * nd.hb)) * std::pow(std::sin(M_PI * v / (2.0 * D.my)), 2)
+                                : std::pow(M_PI * v / D.H, 2);
+    }
+    std::vector<T> h_fp(2 * (size_t)Nf);
+    std::vector<double> h_fxy(2 * (size_t)Nf), h_fwh(2 * (size_t)Nf);
+    for (int i = 0; i < Nf; ++i) {
+        h_fp[i] = (T)fixed_x[i];
+        h_fp[(size_t)Nf + i] = (T)fixed_y[i];
+        h_fxy[i] = fixed_x[i];
+        h_fxy[(size_t)Nf + i] = fixed_y[i];
+        h_fwh[i] = cell_w[Nm + i];
+        h_fwh[(size_t)Nf + i] = cell_h[Nm + i];
+    }
+
+    // ---- upload ---------------------------------------------------------------------------
+    hipStream_t st = ctx->stream;
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    HP_CHECK(up(B.net_start, h_ns.data(), 4 * h_ns.size()));
+    HP_CHECK(up(B.pin_cell, h_pc.data(), 4 * h_pc.size()));
+    HP_CHECK(up(B.pin_off, h_po.data(), sizeof(T) * h_po.size()));
+    HP_CHECK(up(B.pin_offq, h_pq.data(), 4 * h_pq.size()));
+    if (any_w) HP_CHECK(up(B.net_w, h_w.data(), sizeof(T) * h_w.size()));
+    HP_CHECK(up(B.cell_pin_start, h_cps.data(), 4 * h_cps.size()));
+    HP_CHECK(up(B.cell_pins, h_cp.data(), 4 * h_cp.size()));
+    HP_CHECK(up(B.cq, h_cq.data(), 4 * h_cq.size()));
+    HP_CHECK(up(B.rq, h_rq.data(), 4 * h_rq.size()));
+    HP_CHECK(up(B.cstep, h_cs.data(), sizeof(T) * h_cs.size()));
+    HP_CHECK(up(B.cell_wh, h_wh.data(), sizeof(T) * h_wh.size()));
+    std::vector<T> twx = twid(D.mx), twy = twid(D.my), phx = phase(D.mx), phy = phase(D.my);
+    HP_CHECK(up(B.tw_x, twx.data(), sizeof(T) * (size_t)D.mx));
+    HP_CHECK(up(B.tw_y, twy.data(), sizeof(T) * (size_t)D.my));
+    HP_CHECK(up(B.ph_x, phx.data(), sizeof(T) * phx.size()));
+    HP_CHECK(up(B.ph_y, phy.data(), sizeof(T) * phy.size()));
+    HP_CHECK(up(B.omega, h_om.data(), 8 * h_om.size()));
+    HP_CHECK(up(B.den1, h_den.data(), 8 * h_den.size()));
+    HP_CHECK(up(B.fixed_pos, h_fp.data(), sizeof(T) * h_fp.size()));
+    HP_CHECK(up(B.fxy, h_fxy.data(), 8 * h_fxy.size()));
+    HP_CHECK(up(B.fwh, h_fwh.data(), 8 * h_fwh.size()));
+    HP_CHECK(hipMemsetAsync(buf + B.rho_fixed, 0, 8 * (size_t)D.mx * D.my, st));
+
+    nd.net_start = reinterpret_cast<const int32_t *>(buf + B.net_start);
+    nd.pin_cell = reinterpret_cast<const int32_t *>(buf + B.pin_cell);
+    nd.pin_off = buf + B.pin_off;
+    nd.pin_offq = reinterpret_cast<const int2 *>(buf + B.pin_offq);
+    nd.net_w = any_w ? buf + B.net_w : nullptr;
+    nd.cell_pin_start = reinterpret_cast<const int32_t *>(buf + B.cell_pin_start);
+    nd.cell_pins = reinterpret_cast<const int32_t *>(buf + B.cell_pins);
+    nd.cq = reinterpret_cast<const int4 *>(buf + B.cq);
+    nd.rq = reinterpret_cast<const int32_t *>(buf + B.rq);
+    nd.cstep = buf + B.cstep;
+    nd.cell_wh = buf + B.cell_wh;
+    nd.rho_fixed = reinterpret_cast<const int64_t *>(buf + B.rho_fixed);
+    nd.tw_x = buf + B.tw_x;
+    nd.tw_y = buf + B.tw_y;
+    nd.ph_x = buf + B.ph_x;
+    nd.ph_y = buf + B.ph_y;
+    nd.omega = reinterpret_cast<const double *>(buf + B.omega);
+    nd.den1 = reinterpret_cast<const double *>(buf + B.den1);
+    nd.fixed_pos = buf + B.fixed_pos;
+    HP_CHECK(launch_fixed_map<T>(nd, reinterpret_cast<const double *>(buf + B.fxy),
+                                 reinterpret_cast<const double *>(buf + B.fwh),
+                                 reinterpret_cast<int64_t *>(buf + B.rho_fixed), st));
+    HP_CHECK(hipStreamSynchronize(st));  // host staging vectors die at return
+
+    NL.alive = true;
+    NL.shape = S;
+    NL.die = D;
+    NL.bk = bk;
+    NL.L = slot_layout(S, D, sizeof(T));
+    NL.buf = buf;
+    NL.e_parts = spectral_energy_parts<T>(nd);
+    return HP_OK;
+}
+
+int get_slot(hp_ctx *ctx, int32_t id, Slot **s, Netlist **n) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (id < 0 || id >= (int)ctx->slots.size() || !ctx->slots[id].alive)
+        return fail(HP_ESTATE, "unknown slot " + std::to_string(id));
+    *s = &ctx->slots[id];
+    *n = &ctx->nets[(*s)->netlist];
+    return HP_OK;
+}
+
+// Resolve a slot list into launch chunks (all on one netlist).
+int resolve(hp_ctx *ctx, const int32_t *slots, int32_t n, Netlist **net,
+            std::vector<SlotArgs> &chunks, std::vector<Slot *> &ss) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (!slots || n <= 0) return fail(HP_EINVAL, "empty slot list");
+    *net = nullptr;
+    ss.clear();
+    chunks.clear();
+    for (int i = 0; i < n; ++i) {
+        Slot *s;
+        Netlist *nl;
+        int rc = get_slot(ctx, slots[i], &s, &nl);
+        if (rc) return rc;
+        if (*net && nl != *net) return fail(HP_ESTATE, "slots of one call must share a netlist");
+        *net = nl;
+        ss.push_back(s);
+        if (i % kMaxSlots == 0) chunks.push_back(SlotArgs{});
+        SlotArgs &c = chunks.back();
+        c.base[c.n++] = s->base;
+    }
+    return HP_OK;
+}
+
+template <typename T>
+int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p, double *wl,
+              double *energy, double *overflow, void *gx, void *gy) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    if (!p) return fail(HP_EINVAL, "params is NULL");
+    if (!(p->gamma > 0) || !std::isfinite(p->gamma)) return fail(HP_EINVAL, "gamma must be > 0");
+    if (p->grad_mode != 0) return fail(HP_ENOTIMPL, "only the field-force gradient runs on the device");
+    const bool use_fixed = p->lambda >= 0;
+    if (use_fixed && !std::isfinite(p->lambda)) return fail(HP_EINVAL, "lambda must be finite");
+    hipStream_t st = ctx->stream;
+    const NetDev &nd = NL->nd;
+    const SlotLayout &L = NL->L;
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        const SlotArgs &sa = chunks[c];
+        bool dirty = false, any_init = false;
+        for (int i = 0; i < sa.n; ++i) {
+            Slot *s = ss[c * kMaxSlots + i];
+            dirty |= s->map_dirty;
+            any_init |= !use_fixed && !s->lambda_valid;
+        }
+        if (dirty) HP_CHECK(launch_zero_rho<T>(nd, sa, L, st));
+        HP_CHECK(launch_sweep_wa<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, st));
+        HP_CHECK(launch_scatter<T>(nd, sa, L, st));
+        HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0, p->keep_maps != 0, st));
+        HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, false, st));
+        HP_CHECK(launch_eval_finish<T>(nd, sa, L, NL->bk.total_blocks, NL->e_parts, cell_parts(nd),
+                                       use_fixed, any_init, st));
+        for (int i = 0; i < sa.n; ++i) {
+            Slot *s = ss[c * kMaxSlots + i];
+            s->map_dirty = p->keep_maps != 0;
+            s->maps_valid = p->keep_maps != 0;
+            if (!use_fixed) s->lambda_valid = true;
+        }
+    }
+    const size_t rs = sizeof(T), Nm = nd.n_mov;
+    for (int i = 0; i < n; ++i) {
+        if (gx) HP_CHECK(hipMemcpyAsync((char *)gx + i * Nm * rs, ss[i]->base + L.g, Nm * rs,
+                                        hipMemcpyDeviceToDevice, st));
+        if (gy) HP_CHECK(hipMemcpyAsync((char *)gy + i * Nm * rs, ss[i]->base + L.g + Nm * rs,
+                                        Nm * rs, hipMemcpyDeviceToDevice, st));
+    }
+    if (wl || energy || overflow) {
+        std::vector<Scalars> h(n);
+        for (int i = 0; i < n; ++i)
+            HP_CHECK(hipMemcpyAsync(&h[i], ss[i]->base + L.scal, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HP_CHECK(hipStreamSynchronize(st));
+        for (int i = 0; i < n; ++i) {
+            if (wl) wl[i] = h[i].wl;
+            if (energy) energy[i] = h[i].energy;
+            if (overflow) overflow[i] = h[i].overflow;
+        }
+    }
+    return HP_OK;
+}
+
+void init_scalars(Scalars &s, double scale, double decades, int iters) {
+    std::memset(&s, 0, sizeof(s));
+    s.a = 1.0;
+    s.lambda0_scale = scale;
+    s.lambda_ratio = std::pow(10.0, decades / iters);
+    s.best = -1;
+}
+
+}  // namespace
+
+// ============================================================================================
+extern "C" {
+
+const char *hp_last_error(void) { return g_err.c_str(); }
+
+int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
+    if (!out) return fail(HP_EINVAL, "out is NULL");
+    if (precision != 32 && precision != 64) return fail(HP_EINVAL, "precision must be 32 or 64");
+    int ndev = 0;
+    HP_CHECK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(HP_EINVAL, "no such device");
+    HP_CHECK(hipSetDevice(device));
+    if (precision == 32)
+        HP_CHECK(spectral_prepare<float>());
+    else
+        HP_CHECK(spectral_prepare<double>());
+    hp_ctx *c = new hp_ctx;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->precision = precision;
+    *out = c;
+    return HP_OK;
+}
+
+int hp_destroy(hp_ctx *ctx) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    if (e != hipSuccess) return fail(HP_EDEVICE, hipGetErrorString(e));
+    return HP_OK;
+}
+
+size_t hp_netlist_bytes(const hp_ctx *ctx, const hp_shape *s, const hp_die *d) {
+    if (!ctx || check_shape(s) || check_die(ctx, d)) return 0;
+    return net_layout(*s, *d, rsize(ctx)).total;
+}
+
+size_t hp_slot_bytes(const hp_ctx *ctx, const hp_shape *s, const hp_die *d) {
+    if (!ctx || check_shape(s) || check_die(ctx, d)) return 0;
+    return slot_layout(*s, *d, rsize(ctx)).total;
+}
+
+int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die, const double *cell_w,
+                        const double *cell_h, const double *fixed_x, const double *fixed_y,
+                        const int32_t *net_start, const int32_t *pin_cell, const double *pin_ox,
+                        const double *pin_oy, const double *net_weight, void *dev_buf,
+                        size_t dev_bytes, int32_t *out_netlist) {
+    if (!ctx || !out_netlist) return fail(HP_EINVAL, "ctx/out is NULL");
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    rc = check_die(ctx, die);
+    if (rc) return rc;
+    if (!dev_buf || ((uintptr_t)dev_buf & 255)) return fail(HP_EINVAL, "dev_buf must be 256-byte aligned");
+    const size_t need = net_layout(*shape, *die, rsize(ctx)).total;
+    if (dev_bytes < need)
+        return fail(HP_ENOMEM, "netlist buffer needs " + std::to_string(need) + " bytes");
+    HP_CHECK(hipSetDevice(ctx->device));
+    Netlist NL;
+    rc = ctx->precision == 32
+             ? load_netlist<float>(ctx, *shape, *die, cell_w, cell_h, fixed_x, fixed_y, net_start,
+                                   pin_cell, pin_ox, pin_oy, net_weight, (char *)dev_buf, NL)
+             : load_netlist<double>(ctx, *shape, *die, cell_w, cell_h, fixed_x, fixed_y, net_start,
+                                    pin_cell, pin_ox, pin_oy, net_weight, (char *)dev_buf, NL);
+    if (rc) return rc;
+    ctx->nets.push_back(NL);
+    *out_netlist = (int32_t)ctx->nets.size() - 1;
+    return HP_OK;
+}
+
+int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes, int32_t *out_slot) {
+    if (!ctx || !out_slot) return fail(HP_EINVAL, "ctx/out is NULL");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    Netlist &NL = ctx->nets[netlist];
+    if (!dev_buf || ((uintptr_t)dev_buf & 255)) return fail(HP_EINVAL, "dev_buf must be 256-byte aligned");
+    if (dev_bytes < NL.L.total)
+        return fail(HP_ENOMEM, "slot buffer needs " + std::to_string(NL.L.total) + " bytes");
+    char *base = (char *)dev_buf;
+    hipStream_t st = ctx->stream;
+    const size_t rs = rsize(ctx);
+    const size_t Nc = NL.nd.n_cells, Nm = NL.nd.n_mov, Nf = NL.nd.n_fixed;
+    HP_CHECK(hipMemsetAsync(base, 0, NL.L.total, st));
+    for (int a = 0; a < 2; ++a)
+        for (size_t off : {NL.L.u, NL.L.v})
+            if (Nf)
+                HP_CHECK(hipMemcpyAsync(base + off + (a * Nc + Nm) * rs,
+                                        (const char *)NL.nd.fixed_pos + a * Nf * rs, Nf * rs,
+                                        hipMemcpyDeviceToDevice, st));
+    Scalars s;
+    init_scalars(s, 1e-4, 4.0, 1000);
+    HP_CHECK(hipMemcpyAsync(base + NL.L.scal, &s, sizeof(s), hipMemcpyHostToDevice, st));
+    HP_CHECK(hipStreamSynchronize(st));
+    Slot sl;
+    sl.alive = true;
+    sl.netlist = netlist;
+    sl.base = base;
+    ctx->slots.push_back(sl);
+    *out_slot = (int32_t)ctx->slots.size() - 1;
+    return HP_OK;
+}
+
+int hp_slot_free(hp_ctx *ctx, int32_t slot) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    s->alive = false;
+    s->base = nullptr;
+    return HP_OK;
+}
+
+int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, int on_device) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (!x || !y) return fail(HP_EINVAL, "x/y is NULL");
+    const size_t rs = rsize(ctx), Nc = n->nd.n_cells, Nm = n->nd.n_mov;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipStream_t st = ctx->stream;
+    const SlotLayout &L = n->L;
+    for (int a = 0; a < 2; ++a) {
+        const void *src = a ? y : x;
+        HP_CHECK(hipMemcpyAsync(s->base + L.u + a * Nc * rs, src, Nm * rs, k, st));
+        HP_CHECK(hipMemcpyAsync(s->base + L.v + a * Nc * rs, src, Nm * rs, k, st));
+        HP_CHECK(hipMemcpyAsync(s->base + L.vprev + a * Nm * rs, src, Nm * rs, k, st));
+    }
+    Scalars h;
+    HP_CHECK(hipMemcpyAsync(&h, s->base + L.scal, sizeof(h), hipMemcpyDeviceToHost, st));
+    HP_CHECK(hipStreamSynchronize(st));
+    h.k = 0;
+    h.a = 1.0;
+    h.alpha = 0.0;
+    h.lambda_valid = 0;
+    h.hpwl_valid = 0;
+    HP_CHECK(hipMemcpyAsync(s->base + L.scal, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    HP_CHECK(hipStreamSynchronize(st));
+    s->lambda_valid = false;
+    return HP_OK;
+}
+
+int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    const size_t rs = rsize(ctx), Nc = n->nd.n_cells, Nm = n->nd.n_mov;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (x) HP_CHECK(hipMemcpyAsync(x, s->base + n->L.u, Nm * rs, k, ctx->stream));
+    if (y) HP_CHECK(hipMemcpyAsync(y, s->base + n->L.u + Nc * rs, Nm * rs, k, ctx->stream));
+    if (!on_device) HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double decades, int32_t total_iters) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (!(lambda0_scale > 0) || !std::isfinite(decades) || total_iters <= 0)
+        return fail(HP_EINVAL, "bad schedule");
+    Scalars h;
+    HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    h.lambda0_scale = lambda0_scale;
+    h.lambda_ratio = std::pow(10.0, decades / total_iters);
+    HP_CHECK(hipMemcpyAsync(s->base + n->L.scal, &h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p,
+                           double *wl, double *energy, double *overflow, void *gx, void *gy) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    return ctx->precision == 32 ? eval_impl<float>(ctx, slots, n, p, wl, energy, overflow, gx, gy)
+                                : eval_impl<double>(ctx, slots, n, p, wl, energy, overflow, gx, gy);
+}
+
+int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    for (const SlotArgs &sa : chunks) {
+        if (ctx->precision == 32)
+            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, ctx->stream));
+        else
+            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, ctx->stream));
+    }
+    return HP_OK;
+}
+
+int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins, uint64_t seed,
+               int32_t *out_idx, int32_t *out_count) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (mode < 0 || mode > 2) return fail(HP_EINVAL, "unknown perturbation mode");
+    if (mode != 2 && !(fraction >= 0 && fraction <= 1)) return fail(HP_EINVAL, "fraction must be in [0, 1]");
+    if (mode == 0 && !(sigma_bins >= 0 && std::isfinite(sigma_bins)))
+        return fail(HP_EINVAL, "sigma must be finite and >= 0");
+    const int Nm = n->nd.n_mov;
+    int64_t m = mode == 2 ? Nm : (int64_t)std::floor(fraction * Nm + 0.5);
+    if (m > Nm) m = Nm;
+    if (ctx->precision == 32)
+        HP_CHECK(launch_perturb<float>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
+                                       sigma_bins * n->nd.hb, seed, ctx->stream));
+    else
+        HP_CHECK(launch_perturb<double>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
+                                        sigma_bins * n->nd.hb, seed, ctx->stream));
+    s->lambda_valid = false;
+    if (out_idx && m)
+        HP_CHECK(hipMemcpyAsync(out_idx, s->base + n->L.sel, 4 * (size_t)m, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    if (out_count) *out_count = (int32_t)m;
+    if (out_idx || out_count) HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double *out) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    for (const SlotArgs &sa : chunks) {
+        if (ctx->precision == 32)
+            HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
+        else
+            HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
+        HP_CHECK(launch_hpwl_finish(sa, NL->L, ctx->stream));
+    }
+    if (out_q || out) {
+        std::vector<int64_t> h(n);
+        for (int i = 0; i < n; ++i)
+            HP_CHECK(hipMemcpyAsync(&h[i], ss[i]->base + NL->L.scal + offsetof(Scalars, hpwl_q), 8,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HP_CHECK(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < n; ++i) {
+            if (out_q) out_q[i] = h[i];
+            if (out) out[i] = std::ldexp((double)h[i], -16);
+        }
+    }
+    return HP_OK;
+}
+
+int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbent, int32_t *out_best) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    if (n > kMaxSlots) return fail(HP_EINVAL, "at most 32 candidates per selection");
+    Slot *inc;
+    Netlist *ni;
+    rc = get_slot(ctx, incumbent, &inc, &ni);
+    if (rc) return rc;
+    if (ni != NL) return fail(HP_ESTATE, "incumbent is on another netlist");
+    for (Slot *s : ss)
+        if (s == inc) return fail(HP_EINVAL, "the incumbent cannot be a candidate");
+    if (ctx->precision == 32)
+        HP_CHECK(launch_select_best<float>(NL->nd, chunks[0], inc->base, NL->L, ctx->stream));
+    else
+        HP_CHECK(launch_select_best<double>(NL->nd, chunks[0], inc->base, NL->L, ctx->stream));
+    inc->lambda_valid = false;  // conservatively: the device resets it when a candidate wins
+    if (out_best) {
+        int64_t b = -1;
+        HP_CHECK(hipMemcpyAsync(&b, inc->base + NL->L.scal + offsetof(Scalars, best), 8,
+                                hipMemcpyDeviceToHost, ctx->stream));
+        HP_CHECK(hipStreamSynchronize(ctx->stream));
+        *out_best = (int32_t)b;
+    }
+    return HP_OK;
+}
+
+int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (!dst) return fail(HP_EINVAL, "dst is NULL");
+    const size_t nb = (size_t)n->nd.mx * n->nd.my, rs = rsize(ctx);
+    const char *src = nullptr;
+    size_t bytes = 0;
+    if (which == HP_MAP_RHO_FIXED) {
+        src = (const char *)n->nd.rho_fixed;
+        bytes = 8 * nb;
+    } else {
+        if (!s->maps_valid) return fail(HP_ESTATE, "no maps kept: evaluate with keep_maps = 1");
+        switch (which) {
+            case HP_MAP_RHO_MOV: src = s->base + n->L.rho; bytes = 8 * nb; break;
+            case HP_MAP_PSI: src = s->base + n->L.psi; bytes = rs * nb; break;
+            case HP_MAP_EX: src = s->base + n->L.ex; bytes = rs * nb; break;
+            case HP_MAP_EY: src = s->base + n->L.ey; bytes = rs * nb; break;
+            default: return fail(HP_EINVAL, "unknown map");
+        }
+    }
+    HP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (!out) return fail(HP_EINVAL, "out is NULL");
+    Scalars h;
+    HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    out->k = h.k;
+    out->hpwl_q = h.hpwl_valid ? h.hpwl_q : -1;
+    out->overflow_num = h.overflow_num;
+    out->a = h.a;
+    out->alpha = h.alpha;
+    out->lambda = h.lambda;
+    out->wl = h.wl;
+    out->energy = h.energy;
+    out->overflow = h.overflow;
+    return HP_OK;
+}
+
+}  // extern "C"

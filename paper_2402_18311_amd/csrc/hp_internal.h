@@ -1,0 +1,151 @@
+// Internal structures shared by the host code and the kernels of libhybro (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hp {
+
+constexpr int kBlock = 256;      // threads per block for every kernel
+constexpr int kMaxSlots = 32;    // slots per launch (longer lists are chunked)
+constexpr int kMaxBuckets = 8;
+constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
+
+template <typename T> struct V2;
+template <> struct V2<float> { using type = float2; };
+template <> struct V2<double> { using type = double2; };
+template <typename T> using vec2 = typename V2<T>::type;
+
+// Degree buckets of the net sweep: nets with 2..64 pins are processed by a group of G
+// lanes (G = next power of two >= degree), larger ones by a whole block.
+struct Buckets {
+    int32_t n;
+    int32_t G[kMaxBuckets];      // group size, or 0 for block-per-net
+    int32_t net0[kMaxBuckets];   // first (sorted) net of the bucket
+    int32_t net1[kMaxBuckets];
+    int32_t blk0[kMaxBuckets];   // first block; every bucket has a multiple of 8 blocks
+    int32_t nblk[kMaxBuckets];
+    int32_t total_blocks;
+};
+
+// Device view of a loaded netlist (pointers into the caller's netlist buffer).
+struct NetDev {
+    const int32_t *net_start;      // [ns + 1] sweep order (nets with >= 2 pins)
+    const int32_t *pin_cell;       // [ps]
+    const void *pin_off;           // vec2<T> [ps] pin offsets
+    const int2 *pin_offq;          // [ps] offsets quantized to 2^-16
+    const void *net_w;             // T [ns] or nullptr (all weights 1)
+    const int32_t *cell_pin_start; // [n_mov + 1]
+    const int32_t *cell_pins;      // sweep-order pins of each movable cell
+    const int4 *cq;                // [n_mov] (w'q, h'q, dxq, dyq) in 2^-12
+    const int32_t *rq;             // [n_mov] charge scale in 2^-16
+    const void *cstep;             // T [4][n_mov]: pins, area, x max, y max
+    const int64_t *rho_fixed;      // [my][mx]
+    const void *tw_x, *tw_y;       // vec2<T> [M/2] exp(-2 pi i k / M)
+    const void *ph_x, *ph_y;       // vec2<T> [M] (cos, sin)(pi u / (2 M))
+    const double *omega;           // [mx + my] pi u / W, then pi v / H
+    const double *den1;            // [mx + my] per-axis Laplacian symbol (den = dx[u] + dy[v])
+    const void *fixed_pos;         // T [2][n_fixed]
+    const void *cell_wh;           // T [2][n_mov] movable cell sizes
+    int32_t n_cells, n_mov, n_fixed, ns, ps;
+    int32_t mx, my, logmx, logmy;
+    int32_t bq, hq, wq_die, hq_die; // bin size and die size in 2^-12 units
+    double W, H, wb, hb;
+    double density_unit;           // 2^-40 / (wb hb): integer charge -> normalized density
+    int64_t area_q;                // bin area in 2^-40 units
+    double target_density;
+    int64_t total_charge;
+};
+
+// Byte offsets of a slot's arrays inside its buffer (identical for all slots of a netlist).
+struct SlotLayout {
+    size_t u, v;          // T [2][n_cells] (fixed cells in the tail, never modified)
+    size_t vprev, gprev;  // T [2][n_mov]
+    size_t g, gd;         // T [2][n_mov] raw gradient; density part (first evaluation)
+    size_t pin_grad;      // vec2<T> [ps]
+    size_t rho;           // int64 [my][mx] movable charge
+    size_t t1, bx, by, bp;// T [my][mx] spectral intermediates
+    size_t psi, ex, ey;   // T [my][mx]
+    size_t scal;          // Scalars
+    size_t part;          // double partial sums, kPartStride per reduction
+    size_t keys, sel, work; // perturbation scratch
+    size_t pstride;       // doubles per reduction in `part` (max blocks of any reduction)
+    size_t total;
+};
+
+enum { PART_WL = 0, PART_E = 1, PART_N1 = 2, PART_N2 = 3, PART_DV = 4, PART_DG = 5,
+       PART_GMAX = 6, PART_COUNT = 7 };
+
+// Per-slot scalars in device memory.
+struct Scalars {
+    double a, alpha, lambda, lambda_step, lambda0_scale, lambda_ratio;
+    double wl, energy, overflow;
+    double step_alpha, step_coef;
+    int64_t k;
+    int64_t lambda_valid;   // 0 until lambda_0 is derived at the first evaluation
+    int64_t init_this_eval; // the last evaluation derived lambda_0
+    int64_t hpwl_q, hpwl_valid;
+    unsigned long long hpwl_acc;
+    unsigned long long ovf_acc;
+    int64_t overflow_num;
+    // perturbation
+    uint64_t sel_prefix, sel_mask;
+    int64_t sel_remaining, sel_count;
+    uint32_t hist[256];
+    int64_t best;
+};
+
+struct SlotArgs {
+    char *base[kMaxSlots];
+    int32_t n;
+};
+
+__host__ __device__ inline Scalars *scalars(char *base, const SlotLayout &L) {
+    return reinterpret_cast<Scalars *>(base + L.scal);
+}
+
+// ---- launchers (each returns hipError_t of the launch) -----------------------------------
+template <typename T>
+hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
+                           const SlotLayout &L, double inv_gamma, hipStream_t st);
+template <typename T>
+hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
+                             const SlotLayout &L, hipStream_t st);
+template <typename T>
+hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                           bool keep_maps, bool want_psi, hipStream_t st);
+template <typename T>
+hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                            double lambda_fixed, bool use_fixed, bool init_mode,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
+                              int ne, int ncell, bool use_fixed, bool any_init, hipStream_t st);
+hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, hipStream_t st);
+template <typename T> int spectral_energy_parts(const NetDev &nd);
+template <typename T> size_t spectral_max_lds(const NetDev &nd);
+template <typename T> hipError_t spectral_prepare();
+template <typename T>
+hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_zero_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,
+                            int64_t *rho_fixed, hipStream_t st);
+template <typename T>
+hipError_t launch_perturb(const NetDev &nd, char *slot, const SlotLayout &L, int mode,
+                          int64_t m, double sigma_x, double sigma_y, uint64_t seed,
+                          hipStream_t st);
+size_t perturb_work_bytes(int n_mov);
+template <typename T>
+hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumbent,
+                              const SlotLayout &L, hipStream_t st);
+
+int sweep_parts(const Buckets &bk);
+int cell_parts(const NetDev &nd);
+
+}  // namespace hp

@@ -1,0 +1,210 @@
+// Per-cell kernels: the integer charge scatter (density map), and the fused cell gradient
+// (sum of the cell's pin gradients of Eq. 3 plus the electrostatic force on its charge).
+//
+// Charge model (the density D of Eqs. 1-2, ePlace reading): the die is cut into mx x my bins
+// of bq x hq units of 2^-12.  A movable cell's charge rectangle is its own, stretched to at
+// least sqrt(2) bins per side around the cell centre, with its charge density scaled by
+// r = w h / (w' h').  Its charge in bin (j, k) is r_q * ox_j * oy_k with r_q in 2^-16 and the
+// overlaps in 2^-12, i.e. in units of 2^-40 area, exact in int64.  Integer atomics commute,
+// so the map is bit-identical whatever the order in which cells arrive.
+#include "hp_device.h"
+
+namespace hp {
+
+struct RectQ {
+    int l, r, b, t;
+};
+
+__device__ __forceinline__ RectQ cell_rect(const NetDev &nd, double x, double y, int4 c) {
+    // c = (w'q, h'q, dxq, dyq); left edge q12(x) + dxq, clipped to the die
+    const long long L = q12(x) + c.z, B = q12(y) + c.w;
+    RectQ q;
+    q.l = (int)min(max(L, 0LL), (long long)nd.wq_die);
+    q.r = (int)min(max(L + c.x, 0LL), (long long)nd.wq_die);
+    q.b = (int)min(max(B, 0LL), (long long)nd.hq_die);
+    q.t = (int)min(max(B + c.y, 0LL), (long long)nd.hq_die);
+    return q;
+}
+
+__device__ __forceinline__ int overlap(int lo, int hi, int idx, int w) {
+    const int a = max(lo, idx * w), b = min(hi, (idx + 1) * w);
+    return b > a ? b - a : 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scatter_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    char *base = sa.base[blockIdx.y];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nd.n_mov) return;
+    const T *x = reinterpret_cast<const T *>(base + L.v);
+    const T *y = x + nd.n_cells;
+    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
+    const RectQ q = cell_rect(nd, (double)x[i], (double)y[i], nd.cq[i]);
+    if (q.r <= q.l || q.t <= q.b) return;
+    const long long rq = nd.rq[i];
+    const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
+    const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
+    for (int k = k0; k <= k1; ++k) {
+        const long long oy = overlap(q.b, q.t, k, nd.hq);
+        for (int j = j0; j <= j1; ++j) {
+            const long long ox = overlap(q.l, q.r, j, nd.bq);
+            atomicAdd(&rho[(size_t)k * nd.mx + j], (unsigned long long)(rq * ox * oy));
+        }
+    }
+}
+
+// Fixed cells: their true rectangle with charge scale 1 (r_q = 2^16), computed once at load.
+__global__ __launch_bounds__(kBlock) void fixed_map_kernel(NetDev nd, const double *fxy,
+                                                           const double *fwh,
+                                                           unsigned long long *rho) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nd.n_fixed) return;
+    const double w = fwh[i], h = fwh[nd.n_fixed + i];
+    if (!(w > 0.0) || !(h > 0.0)) return;  // pads carry no charge
+    int4 c;
+    c.x = (int)q12(w);
+    c.y = (int)q12(h);
+    c.z = 0;
+    c.w = 0;
+    const RectQ q = cell_rect(nd, fxy[i], fxy[nd.n_fixed + i], c);
+    if (q.r <= q.l || q.t <= q.b) return;
+    for (int k = q.b / nd.hq; k <= (q.t - 1) / nd.hq; ++k) {
+        const long long oy = overlap(q.b, q.t, k, nd.hq);
+        for (int j = q.l / nd.bq; j <= (q.r - 1) / nd.bq; ++j) {
+            const long long ox = overlap(q.l, q.r, j, nd.bq);
+            atomicAdd(&rho[(size_t)k * nd.mx + j], (unsigned long long)(65536LL * ox * oy));
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void zero_rho_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    char *base = sa.base[blockIdx.y];
+    int64_t *rho = reinterpret_cast<int64_t *>(base + L.rho);
+    const size_t nb = (size_t)nd.mx * nd.my;
+    for (size_t b = blockIdx.x * (size_t)kBlock + threadIdx.x; b < nb; b += (size_t)gridDim.x * kBlock)
+        rho[b] = 0;
+}
+
+// Fused cell gradient.  Wirelength part: the sum of the cell's pin gradients (fixed pin
+// order -> deterministic).  Density part: the field force, dN/dx_i = -sum_b q_ib xi_x(b),
+// with q_ib the cell's integer charge in bin b.  Steady state writes g = gWL + lambda gD;
+// on a slot's first evaluation (lambda not yet derived) it writes gWL to g and gD to gd and
+// the per-block L1 norms of both, from which lambda_0 is derived.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                           double lam_fixed, int use_fixed) {
+    char *base = sa.base[blockIdx.y];
+    Scalars *sc = scalars(base, L);
+    const bool init = !use_fixed && sc->lambda_valid == 0;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    T gwx = 0, gwy = 0, gdx = 0, gdy = 0;
+    if (i < nd.n_mov) {
+        const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
+        const int e = nd.cell_pin_start[i + 1];
+        for (int j = nd.cell_pin_start[i]; j < e; ++j) {
+            const vec2<T> g = pg[nd.cell_pins[j]];
+            gwx += g.x;
+            gwy += g.y;
+        }
+        const T *x = reinterpret_cast<const T *>(base + L.v);
+        const T *y = x + nd.n_cells;
+        const T *ex = reinterpret_cast<const T *>(base + L.ex);
+        const T *ey = reinterpret_cast<const T *>(base + L.ey);
+        const RectQ q = cell_rect(nd, (double)x[i], (double)y[i], nd.cq[i]);
+        if (q.r > q.l && q.t > q.b) {
+            const long long rq = nd.rq[i];
+            const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
+            const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
+            for (int k = k0; k <= k1; ++k) {
+                const long long oy = overlap(q.b, q.t, k, nd.hq);
+                for (int j = j0; j <= j1; ++j) {
+                    const long long ox = overlap(q.l, q.r, j, nd.bq);
+                    const T qq = (T)((double)(rq * ox * oy) * 0x1p-40);
+                    const size_t b = (size_t)k * nd.mx + j;
+                    gdx -= qq * ex[b];
+                    gdy -= qq * ey[b];
+                }
+            }
+        }
+    }
+    T *g = reinterpret_cast<T *>(base + L.g);
+    if (!init) {
+        const T lam = (T)(use_fixed ? lam_fixed : sc->lambda);
+        if (i < nd.n_mov) {
+            g[i] = gwx + lam * gdx;
+            g[nd.n_mov + i] = gwy + lam * gdy;
+        }
+    } else {
+        T *gd = reinterpret_cast<T *>(base + L.gd);
+        if (i < nd.n_mov) {
+            g[i] = gwx;
+            g[nd.n_mov + i] = gwy;
+            gd[i] = gdx;
+            gd[nd.n_mov + i] = gdy;
+        }
+        __shared__ double red[4];
+        const double n1 = block_sum((double)(fabs(gwx) + fabs(gwy)), red);
+        const double n2 = block_sum((double)(fabs(gdx) + fabs(gdy)), red);
+        if (threadIdx.x == 0) {
+            double *part = reinterpret_cast<double *>(base + L.part);
+            part[PART_N1 * L.pstride + blockIdx.x] = n1;
+            part[PART_N2 * L.pstride + blockIdx.x] = n2;
+        }
+    }
+}
+
+int cell_parts(const NetDev &nd) { return (nd.n_mov + kBlock - 1) / kBlock; }
+
+template <typename T>
+hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                          hipStream_t st) {
+    if (nd.n_mov == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st, nd,
+                       sa, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                            double lambda_fixed, bool use_fixed, bool /*init_mode*/,
+                            hipStream_t st) {
+    if (nd.n_mov == 0) return hipSuccess;
+    hipLaunchKernelGGL(cell_grad_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st,
+                       nd, sa, L, lambda_fixed, (int)use_fixed);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                           hipStream_t st) {
+    const size_t nb = (size_t)nd.mx * nd.my;
+    const int blocks = (int)std::min<size_t>((nb + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(zero_rho_kernel, dim3(blocks, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,
+                            int64_t *rho_fixed, hipStream_t st) {
+    if (nd.n_fixed == 0) return hipSuccess;
+    hipLaunchKernelGGL(fixed_map_kernel, dim3((nd.n_fixed + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, st, nd, fxy, fwh,
+                       reinterpret_cast<unsigned long long *>(rho_fixed));
+    return hipGetLastError();
+}
+
+#define HP_INST(T)                                                                          \
+    template hipError_t launch_scatter<T>(const NetDev &, const SlotArgs &, const SlotLayout &, \
+                                          hipStream_t);                                     \
+    template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
+                                            const SlotLayout &, double, bool, bool,         \
+                                            hipStream_t);                                   \
+    template hipError_t launch_zero_rho<T>(const NetDev &, const SlotArgs &,                \
+                                           const SlotLayout &, hipStream_t);                \
+    template hipError_t launch_fixed_map<T>(const NetDev &, const double *, const double *, \
+                                            int64_t *, hipStream_t);
+HP_INST(float)
+HP_INST(double)
+#undef HP_INST
+
+}  // namespace hp

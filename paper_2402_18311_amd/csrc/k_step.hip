@@ -1,0 +1,283 @@
+// Reductions that close an evaluation, the preconditioned Nesterov step, the HPWL total and
+// the best-of selection of Alg. 1.  Every floating-point total is a fixed-order reduction of
+// per-block partials (thread t sums partials t, t+256, ... then a fixed tree), so repeated
+// runs are bit-identical.
+#include "hp_device.h"
+
+namespace hp {
+
+__device__ double sum_parts(const double *p, int n, double *red) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
+    return block_sum(s, red);
+}
+__device__ double max_parts(const double *p, int n, double *red) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s = fmax(s, p[i]);
+    return block_max(s, red);
+}
+
+// Totals of one evaluation: WL (Eq. 3), energy N, overflow; on a slot's first evaluation
+// (scheduled lambda, not yet derived) lambda_0 = scale * |grad WL|_1 / |grad N|_1.
+__global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                            int nwl, int ne, int ncell,
+                                                            int use_fixed) {
+    __shared__ double red[4];
+    char *base = sa.base[blockIdx.y];
+    Scalars *sc = scalars(base, L);
+    const double *part = reinterpret_cast<const double *>(base + L.part);
+    const bool init = !use_fixed && sc->lambda_valid == 0;
+    const double wl = sum_parts(part + PART_WL * L.pstride, nwl, red);
+    const double e = sum_parts(part + PART_E * L.pstride, ne, red);
+    double n1 = 0.0, n2 = 0.0;
+    if (init) {
+        n1 = sum_parts(part + PART_N1 * L.pstride, ncell, red);
+        n2 = sum_parts(part + PART_N2 * L.pstride, ncell, red);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sc->wl = wl;
+        sc->energy = 0.5 * nd.wb * nd.hb * e;
+        const unsigned long long ov = sc->ovf_acc;
+        sc->overflow_num = (int64_t)ov;
+        sc->overflow = (double)ov / (double)nd.total_charge;
+        sc->ovf_acc = 0;
+        sc->init_this_eval = init ? 1 : 0;
+        if (init) {
+            sc->lambda = sc->lambda0_scale * (n2 > 0.0 ? n1 / n2 : 1.0);
+            sc->lambda_valid = 1;
+        }
+    }
+}
+
+// First evaluation only: g = gWL + lambda_0 gD.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void combine_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    char *base = sa.base[blockIdx.y];
+    const Scalars *sc = scalars(base, L);
+    if (!sc->init_this_eval) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 2 * nd.n_mov) return;
+    T *g = reinterpret_cast<T *>(base + L.g);
+    const T *gd = reinterpret_cast<const T *>(base + L.gd);
+    g[i] += (T)sc->lambda * gd[i];
+}
+
+// ---- Nesterov -------------------------------------------------------------------------------
+// Preconditioner P_i = max(1, pins_i + lambda area_i), g~ = g / P.
+template <typename T>
+__device__ __forceinline__ double precond(const T *cs, int n, int i, double lam) {
+    const double P = (double)cs[i] + lam * (double)cs[n + i];
+    return P < 1.0 ? 1.0 : P;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    __shared__ double red[4];
+    char *base = sa.base[blockIdx.y];
+    const Scalars *sc = scalars(base, L);
+    const int n = nd.n_mov;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double dv = 0.0, dg = 0.0, gm = 0.0;
+    if (i < n) {
+        const T *cs = reinterpret_cast<const T *>(nd.cstep);
+        const double P = precond(cs, n, i, sc->lambda);
+        const T *v = reinterpret_cast<const T *>(base + L.v);
+        const T *vp = reinterpret_cast<const T *>(base + L.vprev);
+        const T *g = reinterpret_cast<const T *>(base + L.g);
+        const T *gp = reinterpret_cast<const T *>(base + L.gprev);
+        const double gx = (double)g[i] / P, gy = (double)g[n + i] / P;
+        const double ax = (double)v[i] - (double)vp[i];
+        const double ay = (double)v[nd.n_cells + i] - (double)vp[n + i];
+        const double bx = gx - (double)gp[i], by = gy - (double)gp[n + i];
+        dv = ax * ax + ay * ay;
+        dg = bx * bx + by * by;
+        gm = fmax(fabs(gx), fabs(gy));
+    }
+    dv = block_sum(dv, red);
+    dg = block_sum(dg, red);
+    gm = block_max(gm, red);
+    if (threadIdx.x == 0) {
+        double *part = reinterpret_cast<double *>(base + L.part);
+        part[PART_DV * L.pstride + blockIdx.x] = dv;
+        part[PART_DG * L.pstride + blockIdx.x] = dg;
+        part[PART_GMAX * L.pstride + blockIdx.x] = gm;
+    }
+}
+
+// alpha_0 = 0.1 bin / max|g~|; alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein);
+// a' = (1 + sqrt(4 a^2 + 1)) / 2, momentum (a - 1) / a'; lambda grows by the schedule ratio.
+__global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                             int ncell) {
+    __shared__ double red[4];
+    char *base = sa.base[blockIdx.y];
+    Scalars *sc = scalars(base, L);
+    const double *part = reinterpret_cast<const double *>(base + L.part);
+    const double dv = sum_parts(part + PART_DV * L.pstride, ncell, red);
+    const double dg = sum_parts(part + PART_DG * L.pstride, ncell, red);
+    const double gm = max_parts(part + PART_GMAX * L.pstride, ncell, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double alpha;
+        if (sc->k == 0)
+            alpha = 0.1 * nd.wb / (gm > 1e-30 ? gm : 1e-30);
+        else
+            alpha = dg > 0.0 ? sqrt(dv) / sqrt(dg) : sc->alpha;
+        const double a = sc->a;
+        const double an = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
+        sc->step_alpha = alpha;
+        sc->step_coef = (a - 1.0) / an;
+        sc->lambda_step = sc->lambda;
+        sc->a = an;
+        sc->alpha = alpha;
+        sc->k += 1;
+        if (sc->lambda_valid) sc->lambda *= sc->lambda_ratio;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    char *base = sa.base[blockIdx.y];
+    const Scalars *sc = scalars(base, L);
+    const int n = nd.n_mov;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const T *cs = reinterpret_cast<const T *>(nd.cstep);
+    const double P = precond(cs, n, i, sc->lambda_step);
+    const double alpha = sc->step_alpha, coef = sc->step_coef;
+    T *u = reinterpret_cast<T *>(base + L.u);
+    T *v = reinterpret_cast<T *>(base + L.v);
+    T *vp = reinterpret_cast<T *>(base + L.vprev);
+    T *g = reinterpret_cast<T *>(base + L.g);
+    T *gp = reinterpret_cast<T *>(base + L.gprev);
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        const size_t ip = (size_t)ax * nd.n_cells + i;  // positions: [2][n_cells]
+        const size_t ig = (size_t)ax * n + i;           // gradients: [2][n_mov]
+        const double hi = (double)cs[(2 + ax) * n + i];
+        const double gt = (double)g[ig] / P;
+        const double vv = (double)v[ip];
+        double un = vv - alpha * gt;
+        un = un < 0.0 ? 0.0 : (un > hi ? hi : un);
+        const T unt = (T)un;
+        double vn = (double)unt + coef * ((double)unt - (double)u[ip]);
+        vn = vn < 0.0 ? 0.0 : (vn > hi ? hi : vn);
+        vp[ig] = v[ip];
+        gp[ig] = (T)gt;
+        u[ip] = unt;
+        v[ip] = (T)vn;
+    }
+}
+
+// ---- HPWL total -----------------------------------------------------------------------------
+__global__ void hpwl_finish_kernel(SlotArgs sa, SlotLayout L) {
+    if (threadIdx.x != 0) return;
+    Scalars *sc = scalars(sa.base[blockIdx.x], L);
+    sc->hpwl_q = (int64_t)sc->hpwl_acc;
+    sc->hpwl_valid = 1;
+    sc->hpwl_acc = 0;
+}
+
+// ---- best of Alg. 1 -------------------------------------------------------------------------
+// Smallest HPWL among the slots (ties to the lowest list position), kept only if strictly
+// better than the incumbent's (ties go to the incumbent).
+__global__ void select_best_kernel(SlotArgs sa, char *inc, SlotLayout L) {
+    if (threadIdx.x != 0) return;
+    int best = -1;
+    int64_t bv = 0;
+    for (int s = 0; s < sa.n; ++s) {
+        const Scalars *c = scalars(sa.base[s], L);
+        if (!c->hpwl_valid) continue;
+        if (best < 0 || c->hpwl_q < bv) {
+            best = s;
+            bv = c->hpwl_q;
+        }
+    }
+    Scalars *is = scalars(inc, L);
+    if (best >= 0 && is->hpwl_valid && is->hpwl_q <= bv) best = -1;
+    is->best = best;
+    if (best >= 0) {
+        is->hpwl_q = bv;
+        is->hpwl_valid = 1;
+        is->k = 0;
+        is->a = 1.0;
+        is->alpha = 0.0;
+        is->lambda_valid = 0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void copy_best_kernel(NetDev nd, SlotArgs sa, char *inc,
+                                                           SlotLayout L) {
+    const int64_t best = scalars(inc, L)->best;
+    if (best < 0) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nd.n_mov) return;
+    const T *su = reinterpret_cast<const T *>(sa.base[best] + L.u);
+    T *u = reinterpret_cast<T *>(inc + L.u);
+    T *v = reinterpret_cast<T *>(inc + L.v);
+    T *vp = reinterpret_cast<T *>(inc + L.vprev);
+    const T x = su[i], y = su[nd.n_cells + i];
+    u[i] = x;
+    u[nd.n_cells + i] = y;
+    v[i] = x;
+    v[nd.n_cells + i] = y;
+    vp[i] = x;
+    vp[nd.n_mov + i] = y;
+}
+
+// ---- launchers ------------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
+                              int ne, int ncell, bool use_fixed, bool any_init, hipStream_t st) {
+    hipLaunchKernelGGL(eval_finish_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa, L, nwl, ne,
+                       ncell, (int)use_fixed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !any_init || nd.n_mov == 0) return e;
+    hipLaunchKernelGGL(combine_kernel<T>, dim3((2 * nd.n_mov + kBlock - 1) / kBlock, sa.n),
+                       dim3(kBlock), 0, st, nd, sa, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, hipStream_t st) {
+    const int nc = cell_parts(nd);
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa, L, nc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, hipStream_t st) {
+    hipLaunchKernelGGL(hpwl_finish_kernel, dim3(sa.n), dim3(64), 0, st, sa, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumbent,
+                              const SlotLayout &L, hipStream_t st) {
+    hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(64), 0, st, sa, incumbent, L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nd.n_mov == 0) return e;
+    hipLaunchKernelGGL(copy_best_kernel<T>, dim3(cell_parts(nd)), dim3(kBlock), 0, st, nd, sa,
+                       incumbent, L);
+    return hipGetLastError();
+}
+
+#define HP_INST(T)                                                                              \
+    template hipError_t launch_eval_finish<T>(const NetDev &, const SlotArgs &, const SlotLayout &, \
+                                              int, int, int, bool, bool, hipStream_t);          \
+    template hipError_t launch_step<T>(const NetDev &, const SlotArgs &, const SlotLayout &,     \
+                                       hipStream_t);                                            \
+    template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \
+                                              const SlotLayout &, hipStream_t);
+HP_INST(float)
+HP_INST(double)
+#undef HP_INST
+
+}  // namespace hp

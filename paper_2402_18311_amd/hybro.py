@@ -1,0 +1,338 @@
+"""Python binding of libhybro (the C ABI of include/hybro.h).
+
+The hp_* functions below have the C names and only marshal arguments; every step of the
+placer runs in the library's HIP kernels.  PyTorch provides the device memory (uint8 tensors
+lent to the library) and the stream.  There is no fallback: if libhybro.so is missing or no
+GPU is present, these calls raise.
+
+`Placer` is a convenience owner of one netlist and its slots.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhybro.so")
+
+HP_OK, HP_EINVAL, HP_ENOMEM, HP_EDEVICE, HP_ESTATE, HP_ENOTIMPL = 0, -1, -2, -3, -4, -5
+HP_PERTURB_GAUSS, HP_PERTURB_SHUFFLE, HP_PERTURB_UNIFORM = 0, 1, 2
+HP_MAP_RHO_MOV, HP_MAP_RHO_FIXED, HP_MAP_PSI, HP_MAP_EX, HP_MAP_EY = 0, 1, 2, 3, 4
+
+
+class hp_die(C.Structure):
+    _fields_ = [("W", C.c_double), ("H", C.c_double), ("mx", C.c_int32), ("my", C.c_int32),
+                ("target_density", C.c_double), ("stretch", C.c_int32), ("fd5", C.c_int32)]
+
+
+class hp_shape(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("n_movable", C.c_int32), ("n_nets", C.c_int32),
+                ("n_pins", C.c_int32)]
+
+
+class hp_eval_params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("lambda_", C.c_double), ("grad_mode", C.c_int32),
+                ("keep_maps", C.c_int32)]
+
+
+class hp_slot_state(C.Structure):
+    _fields_ = [("k", C.c_int64), ("hpwl_q", C.c_int64), ("overflow_num", C.c_int64),
+                ("a", C.c_double), ("alpha", C.c_double), ("lambda_", C.c_double),
+                ("wl", C.c_double), ("energy", C.c_double), ("overflow", C.c_double)]
+
+
+class HybroError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libhybro error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = C.c_void_p
+_SIGS = {
+    "hp_create": [C.POINTER(_P), C.c_int, _P, C.c_int],
+    "hp_destroy": [_P],
+    "hp_last_error": [],
+    "hp_netlist_bytes": [_P, C.POINTER(hp_shape), C.POINTER(hp_die)],
+    "hp_slot_bytes": [_P, C.POINTER(hp_shape), C.POINTER(hp_die)],
+    "hp_load_netlist_csr": [_P, C.POINTER(hp_shape), C.POINTER(hp_die), _P, _P, _P, _P, _P, _P,
+                            _P, _P, _P, _P, C.c_size_t, C.POINTER(C.c_int32)],
+    "hp_slot_alloc": [_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32)],
+    "hp_slot_free": [_P, C.c_int32],
+    "hp_set_positions": [_P, C.c_int32, _P, _P, C.c_int],
+    "hp_get_positions": [_P, C.c_int32, _P, _P, C.c_int],
+    "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
+    "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
+    "hp_nesterov_step": [_P, _P, C.c_int32],
+    "hp_perturb": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P, _P],
+    "hp_hpwl": [_P, _P, C.c_int32, _P, _P],
+    "hp_select_best": [_P, _P, C.c_int32, C.c_int32, _P],
+    "hp_get_map": [_P, C.c_int32, C.c_int, _P],
+    "hp_get_state": [_P, C.c_int32, C.POINTER(hp_slot_state)],
+}
+
+
+def lib():
+    """Load libhybro.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2402_18311_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.hp_last_error.restype = C.c_char_p
+        L.hp_netlist_bytes.restype = C.c_size_t
+        L.hp_slot_bytes.restype = C.c_size_t
+        _lib = L
+    return _lib
+
+
+def _chk(rc):
+    if rc != HP_OK:
+        raise HybroError(rc, lib().hp_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    """Address of a numpy array, a torch tensor, or None."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+# ---- C-ABI functions (same names) -----------------------------------------------------------
+def hp_create(device=0, stream=None, precision=32):
+    ctx = _P()
+    _chk(lib().hp_create(C.byref(ctx), device, stream, precision))
+    return ctx
+
+
+def hp_destroy(ctx):
+    _chk(lib().hp_destroy(ctx))
+
+
+def hp_last_error():
+    return lib().hp_last_error().decode()
+
+
+def hp_netlist_bytes(ctx, shape, die):
+    return lib().hp_netlist_bytes(ctx, C.byref(shape), C.byref(die))
+
+
+def hp_slot_bytes(ctx, shape, die):
+    return lib().hp_slot_bytes(ctx, C.byref(shape), C.byref(die))
+
+
+def hp_load_netlist_csr(ctx, shape, die, cell_w, cell_h, fixed_x, fixed_y, net_start, pin_cell,
+                        pin_ox, pin_oy, net_weight, dev_buf, dev_bytes):
+    out = C.c_int32()
+    _chk(lib().hp_load_netlist_csr(ctx, C.byref(shape), C.byref(die), _ptr(cell_w), _ptr(cell_h),
+                                   _ptr(fixed_x), _ptr(fixed_y), _ptr(net_start), _ptr(pin_cell),
+                                   _ptr(pin_ox), _ptr(pin_oy), _ptr(net_weight), dev_buf,
+                                   dev_bytes, C.byref(out)))
+    return out.value
+
+
+def hp_slot_alloc(ctx, netlist, dev_buf, dev_bytes):
+    out = C.c_int32()
+    _chk(lib().hp_slot_alloc(ctx, netlist, dev_buf, dev_bytes, C.byref(out)))
+    return out.value
+
+
+def hp_slot_free(ctx, slot):
+    _chk(lib().hp_slot_free(ctx, slot))
+
+
+def hp_set_positions(ctx, slot, x, y, on_device):
+    _chk(lib().hp_set_positions(ctx, slot, _ptr(x), _ptr(y), int(on_device)))
+
+
+def hp_get_positions(ctx, slot, x, y, on_device):
+    _chk(lib().hp_get_positions(ctx, slot, _ptr(x), _ptr(y), int(on_device)))
+
+
+def hp_set_schedule(ctx, slot, lambda0_scale, decades, total_iters):
+    _chk(lib().hp_set_schedule(ctx, slot, lambda0_scale, decades, total_iters))
+
+
+def _slots(slots):
+    a = np.ascontiguousarray(np.atleast_1d(slots), dtype=np.int32)
+    return a, a.ctypes.data, len(a)
+
+
+def hp_eval_objective_grad(ctx, slots, gamma, lam=-1.0, grad_mode=0, keep_maps=False,
+                           want_host=True, grad_x=None, grad_y=None):
+    a, p, n = _slots(slots)
+    prm = hp_eval_params(float(gamma), float(lam), int(grad_mode), int(keep_maps))
+    wl = np.zeros(n) if want_host else None
+    en = np.zeros(n) if want_host else None
+    ov = np.zeros(n) if want_host else None
+    _chk(lib().hp_eval_objective_grad(ctx, p, n, C.byref(prm), _ptr(wl), _ptr(en), _ptr(ov),
+                                      _ptr(grad_x), _ptr(grad_y)))
+    return (wl, en, ov) if want_host else None
+
+
+def hp_nesterov_step(ctx, slots):
+    a, p, n = _slots(slots)
+    _chk(lib().hp_nesterov_step(ctx, p, n))
+
+
+def hp_perturb(ctx, slot, mode, fraction, sigma_bins, seed, n_movable, want_idx=True):
+    """Returns the moved cells' indices (ascending), or their count if want_idx is False."""
+    cnt = C.c_int32()
+    buf = np.zeros(max(1, n_movable), dtype=np.int32) if want_idx else None
+    _chk(lib().hp_perturb(ctx, slot, int(mode), float(fraction), float(sigma_bins),
+                          C.c_uint64(int(seed) & (2**64 - 1)), _ptr(buf), C.byref(cnt)))
+    return buf[: cnt.value].copy() if want_idx else cnt.value
+
+
+def hp_hpwl(ctx, slots, want_host=True):
+    a, p, n = _slots(slots)
+    q = np.zeros(n, dtype=np.int64) if want_host else None
+    _chk(lib().hp_hpwl(ctx, p, n, _ptr(q), None))
+    return q
+
+
+def hp_select_best(ctx, slots, incumbent, want_host=True):
+    a, p, n = _slots(slots)
+    out = C.c_int32(-2)
+    _chk(lib().hp_select_best(ctx, p, n, incumbent, C.byref(out) if want_host else None))
+    return out.value if want_host else None
+
+
+def hp_get_map(ctx, slot, which, shape, dtype):
+    dst = np.zeros(shape, dtype=dtype)
+    _chk(lib().hp_get_map(ctx, slot, int(which), dst.ctypes.data))
+    return dst
+
+
+def hp_get_state(ctx, slot):
+    s = hp_slot_state()
+    _chk(lib().hp_get_state(ctx, slot, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in hp_slot_state._fields_}
+
+
+# ---- convenience owner -----------------------------------------------------------------------
+class Placer:
+    """One netlist on the GPU with any number of slots (placement instances).
+
+    Buffers are torch uint8 tensors on `device`; the library runs on torch's current stream
+    of that device at construction time."""
+
+    def __init__(self, nl, precision=32, device=0, stretch=True, fd5=False,
+                 target_density=1.0, net_weight=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libhybro needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.nl = nl
+        self.precision = precision
+        self.dtype = np.float32 if precision == 32 else np.float64
+        self.tdtype = torch.float32 if precision == 32 else torch.float64
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.ctx = hp_create(device, C.c_void_p(self.stream.cuda_stream), precision)
+        self.shape = hp_shape(nl.n_cells, nl.n_movable, int(len(nl.net_start) - 1),
+                              int(len(nl.pin_cell)))
+        self.die = hp_die(float(nl.W), float(nl.H), int(nl.mx), int(nl.my),
+                          float(target_density), int(stretch), int(fd5))
+        nb = hp_netlist_bytes(self.ctx, self.shape, self.die)
+        if nb == 0:
+            raise HybroError(HP_EINVAL, hp_last_error())
+        self._netbuf = self._alloc(nb)
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)  # noqa: E731
+        self._keep = [f64(nl.cell_w), f64(nl.cell_h), f64(nl.fixed_x), f64(nl.fixed_y),
+                      i32(nl.net_start), i32(nl.pin_cell), f64(nl.pin_ox), f64(nl.pin_oy),
+                      None if net_weight is None else f64(net_weight)]
+        k = self._keep
+        self.netlist = hp_load_netlist_csr(self.ctx, self.shape, self.die, *k,
+                                           self._netbuf.data_ptr(), nb)
+        self.slot_bytes = hp_slot_bytes(self.ctx, self.shape, self.die)
+        self._slotbufs = {}
+
+    def _alloc(self, nbytes):
+        t = self.torch.empty(int(nbytes) + 256, dtype=self.torch.uint8, device=self.dev)
+        off = (-t.data_ptr()) % 256
+        return t[off: off + int(nbytes)]
+
+    def new_slot(self):
+        buf = self._alloc(self.slot_bytes)
+        s = hp_slot_alloc(self.ctx, self.netlist, buf.data_ptr(), self.slot_bytes)
+        self._slotbufs[s] = buf
+        return s
+
+    def free_slot(self, s):
+        hp_slot_free(self.ctx, s)
+        self._slotbufs.pop(s, None)
+
+    def set_positions(self, s, x, y):
+        if isinstance(x, np.ndarray):
+            hp_set_positions(self.ctx, s, np.ascontiguousarray(x, self.dtype),
+                             np.ascontiguousarray(y, self.dtype), False)
+        else:
+            hp_set_positions(self.ctx, s, x.contiguous(), y.contiguous(), True)
+
+    def positions(self, s):
+        x = np.zeros(self.nl.n_movable, self.dtype)
+        y = np.zeros(self.nl.n_movable, self.dtype)
+        hp_get_positions(self.ctx, s, x, y, False)
+        return x, y
+
+    def set_schedule(self, s, lambda0_scale=1e-4, decades=4.0, total_iters=1000):
+        hp_set_schedule(self.ctx, s, lambda0_scale, decades, total_iters)
+
+    def eval(self, slots, gamma, lam=-1.0, keep_maps=False, grads=False, want_host=True):
+        slots = list(np.atleast_1d(slots))
+        gx = gy = None
+        if grads:
+            gx = self.torch.empty((len(slots), self.nl.n_movable), dtype=self.tdtype, device=self.dev)
+            gy = self.torch.empty_like(gx)
+        r = hp_eval_objective_grad(self.ctx, slots, gamma, lam, 0, keep_maps, want_host, gx, gy)
+        if grads:
+            return r, gx, gy
+        return r
+
+    def step(self, slots):
+        hp_nesterov_step(self.ctx, list(np.atleast_1d(slots)))
+
+    def hpwl(self, slots, want_host=True):
+        return hp_hpwl(self.ctx, list(np.atleast_1d(slots)), want_host)
+
+    def perturb(self, s, mode, fraction, sigma_bins, seed, want_idx=True):
+        return hp_perturb(self.ctx, s, mode, fraction, sigma_bins, seed, self.nl.n_movable,
+                          want_idx)
+
+    def select_best(self, slots, incumbent, want_host=True):
+        return hp_select_best(self.ctx, list(np.atleast_1d(slots)), incumbent, want_host)
+
+    def map(self, s, which):
+        sh = (self.nl.my, self.nl.mx)
+        dt = np.int64 if which in (HP_MAP_RHO_MOV, HP_MAP_RHO_FIXED) else self.dtype
+        return hp_get_map(self.ctx, s, which, sh, dt)
+
+    def state(self, s):
+        return hp_get_state(self.ctx, s)
+
+    def run(self, slots, iters, gamma, hpwl_every=0):
+        """iters x [evaluate at v, Nesterov step] on the slots; returns HPWL_q trace if asked."""
+        trace = []
+        for it in range(iters):
+            self.eval(slots, gamma, want_host=False)
+            self.step(slots)
+            if hpwl_every and (it + 1) % hpwl_every == 0:
+                trace.append(self.hpwl(slots))
+        return trace
+
+    def close(self):
+        if self.ctx is not None:
+            hp_destroy(self.ctx)
+            self.ctx = None

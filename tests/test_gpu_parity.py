@@ -1,0 +1,259 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Integer outputs (HPWL, charge maps, overflow numerator, perturbation indices) must match bit
+for bit.  Float tolerances: FP32 path, 1e-5 relative on the wirelength and energy totals and
+1e-4 relative L2 on gradients and fields; FP64 path, the same quantities to 1e-10 (only the
+summation order differs from the oracle).
+"""
+import numpy as np
+import pytest
+
+from paper_2402_18311_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {32: dict(tot=1e-5, l2=1e-4), 64: dict(tot=1e-10, l2=1e-10)}
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def hy():
+    from paper_2402_18311_amd import hybro
+    return hybro
+
+
+_CASES = {
+    "tiny": lambda: netgen.make_netlist("tiny", 0),
+    # several tiles of every kernel, ragged tails, nets up to 2000 pins, 500 macros
+    "small": lambda: netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40),
+    "mid": lambda: netgen.make_netlist("mid", 0),
+}
+_cache = {}
+
+
+def setup(hy, orc, case, prec):
+    key = (case, prec)
+    if key not in _cache:
+        nl = _CASES[case]()
+        _cache[key] = (nl, hy.Placer(nl, precision=prec), orc.Oracle(nl))
+    return _cache[key]
+
+
+PARAMS = [("tiny", 64), ("tiny", 32), ("small", 32), ("small", 64), ("mid", 32)]
+
+
+@pytest.mark.parametrize("case,prec", PARAMS)
+def test_hpwl_bitexact(hy, orc, case, prec):
+    nl, pl, o = setup(hy, orc, case, prec)
+    s = pl.new_slot()
+    for seed in range(2):
+        x, y = nl.random_positions(seed)
+        pl.set_positions(s, x, y)
+        q1 = pl.hpwl(s)[0]
+        q2 = pl.hpwl(s)[0]
+        assert q1 == q2 == o.hpwl_q(x, y)
+    pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", PARAMS)
+def test_eval_parity(hy, orc, case, prec):
+    """WL (Eq. 3), charge maps, overflow, potential/field, energy, gradients."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    tol = TOL[prec]
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    lam = 0.37
+    (wl, en, ov), gx, gy = pl.eval(s, gamma, lam=lam, keep_maps=True, grads=True)
+    ref = o.eval(nl.x0, nl.y0, gamma, maps=True)
+    assert np.array_equal(pl.map(s, hy.HP_MAP_RHO_MOV), ref["rho_mov"])
+    assert np.array_equal(pl.map(s, hy.HP_MAP_RHO_FIXED), ref["rho_fixed"])
+    st = pl.state(s)
+    assert st["overflow_num"] == ref["overflow_num"]
+    assert ov[0] == pytest.approx(ref["overflow"], rel=1e-15)
+    assert wl[0] == pytest.approx(ref["wl"], rel=tol["tot"])
+    assert en[0] == pytest.approx(ref["energy"], rel=tol["tot"])
+    for which, key in ((hy.HP_MAP_PSI, "psi"), (hy.HP_MAP_EX, "ex"), (hy.HP_MAP_EY, "ey")):
+        assert rel_l2(pl.map(s, which), ref[key]) < tol["l2"], key
+    g = np.concatenate([gx.cpu().numpy()[0], gy.cpu().numpy()[0]])
+    gref = np.concatenate([ref["gwx"] + lam * ref["gdx"], ref["gwy"] + lam * ref["gdy"]])
+    assert rel_l2(g, gref) < tol["l2"]
+    # the wirelength part alone (lambda = 0)
+    (wl0, _, _), gx0, gy0 = pl.eval(s, gamma, lam=0.0, grads=True)
+    assert wl0[0] == pytest.approx(ref["wl"], rel=tol["tot"])
+    g0 = np.concatenate([gx0.cpu().numpy()[0], gy0.cpu().numpy()[0]])
+    assert rel_l2(g0, np.concatenate([ref["gwx"], ref["gwy"]])) < tol["l2"]
+    pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32)])
+def test_maps_cleared_and_deterministic(hy, orc, case, prec):
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    x, y = nl.random_positions(11)
+    pl.set_positions(s, x, y)
+    outs = []
+    for keep in (False, True, True, False, True):
+        (wl, en, ov), gx, gy = pl.eval(s, gamma, lam=1.0, keep_maps=keep, grads=True)
+        outs.append((wl[0], en[0], ov[0], gx.cpu().numpy().tobytes(), gy.cpu().numpy().tobytes()))
+    assert all(t == outs[0] for t in outs)  # bit-identical run to run, map reused correctly
+    rm, _ = o.density_q(x, y)
+    assert np.array_equal(pl.map(s, hy.HP_MAP_RHO_MOV), rm)
+    pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("tiny", 32), ("small", 32)])
+def test_lambda_init_and_nesterov_steps(hy, orc, case, prec):
+    """First evaluation derives lambda_0; three [eval, step] iterations follow the oracle."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    n = nl.n_movable
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    pl.set_schedule(s, 1e-4, 4.0, 200)
+    st = o.new_state(nl.x0, nl.y0)
+    ratio = o.lambda_ratio(4.0, 200)
+    lam = None
+    tol = 1e-10 if prec == 64 else 2e-5
+    for it in range(3):
+        (wl, en, ov), gx, gy = pl.eval(s, gamma, grads=True)
+        ref = o.eval(st["v"][:n], st["v"][n:], gamma)
+        gw = np.concatenate([ref["gwx"], ref["gwy"]])
+        gd = np.concatenate([ref["gdx"], ref["gdy"]])
+        if it == 0:
+            lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum()
+        else:
+            lam *= ratio
+        assert pl.state(s)["lambda_"] == pytest.approx(lam, rel=1e-12 if prec == 64 else 1e-5)
+        g = np.concatenate([gx.cpu().numpy()[0], gy.cpu().numpy()[0]])
+        assert rel_l2(g, gw + lam * gd) < TOL[prec]["l2"]
+        pl.step(s)
+        o.nesterov_step(lam, gw + lam * gd, st)
+        x, y = pl.positions(s)
+        u = np.concatenate([x, y]).astype(np.float64)
+        assert np.max(np.abs(u - st["u"])) < tol * nl.W, it
+        sd = pl.state(s)
+        assert sd["k"] == st["k"] and sd["a"] == pytest.approx(st["a"], rel=1e-14)
+        assert sd["alpha"] == pytest.approx(st["alpha"], rel=1e-9 if prec == 64 else 2e-3)
+    pl.free_slot(s)
+
+
+def test_tiny_fp64_placement_matches_oracle(hy, orc):
+    """200 iterations of the plain method on the tiny netlist in FP64."""
+    nl, pl, o = setup(hy, orc, "tiny", 64)
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    pl.set_schedule(s, 1e-4, 4.0, 200)
+    pl.run(s, 200, gamma)
+    hq = pl.hpwl(s)[0]
+    x, y, tr = o.place(nl.x0, nl.y0, 200, gamma, 1e-4, 4.0)
+    ref = tr["hpwl_q"][-1]
+    print(f"tiny fp64 final HPWL gpu={hq / 65536:.6f} oracle={ref / 65536:.6f}")
+    assert abs(hq - ref) <= 1e-6 * ref
+    gx, gy = pl.positions(s)
+    assert np.max(np.abs(gx - x)) < 1e-5 * nl.W and np.max(np.abs(gy - y)) < 1e-5 * nl.H
+    pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
+@pytest.mark.parametrize("mode,frac", [(0, 0.05), (0, 0.5), (1, 0.5), (2, 0.0)])
+def test_perturb_parity(hy, orc, case, prec, mode, frac):
+    nl, pl, o = setup(hy, orc, case, prec)
+    s = pl.new_slot()
+    x0, y0 = nl.random_positions(5)
+    pl.set_positions(s, x0, y0)
+    seed = 0x1234_5678_9ABC_DEF0 + mode
+    idx = pl.perturb(s, mode, frac, 8.0, seed)
+    x, y = pl.positions(s)
+    rx, ry, ridx = o.perturb(x0, y0, mode, frac, 8.0, seed)
+    assert np.array_equal(idx, ridx)
+    # displacements use each platform's own log/cos/sin; FP32 stores round the result
+    tol = 1e-9 * nl.W if prec == 64 else 4e-7 * nl.W
+    assert np.max(np.abs(x - rx)) < tol and np.max(np.abs(y - ry)) < tol
+    # the optimiser restarted at the perturbed placement
+    assert pl.state(s)["k"] == 0
+    pl.free_slot(s)
+
+
+def test_perturb_edge_counts(hy, orc):
+    nl, pl, o = setup(hy, orc, "tiny", 64)
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    assert len(pl.perturb(s, 0, 0.0, 8.0, 1)) == 0
+    assert np.array_equal(pl.perturb(s, 0, 1.0, 8.0, 2), np.arange(nl.n_movable))
+    one = pl.perturb(s, 1, 1.0 / nl.n_movable, 0.0, 3)
+    assert len(one) == 1
+    pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32)])
+def test_batched_slots_equal_single(hy, orc, case, prec):
+    """K slots in one launch give the same bits as each slot alone."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    K = 5
+    ss = [pl.new_slot() for _ in range(K)]
+    for k, s in enumerate(ss):
+        pl.set_positions(s, *nl.random_positions(100 + k))
+    pl.run(ss, 7, gamma)
+    batched = [pl.positions(s) for s in ss]
+    hb = pl.hpwl(ss)
+    for k, s in enumerate(ss):
+        pl.set_positions(s, *nl.random_positions(100 + k))
+        pl.run(s, 7, gamma)
+        x, y = pl.positions(s)
+        assert np.array_equal(x, batched[k][0]) and np.array_equal(y, batched[k][1])
+        assert pl.hpwl(s)[0] == hb[k]
+    for s in ss:
+        pl.free_slot(s)
+
+
+def test_select_best(hy, orc):
+    nl, pl, o = setup(hy, orc, "tiny", 64)
+    inc = pl.new_slot()
+    cands = [pl.new_slot() for _ in range(4)]
+    pos = [nl.random_positions(200 + k) for k in range(4)]
+    for s, p in zip(cands, pos):
+        pl.set_positions(s, *p)
+    pl.set_positions(inc, *nl.random_positions(300))
+    hq = pl.hpwl(cands)
+    hi = pl.hpwl(inc)[0]
+    want = o.hpwl_q(*pos[int(np.argmin(hq))])
+    assert want == hq.min()
+    b = pl.select_best(cands, inc)
+    if hq.min() < hi:
+        assert b == int(np.argmin(hq))  # argmin ties to the lowest index
+        x, y = pl.positions(inc)
+        assert np.array_equal(x, pos[b][0]) and np.array_equal(y, pos[b][1])
+        assert pl.hpwl(inc)[0] == hq.min()
+    else:
+        assert b == -1
+    # the incumbent now holds the best; a second selection keeps it (ties go to it)
+    assert pl.select_best(cands, inc) == -1
+    for s in cands + [inc]:
+        pl.free_slot(s)
+
+
+def test_errors(hy, orc):
+    nl, pl, o = setup(hy, orc, "tiny", 64)
+    with pytest.raises(hy.HybroError) as e:
+        pl.eval([12345], 1.0)
+    assert e.value.code == hy.HP_ESTATE
+    s = pl.new_slot()
+    with pytest.raises(hy.HybroError) as e:
+        pl.eval(s, -1.0)
+    assert e.value.code == hy.HP_EINVAL
+    with pytest.raises(hy.HybroError) as e:
+        hy.hp_eval_objective_grad(pl.ctx, [s], 1.0, grad_mode=1)
+    assert e.value.code == hy.HP_ENOTIMPL
+    with pytest.raises(hy.HybroError) as e:
+        pl.map(s, hy.HP_MAP_PSI)  # no kept maps yet
+    assert e.value.code == hy.HP_ESTATE
+    pl.free_slot(s)
