@@ -1,0 +1,208 @@
+"""Benchmark of the placer hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid] [--no-cpu-baseline]
+
+Workload: the "mid" synthetic netlist (210,000 movable unit-height cells, 500 fixed macros on
+20% of the die, 220,000 nets with 0.1% of 200-2000 pins, 512 x 512 bins, FP32), shaped like
+the adaptec1 design of Table 1.  One step is one iteration of the placer: the objective and
+gradient of Eq. 2 (WA wirelength of Eq. 3, charge scatter, Poisson solve, field gather), the
+preconditioned Nesterov step, and the exact HPWL of Eq. 1 with the overflow.  The timed region
+is one Hybro round (Alg. 1) on that netlist: perturb the incumbent (Gaussian, 5% of the cells,
+sigma = 8 bins), K placer iterations, then keep the better of the result and the incumbent.
+
+Prints one JSON line: iterations/s, per-step milliseconds, the roofline of the dominant kernel
+(algorithmic bytes / its average duration from HIP events recorded around every launch in the
+timed region) and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("placer iters/sec + HBM GB/s; batched-vs-plain restarts/sec, p50/p99 at equal HPWL")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(nl, rs=4):
+    """Compulsory bytes each kernel must move per launch (each input read once, each output
+    written once), for one slot.  Intermediates count for the kernel that produces or consumes
+    them."""
+    deg = np.diff(nl.net_start)
+    E2 = int(np.sum(deg >= 2))
+    P2 = int(np.sum(deg[deg >= 2]))
+    N, Nall = nl.n_movable, nl.n_cells
+    Pm = int(np.sum(nl.pin_cell[np.repeat(deg >= 2, deg)] < N))
+    M2 = nl.mx * nl.my
+    return {
+        # net_start, pin cell ids, pin offsets, every cell position once, pin gradients out
+        "sweep_wa": 4 * (E2 + 1) + 4 * P2 + 2 * rs * P2 + 2 * rs * Nall + 2 * rs * P2,
+        # net_start, pin cell ids, quantized offsets, positions
+        "sweep_hpwl": 4 * (E2 + 1) + 4 * P2 + 8 * P2 + 2 * rs * Nall,
+        # positions, charge constants (16 + 4 B), the int64 map written once
+        "scatter_kernel": 2 * rs * N + 20 * N + 8 * M2,
+        # cell CSR, pin gradients, positions, charge constants, two field maps, gradient out
+        "cell_grad_kernel": 4 * (N + 1) + 4 * Pm + 2 * rs * Pm + 2 * rs * N + 20 * N
+        + 2 * rs * M2 + 2 * rs * N,
+        # movable + fixed int64 maps in, row transform out, movable map cleared
+        "spec_rows_fwd": 8 * M2 + 8 * M2 + rs * M2 + 8 * M2,
+        "spec_cols": rs * M2 + 2 * rs * M2,
+        "spec_rows_inv": 2 * rs * M2 + 2 * rs * M2,
+        # v, v_prev, g, g_prev, pins + area
+        "step_norms_kernel": 4 * 2 * rs * N + 2 * rs * N,
+        # pins, area, clamp bounds, v, u, g in; u, v, v_prev, g_prev out
+        "step_update_kernel": 4 * rs * N + 3 * 2 * rs * N + 4 * 2 * rs * N,
+    }
+
+
+def cpu_baseline(nl, gamma, budget_s=20.0, max_iters=12):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: whole placer
+    iterations (objective + gradient, Nesterov step, exact HPWL) from the initial positions."""
+    from oracle import oracle as O
+    o = O.Oracle(nl)
+    n = nl.n_movable
+    st = o.new_state(nl.x0, nl.y0)
+    ratio = o.lambda_ratio(4.0, 1000)
+    lam = None
+    t0 = time.perf_counter()
+    it = 0
+    while it < max_iters:
+        r = o.eval(st["v"][:n], st["v"][n:], gamma)
+        gw = np.concatenate([r["gwx"], r["gwy"]])
+        gd = np.concatenate([r["gdx"], r["gdy"]])
+        lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum() if lam is None else lam * ratio
+        o.nesterov_step(lam, gw + lam * gd, st)
+        o.hpwl_q(st["u"][:n], st["u"][n:])
+        it += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": it / dt, "unit": "iter/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{it} placer iterations (objective+gradient, Nesterov step, exact HPWL) "
+                      f"of the mid workload from its initial placement, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without the per-launch events (no roofline)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs the placer on a single MI355X; "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2402_18311_amd import hybro as hy
+    from paper_2402_18311_amd import netgen
+    if not os.path.exists(hy.LIB_PATH):
+        from paper_2402_18311_amd import build as b
+        b.build()
+
+    nl = netgen.make_netlist(args.workload, args.seed)
+    gamma = 4 * nl.bin_w
+    K, W = args.steps, args.warmup
+    pl = hy.Placer(nl, precision=32)
+    work, inc = pl.new_slot(), pl.new_slot()
+    pl.set_positions(work, nl.x0, nl.y0)
+    pl.set_schedule(work, 1e-4, 4.0, max(K, W, 1))
+
+    def iteration():
+        pl.eval(work, gamma, want_host=False)
+        pl.step(work)
+        pl.hpwl(work, want_host=False)
+
+    log(f"[bench] {nl.name}: {nl.n_movable} movable, {nl.n_fixed} fixed, {nl.n_nets} nets, "
+        f"{nl.n_pins} pins, {nl.mx}x{nl.my} bins; warmup {W}, steps {K}")
+    for _ in range(W):
+        iteration()
+    pl.hpwl(work)
+    pl.select_best([work], inc)  # the incumbent starts as the warmed-up placement
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+
+    if not args.no_profile:
+        hy.hp_profile_enable(pl.ctx, True)
+        hy.hp_profile_read(pl.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0xC0FFEE, want_idx=False)
+    pl.set_schedule(work, 1e-4, 4.0, K)
+    for _ in range(K):
+        iteration()
+    best = pl.select_best([work], inc, want_host=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {}
+    if not args.no_profile:
+        prof = hy.hp_profile_read(pl.ctx, reset=True)
+        hy.hp_profile_enable(pl.ctx, False)
+    del best
+    final = pl.state(inc)
+    log(f"[bench] timed {K} iterations in {dt:.3f} s; incumbent HPWL "
+        f"{final['hpwl_q'] / 65536:.1f}")
+
+    ab = algorithmic_bytes(nl)
+    kernels = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1), "total_ms": ms}
+               for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    roof = None
+    if prof:
+        dom = next(iter(kernels))
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        b = ab.get(dom)
+        if b is not None:
+            achieved = b / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": dom, "algorithmic_bytes": int(b),
+                    "avg_us": round(kernels[dom]["avg_us"], 2)}
+        for k, v in kernels.items():
+            if k in ab:
+                v["algorithmic_gbs"] = round(ab[k] / (v["avg_us"] * 1e-6) / 1e9, 1)
+    it_bytes = sum(ab[k] for k in ("sweep_wa", "scatter_kernel", "cell_grad_kernel",
+                                   "spec_rows_fwd", "spec_cols", "spec_rows_inv",
+                                   "step_norms_kernel", "step_update_kernel", "sweep_hpwl"))
+    ms_step = 1e3 * dt / K
+    out = {
+        "metric": METRIC, "value": round(K / dt, 2), "unit": "iter/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{nl.name}: {nl.n_movable} movable cells, {nl.n_fixed} fixed "
+                               f"macros (20% of die), {nl.n_nets} nets / {nl.n_pins} pins, "
+                               f"{nl.mx}x{nl.my} bins, gamma = 4 bins, one Hybro round "
+                               f"(Gaussian perturb 5%, sigma 8 bins) of {K} iterations",
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "hbm_gbps_algorithmic": round(it_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "profiled": not args.no_profile,
+        "final_hpwl": final["hpwl_q"] / 65536,
+        "roofline": roof,
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
+                        for kk, vv in v.items()} for k, v in kernels.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(nl, gamma)
+    pl.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -961,3 +961,11 @@ int32_t orc_argmin_i64(const int64_t *v, int32_t n)
         if (b < 0 || v[i] < v[b]) b = i;
     return b;
 }
+
+/* Threads the oracle's parallel loops use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif

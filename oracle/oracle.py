@@ -90,6 +90,7 @@ def lib():
             "orc_shuffle_perm": (u64, [u64, u64, u64]),
             "orc_perturb": (i32, [P, P, P, C.c_int, d, d, u64, P]),
             "orc_argmin_i64": (i32, [P, i32]),
+            "orc_num_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -285,6 +286,10 @@ def splitmix(seed, i):
 
 def shuffle_perm(j, m, seed):
     return int(lib().orc_shuffle_perm(j, m, seed & (2**64 - 1)))
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def argmin_i64(v):

@@ -144,6 +144,7 @@ struct hp_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     int precision = 32;
+    int lds_budget = 65536;
     std::vector<Netlist> nets;
     std::vector<Slot> slots;
 };
@@ -236,6 +237,9 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.density_unit = std::ldexp(1.0, -40) / (nd.wb * nd.hb);
     nd.area_q = (int64_t)nd.bq * nd.hq * 65536;
     nd.target_density = D.target_density;
+    nd.lds_budget = ctx->lds_budget;
+    if (spectral_max_lds<T>(nd) > (size_t)nd.lds_budget)
+        return fail(HP_EINVAL, "bin grid too large for this device's LDS at this precision");
 
     // ---- degree buckets -------------------------------------------------------------------
     // order: block-per-net (largest first), then groups of 64, 32, ..., 2 lanes
@@ -519,7 +523,7 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0, p->keep_maps != 0, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, false, st));
         HP_CHECK(launch_eval_finish<T>(nd, sa, L, NL->bk.total_blocks, NL->e_parts, cell_parts(nd),
-                                       use_fixed, any_init, st));
+                                       use_fixed, use_fixed ? p->lambda : 0.0, any_init, st));
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];
             s->map_dirty = p->keep_maps != 0;
@@ -558,8 +562,75 @@ void init_scalars(Scalars &s, double scale, double decades, int iters) {
 
 }  // namespace
 
+// ---- per-kernel timing (process-wide; used from one thread) --------------------------------
+namespace hp {
+namespace {
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+struct ProfAcc {
+    std::string name;
+    int64_t count = 0;
+    double ms = 0.0;
+};
+std::vector<ProfAcc> g_prof_acc;
+}  // namespace
+bool prof_on() { return g_prof_on; }
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+void prof_push(const char *name, hipEvent_t a, hipEvent_t b) { g_prof_pending.push_back({name, a, b}); }
+}  // namespace hp
+
 // ============================================================================================
 extern "C" {
+
+int hp_profile_enable(hp_ctx *ctx, int on) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    hp::g_prof_on = on != 0;
+    return HP_OK;
+}
+
+int hp_profile_read(hp_ctx *ctx, hp_kernel_time *out, int32_t max, int32_t *n_out, int reset) {
+    if (!ctx || !n_out) return fail(HP_EINVAL, "ctx/n_out is NULL");
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    HP_CHECK(hipDeviceSynchronize());
+    for (const ProfRec &r : hp::g_prof_pending) {
+        float ms = 0.f;
+        HP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+        auto it = std::find_if(hp::g_prof_acc.begin(), hp::g_prof_acc.end(),
+                               [&](const hp::ProfAcc &a) { return a.name == r.name; });
+        if (it == hp::g_prof_acc.end()) {
+            hp::g_prof_acc.push_back({r.name, 0, 0.0});
+            it = hp::g_prof_acc.end() - 1;
+        }
+        it->count += 1;
+        it->ms += ms;
+        hp::g_prof_pool.push_back(r.a);
+        hp::g_prof_pool.push_back(r.b);
+    }
+    hp::g_prof_pending.clear();
+    int32_t n = 0;
+    for (const hp::ProfAcc &a : hp::g_prof_acc) {
+        if (out && n < max) {
+            std::memset(&out[n], 0, sizeof(hp_kernel_time));
+            std::strncpy(out[n].name, a.name.c_str(), sizeof(out[n].name) - 1);
+            out[n].count = a.count;
+            out[n].total_ms = a.ms;
+        }
+        ++n;
+    }
+    *n_out = n;
+    if (reset) hp::g_prof_acc.clear();
+    return HP_OK;
+}
 
 const char *hp_last_error(void) { return g_err.c_str(); }
 
@@ -570,14 +641,23 @@ int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
     HP_CHECK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(HP_EINVAL, "no such device");
     HP_CHECK(hipSetDevice(device));
-    if (precision == 32)
-        HP_CHECK(spectral_prepare<float>());
-    else
-        HP_CHECK(spectral_prepare<double>());
+    // LDS a block may take: the device limit if the runtime lets the spectral passes opt in
+    // to more than the 64 KB default, else 64 KB
+    int lds = 65536;
+    HP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    if (lds > 65536) {
+        const hipError_t e = precision == 32 ? spectral_prepare<float>(lds)
+                                             : spectral_prepare<double>(lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            lds = 65536;
+        }
+    }
     hp_ctx *c = new hp_ctx;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->precision = precision;
+    c->lds_budget = lds;
     *out = c;
     return HP_OK;
 }

@@ -47,6 +47,7 @@ struct NetDev {
     const void *fixed_pos;         // T [2][n_fixed]
     const void *cell_wh;           // T [2][n_mov] movable cell sizes
     int32_t n_cells, n_mov, n_fixed, ns, ps;
+    int32_t lds_budget;            // dynamic LDS bytes a block may use on this device
     int32_t mx, my, logmx, logmy;
     int32_t bq, hq, wq_die, hq_die; // bin size and die size in 2^-12 units
     double W, H, wb, hb;
@@ -103,6 +104,30 @@ __host__ __device__ inline Scalars *scalars(char *base, const SlotLayout &L) {
     return reinterpret_cast<Scalars *>(base + L.scal);
 }
 
+// ---- optional per-kernel timing --------------------------------------------------------------
+// When enabled, every launch is bracketed by two HIP events on its stream; the elapsed times
+// are collected by hp_profile_read.
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+bool prof_on();
+hipEvent_t prof_event();
+void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
+
+#define HP_LAUNCH(NAME, K, GRID, BLOCK, SHMEM, STREAM, ...)                              \
+    do {                                                                                \
+        if (::hp::prof_on()) {                                                          \
+            hipEvent_t ea_ = ::hp::prof_event(), eb_ = ::hp::prof_event();              \
+            (void)hipEventRecord(ea_, STREAM);                                          \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);              \
+            (void)hipEventRecord(eb_, STREAM);                                          \
+            ::hp::prof_push(NAME, ea_, eb_);                                            \
+        } else {                                                                        \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);              \
+        }                                                                               \
+    } while (0)
+
 // ---- launchers (each returns hipError_t of the launch) -----------------------------------
 template <typename T>
 hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
@@ -122,11 +147,12 @@ hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayo
                             hipStream_t st);
 template <typename T>
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
-                              int ne, int ncell, bool use_fixed, bool any_init, hipStream_t st);
+                              int ne, int ncell, bool use_fixed, double lam_fixed, bool any_init,
+                              hipStream_t st);
 hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, hipStream_t st);
 template <typename T> int spectral_energy_parts(const NetDev &nd);
 template <typename T> size_t spectral_max_lds(const NetDev &nd);
-template <typename T> hipError_t spectral_prepare();
+template <typename T> hipError_t spectral_prepare(int bytes);
 template <typename T>
 hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                        hipStream_t st);

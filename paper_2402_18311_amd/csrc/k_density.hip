@@ -159,7 +159,7 @@ template <typename T>
 hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                           hipStream_t st) {
     if (nd.n_mov == 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st, nd,
+    HP_LAUNCH("scatter_kernel", scatter_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st, nd,
                        sa, L);
     return hipGetLastError();
 }
@@ -169,7 +169,7 @@ hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayo
                             double lambda_fixed, bool use_fixed, bool /*init_mode*/,
                             hipStream_t st) {
     if (nd.n_mov == 0) return hipSuccess;
-    hipLaunchKernelGGL(cell_grad_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st,
+    HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st,
                        nd, sa, L, lambda_fixed, (int)use_fixed);
     return hipGetLastError();
 }
@@ -179,7 +179,7 @@ hipError_t launch_zero_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayou
                            hipStream_t st) {
     const size_t nb = (size_t)nd.mx * nd.my;
     const int blocks = (int)std::min<size_t>((nb + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL(zero_rho_kernel, dim3(blocks, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    HP_LAUNCH("zero_rho_kernel", zero_rho_kernel, dim3(blocks, sa.n), dim3(kBlock), 0, st, nd, sa, L);
     return hipGetLastError();
 }
 
@@ -187,7 +187,7 @@ template <typename T>
 hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,
                             int64_t *rho_fixed, hipStream_t st) {
     if (nd.n_fixed == 0) return hipSuccess;
-    hipLaunchKernelGGL(fixed_map_kernel, dim3((nd.n_fixed + kBlock - 1) / kBlock),
+    HP_LAUNCH("fixed_map_kernel", fixed_map_kernel, dim3((nd.n_fixed + kBlock - 1) / kBlock),
                        dim3(kBlock), 0, st, nd, fxy, fwh,
                        reinterpret_cast<unsigned long long *>(rho_fixed));
     return hipGetLastError();

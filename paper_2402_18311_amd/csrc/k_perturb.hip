@@ -260,31 +260,31 @@ hipError_t launch_perturb(const NetDev &nd, char *base, const SlotLayout &L, int
                           double sigma_x, double sigma_y, uint64_t seed, hipStream_t st) {
     const int nblk = (nd.n_mov + kBlock - 1) / kBlock;
     const int gb = nblk > 0 ? nblk : 1;
-    hipLaunchKernelGGL(perturb_init_kernel<T>, dim3(gb), dim3(kBlock), 0, st, nd, base, L, seed, m);
+    HP_LAUNCH("perturb_init_kernel", perturb_init_kernel<T>, dim3(gb), dim3(kBlock), 0, st, nd, base, L, seed, m);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || m == 0) return e;
     const int mb = (int)((m + kBlock - 1) / kBlock);
     if (mode == 2) {
-        hipLaunchKernelGGL(apply_gauss_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m, 0.0,
+        HP_LAUNCH("apply_gauss_kernel", apply_gauss_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m, 0.0,
                            0.0, seed, 1);
         return hipGetLastError();
     }
     const int hb = nblk < 2048 ? nblk : 2048;
     for (int pass = 0; pass < 8; ++pass) {
         const int shift = 56 - 8 * pass;
-        hipLaunchKernelGGL(select_hist_kernel, dim3(hb), dim3(kBlock), 0, st, nd, base, L, shift);
-        hipLaunchKernelGGL(select_pick_kernel, dim3(1), dim3(64), 0, st, base, L, shift);
+        HP_LAUNCH("select_hist_kernel", select_hist_kernel, dim3(hb), dim3(kBlock), 0, st, nd, base, L, shift);
+        HP_LAUNCH("select_pick_kernel", select_pick_kernel, dim3(1), dim3(64), 0, st, base, L, shift);
     }
-    hipLaunchKernelGGL(select_count_kernel, dim3(nblk), dim3(kBlock), 0, st, nd, base, L);
-    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(kBlock), 0, st, base, L, nblk);
-    hipLaunchKernelGGL(select_write_kernel, dim3(nblk), dim3(kBlock), 0, st, nd, base, L);
+    HP_LAUNCH("select_count_kernel", select_count_kernel, dim3(nblk), dim3(kBlock), 0, st, nd, base, L);
+    HP_LAUNCH("select_scan_kernel", select_scan_kernel, dim3(1), dim3(kBlock), 0, st, base, L, nblk);
+    HP_LAUNCH("select_write_kernel", select_write_kernel, dim3(nblk), dim3(kBlock), 0, st, nd, base, L);
     if (mode == 0) {
-        hipLaunchKernelGGL(apply_gauss_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m,
+        HP_LAUNCH("apply_gauss_kernel", apply_gauss_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m,
                            sigma_x, sigma_y, seed, 0);
     } else {
-        hipLaunchKernelGGL(shuffle_gather_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m,
+        HP_LAUNCH("shuffle_gather_kernel", shuffle_gather_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m,
                            seed);
-        hipLaunchKernelGGL(shuffle_apply_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m);
+        HP_LAUNCH("shuffle_apply_kernel", shuffle_apply_kernel<T>, dim3(mb), dim3(kBlock), 0, st, nd, base, L, m);
     }
     return hipGetLastError();
 }

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
 template <typename T>
 static int cols_per_block(const NetDev &nd) {
     int C = 16;
-    while (C > 2 && 2ull * C * nd.my * sizeof(T) > 131072ull) C /= 2;
+    while (C > 2 && 2ull * C * nd.my * sizeof(T) > (unsigned long long)nd.lds_budget) C /= 2;
     return C < nd.mx ? C : nd.mx;
 }
 
@@ -302,7 +302,7 @@ hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayou
     if (lpb < 1) lpb = 1;
     if (lpb > nd.my / 2) lpb = nd.my / 2;
     size_t sh1 = sizeof(vec2<T>) * (size_t)lpb * nd.mx;
-    hipLaunchKernelGGL(spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kBlock), sh1, st, nd,
+    HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kBlock), sh1, st, nd,
                        sa, L, lpb, (int)keep_maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -310,13 +310,13 @@ hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayou
     int logC = 0;
     while ((1 << logC) < C) ++logC;
     size_t sh2 = 2 * sizeof(T) * (size_t)C * nd.my;
-    hipLaunchKernelGGL(spec_cols<T>, dim3(nd.mx / C, sa.n), dim3(kBlock), sh2, st, nd, sa, L, C,
+    HP_LAUNCH("spec_cols", spec_cols<T>, dim3(nd.mx / C, sa.n), dim3(kBlock), sh2, st, nd, sa, L, C,
                        logC, (int)want_psi);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nst = want_psi ? 3 : 2;
     size_t sh3 = sizeof(T) * (size_t)nst * 2 * nd.mx + sizeof(vec2<T>) * (size_t)nst * nd.mx;
-    hipLaunchKernelGGL(spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kBlock), sh3, st, nd, sa, L,
+    HP_LAUNCH("spec_rows_inv", spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kBlock), sh3, st, nd, sa, L,
                        (int)want_psi);
     return hipGetLastError();
 }
@@ -333,17 +333,17 @@ size_t spectral_max_lds(const NetDev &nd) {
     return std::max(a, std::max(b, c));
 }
 
+// Ask for `bytes` of dynamic LDS per block on the three passes (above the 64 KB default).
 template <typename T>
-hipError_t spectral_prepare() {
-    // allow up to 160 KB of dynamic LDS per block
+hipError_t spectral_prepare(int bytes) {
     hipError_t e = hipFuncSetAttribute((const void *)spec_rows_fwd<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)spec_cols<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            163840);
+                            bytes);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)spec_rows_inv<T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 #define HP_INST(T)                                                                            \
@@ -351,7 +351,7 @@ hipError_t spectral_prepare() {
                                            bool, bool, hipStream_t);                          \
     template int spectral_energy_parts<T>(const NetDev &);                                    \
     template size_t spectral_max_lds<T>(const NetDev &);                                      \
-    template hipError_t spectral_prepare<T>();
+    template hipError_t spectral_prepare<T>(int);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

@@ -21,7 +21,7 @@ __device__ double max_parts(const double *p, int n, double *red) {
 // (scheduled lambda, not yet derived) lambda_0 = scale * |grad WL|_1 / |grad N|_1.
 __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                             int nwl, int ne, int ncell,
-                                                            int use_fixed) {
+                                                            int use_fixed, double lam_fixed) {
     __shared__ double red[4];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
@@ -47,6 +47,8 @@ __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs
             sc->lambda = sc->lambda0_scale * (n2 > 0.0 ? n1 / n2 : 1.0);
             sc->lambda_valid = 1;
         }
+        // the Nesterov step preconditions with the lambda this evaluation used
+        sc->lambda_step = use_fixed ? lam_fixed : sc->lambda;
     }
 }
 
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs 
     double dv = 0.0, dg = 0.0, gm = 0.0;
     if (i < n) {
         const T *cs = reinterpret_cast<const T *>(nd.cstep);
-        const double P = precond(cs, n, i, sc->lambda);
+        const double P = precond(cs, n, i, sc->lambda_step);
         const T *v = reinterpret_cast<const T *>(base + L.v);
         const T *vp = reinterpret_cast<const T *>(base + L.vprev);
         const T *g = reinterpret_cast<const T *>(base + L.g);
@@ -127,7 +129,6 @@ __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArg
         const double an = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
         sc->step_alpha = alpha;
         sc->step_coef = (a - 1.0) / an;
-        sc->lambda_step = sc->lambda;
         sc->a = an;
         sc->alpha = alpha;
         sc->k += 1;
@@ -229,12 +230,13 @@ __global__ __launch_bounds__(kBlock) void copy_best_kernel(NetDev nd, SlotArgs s
 // ---- launchers ------------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
-                              int ne, int ncell, bool use_fixed, bool any_init, hipStream_t st) {
-    hipLaunchKernelGGL(eval_finish_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa, L, nwl, ne,
-                       ncell, (int)use_fixed);
+                              int ne, int ncell, bool use_fixed, double lam_fixed, bool any_init,
+                              hipStream_t st) {
+    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa,
+              L, nwl, ne, ncell, (int)use_fixed, lam_fixed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !any_init || nd.n_mov == 0) return e;
-    hipLaunchKernelGGL(combine_kernel<T>, dim3((2 * nd.n_mov + kBlock - 1) / kBlock, sa.n),
+    HP_LAUNCH("combine_kernel", combine_kernel<T>, dim3((2 * nd.n_mov + kBlock - 1) / kBlock, sa.n),
                        dim3(kBlock), 0, st, nd, sa, L);
     return hipGetLastError();
 }
@@ -243,35 +245,35 @@ template <typename T>
 hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, hipStream_t st) {
     const int nc = cell_parts(nd);
     if (nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    HP_LAUNCH("step_norms_kernel", step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa, L, nc);
+    HP_LAUNCH("step_scalars_kernel", step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa, L, nc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
     return hipGetLastError();
 }
 
 hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, hipStream_t st) {
-    hipLaunchKernelGGL(hpwl_finish_kernel, dim3(sa.n), dim3(64), 0, st, sa, L);
+    HP_LAUNCH("hpwl_finish_kernel", hpwl_finish_kernel, dim3(sa.n), dim3(64), 0, st, sa, L);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumbent,
                               const SlotLayout &L, hipStream_t st) {
-    hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(64), 0, st, sa, incumbent, L);
+    HP_LAUNCH("select_best_kernel", select_best_kernel, dim3(1), dim3(64), 0, st, sa, incumbent, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nd.n_mov == 0) return e;
-    hipLaunchKernelGGL(copy_best_kernel<T>, dim3(cell_parts(nd)), dim3(kBlock), 0, st, nd, sa,
+    HP_LAUNCH("copy_best_kernel", copy_best_kernel<T>, dim3(cell_parts(nd)), dim3(kBlock), 0, st, nd, sa,
                        incumbent, L);
     return hipGetLastError();
 }
 
 #define HP_INST(T)                                                                              \
     template hipError_t launch_eval_finish<T>(const NetDev &, const SlotArgs &, const SlotLayout &, \
-                                              int, int, int, bool, bool, hipStream_t);          \
+                                              int, int, int, bool, double, bool, hipStream_t);  \
     template hipError_t launch_step<T>(const NetDev &, const SlotArgs &, const SlotLayout &,     \
                                        hipStream_t);                                            \
     template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \

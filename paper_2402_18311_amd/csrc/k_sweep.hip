@@ -234,7 +234,7 @@ hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &
                            const SlotLayout &L, double inv_gamma, hipStream_t st) {
     if (bk.total_blocks == 0) return hipSuccess;
     dim3 grid(bk.total_blocks, sa.n);
-    hipLaunchKernelGGL((sweep_kernel<T, MODE_WA>), grid, dim3(kBlock), 0, st, nd, bk, sa, L,
+    HP_LAUNCH("sweep_wa", (sweep_kernel<T, MODE_WA>), grid, dim3(kBlock), 0, st, nd, bk, sa, L,
                        (T)inv_gamma);
     return hipGetLastError();
 }
@@ -244,7 +244,7 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
                              const SlotLayout &L, hipStream_t st) {
     if (bk.total_blocks == 0) return hipSuccess;
     dim3 grid(bk.total_blocks, sa.n);
-    hipLaunchKernelGGL((sweep_kernel<T, MODE_HPWL>), grid, dim3(kBlock), 0, st, nd, bk, sa,
+    HP_LAUNCH("sweep_hpwl", (sweep_kernel<T, MODE_HPWL>), grid, dim3(kBlock), 0, st, nd, bk, sa,
                        L, (T)0);
     return hipGetLastError();
 }

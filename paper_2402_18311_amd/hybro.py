@@ -71,7 +71,26 @@ _SIGS = {
     "hp_select_best": [_P, _P, C.c_int32, C.c_int32, _P],
     "hp_get_map": [_P, C.c_int32, C.c_int, _P],
     "hp_get_state": [_P, C.c_int32, C.POINTER(hp_slot_state)],
+    "hp_profile_enable": [_P, C.c_int],
+    "hp_profile_read": [_P, _P, C.c_int32, C.POINTER(C.c_int32), C.c_int],
 }
+
+
+class hp_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("count", C.c_int64), ("total_ms", C.c_double)]
+
+
+def hp_profile_enable(ctx, on):
+    _chk(lib().hp_profile_enable(ctx, int(on)))
+
+
+def hp_profile_read(ctx, reset=True):
+    """{kernel name: (launches, total ms)} accumulated since the last read."""
+    n = C.c_int32()
+    _chk(lib().hp_profile_read(ctx, None, 0, C.byref(n), 0))
+    arr = (hp_kernel_time * max(1, n.value))()
+    _chk(lib().hp_profile_read(ctx, arr, n.value, C.byref(n), int(reset)))
+    return {arr[i].name.decode(): (arr[i].count, arr[i].total_ms) for i in range(n.value)}
 
 
 def lib():
