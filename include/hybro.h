@@ -171,17 +171,18 @@ typedef struct {
 } hp_slot_state;
 int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out);
 
-/* Per-kernel timing.  While enabled, every kernel launch is bracketed by two HIP events on
- * the context's stream (a small host cost per launch).  hp_profile_read synchronises, adds
- * the elapsed times of all launches since the last read to per-kernel totals, copies up to
- * `max` totals to `out` (host), sets *n_out to the number of kernels seen, and clears the
- * totals if `reset`. */
+/* Per-kernel timing.  While enabled, every launch of the kernel named only_kernel (or of every
+ * kernel if it is NULL) is bracketed by two HIP events on the context's stream (a small host
+ * cost per bracketed launch).  hp_profile_read synchronises, adds the elapsed times of all
+ * bracketed launches since the last read to per-kernel totals, copies up to `max` totals to
+ * `out` (host), sets *n_out to the number of kernels seen, and clears the totals if `reset`.
+ * The profiler state is process-wide. */
 typedef struct {
     char name[48];
     int64_t count;
     double total_ms;
 } hp_kernel_time;
-int hp_profile_enable(hp_ctx *ctx, int on);
+int hp_profile_enable(hp_ctx *ctx, int on, const char *only_kernel);
 int hp_profile_read(hp_ctx *ctx, hp_kernel_time *out, int32_t max, int32_t *n_out, int reset);
 
 #ifdef __cplusplus

@@ -78,8 +78,35 @@ size_t part_stride(const hp_shape &s, const hp_die &d) {
     return std::max<size_t>({sweep, cells, (size_t)d.mx, 1});
 }
 
-SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs) {
+// Geometry of the tile-binned scatter that depends only on the grid and the cell count.
+struct BinGeom {
+    int log_ts, ntx, nty, ntiles, sort_cells, sort_blocks, max_chunks;
+};
+
+BinGeom bin_geom(const hp_shape &s, const hp_die &d) {
+    BinGeom g{};
+    int ts = 16;
+    while (ts < std::min(d.mx, d.my) && (d.mx / ts) * (d.my / ts) > 8192) ts *= 2;
+    ts = std::min(ts, std::min(d.mx, d.my));
+    g.log_ts = 0;
+    while ((1 << g.log_ts) < ts) ++g.log_ts;
+    g.ntx = d.mx / ts;
+    g.nty = d.my / ts;
+    g.ntiles = g.ntx * g.nty;
+    const int n = std::max(1, s.n_movable);
+    g.sort_cells = 2048 * ((n + 2048 * 512 - 1) / (2048 * 512));
+    g.sort_blocks = (n + g.sort_cells - 1) / g.sort_cells;
+    g.max_chunks = (n + kChunk - 1) / kChunk + g.ntiles;
+    return g;
+}
+
+// halo: widest charge footprint in bins minus one (at most the tile size); the byte-size
+// bound used before a netlist is known takes the largest allowed halo.
+SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo = -1) {
     SlotLayout L{};
+    const BinGeom g = bin_geom(s, d);
+    if (halo < 0) halo = 1 << g.log_ts;
+    const size_t ws = (size_t)(1 << g.log_ts) + halo;
     size_t o = 0;
     auto put = [&](size_t &f, size_t bytes) {
         f = o;
@@ -107,6 +134,13 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     put(L.keys, 8 * Nm);
     put(L.sel, 4 * Nm);
     put(L.work, perturb_work_bytes((int)Nm));
+    put(L.tile, 4 * Nm);
+    put(L.sorted, 4 * Nm);
+    put(L.scnt, 4 * (size_t)g.sort_blocks * g.ntiles);
+    put(L.soff, 4 * (size_t)g.sort_blocks * g.ntiles);
+    put(L.tstart, 4 * ((size_t)g.ntiles + 1));
+    put(L.cstart, 4 * ((size_t)g.ntiles + 1));
+    put(L.wins, 8 * (size_t)g.max_chunks * ws * ws);
     L.total = o;
     return L;
 }
@@ -127,7 +161,6 @@ struct Slot {
     int netlist = -1;
     char *base = nullptr;
     bool lambda_valid = false;  // host mirror of the device flag
-    bool map_dirty = false;     // the movable map was kept by the last evaluation
     bool maps_valid = false;
 };
 
@@ -277,6 +310,12 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
         blk += nblk;
         ++bk.n;
     }
+    if (bk.n == 0) {  // no net with two pins: one idle bucket so the reductions still run
+        bk.n = 1;
+        bk.G[0] = 0;
+        bk.nblk[0] = kXcds;
+        blk = kXcds;
+    }
     bk.total_blocks = blk;
     if ((size_t)blk > part_stride(S, D)) return fail(HP_EINVAL, "internal: sweep block bound");
     const int ns = (int)order.size();
@@ -328,6 +367,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     std::vector<int32_t> h_cq(4 * (size_t)Nm), h_rq(Nm);
     std::vector<T> h_cs(4 * (size_t)Nm), h_wh(2 * (size_t)Nm);
     int64_t total_charge = 0;
+    long long halo = 0;
     {
 #pragma clang fp contract(off)
         for (int i = 0; i < Nm; ++i) {
@@ -354,9 +394,25 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             h_cs[3 * (size_t)Nm + i] = (T)(D.H - h);
             h_wh[i] = (T)w;
             h_wh[(size_t)Nm + i] = (T)h;
+            // bins a rectangle of this width can span, minus one
+            halo = std::max<long long>(halo, std::max((nd.bq + wq - 2) / nd.bq, (nd.hq + hq - 2) / nd.hq));
         }
     }
     nd.total_charge = total_charge > 0 ? total_charge : 1;
+    {
+        const BinGeom g = bin_geom(S, D);
+        if (halo > (1 << g.log_ts))
+            return fail(HP_EINVAL, "a movable cell's charge spans more bins than the scatter tile");
+        nd.log_ts = g.log_ts;
+        nd.ntx = g.ntx;
+        nd.nty = g.nty;
+        nd.ntiles = g.ntiles;
+        nd.halo = (int)halo;
+        nd.win_side = (1 << g.log_ts) + (int)halo;
+        nd.sort_cells = g.sort_cells;
+        nd.sort_blocks = g.sort_blocks;
+        nd.max_chunks = g.max_chunks;
+    }
 
     // spectral tables: FFT twiddles exp(-2 pi i k / M), DCT phases (cos, sin)(pi u / 2M),
     // w_u = pi u / W and the per-axis Laplacian symbol
@@ -455,7 +511,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     NL.shape = S;
     NL.die = D;
     NL.bk = bk;
-    NL.L = slot_layout(S, D, sizeof(T));
+    NL.L = slot_layout(S, D, sizeof(T), nd.halo);
     NL.buf = buf;
     NL.e_parts = spectral_energy_parts<T>(nd);
     return HP_OK;
@@ -511,22 +567,17 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
     const SlotLayout &L = NL->L;
     for (size_t c = 0; c < chunks.size(); ++c) {
         const SlotArgs &sa = chunks[c];
-        bool dirty = false, any_init = false;
-        for (int i = 0; i < sa.n; ++i) {
-            Slot *s = ss[c * kMaxSlots + i];
-            dirty |= s->map_dirty;
-            any_init |= !use_fixed && !s->lambda_valid;
-        }
-        if (dirty) HP_CHECK(launch_zero_rho<T>(nd, sa, L, st));
+        bool any_init = false;
+        for (int i = 0; i < sa.n; ++i) any_init |= !use_fixed && !ss[c * kMaxSlots + i]->lambda_valid;
         HP_CHECK(launch_sweep_wa<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, st));
         HP_CHECK(launch_scatter<T>(nd, sa, L, st));
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0, p->keep_maps != 0, st));
-        HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, false, st));
-        HP_CHECK(launch_eval_finish<T>(nd, sa, L, NL->bk.total_blocks, NL->e_parts, cell_parts(nd),
-                                       use_fixed, use_fixed ? p->lambda : 0.0, any_init, st));
+        HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed,
+                                     NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
+                                     st));
+        if (any_init) HP_CHECK(launch_combine<T>(nd, sa, L, st));
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];
-            s->map_dirty = p->keep_maps != 0;
             s->maps_valid = p->keep_maps != 0;
             if (!use_fixed) s->lambda_valid = true;
         }
@@ -566,6 +617,7 @@ void init_scalars(Scalars &s, double scale, double decades, int iters) {
 namespace hp {
 namespace {
 bool g_prof_on = false;
+std::string g_prof_only;  // empty: every kernel
 std::vector<ProfRec> g_prof_pending;
 std::vector<hipEvent_t> g_prof_pool;
 struct ProfAcc {
@@ -575,7 +627,9 @@ struct ProfAcc {
 };
 std::vector<ProfAcc> g_prof_acc;
 }  // namespace
-bool prof_on() { return g_prof_on; }
+bool prof_want(const char *name) {
+    return g_prof_on && (g_prof_only.empty() || g_prof_only == name);
+}
 hipEvent_t prof_event() {
     if (!g_prof_pool.empty()) {
         hipEvent_t e = g_prof_pool.back();
@@ -592,9 +646,10 @@ void prof_push(const char *name, hipEvent_t a, hipEvent_t b) { g_prof_pending.pu
 // ============================================================================================
 extern "C" {
 
-int hp_profile_enable(hp_ctx *ctx, int on) {
+int hp_profile_enable(hp_ctx *ctx, int on, const char *only_kernel) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     hp::g_prof_on = on != 0;
+    hp::g_prof_only = only_kernel ? only_kernel : "";
     return HP_OK;
 }
 
@@ -871,7 +926,7 @@ int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double
             HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
         else
             HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
-        HP_CHECK(launch_hpwl_finish(sa, NL->L, ctx->stream));
+        HP_CHECK(launch_hpwl_finish(sa, NL->L, NL->bk.total_blocks, ctx->stream));
     }
     if (out_q || out) {
         std::vector<int64_t> h(n);

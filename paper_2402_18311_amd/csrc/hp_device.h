@@ -59,6 +59,49 @@ template <typename T> __device__ __forceinline__ T block_min(T v, T *red) {
     return min(min(red[0], red[1]), min(red[2], red[3]));
 }
 
+// Fixed-order sums of n per-block partials by one block (thread t takes t, t+256, ...).
+template <typename T> __device__ T sum_parts(const T *p, int n, T *red) {
+    T s = 0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
+    return block_sum(s, red);
+}
+__device__ inline double max_parts(const double *p, int n, double *red) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s = fmax(s, p[i]);
+    return block_max(s, red);
+}
+
+// Movable charge of bin (k, j) assembled from the binned scatter's chunk windows: the chunks
+// of the bin's own tile, and of the tiles to its left / below / below-left whose windows
+// reach into it (the bin lies within the halo of their far edges).
+__device__ __forceinline__ long long binned_charge(const NetDev &nd, const char *base,
+                                                   const SlotLayout &L, int k, int j) {
+    const int *cstart = reinterpret_cast<const int *>(base + L.cstart);
+    const unsigned long long *W = reinterpret_cast<const unsigned long long *>(base + L.wins);
+    const int ts = 1 << nd.log_ts, ws = nd.win_side, nw = ws * ws;
+    const int ty = k >> nd.log_ts, tx = j >> nd.log_ts, kk = k & (ts - 1), jj = j & (ts - 1);
+    unsigned long long s = 0;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+        if (dy && (kk >= nd.halo || ty == 0)) continue;
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            if (dx && (jj >= nd.halo || tx == 0)) continue;
+            const int t = (ty - dy) * nd.ntx + (tx - dx);
+            const int off = (kk + dy * ts) * ws + jj + dx * ts;
+            const int c1 = cstart[t + 1];
+            int c = cstart[t];
+            for (; c + 4 <= c1; c += 4) {  // independent loads in flight when a tile is crowded
+                const unsigned long long a0 = W[(size_t)c * nw + off], a1 = W[(size_t)(c + 1) * nw + off];
+                const unsigned long long a2 = W[(size_t)(c + 2) * nw + off], a3 = W[(size_t)(c + 3) * nw + off];
+                s += (a0 + a1) + (a2 + a3);
+            }
+            for (; c < c1; ++c) s += W[(size_t)c * nw + off];
+        }
+    }
+    return (long long)s;
+}
+
 // Map a block index inside a bucket of nb blocks (nb a multiple of kXcds) so that each XCD
 // (which receives blocks i with i % 8 == xcd) works on one contiguous eighth of the bucket.
 __device__ __forceinline__ int xcd_remap(int i, int nb) {

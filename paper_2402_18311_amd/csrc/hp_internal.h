@@ -9,6 +9,7 @@ constexpr int kBlock = 256;      // threads per block for every kernel
 constexpr int kMaxSlots = 32;    // slots per launch (longer lists are chunked)
 constexpr int kMaxBuckets = 8;
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
+constexpr int kChunk = 2048;     // cells per accumulation block of the binned scatter
 
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };
@@ -48,6 +49,10 @@ struct NetDev {
     const void *cell_wh;           // T [2][n_mov] movable cell sizes
     int32_t n_cells, n_mov, n_fixed, ns, ps;
     int32_t lds_budget;            // dynamic LDS bytes a block may use on this device
+    // tile-binned charge scatter: ts x ts bin tiles (ts = 1 << log_ts), ntx x nty of them;
+    // halo = widest charge footprint in bins - 1; windows of win_side = ts + halo bins
+    int32_t log_ts, ntx, nty, ntiles, halo, win_side;
+    int32_t sort_cells, sort_blocks, max_chunks;  // cells per counting block; chunk bound
     int32_t mx, my, logmx, logmy;
     int32_t bq, hq, wq_die, hq_die; // bin size and die size in 2^-12 units
     double W, H, wb, hb;
@@ -69,12 +74,18 @@ struct SlotLayout {
     size_t scal;          // Scalars
     size_t part;          // double partial sums, kPartStride per reduction
     size_t keys, sel, work; // perturbation scratch
+    size_t tile, sorted;  // int32 [n_mov]: each cell's tile, cells in tile order
+    size_t scnt, soff;    // int32 [sort_blocks][ntiles] histograms; their column offsets
+    size_t tstart, cstart;// int32 [ntiles + 1]: tile cell ranges, tile chunk ranges
+    size_t wins;          // int64 [max_chunks][win_side^2] per-chunk charge windows
     size_t pstride;       // doubles per reduction in `part` (max blocks of any reduction)
     size_t total;
 };
 
+// Per-block partials of every per-slot reduction (doubles; HPWL and overflow are int64 stored
+// in the same 8-byte cells).
 enum { PART_WL = 0, PART_E = 1, PART_N1 = 2, PART_N2 = 3, PART_DV = 4, PART_DG = 5,
-       PART_GMAX = 6, PART_COUNT = 7 };
+       PART_GMAX = 6, PART_HPWL = 7, PART_OVF = 8, PART_COUNT = 9 };
 
 // Per-slot scalars in device memory.
 struct Scalars {
@@ -85,8 +96,6 @@ struct Scalars {
     int64_t lambda_valid;   // 0 until lambda_0 is derived at the first evaluation
     int64_t init_this_eval; // the last evaluation derived lambda_0
     int64_t hpwl_q, hpwl_valid;
-    unsigned long long hpwl_acc;
-    unsigned long long ovf_acc;
     int64_t overflow_num;
     // perturbation
     uint64_t sel_prefix, sel_mask;
@@ -111,13 +120,13 @@ struct ProfRec {
     const char *name;
     hipEvent_t a, b;
 };
-bool prof_on();
+bool prof_want(const char *name);
 hipEvent_t prof_event();
 void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
 
 #define HP_LAUNCH(NAME, K, GRID, BLOCK, SHMEM, STREAM, ...)                              \
     do {                                                                                \
-        if (::hp::prof_on()) {                                                          \
+        if (::hp::prof_want(NAME)) {                                                    \
             hipEvent_t ea_ = ::hp::prof_event(), eb_ = ::hp::prof_event();              \
             (void)hipEventRecord(ea_, STREAM);                                          \
             hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);              \
@@ -141,24 +150,26 @@ hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout
 template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st);
+// The cell-gradient launch is followed by the evaluation's closing reduction (totals of nwl
+// sweep, ne energy and nov overflow partials; lambda_0 on a first evaluation).
+hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
+                              int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
+                              hipStream_t st);
+hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, int nparts, hipStream_t st);
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                            double lambda_fixed, bool use_fixed, bool init_mode,
+                            double lambda_fixed, bool use_fixed, int nwl, int ne, int nov,
                             hipStream_t st);
 template <typename T>
-hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
-                              int ne, int ncell, bool use_fixed, double lam_fixed, bool any_init,
-                              hipStream_t st);
-hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, hipStream_t st);
+hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                          hipStream_t st);
 template <typename T> int spectral_energy_parts(const NetDev &nd);
+int spectral_overflow_parts(const NetDev &nd);
 template <typename T> size_t spectral_max_lds(const NetDev &nd);
 template <typename T> hipError_t spectral_prepare(int bytes);
 template <typename T>
 hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                        hipStream_t st);
-template <typename T>
-hipError_t launch_zero_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                           hipStream_t st);
 template <typename T>
 hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,
                             int64_t *rho_fixed, hipStream_t st);

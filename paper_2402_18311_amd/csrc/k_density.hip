@@ -1,12 +1,12 @@
-// Per-cell kernels: the integer charge scatter (density map), and the fused cell gradient
-// (sum of the cell's pin gradients of Eq. 3 plus the electrostatic force on its charge).
+// Per-cell kernels: the fixed cells' static charge map, and the fused cell gradient (sum of the
+// cell's pin gradients of Eq. 3 plus the electrostatic force on its charge).
 //
 // Charge model (the density D of Eqs. 1-2, ePlace reading): the die is cut into mx x my bins
 // of bq x hq units of 2^-12.  A movable cell's charge rectangle is its own, stretched to at
 // least sqrt(2) bins per side around the cell centre, with its charge density scaled by
 // r = w h / (w' h').  Its charge in bin (j, k) is r_q * ox_j * oy_k with r_q in 2^-16 and the
-// overlaps in 2^-12, i.e. in units of 2^-40 area, exact in int64.  Integer atomics commute,
-// so the map is bit-identical whatever the order in which cells arrive.
+// overlaps in 2^-12, i.e. in units of 2^-40 area, exact in int64.  (The movable cells' map
+// is built by the binned scatter.)
 #include "hp_device.h"
 
 namespace hp {
@@ -31,28 +31,6 @@ __device__ __forceinline__ int overlap(int lo, int hi, int idx, int w) {
     return b > a ? b - a : 0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void scatter_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
-    char *base = sa.base[blockIdx.y];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= nd.n_mov) return;
-    const T *x = reinterpret_cast<const T *>(base + L.v);
-    const T *y = x + nd.n_cells;
-    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
-    const RectQ q = cell_rect(nd, (double)x[i], (double)y[i], nd.cq[i]);
-    if (q.r <= q.l || q.t <= q.b) return;
-    const long long rq = nd.rq[i];
-    const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
-    const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
-    for (int k = k0; k <= k1; ++k) {
-        const long long oy = overlap(q.b, q.t, k, nd.hq);
-        for (int j = j0; j <= j1; ++j) {
-            const long long ox = overlap(q.l, q.r, j, nd.bq);
-            atomicAdd(&rho[(size_t)k * nd.mx + j], (unsigned long long)(rq * ox * oy));
-        }
-    }
-}
-
 // Fixed cells: their true rectangle with charge scale 1 (r_q = 2^16), computed once at load.
 __global__ __launch_bounds__(kBlock) void fixed_map_kernel(NetDev nd, const double *fxy,
                                                            const double *fwh,
@@ -75,14 +53,6 @@ __global__ __launch_bounds__(kBlock) void fixed_map_kernel(NetDev nd, const doub
             atomicAdd(&rho[(size_t)k * nd.mx + j], (unsigned long long)(65536LL * ox * oy));
         }
     }
-}
-
-__global__ __launch_bounds__(kBlock) void zero_rho_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
-    char *base = sa.base[blockIdx.y];
-    int64_t *rho = reinterpret_cast<int64_t *>(base + L.rho);
-    const size_t nb = (size_t)nd.mx * nd.my;
-    for (size_t b = blockIdx.x * (size_t)kBlock + threadIdx.x; b < nb; b += (size_t)gridDim.x * kBlock)
-        rho[b] = 0;
 }
 
 // Fused cell gradient.  Wirelength part: the sum of the cell's pin gradients (fixed pin
@@ -156,31 +126,15 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
 int cell_parts(const NetDev &nd) { return (nd.n_mov + kBlock - 1) / kBlock; }
 
 template <typename T>
-hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                          hipStream_t st) {
-    if (nd.n_mov == 0) return hipSuccess;
-    HP_LAUNCH("scatter_kernel", scatter_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st, nd,
-                       sa, L);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                            double lambda_fixed, bool use_fixed, bool /*init_mode*/,
+                            double lambda_fixed, bool use_fixed, int nwl, int ne, int nov,
                             hipStream_t st) {
-    if (nd.n_mov == 0) return hipSuccess;
-    HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(cell_parts(nd), sa.n), dim3(kBlock), 0, st,
-                       nd, sa, L, lambda_fixed, (int)use_fixed);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_zero_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                           hipStream_t st) {
-    const size_t nb = (size_t)nd.mx * nd.my;
-    const int blocks = (int)std::min<size_t>((nb + kBlock - 1) / kBlock, 4096);
-    HP_LAUNCH("zero_rho_kernel", zero_rho_kernel, dim3(blocks, sa.n), dim3(kBlock), 0, st, nd, sa, L);
-    return hipGetLastError();
+    const int nb = std::max(1, cell_parts(nd));
+    HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(nb, sa.n), dim3(kBlock), 0, st, nd, sa,
+              L, lambda_fixed, (int)use_fixed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, st);
 }
 
 template <typename T>
@@ -194,13 +148,9 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 }
 
 #define HP_INST(T)                                                                          \
-    template hipError_t launch_scatter<T>(const NetDev &, const SlotArgs &, const SlotLayout &, \
-                                          hipStream_t);                                     \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
-                                            const SlotLayout &, double, bool, bool,         \
+                                            const SlotLayout &, double, bool, int, int, int, \
                                             hipStream_t);                                   \
-    template hipError_t launch_zero_rho<T>(const NetDev &, const SlotArgs &,                \
-                                           const SlotLayout &, hipStream_t);                \
     template hipError_t launch_fixed_map<T>(const NetDev &, const double *, const double *, \
                                             int64_t *, hipStream_t);
 HP_INST(float)

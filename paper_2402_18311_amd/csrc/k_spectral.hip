@@ -90,15 +90,15 @@ __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, 
         const int l = idx >> logM, j = idx & (M - 1);
         const int ra = (blockIdx.x * lpb + l) * 2;
         const size_t ia = (size_t)ra * M + j, ib = ia + M;
-        const int64_t ma = rho[ia], mb = rho[ib];
+        const int64_t ma = binned_charge(nd, base, L, ra, j), mb = binned_charge(nd, base, L, ra + 1, j);
         const int64_t fa = nd.rho_fixed[ia], fb = nd.rho_fixed[ib];
         const int64_t ca = __double2ll_rn(nd.target_density * (double)(nd.area_q - fa));
         const int64_t cb = __double2ll_rn(nd.target_density * (double)(nd.area_q - fb));
         if (ma > ca) over += ma - ca;
         if (mb > cb) over += mb - cb;
-        if (!keep) {
-            rho[ia] = 0;
-            rho[ib] = 0;
+        if (keep) {  // the movable map itself is only materialised for inspection
+            rho[ia] = ma;
+            rho[ib] = mb;
         }
         buf[l * M + brev(mperm(j, M), logM)] =
             cmk<T>((T)((double)(ma + fa) * nd.density_unit), (T)((double)(mb + fb) * nd.density_unit));
@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, 
     }
     __shared__ long long red[4];
     over = block_sum(over, red);
-    if (threadIdx.x == 0 && over) atomicAdd(&scalars(base, L)->ovf_acc, (unsigned long long)over);
+    if (threadIdx.x == 0)
+        (reinterpret_cast<long long *>(base + L.part) + PART_OVF * L.pstride)[blockIdx.x] = over;
 }
 
 // ---- C ----------------------------------------------------------------------------------
@@ -170,24 +171,24 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
             const int l = idx >> logM, v = idx & (M - 1);
             const int c = h * hc + l, u = u0 + c;
             const T *ac = acol + c * M;
-            const double wu = nd.omega[u];
+            const T wu = (T)nd.omega[u], du = (T)nd.den1[u];
             // X(v) = a_uv w_u / den ; cosine sum in y
-            auto X = [&](int vv) -> double {
-                if ((u | vv) == 0) return 0.0;
-                return (double)ac[vv] * wu / (nd.den1[u] + nd.den1[mx + vv]);
+            auto X = [&](int vv) -> T {
+                if ((u | vv) == 0) return T(0);
+                return ac[vv] * wu / (du + (T)nd.den1[mx + vv]);
             };
             // Y(v) = a_uv w_v / den ; sine sum in y -> reversed coefficients
-            auto Y = [&](int vv) -> double {
-                if ((u | vv) == 0) return 0.0;
-                return (double)ac[vv] * nd.omega[mx + vv] / (nd.den1[u] + nd.den1[mx + vv]);
+            auto Y = [&](int vv) -> T {
+                if ((u | vv) == 0) return T(0);
+                return ac[vv] * (T)nd.omega[mx + vv] / (du + (T)nd.den1[mx + vv]);
             };
-            const double xp = v ? 0.5 * X(v) : X(0);
-            const double xq = v ? 0.5 * X(M - v) : 0.0;
+            const T xp = v ? T(0.5) * X(v) : X(0);
+            const T xq = v ? T(0.5) * X(M - v) : T(0);
             // reversed: Yt(0) = 0, Yt(w) = Y(M - w)
-            const double yp = v ? 0.5 * Y(M - v) : 0.0;
-            const double yq = v ? 0.5 * Y(v) : 0.0;
-            const vec2<T> VX = idct_pre<T>((T)xp, (T)xq, ph[v]);
-            const vec2<T> VY = idct_pre<T>((T)yp, (T)yq, ph[v]);
+            const T yp = v ? T(0.5) * Y(M - v) : T(0);
+            const T yq = v ? T(0.5) * Y(v) : T(0);
+            const vec2<T> VX = idct_pre<T>(xp, xq, ph[v]);
+            const vec2<T> VY = idct_pre<T>(yp, yq, ph[v]);
             work[l * M + brev(v, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
         }
         __syncthreads();
@@ -209,13 +210,14 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
             for (int h = 0; h < 2; ++h) {
                 const int c = 2 * l + h, u = u0 + c;
                 const T *ac = acol + c * M;
-                auto P = [&](int vv) -> double {
-                    if ((u | vv) == 0) return 0.0;
-                    return (double)ac[vv] / (nd.den1[u] + nd.den1[mx + vv]);
+                const T du = (T)nd.den1[u];
+                auto P = [&](int vv) -> T {
+                    if ((u | vv) == 0) return T(0);
+                    return ac[vv] / (du + (T)nd.den1[mx + vv]);
                 };
-                const double pp = v ? 0.5 * P(v) : P(0);
-                const double pq = v ? 0.5 * P(M - v) : 0.0;
-                V2v[h] = idct_pre<T>((T)pp, (T)pq, ph[v]);
+                const T pp = v ? T(0.5) * P(v) : P(0);
+                const T pq = v ? T(0.5) * P(M - v) : T(0);
+                V2v[h] = idct_pre<T>(pp, pq, ph[v]);
             }
             work[l * M + brev(v, logM)] = cmk<T>(V2v[0].x - V2v[1].y, V2v[0].y + V2v[1].x);
         }
@@ -287,20 +289,30 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
     }
 }
 
+// Columns per block of the C pass: one complex line (two real columns) per block gives
+// mx / 2 blocks; the strided 8-byte row segments it reads come from L2/MALL, where the
+// intermediate maps live, so parallelism wins over coalescing here.
 template <typename T>
 static int cols_per_block(const NetDev &nd) {
-    int C = 16;
+    int C = 2;
     while (C > 2 && 2ull * C * nd.my * sizeof(T) > (unsigned long long)nd.lds_budget) C /= 2;
     return C < nd.mx ? C : nd.mx;
 }
 
-template <typename T>
-hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                           bool keep_maps, bool want_psi, hipStream_t st) {
-    // R1: lpb complex lines (2 rows each) per block
+// R1 takes lpb complex lines (2 rows each) per block
+static int rows_fwd_lines(const NetDev &nd) {
     int lpb = 512 / nd.mx;
     if (lpb < 1) lpb = 1;
     if (lpb > nd.my / 2) lpb = nd.my / 2;
+    return lpb;
+}
+
+int spectral_overflow_parts(const NetDev &nd) { return nd.my / 2 / rows_fwd_lines(nd); }
+
+template <typename T>
+hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                           bool keep_maps, bool want_psi, hipStream_t st) {
+    const int lpb = rows_fwd_lines(nd);
     size_t sh1 = sizeof(vec2<T>) * (size_t)lpb * nd.mx;
     HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kBlock), sh1, st, nd,
                        sa, L, lpb, (int)keep_maps);

@@ -1,34 +1,27 @@
-// Reductions that close an evaluation, the preconditioned Nesterov step, the HPWL total and
-// the best-of selection of Alg. 1.  Every floating-point total is a fixed-order reduction of
-// per-block partials (thread t sums partials t, t+256, ... then a fixed tree), so repeated
-// runs are bit-identical.
+// Closing reductions of an evaluation and of the HPWL sweep, the preconditioned Nesterov step,
+// the first-evaluation gradient combination, and the best-of selection of Alg. 1.  Every total
+// is a fixed-order reduction of per-block partials (thread t sums partials t, t+256, ... then
+// a fixed tree) by one block per slot, so repeated runs are bit-identical.
 #include "hp_device.h"
 
 namespace hp {
 
-__device__ double sum_parts(const double *p, int n, double *red) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
-    return block_sum(s, red);
-}
-__device__ double max_parts(const double *p, int n, double *red) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s = fmax(s, p[i]);
-    return block_max(s, red);
-}
-
-// Totals of one evaluation: WL (Eq. 3), energy N, overflow; on a slot's first evaluation
-// (scheduled lambda, not yet derived) lambda_0 = scale * |grad WL|_1 / |grad N|_1.
+// Totals of one evaluation: WL (Eq. 3), energy N, overflow; lambda_0 on a slot's first
+// evaluation with the scheduled lambda (scale * |grad WL|_1 / |grad N|_1); the lambda the
+// following step preconditions with.
 __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                            int nwl, int ne, int ncell,
+                                                            int nwl, int ne, int nov, int ncell,
                                                             int use_fixed, double lam_fixed) {
     __shared__ double red[4];
+    __shared__ long long redi[4];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
     const bool init = !use_fixed && sc->lambda_valid == 0;
     const double wl = sum_parts(part + PART_WL * L.pstride, nwl, red);
     const double e = sum_parts(part + PART_E * L.pstride, ne, red);
+    const long long ov =
+        sum_parts(reinterpret_cast<const long long *>(part) + PART_OVF * L.pstride, nov, redi);
     double n1 = 0.0, n2 = 0.0;
     if (init) {
         n1 = sum_parts(part + PART_N1 * L.pstride, ncell, red);
@@ -38,18 +31,42 @@ __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs
     if (threadIdx.x == 0) {
         sc->wl = wl;
         sc->energy = 0.5 * nd.wb * nd.hb * e;
-        const unsigned long long ov = sc->ovf_acc;
-        sc->overflow_num = (int64_t)ov;
+        sc->overflow_num = ov;
         sc->overflow = (double)ov / (double)nd.total_charge;
-        sc->ovf_acc = 0;
         sc->init_this_eval = init ? 1 : 0;
         if (init) {
             sc->lambda = sc->lambda0_scale * (n2 > 0.0 ? n1 / n2 : 1.0);
             sc->lambda_valid = 1;
         }
-        // the Nesterov step preconditions with the lambda this evaluation used
         sc->lambda_step = use_fixed ? lam_fixed : sc->lambda;
     }
+}
+
+// HPWL (Eq. 1) total of the per-block partials of the sweep.
+__global__ __launch_bounds__(kBlock) void hpwl_finish_kernel(SlotArgs sa, SlotLayout L, int n) {
+    __shared__ long long red[4];
+    char *base = sa.base[blockIdx.x];
+    const long long h =
+        sum_parts(reinterpret_cast<const long long *>(base + L.part) + PART_HPWL * L.pstride, n, red);
+    if (threadIdx.x == 0) {
+        Scalars *sc = scalars(base, L);
+        sc->hpwl_q = h;
+        sc->hpwl_valid = 1;
+    }
+}
+
+hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
+                              int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
+                              hipStream_t st) {
+    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa,
+              L, nwl, ne, nov, ncell, (int)use_fixed, lam_fixed);
+    return hipGetLastError();
+}
+
+hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, int nparts, hipStream_t st) {
+    HP_LAUNCH("hpwl_finish_kernel", hpwl_finish_kernel, dim3(sa.n), dim3(kBlock), 0, st, sa, L,
+              nparts);
+    return hipGetLastError();
 }
 
 // First evaluation only: g = gWL + lambda_0 gD.
@@ -66,13 +83,15 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(NetDev nd, SlotArgs sa,
 }
 
 // ---- Nesterov -------------------------------------------------------------------------------
-// Preconditioner P_i = max(1, pins_i + lambda area_i), g~ = g / P.
+// Preconditioner P_i = max(1, pins_i + lambda area_i), g~ = g / P, with the lambda of the
+// evaluation that produced g.
 template <typename T>
 __device__ __forceinline__ double precond(const T *cs, int n, int i, double lam) {
     const double P = (double)cs[i] + lam * (double)cs[n + i];
     return P < 1.0 ? 1.0 : P;
 }
 
+// Per block: |v - v_prev|^2, |g~ - g~_prev|^2, max|g~|.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     __shared__ double red[4];
@@ -99,32 +118,32 @@ __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs 
     dv = block_sum(dv, red);
     dg = block_sum(dg, red);
     gm = block_max(gm, red);
+    double *part = reinterpret_cast<double *>(base + L.part);
     if (threadIdx.x == 0) {
-        double *part = reinterpret_cast<double *>(base + L.part);
         part[PART_DV * L.pstride + blockIdx.x] = dv;
         part[PART_DG * L.pstride + blockIdx.x] = dg;
         part[PART_GMAX * L.pstride + blockIdx.x] = gm;
     }
 }
 
-// alpha_0 = 0.1 bin / max|g~|; alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein);
-// a' = (1 + sqrt(4 a^2 + 1)) / 2, momentum (a - 1) / a'; lambda grows by the schedule ratio.
+// alpha_0 = 0.1 bin / max|g~| or alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein);
+// a' = (1 + sqrt(4 a^2 + 1)) / 2 with momentum (a - 1) / a'; lambda grows by the schedule's
+// ratio.
 __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                             int ncell) {
+                                                             int nb) {
     __shared__ double red[4];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
-    const double dv = sum_parts(part + PART_DV * L.pstride, ncell, red);
-    const double dg = sum_parts(part + PART_DG * L.pstride, ncell, red);
-    const double gm = max_parts(part + PART_GMAX * L.pstride, ncell, red);
-    __syncthreads();
+    const double DV = sum_parts(part + PART_DV * L.pstride, nb, red);
+    const double DG = sum_parts(part + PART_DG * L.pstride, nb, red);
+    const double GM = max_parts(part + PART_GMAX * L.pstride, nb, red);
     if (threadIdx.x == 0) {
         double alpha;
         if (sc->k == 0)
-            alpha = 0.1 * nd.wb / (gm > 1e-30 ? gm : 1e-30);
+            alpha = 0.1 * nd.wb / (GM > 1e-30 ? GM : 1e-30);
         else
-            alpha = dg > 0.0 ? sqrt(dv) / sqrt(dg) : sc->alpha;
+            alpha = DG > 0.0 ? sqrt(DV) / sqrt(DG) : sc->alpha;
         const double a = sc->a;
         const double an = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
         sc->step_alpha = alpha;
@@ -136,6 +155,7 @@ __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArg
     }
 }
 
+// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     char *base = sa.base[blockIdx.y];
@@ -168,15 +188,6 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
         u[ip] = unt;
         v[ip] = (T)vn;
     }
-}
-
-// ---- HPWL total -----------------------------------------------------------------------------
-__global__ void hpwl_finish_kernel(SlotArgs sa, SlotLayout L) {
-    if (threadIdx.x != 0) return;
-    Scalars *sc = scalars(sa.base[blockIdx.x], L);
-    sc->hpwl_q = (int64_t)sc->hpwl_acc;
-    sc->hpwl_valid = 1;
-    sc->hpwl_acc = 0;
 }
 
 // ---- best of Alg. 1 -------------------------------------------------------------------------
@@ -229,15 +240,11 @@ __global__ __launch_bounds__(kBlock) void copy_best_kernel(NetDev nd, SlotArgs s
 
 // ---- launchers ------------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
-                              int ne, int ncell, bool use_fixed, double lam_fixed, bool any_init,
-                              hipStream_t st) {
-    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa,
-              L, nwl, ne, ncell, (int)use_fixed, lam_fixed);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !any_init || nd.n_mov == 0) return e;
+hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                          hipStream_t st) {
+    if (nd.n_mov == 0) return hipSuccess;
     HP_LAUNCH("combine_kernel", combine_kernel<T>, dim3((2 * nd.n_mov + kBlock - 1) / kBlock, sa.n),
-                       dim3(kBlock), 0, st, nd, sa, L);
+              dim3(kBlock), 0, st, nd, sa, L);
     return hipGetLastError();
 }
 
@@ -248,15 +255,12 @@ hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L
     HP_LAUNCH("step_norms_kernel", step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("step_scalars_kernel", step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa, L, nc);
+    HP_LAUNCH("step_scalars_kernel", step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa,
+              L, nc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
-    return hipGetLastError();
-}
-
-hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, hipStream_t st) {
-    HP_LAUNCH("hpwl_finish_kernel", hpwl_finish_kernel, dim3(sa.n), dim3(64), 0, st, sa, L);
+    HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa,
+              L);
     return hipGetLastError();
 }
 
@@ -266,14 +270,14 @@ hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumb
     HP_LAUNCH("select_best_kernel", select_best_kernel, dim3(1), dim3(64), 0, st, sa, incumbent, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nd.n_mov == 0) return e;
-    HP_LAUNCH("copy_best_kernel", copy_best_kernel<T>, dim3(cell_parts(nd)), dim3(kBlock), 0, st, nd, sa,
-                       incumbent, L);
+    HP_LAUNCH("copy_best_kernel", copy_best_kernel<T>, dim3(cell_parts(nd)), dim3(kBlock), 0, st, nd,
+              sa, incumbent, L);
     return hipGetLastError();
 }
 
 #define HP_INST(T)                                                                              \
-    template hipError_t launch_eval_finish<T>(const NetDev &, const SlotArgs &, const SlotLayout &, \
-                                              int, int, int, bool, double, bool, hipStream_t);  \
+    template hipError_t launch_combine<T>(const NetDev &, const SlotArgs &, const SlotLayout &,  \
+                                          hipStream_t);                                         \
     template hipError_t launch_step<T>(const NetDev &, const SlotArgs &, const SlotLayout &,     \
                                        hipStream_t);                                            \
     template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \

@@ -222,8 +222,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(NetDev nd, Buckets bk, Sl
         }
         __shared__ long long red[4];
         const long long tot = block_sum((long long)h, red);
-        if (threadIdx.x == 0 && tot != 0)
-            atomicAdd(&scalars(base, L)->hpwl_acc, (unsigned long long)tot);
+        if (threadIdx.x == 0)
+            (reinterpret_cast<long long *>(base + L.part) + PART_HPWL * L.pstride)[blockIdx.x] = tot;
     }
 }
 

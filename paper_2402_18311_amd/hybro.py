@@ -71,7 +71,7 @@ _SIGS = {
     "hp_select_best": [_P, _P, C.c_int32, C.c_int32, _P],
     "hp_get_map": [_P, C.c_int32, C.c_int, _P],
     "hp_get_state": [_P, C.c_int32, C.POINTER(hp_slot_state)],
-    "hp_profile_enable": [_P, C.c_int],
+    "hp_profile_enable": [_P, C.c_int, C.c_char_p],
     "hp_profile_read": [_P, _P, C.c_int32, C.POINTER(C.c_int32), C.c_int],
 }
 
@@ -80,8 +80,8 @@ class hp_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("count", C.c_int64), ("total_ms", C.c_double)]
 
 
-def hp_profile_enable(ctx, on):
-    _chk(lib().hp_profile_enable(ctx, int(on)))
+def hp_profile_enable(ctx, on, only_kernel=None):
+    _chk(lib().hp_profile_enable(ctx, int(on), None if only_kernel is None else only_kernel.encode()))
 
 
 def hp_profile_read(ctx, reset=True):
