@@ -126,8 +126,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.by, rs * nb);
     put(L.bp, rs * nb);
     put(L.psi, rs * nb);
-    put(L.ex, rs * nb);
-    put(L.ey, rs * nb);
+    put(L.exy, 2 * rs * nb);
     put(L.scal, sizeof(Scalars));
     L.pstride = part_stride(s, d);
     put(L.part, 8 * PART_COUNT * L.pstride);
@@ -292,6 +291,19 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     std::stable_sort(members[0].begin(), members[0].end(), [&](int a, int b) {
         return net_start[a + 1] - net_start[a] > net_start[b + 1] - net_start[b];
     });
+    // group-per-net buckets: order nets by their lowest cell, so neighbouring lanes gather
+    // neighbouring cells and each XCD's share of a bucket covers a compact cell range
+    {
+        std::vector<int32_t> minc(E, 0);
+        for (int e = 0; e < E; ++e) {
+            int32_t m = INT32_MAX;
+            for (int p = net_start[e]; p < net_start[e + 1]; ++p) m = std::min(m, pin_cell[p]);
+            minc[e] = m;
+        }
+        for (int b = 1; b < 7; ++b)
+            std::stable_sort(members[b].begin(), members[b].end(),
+                             [&](int a, int c) { return minc[a] < minc[c]; });
+    }
     std::vector<int> order;
     Buckets bk{};
     int blk = 0;
@@ -446,8 +458,8 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     std::vector<T> h_fp(2 * (size_t)Nf);
     std::vector<double> h_fxy(2 * (size_t)Nf), h_fwh(2 * (size_t)Nf);
     for (int i = 0; i < Nf; ++i) {
-        h_fp[i] = (T)fixed_x[i];
-        h_fp[(size_t)Nf + i] = (T)fixed_y[i];
+        h_fp[2 * (size_t)i] = (T)fixed_x[i];  // (x, y) pairs, the layout of slot positions
+        h_fp[2 * (size_t)i + 1] = (T)fixed_y[i];
         h_fxy[i] = fixed_x[i];
         h_fxy[(size_t)Nf + i] = fixed_y[i];
         h_fwh[i] = cell_w[Nm + i];
@@ -773,14 +785,12 @@ int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
     char *base = (char *)dev_buf;
     hipStream_t st = ctx->stream;
     const size_t rs = rsize(ctx);
-    const size_t Nc = NL.nd.n_cells, Nm = NL.nd.n_mov, Nf = NL.nd.n_fixed;
+    const size_t Nm = NL.nd.n_mov, Nf = NL.nd.n_fixed;
     HP_CHECK(hipMemsetAsync(base, 0, NL.L.total, st));
-    for (int a = 0; a < 2; ++a)
-        for (size_t off : {NL.L.u, NL.L.v})
-            if (Nf)
-                HP_CHECK(hipMemcpyAsync(base + off + (a * Nc + Nm) * rs,
-                                        (const char *)NL.nd.fixed_pos + a * Nf * rs, Nf * rs,
-                                        hipMemcpyDeviceToDevice, st));
+    for (size_t off : {NL.L.u, NL.L.v})  // fixed cells' (x, y) pairs after the movable ones
+        if (Nf)
+            HP_CHECK(hipMemcpyAsync(base + off + 2 * Nm * rs, NL.nd.fixed_pos, 2 * Nf * rs,
+                                    hipMemcpyDeviceToDevice, st));
     Scalars s;
     init_scalars(s, 1e-4, 4.0, 1000);
     HP_CHECK(hipMemcpyAsync(base + NL.L.scal, &s, sizeof(s), hipMemcpyHostToDevice, st));
@@ -811,15 +821,17 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!x || !y) return fail(HP_EINVAL, "x/y is NULL");
-    const size_t rs = rsize(ctx), Nc = n->nd.n_cells, Nm = n->nd.n_mov;
-    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     hipStream_t st = ctx->stream;
     const SlotLayout &L = n->L;
-    for (int a = 0; a < 2; ++a) {
-        const void *src = a ? y : x;
-        HP_CHECK(hipMemcpyAsync(s->base + L.u + a * Nc * rs, src, Nm * rs, k, st));
-        HP_CHECK(hipMemcpyAsync(s->base + L.v + a * Nc * rs, src, Nm * rs, k, st));
-        HP_CHECK(hipMemcpyAsync(s->base + L.vprev + a * Nm * rs, src, Nm * rs, k, st));
+    if (Nm) {
+        // interleave into u's (x, y) pairs, then copy u to v and v_prev
+        const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        for (int a = 0; a < 2; ++a)
+            HP_CHECK(hipMemcpy2DAsync(s->base + L.u + a * rs, 2 * rs, a ? y : x, rs, rs, Nm, k, st));
+        HP_CHECK(hipMemcpyAsync(s->base + L.v, s->base + L.u, 2 * Nm * rs, hipMemcpyDeviceToDevice, st));
+        HP_CHECK(hipMemcpyAsync(s->base + L.vprev, s->base + L.u, 2 * Nm * rs, hipMemcpyDeviceToDevice,
+                                st));
     }
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + L.scal, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -840,10 +852,11 @@ int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device)
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
-    const size_t rs = rsize(ctx), Nc = n->nd.n_cells, Nm = n->nd.n_mov;
+    const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (x) HP_CHECK(hipMemcpyAsync(x, s->base + n->L.u, Nm * rs, k, ctx->stream));
-    if (y) HP_CHECK(hipMemcpyAsync(y, s->base + n->L.u + Nc * rs, Nm * rs, k, ctx->stream));
+    if (Nm && x) HP_CHECK(hipMemcpy2DAsync(x, rs, s->base + n->L.u, 2 * rs, rs, Nm, k, ctx->stream));
+    if (Nm && y)
+        HP_CHECK(hipMemcpy2DAsync(y, rs, s->base + n->L.u + rs, 2 * rs, rs, Nm, k, ctx->stream));
     if (!on_device) HP_CHECK(hipStreamSynchronize(ctx->stream));
     return HP_OK;
 }
@@ -988,8 +1001,12 @@ int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
         switch (which) {
             case HP_MAP_RHO_MOV: src = s->base + n->L.rho; bytes = 8 * nb; break;
             case HP_MAP_PSI: src = s->base + n->L.psi; bytes = rs * nb; break;
-            case HP_MAP_EX: src = s->base + n->L.ex; bytes = rs * nb; break;
-            case HP_MAP_EY: src = s->base + n->L.ey; bytes = rs * nb; break;
+            case HP_MAP_EX:
+            case HP_MAP_EY:  // one component of the interleaved (xi_x, xi_y) map
+                HP_CHECK(hipMemcpy2DAsync(dst, rs, s->base + n->L.exy + (which == HP_MAP_EY ? rs : 0),
+                                          2 * rs, rs, nb, hipMemcpyDeviceToHost, ctx->stream));
+                HP_CHECK(hipStreamSynchronize(ctx->stream));
+                return HP_OK;
             default: return fail(HP_EINVAL, "unknown map");
         }
     }

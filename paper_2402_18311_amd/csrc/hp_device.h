@@ -4,6 +4,13 @@
 
 namespace hp {
 
+template <typename T> __device__ __forceinline__ vec2<T> cmk2(T a, T b) {
+    vec2<T> r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+
 __device__ __forceinline__ int64_t q16(double v) { return __double2ll_rn(v * 65536.0); }
 __device__ __forceinline__ int64_t q12(double v) { return __double2ll_rn(v * 4096.0); }
 

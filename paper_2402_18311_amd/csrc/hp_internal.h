@@ -64,13 +64,15 @@ struct NetDev {
 
 // Byte offsets of a slot's arrays inside its buffer (identical for all slots of a netlist).
 struct SlotLayout {
-    size_t u, v;          // T [2][n_cells] (fixed cells in the tail, never modified)
-    size_t vprev, gprev;  // T [2][n_mov]
+    size_t u, v;          // vec2<T> [n_cells] (x, y) pairs (fixed cells in the tail, unchanged)
+    size_t vprev;         // vec2<T> [n_mov]
+    size_t gprev;         // T [2][n_mov]
     size_t g, gd;         // T [2][n_mov] raw gradient; density part (first evaluation)
     size_t pin_grad;      // vec2<T> [ps]
     size_t rho;           // int64 [my][mx] movable charge
     size_t t1, bx, by, bp;// T [my][mx] spectral intermediates
-    size_t psi, ex, ey;   // T [my][mx]
+    size_t psi;           // T [my][mx] potential
+    size_t exy;           // vec2<T> [my][mx] field (xi_x, xi_y)
     size_t scal;          // Scalars
     size_t part;          // double partial sums, kPartStride per reduction
     size_t keys, sel, work; // perturbation scratch

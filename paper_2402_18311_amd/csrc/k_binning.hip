@@ -38,8 +38,9 @@ __device__ __forceinline__ int overlap_b(int lo, int hi, int idx, int w) {
 
 // tile of cell i, or -1 if its charge rectangle is empty (fully clipped)
 template <typename T>
-__device__ __forceinline__ int cell_tile(const NetDev &nd, const T *x, const T *y, int i) {
-    const RectQ q = cell_rect_b(nd, (double)x[i], (double)y[i], nd.cq[i]);
+__device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i) {
+    const vec2<T> p = pos[i];
+    const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
     if (q.r <= q.l || q.t <= q.b) return -1;
     return ((q.b / nd.hq) >> nd.log_ts) * nd.ntx + ((q.l / nd.bq) >> nd.log_ts);
 }
@@ -48,14 +49,13 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void bin_count_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     extern __shared__ int hist[];  // [ntiles]
     char *base = sa.base[blockIdx.y];
-    const T *x = reinterpret_cast<const T *>(base + L.v);
-    const T *y = x + nd.n_cells;
+    const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
     int *tile = reinterpret_cast<int *>(base + L.tile);
     for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) hist[t] = 0;
     __syncthreads();
     const int i0 = blockIdx.x * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
     for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        const int t = cell_tile<T>(nd, x, y, i);
+        const int t = cell_tile<T>(nd, pos, i);
         tile[i] = t;
         if (t >= 0) atomicAdd(&hist[t], 1);
     }
@@ -174,12 +174,12 @@ __global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nd, SlotArgs s
     for (int b = threadIdx.x; b < nw; b += kBlock) win[b] = 0;
     __syncthreads();
     const int j00 = (t % nd.ntx) << nd.log_ts, k00 = (t / nd.ntx) << nd.log_ts;
-    const T *x = reinterpret_cast<const T *>(base + L.v);
-    const T *y = x + nd.n_cells;
+    const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
     const int *sorted = reinterpret_cast<const int *>(base + L.sorted);
     for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
         const int i = sorted[s];
-        const RectQ q = cell_rect_b(nd, (double)x[i], (double)y[i], nd.cq[i]);
+        const vec2<T> p = pos[i];
+        const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
         const long long rq = nd.rq[i];
         const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
         const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;

@@ -76,11 +76,9 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             gwx += g.x;
             gwy += g.y;
         }
-        const T *x = reinterpret_cast<const T *>(base + L.v);
-        const T *y = x + nd.n_cells;
-        const T *ex = reinterpret_cast<const T *>(base + L.ex);
-        const T *ey = reinterpret_cast<const T *>(base + L.ey);
-        const RectQ q = cell_rect(nd, (double)x[i], (double)y[i], nd.cq[i]);
+        const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+        const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
+        const RectQ q = cell_rect(nd, (double)p.x, (double)p.y, nd.cq[i]);
         if (q.r > q.l && q.t > q.b) {
             const long long rq = nd.rq[i];
             const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
@@ -90,9 +88,9 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
                 for (int j = j0; j <= j1; ++j) {
                     const long long ox = overlap(q.l, q.r, j, nd.bq);
                     const T qq = (T)((double)(rq * ox * oy) * 0x1p-40);
-                    const size_t b = (size_t)k * nd.mx + j;
-                    gdx -= qq * ex[b];
-                    gdy -= qq * ey[b];
+                    const vec2<T> e = exy[(size_t)k * nd.mx + j];
+                    gdx -= qq * e.x;
+                    gdy -= qq * e.y;
                 }
             }
         }

@@ -61,13 +61,9 @@ __global__ __launch_bounds__(kBlock) void perturb_init_kernel(NetDev nd, char *b
     }
     if (i < 256) sc->hist[i] = 0;
     if (i >= nd.n_mov) return;
-    const T *u = reinterpret_cast<const T *>(base + L.u);
-    T *v = reinterpret_cast<T *>(base + L.v);
-    T *vp = reinterpret_cast<T *>(base + L.vprev);
-    v[i] = u[i];
-    v[nd.n_cells + i] = u[nd.n_cells + i];
-    vp[i] = u[i];
-    vp[nd.n_mov + i] = u[nd.n_cells + i];
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.u)[i];
+    reinterpret_cast<vec2<T> *>(base + L.v)[i] = p;
+    reinterpret_cast<vec2<T> *>(base + L.vprev)[i] = p;
     reinterpret_cast<uint64_t *>(base + L.keys)[i] = splitmix(seed, (uint64_t)i);
 }
 
@@ -194,11 +190,10 @@ __device__ __forceinline__ void put(char *base, const NetDev &nd, const SlotLayo
     const double hx = (double)cs[2 * nd.n_mov + c], hy = (double)cs[3 * nd.n_mov + c];
     x = x < 0.0 ? 0.0 : (x > hx ? hx : x);
     y = y < 0.0 ? 0.0 : (y > hy ? hy : y);
-    T *u = reinterpret_cast<T *>(base + L.u);
-    T *v = reinterpret_cast<T *>(base + L.v);
-    T *vp = reinterpret_cast<T *>(base + L.vprev);
-    u[c] = v[c] = vp[c] = (T)x;
-    u[nd.n_cells + c] = v[nd.n_cells + c] = vp[nd.n_mov + c] = (T)y;
+    const vec2<T> p = cmk2<T>((T)x, (T)y);
+    reinterpret_cast<vec2<T> *>(base + L.u)[c] = p;
+    reinterpret_cast<vec2<T> *>(base + L.v)[c] = p;
+    reinterpret_cast<vec2<T> *>(base + L.vprev)[c] = p;
 }
 
 template <typename T>
@@ -211,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void apply_gauss_kernel(NetDev nd, char *ba
     const uint64_t k2 = mix64(splitmix(seed, (uint64_t)c));
     const double u1 = ((double)(k2 >> 32) + 0.5) / 4294967296.0;
     const double u2 = ((double)(k2 & 0xffffffffULL) + 0.5) / 4294967296.0;
-    const T *u = reinterpret_cast<const T *>(base + L.u);
+    const vec2<T> *u = reinterpret_cast<const vec2<T> *>(base + L.u);
     if (uniform) {
         const T *cs = reinterpret_cast<const T *>(nd.cstep);
         put<T>(base, nd, L, c, u1 * (double)cs[2 * nd.n_mov + c], u2 * (double)cs[3 * nd.n_mov + c]);
@@ -219,7 +214,8 @@ __global__ __launch_bounds__(kBlock) void apply_gauss_kernel(NetDev nd, char *ba
     } else {
         const double rad = sqrt(-2.0 * log(u1));
         const double dx = sx * rad * cos(2.0 * M_PI * u2), dy = sy * rad * sin(2.0 * M_PI * u2);
-        put<T>(base, nd, L, c, (double)u[c] + dx, (double)u[nd.n_cells + c] + dy);
+        const vec2<T> p = u[c];
+        put<T>(base, nd, L, c, (double)p.x + dx, (double)p.y + dy);
     }
 }
 
@@ -231,11 +227,11 @@ __global__ __launch_bounds__(kBlock) void shuffle_gather_kernel(NetDev nd, char 
     if (j >= m) return;
     const int32_t *sel = reinterpret_cast<const int32_t *>(base + L.sel);
     const int s = sel[shuffle_perm((uint64_t)j, (uint64_t)m, seed)];
-    const T *u = reinterpret_cast<const T *>(base + L.u);
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.u)[s];
     const T *wh = reinterpret_cast<const T *>(nd.cell_wh);
     double *cen = reinterpret_cast<double *>(base + L.work);
-    cen[2 * j] = (double)u[s] + 0.5 * (double)wh[s];
-    cen[2 * j + 1] = (double)u[nd.n_cells + s] + 0.5 * (double)wh[nd.n_mov + s];
+    cen[2 * j] = (double)p.x + 0.5 * (double)wh[s];
+    cen[2 * j + 1] = (double)p.y + 0.5 * (double)wh[nd.n_mov + s];
 }
 
 template <typename T>

@@ -272,16 +272,14 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
     }
     __syncthreads();
     fft_lds<T>(work, nlines, M, logM, reinterpret_cast<const vec2<T> *>(nd.tw_x), true);
-    T *ex = reinterpret_cast<T *>(base + L.ex);
-    T *ey = reinterpret_cast<T *>(base + L.ey);
+    vec2<T> *exy = reinterpret_cast<vec2<T> *>(base + L.exy);
     T *psi = reinterpret_cast<T *>(base + L.psi);
     for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
         const int r = idx >> logM, j = idx & (M - 1);
         const int n = mperm(j, M);
         const vec2<T> z = work[r * M + n];
         const size_t o = (size_t)(k0 + r) * M + j;
-        ex[o] = (j & 1) ? -z.x : z.x;
-        ey[o] = z.y;
+        exy[o] = cmk<T>((j & 1) ? -z.x : z.x, z.y);
         if (want_psi) {
             const vec2<T> zp = work[2 * M + n];
             psi[o] = r ? zp.y : zp.x;

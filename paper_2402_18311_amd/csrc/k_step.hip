@@ -103,13 +103,13 @@ __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs 
     if (i < n) {
         const T *cs = reinterpret_cast<const T *>(nd.cstep);
         const double P = precond(cs, n, i, sc->lambda_step);
-        const T *v = reinterpret_cast<const T *>(base + L.v);
-        const T *vp = reinterpret_cast<const T *>(base + L.vprev);
+        const vec2<T> v = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+        const vec2<T> vp = reinterpret_cast<const vec2<T> *>(base + L.vprev)[i];
         const T *g = reinterpret_cast<const T *>(base + L.g);
         const T *gp = reinterpret_cast<const T *>(base + L.gprev);
         const double gx = (double)g[i] / P, gy = (double)g[n + i] / P;
-        const double ax = (double)v[i] - (double)vp[i];
-        const double ay = (double)v[nd.n_cells + i] - (double)vp[n + i];
+        const double ax = (double)v.x - (double)vp.x;
+        const double ay = (double)v.y - (double)vp.y;
         const double bx = gx - (double)gp[i], by = gy - (double)gp[n + i];
         dv = ax * ax + ay * ay;
         dg = bx * bx + by * by;
@@ -166,28 +166,30 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
     const T *cs = reinterpret_cast<const T *>(nd.cstep);
     const double P = precond(cs, n, i, sc->lambda_step);
     const double alpha = sc->step_alpha, coef = sc->step_coef;
-    T *u = reinterpret_cast<T *>(base + L.u);
-    T *v = reinterpret_cast<T *>(base + L.v);
-    T *vp = reinterpret_cast<T *>(base + L.vprev);
-    T *g = reinterpret_cast<T *>(base + L.g);
+    vec2<T> *u = reinterpret_cast<vec2<T> *>(base + L.u);
+    vec2<T> *v = reinterpret_cast<vec2<T> *>(base + L.v);
+    vec2<T> *vp = reinterpret_cast<vec2<T> *>(base + L.vprev);
+    const T *g = reinterpret_cast<const T *>(base + L.g);
     T *gp = reinterpret_cast<T *>(base + L.gprev);
+    const vec2<T> v0 = v[i], u0 = u[i];
+    T un2[2], vn2[2];
 #pragma unroll
     for (int ax = 0; ax < 2; ++ax) {
-        const size_t ip = (size_t)ax * nd.n_cells + i;  // positions: [2][n_cells]
-        const size_t ig = (size_t)ax * n + i;           // gradients: [2][n_mov]
+        const size_t ig = (size_t)ax * n + i;  // gradients: [2][n_mov]
         const double hi = (double)cs[(2 + ax) * n + i];
         const double gt = (double)g[ig] / P;
-        const double vv = (double)v[ip];
-        double un = vv - alpha * gt;
+        double un = (double)(ax ? v0.y : v0.x) - alpha * gt;
         un = un < 0.0 ? 0.0 : (un > hi ? hi : un);
         const T unt = (T)un;
-        double vn = (double)unt + coef * ((double)unt - (double)u[ip]);
+        double vn = (double)unt + coef * ((double)unt - (double)(ax ? u0.y : u0.x));
         vn = vn < 0.0 ? 0.0 : (vn > hi ? hi : vn);
-        vp[ig] = v[ip];
         gp[ig] = (T)gt;
-        u[ip] = unt;
-        v[ip] = (T)vn;
+        un2[ax] = unt;
+        vn2[ax] = (T)vn;
     }
+    vp[i] = v0;
+    u[i] = cmk2<T>(un2[0], un2[1]);
+    v[i] = cmk2<T>(vn2[0], vn2[1]);
 }
 
 // ---- best of Alg. 1 -------------------------------------------------------------------------
@@ -225,17 +227,10 @@ __global__ __launch_bounds__(kBlock) void copy_best_kernel(NetDev nd, SlotArgs s
     if (best < 0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= nd.n_mov) return;
-    const T *su = reinterpret_cast<const T *>(sa.base[best] + L.u);
-    T *u = reinterpret_cast<T *>(inc + L.u);
-    T *v = reinterpret_cast<T *>(inc + L.v);
-    T *vp = reinterpret_cast<T *>(inc + L.vprev);
-    const T x = su[i], y = su[nd.n_cells + i];
-    u[i] = x;
-    u[nd.n_cells + i] = y;
-    v[i] = x;
-    v[nd.n_cells + i] = y;
-    vp[i] = x;
-    vp[nd.n_mov + i] = y;
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(sa.base[best] + L.u)[i];
+    reinterpret_cast<vec2<T> *>(inc + L.u)[i] = p;
+    reinterpret_cast<vec2<T> *>(inc + L.v)[i] = p;
+    reinterpret_cast<vec2<T> *>(inc + L.vprev)[i] = p;
 }
 
 // ---- launchers ------------------------------------------------------------------------------

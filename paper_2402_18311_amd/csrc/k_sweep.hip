@@ -3,12 +3,12 @@
 //
 // Nets are grouped at load time by degree.  A net with d <= 64 pins is handled by an aligned
 // group of G = nextpow2(d) lanes, one pin per lane: the pin loads of a wave are contiguous
-// (coalesced), the cell-position loads are the only gathers, and the max/min/exp-sum
-// reductions are xor butterflies inside the group.  A larger net gets a whole block and
-// streams its pins three times (max/min, exp sums, gradients); the repeats hit L2.
-// Blocks of each bucket are remapped so that every XCD walks one contiguous eighth of the
-// bucket: with Rent-like netlists that eighth touches a compact range of cells, which keeps
-// each XCD's position gathers inside its own L2.
+// (coalesced), the cell-position loads (one interleaved (x, y) pair per pin) are the only
+// gathers, and the max/min/exp-sum reductions are xor butterflies inside the group.  A larger
+// net gets a whole block and streams its pins three times (max/min, exp sums, gradients); the
+// repeats hit L2.  Within a bucket nets are ordered by their lowest cell, and the blocks of
+// each bucket are remapped so that every XCD walks one contiguous eighth of it: neighbouring
+// lanes then gather neighbouring cells, and each XCD's gathers stay in a compact cell range.
 #include "hp_device.h"
 
 namespace hp {
@@ -22,8 +22,8 @@ namespace hp {
 //   dWL/dx_i = a+_i/b+ (1 + (x_i - m+ - r+)/gamma) - a-_i/b- (1 - (x_i - m- - r-)/gamma)
 template <typename T, int G>
 __device__ __forceinline__ void wa_groups(const NetDev &nd, int net0, int net1, int local,
-                                          const T *__restrict__ x, const T *__restrict__ y,
-                                          T invg, vec2<T> *__restrict__ pg, double &wl) {
+                                          const vec2<T> *__restrict__ pos, T invg,
+                                          vec2<T> *__restrict__ pg, double &wl) {
     constexpr int NPB = kBlock / G;
     const int lane = threadIdx.x & (G - 1);
     const int net = net0 + local * NPB + (int)threadIdx.x / G;
@@ -39,8 +39,9 @@ __device__ __forceinline__ void wa_groups(const NetDev &nd, int net0, int net1, 
     if (act) {
         const int c = nd.pin_cell[p];
         const vec2<T> o = reinterpret_cast<const vec2<T> *>(nd.pin_off)[p];
-        px = x[c] + o.x;
-        py = y[c] + o.y;
+        const vec2<T> q = pos[c];
+        px = q.x + o.x;
+        py = q.y + o.y;
     }
     const T inf = pos_inf<T>();
     const T xmax = group_max<G>(act ? px : -inf), xmin = group_min<G>(act ? px : inf);
@@ -68,18 +69,16 @@ __device__ __forceinline__ void wa_groups(const NetDev &nd, int net0, int net1, 
 }
 
 template <typename T>
-__device__ void wa_block(const NetDev &nd, int net, const T *__restrict__ x,
-                         const T *__restrict__ y, T invg, vec2<T> *__restrict__ pg,
-                         double &wl) {
+__device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ pos, T invg,
+                         vec2<T> *__restrict__ pg, double &wl) {
     __shared__ T red[4];
     const int s = nd.net_start[net], d = nd.net_start[net + 1] - s;
     const T inf = pos_inf<T>();
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
     T lxM = -inf, lxm = inf, lyM = -inf, lym = inf;
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const int c = nd.pin_cell[s + i];
-        const vec2<T> o = off[s + i];
-        const T px = x[c] + o.x, py = y[c] + o.y;
+        const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
+        const T px = q.x + o.x, py = q.y + o.y;
         lxM = max(lxM, px);
         lxm = min(lxm, px);
         lyM = max(lyM, py);
@@ -89,9 +88,8 @@ __device__ void wa_block(const NetDev &nd, int net, const T *__restrict__ x,
     const T ymax = block_max(lyM, red), ymin = block_min(lym, red);
     T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const int c = nd.pin_cell[s + i];
-        const vec2<T> o = off[s + i];
-        const T px = x[c] + o.x, py = y[c] + o.y;
+        const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
+        const T px = q.x + o.x, py = q.y + o.y;
         const T dxp = px - xmax, dxm = px - xmin, dyp = py - ymax, dym = py - ymin;
         const T axp = dev_exp<T>(dxp * invg), axm = dev_exp<T>(-dxm * invg);
         const T ayp = dev_exp<T>(dyp * invg), aym = dev_exp<T>(-dym * invg);
@@ -110,9 +108,8 @@ __device__ void wa_block(const NetDev &nd, int net, const T *__restrict__ x,
     const T ryp = block_sum(s6, red) / byp, rym = block_sum(s7, red) / bym;
     const T w = nd.net_w ? reinterpret_cast<const T *>(nd.net_w)[net] : T(1);
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const int c = nd.pin_cell[s + i];
-        const vec2<T> o = off[s + i];
-        const T px = x[c] + o.x, py = y[c] + o.y;
+        const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
+        const T px = q.x + o.x, py = q.y + o.y;
         const T dxp = px - xmax, dxm = px - xmin, dyp = py - ymax, dym = py - ymin;
         const T axp = dev_exp<T>(dxp * invg), axm = dev_exp<T>(-dxm * invg);
         const T ayp = dev_exp<T>(dyp * invg), aym = dev_exp<T>(-dym * invg);
@@ -130,8 +127,7 @@ __device__ void wa_block(const NetDev &nd, int net, const T *__restrict__ x,
 // Pin coordinate q16(cell) + q16(offset), both exact integers; per net the x and y extents.
 template <typename T, int G>
 __device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, int net0, int net1, int local,
-                                               const T *__restrict__ x,
-                                               const T *__restrict__ y) {
+                                               const vec2<T> *__restrict__ pos) {
     constexpr int NPB = kBlock / G;
     const int lane = threadIdx.x & (G - 1);
     const int net = net0 + local * NPB + (int)threadIdx.x / G;
@@ -143,10 +139,10 @@ __device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, int net0, int n
     const bool act = lane < d;
     long long px = 0, py = 0;
     if (act) {
-        const int c = nd.pin_cell[s + lane];
+        const vec2<T> q = pos[nd.pin_cell[s + lane]];
         const int2 o = nd.pin_offq[s + lane];
-        px = q16((double)x[c]) + o.x;
-        py = q16((double)y[c]) + o.y;
+        px = q16((double)q.x) + o.x;
+        py = q16((double)q.y) + o.y;
     }
     const long long big = 0x3fffffffffffffffLL;
     const long long xM = group_max<G>(act ? px : -big), xm = group_min<G>(act ? px : big);
@@ -155,16 +151,15 @@ __device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, int net0, int n
 }
 
 template <typename T>
-__device__ int64_t hpwl_block(const NetDev &nd, int net, const T *__restrict__ x,
-                              const T *__restrict__ y) {
+__device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restrict__ pos) {
     __shared__ long long red[4];
     const int s = nd.net_start[net], d = nd.net_start[net + 1] - s;
     const long long big = 0x3fffffffffffffffLL;
     long long xM = -big, xm = big, yM = -big, ym = big;
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const int c = nd.pin_cell[s + i];
+        const vec2<T> q = pos[nd.pin_cell[s + i]];
         const int2 o = nd.pin_offq[s + i];
-        const long long px = q16((double)x[c]) + o.x, py = q16((double)y[c]) + o.y;
+        const long long px = q16((double)q.x) + o.x, py = q16((double)q.y) + o.y;
         xM = max(xM, px);
         xm = min(xm, px);
         yM = max(yM, py);
@@ -187,20 +182,19 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(NetDev nd, Buckets bk, Sl
     while (b + 1 < bk.n && (int)blockIdx.x >= bk.blk0[b + 1]) ++b;
     const int local = xcd_remap((int)blockIdx.x - bk.blk0[b], bk.nblk[b]);
     const int net0 = bk.net0[b], net1 = bk.net1[b];
-    const T *x = reinterpret_cast<const T *>(base + (MODE == MODE_WA ? L.v : L.u));
-    const T *y = x + nd.n_cells;
+    const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + (MODE == MODE_WA ? L.v : L.u));
     if constexpr (MODE == MODE_WA) {
         vec2<T> *pg = reinterpret_cast<vec2<T> *>(base + L.pin_grad);
         double wl = 0.0;
         switch (bk.G[b]) {
-            case 2: wa_groups<T, 2>(nd, net0, net1, local, x, y, invg, pg, wl); break;
-            case 4: wa_groups<T, 4>(nd, net0, net1, local, x, y, invg, pg, wl); break;
-            case 8: wa_groups<T, 8>(nd, net0, net1, local, x, y, invg, pg, wl); break;
-            case 16: wa_groups<T, 16>(nd, net0, net1, local, x, y, invg, pg, wl); break;
-            case 32: wa_groups<T, 32>(nd, net0, net1, local, x, y, invg, pg, wl); break;
-            case 64: wa_groups<T, 64>(nd, net0, net1, local, x, y, invg, pg, wl); break;
+            case 2: wa_groups<T, 2>(nd, net0, net1, local, pos, invg, pg, wl); break;
+            case 4: wa_groups<T, 4>(nd, net0, net1, local, pos, invg, pg, wl); break;
+            case 8: wa_groups<T, 8>(nd, net0, net1, local, pos, invg, pg, wl); break;
+            case 16: wa_groups<T, 16>(nd, net0, net1, local, pos, invg, pg, wl); break;
+            case 32: wa_groups<T, 32>(nd, net0, net1, local, pos, invg, pg, wl); break;
+            case 64: wa_groups<T, 64>(nd, net0, net1, local, pos, invg, pg, wl); break;
             default:
-                if (net0 + local < net1) wa_block<T>(nd, net0 + local, x, y, invg, pg, wl);
+                if (net0 + local < net1) wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
                 break;
         }
         __shared__ double red[4];
@@ -210,14 +204,14 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(NetDev nd, Buckets bk, Sl
     } else {
         int64_t h = 0;
         switch (bk.G[b]) {
-            case 2: h = hpwl_groups<T, 2>(nd, net0, net1, local, x, y); break;
-            case 4: h = hpwl_groups<T, 4>(nd, net0, net1, local, x, y); break;
-            case 8: h = hpwl_groups<T, 8>(nd, net0, net1, local, x, y); break;
-            case 16: h = hpwl_groups<T, 16>(nd, net0, net1, local, x, y); break;
-            case 32: h = hpwl_groups<T, 32>(nd, net0, net1, local, x, y); break;
-            case 64: h = hpwl_groups<T, 64>(nd, net0, net1, local, x, y); break;
+            case 2: h = hpwl_groups<T, 2>(nd, net0, net1, local, pos); break;
+            case 4: h = hpwl_groups<T, 4>(nd, net0, net1, local, pos); break;
+            case 8: h = hpwl_groups<T, 8>(nd, net0, net1, local, pos); break;
+            case 16: h = hpwl_groups<T, 16>(nd, net0, net1, local, pos); break;
+            case 32: h = hpwl_groups<T, 32>(nd, net0, net1, local, pos); break;
+            case 64: h = hpwl_groups<T, 64>(nd, net0, net1, local, pos); break;
             default:
-                if (net0 + local < net1) h = hpwl_block<T>(nd, net0 + local, x, y);
+                if (net0 + local < net1) h = hpwl_block<T>(nd, net0 + local, pos);
                 break;
         }
         __shared__ long long red[4];
@@ -232,20 +226,18 @@ int sweep_parts(const Buckets &bk) { return bk.total_blocks; }
 template <typename T>
 hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                            const SlotLayout &L, double inv_gamma, hipStream_t st) {
-    if (bk.total_blocks == 0) return hipSuccess;
     dim3 grid(bk.total_blocks, sa.n);
     HP_LAUNCH("sweep_wa", (sweep_kernel<T, MODE_WA>), grid, dim3(kBlock), 0, st, nd, bk, sa, L,
-                       (T)inv_gamma);
+              (T)inv_gamma);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st) {
-    if (bk.total_blocks == 0) return hipSuccess;
     dim3 grid(bk.total_blocks, sa.n);
     HP_LAUNCH("sweep_hpwl", (sweep_kernel<T, MODE_HPWL>), grid, dim3(kBlock), 0, st, nd, bk, sa,
-                       L, (T)0);
+              L, (T)0);
     return hipGetLastError();
 }
 
