@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no roofline)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the round, copy 256 MiB device-to-device once: the reference "
+                         "dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the placer on a single MI355X; "
@@ -194,6 +197,12 @@ def main():
     final = pl.state(inc)
     log(f"[bench] timed {K} iterations in {dt:.3f} s; incumbent HPWL "
         f"{final['hpwl_q'] / 65536:.1f}")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     roof = None
     if dom and dom in live:

@@ -161,6 +161,7 @@ struct Slot {
     char *base = nullptr;
     bool lambda_valid = false;  // host mirror of the device flag
     bool maps_valid = false;
+    bool hpwl_pending = false;  // an HPWL sweep ran; its partials are not yet reduced
 };
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -561,6 +562,22 @@ int resolve(hp_ctx *ctx, const int32_t *slots, int32_t n, Netlist **net,
     return HP_OK;
 }
 
+// Reduce the HPWL partials of slots whose sweep has not been totalled yet.
+int finish_hpwl(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
+    SlotArgs sa{};
+    for (Slot *s : ss) {
+        if (!s->hpwl_pending) continue;
+        s->hpwl_pending = false;
+        sa.base[sa.n++] = s->base;
+        if (sa.n == kMaxSlots) {
+            HP_CHECK(launch_hpwl_finish(sa, NL->L, NL->bk.total_blocks, ctx->stream));
+            sa.n = 0;
+        }
+    }
+    if (sa.n) HP_CHECK(launch_hpwl_finish(sa, NL->L, NL->bk.total_blocks, ctx->stream));
+    return HP_OK;
+}
+
 template <typename T>
 int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p, double *wl,
               double *energy, double *overflow, void *gx, void *gy) {
@@ -844,6 +861,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     HP_CHECK(hipMemcpyAsync(s->base + L.scal, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HP_CHECK(hipStreamSynchronize(st));
     s->lambda_valid = false;
+    s->hpwl_pending = false;
     return HP_OK;
 }
 
@@ -920,6 +938,7 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
         HP_CHECK(launch_perturb<double>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
                                         sigma_bins * n->nd.hb, seed, ctx->stream));
     s->lambda_valid = false;
+    s->hpwl_pending = false;  // the device cleared hpwl_valid
     if (out_idx && m)
         HP_CHECK(hipMemcpyAsync(out_idx, s->base + n->L.sel, 4 * (size_t)m, hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -939,9 +958,12 @@ int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double
             HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
         else
             HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
-        HP_CHECK(launch_hpwl_finish(sa, NL->L, NL->bk.total_blocks, ctx->stream));
     }
+    // the total is reduced from the sweep's per-block partials when first needed
+    for (Slot *s : ss) s->hpwl_pending = true;
     if (out_q || out) {
+        rc = finish_hpwl(ctx, NL, ss);
+        if (rc) return rc;
         std::vector<int64_t> h(n);
         for (int i = 0; i < n; ++i)
             HP_CHECK(hipMemcpyAsync(&h[i], ss[i]->base + NL->L.scal + offsetof(Scalars, hpwl_q), 8,
@@ -969,6 +991,10 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbe
     if (ni != NL) return fail(HP_ESTATE, "incumbent is on another netlist");
     for (Slot *s : ss)
         if (s == inc) return fail(HP_EINVAL, "the incumbent cannot be a candidate");
+    std::vector<Slot *> all(ss);
+    all.push_back(inc);
+    rc = finish_hpwl(ctx, NL, all);
+    if (rc) return rc;
     if (ctx->precision == 32)
         HP_CHECK(launch_select_best<float>(NL->nd, chunks[0], inc->base, NL->L, ctx->stream));
     else
@@ -1021,6 +1047,8 @@ int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!out) return fail(HP_EINVAL, "out is NULL");
+    rc = finish_hpwl(ctx, n, std::vector<Slot *>{s});
+    if (rc) return rc;
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HP_CHECK(hipStreamSynchronize(ctx->stream));

@@ -69,12 +69,20 @@ template <typename T> __device__ __forceinline__ T block_min(T v, T *red) {
 // Fixed-order sums of n per-block partials by one block (thread t takes t, t+256, ...).
 template <typename T> __device__ T sum_parts(const T *p, int n, T *red) {
     T s = 0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
+    int i = threadIdx.x;
+    for (; i + 3 * kBlock < n; i += 4 * kBlock) {  // four independent loads in flight
+        const T a = p[i], b = p[i + kBlock], c = p[i + 2 * kBlock], d = p[i + 3 * kBlock];
+        s += (a + b) + (c + d);
+    }
+    for (; i < n; i += kBlock) s += p[i];
     return block_sum(s, red);
 }
 __device__ inline double max_parts(const double *p, int n, double *red) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s = fmax(s, p[i]);
+    int i = threadIdx.x;
+    for (; i + 3 * kBlock < n; i += 4 * kBlock)
+        s = fmax(fmax(s, fmax(p[i], p[i + kBlock])), fmax(p[i + 2 * kBlock], p[i + 3 * kBlock]));
+    for (; i < n; i += kBlock) s = fmax(s, p[i]);
     return block_max(s, red);
 }
 

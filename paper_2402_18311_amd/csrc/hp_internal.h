@@ -1,6 +1,7 @@
 // Internal structures shared by the host code and the kernels of libhybro (gfx950 only).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace hp {
@@ -116,7 +117,7 @@ __host__ __device__ inline Scalars *scalars(char *base, const SlotLayout &L) {
 }
 
 // ---- optional per-kernel timing --------------------------------------------------------------
-// When enabled, every launch is bracketed by two HIP events on its stream; the elapsed times
+// When enabled, every selected launch carries a start and a stop HIP event; the elapsed times
 // are collected by hp_profile_read.
 struct ProfRec {
     const char *name;
@@ -126,13 +127,13 @@ bool prof_want(const char *name);
 hipEvent_t prof_event();
 void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
 
+// The events are handed to the dispatch itself (hipExtLaunchKernelGGL), so they time the
+// kernel's execution, not the gap before it starts.
 #define HP_LAUNCH(NAME, K, GRID, BLOCK, SHMEM, STREAM, ...)                              \
     do {                                                                                \
         if (::hp::prof_want(NAME)) {                                                    \
             hipEvent_t ea_ = ::hp::prof_event(), eb_ = ::hp::prof_event();              \
-            (void)hipEventRecord(ea_, STREAM);                                          \
-            hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);              \
-            (void)hipEventRecord(eb_, STREAM);                                          \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, ea_, eb_, 0, __VA_ARGS__); \
             ::hp::prof_push(NAME, ea_, eb_);                                            \
         } else {                                                                        \
             hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);              \

@@ -1,8 +1,9 @@
 // Spectral Poisson solve on the bin grid (the electrostatic density term; cosine basis,
 // Neumann walls), in three LDS-staged passes over the [my][mx] maps:
 //
-//   R1 (rows):    rho = (movable + fixed charge) * unit; T1[k][u] = sum_j rho_kj C_x(u, j)
-//                 also the overflow sum, and the movable map is cleared for the next call
+//   R1 (rows):    rho = (movable + fixed charge) * unit; T1[k][u] = sum_j rho_kj C_x(u, j);
+//                 the movable charge is assembled from the binned scatter's windows, and the
+//                 overflow partial sums are taken on the way
 //   C  (columns): a_uv = c_u c_v / (mx my) sum_k T1[k][u] C_y(v, k); energy partial sums;
 //                 Bx[k][u] = sum_v a_uv w_u/den C_y(v, k), By[k][u] = sum_v a_uv w_v/den S_y(v, k),
 //                 Bp[k][u] = sum_v a_uv/den C_y(v, k)
@@ -15,8 +16,9 @@
 // inverse, V_u = exp(i pi u / 2M)(A'_u - i A'_{M-u}) with A'_0 = A_0, A'_u = A_u / 2, A'_M = 0,
 //   v = IFFT(V) is real and x_2n = v_n, x_{2n+1} = v_{M-1-n};
 // and a sine sum is a cosine sum of the reversed coefficients times (-1)^j.  Two real lines
-// share one complex FFT.  The FFT is a radix-2 decimation-in-time transform in LDS over a
-// batch of lines, with twiddles from a table built on the host in double precision.
+// share one complex FFT.  The FFT is a decimation-in-time transform in LDS (radix-4 passes,
+// one radix-2 pass for odd log M) over a batch of lines.  Each block first copies the
+// twiddles, DCT phases and per-axis symbols (tables built on the host in FP64) to LDS.
 #include "hp_device.h"
 
 namespace hp {
@@ -28,19 +30,56 @@ __device__ __forceinline__ vec2<T> cmk(T a, T b) {
     r.y = b;
     return r;
 }
+template <typename T>
+__device__ __forceinline__ vec2<T> cmul(vec2<T> a, vec2<T> b) {
+    return cmk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ vec2<T> cadd(vec2<T> a, vec2<T> b) { return cmk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ vec2<T> csub(vec2<T> a, vec2<T> b) { return cmk<T>(a.x - b.x, a.y - b.y); }
 
 __device__ __forceinline__ int brev(int n, int logM) { return (int)(__brev((unsigned)n) >> (32 - logM)); }
 // position of element j in Makhoul's reordered sequence (and of output j in the inverse)
 __device__ __forceinline__ int mperm(int j, int M) { return (j & 1) ? (M - 1 - (j >> 1)) : (j >> 1); }
 
+// In-place FFT of nlines lines of length M held in bit-reversed order; tw[k] = exp(-2 pi i k/M)
+// (conjugated for the inverse).  A radix-4 pass performs DIT stages s and s+1 at once: with
+// h = 2^s, w1 = W_{2h}^pos and w2 = W_{4h}^pos, and W_{4h}^h = -i (forward) or +i (inverse).
 template <typename T>
-__device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T> *__restrict__ tw,
-                        bool inverse) {
-    const int hm = M >> 1;
-    const int total = nlines * hm;
-    for (int s = 0; s < logM; ++s) {
-        const int half = 1 << s;
-        const int tsh = logM - 1 - s;
+__device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T> *tw, bool inverse) {
+    int s = 0;
+    for (; s + 1 < logM; s += 2) {
+        const int h = 1 << s;
+        const int q = M >> 2;
+        const int total = nlines * q;
+        const int sh1 = logM - 1 - s, sh2 = logM - 2 - s;
+        for (int b = threadIdx.x; b < total; b += kBlock) {
+            const int line = b >> (logM - 2);
+            const int t = b & (q - 1);
+            const int pos = t & (h - 1);
+            const int i0 = ((t >> s) << (s + 2)) | pos;
+            vec2<T> w1 = tw[pos << sh1], w2 = tw[pos << sh2];
+            if (inverse) {
+                w1.y = -w1.y;
+                w2.y = -w2.y;
+            }
+            vec2<T> *Lb = buf + (size_t)line * M;
+            const vec2<T> x0 = Lb[i0], x1 = Lb[i0 + h], x2 = Lb[i0 + 2 * h], x3 = Lb[i0 + 3 * h];
+            const vec2<T> c1 = cmul<T>(w1, x1), c3 = cmul<T>(w1, x3);
+            const vec2<T> b0 = cadd<T>(x0, c1), b1 = csub<T>(x0, c1);
+            const vec2<T> b2 = cadd<T>(x2, c3), b3 = csub<T>(x2, c3);
+            const vec2<T> d2 = cmul<T>(w2, b2), d3 = cmul<T>(w2, b3);
+            const vec2<T> e3 = inverse ? cmk<T>(-d3.y, d3.x) : cmk<T>(d3.y, -d3.x);
+            Lb[i0] = cadd<T>(b0, d2);
+            Lb[i0 + 2 * h] = csub<T>(b0, d2);
+            Lb[i0 + h] = cadd<T>(b1, e3);
+            Lb[i0 + 3 * h] = csub<T>(b1, e3);
+        }
+        __syncthreads();
+    }
+    if (s < logM) {  // one radix-2 stage left
+        const int half = 1 << s, hm = M >> 1, total = nlines * hm, tsh = logM - 1 - s;
         for (int b = threadIdx.x; b < total; b += kBlock) {
             const int line = b >> (logM - 1);
             const int t = b & (hm - 1);
@@ -49,10 +88,9 @@ __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T>
             vec2<T> w = tw[pos << tsh];
             if (inverse) w.y = -w.y;
             vec2<T> *Lb = buf + (size_t)line * M;
-            const vec2<T> a = Lb[i0], c0 = Lb[i0 + half];
-            const T cr = c0.x * w.x - c0.y * w.y, ci = c0.x * w.y + c0.y * w.x;
-            Lb[i0] = cmk<T>(a.x + cr, a.y + ci);
-            Lb[i0 + half] = cmk<T>(a.x - cr, a.y - ci);
+            const vec2<T> a = Lb[i0], c = cmul<T>(w, Lb[i0 + half]);
+            Lb[i0] = cadd<T>(a, c);
+            Lb[i0 + half] = csub<T>(a, c);
         }
         __syncthreads();
     }
@@ -75,14 +113,32 @@ __device__ __forceinline__ vec2<T> idct_pre(T p, T q, vec2<T> ph) {
     return cmk<T>(p * ph.x + q * ph.y, p * ph.y - q * ph.x);
 }
 
+// Copy the FFT twiddles (M/2) and DCT phases (M) of one axis to LDS.
+template <typename T>
+__device__ __forceinline__ void load_tables(vec2<T> *s_tw, vec2<T> *s_ph, const void *tw, const void *ph,
+                                            int M) {
+    const vec2<T> *gtw = reinterpret_cast<const vec2<T> *>(tw);
+    const vec2<T> *gph = reinterpret_cast<const vec2<T> *>(ph);
+    for (int i = threadIdx.x; i < M / 2; i += kBlock) s_tw[i] = gtw[i];
+    for (int i = threadIdx.x; i < M; i += kBlock) s_ph[i] = gph[i];
+}
+
+// LDS layout helpers (16-byte aligned sections)
+__host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
+
 // ---- R1 ---------------------------------------------------------------------------------
+// lds: tw [M/2] | ph [M] | buf [lpb][M]
 template <typename T>
 __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, SlotLayout L,
                                                         int lpb, int keep) {
     extern __shared__ __align__(16) unsigned char smem[];
-    vec2<T> *buf = reinterpret_cast<vec2<T> *>(smem);
-    char *base = sa.base[blockIdx.y];
     const int M = nd.mx, logM = nd.logmx;
+    vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem);
+    vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + al16(sizeof(vec2<T>) * (M / 2)));
+    vec2<T> *buf = reinterpret_cast<vec2<T> *>(smem + al16(sizeof(vec2<T>) * (M / 2)) +
+                                               al16(sizeof(vec2<T>) * M));
+    char *base = sa.base[blockIdx.y];
+    load_tables<T>(s_tw, s_ph, nd.tw_x, nd.ph_x, M);
     int64_t *rho = reinterpret_cast<int64_t *>(base + L.rho);
     T *t1 = reinterpret_cast<T *>(base + L.t1);
     long long over = 0;
@@ -104,12 +160,11 @@ __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, 
             cmk<T>((T)((double)(ma + fa) * nd.density_unit), (T)((double)(mb + fb) * nd.density_unit));
     }
     __syncthreads();
-    fft_lds<T>(buf, lpb, M, logM, reinterpret_cast<const vec2<T> *>(nd.tw_x), false);
-    const vec2<T> *ph = reinterpret_cast<const vec2<T> *>(nd.ph_x);
+    fft_lds<T>(buf, lpb, M, logM, s_tw, false);
     for (int idx = threadIdx.x; idx < lpb * M; idx += kBlock) {
         const int l = idx >> logM, u = idx & (M - 1);
         const int ra = (blockIdx.x * lpb + l) * 2;
-        const vec2<T> F = dct_post<T>(buf + l * M, u, M, ph[u]);
+        const vec2<T> F = dct_post<T>(buf + l * M, u, M, s_ph[u]);
         t1[(size_t)ra * M + u] = F.x;
         t1[(size_t)(ra + 1) * M + u] = F.y;
     }
@@ -119,41 +174,58 @@ __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, 
         (reinterpret_cast<long long *>(base + L.part) + PART_OVF * L.pstride)[blockIdx.x] = over;
 }
 
-// ---- C ----------------------------------------------------------------------------------
+// ---- C: two columns per block -------------------------------------------------------------
+// lds: tw [M/2] | ph [M] | den_y [M] | om_y [M] | acol [2][M] | work [2][M]
 template <typename T>
-__global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L, int C,
-                                                    int logC, int want_psi) {
+__host__ __device__ inline size_t cols_lds(int M) {
+    return al16(sizeof(vec2<T>) * (M / 2)) + al16(sizeof(vec2<T>) * M) + 2 * al16(sizeof(T) * M) +
+           al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L, int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.my, logM = nd.logmy, mx = nd.mx;
-    T *acol = reinterpret_cast<T *>(smem);                                  // [C][M]
-    vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + sizeof(T) * (size_t)C * M);  // [C/2][M]
+    size_t o = 0;
+    vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem + o);
+    o += al16(sizeof(vec2<T>) * (M / 2));
+    vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + o);
+    o += al16(sizeof(vec2<T>) * M);
+    T *s_den = reinterpret_cast<T *>(smem + o);
+    o += al16(sizeof(T) * M);
+    T *s_om = reinterpret_cast<T *>(smem + o);
+    o += al16(sizeof(T) * M);
+    T *acol = reinterpret_cast<T *>(smem + o);  // [2][M]
+    o += al16(sizeof(T) * 2 * M);
+    vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M]
     char *base = sa.base[blockIdx.y];
-    const int u0 = blockIdx.x * C;
+    const int u0 = blockIdx.x * 2;
+    load_tables<T>(s_tw, s_ph, nd.tw_y, nd.ph_y, M);
+    for (int v = threadIdx.x; v < M; v += kBlock) {
+        s_den[v] = (T)nd.den1[mx + v];
+        s_om[v] = (T)nd.omega[mx + v];
+    }
+    // load the two columns as one complex line, Makhoul-reordered, bit-reversed
     const T *t1 = reinterpret_cast<const T *>(base + L.t1);
-    const vec2<T> *tw = reinterpret_cast<const vec2<T> *>(nd.tw_y);
-    const vec2<T> *ph = reinterpret_cast<const vec2<T> *>(nd.ph_y);
-    T *wr = reinterpret_cast<T *>(work);
-    // load the column strip, two columns per complex line, Makhoul-reordered, bit-reversed
-    for (int idx = threadIdx.x; idx < C * M; idx += kBlock) {
-        const int k = idx >> logC, c = idx & (C - 1);
-        wr[2 * ((c >> 1) * M + brev(mperm(k, M), logM)) + (c & 1)] = t1[(size_t)k * mx + u0 + c];
+    for (int k = threadIdx.x; k < M; k += kBlock) {
+        const vec2<T> c = *reinterpret_cast<const vec2<T> *>(t1 + (size_t)k * mx + u0);
+        work[brev(mperm(k, M), logM)] = c;
     }
     __syncthreads();
-    fft_lds<T>(work, C / 2, M, logM, tw, false);
+    fft_lds<T>(work, 1, M, logM, s_tw, false);
     const double norm = 1.0 / ((double)nd.mx * nd.my);
+    const double cu0 = u0 ? 2.0 : 1.0;  // u0 + 1 > 0 always
+    const double dux0 = nd.den1[u0], dux1 = nd.den1[u0 + 1];
     double e = 0.0;
-    for (int idx = threadIdx.x; idx < (C / 2) * M; idx += kBlock) {
-        const int l = idx >> logM, v = idx & (M - 1);
-        const vec2<T> F = dct_post<T>(work + l * M, v, M, ph[v]);
+    for (int v = threadIdx.x; v < M; v += kBlock) {
+        const vec2<T> F = dct_post<T>(work, v, M, s_ph[v]);
         const double cv = v ? 2.0 : 1.0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = 2 * l + h, u = u0 + c;
-            const double cu = u ? 2.0 : 1.0;
-            const double a = cu * cv * norm * (double)(h ? F.y : F.x);
-            acol[c * M + v] = (T)a;
-            if (u | v) e += a * a * ((double)nd.mx * nd.my) / (cu * cv * (nd.den1[u] + nd.den1[mx + v]));
-        }
+        const double a0 = cu0 * cv * norm * (double)F.x, a1 = 2.0 * cv * norm * (double)F.y;
+        acol[v] = (T)a0;
+        acol[M + v] = (T)a1;
+        const double dv = nd.den1[mx + v];
+        if (u0 | v) e += a0 * a0 * ((double)nd.mx * nd.my) / (cu0 * cv * (dux0 + dv));
+        e += a1 * a1 * ((double)nd.mx * nd.my) / (2.0 * cv * (dux1 + dv));
     }
     __syncthreads();
     __shared__ double red[4];
@@ -161,87 +233,76 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
     if (threadIdx.x == 0)
         reinterpret_cast<double *>(base + L.part)[PART_E * L.pstride + blockIdx.x] = e;
 
+    // (Bx + i By) of column h on complex line h: X(v) = a_uv w_u / den (cosine sum in y),
+    // Y(v) = a_uv w_v / den (sine sum in y -> reversed coefficients)
+    for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
+        const int h = idx >> logM, v = idx & (M - 1);
+        const int u = u0 + h;
+        const T *ac = acol + h * M;
+        const T wu = (T)nd.omega[u], du = (T)nd.den1[u];
+        auto X = [&](int vv) -> T { return (u | vv) ? ac[vv] * wu / (du + s_den[vv]) : T(0); };
+        auto Y = [&](int vv) -> T { return (u | vv) ? ac[vv] * s_om[vv] / (du + s_den[vv]) : T(0); };
+        const T xp = v ? T(0.5) * X(v) : X(0);
+        const T xq = v ? T(0.5) * X(M - v) : T(0);
+        const T yp = v ? T(0.5) * Y(M - v) : T(0);
+        const T yq = v ? T(0.5) * Y(v) : T(0);
+        const vec2<T> VX = idct_pre<T>(xp, xq, s_ph[v]), VY = idct_pre<T>(yp, yq, s_ph[v]);
+        work[h * M + brev(v, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
+    }
+    __syncthreads();
+    fft_lds<T>(work, 2, M, logM, s_tw, true);
     T *bx = reinterpret_cast<T *>(base + L.bx);
     T *by = reinterpret_cast<T *>(base + L.by);
-    T *bp = reinterpret_cast<T *>(base + L.bp);
-    const int hc = C / 2;
-    // (Bx, By) of one column per complex line; two batches of C/2 columns
-    for (int h = 0; h < 2; ++h) {
-        for (int idx = threadIdx.x; idx < hc * M; idx += kBlock) {
-            const int l = idx >> logM, v = idx & (M - 1);
-            const int c = h * hc + l, u = u0 + c;
-            const T *ac = acol + c * M;
-            const T wu = (T)nd.omega[u], du = (T)nd.den1[u];
-            // X(v) = a_uv w_u / den ; cosine sum in y
-            auto X = [&](int vv) -> T {
-                if ((u | vv) == 0) return T(0);
-                return ac[vv] * wu / (du + (T)nd.den1[mx + vv]);
-            };
-            // Y(v) = a_uv w_v / den ; sine sum in y -> reversed coefficients
-            auto Y = [&](int vv) -> T {
-                if ((u | vv) == 0) return T(0);
-                return ac[vv] * (T)nd.omega[mx + vv] / (du + (T)nd.den1[mx + vv]);
-            };
-            const T xp = v ? T(0.5) * X(v) : X(0);
-            const T xq = v ? T(0.5) * X(M - v) : T(0);
-            // reversed: Yt(0) = 0, Yt(w) = Y(M - w)
-            const T yp = v ? T(0.5) * Y(M - v) : T(0);
-            const T yq = v ? T(0.5) * Y(v) : T(0);
-            const vec2<T> VX = idct_pre<T>(xp, xq, ph[v]);
-            const vec2<T> VY = idct_pre<T>(yp, yq, ph[v]);
-            work[l * M + brev(v, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
-        }
-        __syncthreads();
-        fft_lds<T>(work, hc, M, logM, tw, true);
-        for (int idx = threadIdx.x; idx < hc * M; idx += kBlock) {
-            const int k = idx / hc, l = idx - k * hc;
-            const vec2<T> z = work[l * M + mperm(k, M)];
-            const size_t o = (size_t)k * mx + u0 + h * hc + l;
-            bx[o] = z.x;
-            by[o] = (k & 1) ? -z.y : z.y;
-        }
-        __syncthreads();
+    for (int k = threadIdx.x; k < M; k += kBlock) {
+        const int n = mperm(k, M);
+        const vec2<T> z0 = work[n], z1 = work[M + n];
+        const T sg = (k & 1) ? T(-1) : T(1);
+        *reinterpret_cast<vec2<T> *>(bx + (size_t)k * mx + u0) = cmk<T>(z0.x, z1.x);
+        *reinterpret_cast<vec2<T> *>(by + (size_t)k * mx + u0) = cmk<T>(sg * z0.y, sg * z1.y);
     }
     if (want_psi) {
-        for (int idx = threadIdx.x; idx < hc * M; idx += kBlock) {
-            const int l = idx >> logM, v = idx & (M - 1);
+        __syncthreads();
+        for (int v = threadIdx.x; v < M; v += kBlock) {
             vec2<T> V2v[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int c = 2 * l + h, u = u0 + c;
-                const T *ac = acol + c * M;
+                const int u = u0 + h;
+                const T *ac = acol + h * M;
                 const T du = (T)nd.den1[u];
-                auto P = [&](int vv) -> T {
-                    if ((u | vv) == 0) return T(0);
-                    return ac[vv] / (du + (T)nd.den1[mx + vv]);
-                };
+                auto P = [&](int vv) -> T { return (u | vv) ? ac[vv] / (du + s_den[vv]) : T(0); };
                 const T pp = v ? T(0.5) * P(v) : P(0);
                 const T pq = v ? T(0.5) * P(M - v) : T(0);
-                V2v[h] = idct_pre<T>(pp, pq, ph[v]);
+                V2v[h] = idct_pre<T>(pp, pq, s_ph[v]);
             }
-            work[l * M + brev(v, logM)] = cmk<T>(V2v[0].x - V2v[1].y, V2v[0].y + V2v[1].x);
+            work[brev(v, logM)] = cmk<T>(V2v[0].x - V2v[1].y, V2v[0].y + V2v[1].x);
         }
         __syncthreads();
-        fft_lds<T>(work, hc, M, logM, tw, true);
-        for (int idx = threadIdx.x; idx < C * M; idx += kBlock) {
-            const int k = idx >> logC, c = idx & (C - 1);
-            const vec2<T> z = work[(c >> 1) * M + mperm(k, M)];
-            bp[(size_t)k * mx + u0 + c] = (c & 1) ? z.y : z.x;
-        }
+        fft_lds<T>(work, 1, M, logM, s_tw, true);
+        T *bp = reinterpret_cast<T *>(base + L.bp);
+        for (int k = threadIdx.x; k < M; k += kBlock)
+            *reinterpret_cast<vec2<T> *>(bp + (size_t)k * mx + u0) = work[mperm(k, M)];
     }
 }
 
 // ---- R2 ---------------------------------------------------------------------------------
+// lds: tw [M/2] | ph [M] | stage [nst][2][M] | work [nst][M]
 template <typename T>
 __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, SlotLayout L,
                                                         int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.mx, logM = nd.logmx;
     const int nst = want_psi ? 3 : 2;
-    T *stage = reinterpret_cast<T *>(smem);  // [nst][2][M]
-    vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + sizeof(T) * (size_t)nst * 2 * M);
+    size_t o = 0;
+    vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem + o);
+    o += al16(sizeof(vec2<T>) * (M / 2));
+    vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + o);
+    o += al16(sizeof(vec2<T>) * M);
+    T *stage = reinterpret_cast<T *>(smem + o);  // [nst][2][M]
+    o += al16(sizeof(T) * (size_t)nst * 2 * M);
+    vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);
     char *base = sa.base[blockIdx.y];
     const int k0 = blockIdx.x * 2;
+    load_tables<T>(s_tw, s_ph, nd.tw_x, nd.ph_x, M);
     const T *src[3] = {reinterpret_cast<const T *>(base + L.bx), reinterpret_cast<const T *>(base + L.by),
                        reinterpret_cast<const T *>(base + L.bp)};
     for (int idx = threadIdx.x; idx < nst * 2 * M; idx += kBlock) {
@@ -249,7 +310,6 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
         stage[idx] = src[a][(size_t)k0 * M + rem];
     }
     __syncthreads();
-    const vec2<T> *ph = reinterpret_cast<const vec2<T> *>(nd.ph_x);
     const int nlines = want_psi ? 3 : 2;
     for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
         const int r = idx >> logM, u = idx & (M - 1);
@@ -259,42 +319,32 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
         const T xq = u ? T(0.5) * sbx[u] : T(0);
         const T yp = u ? T(0.5) * sby[u] : sby[0];
         const T yq = u ? T(0.5) * sby[M - u] : T(0);
-        const vec2<T> VX = idct_pre<T>(xp, xq, ph[u]), VY = idct_pre<T>(yp, yq, ph[u]);
+        const vec2<T> VX = idct_pre<T>(xp, xq, s_ph[u]), VY = idct_pre<T>(yp, yq, s_ph[u]);
         work[r * M + brev(u, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
     }
     if (want_psi) {
         for (int u = threadIdx.x; u < M; u += kBlock) {
             const T *s0 = stage + 4 * M, *s1 = stage + 5 * M;
-            const vec2<T> A = idct_pre<T>(u ? T(0.5) * s0[u] : s0[0], u ? T(0.5) * s0[M - u] : T(0), ph[u]);
-            const vec2<T> B = idct_pre<T>(u ? T(0.5) * s1[u] : s1[0], u ? T(0.5) * s1[M - u] : T(0), ph[u]);
+            const vec2<T> A = idct_pre<T>(u ? T(0.5) * s0[u] : s0[0], u ? T(0.5) * s0[M - u] : T(0), s_ph[u]);
+            const vec2<T> B = idct_pre<T>(u ? T(0.5) * s1[u] : s1[0], u ? T(0.5) * s1[M - u] : T(0), s_ph[u]);
             work[2 * M + brev(u, logM)] = cmk<T>(A.x - B.y, A.y + B.x);
         }
     }
     __syncthreads();
-    fft_lds<T>(work, nlines, M, logM, reinterpret_cast<const vec2<T> *>(nd.tw_x), true);
+    fft_lds<T>(work, nlines, M, logM, s_tw, true);
     vec2<T> *exy = reinterpret_cast<vec2<T> *>(base + L.exy);
     T *psi = reinterpret_cast<T *>(base + L.psi);
     for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
         const int r = idx >> logM, j = idx & (M - 1);
         const int n = mperm(j, M);
         const vec2<T> z = work[r * M + n];
-        const size_t o = (size_t)(k0 + r) * M + j;
-        exy[o] = cmk<T>((j & 1) ? -z.x : z.x, z.y);
+        const size_t oo = (size_t)(k0 + r) * M + j;
+        exy[oo] = cmk<T>((j & 1) ? -z.x : z.x, z.y);
         if (want_psi) {
             const vec2<T> zp = work[2 * M + n];
-            psi[o] = r ? zp.y : zp.x;
+            psi[oo] = r ? zp.y : zp.x;
         }
     }
-}
-
-// Columns per block of the C pass: one complex line (two real columns) per block gives
-// mx / 2 blocks; the strided 8-byte row segments it reads come from L2/MALL, where the
-// intermediate maps live, so parallelism wins over coalescing here.
-template <typename T>
-static int cols_per_block(const NetDev &nd) {
-    int C = 2;
-    while (C > 2 && 2ull * C * nd.my * sizeof(T) > (unsigned long long)nd.lds_budget) C /= 2;
-    return C < nd.mx ? C : nd.mx;
 }
 
 // R1 takes lpb complex lines (2 rows each) per block
@@ -308,39 +358,40 @@ static int rows_fwd_lines(const NetDev &nd) {
 int spectral_overflow_parts(const NetDev &nd) { return nd.my / 2 / rows_fwd_lines(nd); }
 
 template <typename T>
+static size_t rows_fwd_lds(const NetDev &nd) {
+    return al16(sizeof(vec2<T>) * (nd.mx / 2)) + al16(sizeof(vec2<T>) * nd.mx) +
+           sizeof(vec2<T>) * (size_t)rows_fwd_lines(nd) * nd.mx;
+}
+template <typename T>
+static size_t rows_inv_lds(const NetDev &nd, int nst) {
+    return al16(sizeof(vec2<T>) * (nd.mx / 2)) + al16(sizeof(vec2<T>) * nd.mx) +
+           al16(sizeof(T) * (size_t)nst * 2 * nd.mx) + sizeof(vec2<T>) * (size_t)nst * nd.mx;
+}
+
+template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st) {
     const int lpb = rows_fwd_lines(nd);
-    size_t sh1 = sizeof(vec2<T>) * (size_t)lpb * nd.mx;
-    HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kBlock), sh1, st, nd,
-                       sa, L, lpb, (int)keep_maps);
+    HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kBlock),
+              rows_fwd_lds<T>(nd), st, nd, sa, L, lpb, (int)keep_maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int C = cols_per_block<T>(nd);
-    int logC = 0;
-    while ((1 << logC) < C) ++logC;
-    size_t sh2 = 2 * sizeof(T) * (size_t)C * nd.my;
-    HP_LAUNCH("spec_cols", spec_cols<T>, dim3(nd.mx / C, sa.n), dim3(kBlock), sh2, st, nd, sa, L, C,
-                       logC, (int)want_psi);
+    HP_LAUNCH("spec_cols", spec_cols<T>, dim3(nd.mx / 2, sa.n), dim3(kBlock), cols_lds<T>(nd.my), st,
+              nd, sa, L, (int)want_psi);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nst = want_psi ? 3 : 2;
-    size_t sh3 = sizeof(T) * (size_t)nst * 2 * nd.mx + sizeof(vec2<T>) * (size_t)nst * nd.mx;
-    HP_LAUNCH("spec_rows_inv", spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kBlock), sh3, st, nd, sa, L,
-                       (int)want_psi);
+    HP_LAUNCH("spec_rows_inv", spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kBlock),
+              rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
     return hipGetLastError();
 }
 
 template <typename T>
-int spectral_energy_parts(const NetDev &nd) { return nd.mx / cols_per_block<T>(nd); }
+int spectral_energy_parts(const NetDev &nd) { return nd.mx / 2; }
 
 template <typename T>
 size_t spectral_max_lds(const NetDev &nd) {
-    const int C = cols_per_block<T>(nd);
-    size_t a = sizeof(vec2<T>) * (size_t)std::max(1, std::min(512 / nd.mx, nd.my / 2)) * nd.mx;
-    size_t b = 2 * sizeof(T) * (size_t)C * nd.my;
-    size_t c = sizeof(T) * 6 * (size_t)nd.mx + sizeof(vec2<T>) * 3 * (size_t)nd.mx;
-    return std::max(a, std::max(b, c));
+    return std::max(rows_fwd_lds<T>(nd), std::max(cols_lds<T>(nd.my), rows_inv_lds<T>(nd, 3)));
 }
 
 // Ask for `bytes` of dynamic LDS per block on the three passes (above the 64 KB default).
