@@ -133,27 +133,35 @@ class Oracle:
 
     # -- Eq. 1 --------------------------------------------------------------------------
     def hpwl(self, x, y) -> float:
-        return self.L.orc_hpwl(self.ref, _p(_f64(x)), _p(_f64(y)))
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
+        return self.L.orc_hpwl(self.ref, _p(x), _p(y))
 
     def hpwl_q(self, x, y, per_net=False):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
         pn = np.zeros(self.net.n_nets, dtype=np.int64) if per_net else None
-        t = self.L.orc_hpwl_q(self.ref, _p(_f64(x)), _p(_f64(y)), _p(pn))
+        t = self.L.orc_hpwl_q(self.ref, _p(x), _p(y), _p(pn))
         return (t, pn) if per_net else t
 
     # -- Eq. 3 --------------------------------------------------------------------------
     def wa(self, x, y, gamma, per_net=False):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
         N = self.nl.n_movable
         gx, gy = np.zeros(N), np.zeros(N)
         pn = np.zeros(self.net.n_nets) if per_net else None
-        wl = self.L.orc_wa(self.ref, _p(_f64(x)), _p(_f64(y)), float(gamma), _p(gx), _p(gy),
+        wl = self.L.orc_wa(self.ref, _p(x), _p(y), float(gamma), _p(gx), _p(gy),
                            _p(pn))
         return (wl, gx, gy, pn) if per_net else (wl, gx, gy)
 
     # -- density ------------------------------------------------------------------------
     def density_q(self, x, y):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
         rm = np.zeros(self.nb, dtype=np.int64)
         rf = np.zeros(self.nb, dtype=np.int64)
-        self.L.orc_density_q(self.ref, _p(_f64(x)), _p(_f64(y)), _p(rm), _p(rf))
+        self.L.orc_density_q(self.ref, _p(x), _p(y), _p(rm), _p(rf))
         return rm.reshape(self.nl.my, self.nl.mx), rf.reshape(self.nl.my, self.nl.mx)
 
     def total_charge_q(self) -> int:
@@ -167,29 +175,39 @@ class Oracle:
         return v, num.value
 
     def density_float(self, x, y):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
         rho = np.zeros(self.nb)
-        self.L.orc_density_float(self.ref, _p(_f64(x)), _p(_f64(y)), _p(rho))
+        self.L.orc_density_float(self.ref, _p(x), _p(y), _p(rho))
         return rho.reshape(self.nl.my, self.nl.mx)
 
     def grad_field(self, x, y, ex, ey):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y, ex, ey = _f64(x), _f64(y), _f64(ex), _f64(ey)
         N = self.nl.n_movable
         gx, gy = np.zeros(N), np.zeros(N)
-        self.L.orc_density_grad_field(self.ref, _p(_f64(x)), _p(_f64(y)), _p(_f64(ex)),
-                                      _p(_f64(ey)), _p(gx), _p(gy))
+        self.L.orc_density_grad_field(self.ref, _p(x), _p(y), _p(ex),
+                                      _p(ey), _p(gx), _p(gy))
         return gx, gy
 
     def grad_exact(self, x, y, psi):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y, psi = _f64(x), _f64(y), _f64(psi)
         N = self.nl.n_movable
         gx, gy = np.zeros(N), np.zeros(N)
-        self.L.orc_density_grad_exact(self.ref, _p(_f64(x)), _p(_f64(y)), _p(_f64(psi)),
+        self.L.orc_density_grad_exact(self.ref, _p(x), _p(y), _p(psi),
                                       _p(gx), _p(gy))
         return gx, gy
 
     def energy_float(self, x, y, fd5=False):
-        return self.L.orc_density_energy_float(self.ref, _p(_f64(x)), _p(_f64(y)), int(fd5))
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
+        return self.L.orc_density_energy_float(self.ref, _p(x), _p(y), int(fd5))
 
     # -- objective ----------------------------------------------------------------------
     def eval(self, x, y, gamma, target_density=1.0, grad_mode=0, fd5=False, maps=False):
+        # float64 copies held for the duration of the call (ctypes keeps only addresses)
+        x, y = _f64(x), _f64(y)
         N = self.nl.n_movable
         nb = self.nb
         pr = _EvalParams(float(gamma), float(target_density), int(grad_mode), int(fd5))
@@ -198,7 +216,7 @@ class Oracle:
         rm = np.zeros(nb, dtype=np.int64) if maps else None
         rf = np.zeros(nb, dtype=np.int64) if maps else None
         psi, ex, ey = ((np.zeros(nb) for _ in range(3)) if maps else (None, None, None))
-        self.L.orc_eval(self.ref, _p(_f64(x)), _p(_f64(y)), C.byref(pr), C.byref(wl),
+        self.L.orc_eval(self.ref, _p(x), _p(y), C.byref(pr), C.byref(wl),
                         C.byref(en), C.byref(ov), C.byref(on), _p(gwx), _p(gwy), _p(gdx),
                         _p(gdy), _p(rm), _p(rf), _p(psi), _p(ex), _p(ey))
         out = dict(wl=wl.value, energy=en.value, overflow=ov.value, overflow_num=on.value,

@@ -234,3 +234,22 @@ def test_field_gradient_descends_energy(orc):
     step = 0.2 * nl.bin_w / np.abs(np.concatenate([out["gdx"], out["gdy"]])).max()
     out2 = o.eval(nl.x0 - step * out["gdx"], nl.y0 - step * out["gdy"], 4 * nl.bin_w)
     assert out2["energy"] < out["energy"]
+
+
+def test_oracle_inputs_of_any_float_dtype(orc):
+    """Marshalling: positions given as float32 (values exact in both types) produce the same
+    results as float64 ones, i.e. the converted copies outlive the C call."""
+    from paper_2402_18311_amd import netgen
+    nl = netgen.make_small(3_001, 3_100, 32, seed=5, n_fixed=8)
+    o = orc.Oracle(nl)
+    x64, y64 = nl.random_positions(2)
+    x32, y32 = x64.astype(np.float32), y64.astype(np.float32)
+    assert np.array_equal(x32.astype(np.float64), x64)  # generator values are multiples of 2^-8
+    for _ in range(3):  # fresh temporaries each time, so freed memory would be reused
+        assert o.hpwl_q(x32, y32) == o.hpwl_q(x64, y64)
+        r32, f32 = o.density_q(x32, y32)
+        r64, f64 = o.density_q(x64, y64)
+        assert np.array_equal(r32, r64) and np.array_equal(f32, f64)
+        e32 = o.eval(x32, y32, 4 * nl.bin_w)
+        e64 = o.eval(x64, y64, 4 * nl.bin_w)
+        assert e32["overflow_num"] == e64["overflow_num"] and e32["wl"] == e64["wl"]
