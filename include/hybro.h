@@ -99,9 +99,12 @@ int hp_slot_free(hp_ctx *ctx, int32_t slot);
 
 /* Set the movable cells' positions (real [n_movable] each; host or device memory) and
  * restart the optimiser there: u = v = v_prev = (x, y), k = 0, a = 1, lambda re-derived at
- * the next evaluation.  hp_get_positions copies out the major solution u. */
+ * the next evaluation.  hp_get_positions copies out the major solution u;
+ * hp_get_eval_positions copies out the look-ahead point v of the Nesterov method, where the
+ * next hp_eval_objective_grad is taken.  x or y may be NULL to skip that axis. */
 int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, int on_device);
 int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device);
+int hp_get_eval_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device);
 
 /* lambda schedule of Eq. 2 ("small at the beginning", Sec. 3): at the first evaluation after
  * hp_set_positions / hp_perturb, lambda_0 = lambda0_scale * |grad WL|_1 / |grad N|_1; every

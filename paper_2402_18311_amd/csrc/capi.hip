@@ -30,6 +30,13 @@ int fail(int code, const std::string &msg) {
             return fail(HP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Propagate a failed HP_* return code of a helper.
+#define HP_TRY(call)                 \
+    do {                             \
+        const int r_ = (call);       \
+        if (r_ != HP_OK) return r_;  \
+    } while (0)
+
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct NetBuf {
@@ -162,6 +169,9 @@ struct Slot {
     bool lambda_valid = false;  // host mirror of the device flag
     bool maps_valid = false;
     bool hpwl_pending = false;  // an HPWL sweep ran; its partials are not yet reduced
+    bool step_proposed = false; // the last evaluation formed the next step's proposal
+    int since_group = -1;       // evaluations since the scatter's tile order was built (-1: none)
+    bool rho_dirty = false;     // rho holds a kept map, not zeros
 };
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -180,9 +190,32 @@ struct hp_ctx {
     int lds_budget = 65536;
     std::vector<Netlist> nets;
     std::vector<Slot> slots;
+    // The net sweeps (WA and HPWL) run on a second stream of the context, so that they overlap
+    // the charge scatter and the Poisson solve, which do not depend on them.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_side = nullptr;
+    bool side_pending = false;  // the side stream holds work the context stream has not joined
 };
 
 namespace {
+
+// Order the side stream after all work enqueued on the context stream so far.
+int fork_side(hp_ctx *c) {
+    HP_CHECK(hipEventRecord(c->ev_fork, c->stream));
+    HP_CHECK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    c->side_pending = true;
+    return HP_OK;
+}
+
+// Order the context stream after all work enqueued on the side stream so far.  Every entry
+// point that reads or writes slot state joins first, so results never depend on the overlap.
+int join_side(hp_ctx *c) {
+    if (!c || !c->side_pending) return HP_OK;
+    HP_CHECK(hipEventRecord(c->ev_side, c->side));
+    HP_CHECK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
+    c->side_pending = false;
+    return HP_OK;
+}
 
 size_t rsize(const hp_ctx *c) { return c->precision == 64 ? 8 : 4; }
 
@@ -597,10 +630,20 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
     for (size_t c = 0; c < chunks.size(); ++c) {
         const SlotArgs &sa = chunks[c];
         bool any_init = false;
-        for (int i = 0; i < sa.n; ++i) any_init |= !use_fixed && !ss[c * kMaxSlots + i]->lambda_valid;
-        HP_CHECK(launch_sweep_wa<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, st));
-        HP_CHECK(launch_scatter<T>(nd, sa, L, st));
+        bool regroup = false, dirty = false;
+        for (int i = 0; i < sa.n; ++i) {
+            const Slot *s = ss[c * kMaxSlots + i];
+            any_init |= !use_fixed && !s->lambda_valid;
+            regroup |= s->since_group < 0 || s->since_group >= kRegroupEvery;
+            dirty |= s->rho_dirty;
+        }
+        // the WA sweep on the side stream, beside the scatter and the Poisson solve
+        HP_TRY(fork_side(ctx));
+        HP_CHECK(launch_sweep_wa<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, ctx->side));
+        if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
+        HP_CHECK(launch_scatter<T>(nd, sa, L, regroup, st));
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0, p->keep_maps != 0, st));
+        HP_TRY(join_side(ctx));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
                                      st));
@@ -608,7 +651,11 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];
             s->maps_valid = p->keep_maps != 0;
+            // a steady-state evaluation (lambda known) also proposed the next step
+            s->step_proposed = use_fixed || s->lambda_valid;
             if (!use_fixed) s->lambda_valid = true;
+            s->since_group = regroup ? 1 : s->since_group + 1;
+            s->rho_dirty = p->keep_maps != 0;
         }
     }
     const size_t rs = sizeof(T), Nm = nd.n_mov;
@@ -737,18 +784,36 @@ int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
             lds = 65536;
         }
     }
+    hipStream_t side = nullptr;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    HP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+    if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(side);
+        return fail(HP_EDEVICE, "hipEventCreateWithFlags failed");
+    }
     hp_ctx *c = new hp_ctx;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->precision = precision;
     c->lds_budget = lds;
+    c->side = side;
+    c->ev_fork = e1;
+    c->ev_side = e2;
     *out = c;
     return HP_OK;
 }
 
 int hp_destroy(hp_ctx *ctx) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
-    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    (void)join_side(ctx);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    const hipError_t e2 = hipStreamSynchronize(ctx->side);
+    if (e == hipSuccess) e = e2;
+    (void)hipEventDestroy(ctx->ev_fork);
+    (void)hipEventDestroy(ctx->ev_side);
+    (void)hipStreamDestroy(ctx->side);
     delete ctx;
     if (e != hipSuccess) return fail(HP_EDEVICE, hipGetErrorString(e));
     return HP_OK;
@@ -801,6 +866,7 @@ int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
         return fail(HP_ENOMEM, "slot buffer needs " + std::to_string(NL.L.total) + " bytes");
     char *base = (char *)dev_buf;
     hipStream_t st = ctx->stream;
+    HP_TRY(join_side(ctx));
     const size_t rs = rsize(ctx);
     const size_t Nm = NL.nd.n_mov, Nf = NL.nd.n_fixed;
     HP_CHECK(hipMemsetAsync(base, 0, NL.L.total, st));
@@ -826,6 +892,7 @@ int hp_slot_free(hp_ctx *ctx, int32_t slot) {
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
+    HP_TRY(join_side(ctx));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
     s->alive = false;
     s->base = nullptr;
@@ -838,6 +905,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!x || !y) return fail(HP_EINVAL, "x/y is NULL");
+    HP_TRY(join_side(ctx));
     const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     hipStream_t st = ctx->stream;
     const SlotLayout &L = n->L;
@@ -862,21 +930,40 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     HP_CHECK(hipStreamSynchronize(st));
     s->lambda_valid = false;
     s->hpwl_pending = false;
+    s->step_proposed = false;
+    s->since_group = -1;
     return HP_OK;
 }
 
-int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device) {
+namespace {
+int get_pos(hp_ctx *ctx, int32_t slot, size_t which, void *x, void *y, int on_device) {
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (Nm && x) HP_CHECK(hipMemcpy2DAsync(x, rs, s->base + n->L.u, 2 * rs, rs, Nm, k, ctx->stream));
-    if (Nm && y)
-        HP_CHECK(hipMemcpy2DAsync(y, rs, s->base + n->L.u + rs, 2 * rs, rs, Nm, k, ctx->stream));
+    const char *src = s->base + which;  // (x, y) pairs
+    HP_TRY(join_side(ctx));
+    if (Nm && x) HP_CHECK(hipMemcpy2DAsync(x, rs, src, 2 * rs, rs, Nm, k, ctx->stream));
+    if (Nm && y) HP_CHECK(hipMemcpy2DAsync(y, rs, src + rs, 2 * rs, rs, Nm, k, ctx->stream));
     if (!on_device) HP_CHECK(hipStreamSynchronize(ctx->stream));
     return HP_OK;
+}
+}  // namespace
+
+int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (slot < 0 || slot >= (int)ctx->slots.size() || !ctx->slots[slot].alive)
+        return fail(HP_ESTATE, "unknown slot " + std::to_string(slot));
+    return get_pos(ctx, slot, ctx->nets[ctx->slots[slot].netlist].L.u, x, y, on_device);
+}
+
+int hp_get_eval_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (slot < 0 || slot >= (int)ctx->slots.size() || !ctx->slots[slot].alive)
+        return fail(HP_ESTATE, "unknown slot " + std::to_string(slot));
+    return get_pos(ctx, slot, ctx->nets[ctx->slots[slot].netlist].L.v, x, y, on_device);
 }
 
 int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double decades, int32_t total_iters) {
@@ -886,6 +973,7 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
     if (rc) return rc;
     if (!(lambda0_scale > 0) || !std::isfinite(decades) || total_iters <= 0)
         return fail(HP_EINVAL, "bad schedule");
+    HP_TRY(join_side(ctx));
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
@@ -909,12 +997,17 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n) {
     std::vector<Slot *> ss;
     int rc = resolve(ctx, slots, n, &NL, chunks, ss);
     if (rc) return rc;
-    for (const SlotArgs &sa : chunks) {
+    HP_TRY(join_side(ctx));
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        const SlotArgs &sa = chunks[c];
+        bool proposed = true;
+        for (int i = 0; i < sa.n; ++i) proposed &= ss[c * kMaxSlots + i]->step_proposed;
         if (ctx->precision == 32)
-            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, ctx->stream));
+            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, proposed, ctx->stream));
         else
-            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, ctx->stream));
+            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, proposed, ctx->stream));
     }
+    for (Slot *s : ss) s->step_proposed = false;
     return HP_OK;
 }
 
@@ -931,6 +1024,7 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
     const int Nm = n->nd.n_mov;
     int64_t m = mode == 2 ? Nm : (int64_t)std::floor(fraction * Nm + 0.5);
     if (m > Nm) m = Nm;
+    HP_TRY(join_side(ctx));
     if (ctx->precision == 32)
         HP_CHECK(launch_perturb<float>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
                                        sigma_bins * n->nd.hb, seed, ctx->stream));
@@ -938,6 +1032,8 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
         HP_CHECK(launch_perturb<double>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
                                         sigma_bins * n->nd.hb, seed, ctx->stream));
     s->lambda_valid = false;
+    s->step_proposed = false;
+    s->since_group = -1;
     s->hpwl_pending = false;  // the device cleared hpwl_valid
     if (out_idx && m)
         HP_CHECK(hipMemcpyAsync(out_idx, s->base + n->L.sel, 4 * (size_t)m, hipMemcpyDeviceToHost,
@@ -953,15 +1049,22 @@ int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double
     std::vector<Slot *> ss;
     int rc = resolve(ctx, slots, n, &NL, chunks, ss);
     if (rc) return rc;
+    // the sweep runs on the side stream: it reads only u and writes only its own partials, so
+    // it overlaps whatever is enqueued next until an entry point joins
+    HP_TRY(fork_side(ctx));
     for (const SlotArgs &sa : chunks) {
         if (ctx->precision == 32)
-            HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
+            HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->side));
         else
-            HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
+            HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->side));
     }
     // the total is reduced from the sweep's per-block partials when first needed
     for (Slot *s : ss) s->hpwl_pending = true;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (ctx->stream) HP_CHECK(hipStreamIsCapturing(ctx->stream, &cap));  // never on the null stream
+    if (cap != hipStreamCaptureStatusNone) HP_TRY(join_side(ctx));  // a capture must end joined
     if (out_q || out) {
+        HP_TRY(join_side(ctx));
         rc = finish_hpwl(ctx, NL, ss);
         if (rc) return rc;
         std::vector<int64_t> h(n);
@@ -993,6 +1096,7 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbe
         if (s == inc) return fail(HP_EINVAL, "the incumbent cannot be a candidate");
     std::vector<Slot *> all(ss);
     all.push_back(inc);
+    HP_TRY(join_side(ctx));
     rc = finish_hpwl(ctx, NL, all);
     if (rc) return rc;
     if (ctx->precision == 32)
@@ -1000,6 +1104,8 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbe
     else
         HP_CHECK(launch_select_best<double>(NL->nd, chunks[0], inc->base, NL->L, ctx->stream));
     inc->lambda_valid = false;  // conservatively: the device resets it when a candidate wins
+    inc->step_proposed = false;
+    inc->since_group = -1;
     if (out_best) {
         int64_t b = -1;
         HP_CHECK(hipMemcpyAsync(&b, inc->base + NL->L.scal + offsetof(Scalars, best), 8,
@@ -1016,6 +1122,7 @@ int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!dst) return fail(HP_EINVAL, "dst is NULL");
+    HP_TRY(join_side(ctx));
     const size_t nb = (size_t)n->nd.mx * n->nd.my, rs = rsize(ctx);
     const char *src = nullptr;
     size_t bytes = 0;
@@ -1047,6 +1154,7 @@ int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!out) return fail(HP_EINVAL, "out is NULL");
+    HP_TRY(join_side(ctx));
     rc = finish_hpwl(ctx, n, std::vector<Slot *>{s});
     if (rc) return rc;
     Scalars h;

@@ -66,8 +66,9 @@ template <typename T> __device__ __forceinline__ T block_min(T v, T *red) {
     return min(min(red[0], red[1]), min(red[2], red[3]));
 }
 
-// Fixed-order sums of n per-block partials by one block (thread t takes t, t+256, ...).
-template <typename T> __device__ T sum_parts(const T *p, int n, T *red) {
+// Fixed-order sums of n per-block partials by one block: thread t sums t, t+256, ... (the
+// thread_* part), then the block tree.
+template <typename T> __device__ __forceinline__ T thread_sum(const T *p, int n) {
     T s = 0;
     int i = threadIdx.x;
     for (; i + 3 * kBlock < n; i += 4 * kBlock) {  // four independent loads in flight
@@ -75,15 +76,82 @@ template <typename T> __device__ T sum_parts(const T *p, int n, T *red) {
         s += (a + b) + (c + d);
     }
     for (; i < n; i += kBlock) s += p[i];
-    return block_sum(s, red);
+    return s;
 }
-__device__ inline double max_parts(const double *p, int n, double *red) {
+__device__ __forceinline__ double thread_max(const double *p, int n) {
     double s = 0.0;
     int i = threadIdx.x;
     for (; i + 3 * kBlock < n; i += 4 * kBlock)
         s = fmax(fmax(s, fmax(p[i], p[i + kBlock])), fmax(p[i + 2 * kBlock], p[i + 3 * kBlock]));
     for (; i < n; i += kBlock) s = fmax(s, p[i]);
-    return block_max(s, red);
+    return s;
+}
+template <typename T> __device__ T sum_parts(const T *p, int n, T *red) {
+    return block_sum(thread_sum(p, n), red);
+}
+__device__ inline double max_parts(const double *p, int n, double *red) {
+    return block_max(thread_max(p, n), red);
+}
+
+// Preconditioner of the Nesterov step (ePlace reading): P_i = max(1, pins_i + lambda area_i),
+// with the lambda of the evaluation that produced the gradient.
+template <typename T>
+__device__ __forceinline__ double precond(const T *cs, int n, int i, double lam) {
+    const double P = (double)cs[i] + lam * (double)cs[n + i];
+    return P < 1.0 ? 1.0 : P;
+}
+
+// The step's three reductions for the block's cells (cell i = blockIdx.x * 256 + threadIdx.x,
+// gradient (g0, g1) of cell i, valid when `live`): |v - v_prev|^2, |g~ - g~_prev|^2 and
+// max|g~| with g~ = g / P, stored as the block's partials.  Both the step kernels and the
+// fused cell-gradient pass call this, so their partials are identical.
+template <typename T>
+__device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, const SlotLayout &L,
+                                                 int i, bool live, T g0, T g1, double lam,
+                                                 double *red) {
+    double dv = 0.0, dg = 0.0, gm = 0.0;
+    if (live) {
+        const int n = nd.n_mov;
+        const T *cs = reinterpret_cast<const T *>(nd.cstep);
+        const double P = precond(cs, n, i, lam);
+        const vec2<T> v = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+        const vec2<T> vp = reinterpret_cast<const vec2<T> *>(base + L.vprev)[i];
+        const T *gp = reinterpret_cast<const T *>(base + L.gprev);
+        const double gx = (double)g0 / P, gy = (double)g1 / P;
+        const double ax = (double)v.x - (double)vp.x;
+        const double ay = (double)v.y - (double)vp.y;
+        const double bx = gx - (double)gp[i], by = gy - (double)gp[n + i];
+        dv = ax * ax + ay * ay;
+        dg = bx * bx + by * by;
+        gm = fmax(fabs(gx), fabs(gy));
+    }
+    dv = block_sum(dv, red);
+    dg = block_sum(dg, red);
+    gm = block_max(gm, red);
+    if (threadIdx.x == 0) {
+        double *part = reinterpret_cast<double *>(base + L.part);
+        part[PART_DV * L.pstride + blockIdx.x] = dv;
+        part[PART_DG * L.pstride + blockIdx.x] = dg;
+        part[PART_GMAX * L.pstride + blockIdx.x] = gm;
+    }
+}
+
+// Step proposal from the totals of the three reductions: alpha_0 = 0.1 bin / max|g~| on the
+// first step, else alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein, the previous
+// alpha when the gradient did not change); a' = (1 + sqrt(4 a^2 + 1)) / 2 and momentum
+// (a - 1) / a'.  The step kernel commits it (a = a', k + 1, lambda times the ratio).
+__device__ __forceinline__ void step_propose(Scalars *sc, double DV, double DG, double GM,
+                                             double wb) {
+    double alpha;
+    if (sc->k == 0)
+        alpha = 0.1 * wb / (GM > 1e-30 ? GM : 1e-30);
+    else
+        alpha = DG > 0.0 ? sqrt(DV) / sqrt(DG) : sc->alpha;
+    const double a = sc->a;
+    const double an = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
+    sc->step_alpha = alpha;
+    sc->step_coef = (a - 1.0) / an;
+    sc->step_a = an;
 }
 
 // Movable charge of bin (k, j) assembled from the binned scatter's chunk windows: the chunks

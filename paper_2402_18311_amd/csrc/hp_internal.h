@@ -11,6 +11,7 @@ constexpr int kMaxSlots = 32;    // slots per launch (longer lists are chunked)
 constexpr int kMaxBuckets = 8;
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
 constexpr int kChunk = 2048;     // cells per accumulation block of the binned scatter
+constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
 
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };
@@ -94,7 +95,7 @@ enum { PART_WL = 0, PART_E = 1, PART_N1 = 2, PART_N2 = 3, PART_DV = 4, PART_DG =
 struct Scalars {
     double a, alpha, lambda, lambda_step, lambda0_scale, lambda_ratio;
     double wl, energy, overflow;
-    double step_alpha, step_coef;
+    double step_alpha, step_coef, step_a;  // proposal of the next step (see step_propose)
     int64_t k;
     int64_t lambda_valid;   // 0 until lambda_0 is derived at the first evaluation
     int64_t init_this_eval; // the last evaluation derived lambda_0
@@ -147,9 +148,14 @@ hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st);
+// The binned charge scatter; `regroup` rebuilds the cells' tile order from the current
+// positions first (otherwise the last order is reused: exact, cells that left their window
+// take the atomic path).
 template <typename T>
-hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool regroup,
                           hipStream_t st);
+hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                            hipStream_t st);
 template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st);
@@ -170,8 +176,10 @@ template <typename T> int spectral_energy_parts(const NetDev &nd);
 int spectral_overflow_parts(const NetDev &nd);
 template <typename T> size_t spectral_max_lds(const NetDev &nd);
 template <typename T> hipError_t spectral_prepare(int bytes);
+// One Nesterov step; `proposed`: every slot's evaluation already formed the step's
+// reductions and proposal (steady state), so only the update runs.
 template <typename T>
-hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool proposed,
                        hipStream_t st);
 template <typename T>
 hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,

@@ -1,7 +1,7 @@
-// Integer charge scatter (the density D of Eqs. 1-2, ePlace reading) without global atomics.
+// Integer charge scatter (the density D of Eqs. 1-2, ePlace reading), built in LDS.
 //
-// Device-scope int64 atomics run at ~22 G/s on this part whatever their scope, and serialise
-// when cells clump, so the map is built from LDS instead:
+// Device-scope int64 atomics run at ~22 G/s on this part and serialise when cells clump, so
+// the bulk of the map is built from LDS windows:
 //   1. count: each block takes a contiguous run of cells, finds each cell's tile (the
 //      ts x ts bin tile holding the lower-left bin of its charge rectangle), and writes its
 //      per-tile histogram (LDS atomics only);
@@ -11,8 +11,14 @@
 //   4. accumulate: one block per chunk sums its cells' integer charges into an LDS window of
 //      (ts + halo)^2 bins (halo = widest footprint - 1) and stores the window;
 // and the row pass of the Poisson solve assembles each bin from the windows of its own tile
-// and of the tiles left of / below it.  Integer sums do not depend on order, so the map is
-// bit-identical however cells land in the sorted order, and no step contends globally.
+// and of the tiles left of / below it.
+//
+// Steps 1-3 are only a grouping: every cell is in the order exactly once, and a cell whose
+// charge rectangle no longer fits its chunk's window (it moved since the order was built)
+// adds its charge to the slot's movable map directly with global atomics; the row pass adds
+// that map and clears it.  Integer sums do not depend on order, so the map is bit-identical
+// however stale the order is, and the order is rebuilt only every few evaluations, when cells
+// have drifted little.
 #include "hp_device.h"
 
 namespace hp {
@@ -36,13 +42,14 @@ __device__ __forceinline__ int overlap_b(int lo, int hi, int idx, int w) {
     return b > a ? b - a : 0;
 }
 
-// tile of cell i, or -1 if its charge rectangle is empty (fully clipped)
+// tile of cell i: the tile of its charge rectangle's lower-left bin (clamped into the die, so
+// that a cell whose rectangle is clipped away still has a place in the order)
 template <typename T>
 __device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i) {
     const vec2<T> p = pos[i];
     const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
-    if (q.r <= q.l || q.t <= q.b) return -1;
-    return ((q.b / nd.hq) >> nd.log_ts) * nd.ntx + ((q.l / nd.bq) >> nd.log_ts);
+    const int j = min(q.l / nd.bq, nd.mx - 1), k = min(q.b / nd.hq, nd.my - 1);
+    return (k >> nd.log_ts) * nd.ntx + (j >> nd.log_ts);
 }
 
 template <typename T>
@@ -57,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void bin_count_kernel(NetDev nd, SlotArgs s
     for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const int t = cell_tile<T>(nd, pos, i);
         tile[i] = t;
-        if (t >= 0) atomicAdd(&hist[t], 1);
+        atomicAdd(&hist[t], 1);
     }
     __syncthreads();
     int *cnt = reinterpret_cast<int *>(base + L.scnt) + (size_t)blockIdx.x * nd.ntiles;
@@ -146,7 +153,6 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nd, SlotArgs s
     const int i0 = blockIdx.x * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
     for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const int t = tile[i];
-        if (t < 0) continue;
         const int r = atomicAdd(&rank[t], 1);
         sorted[tstart[t] + cnt[t] + r] = i;
     }
@@ -176,18 +182,25 @@ __global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nd, SlotArgs s
     const int j00 = (t % nd.ntx) << nd.log_ts, k00 = (t / nd.ntx) << nd.log_ts;
     const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
     const int *sorted = reinterpret_cast<const int *>(base + L.sorted);
+    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
     for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
         const int i = sorted[s];
         const vec2<T> p = pos[i];
         const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
+        if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
         const long long rq = nd.rq[i];
         const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
         const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
+        const bool inside = j0 >= j00 && j1 < j00 + ws && k0 >= k00 && k1 < k00 + ws;
         for (int k = k0; k <= k1; ++k) {
             const long long oy = overlap_b(q.b, q.t, k, nd.hq);
             for (int j = j0; j <= j1; ++j) {
                 const long long ox = overlap_b(q.l, q.r, j, nd.bq);
-                atomicAdd(&win[(k - k00) * ws + (j - j00)], (unsigned long long)(rq * ox * oy));
+                const unsigned long long c = (unsigned long long)(rq * ox * oy);
+                if (inside)
+                    atomicAdd(&win[(k - k00) * ws + (j - j00)], c);
+                else  // moved out of the window since the order was built
+                    atomicAdd(&rho[(size_t)k * nd.mx + j], c);
             }
         }
     }
@@ -197,12 +210,14 @@ __global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nd, SlotArgs s
 }
 
 template <typename T>
-hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool regroup,
                           hipStream_t st) {
     const size_t hsh = sizeof(int) * (size_t)nd.ntiles;
+    hipError_t e;
+    if (!regroup) goto accumulate;
     HP_LAUNCH("bin_count_kernel", bin_count_kernel<T>, dim3(nd.sort_blocks, sa.n), dim3(kBlock), hsh,
               st, nd, sa, L);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     HP_LAUNCH("bin_scan_kernel", bin_scan_kernel, dim3(1, sa.n), dim3(kScanThreads), 0, st, nd, sa, L);
     e = hipGetLastError();
@@ -211,6 +226,7 @@ hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout
               nd, sa, L);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+accumulate:
     const size_t wsh = sizeof(unsigned long long) * (size_t)nd.win_side * nd.win_side;
     HP_LAUNCH("bin_accum_kernel", bin_accum_kernel<T>, dim3(nd.max_chunks, sa.n), dim3(kBlock), wsh,
               st, nd, sa, L);
@@ -218,8 +234,8 @@ hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout
 }
 
 template hipError_t launch_scatter<float>(const NetDev &, const SlotArgs &, const SlotLayout &,
-                                          hipStream_t);
+                                          bool, hipStream_t);
 template hipError_t launch_scatter<double>(const NetDev &, const SlotArgs &, const SlotLayout &,
-                                           hipStream_t);
+                                           bool, hipStream_t);
 
 }  // namespace hp

@@ -59,7 +59,8 @@ __global__ __launch_bounds__(kBlock) void fixed_map_kernel(NetDev nd, const doub
 // order -> deterministic).  Density part: the field force, dN/dx_i = -sum_b q_ib xi_x(b),
 // with q_ib the cell's integer charge in bin b.  Steady state writes g = gWL + lambda gD;
 // on a slot's first evaluation (lambda not yet derived) it writes gWL to g and gD to gd and
-// the per-block L1 norms of both, from which lambda_0 is derived.
+// the per-block L1 norms of both, from which lambda_0 is derived.  In steady state the block
+// also forms its partials of the following Nesterov step's reductions.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                            double lam_fixed, int use_fixed) {
@@ -97,11 +98,16 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
     }
     T *g = reinterpret_cast<T *>(base + L.g);
     if (!init) {
-        const T lam = (T)(use_fixed ? lam_fixed : sc->lambda);
+        const double lam_step = use_fixed ? lam_fixed : sc->lambda;
+        const T lam = (T)lam_step;
+        const T g0 = gwx + lam * gdx, g1 = gwy + lam * gdy;
         if (i < nd.n_mov) {
-            g[i] = gwx + lam * gdx;
-            g[nd.n_mov + i] = gwy + lam * gdy;
+            g[i] = g0;
+            g[nd.n_mov + i] = g1;
         }
+        // the following step's reductions, from the gradient just formed
+        __shared__ double red[4];
+        step_block_norms<T>(nd, base, L, i, i < nd.n_mov, g0, g1, lam_step, red);
     } else {
         T *gd = reinterpret_cast<T *>(base + L.gd);
         if (i < nd.n_mov) {
@@ -122,6 +128,20 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
 }
 
 int cell_parts(const NetDev &nd) { return (nd.n_mov + kBlock - 1) / kBlock; }
+
+// Zero the slots' movable charge maps (after an evaluation that kept them for inspection).
+__global__ __launch_bounds__(kBlock) void clear_rho_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    long long *rho = reinterpret_cast<long long *>(sa.base[blockIdx.y] + L.rho);
+    const size_t n = (size_t)nd.mx * nd.my;
+    for (size_t b = (size_t)blockIdx.x * kBlock + threadIdx.x; b < n; b += (size_t)gridDim.x * kBlock)
+        rho[b] = 0;
+}
+
+hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                            hipStream_t st) {
+    HP_LAUNCH("clear_rho_kernel", clear_rho_kernel, dim3(256, sa.n), dim3(kBlock), 0, st, nd, sa, L);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,

@@ -146,15 +146,21 @@ __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, 
         const int l = idx >> logM, j = idx & (M - 1);
         const int ra = (blockIdx.x * lpb + l) * 2;
         const size_t ia = (size_t)ra * M + j, ib = ia + M;
-        const int64_t ma = binned_charge(nd, base, L, ra, j), mb = binned_charge(nd, base, L, ra + 1, j);
+        // windows of the binned scatter, plus the charge its out-of-window cells added to rho
+        const int64_t oa = rho[ia], ob = rho[ib];
+        const int64_t ma = binned_charge(nd, base, L, ra, j) + oa;
+        const int64_t mb = binned_charge(nd, base, L, ra + 1, j) + ob;
         const int64_t fa = nd.rho_fixed[ia], fb = nd.rho_fixed[ib];
         const int64_t ca = __double2ll_rn(nd.target_density * (double)(nd.area_q - fa));
         const int64_t cb = __double2ll_rn(nd.target_density * (double)(nd.area_q - fb));
         if (ma > ca) over += ma - ca;
         if (mb > cb) over += mb - cb;
-        if (keep) {  // the movable map itself is only materialised for inspection
+        if (keep) {  // the whole movable map, for inspection (cleared before the next scatter)
             rho[ia] = ma;
             rho[ib] = mb;
+        } else {  // leave rho zero for the next scatter
+            if (oa) rho[ia] = 0;
+            if (ob) rho[ib] = 0;
         }
         buf[l * M + brev(mperm(j, M), logM)] =
             cmk<T>((T)((double)(ma + fa) * nd.density_unit), (T)((double)(mb + fb) * nd.density_unit));

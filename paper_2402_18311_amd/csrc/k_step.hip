@@ -8,37 +8,58 @@ namespace hp {
 
 // Totals of one evaluation: WL (Eq. 3), energy N, overflow; lambda_0 on a slot's first
 // evaluation with the scheduled lambda (scale * |grad WL|_1 / |grad N|_1); the lambda the
-// following step preconditions with.
+// following step preconditions with and, in steady state, that step's proposal from the
+// reductions the cell-gradient pass formed.
 __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                             int nwl, int ne, int nov, int ncell,
                                                             int use_fixed, double lam_fixed) {
-    __shared__ double red[4];
-    __shared__ long long redi[4];
+    __shared__ double rs[4][4], rm[4];
+    __shared__ long long ri[4];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
     const bool init = !use_fixed && sc->lambda_valid == 0;
-    const double wl = sum_parts(part + PART_WL * L.pstride, nwl, red);
-    const double e = sum_parts(part + PART_E * L.pstride, ne, red);
-    const long long ov =
-        sum_parts(reinterpret_cast<const long long *>(part) + PART_OVF * L.pstride, nov, redi);
-    double n1 = 0.0, n2 = 0.0;
-    if (init) {
-        n1 = sum_parts(part + PART_N1 * L.pstride, ncell, red);
-        n2 = sum_parts(part + PART_N2 * L.pstride, ncell, red);
+    const bool prop = !init && ncell > 0;
+    // every reduction's loads first, then one block tree for all of them (the same trees as
+    // block_sum / block_max, so the totals equal separate reductions bit for bit)
+    double v[4];
+    v[0] = thread_sum(part + PART_WL * L.pstride, nwl);
+    v[1] = thread_sum(part + PART_E * L.pstride, ne);
+    v[2] = init ? thread_sum(part + PART_N1 * L.pstride, ncell)
+                : (prop ? thread_sum(part + PART_DV * L.pstride, ncell) : 0.0);
+    v[3] = init ? thread_sum(part + PART_N2 * L.pstride, ncell)
+                : (prop ? thread_sum(part + PART_DG * L.pstride, ncell) : 0.0);
+    double gm = prop ? thread_max(part + PART_GMAX * L.pstride, ncell) : 0.0;
+    long long ov = thread_sum(reinterpret_cast<const long long *>(part) + PART_OVF * L.pstride, nov);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = group_sum<64>(v[j]);
+    gm = group_max<64>(gm);
+    ov = group_sum<64>(ov);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rs[w][j] = v[j];
+        rm[w] = gm;
+        ri[w] = ov;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        sc->wl = wl;
-        sc->energy = 0.5 * nd.wb * nd.hb * e;
-        sc->overflow_num = ov;
-        sc->overflow = (double)ov / (double)nd.total_charge;
+        double t[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[j] = (rs[0][j] + rs[1][j]) + (rs[2][j] + rs[3][j]);
+        const double GM = fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3]));
+        const long long OV = (ri[0] + ri[1]) + (ri[2] + ri[3]);
+        sc->wl = t[0];
+        sc->energy = 0.5 * nd.wb * nd.hb * t[1];
+        sc->overflow_num = OV;
+        sc->overflow = (double)OV / (double)nd.total_charge;
         sc->init_this_eval = init ? 1 : 0;
         if (init) {
-            sc->lambda = sc->lambda0_scale * (n2 > 0.0 ? n1 / n2 : 1.0);
+            sc->lambda = sc->lambda0_scale * (t[3] > 0.0 ? t[2] / t[3] : 1.0);
             sc->lambda_valid = 1;
         }
         sc->lambda_step = use_fixed ? lam_fixed : sc->lambda;
+        if (prop) step_propose(sc, t[2], t[3], GM, nd.wb);
     }
 }
 
@@ -83,15 +104,8 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(NetDev nd, SlotArgs sa,
 }
 
 // ---- Nesterov -------------------------------------------------------------------------------
-// Preconditioner P_i = max(1, pins_i + lambda area_i), g~ = g / P, with the lambda of the
-// evaluation that produced g.
-template <typename T>
-__device__ __forceinline__ double precond(const T *cs, int n, int i, double lam) {
-    const double P = (double)cs[i] + lam * (double)cs[n + i];
-    return P < 1.0 ? 1.0 : P;
-}
-
-// Per block: |v - v_prev|^2, |g~ - g~_prev|^2, max|g~|.
+// The step's reductions when the evaluation did not form them (a slot's first evaluation, or a
+// second step on one gradient): per block |v - v_prev|^2, |g~ - g~_prev|^2, max|g~|.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     __shared__ double red[4];
@@ -99,36 +113,13 @@ __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs 
     const Scalars *sc = scalars(base, L);
     const int n = nd.n_mov;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    double dv = 0.0, dg = 0.0, gm = 0.0;
-    if (i < n) {
-        const T *cs = reinterpret_cast<const T *>(nd.cstep);
-        const double P = precond(cs, n, i, sc->lambda_step);
-        const vec2<T> v = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-        const vec2<T> vp = reinterpret_cast<const vec2<T> *>(base + L.vprev)[i];
-        const T *g = reinterpret_cast<const T *>(base + L.g);
-        const T *gp = reinterpret_cast<const T *>(base + L.gprev);
-        const double gx = (double)g[i] / P, gy = (double)g[n + i] / P;
-        const double ax = (double)v.x - (double)vp.x;
-        const double ay = (double)v.y - (double)vp.y;
-        const double bx = gx - (double)gp[i], by = gy - (double)gp[n + i];
-        dv = ax * ax + ay * ay;
-        dg = bx * bx + by * by;
-        gm = fmax(fabs(gx), fabs(gy));
-    }
-    dv = block_sum(dv, red);
-    dg = block_sum(dg, red);
-    gm = block_max(gm, red);
-    double *part = reinterpret_cast<double *>(base + L.part);
-    if (threadIdx.x == 0) {
-        part[PART_DV * L.pstride + blockIdx.x] = dv;
-        part[PART_DG * L.pstride + blockIdx.x] = dg;
-        part[PART_GMAX * L.pstride + blockIdx.x] = gm;
-    }
+    const T *g = reinterpret_cast<const T *>(base + L.g);
+    const bool live = i < n;
+    step_block_norms<T>(nd, base, L, i, live, live ? g[i] : (T)0, live ? g[n + i] : (T)0,
+                        sc->lambda_step, red);
 }
 
-// alpha_0 = 0.1 bin / max|g~| or alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein);
-// a' = (1 + sqrt(4 a^2 + 1)) / 2 with momentum (a - 1) / a'; lambda grows by the schedule's
-// ratio.
+// Totals of those reductions and the step proposal.
 __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                              int nb) {
     __shared__ double red[4];
@@ -138,30 +129,24 @@ __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArg
     const double DV = sum_parts(part + PART_DV * L.pstride, nb, red);
     const double DG = sum_parts(part + PART_DG * L.pstride, nb, red);
     const double GM = max_parts(part + PART_GMAX * L.pstride, nb, red);
-    if (threadIdx.x == 0) {
-        double alpha;
-        if (sc->k == 0)
-            alpha = 0.1 * nd.wb / (GM > 1e-30 ? GM : 1e-30);
-        else
-            alpha = DG > 0.0 ? sqrt(DV) / sqrt(DG) : sc->alpha;
-        const double a = sc->a;
-        const double an = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
-        sc->step_alpha = alpha;
-        sc->step_coef = (a - 1.0) / an;
-        sc->a = an;
-        sc->alpha = alpha;
-        sc->k += 1;
-        if (sc->lambda_valid) sc->lambda *= sc->lambda_ratio;
-    }
+    if (threadIdx.x == 0) step_propose(sc, DV, DG, GM, nd.wb);
 }
 
-// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~.
+// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~.  One
+// thread commits the proposal (a = a', alpha, k + 1, lambda times the schedule's ratio); the
+// other blocks read only the proposal's own fields.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     char *base = sa.base[blockIdx.y];
-    const Scalars *sc = scalars(base, L);
+    Scalars *sc = scalars(base, L);
     const int n = nd.n_mov;
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) {
+        sc->a = sc->step_a;
+        sc->alpha = sc->step_alpha;
+        sc->k += 1;
+        if (sc->lambda_valid) sc->lambda *= sc->lambda_ratio;
+    }
     if (i >= n) return;
     const T *cs = reinterpret_cast<const T *>(nd.cstep);
     const double P = precond(cs, n, i, sc->lambda_step);
@@ -244,16 +229,21 @@ hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout
 }
 
 template <typename T>
-hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, hipStream_t st) {
+hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool proposed,
+                       hipStream_t st) {
     const int nc = cell_parts(nd);
     if (nc == 0) return hipSuccess;
-    HP_LAUNCH("step_norms_kernel", step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa, L);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    HP_LAUNCH("step_scalars_kernel", step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa,
-              L, nc);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (!proposed) {
+        HP_LAUNCH("step_norms_kernel", step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd,
+                  sa, L);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        HP_LAUNCH("step_scalars_kernel", step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd,
+                  sa, L, nc);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa,
               L);
     return hipGetLastError();
@@ -274,7 +264,7 @@ hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumb
     template hipError_t launch_combine<T>(const NetDev &, const SlotArgs &, const SlotLayout &,  \
                                           hipStream_t);                                         \
     template hipError_t launch_step<T>(const NetDev &, const SlotArgs &, const SlotLayout &,     \
-                                       hipStream_t);                                            \
+                                       bool, hipStream_t);                                      \
     template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \
                                               const SlotLayout &, hipStream_t);
 HP_INST(float)

@@ -63,6 +63,7 @@ _SIGS = {
     "hp_slot_free": [_P, C.c_int32],
     "hp_set_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_get_positions": [_P, C.c_int32, _P, _P, C.c_int],
+    "hp_get_eval_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
     "hp_nesterov_step": [_P, _P, C.c_int32],
@@ -176,6 +177,10 @@ def hp_set_positions(ctx, slot, x, y, on_device):
 
 def hp_get_positions(ctx, slot, x, y, on_device):
     _chk(lib().hp_get_positions(ctx, slot, _ptr(x), _ptr(y), int(on_device)))
+
+
+def hp_get_eval_positions(ctx, slot, x, y, on_device):
+    _chk(lib().hp_get_eval_positions(ctx, slot, _ptr(x), _ptr(y), int(on_device)))
 
 
 def hp_set_schedule(ctx, slot, lambda0_scale, decades, total_iters):
@@ -304,6 +309,13 @@ class Placer:
         x = np.zeros(self.nl.n_movable, self.dtype)
         y = np.zeros(self.nl.n_movable, self.dtype)
         hp_get_positions(self.ctx, s, x, y, False)
+        return x, y
+
+    def eval_positions(self, s):
+        """The look-ahead point v where the next evaluation is taken."""
+        x = np.zeros(self.nl.n_movable, self.dtype)
+        y = np.zeros(self.nl.n_movable, self.dtype)
+        hp_get_eval_positions(self.ctx, s, x, y, False)
         return x, y
 
     def set_schedule(self, s, lambda0_scale=1e-4, decades=4.0, total_iters=1000):

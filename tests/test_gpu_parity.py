@@ -108,6 +108,32 @@ def test_maps_cleared_and_deterministic(hy, orc, case, prec):
     pl.free_slot(s)
 
 
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
+def test_charge_map_exact_with_reused_grouping(hy, orc, case, prec):
+    """The scatter rebuilds its tile order only every few evaluations, and cells that left
+    their chunk's window since then take the atomic path.  Along a placement from random
+    positions (large early moves, so many cells leave their windows) the charge map and the
+    overflow numerator at every evaluation point stay bit-exact, with maps kept or cleared."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    pl.set_schedule(s, 1e-4, 4.0, 200)
+    rf = None
+    for it in range(11):
+        keep = it % 3 == 2
+        vx, vy = pl.eval_positions(s)
+        pl.eval(s, gamma, keep_maps=keep)
+        rm, rf_ = o.density_q(vx, vy)
+        rf = rf_ if rf is None else rf
+        _, num = o.overflow(rm, rf)
+        assert pl.state(s)["overflow_num"] == num, it
+        if keep:
+            assert np.array_equal(pl.map(s, hy.HP_MAP_RHO_MOV), rm), it
+        pl.step(s)
+    pl.free_slot(s)
+
+
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("tiny", 32), ("small", 32)])
 def test_lambda_init_and_nesterov_steps(hy, orc, case, prec):
     """First evaluation derives lambda_0; three [eval, step] iterations follow the oracle."""
