@@ -47,17 +47,22 @@ def algorithmic_bytes(nl, rs=4):
     N, Nall = nl.n_movable, nl.n_cells
     Pm = int(np.sum(nl.pin_cell[np.repeat(deg >= 2, deg)] < N))
     M2 = nl.mx * nl.my
+    wa = 4 * (E2 + 1) + 4 * P2 + 2 * rs * P2 + 2 * rs * Nall + 2 * rs * P2
+    hpwl = 4 * (E2 + 1) + 4 * P2 + 8 * P2 + 2 * rs * Nall
+    scatter = 2 * rs * N + 20 * N + 8 * M2
     return {
-        # net_start, pin cell ids, pin offsets, every cell position once, pin gradients out
-        "sweep_wa": 4 * (E2 + 1) + 4 * P2 + 2 * rs * P2 + 2 * rs * Nall + 2 * rs * P2,
-        # net_start, pin cell ids, quantized offsets, positions
-        "sweep_hpwl": 4 * (E2 + 1) + 4 * P2 + 8 * P2 + 2 * rs * Nall,
-        # the charge scatter as a whole: positions and charge constants (16 + 4 B) in, the
-        # int64 map out once; its sort and its tile windows are intermediates
-        "bin_accum_kernel": 2 * rs * N + 20 * N + 8 * M2,
-        # cell CSR, pin gradients, positions, charge constants, two field maps, gradient out
+        # the first launch of an evaluation: WA sweep of v (net_start, pin cell ids, pin
+        # offsets, every position once, pin gradients out), HPWL sweep of u (quantized offsets,
+        # u; the topology is shared), and the charge scatter of v (charge constants in, the
+        # int64 map out; v already counted); the grouping and tile windows are intermediates
+        "eval_front_kernel": wa + (8 * P2 + 2 * rs * Nall) + (20 * N + 8 * M2),
+        "sweep_wa": wa,
+        "sweep_hpwl": hpwl,
+        "bin_accum_kernel": scatter,
+        # cell CSR, pin gradients, positions, charge constants, the field map, gradient out;
+        # for the next step's reductions also v_prev, g_prev and the preconditioner's inputs
         "cell_grad_kernel": 4 * (N + 1) + 4 * Pm + 2 * rs * Pm + 2 * rs * N + 20 * N
-        + 2 * rs * M2 + 2 * rs * N,
+        + 2 * rs * M2 + 2 * rs * N + 3 * 2 * rs * N,
         # fixed int64 map in, row transform out (the movable map is the scatter's output)
         "spec_rows_fwd": 8 * M2 + rs * M2,
         "spec_cols": rs * M2 + 2 * rs * M2,
@@ -130,16 +135,11 @@ def main():
     pl = hy.Placer(nl, precision=32)
     work, inc = pl.new_slot(), pl.new_slot()
 
-    def iteration():
-        pl.eval(work, gamma, want_host=False)
-        pl.step(work)
-        pl.hpwl(work, want_host=False)
-
     def round_(iters, seed):
-        """One Hybro round on `work`: perturb, iters placer iterations, keep the best."""
+        """One Hybro round on `work`: perturb, iters placer iterations (objective + gradient,
+        Nesterov step, exact HPWL; one library call), keep the best."""
         pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, seed, want_idx=False)
-        for _ in range(iters):
-            iteration()
+        pl.iterate(work, gamma, iters, hpwl=True)
         pl.select_best([work], inc, want_host=False)
 
     def restart_from_incumbent(iters):
@@ -158,8 +158,7 @@ def main():
     pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.5, 8.0, 2, want_idx=False)
     pl.set_positions(work, nl.x0, nl.y0)
     pl.set_schedule(work, 1e-4, 4.0, max(W, 1))
-    for _ in range(W):
-        iteration()
+    pl.iterate(work, gamma, W, hpwl=True)
     pl.hpwl(work)
     pl.select_best([work], inc)
     torch.cuda.synchronize()
@@ -216,9 +215,8 @@ def main():
     for k, v in kernels.items():
         if k in ab:
             v["algorithmic_gbs"] = round(ab[k] / (v["avg_us"] * 1e-6) / 1e9, 1)
-    it_bytes = sum(ab[k] for k in ("sweep_wa", "bin_accum_kernel", "cell_grad_kernel",
-                                   "spec_rows_fwd", "spec_cols", "spec_rows_inv",
-                                   "step_norms_kernel", "step_update_kernel", "sweep_hpwl"))
+    it_bytes = sum(ab[k] for k in ("eval_front_kernel", "cell_grad_kernel", "spec_rows_fwd",
+                                   "spec_cols", "spec_rows_inv", "step_update_kernel"))
     ms_step = 1e3 * dt / K
     out = {
         "metric": METRIC, "value": round(K / dt, 2), "unit": "iter/s", "n_gpus": 1, "steps": K,

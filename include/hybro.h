@@ -50,9 +50,11 @@ enum {
     HP_ENOTIMPL = -5
 };
 
-/* Die and bin grid.  mx, my: number of bins, powers of two in [8, 4096]; the bin width W/mx
- * and height H/my must be multiples of 2^-12 (so bin edges are exact in the 2^-12 integer
- * coordinates of the density map).  target_density: the rho_t of the overflow measure.
+/* Die and bin grid.  W, H: at most 16384 (the exact HPWL works on 32-bit pin coordinates in
+ * 2^-16 units, so pin coordinates must stay within (-2^15, 2^15); positions the library
+ * produces stay inside the die).  mx, my: number of bins, powers of two in [8, 4096]; the bin
+ * width W/mx and height H/my must be multiples of 2^-12 (so bin edges are exact in the 2^-12
+ * integer coordinates of the density map).  target_density: the rho_t of the overflow measure.
  * stretch: 1 spreads a small cell's charge over at least sqrt(2) bins per side (ePlace local
  * smoothing), 0 uses the cell's own rectangle.  fd5: 1 uses the 5-point Laplacian's
  * eigenvalues in the Poisson solve instead of the continuous ones. */
@@ -137,6 +139,24 @@ int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n_slots,
  * Barzilai-Borwein |v - v_prev| / |g~ - g~_prev|, u' = clamp(v - alpha g~),
  * a' = (1 + sqrt(4 a^2 + 1)) / 2, v' = clamp(u' + (a - 1)/a' (u' - u)).  Device only. */
 int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n_slots);
+
+/* `iters` iterations of the placer (Sec. 3.1) on every listed slot, all on the device: each is
+ * hp_eval_objective_grad with the slots' scheduled lambda and the given gamma (nothing returned
+ * to the host), hp_nesterov_step and, with HP_ITER_HPWL, hp_hpwl without outputs.  With
+ * HP_ITER_GRAPH, once every slot is in steady state (lambda derived) the iterations run as
+ * replays of a HIP graph of a fixed block of them, captured at the first such call for this
+ * slot list, gamma and flags and kept until one of the slots is freed; results are
+ * bit-identical with and without it.  While per-kernel timing is enabled no graph is used.
+ * Leftover iterations (fewer than a block, or before steady state) run as plain launches.
+ * HP_ITER_GRAPH is currently disabled and returns HP_ENOTIMPL: the first device run of the
+ * replay stalled in a later stream synchronisation, and the cause is not yet established. */
+enum { HP_ITER_HPWL = 1, HP_ITER_GRAPH = 2 };
+typedef struct {
+    double gamma;
+    int32_t flags;
+} hp_iter_params;
+int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const hp_iter_params *p,
+               int32_t iters);
 
 /* Perturbation of Alg. 1 / Sec. 4.2 on slot's major solution u, which also restarts the
  * optimiser there.  mode HP_PERTURB_GAUSS: the round(fraction * n_movable) cells with the

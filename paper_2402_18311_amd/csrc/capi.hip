@@ -39,6 +39,10 @@ int fail(int code, const std::string &msg) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Pin slots of the sweep order: a net of d <= 64 pins takes G = nextpow2(d) < 2d slots (the
+// unused ones padded), a larger net exactly d, so 2 * n_pins bounds them.
+size_t sweep_slots_bound(const hp_shape &s) { return 2 * (size_t)s.n_pins + 64; }
+
 struct NetBuf {
     size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
         cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh, total;
@@ -52,11 +56,11 @@ NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
         o = align256(o + bytes);
     };
     const size_t E = s.n_nets, P = s.n_pins, Nm = s.n_movable, Nf = s.n_cells - s.n_movable;
-    const size_t mx = d.mx, my = d.my;
+    const size_t mx = d.mx, my = d.my, PS = sweep_slots_bound(s);
     put(b.net_start, 4 * (E + 1));
-    put(b.pin_cell, 4 * P);
-    put(b.pin_off, 2 * rs * P);
-    put(b.pin_offq, 8 * P);
+    put(b.pin_cell, 4 * PS);
+    put(b.pin_off, 2 * rs * PS);
+    put(b.pin_offq, 8 * PS);
     put(b.net_w, rs * E);
     put(b.cell_pin_start, 4 * (Nm + 1));
     put(b.cell_pins, 4 * P);
@@ -126,7 +130,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.gprev, 2 * rs * Nm);
     put(L.g, 2 * rs * Nm);
     put(L.gd, 2 * rs * Nm);
-    put(L.pin_grad, 2 * rs * P);
+    put(L.pin_grad, 2 * rs * sweep_slots_bound(s));
     put(L.rho, 8 * nb);
     put(L.t1, rs * nb);
     put(L.bx, rs * nb);
@@ -146,6 +150,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.soff, 4 * (size_t)g.sort_blocks * g.ntiles);
     put(L.tstart, 4 * ((size_t)g.ntiles + 1));
     put(L.cstart, 4 * ((size_t)g.ntiles + 1));
+    put(L.chunk, 16 * (size_t)g.max_chunks);
     put(L.wins, 8 * (size_t)g.max_chunks * ws * ws);
     L.total = o;
     return L;
@@ -168,7 +173,8 @@ struct Slot {
     char *base = nullptr;
     bool lambda_valid = false;  // host mirror of the device flag
     bool maps_valid = false;
-    bool hpwl_pending = false;  // an HPWL sweep ran; its partials are not yet reduced
+    bool hpwl_requested = false; // hp_hpwl was called; its sweep is not launched yet
+    bool hpwl_pending = false;  // an HPWL sweep was launched; its partials are not yet reduced
     bool step_proposed = false; // the last evaluation formed the next step's proposal
     int since_group = -1;       // evaluations since the scatter's tile order was built (-1: none)
     bool rho_dirty = false;     // rho holds a kept map, not zeros
@@ -190,32 +196,9 @@ struct hp_ctx {
     int lds_budget = 65536;
     std::vector<Netlist> nets;
     std::vector<Slot> slots;
-    // The net sweeps (WA and HPWL) run on a second stream of the context, so that they overlap
-    // the charge scatter and the Poisson solve, which do not depend on them.
-    hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_side = nullptr;
-    bool side_pending = false;  // the side stream holds work the context stream has not joined
 };
 
 namespace {
-
-// Order the side stream after all work enqueued on the context stream so far.
-int fork_side(hp_ctx *c) {
-    HP_CHECK(hipEventRecord(c->ev_fork, c->stream));
-    HP_CHECK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    c->side_pending = true;
-    return HP_OK;
-}
-
-// Order the context stream after all work enqueued on the side stream so far.  Every entry
-// point that reads or writes slot state joins first, so results never depend on the overlap.
-int join_side(hp_ctx *c) {
-    if (!c || !c->side_pending) return HP_OK;
-    HP_CHECK(hipEventRecord(c->ev_side, c->side));
-    HP_CHECK(hipStreamWaitEvent(c->stream, c->ev_side, 0));
-    c->side_pending = false;
-    return HP_OK;
-}
 
 size_t rsize(const hp_ctx *c) { return c->precision == 64 ? 8 : 4; }
 
@@ -232,8 +215,8 @@ int check_die(const hp_ctx *ctx, const hp_die *d) {
     const double bq = d->W / d->mx * 4096.0, hq = d->H / d->my * 4096.0;
     if (bq != std::floor(bq) || hq != std::floor(hq) || bq < 1 || hq < 1)
         return fail(HP_EINVAL, "bin width and height must be multiples of 2^-12");
-    if (d->W * 4096.0 >= 2147483647.0 || d->H * 4096.0 >= 2147483647.0)
-        return fail(HP_EINVAL, "die too large for 2^-12 integer coordinates");
+    if (d->W > 16384.0 || d->H > 16384.0)  // pin coordinates in 2^-16 units stay below 2^31
+        return fail(HP_EINVAL, "die sides must be at most 16384 (32-bit exact HPWL coordinates)");
     if (!(d->target_density > 0 && d->target_density <= 1e6))
         return fail(HP_EINVAL, "target_density must be positive");
     return HP_OK;
@@ -310,6 +293,9 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     // ---- degree buckets -------------------------------------------------------------------
     // order: block-per-net (largest first), then groups of 64, 32, ..., 2 lanes
     const int Gs[7] = {0, 64, 32, 16, 8, 4, 2};
+    // Group buckets are laid out padded: net j of the bucket owns pin slots
+    // [pin0 + j G, pin0 + (j + 1) G), its pins first, the rest marked by cell -1, so a lane
+    // finds its pin slot from its index alone.  Each block takes kNetsPerLane x (256 / G) nets.
     std::vector<std::vector<int>> members(7);
     for (int e = 0; e < E; ++e) {
         const int d = net_start[e + 1] - net_start[e];
@@ -344,7 +330,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     for (int b = 0; b < 7; ++b) {
         if (members[b].empty()) continue;
         const int G = Gs[b];
-        const int npb = G ? kBlock / G : 1;
+        const int npb = G ? kNetsPerLane * (kBlock / G) : 1;
         int nblk = ((int)members[b].size() + npb - 1) / npb;
         nblk = (nblk + kXcds - 1) / kXcds * kXcds;
         bk.G[bk.n] = G;
@@ -370,29 +356,39 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     std::vector<int32_t> h_ns(ns + 1), h_pc;
     std::vector<T> h_po, h_w;
     std::vector<int32_t> h_pq;
-    std::vector<int32_t> orig_to_sweep(P, -1);
     h_pc.reserve(P);
     h_po.reserve(2 * (size_t)P);
     h_pq.reserve(2 * (size_t)P);
     bool any_w = false;
     if (net_weight)
         for (int e = 0; e < E; ++e) any_w |= net_weight[e] != 1.0;
-    for (int i = 0; i < ns; ++i) {
-        const int e = order[i];
-        h_ns[i] = (int32_t)h_pc.size();
-        for (int p = net_start[e]; p < net_start[e + 1]; ++p) {
-            orig_to_sweep[p] = (int32_t)h_pc.size();
-            h_pc.push_back(pin_cell[p]);
-            h_po.push_back((T)pin_ox[p]);
-            h_po.push_back((T)pin_oy[p]);
-            h_pq.push_back((int32_t)std::llrint(pin_ox[p] * 65536.0));
-            h_pq.push_back((int32_t)std::llrint(pin_oy[p] * 65536.0));
+    for (int b = 0, i = 0; b < bk.n; ++b) {
+        const int G = bk.G[b];
+        bk.pin0[b] = (int32_t)h_pc.size();
+        for (; i < bk.net1[b]; ++i) {
+            const int e = order[i];
+            h_ns[i] = (int32_t)h_pc.size();
+            for (int p = net_start[e]; p < net_start[e + 1]; ++p) {
+                h_pc.push_back(pin_cell[p]);
+                h_po.push_back((T)pin_ox[p]);
+                h_po.push_back((T)pin_oy[p]);
+                h_pq.push_back((int32_t)std::llrint(pin_ox[p] * 65536.0));
+                h_pq.push_back((int32_t)std::llrint(pin_oy[p] * 65536.0));
+            }
+            for (int k = net_start[e + 1] - net_start[e]; k < G; ++k) {  // padding lanes
+                h_pc.push_back(-1);
+                h_po.push_back(T(0));
+                h_po.push_back(T(0));
+                h_pq.push_back(0);
+                h_pq.push_back(0);
+            }
+            if (any_w) h_w.push_back((T)net_weight[e]);
         }
-        if (any_w) h_w.push_back((T)net_weight[e]);
     }
     h_ns[ns] = (int32_t)h_pc.size();
     const int ps = (int)h_pc.size();
     nd.ps = ps;
+    if ((size_t)ps > sweep_slots_bound(S)) return fail(HP_EINVAL, "internal: sweep slot bound");
 
     // cell -> sweep-pin CSR (movable cells), and pin counts over all nets for the
     // preconditioner
@@ -400,13 +396,13 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     for (int p = 0; p < P; ++p)
         if (pin_cell[p] < Nm) cnt_all[pin_cell[p]]++;
     for (int q = 0; q < ps; ++q)
-        if (h_pc[q] < Nm) h_cps[h_pc[q] + 1]++;
+        if (h_pc[q] >= 0 && h_pc[q] < Nm) h_cps[h_pc[q] + 1]++;
     for (int i = 0; i < Nm; ++i) h_cps[i + 1] += h_cps[i];
     std::vector<int32_t> h_cp(h_cps[Nm]);
     {
         std::vector<int32_t> fill(h_cps.begin(), h_cps.end() - 1);
         for (int q = 0; q < ps; ++q)
-            if (h_pc[q] < Nm) h_cp[fill[h_pc[q]]++] = q;
+            if (h_pc[q] >= 0 && h_pc[q] < Nm) h_cp[fill[h_pc[q]]++] = q;
     }
 
     // per-cell charge constants (2^-12 / 2^-16 integers, computed in FP64 once)
@@ -586,6 +582,8 @@ int resolve(hp_ctx *ctx, const int32_t *slots, int32_t n, Netlist **net,
         int rc = get_slot(ctx, slots[i], &s, &nl);
         if (rc) return rc;
         if (*net && nl != *net) return fail(HP_ESTATE, "slots of one call must share a netlist");
+        for (Slot *o : ss)
+            if (o == s) return fail(HP_EINVAL, "slot " + std::to_string(slots[i]) + " listed twice");
         *net = nl;
         ss.push_back(s);
         if (i % kMaxSlots == 0) chunks.push_back(SlotArgs{});
@@ -595,8 +593,32 @@ int resolve(hp_ctx *ctx, const int32_t *slots, int32_t n, Netlist **net,
     return HP_OK;
 }
 
+// hp_hpwl only records the request; the sweep of u runs inside the next evaluation's first
+// launch, or here, before anything that would change u or read the result.
+int launch_requested_hpwl(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
+    SlotArgs sa{};
+    auto go = [&]() -> int {
+        if (ctx->precision == 32)
+            HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
+        else
+            HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->stream));
+        sa.n = 0;
+        return HP_OK;
+    };
+    for (Slot *s : ss) {
+        if (!s->hpwl_requested) continue;
+        s->hpwl_requested = false;
+        s->hpwl_pending = true;
+        sa.base[sa.n++] = s->base;
+        if (sa.n == kMaxSlots) HP_TRY(go());
+    }
+    if (sa.n) HP_TRY(go());
+    return HP_OK;
+}
+
 // Reduce the HPWL partials of slots whose sweep has not been totalled yet.
 int finish_hpwl(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
+    HP_TRY(launch_requested_hpwl(ctx, NL, ss));
     SlotArgs sa{};
     for (Slot *s : ss) {
         if (!s->hpwl_pending) continue;
@@ -611,19 +633,19 @@ int finish_hpwl(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
     return HP_OK;
 }
 
-template <typename T>
-int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p, double *wl,
-              double *energy, double *overflow, void *gx, void *gy) {
-    Netlist *NL;
-    std::vector<SlotArgs> chunks;
-    std::vector<Slot *> ss;
-    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
-    if (rc) return rc;
+int check_eval_params(const hp_eval_params *p) {
     if (!p) return fail(HP_EINVAL, "params is NULL");
     if (!(p->gamma > 0) || !std::isfinite(p->gamma)) return fail(HP_EINVAL, "gamma must be > 0");
     if (p->grad_mode != 0) return fail(HP_ENOTIMPL, "only the field-force gradient runs on the device");
+    if (p->lambda >= 0 && !std::isfinite(p->lambda)) return fail(HP_EINVAL, "lambda must be finite");
+    return HP_OK;
+}
+
+// The launches of one evaluation of resolved slots (parameters already checked).
+template <typename T>
+int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
+                  const std::vector<Slot *> &ss, const hp_eval_params *p) {
     const bool use_fixed = p->lambda >= 0;
-    if (use_fixed && !std::isfinite(p->lambda)) return fail(HP_EINVAL, "lambda must be finite");
     hipStream_t st = ctx->stream;
     const NetDev &nd = NL->nd;
     const SlotLayout &L = NL->L;
@@ -631,19 +653,23 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
         const SlotArgs &sa = chunks[c];
         bool any_init = false;
         bool regroup = false, dirty = false;
+        uint32_t hmask = 0;  // slots whose requested HPWL sweep rides along
         for (int i = 0; i < sa.n; ++i) {
-            const Slot *s = ss[c * kMaxSlots + i];
+            Slot *s = ss[c * kMaxSlots + i];
             any_init |= !use_fixed && !s->lambda_valid;
             regroup |= s->since_group < 0 || s->since_group >= kRegroupEvery;
             dirty |= s->rho_dirty;
+            if (s->hpwl_requested) {
+                hmask |= 1u << i;
+                s->hpwl_requested = false;
+                s->hpwl_pending = true;
+            }
         }
-        // the WA sweep on the side stream, beside the scatter and the Poisson solve
-        HP_TRY(fork_side(ctx));
-        HP_CHECK(launch_sweep_wa<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, ctx->side));
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
-        HP_CHECK(launch_scatter<T>(nd, sa, L, regroup, st));
+        // WA sweep, HPWL sweep and the scatter (or the counting pass of a regroup) in one launch
+        HP_CHECK(launch_eval_front<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, hmask, regroup, st));
+        if (regroup) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, st));
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0, p->keep_maps != 0, st));
-        HP_TRY(join_side(ctx));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
                                      st));
@@ -658,7 +684,22 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
             s->rho_dirty = p->keep_maps != 0;
         }
     }
-    const size_t rs = sizeof(T), Nm = nd.n_mov;
+    return HP_OK;
+}
+
+template <typename T>
+int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p, double *wl,
+              double *energy, double *overflow, void *gx, void *gy) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    HP_TRY(check_eval_params(p));
+    HP_TRY(eval_resolved<T>(ctx, NL, chunks, ss, p));
+    hipStream_t st = ctx->stream;
+    const SlotLayout &L = NL->L;
+    const size_t rs = sizeof(T), Nm = NL->nd.n_mov;
     for (int i = 0; i < n; ++i) {
         if (gx) HP_CHECK(hipMemcpyAsync((char *)gx + i * Nm * rs, ss[i]->base + L.g, Nm * rs,
                                         hipMemcpyDeviceToDevice, st));
@@ -718,6 +759,34 @@ hipEvent_t prof_event() {
 }
 void prof_push(const char *name, hipEvent_t a, hipEvent_t b) { g_prof_pending.push_back({name, a, b}); }
 }  // namespace hp
+
+namespace {
+int step_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
+                  const std::vector<Slot *> &ss) {
+    HP_TRY(launch_requested_hpwl(ctx, NL, ss));  // the step changes u
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        const SlotArgs &sa = chunks[c];
+        bool proposed = true;
+        for (int i = 0; i < sa.n; ++i) proposed &= ss[c * kMaxSlots + i]->step_proposed;
+        if (ctx->precision == 32)
+            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, proposed, ctx->stream));
+        else
+            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, proposed, ctx->stream));
+    }
+    for (Slot *s : ss) s->step_proposed = false;
+    return HP_OK;
+}
+
+// An HPWL request of resolved slots: the sweep of u reads only u and writes only its own
+// partials, so it is deferred into the next evaluation's first launch (where it fills the
+// machine beside the WA sweep) or launched before anything that changes u or reads it; the
+// total is reduced from the partials when first needed.
+int hpwl_resolved(hp_ctx *, Netlist *, const std::vector<SlotArgs> &,
+                  const std::vector<Slot *> &ss) {
+    for (Slot *s : ss) s->hpwl_requested = true;
+    return HP_OK;
+}
+}  // namespace
 
 // ============================================================================================
 extern "C" {
@@ -784,36 +853,18 @@ int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
             lds = 65536;
         }
     }
-    hipStream_t side = nullptr;
-    hipEvent_t e1 = nullptr, e2 = nullptr;
-    HP_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
-    if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
-        if (e1) (void)hipEventDestroy(e1);
-        (void)hipStreamDestroy(side);
-        return fail(HP_EDEVICE, "hipEventCreateWithFlags failed");
-    }
     hp_ctx *c = new hp_ctx;
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->precision = precision;
     c->lds_budget = lds;
-    c->side = side;
-    c->ev_fork = e1;
-    c->ev_side = e2;
     *out = c;
     return HP_OK;
 }
 
 int hp_destroy(hp_ctx *ctx) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
-    (void)join_side(ctx);
-    hipError_t e = hipStreamSynchronize(ctx->stream);
-    const hipError_t e2 = hipStreamSynchronize(ctx->side);
-    if (e == hipSuccess) e = e2;
-    (void)hipEventDestroy(ctx->ev_fork);
-    (void)hipEventDestroy(ctx->ev_side);
-    (void)hipStreamDestroy(ctx->side);
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
     delete ctx;
     if (e != hipSuccess) return fail(HP_EDEVICE, hipGetErrorString(e));
     return HP_OK;
@@ -866,7 +917,6 @@ int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
         return fail(HP_ENOMEM, "slot buffer needs " + std::to_string(NL.L.total) + " bytes");
     char *base = (char *)dev_buf;
     hipStream_t st = ctx->stream;
-    HP_TRY(join_side(ctx));
     const size_t rs = rsize(ctx);
     const size_t Nm = NL.nd.n_mov, Nf = NL.nd.n_fixed;
     HP_CHECK(hipMemsetAsync(base, 0, NL.L.total, st));
@@ -892,7 +942,6 @@ int hp_slot_free(hp_ctx *ctx, int32_t slot) {
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
-    HP_TRY(join_side(ctx));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
     s->alive = false;
     s->base = nullptr;
@@ -905,7 +954,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!x || !y) return fail(HP_EINVAL, "x/y is NULL");
-    HP_TRY(join_side(ctx));
+    HP_TRY(launch_requested_hpwl(ctx, n, std::vector<Slot *>{s}));  // before u changes
     const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     hipStream_t st = ctx->stream;
     const SlotLayout &L = n->L;
@@ -944,7 +993,6 @@ int get_pos(hp_ctx *ctx, int32_t slot, size_t which, void *x, void *y, int on_de
     const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const char *src = s->base + which;  // (x, y) pairs
-    HP_TRY(join_side(ctx));
     if (Nm && x) HP_CHECK(hipMemcpy2DAsync(x, rs, src, 2 * rs, rs, Nm, k, ctx->stream));
     if (Nm && y) HP_CHECK(hipMemcpy2DAsync(y, rs, src + rs, 2 * rs, rs, Nm, k, ctx->stream));
     if (!on_device) HP_CHECK(hipStreamSynchronize(ctx->stream));
@@ -973,7 +1021,6 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
     if (rc) return rc;
     if (!(lambda0_scale > 0) || !std::isfinite(decades) || total_iters <= 0)
         return fail(HP_EINVAL, "bad schedule");
-    HP_TRY(join_side(ctx));
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
@@ -997,17 +1044,59 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n) {
     std::vector<Slot *> ss;
     int rc = resolve(ctx, slots, n, &NL, chunks, ss);
     if (rc) return rc;
-    HP_TRY(join_side(ctx));
-    for (size_t c = 0; c < chunks.size(); ++c) {
-        const SlotArgs &sa = chunks[c];
-        bool proposed = true;
-        for (int i = 0; i < sa.n; ++i) proposed &= ss[c * kMaxSlots + i]->step_proposed;
-        if (ctx->precision == 32)
-            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, proposed, ctx->stream));
-        else
-            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, proposed, ctx->stream));
+    return step_resolved(ctx, NL, chunks, ss);
+}
+
+int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double *out) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    HP_TRY(hpwl_resolved(ctx, NL, chunks, ss));
+    if (out_q || out) {
+        rc = finish_hpwl(ctx, NL, ss);
+        if (rc) return rc;
+        std::vector<int64_t> h(n);
+        for (int i = 0; i < n; ++i)
+            HP_CHECK(hipMemcpyAsync(&h[i], ss[i]->base + NL->L.scal + offsetof(Scalars, hpwl_q), 8,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HP_CHECK(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < n; ++i) {
+            if (out_q) out_q[i] = h[i];
+            if (out) out[i] = std::ldexp((double)h[i], -16);
+        }
     }
-    for (Slot *s : ss) s->step_proposed = false;
+    return HP_OK;
+}
+
+
+int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_params *p,
+               int32_t iters) {
+    Netlist *NL;
+    std::vector<SlotArgs> chunks;
+    std::vector<Slot *> ss;
+    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
+    if (rc) return rc;
+    if (!p) return fail(HP_EINVAL, "params is NULL");
+    if (iters < 0) return fail(HP_EINVAL, "iters must be >= 0");
+    if (p->flags & ~(HP_ITER_HPWL | HP_ITER_GRAPH)) return fail(HP_EINVAL, "unknown flags");
+    // Graph replay is switched off: its first run on the device stalled (a stream
+    // synchronisation after the replays never returned) and the cause is not established.
+    if (p->flags & HP_ITER_GRAPH)
+        return fail(HP_ENOTIMPL, "HP_ITER_GRAPH is disabled in this build (replay stalled; cause open)");
+    const hp_eval_params ep{p->gamma, -1.0, 0, 0};
+    HP_TRY(check_eval_params(&ep));
+    const bool with_hpwl = (p->flags & HP_ITER_HPWL) != 0;
+    auto iteration = [&]() -> int {
+        HP_TRY(ctx->precision == 32 ? eval_resolved<float>(ctx, NL, chunks, ss, &ep)
+                                    : eval_resolved<double>(ctx, NL, chunks, ss, &ep));
+        HP_TRY(step_resolved(ctx, NL, chunks, ss));
+        if (with_hpwl) HP_TRY(hpwl_resolved(ctx, NL, chunks, ss));
+        return HP_OK;
+    };
+    int done = 0;
+    for (; done < iters; ++done) HP_TRY(iteration());
     return HP_OK;
 }
 
@@ -1024,7 +1113,7 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
     const int Nm = n->nd.n_mov;
     int64_t m = mode == 2 ? Nm : (int64_t)std::floor(fraction * Nm + 0.5);
     if (m > Nm) m = Nm;
-    HP_TRY(join_side(ctx));
+    HP_TRY(launch_requested_hpwl(ctx, n, std::vector<Slot *>{s}));  // before u changes
     if (ctx->precision == 32)
         HP_CHECK(launch_perturb<float>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
                                        sigma_bins * n->nd.hb, seed, ctx->stream));
@@ -1040,43 +1129,6 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
                                 ctx->stream));
     if (out_count) *out_count = (int32_t)m;
     if (out_idx || out_count) HP_CHECK(hipStreamSynchronize(ctx->stream));
-    return HP_OK;
-}
-
-int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double *out) {
-    Netlist *NL;
-    std::vector<SlotArgs> chunks;
-    std::vector<Slot *> ss;
-    int rc = resolve(ctx, slots, n, &NL, chunks, ss);
-    if (rc) return rc;
-    // the sweep runs on the side stream: it reads only u and writes only its own partials, so
-    // it overlaps whatever is enqueued next until an entry point joins
-    HP_TRY(fork_side(ctx));
-    for (const SlotArgs &sa : chunks) {
-        if (ctx->precision == 32)
-            HP_CHECK(launch_sweep_hpwl<float>(NL->nd, NL->bk, sa, NL->L, ctx->side));
-        else
-            HP_CHECK(launch_sweep_hpwl<double>(NL->nd, NL->bk, sa, NL->L, ctx->side));
-    }
-    // the total is reduced from the sweep's per-block partials when first needed
-    for (Slot *s : ss) s->hpwl_pending = true;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (ctx->stream) HP_CHECK(hipStreamIsCapturing(ctx->stream, &cap));  // never on the null stream
-    if (cap != hipStreamCaptureStatusNone) HP_TRY(join_side(ctx));  // a capture must end joined
-    if (out_q || out) {
-        HP_TRY(join_side(ctx));
-        rc = finish_hpwl(ctx, NL, ss);
-        if (rc) return rc;
-        std::vector<int64_t> h(n);
-        for (int i = 0; i < n; ++i)
-            HP_CHECK(hipMemcpyAsync(&h[i], ss[i]->base + NL->L.scal + offsetof(Scalars, hpwl_q), 8,
-                                    hipMemcpyDeviceToHost, ctx->stream));
-        HP_CHECK(hipStreamSynchronize(ctx->stream));
-        for (int i = 0; i < n; ++i) {
-            if (out_q) out_q[i] = h[i];
-            if (out) out[i] = std::ldexp((double)h[i], -16);
-        }
-    }
     return HP_OK;
 }
 
@@ -1096,7 +1148,6 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbe
         if (s == inc) return fail(HP_EINVAL, "the incumbent cannot be a candidate");
     std::vector<Slot *> all(ss);
     all.push_back(inc);
-    HP_TRY(join_side(ctx));
     rc = finish_hpwl(ctx, NL, all);
     if (rc) return rc;
     if (ctx->precision == 32)
@@ -1122,7 +1173,6 @@ int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!dst) return fail(HP_EINVAL, "dst is NULL");
-    HP_TRY(join_side(ctx));
     const size_t nb = (size_t)n->nd.mx * n->nd.my, rs = rsize(ctx);
     const char *src = nullptr;
     size_t bytes = 0;
@@ -1154,7 +1204,6 @@ int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     if (!out) return fail(HP_EINVAL, "out is NULL");
-    HP_TRY(join_side(ctx));
     rc = finish_hpwl(ctx, n, std::vector<Slot *>{s});
     if (rc) return rc;
     Scalars h;

@@ -1,0 +1,99 @@
+// Device bodies of the binned charge scatter, shared by its own kernels and by the fused first
+// launch of an evaluation.  The scheme is described in k_binning.hip.
+#pragma once
+#include "hp_device.h"
+
+namespace hp {
+
+struct RectQ {
+    int l, r, b, t;
+};
+
+__device__ __forceinline__ RectQ cell_rect_b(const NetDev &nd, double x, double y, int4 c) {
+    const long long L = q12(x) + c.z, B = q12(y) + c.w;
+    RectQ q;
+    q.l = (int)min(max(L, 0LL), (long long)nd.wq_die);
+    q.r = (int)min(max(L + c.x, 0LL), (long long)nd.wq_die);
+    q.b = (int)min(max(B, 0LL), (long long)nd.hq_die);
+    q.t = (int)min(max(B + c.y, 0LL), (long long)nd.hq_die);
+    return q;
+}
+
+__device__ __forceinline__ int overlap_b(int lo, int hi, int idx, int w) {
+    const int a = max(lo, idx * w), b = min(hi, (idx + 1) * w);
+    return b > a ? b - a : 0;
+}
+
+// tile of cell i: the tile of its charge rectangle's lower-left bin (clamped into the die, so
+// that a cell whose rectangle is clipped away still has a place in the order)
+template <typename T>
+__device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i) {
+    const vec2<T> p = pos[i];
+    const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
+    const int j = min(q.l / nd.bq, nd.mx - 1), k = min(q.b / nd.hq, nd.my - 1);
+    return (k >> nd.log_ts) * nd.ntx + (j >> nd.log_ts);
+}
+
+// Counting pass of the grouping for block `blk` of the cells (dynamic LDS: int [ntiles]).
+template <typename T>
+__device__ __forceinline__ void count_body(const NetDev &nd, char *base, const SlotLayout &L, int blk) {
+    extern __shared__ int hist[];  // [ntiles]
+    if (blk >= nd.sort_blocks) return;  // block-uniform (the launch may round the grid up)
+    const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
+    int *tile = reinterpret_cast<int *>(base + L.tile);
+    for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) hist[t] = 0;
+    __syncthreads();
+    const int i0 = blk * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
+    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const int t = cell_tile<T>(nd, pos, i);
+        tile[i] = t;
+        atomicAdd(&hist[t], 1);
+    }
+    __syncthreads();
+    int *cnt = reinterpret_cast<int *>(base + L.scnt) + (size_t)blk * nd.ntiles;
+    for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) cnt[t] = hist[t];
+}
+
+// Accumulation of chunk c of the grouped order into its LDS window (dynamic LDS: uint64
+// [win_side^2]); cells outside the window add to rho with global atomics.
+template <typename T>
+__device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const SlotLayout &L, int c) {
+    extern __shared__ unsigned long long win[];  // [win_side^2]
+    const int *cstart = reinterpret_cast<const int *>(base + L.cstart);
+    if (c >= nd.max_chunks || c >= cstart[nd.ntiles]) return;  // block-uniform
+    const int4 ck = reinterpret_cast<const int4 *>(base + L.chunk)[c];
+    const int t = ck.x, s0 = ck.y, s1 = ck.z;
+    const int ws = nd.win_side, nw = ws * ws;
+    for (int b = threadIdx.x; b < nw; b += kBlock) win[b] = 0;
+    __syncthreads();
+    const int j00 = (t % nd.ntx) << nd.log_ts, k00 = (t / nd.ntx) << nd.log_ts;
+    const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
+    const int *sorted = reinterpret_cast<const int *>(base + L.sorted);
+    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
+    for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
+        const int i = sorted[s];
+        const vec2<T> p = pos[i];
+        const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
+        if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
+        const long long rq = nd.rq[i];
+        const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
+        const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
+        const bool inside = j0 >= j00 && j1 < j00 + ws && k0 >= k00 && k1 < k00 + ws;
+        for (int k = k0; k <= k1; ++k) {
+            const long long oy = overlap_b(q.b, q.t, k, nd.hq);
+            for (int j = j0; j <= j1; ++j) {
+                const long long ox = overlap_b(q.l, q.r, j, nd.bq);
+                const unsigned long long c = (unsigned long long)(rq * ox * oy);
+                if (inside)
+                    atomicAdd(&win[(k - k00) * ws + (j - j00)], c);
+                else  // moved out of the window since the order was built
+                    atomicAdd(&rho[(size_t)k * nd.mx + j], c);
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long *out = reinterpret_cast<unsigned long long *>(base + L.wins) + (size_t)c * nw;
+    for (int b = threadIdx.x; b < nw; b += kBlock) out[b] = win[b];
+}
+
+}  // namespace hp

@@ -1,5 +1,7 @@
 // Device-side helpers of libhybro: wave/block reductions and fixed-point conversions.
 #pragma once
+#include <climits>
+
 #include "hp_internal.h"
 
 namespace hp {
@@ -12,6 +14,12 @@ template <typename T> __device__ __forceinline__ vec2<T> cmk2(T a, T b) {
 }
 
 __device__ __forceinline__ int64_t q16(double v) { return __double2ll_rn(v * 65536.0); }
+// The same quantization in int32 (exact: scaling by 2^16 is exact in either type and the
+// result is rounded half to even once); valid for |v| < 2^15, which load-time validation of
+// the die guarantees for positions and pin offsets.
+template <typename T> __device__ __forceinline__ int q16i(T v);
+template <> __device__ __forceinline__ int q16i<float>(float v) { return __float2int_rn(v * 65536.0f); }
+template <> __device__ __forceinline__ int q16i<double>(double v) { return __double2int_rn(v * 65536.0); }
 __device__ __forceinline__ int64_t q12(double v) { return __double2ll_rn(v * 4096.0); }
 
 template <typename T> __device__ __forceinline__ T dev_exp(T v);
@@ -25,22 +33,82 @@ template <> __device__ __forceinline__ double pos_inf<double>() {
 }
 
 // Reductions inside aligned groups of G lanes (G a power of two <= 64); every lane of the
-// group gets the result.  The xor butterfly is a fixed order, so results are reproducible.
+// group gets the result.  Partners are combined smallest stride first: lane ^ 1 and lane ^ 2 by
+// DPP quad permutes, then the other quad of the 8-lane half-row (DPP half-row mirror), the
+// other half of the 16-lane row (DPP row mirror), lane ^ 16 (ds_swizzle) and lane ^ 32
+// (bpermute).  After each step every lane of a 2S-lane subgroup holds the same value (x + y
+// and y + x are equal), so the result is uniform over the group and run-to-run identical.
+template <int S> __device__ __forceinline__ int lane_partner32(int v) {
+    if constexpr (S == 1)
+        return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    else if constexpr (S == 2)
+        return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    else if constexpr (S == 4)
+        return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    else if constexpr (S == 8)
+        return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    else if constexpr (S == 16)
+        return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // bitmask mode: lane ^ 16 within 32
+    else
+        return __shfl_xor(v, 32);
+}
+template <int S, typename T> __device__ __forceinline__ T lane_partner(T v) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, lane_partner32<S>(__builtin_bit_cast(int, v)));
+    } else {
+        static_assert(sizeof(T) == 8, "32- or 64-bit values");
+        const long long b = __builtin_bit_cast(long long, v);
+        const int lo = lane_partner32<S>((int)(b & 0xffffffffLL));
+        const int hi = lane_partner32<S>((int)(b >> 32));
+        return __builtin_bit_cast(T, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                 (unsigned long long)(unsigned)lo));
+    }
+}
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    for (int s = 1; s < G; s <<= 1) {
+        if (s == 1) v += lane_partner<1>(v);
+        if (s == 2) v += lane_partner<2>(v);
+        if (s == 4) v += lane_partner<4>(v);
+        if (s == 8) v += lane_partner<8>(v);
+        if (s == 16) v += lane_partner<16>(v);
+        if (s == 32) v += lane_partner<32>(v);
+    }
     return v;
 }
 template <int G, typename T> __device__ __forceinline__ T group_max(T v) {
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, G));
+    for (int s = 1; s < G; s <<= 1) {
+        if (s == 1) v = max(v, lane_partner<1>(v));
+        if (s == 2) v = max(v, lane_partner<2>(v));
+        if (s == 4) v = max(v, lane_partner<4>(v));
+        if (s == 8) v = max(v, lane_partner<8>(v));
+        if (s == 16) v = max(v, lane_partner<16>(v));
+        if (s == 32) v = max(v, lane_partner<32>(v));
+    }
     return v;
 }
 template <int G, typename T> __device__ __forceinline__ T group_min(T v) {
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, G));
+    for (int s = 1; s < G; s <<= 1) {
+        if (s == 1) v = min(v, lane_partner<1>(v));
+        if (s == 2) v = min(v, lane_partner<2>(v));
+        if (s == 4) v = min(v, lane_partner<4>(v));
+        if (s == 8) v = min(v, lane_partner<8>(v));
+        if (s == 16) v = min(v, lane_partner<16>(v));
+        if (s == 32) v = min(v, lane_partner<32>(v));
+    }
     return v;
 }
+
+// Fast forms for the FP32 path of the WA sweep (exp via the hardware exp2, reciprocal by the
+// hardware estimate, ~1 ulp); the FP64 path keeps the library functions.
+template <typename T> __device__ __forceinline__ T wa_exp(T v);
+template <> __device__ __forceinline__ float wa_exp<float>(float v) { return __expf(v); }
+template <> __device__ __forceinline__ double wa_exp<double>(double v) { return exp(v); }
+template <typename T> __device__ __forceinline__ T wa_rcp(T v);
+template <> __device__ __forceinline__ float wa_rcp<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ __forceinline__ double wa_rcp<double>(double v) { return 1.0 / v; }
 
 // Block-wide reductions for kBlock = 256 threads (4 waves); all threads get the result.
 // `red` is a __shared__ scratch of >= 4 elements; the leading barrier makes reuse safe.
@@ -66,12 +134,47 @@ template <typename T> __device__ __forceinline__ T block_min(T v, T *red) {
     return min(min(red[0], red[1]), min(red[2], red[3]));
 }
 
+// N block-wide reductions at once (one pair of barriers), each with the same tree as
+// block_sum / block_max: xor butterfly in the wave, then (w0 op w1) op (w2 op w3).  `red`
+// holds >= 4 * N elements; every thread gets the results in v.
+template <int N, typename T> __device__ __forceinline__ void block_sum_n(T (&v)[N], T *red) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = group_sum<64>(v[j]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) red[(threadIdx.x >> 6) * N + j] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = (red[j] + red[N + j]) + (red[2 * N + j] + red[3 * N + j]);
+}
+template <int N, typename T> __device__ __forceinline__ void block_max_n(T (&v)[N], T *red) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = group_max<64>(v[j]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) red[(threadIdx.x >> 6) * N + j] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        v[j] = max(max(red[j], red[N + j]), max(red[2 * N + j], red[3 * N + j]));
+}
+
 // Fixed-order sums of n per-block partials by one block: thread t sums t, t+256, ... (the
 // thread_* part), then the block tree.
 template <typename T> __device__ __forceinline__ T thread_sum(const T *p, int n) {
     T s = 0;
     int i = threadIdx.x;
-    for (; i + 3 * kBlock < n; i += 4 * kBlock) {  // four independent loads in flight
+    for (; i + 7 * kBlock < n; i += 8 * kBlock) {  // eight independent loads in flight
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = p[i + u * kBlock];
+        s += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    for (; i + 3 * kBlock < n; i += 4 * kBlock) {
         const T a = p[i], b = p[i + kBlock], c = p[i + 2 * kBlock], d = p[i + 3 * kBlock];
         s += (a + b) + (c + d);
     }
@@ -103,7 +206,7 @@ __device__ __forceinline__ double precond(const T *cs, int n, int i, double lam)
 
 // The step's three reductions for the block's cells (cell i = blockIdx.x * 256 + threadIdx.x,
 // gradient (g0, g1) of cell i, valid when `live`): |v - v_prev|^2, |g~ - g~_prev|^2 and
-// max|g~| with g~ = g / P, stored as the block's partials.  Both the step kernels and the
+// max|g~| with g~ = g / P, stored as the block's partials.  `red` holds >= 12 doubles.  Both the step kernels and the
 // fused cell-gradient pass call this, so their partials are identical.
 template <typename T>
 __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, const SlotLayout &L,
@@ -125,14 +228,23 @@ __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, c
         dg = bx * bx + by * by;
         gm = fmax(fabs(gx), fabs(gy));
     }
-    dv = block_sum(dv, red);
-    dg = block_sum(dg, red);
-    gm = block_max(gm, red);
+    // one pair of barriers for the three (trees as in block_sum / block_max)
+    dv = group_sum<64>(dv);
+    dg = group_sum<64>(dg);
+    gm = group_max<64>(gm);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        red[w] = dv;
+        red[4 + w] = dg;
+        red[8 + w] = gm;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double *part = reinterpret_cast<double *>(base + L.part);
-        part[PART_DV * L.pstride + blockIdx.x] = dv;
-        part[PART_DG * L.pstride + blockIdx.x] = dg;
-        part[PART_GMAX * L.pstride + blockIdx.x] = gm;
+        part[PART_DV * L.pstride + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        part[PART_DG * L.pstride + blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+        part[PART_GMAX * L.pstride + blockIdx.x] = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
     }
 }
 

@@ -12,6 +12,7 @@ constexpr int kMaxBuckets = 8;
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
 constexpr int kChunk = 2048;     // cells per accumulation block of the binned scatter
 constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
+constexpr int kNetsPerLane = 2;  // nets each lane group sweeps (their loads issued together)
 
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };
@@ -19,7 +20,8 @@ template <> struct V2<double> { using type = double2; };
 template <typename T> using vec2 = typename V2<T>::type;
 
 // Degree buckets of the net sweep: nets with 2..64 pins are processed by a group of G
-// lanes (G = next power of two >= degree), larger ones by a whole block.
+// lanes (G = next power of two >= degree; kNetsPerLane nets per group), larger ones by a
+// whole block.
 struct Buckets {
     int32_t n;
     int32_t G[kMaxBuckets];      // group size, or 0 for block-per-net
@@ -27,6 +29,7 @@ struct Buckets {
     int32_t net1[kMaxBuckets];
     int32_t blk0[kMaxBuckets];   // first block; every bucket has a multiple of 8 blocks
     int32_t nblk[kMaxBuckets];
+    int32_t pin0[kMaxBuckets];   // group buckets: first pin slot (G slots per net, padded)
     int32_t total_blocks;
 };
 
@@ -81,6 +84,7 @@ struct SlotLayout {
     size_t tile, sorted;  // int32 [n_mov]: each cell's tile, cells in tile order
     size_t scnt, soff;    // int32 [sort_blocks][ntiles] histograms; their column offsets
     size_t tstart, cstart;// int32 [ntiles + 1]: tile cell ranges, tile chunk ranges
+    size_t chunk;         // int4 [max_chunks]: each chunk's (tile, first, end) in the order
     size_t wins;          // int64 [max_chunks][win_side^2] per-chunk charge windows
     size_t pstride;       // doubles per reduction in `part` (max blocks of any reduction)
     size_t total;
@@ -142,18 +146,21 @@ void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
     } while (0)
 
 // ---- launchers (each returns hipError_t of the launch) -----------------------------------
+// First launch of an evaluation (WA sweep of v, charge accumulation or the counting pass of a
+// regroup, and the HPWL sweep of u for the slots in hpwl_mask, bit i = slot i of the launch).
 template <typename T>
-hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
-                           const SlotLayout &L, double inv_gamma, hipStream_t st);
+hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
+                             const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
+                             bool regroup, hipStream_t st);
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st);
-// The binned charge scatter; `regroup` rebuilds the cells' tile order from the current
-// positions first (otherwise the last order is reused: exact, cells that left their window
-// take the atomic path).
+// Scan, place and accumulate of a regroup whose counting pass the first launch ran.
 template <typename T>
-hipError_t launch_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool regroup,
-                          hipStream_t st);
+hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                               hipStream_t st);
+size_t scatter_count_lds(const NetDev &nd);
+size_t scatter_accum_lds(const NetDev &nd);
 hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             hipStream_t st);
 template <typename T>

@@ -70,28 +70,72 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
     const int i = blockIdx.x * kBlock + threadIdx.x;
     T gwx = 0, gwy = 0, gdx = 0, gdy = 0;
     if (i < nd.n_mov) {
+        // Loads are issued in dependency rounds, each round's loads all in flight before any
+        // of them is used: (1) the cell's pin range, position and charge constants; (2) the
+        // field at its charge footprint (a fixed 3 x 4 bin window on clamped in-footprint
+        // indices) and its first pin indices; (3) the pin gradients.  Sums keep pin order and
+        // row-major bin order.
         const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
+        const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
         const int e = nd.cell_pin_start[i + 1];
-        for (int j = nd.cell_pin_start[i]; j < e; ++j) {
+        int j = nd.cell_pin_start[i];
+        const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+        const long long rq = nd.rq[i];
+        const RectQ q = cell_rect(nd, (double)p.x, (double)p.y, nd.cq[i]);
+        const bool has = q.r > q.l && q.t > q.b;
+        const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
+        const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
+        constexpr int KR = 3, JC = 4;
+        const bool small = has && k1 - k0 < KR && j1 - j0 < JC;
+        vec2<T> f[KR][JC];
+        if (small) {
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk)
+#pragma unroll
+                for (int jj = 0; jj < JC; ++jj)
+                    f[kk][jj] = exy[(size_t)min(k0 + kk, k1) * nd.mx + min(j0 + jj, j1)];
+        }
+        for (; j + 4 <= e; j += 4) {  // four gathers in flight, summed in pin order
+            const int p0 = nd.cell_pins[j], p1 = nd.cell_pins[j + 1];
+            const int p2 = nd.cell_pins[j + 2], p3 = nd.cell_pins[j + 3];
+            const vec2<T> g0 = pg[p0], g1 = pg[p1], g2 = pg[p2], g3 = pg[p3];
+            gwx += g0.x;
+            gwy += g0.y;
+            gwx += g1.x;
+            gwy += g1.y;
+            gwx += g2.x;
+            gwy += g2.y;
+            gwx += g3.x;
+            gwy += g3.y;
+        }
+        for (; j < e; ++j) {
             const vec2<T> g = pg[nd.cell_pins[j]];
             gwx += g.x;
             gwy += g.y;
         }
-        const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-        const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
-        const RectQ q = cell_rect(nd, (double)p.x, (double)p.y, nd.cq[i]);
-        if (q.r > q.l && q.t > q.b) {
-            const long long rq = nd.rq[i];
-            const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
-            const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
+        if (small) {
+#pragma unroll
+            for (int kk = 0; kk < KR; ++kk) {
+                if (k0 + kk > k1) continue;
+                const long long oy = overlap(q.b, q.t, k0 + kk, nd.hq);
+#pragma unroll
+                for (int jj = 0; jj < JC; ++jj) {
+                    if (j0 + jj > j1) continue;
+                    const long long ox = overlap(q.l, q.r, j0 + jj, nd.bq);
+                    const T qq = (T)((double)(rq * ox * oy) * 0x1p-40);
+                    gdx -= qq * f[kk][jj].x;
+                    gdy -= qq * f[kk][jj].y;
+                }
+            }
+        } else if (has) {  // footprints wider than the window: plain loop
             for (int k = k0; k <= k1; ++k) {
                 const long long oy = overlap(q.b, q.t, k, nd.hq);
-                for (int j = j0; j <= j1; ++j) {
-                    const long long ox = overlap(q.l, q.r, j, nd.bq);
+                for (int jx = j0; jx <= j1; ++jx) {
+                    const long long ox = overlap(q.l, q.r, jx, nd.bq);
                     const T qq = (T)((double)(rq * ox * oy) * 0x1p-40);
-                    const vec2<T> e = exy[(size_t)k * nd.mx + j];
-                    gdx -= qq * e.x;
-                    gdy -= qq * e.y;
+                    const vec2<T> ev = exy[(size_t)k * nd.mx + jx];
+                    gdx -= qq * ev.x;
+                    gdy -= qq * ev.y;
                 }
             }
         }
@@ -106,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             g[nd.n_mov + i] = g1;
         }
         // the following step's reductions, from the gradient just formed
-        __shared__ double red[4];
+        __shared__ double red[4 * 3];
         step_block_norms<T>(nd, base, L, i, i < nd.n_mov, g0, g1, lam_step, red);
     } else {
         T *gd = reinterpret_cast<T *>(base + L.gd);
@@ -116,13 +160,13 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             gd[i] = gdx;
             gd[nd.n_mov + i] = gdy;
         }
-        __shared__ double red[4];
-        const double n1 = block_sum((double)(fabs(gwx) + fabs(gwy)), red);
-        const double n2 = block_sum((double)(fabs(gdx) + fabs(gdy)), red);
+        __shared__ double red[4 * 2];
+        double n[2] = {(double)(fabs(gwx) + fabs(gwy)), (double)(fabs(gdx) + fabs(gdy))};
+        block_sum_n<2>(n, red);
         if (threadIdx.x == 0) {
             double *part = reinterpret_cast<double *>(base + L.part);
-            part[PART_N1 * L.pstride + blockIdx.x] = n1;
-            part[PART_N2 * L.pstride + blockIdx.x] = n2;
+            part[PART_N1 * L.pstride + blockIdx.x] = n[0];
+            part[PART_N2 * L.pstride + blockIdx.x] = n[1];
         }
     }
 }

@@ -20,17 +20,40 @@ __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs
     const double *part = reinterpret_cast<const double *>(base + L.part);
     const bool init = !use_fixed && sc->lambda_valid == 0;
     const bool prop = !init && ncell > 0;
-    // every reduction's loads first, then one block tree for all of them (the same trees as
-    // block_sum / block_max, so the totals equal separate reductions bit for bit)
-    double v[4];
-    v[0] = thread_sum(part + PART_WL * L.pstride, nwl);
-    v[1] = thread_sum(part + PART_E * L.pstride, ne);
-    v[2] = init ? thread_sum(part + PART_N1 * L.pstride, ncell)
-                : (prop ? thread_sum(part + PART_DV * L.pstride, ncell) : 0.0);
-    v[3] = init ? thread_sum(part + PART_N2 * L.pstride, ncell)
-                : (prop ? thread_sum(part + PART_DG * L.pstride, ncell) : 0.0);
-    double gm = prop ? thread_max(part + PART_GMAX * L.pstride, ncell) : 0.0;
-    long long ov = thread_sum(reinterpret_cast<const long long *>(part) + PART_OVF * L.pstride, nov);
+    // One pass over all partial arrays with their loads in flight together (thread t takes
+    // elements t, t + 256, ... of each, in order), then one block tree for all totals (the
+    // trees of block_sum / block_max).
+    const double *pw = part + PART_WL * L.pstride, *pe = part + PART_E * L.pstride;
+    const double *pa = part + (init ? PART_N1 : PART_DV) * L.pstride;
+    const double *pb = part + (init ? PART_N2 : PART_DG) * L.pstride;
+    const double *pg = part + PART_GMAX * L.pstride;
+    const long long *po = reinterpret_cast<const long long *>(part) + PART_OVF * L.pstride;
+    const int nab = (init || prop) ? ncell : 0, ng = prop ? ncell : 0;
+    const int nmax = max(max(nwl, ne), max(nov, nab));
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double gm = 0.0;
+    long long ov = 0;
+    for (int i = threadIdx.x; i < nmax; i += 4 * kBlock) {
+        double a[4][5];
+        long long o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = i + u * kBlock;
+            a[u][0] = j < nwl ? pw[j] : 0.0;
+            a[u][1] = j < ne ? pe[j] : 0.0;
+            a[u][2] = j < nab ? pa[j] : 0.0;
+            a[u][3] = j < nab ? pb[j] : 0.0;
+            a[u][4] = j < ng ? pg[j] : 0.0;
+            o[u] = j < nov ? po[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] += a[u][k];
+            gm = fmax(gm, a[u][4]);
+            ov += o[u];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] = group_sum<64>(v[j]);
     gm = group_max<64>(gm);
@@ -108,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(NetDev nd, SlotArgs sa,
 // second step on one gradient): per block |v - v_prev|^2, |g~ - g~_prev|^2, max|g~|.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
-    __shared__ double red[4];
+    __shared__ double red[4 * 3];
     char *base = sa.base[blockIdx.y];
     const Scalars *sc = scalars(base, L);
     const int n = nd.n_mov;

@@ -2,14 +2,16 @@
 // gradient, and the exact HPWL of Eq. 1.
 //
 // Nets are grouped at load time by degree.  A net with d <= 64 pins is handled by an aligned
-// group of G = nextpow2(d) lanes, one pin per lane: the pin loads of a wave are contiguous
-// (coalesced), the cell-position loads (one interleaved (x, y) pair per pin) are the only
-// gathers, and the max/min/exp-sum reductions are xor butterflies inside the group.  A larger
-// net gets a whole block and streams its pins three times (max/min, exp sums, gradients); the
-// repeats hit L2.  Within a bucket nets are ordered by their lowest cell, and the blocks of
-// each bucket are remapped so that every XCD walks one contiguous eighth of it: neighbouring
-// lanes then gather neighbouring cells, and each XCD's gathers stay in a compact cell range.
-#include "hp_device.h"
+// group of G = nextpow2(d) lanes, one pin per lane, in a padded layout (G pin slots per net)
+// so that a lane finds its pin without reading the net's start: the pin loads of a wave are
+// contiguous (coalesced), the cell-position loads (one interleaved (x, y) pair per pin) are
+// the only gathers, and the max/min/exp-sum reductions are xor butterflies inside the group.
+// A larger net gets a whole block, which stages up to 2048 of its pin coordinates in LDS for
+// its three passes (max/min, exp sums, gradients).  Within a bucket nets are ordered by their
+// lowest cell, and the blocks of each bucket are remapped so that every XCD walks one
+// contiguous eighth of it: neighbouring lanes then gather neighbouring cells, and each XCD's
+// gathers stay in a compact cell range.
+#include "hp_binning.h"
 
 namespace hp {
 
@@ -20,102 +22,153 @@ namespace hp {
 //   r+ = sum (x_i - m+) a+_i / sum a+_i,  r- = sum (x_i - m-) a-_i / sum a-_i
 //   WL = (m+ - m-) + r+ - r-                                          (Eq. 3, rescaled)
 //   dWL/dx_i = a+_i/b+ (1 + (x_i - m+ - r+)/gamma) - a-_i/b- (1 - (x_i - m- - r-)/gamma)
+// Group buckets: nets of the bucket are laid out padded (net j owns pin slots pin0 + j G ...,
+// padding lanes hold cell -1), so a lane's pin slot follows from its index: one round of
+// loads (cell index, offset) and one of gathers (position).  A block takes R = kNetsPerLane
+// consecutive runs of 256 / G nets; every lane issues the loads of its R nets before using any.
 template <typename T, int G>
-__device__ __forceinline__ void wa_groups(const NetDev &nd, int net0, int net1, int local,
+__device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, int b, int local,
                                           const vec2<T> *__restrict__ pos, T invg,
                                           vec2<T> *__restrict__ pg, double &wl) {
-    constexpr int NPB = kBlock / G;
+    constexpr int NPB = kBlock / G, R = kNetsPerLane;
     const int lane = threadIdx.x & (G - 1);
-    const int net = net0 + local * NPB + (int)threadIdx.x / G;
-    const bool vnet = net < net1;
-    int s = 0, d = 0;
-    if (vnet) {
-        s = nd.net_start[net];
-        d = nd.net_start[net + 1] - s;
+    const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
+    const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
+    // all loads issued on clamped in-range indices before any use: a net past the bucket's end
+    // reads the bucket's first slot, a padding lane's cell -1 reads cell 0; both are ignored
+    int net[R], p[R], c[R];
+    vec2<T> o[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        net[r] = net0 + (local * R + r) * NPB + (int)threadIdx.x / G;
+        p[r] = net[r] < net1 ? pin0 + (net[r] - net0) * G + lane : pin0;
+        c[r] = nd.pin_cell[p[r]];
+        o[r] = off[p[r]];
     }
-    const bool act = lane < d;
-    const int p = s + lane;
-    T px = 0, py = 0;
-    if (act) {
-        const int c = nd.pin_cell[p];
-        const vec2<T> o = reinterpret_cast<const vec2<T> *>(nd.pin_off)[p];
-        const vec2<T> q = pos[c];
-        px = q.x + o.x;
-        py = q.y + o.y;
+    vec2<T> q[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) q[r] = pos[max(c[r], 0)];
+    T px[R], py[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (net[r] >= net1) c[r] = -1;
+        px[r] = c[r] >= 0 ? q[r].x + o[r].x : T(0);
+        py[r] = c[r] >= 0 ? q[r].y + o[r].y : T(0);
     }
     const T inf = pos_inf<T>();
-    const T xmax = group_max<G>(act ? px : -inf), xmin = group_min<G>(act ? px : inf);
-    const T ymax = group_max<G>(act ? py : -inf), ymin = group_min<G>(act ? py : inf);
-    const T dxp = act ? px - xmax : T(0), dxm = act ? px - xmin : T(0);
-    const T dyp = act ? py - ymax : T(0), dym = act ? py - ymin : T(0);
-    const T axp = act ? dev_exp<T>(dxp * invg) : T(0), axm = act ? dev_exp<T>(-dxm * invg) : T(0);
-    const T ayp = act ? dev_exp<T>(dyp * invg) : T(0), aym = act ? dev_exp<T>(-dym * invg) : T(0);
-    const T bxp = group_sum<G>(axp), bxm = group_sum<G>(axm);
-    const T byp = group_sum<G>(ayp), bym = group_sum<G>(aym);
-    const T rxp = group_sum<G>(dxp * axp) / bxp, rxm = group_sum<G>(dxm * axm) / bxm;
-    const T ryp = group_sum<G>(dyp * ayp) / byp, rym = group_sum<G>(dym * aym) / bym;
-    const T w = (vnet && nd.net_w) ? reinterpret_cast<const T *>(nd.net_w)[net] : T(1);
-    if (act) {
-        const T gx = axp / bxp * (T(1) + (dxp - rxp) * invg) - axm / bxm * (T(1) - (dxm - rxm) * invg);
-        const T gy = ayp / byp * (T(1) + (dyp - ryp) * invg) - aym / bym * (T(1) - (dym - rym) * invg);
-        vec2<T> o;
-        o.x = w * gx;
-        o.y = w * gy;
-        pg[p] = o;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool act = c[r] >= 0, vnet = net[r] < net1;
+        const T xmax = group_max<G>(act ? px[r] : -inf), xmin = group_min<G>(act ? px[r] : inf);
+        const T ymax = group_max<G>(act ? py[r] : -inf), ymin = group_min<G>(act ? py[r] : inf);
+        const T dxp = act ? px[r] - xmax : T(0), dxm = act ? px[r] - xmin : T(0);
+        const T dyp = act ? py[r] - ymax : T(0), dym = act ? py[r] - ymin : T(0);
+        const T axp = act ? wa_exp<T>(dxp * invg) : T(0), axm = act ? wa_exp<T>(-dxm * invg) : T(0);
+        const T ayp = act ? wa_exp<T>(dyp * invg) : T(0), aym = act ? wa_exp<T>(-dym * invg) : T(0);
+        // b >= 1 for a real net (its extreme pin contributes exp(0)); padding-only groups are
+        // never written or counted
+        const T ibxp = wa_rcp<T>(group_sum<G>(axp)), ibxm = wa_rcp<T>(group_sum<G>(axm));
+        const T ibyp = wa_rcp<T>(group_sum<G>(ayp)), ibym = wa_rcp<T>(group_sum<G>(aym));
+        const T rxp = group_sum<G>(dxp * axp) * ibxp, rxm = group_sum<G>(dxm * axm) * ibxm;
+        const T ryp = group_sum<G>(dyp * ayp) * ibyp, rym = group_sum<G>(dym * aym) * ibym;
+        const T w = (vnet && nd.net_w) ? reinterpret_cast<const T *>(nd.net_w)[net[r]] : T(1);
+        if (act) {
+            const T gx = axp * ibxp * (T(1) + (dxp - rxp) * invg) - axm * ibxm * (T(1) - (dxm - rxm) * invg);
+            const T gy = ayp * ibyp * (T(1) + (dyp - ryp) * invg) - aym * ibym * (T(1) - (dym - rym) * invg);
+            pg[p[r]] = cmk2<T>(w * gx, w * gy);
+        }
+        if (vnet && lane == 0)
+            wl += (double)(w * (((xmax - xmin) + (rxp - rxm)) + ((ymax - ymin) + (ryp - rym))));
     }
-    wl = (vnet && lane == 0)
-             ? (double)(w * (((xmax - xmin) + (rxp - rxm)) + ((ymax - ymin) + (ryp - rym))))
-             : 0.0;
+}
+
+// Block-per-net sweep.  The first kNetRegs * kBlock pins of the net are loaded once, with all
+// of a thread's cell-index loads in flight together and then all its position loads, and kept
+// in LDS for the three passes (each thread reads back only its own pins, so no barrier); pins
+// beyond that (nets over 2048 pins) are re-streamed in each pass.  Per-thread sums run in pin
+// order and the block trees are those of block_sum / block_max.
+constexpr int kNetRegs = 8;
+
+template <typename T>
+__device__ __forceinline__ void net_pins_to_lds(const NetDev &nd, int s, int d,
+                                                const vec2<T> *__restrict__ pos, vec2<T> *sp) {
+    // Every load is issued unconditionally on a clamped in-range index and used only after all
+    // are in flight (a load whose use sits inside its own branch would be waited for there).
+    const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
+    int c[kNetRegs];
+    vec2<T> o[kNetRegs];
+#pragma unroll
+    for (int k = 0; k < kNetRegs; ++k) {
+        const int i = min((int)threadIdx.x + k * kBlock, d - 1);
+        c[k] = nd.pin_cell[s + i];
+        o[k] = off[s + i];
+    }
+    vec2<T> q[kNetRegs];
+#pragma unroll
+    for (int k = 0; k < kNetRegs; ++k) q[k] = pos[c[k]];
+#pragma unroll
+    for (int k = 0; k < kNetRegs; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        if (i < d) sp[i] = cmk2<T>(q[k].x + o[k].x, q[k].y + o[k].y);
+    }
 }
 
 template <typename T>
 __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ pos, T invg,
                          vec2<T> *__restrict__ pg, double &wl) {
-    __shared__ T red[4];
+    __shared__ T red[4 * 8];
+    __shared__ vec2<T> sp[kNetRegs * kBlock];
     const int s = nd.net_start[net], d = nd.net_start[net + 1] - s;
     const T inf = pos_inf<T>();
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
-    T lxM = -inf, lxm = inf, lyM = -inf, lym = inf;
-    for (int i = threadIdx.x; i < d; i += kBlock) {
+    net_pins_to_lds<T>(nd, s, d, pos, sp);
+    const int dr = min(d, kNetRegs * kBlock);  // pins held in LDS
+    auto pin = [&](int i) -> vec2<T> {
+        if (i < dr) return sp[i];
         const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
-        const T px = q.x + o.x, py = q.y + o.y;
-        lxM = max(lxM, px);
-        lxm = min(lxm, px);
-        lyM = max(lyM, py);
-        lym = min(lym, py);
-    }
-    const T xmax = block_max(lxM, red), xmin = block_min(lxm, red);
-    const T ymax = block_max(lyM, red), ymin = block_min(lym, red);
-    T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
+        return cmk2<T>(q.x + o.x, q.y + o.y);
+    };
+    // pass 1: extents (max x, -min x, max y, -min y)
+    T m[4] = {-inf, -inf, -inf, -inf};
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
-        const T px = q.x + o.x, py = q.y + o.y;
-        const T dxp = px - xmax, dxm = px - xmin, dyp = py - ymax, dym = py - ymin;
-        const T axp = dev_exp<T>(dxp * invg), axm = dev_exp<T>(-dxm * invg);
-        const T ayp = dev_exp<T>(dyp * invg), aym = dev_exp<T>(-dym * invg);
-        s0 += axp;
-        s1 += axm;
-        s2 += ayp;
-        s3 += aym;
-        s4 += dxp * axp;
-        s5 += dxm * axm;
-        s6 += dyp * ayp;
-        s7 += dym * aym;
+        const vec2<T> p = pin(i);
+        m[0] = max(m[0], p.x);
+        m[1] = max(m[1], -p.x);
+        m[2] = max(m[2], p.y);
+        m[3] = max(m[3], -p.y);
     }
-    const T bxp = block_sum(s0, red), bxm = block_sum(s1, red);
-    const T byp = block_sum(s2, red), bym = block_sum(s3, red);
-    const T rxp = block_sum(s4, red) / bxp, rxm = block_sum(s5, red) / bxm;
-    const T ryp = block_sum(s6, red) / byp, rym = block_sum(s7, red) / bym;
+    block_max_n<4>(m, red);
+    const T xmax = m[0], xmin = -m[1], ymax = m[2], ymin = -m[3];
+    // pass 2: exponential sums
+    T sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < d; i += kBlock) {
+        const vec2<T> p = pin(i);
+        const T dxp = p.x - xmax, dxm = p.x - xmin, dyp = p.y - ymax, dym = p.y - ymin;
+        const T axp = wa_exp<T>(dxp * invg), axm = wa_exp<T>(-dxm * invg);
+        const T ayp = wa_exp<T>(dyp * invg), aym = wa_exp<T>(-dym * invg);
+        sm[0] += axp;
+        sm[1] += axm;
+        sm[2] += ayp;
+        sm[3] += aym;
+        sm[4] += dxp * axp;
+        sm[5] += dxm * axm;
+        sm[6] += dyp * ayp;
+        sm[7] += dym * aym;
+    }
+    block_sum_n<8>(sm, red);
+    const T ibxp = wa_rcp<T>(sm[0]), ibxm = wa_rcp<T>(sm[1]);
+    const T ibyp = wa_rcp<T>(sm[2]), ibym = wa_rcp<T>(sm[3]);
+    const T rxp = sm[4] * ibxp, rxm = sm[5] * ibxm, ryp = sm[6] * ibyp, rym = sm[7] * ibym;
     const T w = nd.net_w ? reinterpret_cast<const T *>(nd.net_w)[net] : T(1);
+    // pass 3: per-pin gradients
     for (int i = threadIdx.x; i < d; i += kBlock) {
-        const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
-        const T px = q.x + o.x, py = q.y + o.y;
-        const T dxp = px - xmax, dxm = px - xmin, dyp = py - ymax, dym = py - ymin;
-        const T axp = dev_exp<T>(dxp * invg), axm = dev_exp<T>(-dxm * invg);
-        const T ayp = dev_exp<T>(dyp * invg), aym = dev_exp<T>(-dym * invg);
+        const vec2<T> p = pin(i);
+        const T dxp = p.x - xmax, dxm = p.x - xmin, dyp = p.y - ymax, dym = p.y - ymin;
+        const T axp = wa_exp<T>(dxp * invg), axm = wa_exp<T>(-dxm * invg);
+        const T ayp = wa_exp<T>(dyp * invg), aym = wa_exp<T>(-dym * invg);
         vec2<T> g;
-        g.x = w * (axp / bxp * (T(1) + (dxp - rxp) * invg) - axm / bxm * (T(1) - (dxm - rxm) * invg));
-        g.y = w * (ayp / byp * (T(1) + (dyp - ryp) * invg) - aym / bym * (T(1) - (dym - rym) * invg));
+        g.x = w * (axp * ibxp * (T(1) + (dxp - rxp) * invg) - axm * ibxm * (T(1) - (dxm - rxm) * invg));
+        g.y = w * (ayp * ibyp * (T(1) + (dyp - ryp) * invg) - aym * ibym * (T(1) - (dym - rym) * invg));
         pg[s + i] = g;
     }
     wl = threadIdx.x == 0
@@ -126,73 +179,104 @@ __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ 
 // ---- exact HPWL ----------------------------------------------------------------------------
 // Pin coordinate q16(cell) + q16(offset), both exact integers; per net the x and y extents.
 template <typename T, int G>
-__device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, int net0, int net1, int local,
+__device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, const Buckets &bk, int b, int local,
                                                const vec2<T> *__restrict__ pos) {
-    constexpr int NPB = kBlock / G;
+    constexpr int NPB = kBlock / G, R = kNetsPerLane;
     const int lane = threadIdx.x & (G - 1);
-    const int net = net0 + local * NPB + (int)threadIdx.x / G;
-    int s = 0, d = 0;
-    if (net < net1) {
-        s = nd.net_start[net];
-        d = nd.net_start[net + 1] - s;
+    const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
+    int p[R], c[R];
+    int2 o[R];
+    bool vn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {  // loads on clamped indices first (see wa_groups)
+        const int net = net0 + (local * R + r) * NPB + (int)threadIdx.x / G;
+        vn[r] = net < net1;
+        p[r] = vn[r] ? pin0 + (net - net0) * G + lane : pin0;
+        c[r] = nd.pin_cell[p[r]];
+        o[r] = nd.pin_offq[p[r]];
     }
-    const bool act = lane < d;
-    long long px = 0, py = 0;
-    if (act) {
-        const vec2<T> q = pos[nd.pin_cell[s + lane]];
-        const int2 o = nd.pin_offq[s + lane];
-        px = q16((double)q.x) + o.x;
-        py = q16((double)q.y) + o.y;
+    vec2<T> q[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) q[r] = pos[max(c[r], 0)];
+    int px[R], py[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!vn[r]) c[r] = -1;
+        px[r] = c[r] >= 0 ? q16i<T>(q[r].x) + o[r].x : 0;
+        py[r] = c[r] >= 0 ? q16i<T>(q[r].y) + o[r].y : 0;
     }
-    const long long big = 0x3fffffffffffffffLL;
-    const long long xM = group_max<G>(act ? px : -big), xm = group_min<G>(act ? px : big);
-    const long long yM = group_max<G>(act ? py : -big), ym = group_min<G>(act ? py : big);
-    return (act && lane == 0) ? (int64_t)((xM - xm) + (yM - ym)) : 0;
+    int64_t h = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool act = c[r] >= 0;
+        const int xM = group_max<G>(act ? px[r] : INT_MIN), xm = group_min<G>(act ? px[r] : INT_MAX);
+        const int yM = group_max<G>(act ? py[r] : INT_MIN), ym = group_min<G>(act ? py[r] : INT_MAX);
+        if (act && lane == 0) h += ((int64_t)xM - xm) + ((int64_t)yM - ym);
+    }
+    return h;
 }
 
 template <typename T>
 __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restrict__ pos) {
-    __shared__ long long red[4];
+    __shared__ int red[4 * 4];
     const int s = nd.net_start[net], d = nd.net_start[net + 1] - s;
-    const long long big = 0x3fffffffffffffffLL;
-    long long xM = -big, xm = big, yM = -big, ym = big;
-    for (int i = threadIdx.x; i < d; i += kBlock) {
-        const vec2<T> q = pos[nd.pin_cell[s + i]];
+    int m[4] = {-INT_MAX, -INT_MAX, -INT_MAX, -INT_MAX};  // max x, -min x, max y, -min y
+    auto ext = [&](int i, int c) {
+        const vec2<T> q = pos[c];
         const int2 o = nd.pin_offq[s + i];
-        const long long px = q16((double)q.x) + o.x, py = q16((double)q.y) + o.y;
-        xM = max(xM, px);
-        xm = min(xm, px);
-        yM = max(yM, py);
-        ym = min(ym, py);
+        const int px = q16i<T>(q.x) + o.x, py = q16i<T>(q.y) + o.y;
+        m[0] = max(m[0], px);
+        m[1] = max(m[1], -px);
+        m[2] = max(m[2], py);
+        m[3] = max(m[3], -py);
+    };
+    // the first kNetRegs pins per thread: all loads in flight (clamped indices), then used
+    int c[kNetRegs];
+    int2 o[kNetRegs];
+#pragma unroll
+    for (int k = 0; k < kNetRegs; ++k) {
+        const int i = min((int)threadIdx.x + k * kBlock, d - 1);
+        c[k] = nd.pin_cell[s + i];
+        o[k] = nd.pin_offq[s + i];
     }
-    xM = block_max(xM, red);
-    xm = block_min(xm, red);
-    yM = block_max(yM, red);
-    ym = block_min(ym, red);
-    return threadIdx.x == 0 ? (int64_t)((xM - xm) + (yM - ym)) : 0;
+    vec2<T> q[kNetRegs];
+#pragma unroll
+    for (int k = 0; k < kNetRegs; ++k) q[k] = pos[c[k]];
+#pragma unroll
+    for (int k = 0; k < kNetRegs; ++k) {
+        if ((int)threadIdx.x + k * kBlock >= d) continue;
+        const int px = q16i<T>(q[k].x) + o[k].x, py = q16i<T>(q[k].y) + o[k].y;
+        m[0] = max(m[0], px);
+        m[1] = max(m[1], -px);
+        m[2] = max(m[2], py);
+        m[3] = max(m[3], -py);
+    }
+    for (int i = threadIdx.x + kNetRegs * kBlock; i < d; i += kBlock) ext(i, nd.pin_cell[s + i]);
+    block_max_n<4>(m, red);
+    return threadIdx.x == 0 ? ((int64_t)m[0] + m[1]) + ((int64_t)m[2] + m[3]) : 0;
 }
 
 enum { MODE_WA = 0, MODE_HPWL = 1 };
 
+// Block `bx` (0 <= bx < bk.total_blocks) of a sweep of one slot: WA over v, or HPWL over u.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(NetDev nd, Buckets bk, SlotArgs sa,
-                                                       SlotLayout L, T invg) {
-    char *base = sa.base[blockIdx.y];
+__device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, char *base,
+                                           const SlotLayout &L, T invg, int bx) {
     int b = 0;
-    while (b + 1 < bk.n && (int)blockIdx.x >= bk.blk0[b + 1]) ++b;
-    const int local = xcd_remap((int)blockIdx.x - bk.blk0[b], bk.nblk[b]);
+    while (b + 1 < bk.n && bx >= bk.blk0[b + 1]) ++b;
+    const int local = xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
     const int net0 = bk.net0[b], net1 = bk.net1[b];
     const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + (MODE == MODE_WA ? L.v : L.u));
     if constexpr (MODE == MODE_WA) {
         vec2<T> *pg = reinterpret_cast<vec2<T> *>(base + L.pin_grad);
         double wl = 0.0;
         switch (bk.G[b]) {
-            case 2: wa_groups<T, 2>(nd, net0, net1, local, pos, invg, pg, wl); break;
-            case 4: wa_groups<T, 4>(nd, net0, net1, local, pos, invg, pg, wl); break;
-            case 8: wa_groups<T, 8>(nd, net0, net1, local, pos, invg, pg, wl); break;
-            case 16: wa_groups<T, 16>(nd, net0, net1, local, pos, invg, pg, wl); break;
-            case 32: wa_groups<T, 32>(nd, net0, net1, local, pos, invg, pg, wl); break;
-            case 64: wa_groups<T, 64>(nd, net0, net1, local, pos, invg, pg, wl); break;
+            case 2: wa_groups<T, 2>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 4: wa_groups<T, 4>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 8: wa_groups<T, 8>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 16: wa_groups<T, 16>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 32: wa_groups<T, 32>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 64: wa_groups<T, 64>(nd, bk, b, local, pos, invg, pg, wl); break;
             default:
                 if (net0 + local < net1) wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
                 break;
@@ -200,16 +284,16 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(NetDev nd, Buckets bk, Sl
         __shared__ double red[4];
         const double tot = block_sum(wl, red);
         if (threadIdx.x == 0)
-            reinterpret_cast<double *>(base + L.part)[PART_WL * L.pstride + blockIdx.x] = tot;
+            reinterpret_cast<double *>(base + L.part)[PART_WL * L.pstride + bx] = tot;
     } else {
         int64_t h = 0;
         switch (bk.G[b]) {
-            case 2: h = hpwl_groups<T, 2>(nd, net0, net1, local, pos); break;
-            case 4: h = hpwl_groups<T, 4>(nd, net0, net1, local, pos); break;
-            case 8: h = hpwl_groups<T, 8>(nd, net0, net1, local, pos); break;
-            case 16: h = hpwl_groups<T, 16>(nd, net0, net1, local, pos); break;
-            case 32: h = hpwl_groups<T, 32>(nd, net0, net1, local, pos); break;
-            case 64: h = hpwl_groups<T, 64>(nd, net0, net1, local, pos); break;
+            case 2: h = hpwl_groups<T, 2>(nd, bk, b, local, pos); break;
+            case 4: h = hpwl_groups<T, 4>(nd, bk, b, local, pos); break;
+            case 8: h = hpwl_groups<T, 8>(nd, bk, b, local, pos); break;
+            case 16: h = hpwl_groups<T, 16>(nd, bk, b, local, pos); break;
+            case 32: h = hpwl_groups<T, 32>(nd, bk, b, local, pos); break;
+            case 64: h = hpwl_groups<T, 64>(nd, bk, b, local, pos); break;
             default:
                 if (net0 + local < net1) h = hpwl_block<T>(nd, net0 + local, pos);
                 break;
@@ -217,38 +301,78 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(NetDev nd, Buckets bk, Sl
         __shared__ long long red[4];
         const long long tot = block_sum((long long)h, red);
         if (threadIdx.x == 0)
-            (reinterpret_cast<long long *>(base + L.part) + PART_HPWL * L.pstride)[blockIdx.x] = tot;
+            (reinterpret_cast<long long *>(base + L.part) + PART_HPWL * L.pstride)[bx] = tot;
+    }
+}
+
+// The HPWL sweep on its own (a pending hp_hpwl that no evaluation absorbed).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets bk, SlotArgs sa,
+                                                            SlotLayout L) {
+    sweep_body<T, MODE_HPWL>(nd, bk, sa.base[blockIdx.y], L, T(0), blockIdx.x);
+}
+
+// The first launch of an evaluation: three independent jobs in disjoint block ranges of one
+// grid, so that the net sweeps and the charge scatter fill the machine together without a
+// second stream or any cross-stream synchronisation.  Blocks are dispatched in index order,
+// so the longest-latency work comes first:
+//   [0, nsc)             the scatter: the accumulation of v's charge in the existing grouped
+//                        order, or, when the order is rebuilt (regroup), its counting pass;
+//   [nsc, nsc + nw)      the WA sweep of v (nw = the sweep's block count; its block-per-net
+//                        bucket leads);
+//   [nsc + nw, ... + nh) the HPWL sweep of u for the slots in hmask (a deferred hp_hpwl; nh is
+//                        0 or the sweep's block count).
+// nsc and nw are multiples of 8, so every range keeps the XCD striping of its own blocks.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
+                                                            SlotLayout L, T invg, int nsc,
+                                                            uint32_t hmask, int regroup) {
+    char *base = sa.base[blockIdx.y];
+    const int nw = bk.total_blocks;
+    const int bx = blockIdx.x;
+    if (bx < nsc) {
+        if (regroup)
+            count_body<T>(nd, base, L, bx);
+        else
+            accum_body<T>(nd, base, L, bx);
+    } else if (bx < nsc + nw) {
+        sweep_body<T, MODE_WA>(nd, bk, base, L, invg, bx - nsc);
+    } else if ((hmask >> blockIdx.y) & 1u) {
+        sweep_body<T, MODE_HPWL>(nd, bk, base, L, T(0), bx - nsc - nw);
     }
 }
 
 int sweep_parts(const Buckets &bk) { return bk.total_blocks; }
 
 template <typename T>
-hipError_t launch_sweep_wa(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
-                           const SlotLayout &L, double inv_gamma, hipStream_t st) {
-    dim3 grid(bk.total_blocks, sa.n);
-    HP_LAUNCH("sweep_wa", (sweep_kernel<T, MODE_WA>), grid, dim3(kBlock), 0, st, nd, bk, sa, L,
-              (T)inv_gamma);
+hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
+                             const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
+                             bool regroup, hipStream_t st) {
+    const int nh = hpwl_mask ? bk.total_blocks : 0;
+    const int nsc = ((regroup ? nd.sort_blocks : nd.max_chunks) + kXcds - 1) / kXcds * kXcds;
+    const size_t lds = regroup ? scatter_count_lds(nd) : scatter_accum_lds(nd);
+    dim3 grid(nsc + bk.total_blocks + nh, sa.n);
+    HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
+              L, (T)inv_gamma, nsc, hpwl_mask, (int)regroup);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st) {
-    dim3 grid(bk.total_blocks, sa.n);
-    HP_LAUNCH("sweep_hpwl", (sweep_kernel<T, MODE_HPWL>), grid, dim3(kBlock), 0, st, nd, bk, sa,
-              L, (T)0);
+    HP_LAUNCH("sweep_hpwl", sweep_hpwl_kernel<T>, dim3(bk.total_blocks, sa.n), dim3(kBlock), 0, st,
+              nd, bk, sa, L);
     return hipGetLastError();
 }
 
-template hipError_t launch_sweep_wa<float>(const NetDev &, const Buckets &, const SlotArgs &,
-                                           const SlotLayout &, double, hipStream_t);
-template hipError_t launch_sweep_wa<double>(const NetDev &, const Buckets &, const SlotArgs &,
-                                            const SlotLayout &, double, hipStream_t);
-template hipError_t launch_sweep_hpwl<float>(const NetDev &, const Buckets &, const SlotArgs &,
+#define HP_INST(T)                                                                             \
+    template hipError_t launch_eval_front<T>(const NetDev &, const Buckets &, const SlotArgs &, \
+                                             const SlotLayout &, double, uint32_t, bool,        \
+                                             hipStream_t);                                      \
+    template hipError_t launch_sweep_hpwl<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, hipStream_t);
-template hipError_t launch_sweep_hpwl<double>(const NetDev &, const Buckets &,
-                                              const SlotArgs &, const SlotLayout &,
-                                              hipStream_t);
+HP_INST(float)
+HP_INST(double)
+#undef HP_INST
 
 }  // namespace hp

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhybro.so")
 HP_OK, HP_EINVAL, HP_ENOMEM, HP_EDEVICE, HP_ESTATE, HP_ENOTIMPL = 0, -1, -2, -3, -4, -5
 HP_PERTURB_GAUSS, HP_PERTURB_SHUFFLE, HP_PERTURB_UNIFORM = 0, 1, 2
 HP_MAP_RHO_MOV, HP_MAP_RHO_FIXED, HP_MAP_PSI, HP_MAP_EX, HP_MAP_EY = 0, 1, 2, 3, 4
+HP_ITER_HPWL, HP_ITER_GRAPH = 1, 2
 
 
 class hp_die(C.Structure):
@@ -35,6 +36,10 @@ class hp_shape(C.Structure):
 class hp_eval_params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("lambda_", C.c_double), ("grad_mode", C.c_int32),
                 ("keep_maps", C.c_int32)]
+
+
+class hp_iter_params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("flags", C.c_int32)]
 
 
 class hp_slot_state(C.Structure):
@@ -67,6 +72,7 @@ _SIGS = {
     "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
     "hp_nesterov_step": [_P, _P, C.c_int32],
+    "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
     "hp_perturb": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P, _P],
     "hp_hpwl": [_P, _P, C.c_int32, _P, _P],
     "hp_select_best": [_P, _P, C.c_int32, C.c_int32, _P],
@@ -207,6 +213,12 @@ def hp_eval_objective_grad(ctx, slots, gamma, lam=-1.0, grad_mode=0, keep_maps=F
 def hp_nesterov_step(ctx, slots):
     a, p, n = _slots(slots)
     _chk(lib().hp_nesterov_step(ctx, p, n))
+
+
+def hp_iterate(ctx, slots, gamma, iters, flags):
+    a, p, n = _slots(slots)
+    prm = hp_iter_params(float(gamma), int(flags))
+    _chk(lib().hp_iterate(ctx, p, n, C.byref(prm), int(iters)))
 
 
 def hp_perturb(ctx, slot, mode, fraction, sigma_bins, seed, n_movable, want_idx=True):
@@ -362,6 +374,12 @@ class Placer:
             if hpwl_every and (it + 1) % hpwl_every == 0:
                 trace.append(self.hpwl(slots))
         return trace
+
+    def iterate(self, slots, gamma, iters, hpwl=True, graph=False):
+        """iters x [evaluate at v, Nesterov step, HPWL sweep] in one call (the loop runs in the
+        library; `graph` asks for HIP graph replay, which this build rejects)."""
+        flags = (HP_ITER_HPWL if hpwl else 0) | (HP_ITER_GRAPH if graph else 0)
+        hp_iterate(self.ctx, list(np.atleast_1d(slots)), gamma, iters, flags)
 
     def close(self):
         if self.ctx is not None:

@@ -170,6 +170,78 @@ def test_lambda_init_and_nesterov_steps(hy, orc, case, prec):
     pl.free_slot(s)
 
 
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
+def test_iterate_matches_single_calls(hy, orc, case, prec):
+    """hp_iterate (the iteration loop in the library) is bit-identical to the same iterations
+    issued one entry point at a time, alone and with two slots batched, across several calls
+    with host synchronisations between them."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    ref, it1, b1, b2 = (pl.new_slot() for _ in range(4))
+    for s in (ref, it1, b1, b2):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+
+    def snap(s):
+        st = pl.state(s)
+        x, y = pl.positions(s)
+        vx, vy = pl.eval_positions(s)
+        return (st["k"], st["hpwl_q"], st["lambda_"], st["a"], st["alpha"], st["wl"],
+                st["energy"], st["overflow_num"], x.tobytes(), y.tobytes(), vx.tobytes(),
+                vy.tobytes())
+
+    for chunk in (3, 9, 13, 8):
+        for _ in range(chunk):
+            pl.eval(ref, gamma, want_host=False)
+            pl.step(ref)
+            pl.hpwl(ref, want_host=False)
+        pl.iterate(it1, gamma, chunk, hpwl=True, graph=False)
+        pl.iterate([b1, b2], gamma, chunk, hpwl=True, graph=False)
+        want = snap(ref)
+        for s in (it1, b1, b2):
+            assert snap(s) == want, (chunk, s)
+    for s in (ref, it1, b1, b2):
+        pl.free_slot(s)
+
+
+@pytest.mark.skip(reason="HP_ITER_GRAPH is disabled: its first device run stalled in a later "
+                         "stream synchronisation and the cause is not established")
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
+def test_iterate_graph_matches_single_calls(hy, orc, case, prec):
+    """hp_iterate (device-side loop; steady-state blocks replayed from a captured HIP graph)
+    is bit-identical to the same iterations issued one entry point at a time, alone and with
+    two slots batched, across several calls (so the graph is replayed many times, with host
+    synchronisations and other work between the replays)."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    ref, eager, graph, b1, b2 = (pl.new_slot() for _ in range(5))
+    for s in (ref, eager, graph, b1, b2):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+
+    def snap(s):
+        st = pl.state(s)
+        x, y = pl.positions(s)
+        vx, vy = pl.eval_positions(s)
+        return (st["k"], st["hpwl_q"], st["lambda_"], st["a"], st["alpha"], st["wl"],
+                st["energy"], st["overflow_num"], x.tobytes(), y.tobytes(), vx.tobytes(),
+                vy.tobytes())
+
+    for chunk in (3, 9, 13, 8):  # warm-up into steady state, several replays, leftovers
+        for _ in range(chunk):
+            pl.eval(ref, gamma, want_host=False)
+            pl.step(ref)
+            pl.hpwl(ref, want_host=False)
+        pl.iterate(eager, gamma, chunk, hpwl=True, graph=False)
+        pl.iterate(graph, gamma, chunk, hpwl=True, graph=True)
+        pl.iterate([b1, b2], gamma, chunk, hpwl=True, graph=True)
+        want = snap(ref)
+        for s in (eager, graph, b1, b2):
+            assert snap(s) == want, (chunk, s)
+    for s in (ref, eager, graph, b1, b2):
+        pl.free_slot(s)
+
+
 def test_tiny_fp64_placement_matches_oracle(hy, orc):
     """200 iterations of the plain method on the tiny netlist in FP64."""
     nl, pl, o = setup(hy, orc, "tiny", 64)
@@ -282,4 +354,16 @@ def test_errors(hy, orc):
     with pytest.raises(hy.HybroError) as e:
         pl.map(s, hy.HP_MAP_PSI)  # no kept maps yet
     assert e.value.code == hy.HP_ESTATE
+    with pytest.raises(hy.HybroError) as e:
+        pl.eval([s, s], 1.0)  # one slot twice in a launch would race with itself
+    assert e.value.code == hy.HP_EINVAL
+    with pytest.raises(hy.HybroError) as e:
+        hy.hp_iterate(pl.ctx, [s], 1.0, 1, 64)  # unknown flag
+    assert e.value.code == hy.HP_EINVAL
+    with pytest.raises(hy.HybroError) as e:
+        hy.hp_iterate(pl.ctx, [s], 1.0, -1, 0)
+    assert e.value.code == hy.HP_EINVAL
+    with pytest.raises(hy.HybroError) as e:  # switched off; rejected before any launch
+        hy.hp_iterate(pl.ctx, [s], 1.0, 1, hy.HP_ITER_GRAPH)
+    assert e.value.code == hy.HP_ENOTIMPL
     pl.free_slot(s)
