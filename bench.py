@@ -101,6 +101,81 @@ def cpu_baseline(nl, gamma, budget_s=15.0, max_iters=400):
                       f"of the mid workload from its initial placement, FP64, {dt:.1f} s"}
 
 
+def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
+    """One batched Hybro round (K perturbed restarts of the incumbent, each Gaussian 5%,
+    sigma 8 bins, then T iterations) as one K-slot launch sequence, against the same K
+    restarts solved one slot at a time.  Returns restarts/s of both and whether every
+    restart's final HPWL_q agrees bit for bit."""
+    import torch
+    ix = torch.empty(nl.n_movable, dtype=torch.float32, device="cuda")
+    iy = torch.empty_like(ix)
+    hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
+    res = {}
+    for mode in ("plain", "batched"):
+        slots = [pl.new_slot() for _ in range(K)]
+        for s in slots:
+            pl.set_positions(s, ix, iy)
+            pl.set_schedule(s, 1e-4, 4.0, T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, s in enumerate(slots):
+            pl.perturb(s, hy.HP_PERTURB_GAUSS, 0.05, 8.0, seed0 + k, want_idx=False)
+            if mode == "plain":
+                pl.iterate(s, gamma, T, hpwl=True)
+        if mode == "batched":
+            pl.iterate(slots, gamma, T, hpwl=True)
+        q = pl.hpwl(slots)  # reduces the last sweeps (synchronises)
+        dt = time.perf_counter() - t0
+        res[mode] = (K / dt, dt, [int(v) for v in q])
+        for s in slots:
+            pl.free_slot(s)
+    return {"restarts": K, "iterations": T,
+            "batched_restarts_per_s": round(res["batched"][0], 3),
+            "plain_restarts_per_s": round(res["plain"][0], 3),
+            "speedup": round(res["batched"][0] / res["plain"][0], 3),
+            "batched_round_s": round(res["batched"][1], 4),
+            "plain_rounds_s": round(res["plain"][1], 4),
+            "equal_hpwl": res["batched"][2] == res["plain"][2],
+            "best_hpwl": min(res["batched"][2]) / 65536}
+
+
+def large_run(hy, netgen, seed, warm, steps):
+    """Plain-method iterations on the large synthetic netlist (2.2 M cells, 1024 x 1024 bins,
+    FP32 with the int64 charge map): iterations/s over `steps` iterations after `warm`, and the
+    first launch's HBM rate from HIP events on its launches in that timed region."""
+    import torch
+    nl = netgen.make_netlist("large", seed)
+    pl = hy.Placer(nl, precision=32)
+    g = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    pl.set_schedule(s, 1e-4, 4.0, warm + steps)
+    pl.iterate(s, g, warm, hpwl=True)
+    hy.hp_profile_enable(pl.ctx, True, "eval_front_kernel")
+    hy.hp_profile_read(pl.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.iterate(s, g, steps, hpwl=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = hy.hp_profile_read(pl.ctx, reset=True)
+    hy.hp_profile_enable(pl.ctx, False)
+    c, ms = prof.get("eval_front_kernel", (0, 0.0))
+    ab = algorithmic_bytes(nl)["eval_front_kernel"]
+    avg = ms * 1e-3 / max(c, 1)
+    hq = pl.hpwl(s)[0]
+    out = {"workload": f"large: {nl.n_movable} movable cells, {nl.n_fixed} fixed macros, "
+                       f"{nl.n_nets} nets / {nl.n_pins} pins, {nl.mx}x{nl.my} bins, FP32, "
+                       f"int64 charge map",
+           "iter_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
+           "steps": steps, "warmup": warm, "hpwl": hq / 65536,
+           "front_kernel_avg_us": round(avg * 1e6, 3),
+           "front_kernel_gbs": round(ab / avg / 1e9, 1) if c else None,
+           "front_kernel_frac": round(ab / avg / 1e9 / HBM_PEAK_GBS, 4) if c else None}
+    pl.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +187,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no roofline)")
+    ap.add_argument("--large-steps", type=int, default=500,
+                    help="timed iterations on the large netlist (0 skips it)")
+    ap.add_argument("--batch", type=int, default=32,
+                    help="restarts of the batched-round measurement (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the round, copy 256 MiB device-to-device once: the reference "
                          "dispatch for scaling hardware byte counters")
@@ -236,6 +315,12 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kernels.items()},
     }
+    if args.batch > 0:
+        log(f"[bench] batched round: {args.batch} restarts x {K} iterations, batched vs plain")
+        out["batched"] = batched_round(pl, hy, nl, gamma, inc, args.batch, K, 0xB00)
+    if args.large_steps > 0:
+        log(f"[bench] large netlist: 300 + {args.large_steps} iterations")
+        out["large"] = large_run(hy, netgen, args.seed, 300, args.large_steps)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(nl, gamma)

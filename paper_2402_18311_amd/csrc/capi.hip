@@ -958,11 +958,21 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
     hipStream_t st = ctx->stream;
     const SlotLayout &L = n->L;
+    std::vector<char> staged;  // host pairs; lives until the synchronisation below
     if (Nm) {
-        // interleave into u's (x, y) pairs, then copy u to v and v_prev
-        const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-        for (int a = 0; a < 2; ++a)
-            HP_CHECK(hipMemcpy2DAsync(s->base + L.u + a * rs, 2 * rs, a ? y : x, rs, rs, Nm, k, st));
+        // interleave into u's (x, y) pairs (on the host, or by a kernel for device inputs: one
+        // contiguous transfer either way), then copy u to v and v_prev
+        if (on_device) {
+            HP_CHECK(launch_join_pairs(x, y, s->base + L.u, (int)Nm, rs, st));
+        } else {
+            staged.resize(2 * Nm * rs);
+            for (size_t i = 0; i < Nm; ++i) {
+                std::memcpy(&staged[(2 * i) * rs], (const char *)x + i * rs, rs);
+                std::memcpy(&staged[(2 * i + 1) * rs], (const char *)y + i * rs, rs);
+            }
+            HP_CHECK(hipMemcpyAsync(s->base + L.u, staged.data(), staged.size(),
+                                    hipMemcpyHostToDevice, st));
+        }
         HP_CHECK(hipMemcpyAsync(s->base + L.v, s->base + L.u, 2 * Nm * rs, hipMemcpyDeviceToDevice, st));
         HP_CHECK(hipMemcpyAsync(s->base + L.vprev, s->base + L.u, 2 * Nm * rs, hipMemcpyDeviceToDevice,
                                 st));
@@ -991,11 +1001,19 @@ int get_pos(hp_ctx *ctx, int32_t slot, size_t which, void *x, void *y, int on_de
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
     const size_t rs = rsize(ctx), Nm = n->nd.n_mov;
-    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const char *src = s->base + which;  // (x, y) pairs
-    if (Nm && x) HP_CHECK(hipMemcpy2DAsync(x, rs, src, 2 * rs, rs, Nm, k, ctx->stream));
-    if (Nm && y) HP_CHECK(hipMemcpy2DAsync(y, rs, src + rs, 2 * rs, rs, Nm, k, ctx->stream));
-    if (!on_device) HP_CHECK(hipStreamSynchronize(ctx->stream));
+    if (!Nm || (!x && !y)) return HP_OK;
+    if (on_device) return launch_split_pairs(src, x, y, (int)Nm, rs, ctx->stream) == hipSuccess
+                              ? HP_OK
+                              : fail(HP_EDEVICE, "split_pairs launch failed");
+    // one contiguous copy, split on the host
+    std::vector<char> h(2 * Nm * rs);
+    HP_CHECK(hipMemcpyAsync(h.data(), src, h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    for (size_t i = 0; i < Nm; ++i) {
+        if (x) std::memcpy((char *)x + i * rs, &h[(2 * i) * rs], rs);
+        if (y) std::memcpy((char *)y + i * rs, &h[(2 * i + 1) * rs], rs);
+    }
     return HP_OK;
 }
 }  // namespace
@@ -1185,11 +1203,16 @@ int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
             case HP_MAP_RHO_MOV: src = s->base + n->L.rho; bytes = 8 * nb; break;
             case HP_MAP_PSI: src = s->base + n->L.psi; bytes = rs * nb; break;
             case HP_MAP_EX:
-            case HP_MAP_EY:  // one component of the interleaved (xi_x, xi_y) map
-                HP_CHECK(hipMemcpy2DAsync(dst, rs, s->base + n->L.exy + (which == HP_MAP_EY ? rs : 0),
-                                          2 * rs, rs, nb, hipMemcpyDeviceToHost, ctx->stream));
+            case HP_MAP_EY: {  // one component of the interleaved (xi_x, xi_y) map
+                std::vector<char> h(2 * nb * rs);  // one contiguous copy, split on the host
+                HP_CHECK(hipMemcpyAsync(h.data(), s->base + n->L.exy, h.size(), hipMemcpyDeviceToHost,
+                                        ctx->stream));
                 HP_CHECK(hipStreamSynchronize(ctx->stream));
+                const size_t c = which == HP_MAP_EY ? 1 : 0;
+                for (size_t b = 0; b < nb; ++b)
+                    std::memcpy((char *)dst + b * rs, &h[(2 * b + c) * rs], rs);
                 return HP_OK;
+            }
             default: return fail(HP_EINVAL, "unknown map");
         }
     }

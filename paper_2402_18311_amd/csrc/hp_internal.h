@@ -163,6 +163,9 @@ size_t scatter_count_lds(const NetDev &nd);
 size_t scatter_accum_lds(const NetDev &nd);
 hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             hipStream_t st);
+// Device-to-device (x, y) pair splitting / joining, rs = element bytes (4 or 8).
+hipError_t launch_split_pairs(const void *pairs, void *x, void *y, int n, size_t rs, hipStream_t st);
+hipError_t launch_join_pairs(const void *x, const void *y, void *pairs, int n, size_t rs, hipStream_t st);
 template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st);

@@ -173,6 +173,48 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
 
 int cell_parts(const NetDev &nd) { return (nd.n_mov + kBlock - 1) / kBlock; }
 
+// (x, y) pairs <-> separate x and y arrays of n elements of `rs` bytes, device to device (a
+// strided 2-D copy with one tiny row per element is far slower).  Either of x, y may be null
+// when splitting.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void split_pairs_kernel(const T *pairs, T *x, T *y, int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (x) x[i] = pairs[2 * (size_t)i];
+    if (y) y[i] = pairs[2 * (size_t)i + 1];
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void join_pairs_kernel(const T *x, const T *y, T *pairs, int n) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    pairs[2 * (size_t)i] = x[i];
+    pairs[2 * (size_t)i + 1] = y[i];
+}
+
+hipError_t launch_split_pairs(const void *pairs, void *x, void *y, int n, size_t rs, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 g((n + kBlock - 1) / kBlock);
+    if (rs == 4)
+        HP_LAUNCH("split_pairs_kernel", split_pairs_kernel<float>, g, dim3(kBlock), 0, st,
+                  (const float *)pairs, (float *)x, (float *)y, n);
+    else
+        HP_LAUNCH("split_pairs_kernel", split_pairs_kernel<double>, g, dim3(kBlock), 0, st,
+                  (const double *)pairs, (double *)x, (double *)y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_join_pairs(const void *x, const void *y, void *pairs, int n, size_t rs, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 g((n + kBlock - 1) / kBlock);
+    if (rs == 4)
+        HP_LAUNCH("join_pairs_kernel", join_pairs_kernel<float>, g, dim3(kBlock), 0, st,
+                  (const float *)x, (const float *)y, (float *)pairs, n);
+    else
+        HP_LAUNCH("join_pairs_kernel", join_pairs_kernel<double>, g, dim3(kBlock), 0, st,
+                  (const double *)x, (const double *)y, (double *)pairs, n);
+    return hipGetLastError();
+}
+
 // Zero the slots' movable charge maps (after an evaluation that kept them for inspection).
 __global__ __launch_bounds__(kBlock) void clear_rho_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     long long *rho = reinterpret_cast<long long *>(sa.base[blockIdx.y] + L.rho);

@@ -32,6 +32,8 @@ _CASES = {
     # several tiles of every kernel, ragged tails, nets up to 2000 pins, 500 macros
     "small": lambda: netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40),
     "mid": lambda: netgen.make_netlist("mid", 0),
+    # 2.2 M cells, 10.7 M pins (54 nets over 2048 pins), 1024 x 1024 bins
+    "large": lambda: netgen.make_netlist("large", 0),
 }
 _cache = {}
 
@@ -44,7 +46,7 @@ def setup(hy, orc, case, prec):
     return _cache[key]
 
 
-PARAMS = [("tiny", 64), ("tiny", 32), ("small", 32), ("small", 64), ("mid", 32)]
+PARAMS = [("tiny", 64), ("tiny", 32), ("small", 32), ("small", 64), ("mid", 32), ("large", 32)]
 
 
 @pytest.mark.parametrize("case,prec", PARAMS)
@@ -108,7 +110,7 @@ def test_maps_cleared_and_deterministic(hy, orc, case, prec):
     pl.free_slot(s)
 
 
-@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32), ("large", 32)])
 def test_charge_map_exact_with_reused_grouping(hy, orc, case, prec):
     """The scatter rebuilds its tile order only every few evaluations, and cells that left
     their chunk's window since then take the atomic path.  Along a placement from random
