@@ -30,6 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Sources that define the first launch of an evaluation (the dominant kernel); the stored HBM
+# traffic is used only while their hash matches the one it was measured with.
+FRONT_SOURCES = ["paper_2402_18311_amd/csrc/k_sweep.hip", "paper_2402_18311_amd/csrc/hp_binning.h",
+                 "paper_2402_18311_amd/csrc/hp_device.h", "paper_2402_18311_amd/csrc/hp_internal.h"]
+TRAFFIC_FILE = os.path.join("profiles", "eval_front_kernel_mid_traffic.json")
+CALIB_BYTES = 256 << 20  # the calibration copy: 256 MiB read and 256 MiB written
 METRIC = ("placer iters/sec + HBM GB/s; batched-vs-plain restarts/sec, p50/p99 at equal HPWL")
 
 
@@ -99,6 +105,62 @@ def cpu_baseline(nl, gamma, budget_s=15.0, max_iters=400):
     return {"value": it / dt, "unit": "iter/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{it} placer iterations (objective+gradient, Nesterov step, exact HPWL) "
                       f"of the mid workload from its initial placement, FP64, {dt:.1f} s"}
+
+
+def sources_hash(files=FRONT_SOURCES):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel"):
+    """Per-launch HBM traffic of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for the 256 MiB
+    calibration copy of the same run (--copy-calibration).  Writes TRAFFIC_FILE."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        vals, calib = [], []
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if kernel in r["Kernel_Name"]:
+                vals.append(v)
+            elif "copyBuffer" in r["Kernel_Name"]:
+                calib.append(v)
+        return sum(vals) / len(vals), max(calib), len(vals)
+
+    fe, fc, n1 = load(fetch_dir, "FETCH_SIZE")
+    wr, wc, n2 = load(write_dir, "WRITE_SIZE")
+    kib = CALIB_BYTES / 1024
+    ff, wf = kib / fc, kib / wc
+    traffic = (fe * ff + wr * wf) * 1024
+    rec = {"kernel": kernel, "workload": "mid", "fetch_kib_per_launch": round(fe, 1),
+           "write_kib_per_launch": round(wr, 1), "launches": [n1, n2],
+           "calibration_copy_kib": [round(fc, 1), round(wc, 1)],
+           "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+           "traffic_bytes_per_launch": int(traffic), "sources_hash": sources_hash()}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` measured by counters, or None if absent or stale."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel") != kernel or rec.get("sources_hash") != sources_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
@@ -191,10 +253,16 @@ def main():
                     help="timed iterations on the large netlist (0 skips it)")
     ap.add_argument("--batch", type=int, default=32,
                     help="restarts of the batched-round measurement (0 skips it)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="reduce two rocprofv3 --pmc output folders to the stored traffic "
+                         "record and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the round, copy 256 MiB device-to-device once: the reference "
                          "dispatch for scaling hardware byte counters")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the placer on a single MI355X; "
               "--gpus must be 1", file=sys.stderr)
@@ -288,7 +356,8 @@ def main():
         avg_s = ms * 1e-3 / max(c, 1)
         achieved = ab[dom] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(dom),
                 "kernel": dom, "algorithmic_bytes": int(ab[dom]), "launches": c,
                 "avg_us": round(avg_s * 1e6, 3)}
     for k, v in kernels.items():
