@@ -251,6 +251,8 @@ def main():
                     help="time without the per-launch events (no roofline)")
     ap.add_argument("--large-steps", type=int, default=500,
                     help="timed iterations on the large netlist (0 skips it)")
+    ap.add_argument("--serve-jobs", type=int, default=16,
+                    help="jobs of the serving-mix trace (0 skips it)")
     ap.add_argument("--batch", type=int, default=32,
                     help="restarts of the batched-round measurement (0 skips it)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -390,6 +392,11 @@ def main():
     if args.large_steps > 0:
         log(f"[bench] large netlist: 300 + {args.large_steps} iterations")
         out["large"] = large_run(hy, netgen, args.seed, 300, args.large_steps)
+    if args.serve_jobs > 0:
+        from paper_2402_18311_amd import serve
+        log(f"[bench] serving mix: {args.serve_jobs} jobs, 10 k - 2.2 M cells, 500 iterations")
+        out["serving"] = serve.measure(args.serve_jobs, 10_000, 2_200_000, 500, 8.0, 0.8,
+                                       args.seed, log=log)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(nl, gamma)

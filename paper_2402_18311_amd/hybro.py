@@ -107,6 +107,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2402_18311_amd.build`")
+        # torch first: it brings its own HIP runtime (soname libamdhip64.so.7), and the library
+        # must bind to that same runtime rather than load a second one from the ROCm install
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
@@ -382,6 +385,9 @@ class Placer:
         hp_iterate(self.ctx, list(np.atleast_1d(slots)), gamma, iters, flags)
 
     def close(self):
+        """Synchronise and destroy the context, then drop the device buffers."""
         if self.ctx is not None:
             hp_destroy(self.ctx)
             self.ctx = None
+        self._slotbufs = {}
+        self._netbuf = None

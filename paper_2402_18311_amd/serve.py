@@ -1,0 +1,241 @@
+"""Serving loop: placement jobs of uneven size, admitted by HBM budget and run concurrently.
+
+A job is one synthetic netlist placed by the plain method: `iters` iterations (objective and
+gradient of Eq. 2, Nesterov step, exact HPWL of Eq. 1) from its initial positions; its result
+is the final HPWL_q.  Jobs arrive on a trace.  The server admits them in arrival order as long
+as their device buffers (netlist + one slot) fit in the budget — a job larger than the whole
+budget is admitted alone — keeps their state resident while they run, and runs every admitted
+job on its own HIP stream from its own host thread, so the kernels of concurrent jobs overlap
+on the device (jobs on different netlists cannot share launches; slots of one netlist do).
+A finished job releases its memory and the next arrivals are admitted at once.
+
+The baseline is the same trace served sequentially: one job at a time, in arrival order.
+Every kernel is deterministic per slot, so each job's HPWL_q is identical alone and in the mix.
+
+    python -m paper_2402_18311_amd.serve --jobs 200 --budget-gb 8
+
+The scheduler is independent of the executor (`run` callable), so its admission logic is
+tested on the CPU with a stand-in executor.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import threading
+import time
+
+import numpy as np
+
+from . import netgen
+
+
+@dataclasses.dataclass
+class Job:
+    jid: int
+    netlist: object
+    iters: int
+    arrival: float            # seconds after the start of the trace
+    nbytes: int = 0           # device bytes while resident (netlist buffer + one slot)
+    start: float = math.nan   # admission time (trace clock)
+    finish: float = math.nan
+    hpwl_q: int | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+class Scheduler:
+    """Admission by budget in arrival order; one host thread per admitted job.
+
+    `run(job)` executes a job (blocking) and fills job.hpwl_q.  `serve` returns when every job
+    has finished; it records the peak resident bytes and the peak number of concurrent jobs."""
+
+    def __init__(self, budget_bytes: int, run):
+        self.budget = int(budget_bytes)
+        self.run = run
+        self.peak_bytes = 0
+        self.peak_jobs = 0
+
+    def serve(self, jobs: list[Job]) -> None:
+        order = sorted(jobs, key=lambda j: (j.arrival, j.jid))
+        cv = threading.Condition()
+        used = 0
+        active = 0
+        errors: list[BaseException] = []
+        threads = []
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+
+        def worker(job: Job):
+            nonlocal used, active
+            try:
+                self.run(job)
+            except BaseException as e:  # surfaced after the loop
+                errors.append(e)
+            finally:
+                with cv:
+                    job.finish = now()
+                    used -= job.nbytes
+                    active -= 1
+                    cv.notify_all()
+
+        i = 0
+        with cv:
+            while i < len(order):
+                job = order[i]
+                wait = job.arrival - now()
+                if wait > 0:
+                    cv.wait(timeout=wait)
+                    continue
+                fits = used + job.nbytes <= self.budget or active == 0
+                if not fits:
+                    cv.wait()
+                    continue
+                used += job.nbytes
+                active += 1
+                self.peak_bytes = max(self.peak_bytes, used)
+                self.peak_jobs = max(self.peak_jobs, active)
+                job.start = now()
+                t = threading.Thread(target=worker, args=(job,), daemon=True)
+                threads.append(t)
+                t.start()
+                i += 1
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+
+
+def serve_sequential(jobs: list[Job], run) -> None:
+    """The baseline: one job at a time in arrival order, each started at max(arrival, the
+    previous finish)."""
+    t0 = time.perf_counter()
+    for job in sorted(jobs, key=lambda j: (j.arrival, j.jid)):
+        wait = job.arrival - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        job.start = time.perf_counter() - t0
+        run(job)
+        job.finish = time.perf_counter() - t0
+
+
+def stats(jobs: list[Job]) -> dict:
+    lat = np.array([j.latency for j in jobs])
+    span = max(j.finish for j in jobs) - min(j.arrival for j in jobs)
+    return {"jobs": len(jobs), "jobs_per_s": round(len(jobs) / span, 4),
+            "makespan_s": round(span, 4), "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_latency_s": round(float(lat.mean()), 4)}
+
+
+# ---- jobs on the GPU -------------------------------------------------------------------------
+_query = {}
+
+
+def device_bytes(nl, precision: int = 32) -> int:
+    """Device bytes one job holds while resident: its netlist buffer and one slot."""
+    from . import hybro as hy
+    if precision not in _query:
+        _query[precision] = hy.hp_create(0, None, precision)
+    ctx = _query[precision]
+    shape = hy.hp_shape(nl.n_cells, nl.n_movable, int(len(nl.net_start) - 1),
+                        int(len(nl.pin_cell)))
+    die = hy.hp_die(float(nl.W), float(nl.H), int(nl.mx), int(nl.my), 1.0, 1, 0)
+    return int(hy.hp_netlist_bytes(ctx, shape, die) + hy.hp_slot_bytes(ctx, shape, die) + 512)
+
+
+def run_on_gpu(job: Job) -> None:
+    """Place one job on its own stream: load, iterate, read the HPWL, release."""
+    import torch
+
+    from . import hybro as hy
+    # The job's kernels run on its own stream; its buffers come from torch's pool on the
+    # default stream, and are dropped only after hp_destroy has synchronised the job's stream,
+    # so the next allocation may reuse them at once.
+    stream = torch.cuda.Stream()
+    pl = hy.Placer(job.netlist, precision=32, stream=stream)
+    try:
+        s = pl.new_slot()
+        nl = job.netlist
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, job.iters)
+        pl.iterate(s, 4 * nl.bin_w, job.iters, hpwl=True)
+        job.hpwl_q = int(pl.hpwl(s)[0])
+        pl.free_slot(s)
+    finally:
+        pl.close()
+        del pl
+
+
+def make_jobs(n: int, lo: int, hi: int, iters: int, seed: int) -> list[Job]:
+    """n netlists shaped like the mid workload with log-uniform sizes in [lo, hi] cells
+    (arrival times are set by `poisson_arrivals`)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), n)).round().astype(int)
+    jobs = []
+    for i, c in enumerate(sizes):
+        nl = netgen.make_netlist(netgen.scaled_config(int(c)), seed * 1000 + i)
+        jobs.append(Job(i, nl, iters, 0.0))
+    return jobs
+
+
+def poisson_arrivals(jobs: list[Job], rate: float, seed: int) -> None:
+    rng = np.random.default_rng(seed + 7)
+    t = np.cumsum(rng.exponential(1.0 / rate, len(jobs)))
+    for j, a in zip(jobs, t - t[0]):
+        j.arrival = float(a)
+
+
+def fresh(jobs: list[Job]) -> list[Job]:
+    return [Job(j.jid, j.netlist, j.iters, j.arrival, j.nbytes) for j in jobs]
+
+
+def measure(n_jobs=200, lo=10_000, hi=2_200_000, iters=500, budget_gb=8.0, rate_frac=0.8,
+            seed=0, log=print) -> dict:
+    """Config 5: capacity of sequential plain solves (all jobs queued at t = 0), then a Poisson
+    trace at rate_frac x that capacity served sequentially and by the server."""
+    jobs = make_jobs(n_jobs, lo, hi, iters, seed)
+    for j in jobs:
+        j.nbytes = device_bytes(j.netlist)
+    log(f"[serve] {n_jobs} jobs, {sum(j.netlist.n_movable for j in jobs)} cells in all")
+    run_on_gpu(fresh(jobs[:1])[0])  # code objects load lazily: warm every kernel once
+    cap = fresh(jobs)
+    serve_sequential(cap, run_on_gpu)
+    capacity = len(cap) / max(j.finish for j in cap)
+    rate = rate_frac * capacity
+    poisson_arrivals(jobs, rate, seed)
+    log(f"[serve] sequential capacity {capacity:.3f} jobs/s; trace at {rate:.3f} jobs/s")
+    seq = fresh(jobs)
+    serve_sequential(seq, run_on_gpu)
+    srv = fresh(jobs)
+    sch = Scheduler(int(budget_gb * 2**30), run_on_gpu)
+    sch.serve(srv)
+    same = all(a.hpwl_q == b.hpwl_q for a, b in zip(sorted(seq, key=lambda j: j.jid),
+                                                    sorted(srv, key=lambda j: j.jid)))
+    return {"config": {"jobs": n_jobs, "cells": [lo, hi], "iters": iters, "budget_gb": budget_gb,
+                       "arrival_rate_jobs_per_s": round(rate, 4), "rate_frac_of_capacity": rate_frac,
+                       "seed": seed},
+            "sequential_capacity_jobs_per_s": round(capacity, 4),
+            "sequential": stats(seq), "served": stats(srv),
+            "peak_resident_gb": round(sch.peak_bytes / 2**30, 3), "peak_concurrent_jobs": sch.peak_jobs,
+            "equal_hpwl": same}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--jobs", type=int, default=200)
+    ap.add_argument("--lo", type=int, default=10_000)
+    ap.add_argument("--hi", type=int, default=2_200_000)
+    ap.add_argument("--iters", type=int, default=500)
+    ap.add_argument("--budget-gb", type=float, default=8.0)
+    ap.add_argument("--rate-frac", type=float, default=0.8)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args()
+    print(json.dumps(measure(a.jobs, a.lo, a.hi, a.iters, a.budget_gb, a.rate_frac, a.seed)))
+
+
+if __name__ == "__main__":
+    main()
