@@ -119,8 +119,9 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
  *   map, overflow = sum_b max(0, movable charge - target * free area) / total movable charge
  *   (the D(s) <= eps measure of Eq. 1), gradient = grad WL + lambda * grad N over movable
  *   cells.  gamma: the smoothing length of Eq. 3 (same units as positions).  lambda >= 0 is
- *   used as given; lambda < 0 uses each slot's scheduled lambda.  grad_mode 0: field force
- *   (the only mode on the device; 1 returns HP_ENOTIMPL).  keep_maps 1 keeps the charge,
+ *   used as given; lambda < 0 uses each slot's scheduled lambda.  grad_mode 0: the field
+ *   force -sum_b q_ib xi_b (ePlace); 1: the exact adjoint sum_b psi_b dq_ib/dx_i of the
+ *   continuous charge rectangle (also computes the potential map).  keep_maps 1 keeps the charge,
  *   potential and field maps for hp_get_map.  wl/energy/overflow: host double [n_slots] or
  *   NULL (then nothing is synchronised).  grad_x/grad_y: device real [n_slots][n_movable] or
  *   NULL (the gradient always stays in the slot for hp_nesterov_step). */

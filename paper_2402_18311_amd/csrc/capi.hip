@@ -441,6 +441,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
         }
     }
     nd.total_charge = total_charge > 0 ? total_charge : 1;
+    nd.stretch = D.stretch;
     {
         const BinGeom g = bin_geom(S, D);
         if (halo > (1 << g.log_ts))
@@ -636,7 +637,7 @@ int finish_hpwl(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
 int check_eval_params(const hp_eval_params *p) {
     if (!p) return fail(HP_EINVAL, "params is NULL");
     if (!(p->gamma > 0) || !std::isfinite(p->gamma)) return fail(HP_EINVAL, "gamma must be > 0");
-    if (p->grad_mode != 0) return fail(HP_ENOTIMPL, "only the field-force gradient runs on the device");
+    if (p->grad_mode != 0 && p->grad_mode != 1) return fail(HP_EINVAL, "grad_mode must be 0 or 1");
     if (p->lambda >= 0 && !std::isfinite(p->lambda)) return fail(HP_EINVAL, "lambda must be finite");
     return HP_OK;
 }
@@ -669,8 +670,9 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         // WA sweep, HPWL sweep and the scatter (or the counting pass of a regroup) in one launch
         HP_CHECK(launch_eval_front<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, hmask, regroup, st));
         if (regroup) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, st));
-        HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0, p->keep_maps != 0, st));
-        HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed,
+        HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0,
+                                    p->keep_maps != 0 || p->grad_mode == 1, st));
+        HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
                                      st));
         if (any_init) HP_CHECK(launch_combine<T>(nd, sa, L, st));

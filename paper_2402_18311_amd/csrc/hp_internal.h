@@ -65,6 +65,7 @@ struct NetDev {
     int64_t area_q;                // bin area in 2^-40 units
     double target_density;
     int64_t total_charge;
+    int32_t stretch;               // small cells' charge spread over >= sqrt(2) bins per side
 };
 
 // Byte offsets of a slot's arrays inside its buffer (identical for all slots of a netlist).
@@ -175,10 +176,11 @@ hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLa
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
                               hipStream_t st);
 hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, int nparts, hipStream_t st);
+// grad_mode 0: field force -sum q xi; 1: exact adjoint sum psi dq/dx (needs the psi map).
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                            double lambda_fixed, bool use_fixed, int nwl, int ne, int nov,
-                            hipStream_t st);
+                            double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
+                            int nov, hipStream_t st);
 template <typename T>
 hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                           hipStream_t st);

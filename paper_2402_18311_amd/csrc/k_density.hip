@@ -55,6 +55,65 @@ __global__ __launch_bounds__(kBlock) void fixed_map_kernel(NetDev nd, const doub
     }
 }
 
+// d/dlo of the overlap of [lo, hi] (both moving with the cell, clipped to [0, Wd]) with the
+// bin [a, b]: +1 for a moving upper edge inside the bin, -1 for a moving lower edge; an edge
+// clipped by the die does not move.  At a touching edge (zero overlap) the derivative of the
+// motion that enters the bin is kept.
+__device__ __forceinline__ double d_overlap(double lo_raw, double hi_raw, double a, double b,
+                                            double Wd) {
+    const double lo = fmin(fmax(lo_raw, 0.0), Wd), hi = fmin(fmax(hi_raw, 0.0), Wd);
+    const double dlo = (lo_raw >= 0.0 && lo_raw < Wd) ? 1.0 : 0.0;
+    const double dhi = (hi_raw >= 0.0 && hi_raw < Wd) ? 1.0 : 0.0;
+    const double s = lo >= a ? lo : a, ds = lo >= a ? dlo : 0.0;
+    const double t = hi < b ? hi : b, dt = hi < b ? dhi : 0.0;
+    const double o = t - s, d = dt - ds;
+    if (o > 0.0) return d;
+    if (o == 0.0) return d > 0.0 ? d : 0.0;
+    return 0.0;
+}
+__device__ __forceinline__ double overlap_d(double lo, double hi, double a, double b) {
+    const double s = lo > a ? lo : a, t = hi < b ? hi : b;
+    return t > s ? t - s : 0.0;
+}
+
+// Exact adjoint of the density energy for cell i: dN/dx_i = sum_b psi_b d q_ib / dx_i, with
+// q_ib = r * overlap_x * overlap_y of the cell's continuous (unquantized) charge rectangle —
+// its stretched size and charge scale in FP64 — so the gradient is that of the continuous
+// map's energy, with psi from the integer map.  Bins in row-major order over the rectangle and
+// the bins touching it.
+template <typename T>
+__device__ void exact_adjoint(const NetDev &nd, const T *psi, int i, double x, double y, T &gdx,
+                              T &gdy) {
+    const int n = nd.n_mov;
+    const T *wh = reinterpret_cast<const T *>(nd.cell_wh);
+    const double w = (double)wh[i], h = (double)wh[n + i];
+    double ws = w, hs = h, sc = 1.0;
+    if (nd.stretch) {
+        ws = fmax(w, M_SQRT2 * nd.wb);
+        hs = fmax(h, M_SQRT2 * nd.hb);
+        sc = (w * h) / (ws * hs);
+    }
+    const double L = x + (w - ws) * 0.5, B = y + (h - hs) * 0.5;
+    const double l = fmin(fmax(L, 0.0), nd.W), r = fmin(fmax(L + ws, 0.0), nd.W);
+    const double b = fmin(fmax(B, 0.0), nd.H), t = fmin(fmax(B + hs, 0.0), nd.H);
+    const int j0 = max(0, (int)floor(l / nd.wb) - 1), j1 = min(nd.mx - 1, (int)floor(r / nd.wb) + 1);
+    const int k0 = max(0, (int)floor(b / nd.hb) - 1), k1 = min(nd.my - 1, (int)floor(t / nd.hb) + 1);
+    double sx = 0.0, sy = 0.0;
+    for (int k = k0; k <= k1; ++k) {
+        const double oy = overlap_d(b, t, k * nd.hb, (k + 1) * nd.hb);
+        const double doy = d_overlap(B, B + hs, k * nd.hb, (k + 1) * nd.hb, nd.H);
+        for (int j = j0; j <= j1; ++j) {
+            const double ox = overlap_d(l, r, j * nd.wb, (j + 1) * nd.wb);
+            const double dox = d_overlap(L, L + ws, j * nd.wb, (j + 1) * nd.wb, nd.W);
+            const double ps = (double)psi[(size_t)k * nd.mx + j];
+            sx += ps * sc * dox * oy;
+            sy += ps * sc * ox * doy;
+        }
+    }
+    gdx = (T)sx;
+    gdy = (T)sy;
+}
+
 // Fused cell gradient.  Wirelength part: the sum of the cell's pin gradients (fixed pin
 // order -> deterministic).  Density part: the field force, dN/dx_i = -sum_b q_ib xi_x(b),
 // with q_ib the cell's integer charge in bin b.  Steady state writes g = gWL + lambda gD;
@@ -63,7 +122,8 @@ __global__ __launch_bounds__(kBlock) void fixed_map_kernel(NetDev nd, const doub
 // also forms its partials of the following Nesterov step's reductions.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                           double lam_fixed, int use_fixed) {
+                                                           double lam_fixed, int use_fixed,
+                                                           int grad_mode) {
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const bool init = !use_fixed && sc->lambda_valid == 0;
@@ -86,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
         const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
         constexpr int KR = 3, JC = 4;
-        const bool small = has && k1 - k0 < KR && j1 - j0 < JC;
+        const bool small = grad_mode == 0 && has && k1 - k0 < KR && j1 - j0 < JC;
         vec2<T> f[KR][JC];
         if (small) {
 #pragma unroll
@@ -113,7 +173,10 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             gwx += g.x;
             gwy += g.y;
         }
-        if (small) {
+        if (grad_mode == 1) {  // exact adjoint of the continuous charge rectangle
+            exact_adjoint<T>(nd, reinterpret_cast<const T *>(base + L.psi), i, (double)p.x,
+                             (double)p.y, gdx, gdy);
+        } else if (small) {
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
                 if (k0 + kk > k1) continue;
@@ -231,11 +294,11 @@ hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayo
 
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                            double lambda_fixed, bool use_fixed, int nwl, int ne, int nov,
-                            hipStream_t st) {
+                            double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
+                            int nov, hipStream_t st) {
     const int nb = std::max(1, cell_parts(nd));
     HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(nb, sa.n), dim3(kBlock), 0, st, nd, sa,
-              L, lambda_fixed, (int)use_fixed);
+              L, lambda_fixed, (int)use_fixed, grad_mode);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, st);
@@ -254,7 +317,7 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 #define HP_INST(T)                                                                          \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
                                             const SlotLayout &, double, bool, int, int, int, \
-                                            hipStream_t);                                   \
+                                            int, hipStream_t);                              \
     template hipError_t launch_fixed_map<T>(const NetDev &, const double *, const double *, \
                                             int64_t *, hipStream_t);
 HP_INST(float)

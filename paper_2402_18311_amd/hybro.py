@@ -336,13 +336,15 @@ class Placer:
     def set_schedule(self, s, lambda0_scale=1e-4, decades=4.0, total_iters=1000):
         hp_set_schedule(self.ctx, s, lambda0_scale, decades, total_iters)
 
-    def eval(self, slots, gamma, lam=-1.0, keep_maps=False, grads=False, want_host=True):
+    def eval(self, slots, gamma, lam=-1.0, keep_maps=False, grads=False, want_host=True,
+             grad_mode=0):
         slots = list(np.atleast_1d(slots))
         gx = gy = None
         if grads:
             gx = self.torch.empty((len(slots), self.nl.n_movable), dtype=self.tdtype, device=self.dev)
             gy = self.torch.empty_like(gx)
-        r = hp_eval_objective_grad(self.ctx, slots, gamma, lam, 0, keep_maps, want_host, gx, gy)
+        r = hp_eval_objective_grad(self.ctx, slots, gamma, lam, grad_mode, keep_maps, want_host,
+                                   gx, gy)
         if grads:
             return r, gx, gy
         return r

@@ -93,6 +93,33 @@ def test_eval_parity(hy, orc, case, prec):
     pl.free_slot(s)
 
 
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("tiny", 32), ("small", 32)])
+def test_exact_adjoint_parity(hy, orc, case, prec):
+    """grad_mode 1: sum_b psi_b dq_ib/dx_i of the continuous charge rectangle, psi from the
+    integer map, against the oracle's evaluation in the same mode (the oracle's adjoint visits
+    every bin for every cell, so the cases stop at 20 k cells x 128^2 bins)."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    tol = TOL[prec]
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    x, y = nl.random_positions(3)
+    pl.set_positions(s, x, y)
+    lam = 0.61
+    (wl, en, ov), gx, gy = pl.eval(s, gamma, lam=lam, grads=True, grad_mode=1)
+    ref = o.eval(x, y, gamma, grad_mode=1)
+    assert en[0] == pytest.approx(ref["energy"], rel=tol["tot"])
+    g = np.concatenate([gx.cpu().numpy()[0], gy.cpu().numpy()[0]])
+    gref = np.concatenate([ref["gwx"] + lam * ref["gdx"], ref["gwy"] + lam * ref["gdy"]])
+    assert rel_l2(g, gref) < tol["l2"]
+    # with a large lambda the density part dominates the comparison
+    lam = 1e4
+    (_, _, _), gx, gy = pl.eval(s, gamma, lam=lam, grads=True, grad_mode=1)
+    g = np.concatenate([gx.cpu().numpy()[0], gy.cpu().numpy()[0]])
+    gref = np.concatenate([ref["gwx"] + lam * ref["gdx"], ref["gwy"] + lam * ref["gdy"]])
+    assert rel_l2(g, gref) < tol["l2"]
+    pl.free_slot(s)
+
+
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32)])
 def test_maps_cleared_and_deterministic(hy, orc, case, prec):
     nl, pl, o = setup(hy, orc, case, prec)
@@ -351,8 +378,8 @@ def test_errors(hy, orc):
         pl.eval(s, -1.0)
     assert e.value.code == hy.HP_EINVAL
     with pytest.raises(hy.HybroError) as e:
-        hy.hp_eval_objective_grad(pl.ctx, [s], 1.0, grad_mode=1)
-    assert e.value.code == hy.HP_ENOTIMPL
+        hy.hp_eval_objective_grad(pl.ctx, [s], 1.0, grad_mode=2)
+    assert e.value.code == hy.HP_EINVAL
     with pytest.raises(hy.HybroError) as e:
         pl.map(s, hy.HP_MAP_PSI)  # no kept maps yet
     assert e.value.code == hy.HP_ESTATE
