@@ -113,6 +113,9 @@ int hp_get_eval_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_de
  * Nesterov step multiplies it by 10^(decades / total_iters).  Defaults: 1e-4, 4, 1000. */
 int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double decades,
                     int32_t total_iters);
+/* Set the factor lambda is multiplied by at every following Nesterov step (ratio > 0, finite):
+ * for drivers that adapt the penalty of Eq. 2 as the placement evolves.  Synchronises. */
+int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio);
 
 /* Objective of Eq. 2 and its gradient at the slots' reference points v:
  *   wl = sum_e w_e WL_e (Eq. 3, both axes), energy = electrostatic energy N of the charge

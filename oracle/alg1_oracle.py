@@ -1,0 +1,68 @@
+"""Hybro's outer loop (Alg. 1) on the FP64 oracle.
+
+TEST INFRASTRUCTURE ONLY: used by the tests to pin the device driver.  Written from the
+algorithm, not from the device driver (they share no code): place from the initial positions;
+then each round perturbs the best solution (Sec. 4.2), places again and keeps the smaller exact
+HPWL (Eq. 1).  The placer's schedules and stopping rule are the ePlace-style reading recorded
+in the design notes:
+  * stop when the overflow (the D(s) <= eps measure of Eq. 1) is at most 0.10, or after
+    max_iters iterations; overflow and HPWL are looked at every 10 iterations;
+  * smoothing gamma = 4 bins x 10^((20/9) tau - 11/9) for the next 10 iterations, from the
+    overflow tau at the last look;
+  * the penalty weight lambda starts at 1e-4 |grad WL|_1 / |grad N|_1 (first evaluation) and is
+    multiplied after every step by mu = min(1.05, max(0.95, 1.05^(1 - dH / (0.0035 H)))), where
+    dH is the HPWL change per iteration over the last 10 and H the HPWL before them (mu = 1.05
+    until the first look).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _gamma(tau, bin_w):
+    return 4.0 * bin_w * 10.0 ** ((20.0 / 9.0) * tau - 11.0 / 9.0)
+
+
+def _mu(h, h_prev):
+    if h_prev <= 0:
+        return 1.05
+    m = 1.05 ** (1.0 - ((h - h_prev) / 10) / (0.0035 * h_prev))
+    return min(1.05, max(0.95, m))
+
+
+def place_to_convergence(o, nl, x, y, max_iters):
+    """Returns the final (x, y) of the major solution, iterations run, HPWL_q and overflow."""
+    n = nl.n_movable
+    st = o.new_state(x, y)
+    tau = o.eval(st["v"][:n], st["v"][n:], _gamma(1.0, nl.bin_w))["overflow"]
+    h_prev = o.hpwl_q(st["u"][:n], st["u"][n:])
+    lam, ratio, k = None, 1.05, 0
+    while k < max_iters and tau > 0.10:
+        g = _gamma(tau, nl.bin_w)
+        for _ in range(min(10, max_iters - k)):
+            r = o.eval(st["v"][:n], st["v"][n:], g)
+            gw = np.concatenate([r["gwx"], r["gwy"]])
+            gd = np.concatenate([r["gdx"], r["gdy"]])
+            if lam is None:
+                lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum()
+            o.nesterov_step(lam, gw + lam * gd, st)
+            lam *= ratio
+            tau = r["overflow"]
+            k += 1
+        h = o.hpwl_q(st["u"][:n], st["u"][n:])
+        ratio = _mu(h, h_prev)
+        h_prev = h
+    return st["u"][:n].copy(), st["u"][n:].copy(), k, h_prev, tau
+
+
+def hybro(o, nl, rounds, mode, fraction, sigma_bins, seed, max_iters):
+    """Per-round trace: iterations, HPWL_q of the round's placement, best HPWL_q so far."""
+    bx, by, k, best, tau = place_to_convergence(o, nl, nl.x0, nl.y0, max_iters)
+    trace = [(k, best, best)]
+    for r in range(rounds):
+        px, py, _ = o.perturb(bx, by, mode, fraction, sigma_bins, seed + r)
+        x, y, k, h, tau = place_to_convergence(o, nl, px, py, max_iters)
+        if h < best:
+            bx, by, best = x, y, h
+        trace.append((k, h, best))
+    return trace

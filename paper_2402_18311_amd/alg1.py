@@ -1,0 +1,127 @@
+"""Hybro's outer loop (Alg. 1) on the device: place, then repeatedly perturb the best solution,
+re-place it and keep the one with the smallest exact HPWL (Eq. 1).
+
+The paper leaves the analytical placer's schedules and stopping rule to the placer it builds
+on (Sec. 3.1).  This driver uses the ePlace-style rules (a reading):
+  * the placer runs until the density overflow tau (the D(s) <= eps measure of Eq. 1) falls to
+    TAU_STOP, or for at most `max_iters` iterations;
+  * every CHECK iterations the smoothing of Eq. 3 follows the overflow,
+        gamma(tau) = GAMMA_BINS * bin * 10^((20/9) tau - 11/9),
+    and the penalty weight of Eq. 2 is multiplied at every following step by
+        mu = clamp(MU_MAX^(1 - dH / (DH_REF * H)), MU_MIN, MU_MAX),
+    with dH the HPWL change per iteration over the last CHECK iterations and H the HPWL before
+    them; lambda_0 is derived at the first evaluation (scale x |grad WL|_1 / |grad N|_1);
+  * the decisions read only the exact integer HPWL and overflow numerator.
+
+Perturbations (Sec. 4.2): Gaussian moves of a fraction of the cells, Shuffle (all) of a
+fraction, or a uniform random restart (the Multiple-restart baseline).  Every iteration runs
+on the device (hp_iterate); the host reads two integers every CHECK iterations.
+
+    python -m paper_2402_18311_amd.alg1 --workload mid --rounds 5
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+from . import hybro as hy
+from . import netgen
+
+CHECK = 10
+TAU_STOP = 0.10
+GAMMA_BINS = 4.0
+MU_MAX, MU_MIN = 1.05, 0.95
+DH_REF = 3.5e-3
+LAMBDA0_SCALE = 1e-4
+
+MODES = {"gauss": hy.HP_PERTURB_GAUSS, "shuffle": hy.HP_PERTURB_SHUFFLE,
+         "restart": hy.HP_PERTURB_UNIFORM}
+
+
+def gamma_of(tau: float, bin_w: float) -> float:
+    return GAMMA_BINS * bin_w * 10.0 ** ((20.0 / 9.0) * tau - 11.0 / 9.0)
+
+
+def mu_of(h: int, h_prev: int) -> float:
+    d = (h - h_prev) / CHECK
+    m = MU_MAX ** (1.0 - d / (DH_REF * h_prev)) if h_prev > 0 else MU_MAX
+    return min(MU_MAX, max(MU_MIN, m))
+
+
+def global_place(pl, slot: int, max_iters: int) -> dict:
+    """One run of the placer from the slot's current positions: returns iterations, the final
+    HPWL_q of u and the final overflow."""
+    nl = pl.nl
+    _, _, ov = pl.eval(slot, gamma_of(1.0, nl.bin_w), lam=0.0)  # overflow at the start
+    tau = float(ov[0])
+    h_prev = int(pl.hpwl(slot)[0])
+    hy.hp_set_lambda_ratio(pl.ctx, slot, MU_MAX)
+    k = 0
+    while k < max_iters and tau > TAU_STOP:
+        n = min(CHECK, max_iters - k)
+        pl.iterate(slot, gamma_of(tau, nl.bin_w), n, hpwl=True)
+        k += n
+        st = pl.state(slot)
+        tau = float(st["overflow"])
+        h = int(st["hpwl_q"])
+        hy.hp_set_lambda_ratio(pl.ctx, slot, mu_of(h, h_prev))
+        h_prev = h
+    return {"iters": k, "hpwl_q": h_prev, "overflow": tau}
+
+
+def hybro(pl, rounds: int, mode: str = "gauss", fraction: float = 0.05, sigma_bins: float = 8.0,
+          seed: int = 0, max_iters: int = 1000, x0=None, y0=None) -> dict:
+    """Alg. 1: the incumbent is the placement of (x0, y0); each round perturbs it (`mode`),
+    re-places and keeps the better.  Returns the per-round trace."""
+    nl = pl.nl
+    inc, work = pl.new_slot(), pl.new_slot()
+    try:
+        pl.set_positions(inc, nl.x0 if x0 is None else x0, nl.y0 if y0 is None else y0)
+        pl.set_schedule(inc, LAMBDA0_SCALE, 4.0, 1000)
+        pl.set_schedule(work, LAMBDA0_SCALE, 4.0, 1000)
+        first = global_place(pl, inc, max_iters)
+        best = first["hpwl_q"]
+        trace = [{"round": 0, **first, "best_hpwl_q": best}]
+        import torch
+        ix = torch.empty(nl.n_movable, dtype=pl.tdtype, device=pl.dev)
+        iy = torch.empty_like(ix)
+        for r in range(rounds):
+            hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
+            pl.set_positions(work, ix, iy)
+            pl.perturb(work, MODES[mode], fraction, sigma_bins, seed + r, want_idx=False)
+            res = global_place(pl, work, max_iters)
+            won = pl.select_best([work], inc)
+            best = min(best, res["hpwl_q"])
+            trace.append({"round": r + 1, **res, "kept": bool(won >= 0), "best_hpwl_q": best})
+        return {"mode": mode, "rounds": rounds, "best_hpwl_q": best, "trace": trace}
+    finally:
+        pl.free_slot(inc)
+        pl.free_slot(work)
+
+
+def main():
+    ap = argparse.ArgumentParser(description="Hybro (Alg. 1) against Multiple-restart")
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--rounds", type=int, default=5)
+    ap.add_argument("--max-iters", type=int, default=1000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--modes", default="gauss,shuffle,restart")
+    a = ap.parse_args()
+    nl = netgen.make_netlist(a.workload, a.seed)
+    pl = hy.Placer(nl, precision=32)
+    out = {"workload": a.workload, "rounds": a.rounds, "max_iters": a.max_iters, "runs": []}
+    for mode in a.modes.split(","):
+        frac = {"gauss": 0.05, "shuffle": 0.5, "restart": 1.0}[mode]
+        t0 = time.perf_counter()
+        r = hybro(pl, a.rounds, mode, frac, 8.0, a.seed, a.max_iters)
+        r["seconds"] = round(time.perf_counter() - t0, 3)
+        r["gp_iterations"] = sum(t["iters"] for t in r["trace"])
+        out["runs"].append(r)
+        print(f"{mode:8s} best HPWL {r['best_hpwl_q'] / 65536:.1f}  "
+              f"({r['gp_iterations']} iterations, {r['seconds']} s)", flush=True)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1051,6 +1051,18 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
     return HP_OK;
 }
 
+int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (!(ratio > 0) || !std::isfinite(ratio)) return fail(HP_EINVAL, "ratio must be finite and > 0");
+    HP_CHECK(hipMemcpyAsync(s->base + n->L.scal + offsetof(Scalars, lambda_ratio), &ratio,
+                            sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
 int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p,
                            double *wl, double *energy, double *overflow, void *gx, void *gy) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");

@@ -70,6 +70,7 @@ _SIGS = {
     "hp_get_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_get_eval_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
+    "hp_set_lambda_ratio": [_P, C.c_int32, C.c_double],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
     "hp_nesterov_step": [_P, _P, C.c_int32],
     "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
@@ -190,6 +191,10 @@ def hp_get_positions(ctx, slot, x, y, on_device):
 
 def hp_get_eval_positions(ctx, slot, x, y, on_device):
     _chk(lib().hp_get_eval_positions(ctx, slot, _ptr(x), _ptr(y), int(on_device)))
+
+
+def hp_set_lambda_ratio(ctx, slot, ratio):
+    _chk(lib().hp_set_lambda_ratio(ctx, slot, float(ratio)))
 
 
 def hp_set_schedule(ctx, slot, lambda0_scale, decades, total_iters):

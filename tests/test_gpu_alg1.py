@@ -1,0 +1,46 @@
+"""Hybro's outer loop (Alg. 1) on the device against the oracle's, and its invariants."""
+import numpy as np
+import pytest
+
+from paper_2402_18311_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode,frac", [("gauss", 0.05), ("shuffle", 0.5)])
+def test_alg1_matches_oracle_fp64(orc, mode, frac):
+    """Tiny netlist in FP64: every round runs the same number of placer iterations and reaches
+    the same HPWL as the oracle's driver (the decisions read exact integers; the float path
+    differs from the oracle's only in summation order).  The placements are capped at 120
+    iterations: with lambda growing 5% a step, rounding differences grow with the horizon
+    (about 6e-7 in HPWL after 400 iterations), so longer runs are checked for invariants."""
+    from oracle import alg1_oracle
+    from paper_2402_18311_amd import alg1, hybro
+    nl = netgen.make_netlist("tiny", 0)
+    pl = hybro.Placer(nl, precision=64)
+    res = alg1.hybro(pl, 2, mode, frac, 8.0, seed=11, max_iters=120)
+    o = orc.Oracle(nl)
+    ref = alg1_oracle.hybro(o, nl, 2, alg1.MODES[mode], frac, 8.0, 11, 120)
+    for t, (k, h, best) in zip(res["trace"], ref):
+        print(mode, t["iters"], k, t["hpwl_q"], h)
+        assert t["iters"] == k
+        assert abs(t["hpwl_q"] - h) <= 1e-6 * h
+        assert abs(t["best_hpwl_q"] - best) <= 1e-6 * best
+    pl.close()
+
+
+def test_alg1_invariants_mid():
+    """mid in FP32: the best HPWL never rises, equals the smallest round result, and every
+    placement stops at the overflow target or the iteration cap."""
+    from paper_2402_18311_amd import alg1, hybro
+    nl = netgen.make_netlist("mid", 0)
+    pl = hybro.Placer(nl, precision=32)
+    res = alg1.hybro(pl, 2, "gauss", 0.05, 8.0, seed=3, max_iters=600)
+    tr = res["trace"]
+    bests = [t["best_hpwl_q"] for t in tr]
+    assert all(b1 <= b0 for b0, b1 in zip(bests, bests[1:]))
+    assert bests[-1] == min(t["hpwl_q"] for t in tr) == res["best_hpwl_q"]
+    for t in tr:
+        assert t["overflow"] <= alg1.TAU_STOP or t["iters"] == 600
+    print([(t["iters"], t["hpwl_q"] / 65536, round(t["overflow"], 4)) for t in tr])
+    pl.close()
