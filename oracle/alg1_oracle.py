@@ -5,8 +5,10 @@ algorithm, not from the device driver (they share no code): place from the initi
 then each round perturbs the best solution (Sec. 4.2), places again and keeps the smaller exact
 HPWL (Eq. 1).  The placer's schedules and stopping rule are the ePlace-style reading recorded
 in the design notes:
-  * stop when the overflow (the D(s) <= eps measure of Eq. 1) is at most 0.10, or after
-    max_iters iterations; overflow and HPWL are looked at every 10 iterations;
+  * stop when the overflow (the D(s) <= eps measure of Eq. 1) is at most 0.10 and the HPWL
+    moved by at most 0.1% of itself over the last 10 iterations, or after max_iters
+    iterations; overflow and HPWL are looked at every 10 iterations (a look happens before
+    the first stop);
   * smoothing gamma = 4 bins x 10^((20/9) tau - 11/9) for the next 10 iterations, from the
     overflow tau at the last look;
   * the penalty weight lambda starts at 1e-4 |grad WL|_1 / |grad N|_1 (first evaluation) and is
@@ -37,7 +39,8 @@ def place_to_convergence(o, nl, x, y, max_iters):
     tau = o.eval(st["v"][:n], st["v"][n:], _gamma(1.0, nl.bin_w))["overflow"]
     h_prev = o.hpwl_q(st["u"][:n], st["u"][n:])
     lam, ratio, k = None, 1.05, 0
-    while k < max_iters and tau > 0.10:
+    level = False
+    while k < max_iters and not (tau <= 0.10 and level):
         g = _gamma(tau, nl.bin_w)
         for _ in range(min(10, max_iters - k)):
             r = o.eval(st["v"][:n], st["v"][n:], g)
@@ -50,6 +53,7 @@ def place_to_convergence(o, nl, x, y, max_iters):
             tau = r["overflow"]
             k += 1
         h = o.hpwl_q(st["u"][:n], st["u"][n:])
+        level = abs(h - h_prev) <= 0.001 * h_prev
         ratio = _mu(h, h_prev)
         h_prev = h
     return st["u"][:n].copy(), st["u"][n:].copy(), k, h_prev, tau

@@ -3,8 +3,9 @@ re-place it and keep the one with the smallest exact HPWL (Eq. 1).
 
 The paper leaves the analytical placer's schedules and stopping rule to the placer it builds
 on (Sec. 3.1).  This driver uses the ePlace-style rules (a reading):
-  * the placer runs until the density overflow tau (the D(s) <= eps measure of Eq. 1) falls to
-    TAU_STOP, or for at most `max_iters` iterations;
+  * the placer runs until the density overflow tau (the D(s) <= eps measure of Eq. 1) is at
+    most TAU_STOP and the HPWL has levelled off (it moved by at most PLATEAU of itself over the
+    last CHECK iterations), or for at most `max_iters` iterations;
   * every CHECK iterations the smoothing of Eq. 3 follows the overflow,
         gamma(tau) = GAMMA_BINS * bin * 10^((20/9) tau - 11/9),
     and the penalty weight of Eq. 2 is multiplied at every following step by
@@ -30,6 +31,7 @@ from . import netgen
 
 CHECK = 10
 TAU_STOP = 0.10
+PLATEAU = 1e-3
 GAMMA_BINS = 4.0
 MU_MAX, MU_MIN = 1.05, 0.95
 DH_REF = 3.5e-3
@@ -58,13 +60,15 @@ def global_place(pl, slot: int, max_iters: int) -> dict:
     h_prev = int(pl.hpwl(slot)[0])
     hy.hp_set_lambda_ratio(pl.ctx, slot, MU_MAX)
     k = 0
-    while k < max_iters and tau > TAU_STOP:
+    settled = False
+    while k < max_iters and not (tau <= TAU_STOP and settled):
         n = min(CHECK, max_iters - k)
         pl.iterate(slot, gamma_of(tau, nl.bin_w), n, hpwl=True)
         k += n
         st = pl.state(slot)
         tau = float(st["overflow"])
         h = int(st["hpwl_q"])
+        settled = abs(h - h_prev) <= PLATEAU * h_prev
         hy.hp_set_lambda_ratio(pl.ctx, slot, mu_of(h, h_prev))
         h_prev = h
     return {"iters": k, "hpwl_q": h_prev, "overflow": tau}
