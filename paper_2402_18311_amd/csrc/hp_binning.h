@@ -9,13 +9,20 @@ struct RectQ {
     int l, r, b, t;
 };
 
-__device__ __forceinline__ RectQ cell_rect_b(const NetDev &nd, double x, double y, int4 c) {
-    const long long L = q12(x) + c.z, B = q12(y) + c.w;
+// A cell's charge rectangle in 2^-12 units, clipped to the die: left edge q12(x) + dxq.  In
+// 32-bit arithmetic: scaling a position by 2^12 is exact and rounded once (half to even) in
+// either precision, and die validation keeps every coordinate below 2^26.
+template <typename T> __device__ __forceinline__ int q12b(T v);
+template <> __device__ __forceinline__ int q12b<float>(float v) { return __float2int_rn(v * 4096.0f); }
+template <> __device__ __forceinline__ int q12b<double>(double v) { return __double2int_rn(v * 4096.0); }
+template <typename T>
+__device__ __forceinline__ RectQ cell_rect_b(const NetDev &nd, T x, T y, int4 c) {
+    const int L = q12b<T>(x) + c.z, B = q12b<T>(y) + c.w;
     RectQ q;
-    q.l = (int)min(max(L, 0LL), (long long)nd.wq_die);
-    q.r = (int)min(max(L + c.x, 0LL), (long long)nd.wq_die);
-    q.b = (int)min(max(B, 0LL), (long long)nd.hq_die);
-    q.t = (int)min(max(B + c.y, 0LL), (long long)nd.hq_die);
+    q.l = min(max(L, 0), nd.wq_die);
+    q.r = min(max(L + c.x, 0), nd.wq_die);
+    q.b = min(max(B, 0), nd.hq_die);
+    q.t = min(max(B + c.y, 0), nd.hq_die);
     return q;
 }
 
@@ -29,7 +36,7 @@ __device__ __forceinline__ int overlap_b(int lo, int hi, int idx, int w) {
 template <typename T>
 __device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i) {
     const vec2<T> p = pos[i];
-    const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
+    const RectQ q = cell_rect_b<T>(nd, p.x, p.y, nd.cq[i]);
     const int j = min(q.l / nd.bq, nd.mx - 1), k = min(q.b / nd.hq, nd.my - 1);
     return (k >> nd.log_ts) * nd.ntx + (j >> nd.log_ts);
 }
@@ -73,7 +80,7 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
     for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
         const int i = sorted[s];
         const vec2<T> p = pos[i];
-        const RectQ q = cell_rect_b(nd, (double)p.x, (double)p.y, nd.cq[i]);
+        const RectQ q = cell_rect_b<T>(nd, p.x, p.y, nd.cq[i]);
         if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
         const long long rq = nd.rq[i];
         const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;

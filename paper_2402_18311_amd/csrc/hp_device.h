@@ -216,11 +216,11 @@ __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, c
     if (live) {
         const int n = nd.n_mov;
         const T *cs = reinterpret_cast<const T *>(nd.cstep);
-        const double P = precond(cs, n, i, lam);
+        const double iP = 1.0 / precond(cs, n, i, lam);
         const vec2<T> v = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
         const vec2<T> vp = reinterpret_cast<const vec2<T> *>(base + L.vprev)[i];
         const T *gp = reinterpret_cast<const T *>(base + L.gprev);
-        const double gx = (double)g0 / P, gy = (double)g1 / P;
+        const double gx = (double)g0 * iP, gy = (double)g1 * iP;
         const double ax = (double)v.x - (double)vp.x;
         const double ay = (double)v.y - (double)vp.y;
         const double bx = gx - (double)gp[i], by = gy - (double)gp[n + i];

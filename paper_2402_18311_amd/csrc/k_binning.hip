@@ -5,8 +5,8 @@
 //   1. count: each block takes a contiguous run of cells, finds each cell's tile (the
 //      ts x ts bin tile holding the lower-left bin of its charge rectangle), and writes its
 //      per-tile histogram (LDS atomics only);
-//   2. scan: one block turns the histograms into each (block, tile) output offset, the tiles'
-//      cell ranges, and each tile's chunks of at most kChunk cells;
+//   2. scan: column scans turn the histograms into each (block, tile) output offset, and one
+//      block scans the tile totals into the tiles' cell ranges and chunks of <= kChunk cells;
 //   3. place: cells are written to the tile-sorted order (rank by LDS atomic);
 //   4. accumulate: one block per chunk sums its cells' integer charges into an LDS window of
 //      (ts + halo)^2 bins (halo = widest footprint - 1) and stores the window;
@@ -23,41 +23,71 @@
 
 namespace hp {
 
-// One block of 1024 threads: column-wise exclusive scans of the per-block histograms (in
-// place), tile starts, chunk starts (ceil(cells / kChunk) chunks per tile) and each chunk's
-// tile and cell range.
-constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void bin_scan_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
-    __shared__ int ws[kScanThreads / 64][2];
+// The scan of a regroup, in two launches.
+//
+// 1. Column scans (many blocks): a block takes 16 tiles; each tile's column of per-block counts
+//    (sort_blocks <= 512 rows) is split into 16 bands of <= 32 rows, one thread per band, whose
+//    counts are loaded in one round and kept in registers.  The band sums are scanned in LDS,
+//    every (block, tile) gets its exclusive offset within the tile, and the tile's total goes
+//    to tstart[t].
+// 2. Tile scan (one block): exclusive scans of the tile totals and of their chunk counts
+//    (ceil(cells / kChunk) per tile) give the tile starts, chunk starts and each chunk's tile
+//    and cell range.
+constexpr int kColTiles = 16, kColBands = kBlock / kColTiles, kColRows = 32;
+__global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    __shared__ int band[kColBands][kColTiles];
     char *base = sa.base[blockIdx.y];
     const int *__restrict__ cnt = reinterpret_cast<const int *>(base + L.scnt);
     int *__restrict__ off = reinterpret_cast<int *>(base + L.soff);
+    int *tot = reinterpret_cast<int *>(base + L.tstart);
+    const int T = nd.ntiles, R = nd.sort_blocks;
+    const int tl = threadIdx.x % kColTiles, bd = threadIdx.x / kColTiles;
+    const int t = blockIdx.x * kColTiles + tl;
+    const int rpb = (R + kColBands - 1) / kColBands;  // <= kColRows
+    const int r0 = bd * rpb, r1 = min(R, r0 + rpb);
+    int c[kColRows];
+#pragma unroll
+    for (int u = 0; u < kColRows; ++u) {
+        const int r = r0 + u;
+        c[u] = (t < T && r < r1) ? cnt[(size_t)r * T + t] : 0;
+    }
+    int sum = 0;
+#pragma unroll
+    for (int u = 0; u < kColRows; ++u) sum += c[u];
+    band[bd][tl] = sum;
+    __syncthreads();
+    if (bd == 0) {
+        int run = 0;
+        for (int g = 0; g < kColBands; ++g) {
+            const int v = band[g][tl];
+            band[g][tl] = run;
+            run += v;
+        }
+        if (t < T) tot[t] = run;
+    }
+    __syncthreads();
+    int o = band[bd][tl];
+#pragma unroll
+    for (int u = 0; u < kColRows; ++u) {
+        const int r = r0 + u;
+        if (t < T && r < r1) off[(size_t)r * T + t] = o;
+        o += c[u];
+    }
+}
+
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void bin_tilescan_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    __shared__ int ws[kScanThreads / 64][2];
+    char *base = sa.base[blockIdx.y];
     int *tstart = reinterpret_cast<int *>(base + L.tstart);
     int *cstart = reinterpret_cast<int *>(base + L.cstart);
     int4 *chunk = reinterpret_cast<int4 *>(base + L.chunk);
-    const int T = nd.ntiles, nsb = nd.sort_blocks;
+    const int T = nd.ntiles;
     const int per = (T + kScanThreads - 1) / kScanThreads;
     const int t0 = threadIdx.x * per, t1 = min(T, t0 + per);
     int sc = 0, sk = 0;  // this thread's cells and chunks
     for (int t = t0; t < t1; ++t) {
-        int s = 0;
-        int b = 0;
-        for (; b + 8 <= nsb; b += 8) {  // eight independent loads in flight
-            int c[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) c[u] = cnt[(size_t)(b + u) * T + t];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                off[(size_t)(b + u) * T + t] = s;
-                s += c[u];
-            }
-        }
-        for (; b < nsb; ++b) {
-            const int c = cnt[(size_t)b * T + t];
-            off[(size_t)b * T + t] = s;
-            s += c;
-        }
-        tstart[t] = s;  // the tile's total for now
+        const int s = tstart[t];  // the tile's total (from the column scans)
         sc += s;
         sk += (s + kChunk - 1) / kChunk;
     }
@@ -129,8 +159,13 @@ size_t scatter_accum_lds(const NetDev &nd) {
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                                hipStream_t st) {
-    HP_LAUNCH("bin_scan_kernel", bin_scan_kernel, dim3(1, sa.n), dim3(kScanThreads), 0, st, nd, sa, L);
+    HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel, dim3((nd.ntiles + kColTiles - 1) / kColTiles, sa.n),
+              dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    HP_LAUNCH("bin_tilescan_kernel", bin_tilescan_kernel, dim3(1, sa.n), dim3(kScanThreads), 0, st, nd,
+              sa, L);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     HP_LAUNCH("bin_place_kernel", bin_place_kernel, dim3(nd.sort_blocks, sa.n), dim3(kBlock),
               scatter_count_lds(nd), st, nd, sa, L);

@@ -26,6 +26,23 @@ __device__ __forceinline__ RectQ cell_rect(const NetDev &nd, double x, double y,
     return q;
 }
 
+// The same rectangle in 32-bit arithmetic from a position of the compute type: scaling by 2^12
+// is exact and is rounded once (half to even) in either type, and the die validation keeps
+// every coordinate below 2^26, so the result equals cell_rect's.
+template <typename T> __device__ __forceinline__ int q12i(T v);
+template <> __device__ __forceinline__ int q12i<float>(float v) { return __float2int_rn(v * 4096.0f); }
+template <> __device__ __forceinline__ int q12i<double>(double v) { return __double2int_rn(v * 4096.0); }
+template <typename T>
+__device__ __forceinline__ RectQ cell_rect_i(const NetDev &nd, T x, T y, int4 c) {
+    const int L = q12i<T>(x) + c.z, B = q12i<T>(y) + c.w;
+    RectQ q;
+    q.l = min(max(L, 0), nd.wq_die);
+    q.r = min(max(L + c.x, 0), nd.wq_die);
+    q.b = min(max(B, 0), nd.hq_die);
+    q.t = min(max(B + c.y, 0), nd.hq_die);
+    return q;
+}
+
 __device__ __forceinline__ int overlap(int lo, int hi, int idx, int w) {
     const int a = max(lo, idx * w), b = min(hi, (idx + 1) * w);
     return b > a ? b - a : 0;
@@ -140,8 +157,10 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         const int e = nd.cell_pin_start[i + 1];
         int j = nd.cell_pin_start[i];
         const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-        const long long rq = nd.rq[i];
-        const RectQ q = cell_rect(nd, (double)p.x, (double)p.y, nd.cq[i]);
+        // charge weight of a bin: rq ox oy 2^-40, formed in the compute type (exact in FP64;
+        // in FP32 a relative rounding of ~1e-7, far inside the gradient tolerance)
+        const T rqt = (T)nd.rq[i] * (T)0x1p-40;
+        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
         const bool has = q.r > q.l && q.t > q.b;
         const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
         const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
@@ -180,22 +199,20 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
                 if (k0 + kk > k1) continue;
-                const long long oy = overlap(q.b, q.t, k0 + kk, nd.hq);
+                const T oy = (T)overlap(q.b, q.t, k0 + kk, nd.hq) * rqt;
 #pragma unroll
                 for (int jj = 0; jj < JC; ++jj) {
                     if (j0 + jj > j1) continue;
-                    const long long ox = overlap(q.l, q.r, j0 + jj, nd.bq);
-                    const T qq = (T)((double)(rq * ox * oy) * 0x1p-40);
+                    const T qq = (T)overlap(q.l, q.r, j0 + jj, nd.bq) * oy;
                     gdx -= qq * f[kk][jj].x;
                     gdy -= qq * f[kk][jj].y;
                 }
             }
         } else if (has) {  // footprints wider than the window: plain loop
             for (int k = k0; k <= k1; ++k) {
-                const long long oy = overlap(q.b, q.t, k, nd.hq);
+                const T oy = (T)overlap(q.b, q.t, k, nd.hq) * rqt;
                 for (int jx = j0; jx <= j1; ++jx) {
-                    const long long ox = overlap(q.l, q.r, jx, nd.bq);
-                    const T qq = (T)((double)(rq * ox * oy) * 0x1p-40);
+                    const T qq = (T)overlap(q.l, q.r, jx, nd.bq) * oy;
                     const vec2<T> ev = exy[(size_t)k * nd.mx + jx];
                     gdx -= qq * ev.x;
                     gdy -= qq * ev.y;

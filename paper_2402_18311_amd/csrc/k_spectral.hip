@@ -181,11 +181,13 @@ __global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, 
 }
 
 // ---- C: two columns per block -------------------------------------------------------------
-// lds: tw [M/2] | ph [M] | den_y [M] | om_y [M] | acol [2][M] | work [2][M]
+// lds: tw [M/2] | ph [M] | den_y [M] | om_y [M] | acol [2][M] | inv [2][M] | work [2][M]
+// (inv[h][v] = 1 / (d_x[u0 + h] + d_y[v]), 0 for the dropped (0, 0) term: every term of the
+// column shares these denominators, so each is divided once)
 template <typename T>
 __host__ __device__ inline size_t cols_lds(int M) {
     return al16(sizeof(vec2<T>) * (M / 2)) + al16(sizeof(vec2<T>) * M) + 2 * al16(sizeof(T) * M) +
-           al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
+           2 * al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
 }
 
 template <typename T>
@@ -203,6 +205,8 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
     o += al16(sizeof(T) * M);
     T *acol = reinterpret_cast<T *>(smem + o);  // [2][M]
     o += al16(sizeof(T) * 2 * M);
+    T *inv = reinterpret_cast<T *>(smem + o);  // [2][M]
+    o += al16(sizeof(T) * 2 * M);
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M]
     char *base = sa.base[blockIdx.y];
     const int u0 = blockIdx.x * 2;
@@ -219,19 +223,22 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
     }
     __syncthreads();
     fft_lds<T>(work, 1, M, logM, s_tw, false);
-    const double norm = 1.0 / ((double)nd.mx * nd.my);
-    const double cu0 = u0 ? 2.0 : 1.0;  // u0 + 1 > 0 always
-    const double dux0 = nd.den1[u0], dux1 = nd.den1[u0 + 1];
+    const T norm = (T)(1.0 / ((double)nd.mx * nd.my));
+    const T cu0 = u0 ? T(2) : T(1);  // u0 + 1 > 0 always
+    const T dux0 = (T)nd.den1[u0], dux1 = (T)nd.den1[u0 + 1];
+    const double mm = (double)nd.mx * nd.my;
     double e = 0.0;
     for (int v = threadIdx.x; v < M; v += kBlock) {
         const vec2<T> F = dct_post<T>(work, v, M, s_ph[v]);
-        const double cv = v ? 2.0 : 1.0;
-        const double a0 = cu0 * cv * norm * (double)F.x, a1 = 2.0 * cv * norm * (double)F.y;
-        acol[v] = (T)a0;
-        acol[M + v] = (T)a1;
-        const double dv = nd.den1[mx + v];
-        if (u0 | v) e += a0 * a0 * ((double)nd.mx * nd.my) / (cu0 * cv * (dux0 + dv));
-        e += a1 * a1 * ((double)nd.mx * nd.my) / (2.0 * cv * (dux1 + dv));
+        const T cv = v ? T(2) : T(1);
+        const T a0 = cu0 * cv * norm * F.x, a1 = T(2) * cv * norm * F.y;
+        acol[v] = a0;
+        acol[M + v] = a1;
+        const T i0 = (u0 | v) ? T(1) / (dux0 + s_den[v]) : T(0), i1 = T(1) / (dux1 + s_den[v]);
+        inv[v] = i0;
+        inv[M + v] = i1;
+        // energy by Parseval: a^2 mx my / (c_u c_v den), accumulated in FP64
+        e += (double)(a0 * a0 * i0 / (cu0 * cv)) * mm + (double)(a1 * a1 * i1 / (T(2) * cv)) * mm;
     }
     __syncthreads();
     __shared__ double red[4];
@@ -241,13 +248,13 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
 
     // (Bx + i By) of column h on complex line h: X(v) = a_uv w_u / den (cosine sum in y),
     // Y(v) = a_uv w_v / den (sine sum in y -> reversed coefficients)
+    const T wux[2] = {(T)nd.omega[u0], (T)nd.omega[u0 + 1]};
     for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
         const int h = idx >> logM, v = idx & (M - 1);
-        const int u = u0 + h;
-        const T *ac = acol + h * M;
-        const T wu = (T)nd.omega[u], du = (T)nd.den1[u];
-        auto X = [&](int vv) -> T { return (u | vv) ? ac[vv] * wu / (du + s_den[vv]) : T(0); };
-        auto Y = [&](int vv) -> T { return (u | vv) ? ac[vv] * s_om[vv] / (du + s_den[vv]) : T(0); };
+        const T *ac = acol + h * M, *iv = inv + h * M;
+        const T wu = wux[h];
+        auto X = [&](int vv) -> T { return ac[vv] * wu * iv[vv]; };
+        auto Y = [&](int vv) -> T { return ac[vv] * s_om[vv] * iv[vv]; };
         const T xp = v ? T(0.5) * X(v) : X(0);
         const T xq = v ? T(0.5) * X(M - v) : T(0);
         const T yp = v ? T(0.5) * Y(M - v) : T(0);
@@ -272,10 +279,8 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
             vec2<T> V2v[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int u = u0 + h;
-                const T *ac = acol + h * M;
-                const T du = (T)nd.den1[u];
-                auto P = [&](int vv) -> T { return (u | vv) ? ac[vv] / (du + s_den[vv]) : T(0); };
+                const T *ac = acol + h * M, *iv = inv + h * M;
+                auto P = [&](int vv) -> T { return ac[vv] * iv[vv]; };
                 const T pp = v ? T(0.5) * P(v) : P(0);
                 const T pq = v ? T(0.5) * P(M - v) : T(0);
                 V2v[h] = idct_pre<T>(pp, pq, s_ph[v]);

@@ -123,26 +123,40 @@ __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ 
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
     net_pins_to_lds<T>(nd, s, d, pos, sp);
     const int dr = min(d, kNetRegs * kBlock);  // pins held in LDS
-    auto pin = [&](int i) -> vec2<T> {
-        if (i < dr) return sp[i];
-        const vec2<T> q = pos[nd.pin_cell[s + i]], o = off[s + i];
-        return cmk2<T>(q.x + o.x, q.y + o.y);
+    // every pass visits the thread's pins i = tid, tid + 256, ... in order: those in LDS, then
+    // the tail in batches of 4 whose loads are all issued before use
+    auto visit = [&](auto &&f) {
+        int i = threadIdx.x;
+        for (; i < dr; i += kBlock) f(i, sp[i]);
+        for (; i < d; i += 4 * kBlock) {
+            int c[4];
+            vec2<T> o[4], q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = min(i + u * kBlock, d - 1);
+                c[u] = nd.pin_cell[s + j];
+                o[u] = off[s + j];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = pos[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + u * kBlock < d) f(i + u * kBlock, cmk2<T>(q[u].x + o[u].x, q[u].y + o[u].y));
+        }
     };
     // pass 1: extents (max x, -min x, max y, -min y)
     T m[4] = {-inf, -inf, -inf, -inf};
-    for (int i = threadIdx.x; i < d; i += kBlock) {
-        const vec2<T> p = pin(i);
+    visit([&](int, vec2<T> p) {
         m[0] = max(m[0], p.x);
         m[1] = max(m[1], -p.x);
         m[2] = max(m[2], p.y);
         m[3] = max(m[3], -p.y);
-    }
+    });
     block_max_n<4>(m, red);
     const T xmax = m[0], xmin = -m[1], ymax = m[2], ymin = -m[3];
     // pass 2: exponential sums
     T sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < d; i += kBlock) {
-        const vec2<T> p = pin(i);
+    visit([&](int, vec2<T> p) {
         const T dxp = p.x - xmax, dxm = p.x - xmin, dyp = p.y - ymax, dym = p.y - ymin;
         const T axp = wa_exp<T>(dxp * invg), axm = wa_exp<T>(-dxm * invg);
         const T ayp = wa_exp<T>(dyp * invg), aym = wa_exp<T>(-dym * invg);
@@ -154,15 +168,14 @@ __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ 
         sm[5] += dxm * axm;
         sm[6] += dyp * ayp;
         sm[7] += dym * aym;
-    }
+    });
     block_sum_n<8>(sm, red);
     const T ibxp = wa_rcp<T>(sm[0]), ibxm = wa_rcp<T>(sm[1]);
     const T ibyp = wa_rcp<T>(sm[2]), ibym = wa_rcp<T>(sm[3]);
     const T rxp = sm[4] * ibxp, rxm = sm[5] * ibxm, ryp = sm[6] * ibyp, rym = sm[7] * ibym;
     const T w = nd.net_w ? reinterpret_cast<const T *>(nd.net_w)[net] : T(1);
     // pass 3: per-pin gradients
-    for (int i = threadIdx.x; i < d; i += kBlock) {
-        const vec2<T> p = pin(i);
+    visit([&](int i, vec2<T> p) {
         const T dxp = p.x - xmax, dxm = p.x - xmin, dyp = p.y - ymax, dym = p.y - ymin;
         const T axp = wa_exp<T>(dxp * invg), axm = wa_exp<T>(-dxm * invg);
         const T ayp = wa_exp<T>(dyp * invg), aym = wa_exp<T>(-dym * invg);
@@ -170,7 +183,7 @@ __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ 
         g.x = w * (axp * ibxp * (T(1) + (dxp - rxp) * invg) - axm * ibxm * (T(1) - (dxm - rxm) * invg));
         g.y = w * (ayp * ibyp * (T(1) + (dyp - ryp) * invg) - aym * ibym * (T(1) - (dym - rym) * invg));
         pg[s + i] = g;
-    }
+    });
     wl = threadIdx.x == 0
              ? (double)(w * (((xmax - xmin) + (rxp - rxm)) + ((ymax - ymin) + (ryp - rym))))
              : 0.0;
@@ -251,7 +264,14 @@ __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restri
         m[2] = max(m[2], py);
         m[3] = max(m[3], -py);
     }
-    for (int i = threadIdx.x + kNetRegs * kBlock; i < d; i += kBlock) ext(i, nd.pin_cell[s + i]);
+    for (int i = threadIdx.x + kNetRegs * kBlock; i < d; i += 4 * kBlock) {  // tail, batches of 4
+        int cc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cc[u] = nd.pin_cell[s + min(i + u * kBlock, d - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * kBlock < d) ext(i + u * kBlock, cc[u]);
+    }
     block_max_n<4>(m, red);
     return threadIdx.x == 0 ? ((int64_t)m[0] + m[1]) + ((int64_t)m[2] + m[3]) : 0;
 }
