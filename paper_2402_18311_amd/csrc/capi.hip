@@ -291,20 +291,24 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
         return fail(HP_EINVAL, "bin grid too large for this device's LDS at this precision");
 
     // ---- degree buckets -------------------------------------------------------------------
-    // order: block-per-net (largest first), then groups of 64, 32, ..., 2 lanes
-    const int Gs[7] = {0, 64, 32, 16, 8, 4, 2};
-    // Group buckets are laid out padded: net j of the bucket owns pin slots
+    // order: block-per-net (largest first), then waves with 256 and 128 slots per net, then
+    // groups of 64, 32, ..., 2 lanes
+    constexpr int NB = 9;
+    const int Gs[NB] = {0, 256, 128, 64, 32, 16, 8, 4, 2};
+    // Every bucket but the first is laid out padded: net j of the bucket owns pin slots
     // [pin0 + j G, pin0 + (j + 1) G), its pins first, the rest marked by cell -1, so a lane
-    // finds its pin slot from its index alone.  Each block takes kNetsPerLane x (256 / G) nets.
-    std::vector<std::vector<int>> members(7);
+    // finds its pin slots from its index alone (G < 2d, so at most 2P slots).  Each block
+    // takes kNetsPerLane x (256 / G) nets of a group bucket, 4 nets (one per wave) of a wave
+    // bucket, one net of the first.
+    std::vector<std::vector<int>> members(NB);
     for (int e = 0; e < E; ++e) {
         const int d = net_start[e + 1] - net_start[e];
         if (d < 2) continue;
         int b = 0;
-        if (d <= 64) {
+        if (d <= 256) {
             int G = 2;
             while (G < d) G <<= 1;
-            b = 1 + (6 - ilog2(G));
+            b = 1 + (8 - ilog2(G));
         }
         members[b].push_back(e);
     }
@@ -320,17 +324,17 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             for (int p = net_start[e]; p < net_start[e + 1]; ++p) m = std::min(m, pin_cell[p]);
             minc[e] = m;
         }
-        for (int b = 1; b < 7; ++b)
+        for (int b = 1; b < NB; ++b)
             std::stable_sort(members[b].begin(), members[b].end(),
                              [&](int a, int c) { return minc[a] < minc[c]; });
     }
     std::vector<int> order;
     Buckets bk{};
     int blk = 0;
-    for (int b = 0; b < 7; ++b) {
+    for (int b = 0; b < NB; ++b) {
         if (members[b].empty()) continue;
         const int G = Gs[b];
-        const int npb = G ? kNetsPerLane * (kBlock / G) : 1;
+        const int npb = G == 0 ? 1 : G > 64 ? kBlock / 64 : kNetsPerLane * (kBlock / G);
         int nblk = ((int)members[b].size() + npb - 1) / npb;
         nblk = (nblk + kXcds - 1) / kXcds * kXcds;
         bk.G[bk.n] = G;

@@ -8,7 +8,7 @@ namespace hp {
 
 constexpr int kBlock = 256;      // threads per block for every kernel
 constexpr int kMaxSlots = 32;    // slots per launch (longer lists are chunked)
-constexpr int kMaxBuckets = 8;
+constexpr int kMaxBuckets = 12;
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
 constexpr int kChunk = 2048;     // cells per accumulation block of the binned scatter
 constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
@@ -20,16 +20,17 @@ template <> struct V2<double> { using type = double2; };
 template <typename T> using vec2 = typename V2<T>::type;
 
 // Degree buckets of the net sweep: nets with 2..64 pins are processed by a group of G
-// lanes (G = next power of two >= degree; kNetsPerLane nets per group), larger ones by a
-// whole block.
+// lanes (G = next power of two >= degree; kNetsPerLane nets per group), nets with 65..256
+// pins by one wave each (G = next power of two >= degree slots, G / 64 pins per lane), larger
+// ones by a whole block.
 struct Buckets {
     int32_t n;
-    int32_t G[kMaxBuckets];      // group size, or 0 for block-per-net
+    int32_t G[kMaxBuckets];      // pin slots per net (group size up to 64), 0: block-per-net
     int32_t net0[kMaxBuckets];   // first (sorted) net of the bucket
     int32_t net1[kMaxBuckets];
     int32_t blk0[kMaxBuckets];   // first block; every bucket has a multiple of 8 blocks
     int32_t nblk[kMaxBuckets];
-    int32_t pin0[kMaxBuckets];   // group buckets: first pin slot (G slots per net, padded)
+    int32_t pin0[kMaxBuckets];   // padded buckets: first pin slot (G slots per net)
     int32_t total_blocks;
 };
 

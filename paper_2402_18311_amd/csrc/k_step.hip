@@ -1,6 +1,6 @@
 // Closing reductions of an evaluation and of the HPWL sweep, the preconditioned Nesterov step,
 // the first-evaluation gradient combination, and the best-of selection of Alg. 1.  Every total
-// is a fixed-order reduction of per-block partials (thread t sums partials t, t+256, ... then
+// is a fixed-order reduction of per-block partials (thread t sums partials t, t + blockDim, ... then
 // a fixed tree) by one block per slot, so repeated runs are bit-identical.
 #include "hp_device.h"
 
@@ -10,19 +10,23 @@ namespace hp {
 // evaluation with the scheduled lambda (scale * |grad WL|_1 / |grad N|_1); the lambda the
 // following step preconditions with and, in steady state, that step's proposal from the
 // reductions the cell-gradient pass formed.
-__global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                            int nwl, int ne, int nov, int ncell,
-                                                            int use_fixed, double lam_fixed) {
-    __shared__ double rs[4][4], rm[4];
-    __shared__ long long ri[4];
+// One 1024-thread block per slot: the partial counts reach tens of thousands at millions of
+// cells, and a single block is latency bound, so it keeps 16 waves of loads in flight.
+constexpr int kFinBlock = 1024;
+constexpr int kFinWaves = kFinBlock / 64;
+
+__global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                               int nwl, int ne, int nov, int ncell,
+                                                               int use_fixed, double lam_fixed) {
+    __shared__ double rs[kFinWaves][4], rm[kFinWaves];
+    __shared__ long long ri[kFinWaves];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
     const bool init = !use_fixed && sc->lambda_valid == 0;
     const bool prop = !init && ncell > 0;
     // One pass over all partial arrays with their loads in flight together (thread t takes
-    // elements t, t + 256, ... of each, in order), then one block tree for all totals (the
-    // trees of block_sum / block_max).
+    // elements t, t + 1024, ... of each, in order), then a fixed tree over the waves.
     const double *pw = part + PART_WL * L.pstride, *pe = part + PART_E * L.pstride;
     const double *pa = part + (init ? PART_N1 : PART_DV) * L.pstride;
     const double *pb = part + (init ? PART_N2 : PART_DG) * L.pstride;
@@ -33,12 +37,12 @@ __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     double gm = 0.0;
     long long ov = 0;
-    for (int i = threadIdx.x; i < nmax; i += 4 * kBlock) {
+    for (int i = threadIdx.x; i < nmax; i += 4 * kFinBlock) {
         double a[4][5];
         long long o[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int j = i + u * kBlock;
+            const int j = i + u * kFinBlock;
             a[u][0] = j < nwl ? pw[j] : 0.0;
             a[u][1] = j < ne ? pe[j] : 0.0;
             a[u][2] = j < nab ? pa[j] : 0.0;
@@ -67,11 +71,39 @@ __global__ __launch_bounds__(kBlock) void eval_finish_kernel(NetDev nd, SlotArgs
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // Pairwise tree over the 16 wave totals.
         double t[4];
+        double GM;
+        long long OV;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t[j] = (rs[0][j] + rs[1][j]) + (rs[2][j] + rs[3][j]);
-        const double GM = fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3]));
-        const long long OV = (ri[0] + ri[1]) + (ri[2] + ri[3]);
+        for (int j = 0; j < 4; ++j) {
+            double q[kFinWaves];
+#pragma unroll
+            for (int k = 0; k < kFinWaves; ++k) q[k] = rs[k][j];
+#pragma unroll
+            for (int h = kFinWaves / 2; h > 0; h >>= 1)
+#pragma unroll
+                for (int k = 0; k < h; ++k) q[k] += q[k + h];
+            t[j] = q[0];
+        }
+        {
+            double q[kFinWaves];
+            long long qi[kFinWaves];
+#pragma unroll
+            for (int k = 0; k < kFinWaves; ++k) {
+                q[k] = rm[k];
+                qi[k] = ri[k];
+            }
+#pragma unroll
+            for (int h = kFinWaves / 2; h > 0; h >>= 1)
+#pragma unroll
+                for (int k = 0; k < h; ++k) {
+                    q[k] = fmax(q[k], q[k + h]);
+                    qi[k] += qi[k + h];
+                }
+            GM = q[0];
+            OV = qi[0];
+        }
         sc->wl = t[0];
         sc->energy = 0.5 * nd.wb * nd.hb * t[1];
         sc->overflow_num = OV;
@@ -102,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void hpwl_finish_kernel(SlotArgs sa, SlotLa
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
                               hipStream_t st) {
-    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd, sa,
+    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kFinBlock), 0, st, nd, sa,
               L, nwl, ne, nov, ncell, (int)use_fixed, lam_fixed);
     return hipGetLastError();
 }

@@ -6,8 +6,10 @@
 // so that a lane finds its pin without reading the net's start: the pin loads of a wave are
 // contiguous (coalesced), the cell-position loads (one interleaved (x, y) pair per pin) are
 // the only gathers, and the max/min/exp-sum reductions are xor butterflies inside the group.
-// A larger net gets a whole block, which stages up to 2048 of its pin coordinates in LDS for
-// its three passes (max/min, exp sums, gradients).  Within a bucket nets are ordered by their
+// A net with 65..256 pins gets one wave, in the same padded layout with S = 64 PPL slots
+// (PPL = 2 or 4 pins per lane, lane l holding slots l, l + 64, ...), its reductions within the
+// wave; a larger net gets a whole block, which stages up to 2048 of its pin coordinates in
+// LDS for its three passes (max/min, exp sums, gradients).  Within a bucket nets are ordered by their
 // lowest cell, and the blocks of each bucket are remapped so that every XCD walks one
 // contiguous eighth of it: neighbouring lanes then gather neighbouring cells, and each XCD's
 // gathers stay in a compact cell range.
@@ -80,6 +82,89 @@ __device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, i
         if (vnet && lane == 0)
             wl += (double)(w * (((xmax - xmin) + (rxp - rxm)) + ((ymax - ymin) + (ryp - rym))));
     }
+}
+
+// Wave-per-net sweep of a padded bucket with S = 64 PPL slots per net: each wave takes one net
+// and each lane PPL of its pins (all loads issued before use), sums over them in slot order,
+// then the wave's butterflies.
+template <typename T, int PPL>
+__device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int b, int local,
+                                        const vec2<T> *__restrict__ pos, T invg,
+                                        vec2<T> *__restrict__ pg, double &wl) {
+    constexpr int S = 64 * PPL;
+    const int lane = threadIdx.x & 63;
+    const int net0 = bk.net0[b], net1 = bk.net1[b];
+    const int net = net0 + local * (kBlock / 64) + (int)threadIdx.x / 64;
+    const bool vnet = net < net1;
+    const int p0 = bk.pin0[b] + (vnet ? (net - net0) * S : 0) + lane;
+    const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
+    int c[PPL];
+    vec2<T> o[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        c[k] = nd.pin_cell[p0 + 64 * k];
+        o[k] = off[p0 + 64 * k];
+    }
+    vec2<T> q[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) q[k] = pos[max(c[k], 0)];
+    const T inf = pos_inf<T>();
+    T px[PPL], py[PPL];
+    T xM = -inf, xm = inf, yM = -inf, ym = inf;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        if (!vnet) c[k] = -1;
+        px[k] = c[k] >= 0 ? q[k].x + o[k].x : T(0);
+        py[k] = c[k] >= 0 ? q[k].y + o[k].y : T(0);
+        if (c[k] >= 0) {
+            xM = max(xM, px[k]);
+            xm = min(xm, px[k]);
+            yM = max(yM, py[k]);
+            ym = min(ym, py[k]);
+        }
+    }
+    xM = group_max<64>(xM);
+    xm = group_min<64>(xm);
+    yM = group_max<64>(yM);
+    ym = group_min<64>(ym);
+    // the exponentials are formed again in the gradient pass rather than held (register
+    // pressure sets the occupancy of the whole first launch)
+    T sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        const bool act = c[k] >= 0;
+        const T dxp = act ? px[k] - xM : T(0), dxm = act ? px[k] - xm : T(0);
+        const T dyp = act ? py[k] - yM : T(0), dym = act ? py[k] - ym : T(0);
+        const T axp = act ? wa_exp<T>(dxp * invg) : T(0), axm = act ? wa_exp<T>(-dxm * invg) : T(0);
+        const T ayp = act ? wa_exp<T>(dyp * invg) : T(0), aym = act ? wa_exp<T>(-dym * invg) : T(0);
+        sm[0] += axp;
+        sm[1] += axm;
+        sm[2] += ayp;
+        sm[3] += aym;
+        sm[4] += dxp * axp;
+        sm[5] += dxm * axm;
+        sm[6] += dyp * ayp;
+        sm[7] += dym * aym;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sm[j] = group_sum<64>(sm[j]);
+    // an invalid wave (past the bucket's end) has only zero sums; it writes nothing
+    const T ibxp = wa_rcp<T>(sm[0]), ibxm = wa_rcp<T>(sm[1]);
+    const T ibyp = wa_rcp<T>(sm[2]), ibym = wa_rcp<T>(sm[3]);
+    const T rxp = sm[4] * ibxp, rxm = sm[5] * ibxm, ryp = sm[6] * ibyp, rym = sm[7] * ibym;
+    const T w = (vnet && nd.net_w) ? reinterpret_cast<const T *>(nd.net_w)[net] : T(1);
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        if (c[k] < 0) continue;
+        const T dxp = px[k] - xM, dxm = px[k] - xm, dyp = py[k] - yM, dym = py[k] - ym;
+        const T axp = wa_exp<T>(dxp * invg), axm = wa_exp<T>(-dxm * invg);
+        const T ayp = wa_exp<T>(dyp * invg), aym = wa_exp<T>(-dym * invg);
+        const T gx = axp * ibxp * (T(1) + (dxp - rxp) * invg) - axm * ibxm * (T(1) - (dxm - rxm) * invg);
+        const T gy = ayp * ibyp * (T(1) + (dyp - ryp) * invg) - aym * ibym * (T(1) - (dym - rym) * invg);
+        pg[p0 + 64 * k] = cmk2<T>(w * gx, w * gy);
+    }
+    if (vnet && lane == 0)
+        wl += (double)(w * (((xM - xm) + (rxp - rxm)) + ((yM - ym) + (ryp - rym))));
 }
 
 // Block-per-net sweep.  The first kNetRegs * kBlock pins of the net are loaded once, with all
@@ -229,6 +314,44 @@ __device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, const Buckets &
     return h;
 }
 
+// Wave-per-net HPWL of a padded bucket with S = 64 PPL slots per net (see wa_wave).
+template <typename T, int PPL>
+__device__ __forceinline__ int64_t hpwl_wave(const NetDev &nd, const Buckets &bk, int b, int local,
+                                             const vec2<T> *__restrict__ pos) {
+    constexpr int S = 64 * PPL;
+    const int lane = threadIdx.x & 63;
+    const int net0 = bk.net0[b], net1 = bk.net1[b];
+    const int net = net0 + local * (kBlock / 64) + (int)threadIdx.x / 64;
+    const bool vnet = net < net1;
+    const int p0 = bk.pin0[b] + (vnet ? (net - net0) * S : 0) + lane;
+    int c[PPL];
+    int2 o[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        c[k] = nd.pin_cell[p0 + 64 * k];
+        o[k] = nd.pin_offq[p0 + 64 * k];
+    }
+    vec2<T> q[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) q[k] = pos[max(c[k], 0)];
+    int xM = INT_MIN, xm = INT_MAX, yM = INT_MIN, ym = INT_MAX;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        if (vnet && c[k] >= 0) {
+            const int px = q16i<T>(q[k].x) + o[k].x, py = q16i<T>(q[k].y) + o[k].y;
+            xM = max(xM, px);
+            xm = min(xm, px);
+            yM = max(yM, py);
+            ym = min(ym, py);
+        }
+    }
+    xM = group_max<64>(xM);
+    xm = group_min<64>(xm);
+    yM = group_max<64>(yM);
+    ym = group_min<64>(ym);
+    return (vnet && lane == 0) ? ((int64_t)xM - xm) + ((int64_t)yM - ym) : 0;
+}
+
 template <typename T>
 __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restrict__ pos) {
     __shared__ int red[4 * 4];
@@ -297,6 +420,8 @@ __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, 
             case 16: wa_groups<T, 16>(nd, bk, b, local, pos, invg, pg, wl); break;
             case 32: wa_groups<T, 32>(nd, bk, b, local, pos, invg, pg, wl); break;
             case 64: wa_groups<T, 64>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 128: wa_wave<T, 2>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 256: wa_wave<T, 4>(nd, bk, b, local, pos, invg, pg, wl); break;
             default:
                 if (net0 + local < net1) wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
                 break;
@@ -314,6 +439,8 @@ __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, 
             case 16: h = hpwl_groups<T, 16>(nd, bk, b, local, pos); break;
             case 32: h = hpwl_groups<T, 32>(nd, bk, b, local, pos); break;
             case 64: h = hpwl_groups<T, 64>(nd, bk, b, local, pos); break;
+            case 128: h = hpwl_wave<T, 2>(nd, bk, b, local, pos); break;
+            case 256: h = hpwl_wave<T, 4>(nd, bk, b, local, pos); break;
             default:
                 if (net0 + local < net1) h = hpwl_block<T>(nd, net0 + local, pos);
                 break;
