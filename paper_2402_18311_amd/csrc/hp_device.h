@@ -204,13 +204,13 @@ __device__ __forceinline__ double precond(const T *cs, int n, int i, double lam)
     return P < 1.0 ? 1.0 : P;
 }
 
-// The step's three reductions for the block's cells (cell i = blockIdx.x * 256 + threadIdx.x,
-// gradient (g0, g1) of cell i, valid when `live`): |v - v_prev|^2, |g~ - g~_prev|^2 and
-// max|g~| with g~ = g / P, stored as the block's partials.  `red` holds >= 12 doubles.  Both the step kernels and the
-// fused cell-gradient pass call this, so their partials are identical.
+// The step's three reductions for cell block cb (cell i = cb * 256 + threadIdx.x, gradient
+// (g0, g1) of cell i, valid when `live`): |v - v_prev|^2, |g~ - g~_prev|^2 and max|g~| with
+// g~ = g / P, stored as partial cb.  `red` holds >= 12 doubles.  Both the step kernels and
+// the fused cell-gradient pass call this, so their partials are identical.
 template <typename T>
 __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, const SlotLayout &L,
-                                                 int i, bool live, T g0, T g1, double lam,
+                                                 int cb, int i, bool live, T g0, T g1, double lam,
                                                  double *red) {
     double dv = 0.0, dg = 0.0, gm = 0.0;
     if (live) {
@@ -242,9 +242,9 @@ __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, c
     __syncthreads();
     if (threadIdx.x == 0) {
         double *part = reinterpret_cast<double *>(base + L.part);
-        part[PART_DV * L.pstride + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-        part[PART_DG * L.pstride + blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
-        part[PART_GMAX * L.pstride + blockIdx.x] = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
+        part[PART_DV * L.pstride + cb] = (red[0] + red[1]) + (red[2] + red[3]);
+        part[PART_DG * L.pstride + cb] = (red[4] + red[5]) + (red[6] + red[7]);
+        part[PART_GMAX * L.pstride + cb] = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
     }
 }
 

@@ -138,13 +138,18 @@ __device__ void exact_adjoint(const NetDev &nd, const T *psi, int i, double x, d
 // the per-block L1 norms of both, from which lambda_0 is derived.  In steady state the block
 // also forms its partials of the following Nesterov step's reductions.
 template <typename T>
+// Cell block cb = xcd_remap(blockIdx.x) of nb blocks (the grid is nb rounded up to a multiple
+// of 8), so that each XCD walks one contiguous eighth of the cells: the pin gradients that
+// neighbouring cells share stay in that XCD's L2.
 __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                            double lam_fixed, int use_fixed,
-                                                           int grad_mode) {
+                                                           int grad_mode, int nb) {
+    const int cb = xcd_remap(blockIdx.x, gridDim.x);
+    if (cb >= nb) return;  // whole block: no barrier is skipped by part of it
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const bool init = !use_fixed && sc->lambda_valid == 0;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = cb * kBlock + threadIdx.x;
     T gwx = 0, gwy = 0, gdx = 0, gdy = 0;
     if (i < nd.n_mov) {
         // Loads are issued in dependency rounds, each round's loads all in flight before any
@@ -231,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         }
         // the following step's reductions, from the gradient just formed
         __shared__ double red[4 * 3];
-        step_block_norms<T>(nd, base, L, i, i < nd.n_mov, g0, g1, lam_step, red);
+        step_block_norms<T>(nd, base, L, cb, i, i < nd.n_mov, g0, g1, lam_step, red);
     } else {
         T *gd = reinterpret_cast<T *>(base + L.gd);
         if (i < nd.n_mov) {
@@ -245,8 +250,8 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         block_sum_n<2>(n, red);
         if (threadIdx.x == 0) {
             double *part = reinterpret_cast<double *>(base + L.part);
-            part[PART_N1 * L.pstride + blockIdx.x] = n[0];
-            part[PART_N2 * L.pstride + blockIdx.x] = n[1];
+            part[PART_N1 * L.pstride + cb] = n[0];
+            part[PART_N2 * L.pstride + cb] = n[1];
         }
     }
 }
@@ -314,8 +319,9 @@ hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayo
                             double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
                             int nov, hipStream_t st) {
     const int nb = std::max(1, cell_parts(nd));
-    HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(nb, sa.n), dim3(kBlock), 0, st, nd, sa,
-              L, lambda_fixed, (int)use_fixed, grad_mode);
+    const int grid = (nb + kXcds - 1) / kXcds * kXcds;
+    HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(grid, sa.n), dim3(kBlock), 0, st, nd,
+              sa, L, lambda_fixed, (int)use_fixed, grad_mode, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, st);

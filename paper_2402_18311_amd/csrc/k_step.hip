@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs 
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const T *g = reinterpret_cast<const T *>(base + L.g);
     const bool live = i < n;
-    step_block_norms<T>(nd, base, L, i, live, live ? g[i] : (T)0, live ? g[n + i] : (T)0,
+    step_block_norms<T>(nd, base, L, blockIdx.x, i, live, live ? g[i] : (T)0, live ? g[n + i] : (T)0,
                         sc->lambda_step, red);
 }
 

@@ -28,10 +28,13 @@ namespace hp {
 // padding lanes hold cell -1), so a lane's pin slot follows from its index: one round of
 // loads (cell index, offset) and one of gathers (position).  A block takes R = kNetsPerLane
 // consecutive runs of 256 / G nets; every lane issues the loads of its R nets before using any.
-template <typename T, int G>
+// With H, the same lanes also form the exact HPWL (Eq. 1) of the positions `posu` over the
+// same nets (the pin loads are shared; see hpwl_groups for the arithmetic), added to h.
+template <typename T, int G, bool H>
 __device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, int b, int local,
                                           const vec2<T> *__restrict__ pos, T invg,
-                                          vec2<T> *__restrict__ pg, double &wl) {
+                                          vec2<T> *__restrict__ pg, double &wl,
+                                          const vec2<T> *__restrict__ posu, int64_t &h) {
     constexpr int NPB = kBlock / G, R = kNetsPerLane;
     const int lane = threadIdx.x & (G - 1);
     const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
@@ -40,16 +43,32 @@ __device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, i
     // reads the bucket's first slot, a padding lane's cell -1 reads cell 0; both are ignored
     int net[R], p[R], c[R];
     vec2<T> o[R];
+    int2 oq[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         net[r] = net0 + (local * R + r) * NPB + (int)threadIdx.x / G;
         p[r] = net[r] < net1 ? pin0 + (net[r] - net0) * G + lane : pin0;
         c[r] = nd.pin_cell[p[r]];
         o[r] = off[p[r]];
+        if constexpr (H) oq[r] = nd.pin_offq[p[r]];
     }
-    vec2<T> q[R];
+    vec2<T> q[R], qu[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) q[r] = pos[max(c[r], 0)];
+    for (int r = 0; r < R; ++r) {
+        q[r] = pos[max(c[r], 0)];
+        if constexpr (H) qu[r] = posu[max(c[r], 0)];
+    }
+    if constexpr (H) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool act = c[r] >= 0 && net[r] < net1;
+            const int ux = act ? q16i<T>(qu[r].x) + oq[r].x : 0;
+            const int uy = act ? q16i<T>(qu[r].y) + oq[r].y : 0;
+            const int xM = group_max<G>(act ? ux : INT_MIN), xm = group_min<G>(act ? ux : INT_MAX);
+            const int yM = group_max<G>(act ? uy : INT_MIN), ym = group_min<G>(act ? uy : INT_MAX);
+            if (act && lane == 0) h += ((int64_t)xM - xm) + ((int64_t)yM - ym);
+        }
+    }
     T px[R], py[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -87,10 +106,11 @@ __device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, i
 // Wave-per-net sweep of a padded bucket with S = 64 PPL slots per net: each wave takes one net
 // and each lane PPL of its pins (all loads issued before use), sums over them in slot order,
 // then the wave's butterflies.
-template <typename T, int PPL>
+template <typename T, int PPL, bool H>
 __device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int b, int local,
                                         const vec2<T> *__restrict__ pos, T invg,
-                                        vec2<T> *__restrict__ pg, double &wl) {
+                                        vec2<T> *__restrict__ pg, double &wl,
+                                        const vec2<T> *__restrict__ posu, int64_t &h) {
     constexpr int S = 64 * PPL;
     const int lane = threadIdx.x & 63;
     const int net0 = bk.net0[b], net1 = bk.net1[b];
@@ -100,14 +120,37 @@ __device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
     int c[PPL];
     vec2<T> o[PPL];
+    int2 oq[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         c[k] = nd.pin_cell[p0 + 64 * k];
         o[k] = off[p0 + 64 * k];
+        if constexpr (H) oq[k] = nd.pin_offq[p0 + 64 * k];
     }
-    vec2<T> q[PPL];
+    vec2<T> q[PPL], qu[PPL];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) q[k] = pos[max(c[k], 0)];
+    for (int k = 0; k < PPL; ++k) {
+        q[k] = pos[max(c[k], 0)];
+        if constexpr (H) qu[k] = posu[max(c[k], 0)];
+    }
+    if constexpr (H) {  // exact HPWL of posu over the same pins (see hpwl_wave)
+        int uM = INT_MIN, um = INT_MAX, vM = INT_MIN, vm = INT_MAX;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            if (vnet && c[k] >= 0) {
+                const int ux = q16i<T>(qu[k].x) + oq[k].x, uy = q16i<T>(qu[k].y) + oq[k].y;
+                uM = max(uM, ux);
+                um = min(um, ux);
+                vM = max(vM, uy);
+                vm = min(vm, uy);
+            }
+        }
+        uM = group_max<64>(uM);
+        um = group_min<64>(um);
+        vM = group_max<64>(vM);
+        vm = group_min<64>(vm);
+        if (vnet && lane == 0) h += ((int64_t)uM - um) + ((int64_t)vM - vm);
+    }
     const T inf = pos_inf<T>();
     T px[PPL], py[PPL];
     T xM = -inf, xm = inf, yM = -inf, ym = inf;
@@ -402,7 +445,9 @@ __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restri
 enum { MODE_WA = 0, MODE_HPWL = 1 };
 
 // Block `bx` (0 <= bx < bk.total_blocks) of a sweep of one slot: WA over v, or HPWL over u.
-template <typename T, int MODE>
+// MODE_WA with H: the WA sweep of v and the HPWL sweep of u in the same blocks, both partials
+// written.
+template <typename T, int MODE, bool H = false>
 __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, char *base,
                                            const SlotLayout &L, T invg, int bx) {
     int b = 0;
@@ -412,24 +457,35 @@ __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, 
     const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + (MODE == MODE_WA ? L.v : L.u));
     if constexpr (MODE == MODE_WA) {
         vec2<T> *pg = reinterpret_cast<vec2<T> *>(base + L.pin_grad);
+        const vec2<T> *posu = reinterpret_cast<const vec2<T> *>(base + L.u);
         double wl = 0.0;
+        int64_t h = 0;
         switch (bk.G[b]) {
-            case 2: wa_groups<T, 2>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 4: wa_groups<T, 4>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 8: wa_groups<T, 8>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 16: wa_groups<T, 16>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 32: wa_groups<T, 32>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 64: wa_groups<T, 64>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 128: wa_wave<T, 2>(nd, bk, b, local, pos, invg, pg, wl); break;
-            case 256: wa_wave<T, 4>(nd, bk, b, local, pos, invg, pg, wl); break;
+            case 2: wa_groups<T, 2, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 4: wa_groups<T, 4, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 8: wa_groups<T, 8, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 16: wa_groups<T, 16, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 32: wa_groups<T, 32, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 64: wa_groups<T, 64, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 128: wa_wave<T, 2, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 256: wa_wave<T, 4, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
             default:
-                if (net0 + local < net1) wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
+                if (net0 + local < net1) {
+                    wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
+                    if constexpr (H) h = hpwl_block<T>(nd, net0 + local, posu);
+                }
                 break;
         }
         __shared__ double red[4];
         const double tot = block_sum(wl, red);
         if (threadIdx.x == 0)
             reinterpret_cast<double *>(base + L.part)[PART_WL * L.pstride + bx] = tot;
+        if constexpr (H) {
+            __shared__ long long redh[4];
+            const long long th = block_sum((long long)h, redh);
+            if (threadIdx.x == 0)
+                (reinterpret_cast<long long *>(base + L.part) + PART_HPWL * L.pstride)[bx] = th;
+        }
     } else {
         int64_t h = 0;
         switch (bk.G[b]) {
@@ -459,33 +515,31 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
     sweep_body<T, MODE_HPWL>(nd, bk, sa.base[blockIdx.y], L, T(0), blockIdx.x);
 }
 
-// The first launch of an evaluation: three independent jobs in disjoint block ranges of one
-// grid, so that the net sweeps and the charge scatter fill the machine together without a
-// second stream or any cross-stream synchronisation.  Blocks are dispatched in index order,
-// so the longest-latency work comes first:
-//   [0, nsc)             the scatter: the accumulation of v's charge in the existing grouped
-//                        order, or, when the order is rebuilt (regroup), its counting pass;
-//   [nsc, nsc + nw)      the WA sweep of v (nw = the sweep's block count; its block-per-net
-//                        bucket leads);
-//   [nsc + nw, ... + nh) the HPWL sweep of u for the slots in hmask (a deferred hp_hpwl; nh is
-//                        0 or the sweep's block count).
-// nsc and nw are multiples of 8, so every range keeps the XCD striping of its own blocks.
+// The first launch of an evaluation: independent jobs in disjoint block ranges of one grid,
+// so that the net sweep and the charge scatter fill the machine together without a second
+// stream or any cross-stream synchronisation.  Blocks are dispatched in index order, so the
+// longest-latency work comes first:
+//   [0, nsc)        the scatter: the accumulation of v's charge in the existing grouped order,
+//                   or, when the order is rebuilt (regroup), its counting pass;
+//   [nsc, nsc + nw) the WA sweep of v (nw = the sweep's block count; its block-per-net bucket
+//                   leads); for the slots in hmask (a deferred hp_hpwl) the same blocks also
+//                   sweep the HPWL of u, sharing the pin loads.
+// nsc is a multiple of 8, so the sweep keeps the XCD striping of its own blocks.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
                                                             SlotLayout L, T invg, int nsc,
                                                             uint32_t hmask, int regroup) {
     char *base = sa.base[blockIdx.y];
-    const int nw = bk.total_blocks;
     const int bx = blockIdx.x;
     if (bx < nsc) {
         if (regroup)
             count_body<T>(nd, base, L, bx);
         else
             accum_body<T>(nd, base, L, bx);
-    } else if (bx < nsc + nw) {
-        sweep_body<T, MODE_WA>(nd, bk, base, L, invg, bx - nsc);
     } else if ((hmask >> blockIdx.y) & 1u) {
-        sweep_body<T, MODE_HPWL>(nd, bk, base, L, T(0), bx - nsc - nw);
+        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - nsc);
+    } else {
+        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - nsc);
     }
 }
 
@@ -495,10 +549,9 @@ template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
                              bool regroup, hipStream_t st) {
-    const int nh = hpwl_mask ? bk.total_blocks : 0;
     const int nsc = ((regroup ? nd.sort_blocks : nd.max_chunks) + kXcds - 1) / kXcds * kXcds;
     const size_t lds = regroup ? scatter_count_lds(nd) : scatter_accum_lds(nd);
-    dim3 grid(nsc + bk.total_blocks + nh, sa.n);
+    dim3 grid(nsc + bk.total_blocks, sa.n);
     HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
               L, (T)inv_gamma, nsc, hpwl_mask, (int)regroup);
     return hipGetLastError();
