@@ -17,8 +17,12 @@
 //   v = IFFT(V) is real and x_2n = v_n, x_{2n+1} = v_{M-1-n};
 // and a sine sum is a cosine sum of the reversed coefficients times (-1)^j.  Two real lines
 // share one complex FFT.  The FFT is a decimation-in-time transform in LDS (radix-4 passes,
-// one radix-2 pass for odd log M) over a batch of lines.  Each block first copies the
-// twiddles, DCT phases and per-axis symbols (tables built on the host in FP64) to LDS.
+// one radix-2 pass for odd log M) over a batch of lines.  Each block copies the twiddles, DCT
+// phases and per-axis symbols (tables built on the host in FP64) to LDS.
+//
+// With M <= 1024 each pass has only M/2 blocks (one per CU or fewer), so a block's latency is
+// the pass's time: blocks are wide (1024 threads for R1, 512 for C and R2) and every global
+// load of a block, tables included, is issued before the first one is waited for.
 #include "hp_device.h"
 
 namespace hp {
@@ -46,7 +50,7 @@ __device__ __forceinline__ int mperm(int j, int M) { return (j & 1) ? (M - 1 - (
 // In-place FFT of nlines lines of length M held in bit-reversed order; tw[k] = exp(-2 pi i k/M)
 // (conjugated for the inverse).  A radix-4 pass performs DIT stages s and s+1 at once: with
 // h = 2^s, w1 = W_{2h}^pos and w2 = W_{4h}^pos, and W_{4h}^h = -i (forward) or +i (inverse).
-template <typename T>
+template <typename T, int NT>
 __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T> *tw, bool inverse) {
     int s = 0;
     for (; s + 1 < logM; s += 2) {
@@ -54,7 +58,7 @@ __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T>
         const int q = M >> 2;
         const int total = nlines * q;
         const int sh1 = logM - 1 - s, sh2 = logM - 2 - s;
-        for (int b = threadIdx.x; b < total; b += kBlock) {
+        for (int b = threadIdx.x; b < total; b += NT) {
             const int line = b >> (logM - 2);
             const int t = b & (q - 1);
             const int pos = t & (h - 1);
@@ -80,7 +84,7 @@ __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T>
     }
     if (s < logM) {  // one radix-2 stage left
         const int half = 1 << s, hm = M >> 1, total = nlines * hm, tsh = logM - 1 - s;
-        for (int b = threadIdx.x; b < total; b += kBlock) {
+        for (int b = threadIdx.x; b < total; b += NT) {
             const int line = b >> (logM - 1);
             const int t = b & (hm - 1);
             const int pos = t & (half - 1);
@@ -113,14 +117,45 @@ __device__ __forceinline__ vec2<T> idct_pre(T p, T q, vec2<T> ph) {
     return cmk<T>(p * ph.x + q * ph.y, p * ph.y - q * ph.x);
 }
 
-// Copy the FFT twiddles (M/2) and DCT phases (M) of one axis to LDS.
-template <typename T>
-__device__ __forceinline__ void load_tables(vec2<T> *s_tw, vec2<T> *s_ph, const void *tw, const void *ph,
-                                            int M) {
-    const vec2<T> *gtw = reinterpret_cast<const vec2<T> *>(tw);
-    const vec2<T> *gph = reinterpret_cast<const vec2<T> *>(ph);
-    for (int i = threadIdx.x; i < M / 2; i += kBlock) s_tw[i] = gtw[i];
-    for (int i = threadIdx.x; i < M; i += kBlock) s_ph[i] = gph[i];
+// Register prefetch of up to K elements per thread of a table of n (thread t takes t, t + NT,
+// ...), so that several tables' loads are in flight together; put() stores them to LDS.
+template <typename V, int NT, int K>
+struct Prefetch {
+    V r[K];
+    __device__ __forceinline__ void get(const V *g, int n) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < n) r[k] = g[i];
+        }
+    }
+    template <typename S>
+    __device__ __forceinline__ void put(S *s, int n) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < n) s[i] = (S)r[k];
+        }
+    }
+};
+
+// Sum over a block of NT threads (all get the result): wave butterflies, then a pairwise tree
+// over the NT / 64 wave totals.  red: >= NT / 64 elements.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum_nt(T v, T *red) {
+    constexpr int NW = NT / 64;
+    v = group_sum<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T q[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) q[k] = red[k];
+#pragma unroll
+    for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+        for (int k = 0; k < h; ++k) q[k] += q[k + h];
+    return q[0];
 }
 
 // LDS layout helpers (16-byte aligned sections)
@@ -128,54 +163,60 @@ __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~size_t(15)
 
 // ---- R1 ---------------------------------------------------------------------------------
 // lds: tw [M/2] | ph [M] | buf [lpb][M]
+// A block takes 2 lpb consecutive rows (lpb complex lines), one bin per thread and round.
+constexpr int kRowsFwdThreads = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void spec_rows_fwd(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                        int lpb, int keep) {
+__global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                                 int lpb, int keep) {
+    constexpr int NT = kRowsFwdThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.mx, logM = nd.logmx;
     vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem);
     vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + al16(sizeof(vec2<T>) * (M / 2)));
     vec2<T> *buf = reinterpret_cast<vec2<T> *>(smem + al16(sizeof(vec2<T>) * (M / 2)) +
                                                al16(sizeof(vec2<T>) * M));
+    T *bufr = reinterpret_cast<T *>(buf);  // line l, element n: real part 2 (l M + n), imag + 1
     char *base = sa.base[blockIdx.y];
-    load_tables<T>(s_tw, s_ph, nd.tw_x, nd.ph_x, M);
+    Prefetch<vec2<T>, NT, 1> ptw;  // M / 2 <= 1024
+    Prefetch<vec2<T>, NT, 2> pph;  // M <= 2048
+    ptw.get(reinterpret_cast<const vec2<T> *>(nd.tw_x), M / 2);
+    pph.get(reinterpret_cast<const vec2<T> *>(nd.ph_x), M);
     int64_t *rho = reinterpret_cast<int64_t *>(base + L.rho);
     T *t1 = reinterpret_cast<T *>(base + L.t1);
+    const int nel = 2 * lpb * M;
+    const size_t g0 = (size_t)blockIdx.x * nel;  // first bin: row 2 lpb blockIdx.x, column 0
     long long over = 0;
-    for (int idx = threadIdx.x; idx < lpb * M; idx += kBlock) {
-        const int l = idx >> logM, j = idx & (M - 1);
-        const int ra = (blockIdx.x * lpb + l) * 2;
-        const size_t ia = (size_t)ra * M + j, ib = ia + M;
+    for (int e = threadIdx.x; e < nel; e += NT) {
+        const int rl = e >> logM, j = e & (M - 1);  // row within the block (line rl / 2)
+        const size_t ia = g0 + e;
+        const int row = (int)(ia >> logM);
         // windows of the binned scatter, plus the charge its out-of-window cells added to rho
-        const int64_t oa = rho[ia], ob = rho[ib];
-        const int64_t ma = binned_charge(nd, base, L, ra, j) + oa;
-        const int64_t mb = binned_charge(nd, base, L, ra + 1, j) + ob;
-        const int64_t fa = nd.rho_fixed[ia], fb = nd.rho_fixed[ib];
+        const int64_t oa = rho[ia];
+        const int64_t fa = nd.rho_fixed[ia];
+        const int64_t ma = binned_charge(nd, base, L, row, j) + oa;
         const int64_t ca = __double2ll_rn(nd.target_density * (double)(nd.area_q - fa));
-        const int64_t cb = __double2ll_rn(nd.target_density * (double)(nd.area_q - fb));
         if (ma > ca) over += ma - ca;
-        if (mb > cb) over += mb - cb;
-        if (keep) {  // the whole movable map, for inspection (cleared before the next scatter)
+        if (keep)  // the whole movable map, for inspection (cleared before the next scatter)
             rho[ia] = ma;
-            rho[ib] = mb;
-        } else {  // leave rho zero for the next scatter
-            if (oa) rho[ia] = 0;
-            if (ob) rho[ib] = 0;
-        }
-        buf[l * M + brev(mperm(j, M), logM)] =
-            cmk<T>((T)((double)(ma + fa) * nd.density_unit), (T)((double)(mb + fb) * nd.density_unit));
+        else if (oa)  // leave rho zero for the next scatter
+            rho[ia] = 0;
+        bufr[2 * ((rl >> 1) * M + brev(mperm(j, M), logM)) + (rl & 1)] =
+            (T)((double)(ma + fa) * nd.density_unit);
     }
+    ptw.put(s_tw, M / 2);
+    pph.put(s_ph, M);
     __syncthreads();
-    fft_lds<T>(buf, lpb, M, logM, s_tw, false);
-    for (int idx = threadIdx.x; idx < lpb * M; idx += kBlock) {
+    fft_lds<T, NT>(buf, lpb, M, logM, s_tw, false);
+    for (int idx = threadIdx.x; idx < lpb * M; idx += NT) {
         const int l = idx >> logM, u = idx & (M - 1);
-        const int ra = (blockIdx.x * lpb + l) * 2;
+        const size_t ra = g0 + (size_t)(2 * l) * M;
         const vec2<T> F = dct_post<T>(buf + l * M, u, M, s_ph[u]);
-        t1[(size_t)ra * M + u] = F.x;
-        t1[(size_t)(ra + 1) * M + u] = F.y;
+        t1[ra + u] = F.x;
+        t1[ra + M + u] = F.y;
     }
-    __shared__ long long red[4];
-    over = block_sum(over, red);
+    __shared__ long long red[NT / 64];
+    over = block_sum_nt<NT>(over, red);
     if (threadIdx.x == 0)
         (reinterpret_cast<long long *>(base + L.part) + PART_OVF * L.pstride)[blockIdx.x] = over;
 }
@@ -190,8 +231,12 @@ __host__ __device__ inline size_t cols_lds(int M) {
            2 * al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
 }
 
+constexpr int kColsThreads = 512;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L, int want_psi) {
+__global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                          int want_psi) {
+    constexpr int NT = kColsThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.my, logM = nd.logmy, mx = nd.mx;
     size_t o = 0;
@@ -210,25 +255,40 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M]
     char *base = sa.base[blockIdx.y];
     const int u0 = blockIdx.x * 2;
-    load_tables<T>(s_tw, s_ph, nd.tw_y, nd.ph_y, M);
-    for (int v = threadIdx.x; v < M; v += kBlock) {
-        s_den[v] = (T)nd.den1[mx + v];
-        s_om[v] = (T)nd.omega[mx + v];
-    }
-    // load the two columns as one complex line, Makhoul-reordered, bit-reversed
+    // every global load first: the two columns (as one complex line), the y tables and
+    // symbols (M <= 2048: at most 4 elements of each per thread)
     const T *t1 = reinterpret_cast<const T *>(base + L.t1);
-    for (int k = threadIdx.x; k < M; k += kBlock) {
-        const vec2<T> c = *reinterpret_cast<const vec2<T> *>(t1 + (size_t)k * mx + u0);
-        work[brev(mperm(k, M), logM)] = c;
+    vec2<T> col[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = threadIdx.x + q * NT;
+        if (k < M) col[q] = *reinterpret_cast<const vec2<T> *>(t1 + (size_t)k * mx + u0);
     }
+    Prefetch<vec2<T>, NT, 2> ptw;
+    Prefetch<vec2<T>, NT, 4> pph;
+    Prefetch<double, NT, 4> pden, pom;
+    ptw.get(reinterpret_cast<const vec2<T> *>(nd.tw_y), M / 2);
+    pph.get(reinterpret_cast<const vec2<T> *>(nd.ph_y), M);
+    pden.get(nd.den1 + mx, M);
+    pom.get(nd.omega + mx, M);
+    const T dux0 = (T)nd.den1[u0], dux1 = (T)nd.den1[u0 + 1];
+    const T wux[2] = {(T)nd.omega[u0], (T)nd.omega[u0 + 1]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // Makhoul-reordered, bit-reversed
+        const int k = threadIdx.x + q * NT;
+        if (k < M) work[brev(mperm(k, M), logM)] = col[q];
+    }
+    ptw.put(s_tw, M / 2);
+    pph.put(s_ph, M);
+    pden.put(s_den, M);
+    pom.put(s_om, M);
     __syncthreads();
-    fft_lds<T>(work, 1, M, logM, s_tw, false);
+    fft_lds<T, NT>(work, 1, M, logM, s_tw, false);
     const T norm = (T)(1.0 / ((double)nd.mx * nd.my));
     const T cu0 = u0 ? T(2) : T(1);  // u0 + 1 > 0 always
-    const T dux0 = (T)nd.den1[u0], dux1 = (T)nd.den1[u0 + 1];
     const double mm = (double)nd.mx * nd.my;
     double e = 0.0;
-    for (int v = threadIdx.x; v < M; v += kBlock) {
+    for (int v = threadIdx.x; v < M; v += NT) {
         const vec2<T> F = dct_post<T>(work, v, M, s_ph[v]);
         const T cv = v ? T(2) : T(1);
         const T a0 = cu0 * cv * norm * F.x, a1 = T(2) * cv * norm * F.y;
@@ -240,16 +300,14 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
         // energy by Parseval: a^2 mx my / (c_u c_v den), accumulated in FP64
         e += (double)(a0 * a0 * i0 / (cu0 * cv)) * mm + (double)(a1 * a1 * i1 / (T(2) * cv)) * mm;
     }
-    __syncthreads();
-    __shared__ double red[4];
-    e = block_sum(e, red);
+    __shared__ double red[NT / 64];
+    e = block_sum_nt<NT>(e, red);  // its barriers also publish acol / inv
     if (threadIdx.x == 0)
         reinterpret_cast<double *>(base + L.part)[PART_E * L.pstride + blockIdx.x] = e;
 
     // (Bx + i By) of column h on complex line h: X(v) = a_uv w_u / den (cosine sum in y),
     // Y(v) = a_uv w_v / den (sine sum in y -> reversed coefficients)
-    const T wux[2] = {(T)nd.omega[u0], (T)nd.omega[u0 + 1]};
-    for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < 2 * M; idx += NT) {
         const int h = idx >> logM, v = idx & (M - 1);
         const T *ac = acol + h * M, *iv = inv + h * M;
         const T wu = wux[h];
@@ -263,10 +321,10 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
         work[h * M + brev(v, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
     }
     __syncthreads();
-    fft_lds<T>(work, 2, M, logM, s_tw, true);
+    fft_lds<T, NT>(work, 2, M, logM, s_tw, true);
     T *bx = reinterpret_cast<T *>(base + L.bx);
     T *by = reinterpret_cast<T *>(base + L.by);
-    for (int k = threadIdx.x; k < M; k += kBlock) {
+    for (int k = threadIdx.x; k < M; k += NT) {
         const int n = mperm(k, M);
         const vec2<T> z0 = work[n], z1 = work[M + n];
         const T sg = (k & 1) ? T(-1) : T(1);
@@ -275,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
     }
     if (want_psi) {
         __syncthreads();
-        for (int v = threadIdx.x; v < M; v += kBlock) {
+        for (int v = threadIdx.x; v < M; v += NT) {
             vec2<T> V2v[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -288,18 +346,21 @@ __global__ __launch_bounds__(kBlock) void spec_cols(NetDev nd, SlotArgs sa, Slot
             work[brev(v, logM)] = cmk<T>(V2v[0].x - V2v[1].y, V2v[0].y + V2v[1].x);
         }
         __syncthreads();
-        fft_lds<T>(work, 1, M, logM, s_tw, true);
+        fft_lds<T, NT>(work, 1, M, logM, s_tw, true);
         T *bp = reinterpret_cast<T *>(base + L.bp);
-        for (int k = threadIdx.x; k < M; k += kBlock)
+        for (int k = threadIdx.x; k < M; k += NT)
             *reinterpret_cast<vec2<T> *>(bp + (size_t)k * mx + u0) = work[mperm(k, M)];
     }
 }
 
 // ---- R2 ---------------------------------------------------------------------------------
 // lds: tw [M/2] | ph [M] | stage [nst][2][M] | work [nst][M]
+constexpr int kRowsInvThreads = 512;
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                        int want_psi) {
+__global__ __launch_bounds__(kRowsInvThreads) void spec_rows_inv(NetDev nd, SlotArgs sa,
+                                                                 SlotLayout L, int want_psi) {
+    constexpr int NT = kRowsInvThreads;
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.mx, logM = nd.logmx;
     const int nst = want_psi ? 3 : 2;
@@ -313,16 +374,36 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);
     char *base = sa.base[blockIdx.y];
     const int k0 = blockIdx.x * 2;
-    load_tables<T>(s_tw, s_ph, nd.tw_x, nd.ph_x, M);
+    // every global load first: the two rows of Bx, By (and Bp) and the x tables; the rows in
+    // rounds of 8 elements per thread (one round for M <= 1024 without psi)
     const T *src[3] = {reinterpret_cast<const T *>(base + L.bx), reinterpret_cast<const T *>(base + L.by),
                        reinterpret_cast<const T *>(base + L.bp)};
-    for (int idx = threadIdx.x; idx < nst * 2 * M; idx += kBlock) {
-        const int a = idx / (2 * M), rem = idx - a * 2 * M;
-        stage[idx] = src[a][(size_t)k0 * M + rem];
+    Prefetch<vec2<T>, NT, 2> ptw;
+    Prefetch<vec2<T>, NT, 4> pph;
+    ptw.get(reinterpret_cast<const vec2<T> *>(nd.tw_x), M / 2);
+    pph.get(reinterpret_cast<const vec2<T> *>(nd.ph_x), M);
+    const int nall = nst * 2 * M;
+    for (int i0 = 0; i0 < nall; i0 += 8 * NT) {
+        T r[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = i0 + threadIdx.x + q * NT;
+            if (idx < nall) {
+                const int a = idx >> (logM + 1), rem = idx & (2 * M - 1);
+                r[q] = src[a][(size_t)k0 * M + rem];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int idx = i0 + threadIdx.x + q * NT;
+            if (idx < nall) stage[idx] = r[q];
+        }
     }
+    ptw.put(s_tw, M / 2);
+    pph.put(s_ph, M);
     __syncthreads();
     const int nlines = want_psi ? 3 : 2;
-    for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < 2 * M; idx += NT) {
         const int r = idx >> logM, u = idx & (M - 1);
         const T *sbx = stage + r * M, *sby = stage + 2 * M + r * M;
         // xi_x: sine sum of Bx -> cosine sum of the reversed row
@@ -334,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
         work[r * M + brev(u, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
     }
     if (want_psi) {
-        for (int u = threadIdx.x; u < M; u += kBlock) {
+        for (int u = threadIdx.x; u < M; u += NT) {
             const T *s0 = stage + 4 * M, *s1 = stage + 5 * M;
             const vec2<T> A = idct_pre<T>(u ? T(0.5) * s0[u] : s0[0], u ? T(0.5) * s0[M - u] : T(0), s_ph[u]);
             const vec2<T> B = idct_pre<T>(u ? T(0.5) * s1[u] : s1[0], u ? T(0.5) * s1[M - u] : T(0), s_ph[u]);
@@ -342,10 +423,10 @@ __global__ __launch_bounds__(kBlock) void spec_rows_inv(NetDev nd, SlotArgs sa, 
         }
     }
     __syncthreads();
-    fft_lds<T>(work, nlines, M, logM, s_tw, true);
+    fft_lds<T, NT>(work, nlines, M, logM, s_tw, true);
     vec2<T> *exy = reinterpret_cast<vec2<T> *>(base + L.exy);
     T *psi = reinterpret_cast<T *>(base + L.psi);
-    for (int idx = threadIdx.x; idx < 2 * M; idx += kBlock) {
+    for (int idx = threadIdx.x; idx < 2 * M; idx += NT) {
         const int r = idx >> logM, j = idx & (M - 1);
         const int n = mperm(j, M);
         const vec2<T> z = work[r * M + n];
@@ -383,16 +464,16 @@ template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st) {
     const int lpb = rows_fwd_lines(nd);
-    HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kBlock),
+    HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kRowsFwdThreads),
               rows_fwd_lds<T>(nd), st, nd, sa, L, lpb, (int)keep_maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("spec_cols", spec_cols<T>, dim3(nd.mx / 2, sa.n), dim3(kBlock), cols_lds<T>(nd.my), st,
-              nd, sa, L, (int)want_psi);
+    HP_LAUNCH("spec_cols", spec_cols<T>, dim3(nd.mx / 2, sa.n), dim3(kColsThreads), cols_lds<T>(nd.my),
+              st, nd, sa, L, (int)want_psi);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nst = want_psi ? 3 : 2;
-    HP_LAUNCH("spec_rows_inv", spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kBlock),
+    HP_LAUNCH("spec_rows_inv", spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kRowsInvThreads),
               rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
     return hipGetLastError();
 }
