@@ -158,6 +158,14 @@ __device__ __forceinline__ T block_sum_nt(T v, T *red) {
     return q[0];
 }
 
+// The block's line (pair) index: neighbouring lines go to the same XCD (each XCD takes one
+// contiguous eighth of the grid when the grid is a multiple of 8), so the column pass's 8-byte
+// reads and writes of neighbouring columns meet in one L2 and leave it as whole lines, and the
+// row passes' neighbouring rows share their tiles' charge windows.
+__device__ __forceinline__ int spec_block() {
+    return (gridDim.x % kXcds) ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+}
+
 // LDS layout helpers (16-byte aligned sections)
 __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
 
@@ -185,7 +193,8 @@ __global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nd, Slot
     int64_t *rho = reinterpret_cast<int64_t *>(base + L.rho);
     T *t1 = reinterpret_cast<T *>(base + L.t1);
     const int nel = 2 * lpb * M;
-    const size_t g0 = (size_t)blockIdx.x * nel;  // first bin: row 2 lpb blockIdx.x, column 0
+    const int bid = spec_block();
+    const size_t g0 = (size_t)bid * nel;  // first bin: row 2 lpb bid, column 0
     long long over = 0;
     for (int e = threadIdx.x; e < nel; e += NT) {
         const int rl = e >> logM, j = e & (M - 1);  // row within the block (line rl / 2)
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nd, Slot
     __shared__ long long red[NT / 64];
     over = block_sum_nt<NT>(over, red);
     if (threadIdx.x == 0)
-        (reinterpret_cast<long long *>(base + L.part) + PART_OVF * L.pstride)[blockIdx.x] = over;
+        (reinterpret_cast<long long *>(base + L.part) + PART_OVF * L.pstride)[bid] = over;
 }
 
 // ---- C: two columns per block -------------------------------------------------------------
@@ -254,7 +263,8 @@ __global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa
     o += al16(sizeof(T) * 2 * M);
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M]
     char *base = sa.base[blockIdx.y];
-    const int u0 = blockIdx.x * 2;
+    const int bid = spec_block();
+    const int u0 = bid * 2;
     // every global load first: the two columns (as one complex line), the y tables and
     // symbols (M <= 2048: at most 4 elements of each per thread)
     const T *t1 = reinterpret_cast<const T *>(base + L.t1);
@@ -303,7 +313,7 @@ __global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa
     __shared__ double red[NT / 64];
     e = block_sum_nt<NT>(e, red);  // its barriers also publish acol / inv
     if (threadIdx.x == 0)
-        reinterpret_cast<double *>(base + L.part)[PART_E * L.pstride + blockIdx.x] = e;
+        reinterpret_cast<double *>(base + L.part)[PART_E * L.pstride + bid] = e;
 
     // (Bx + i By) of column h on complex line h: X(v) = a_uv w_u / den (cosine sum in y),
     // Y(v) = a_uv w_v / den (sine sum in y -> reversed coefficients)
@@ -373,7 +383,7 @@ __global__ __launch_bounds__(kRowsInvThreads) void spec_rows_inv(NetDev nd, Slot
     o += al16(sizeof(T) * (size_t)nst * 2 * M);
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);
     char *base = sa.base[blockIdx.y];
-    const int k0 = blockIdx.x * 2;
+    const int k0 = spec_block() * 2;
     // every global load first: the two rows of Bx, By (and Bp) and the x tables; the rows in
     // rounds of 8 elements per thread (one round for M <= 1024 without psi)
     const T *src[3] = {reinterpret_cast<const T *>(base + L.bx), reinterpret_cast<const T *>(base + L.by),
