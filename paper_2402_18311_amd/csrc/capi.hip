@@ -43,6 +43,14 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // unused ones padded), a larger net exactly d, so 2 * n_pins bounds them.
 size_t sweep_slots_bound(const hp_shape &s) { return 2 * (size_t)s.n_pins + 64; }
 
+// v is held exactly in T and v * 2^16 is an integer: its 2^-16 quantization is then the
+// exact product, which the device can form from the T value itself.
+template <typename T>
+static bool q16_exact(double v) {
+    const double q = v * 65536.0;
+    return (double)(T)v == v && std::nearbyint(q) == q && std::fabs(q) < 2147483648.0;
+}
+
 struct NetBuf {
     size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
         cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh, total;
@@ -363,7 +371,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     h_pc.reserve(P);
     h_po.reserve(2 * (size_t)P);
     h_pq.reserve(2 * (size_t)P);
-    bool any_w = false;
+    bool any_w = false, offq_exact = true;
     if (net_weight)
         for (int e = 0; e < E; ++e) any_w |= net_weight[e] != 1.0;
     for (int b = 0, i = 0; b < bk.n; ++b) {
@@ -373,6 +381,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             const int e = order[i];
             h_ns[i] = (int32_t)h_pc.size();
             for (int p = net_start[e]; p < net_start[e + 1]; ++p) {
+                offq_exact = offq_exact && q16_exact<T>(pin_ox[p]) && q16_exact<T>(pin_oy[p]);
                 h_pc.push_back(pin_cell[p]);
                 h_po.push_back((T)pin_ox[p]);
                 h_po.push_back((T)pin_oy[p]);
@@ -392,6 +401,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     h_ns[ns] = (int32_t)h_pc.size();
     const int ps = (int)h_pc.size();
     nd.ps = ps;
+    nd.offq_exact = offq_exact ? 1 : 0;
     if ((size_t)ps > sweep_slots_bound(S)) return fail(HP_EINVAL, "internal: sweep slot bound");
 
     // cell -> sweep-pin CSR (movable cells), and pin counts over all nets for the

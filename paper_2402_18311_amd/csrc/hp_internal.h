@@ -67,6 +67,8 @@ struct NetDev {
     double target_density;
     int64_t total_charge;
     int32_t stretch;               // small cells' charge spread over >= sqrt(2) bins per side
+    int32_t offq_exact;            // every pin_off (in T) is a multiple of 2^-16: pin_offq is
+                                   // pin_off * 2^16 exactly, and the sweeps form it from pin_off
 };
 
 // Byte offsets of a slot's arrays inside its buffer (identical for all slots of a netlist).

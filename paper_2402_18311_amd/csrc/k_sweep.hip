@@ -29,7 +29,9 @@ namespace hp {
 // loads (cell index, offset) and one of gathers (position).  A block takes R = kNetsPerLane
 // consecutive runs of 256 / G nets; every lane issues the loads of its R nets before using any.
 // With H, the same lanes also form the exact HPWL (Eq. 1) of the positions `posu` over the
-// same nets (the pin loads are shared; see hpwl_groups for the arithmetic), added to h.
+// same nets (the pin loads are shared; see hpwl_groups for the arithmetic), added to h.  When
+// every offset is a multiple of 2^-16 (nd.offq_exact), the quantized offset is formed from the
+// float one (the same integer) instead of being loaded.
 template <typename T, int G, bool H>
 __device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, int b, int local,
                                           const vec2<T> *__restrict__ pos, T invg,
@@ -50,7 +52,8 @@ __device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, i
         p[r] = net[r] < net1 ? pin0 + (net[r] - net0) * G + lane : pin0;
         c[r] = nd.pin_cell[p[r]];
         o[r] = off[p[r]];
-        if constexpr (H) oq[r] = nd.pin_offq[p[r]];
+        if constexpr (H)
+            oq[r] = nd.offq_exact ? make_int2(q16i<T>(o[r].x), q16i<T>(o[r].y)) : nd.pin_offq[p[r]];
     }
     vec2<T> q[R], qu[R];
 #pragma unroll
@@ -125,7 +128,8 @@ __device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int
     for (int k = 0; k < PPL; ++k) {
         c[k] = nd.pin_cell[p0 + 64 * k];
         o[k] = off[p0 + 64 * k];
-        if constexpr (H) oq[k] = nd.pin_offq[p0 + 64 * k];
+        if constexpr (H)
+            oq[k] = nd.offq_exact ? make_int2(q16i<T>(o[k].x), q16i<T>(o[k].y)) : nd.pin_offq[p0 + 64 * k];
     }
     vec2<T> q[PPL], qu[PPL];
 #pragma unroll

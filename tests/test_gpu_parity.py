@@ -34,7 +34,16 @@ _CASES = {
     "mid": lambda: netgen.make_netlist("mid", 0),
     # 2.2 M cells, 10.7 M pins (54 nets over 2048 pins), 1024 x 1024 bins
     "large": lambda: netgen.make_netlist("large", 0),
+    # pin offsets that are not multiples of 2^-16 (the sweeps then load the quantized ones)
+    "small_offs": lambda: _offsets_off_grid(netgen.make_small(20_011, 21_003, 128, seed=3,
+                                                              n_fixed=40)),
 }
+
+
+def _offsets_off_grid(nl):
+    import dataclasses
+    k = 1.0 - 3.1e-7
+    return dataclasses.replace(nl, pin_ox=nl.pin_ox * k, pin_oy=nl.pin_oy * k)
 _cache = {}
 
 
@@ -59,6 +68,23 @@ def test_hpwl_bitexact(hy, orc, case, prec):
         q1 = pl.hpwl(s)[0]
         q2 = pl.hpwl(s)[0]
         assert q1 == q2 == o.hpwl_q(x, y)
+    pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("small_offs", 32),
+                                       ("small_offs", 64), ("mid", 32)])
+def test_hpwl_in_first_launch_bitexact(hy, orc, case, prec):
+    """A requested HPWL that the next evaluation's first launch sweeps (beside the WA sweep of
+    the same nets) is the oracle's, bit for bit, with offsets on and off the 2^-16 grid."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    s = pl.new_slot()
+    gamma = 4 * nl.bin_w
+    for seed in range(2):
+        x, y = nl.random_positions(seed + 7)
+        pl.set_positions(s, x, y)
+        pl.hpwl(s, want_host=False)
+        pl.eval(s, gamma, want_host=False)
+        assert pl.state(s)["hpwl_q"] == o.hpwl_q(x, y)
     pl.free_slot(s)
 
 
