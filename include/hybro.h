@@ -117,6 +117,18 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
  * for drivers that adapt the penalty of Eq. 2 as the placement evolves.  Synchronises. */
 int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio);
 
+/* Grouping policy of the integer charge scatter (the density term of Eqs. 1-2) for every slot
+ * of a netlist; it changes speed only, never results (the charge map is an integer sum and is
+ * bit-identical under any grouping).  Cells are grouped by bin tile so that each group's charge
+ * is summed in on-chip memory; the grouping is rebuilt every `regroup_every` evaluations
+ * (1..64; cells that left their group's window in between take a slower path), and with
+ * `deferred` = 1 the rebuilding evaluation still accumulates in the previous grouping and the
+ * rebuild finishes after it (fewer launches; better when cells move little), with 0 it
+ * accumulates in the new one.  Defaults: 4 and 1.  Returns HP_EINVAL on values out of range,
+ * HP_ESTATE on an unknown netlist.  Takes effect at the next evaluation; no device work. */
+int hp_set_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t regroup_every, int32_t deferred);
+int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, int32_t *deferred);
+
 /* Objective of Eq. 2 and its gradient at the slots' reference points v:
  *   wl = sum_e w_e WL_e (Eq. 3, both axes), energy = electrostatic energy N of the charge
  *   map, overflow = sum_b max(0, movable charge - target * free area) / total movable charge

@@ -173,6 +173,10 @@ struct Netlist {
     SlotLayout L{};
     char *buf = nullptr;
     int e_parts = 0;
+    // scatter grouping policy (hp_set_scatter_policy): rebuild every `regroup_every`
+    // evaluations; `deferred`: the rebuilding evaluation accumulates in the existing order
+    int regroup_every = kRegroupEvery;
+    bool deferred = true;
 };
 
 struct Slot {
@@ -667,12 +671,13 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
     for (size_t c = 0; c < chunks.size(); ++c) {
         const SlotArgs &sa = chunks[c];
         bool any_init = false;
-        bool regroup = false, dirty = false;
+        bool fresh = false, due = false, dirty = false;
         uint32_t hmask = 0;  // slots whose requested HPWL sweep rides along
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];
             any_init |= !use_fixed && !s->lambda_valid;
-            regroup |= s->since_group < 0 || s->since_group >= kRegroupEvery;
+            fresh |= s->since_group < 0;
+            due |= s->since_group >= NL->regroup_every;
             dirty |= s->rho_dirty;
             if (s->hpwl_requested) {
                 hmask |= 1u << i;
@@ -681,11 +686,22 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
             }
         }
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
-        // WA sweep, HPWL sweep and the scatter (or the counting pass of a regroup) in one launch
-        HP_CHECK(launch_eval_front<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, hmask, regroup, st));
-        if (regroup) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, st));
+        // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
+        // a netlist whose policy is not deferred, counts for a new order in the first launch
+        // and accumulates in it right after (regroup tail with accumulation).  A deferred
+        // periodic rebuild accumulates in the existing order in the first launch and counts
+        // for the new order in the same launch; the rest of the rebuild (scans, place) runs
+        // after the row pass, the last reader of the existing order's windows, so the next
+        // evaluation accumulates in the new order.
+        const bool rebuild_now = fresh || (due && !NL->deferred);
+        const bool accum_now = !rebuild_now, count_now = fresh || due;
+        // WA sweep, HPWL sweep and the scatter's accumulation and/or counting in one launch
+        HP_CHECK(launch_eval_front<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, hmask, accum_now,
+                                      count_now, st));
+        if (rebuild_now) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, true, st));
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0,
                                     p->keep_maps != 0 || p->grad_mode == 1, st));
+        if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
                                      st));
@@ -696,7 +712,7 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
             // a steady-state evaluation (lambda known) also proposed the next step
             s->step_proposed = use_fixed || s->lambda_valid;
             if (!use_fixed) s->lambda_valid = true;
-            s->since_group = regroup ? 1 : s->since_group + 1;
+            s->since_group = count_now ? 1 : s->since_group + 1;
             s->rho_dirty = p->keep_maps != 0;
         }
     }
@@ -1062,6 +1078,27 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
     h.lambda_ratio = std::pow(10.0, decades / total_iters);
     HP_CHECK(hipMemcpyAsync(s->base + n->L.scal, &h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_set_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t regroup_every, int32_t deferred) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    if (regroup_every < 1 || regroup_every > 64)
+        return fail(HP_EINVAL, "regroup_every must be in [1, 64]");
+    if (deferred != 0 && deferred != 1) return fail(HP_EINVAL, "deferred must be 0 or 1");
+    ctx->nets[netlist].regroup_every = regroup_every;
+    ctx->nets[netlist].deferred = deferred != 0;
+    return HP_OK;
+}
+
+int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, int32_t *deferred) {
+    if (!ctx || !regroup_every || !deferred) return fail(HP_EINVAL, "ctx/out is NULL");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    *regroup_every = ctx->nets[netlist].regroup_every;
+    *deferred = ctx->nets[netlist].deferred ? 1 : 0;
     return HP_OK;
 }
 

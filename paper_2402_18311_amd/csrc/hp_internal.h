@@ -155,14 +155,14 @@ void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
-                             bool regroup, hipStream_t st);
+                             bool accum, bool count, hipStream_t st);
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st);
 // Scan, place and accumulate of a regroup whose counting pass the first launch ran.
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                               hipStream_t st);
+                               bool accum, hipStream_t st);
 size_t scatter_count_lds(const NetDev &nd);
 size_t scatter_accum_lds(const NetDev &nd);
 hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,

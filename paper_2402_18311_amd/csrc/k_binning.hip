@@ -155,10 +155,10 @@ size_t scatter_accum_lds(const NetDev &nd) {
 }
 
 // The rest of a rebuild after its counting pass (which the evaluation's first launch runs):
-// scan, place, then the accumulation of the fresh order.
+// scan, place, then (accum) the accumulation of the fresh order.
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                               hipStream_t st) {
+                               bool accum, hipStream_t st) {
     HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel, dim3((nd.ntiles + kColTiles - 1) / kColTiles, sa.n),
               dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
@@ -170,15 +170,15 @@ hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotL
     HP_LAUNCH("bin_place_kernel", bin_place_kernel, dim3(nd.sort_blocks, sa.n), dim3(kBlock),
               scatter_count_lds(nd), st, nd, sa, L);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !accum) return e;
     HP_LAUNCH("bin_accum_kernel", bin_accum_kernel<T>, dim3(nd.max_chunks, sa.n), dim3(kBlock),
               scatter_accum_lds(nd), st, nd, sa, L);
     return hipGetLastError();
 }
 
 template hipError_t launch_regroup_tail<float>(const NetDev &, const SlotArgs &, const SlotLayout &,
-                                               hipStream_t);
+                                               bool, hipStream_t);
 template hipError_t launch_regroup_tail<double>(const NetDev &, const SlotArgs &,
-                                                const SlotLayout &, hipStream_t);
+                                                const SlotLayout &, bool, hipStream_t);
 
 }  // namespace hp

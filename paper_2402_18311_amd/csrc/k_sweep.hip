@@ -523,27 +523,29 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
 // so that the net sweep and the charge scatter fill the machine together without a second
 // stream or any cross-stream synchronisation.  Blocks are dispatched in index order, so the
 // longest-latency work comes first:
-//   [0, nsc)        the scatter: the accumulation of v's charge in the existing grouped order,
-//                   or, when the order is rebuilt (regroup), its counting pass;
-//   [nsc, nsc + nw) the WA sweep of v (nw = the sweep's block count; its block-per-net bucket
-//                   leads); for the slots in hmask (a deferred hp_hpwl) the same blocks also
-//                   sweep the HPWL of u, sharing the pin loads.
-// nsc is a multiple of 8, so the sweep keeps the XCD striping of its own blocks.
+//   [0, nacc)                 the accumulation of v's charge in the existing grouped order
+//                             (nacc = 0 when the slot has no grouping yet);
+//   [nacc, nacc + ncnt)       the counting pass of a new grouping from v (ncnt = 0 between
+//                             rebuilds);
+//   [nacc + ncnt, ... + nw)   the WA sweep of v (nw = the sweep's block count; its
+//                             block-per-net bucket leads); for the slots in hmask (a deferred
+//                             hp_hpwl) the same blocks also sweep the HPWL of u, sharing the pin
+//                             loads.
+// nacc and ncnt are multiples of 8, so the sweep keeps the XCD striping of its own blocks.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
-                                                            SlotLayout L, T invg, int nsc,
-                                                            uint32_t hmask, int regroup) {
+                                                            SlotLayout L, T invg, int nacc,
+                                                            int ncnt, uint32_t hmask) {
     char *base = sa.base[blockIdx.y];
     const int bx = blockIdx.x;
-    if (bx < nsc) {
-        if (regroup)
-            count_body<T>(nd, base, L, bx);
-        else
-            accum_body<T>(nd, base, L, bx);
+    if (bx < nacc) {
+        accum_body<T>(nd, base, L, bx);
+    } else if (bx < nacc + ncnt) {
+        count_body<T>(nd, base, L, bx - nacc);
     } else if ((hmask >> blockIdx.y) & 1u) {
-        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - nsc);
+        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - nacc - ncnt);
     } else {
-        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - nsc);
+        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - nacc - ncnt);
     }
 }
 
@@ -552,12 +554,13 @@ int sweep_parts(const Buckets &bk) { return bk.total_blocks; }
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
-                             bool regroup, hipStream_t st) {
-    const int nsc = ((regroup ? nd.sort_blocks : nd.max_chunks) + kXcds - 1) / kXcds * kXcds;
-    const size_t lds = regroup ? scatter_count_lds(nd) : scatter_accum_lds(nd);
-    dim3 grid(nsc + bk.total_blocks, sa.n);
+                             bool accum, bool count, hipStream_t st) {
+    const int nacc = accum ? (nd.max_chunks + kXcds - 1) / kXcds * kXcds : 0;
+    const int ncnt = count ? (nd.sort_blocks + kXcds - 1) / kXcds * kXcds : 0;
+    const size_t lds = std::max(accum ? scatter_accum_lds(nd) : 0, count ? scatter_count_lds(nd) : 0);
+    dim3 grid(nacc + ncnt + bk.total_blocks, sa.n);
     HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
-              L, (T)inv_gamma, nsc, hpwl_mask, (int)regroup);
+              L, (T)inv_gamma, nacc, ncnt, hpwl_mask);
     return hipGetLastError();
 }
 
@@ -571,7 +574,7 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
 
 #define HP_INST(T)                                                                             \
     template hipError_t launch_eval_front<T>(const NetDev &, const Buckets &, const SlotArgs &, \
-                                             const SlotLayout &, double, uint32_t, bool,        \
+                                             const SlotLayout &, double, uint32_t, bool, bool,  \
                                              hipStream_t);                                      \
     template hipError_t launch_sweep_hpwl<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, hipStream_t);

@@ -71,6 +71,8 @@ _SIGS = {
     "hp_get_eval_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
     "hp_set_lambda_ratio": [_P, C.c_int32, C.c_double],
+    "hp_set_scatter_policy": [_P, C.c_int32, C.c_int32, C.c_int32],
+    "hp_get_scatter_policy": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
     "hp_nesterov_step": [_P, _P, C.c_int32],
     "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
@@ -195,6 +197,16 @@ def hp_get_eval_positions(ctx, slot, x, y, on_device):
 
 def hp_set_lambda_ratio(ctx, slot, ratio):
     _chk(lib().hp_set_lambda_ratio(ctx, slot, float(ratio)))
+
+
+def hp_set_scatter_policy(ctx, netlist, regroup_every, deferred):
+    _chk(lib().hp_set_scatter_policy(ctx, netlist, int(regroup_every), int(bool(deferred))))
+
+
+def hp_get_scatter_policy(ctx, netlist):
+    r, d = C.c_int32(), C.c_int32()
+    _chk(lib().hp_get_scatter_policy(ctx, netlist, C.byref(r), C.byref(d)))
+    return int(r.value), bool(d.value)
 
 
 def hp_set_schedule(ctx, slot, lambda0_scale, decades, total_iters):
@@ -374,6 +386,13 @@ class Placer:
 
     def state(self, s):
         return hp_get_state(self.ctx, s)
+
+    def set_scatter_policy(self, regroup_every=4, deferred=True):
+        """Grouping policy of the charge scatter for every slot (speed only; see hybro.h)."""
+        hp_set_scatter_policy(self.ctx, self.netlist, regroup_every, deferred)
+
+    def scatter_policy(self):
+        return hp_get_scatter_policy(self.ctx, self.netlist)
 
     def run(self, slots, iters, gamma, hpwl_every=0):
         """iters x [evaluate at v, Nesterov step] on the slots; returns HPWL_q trace if asked."""

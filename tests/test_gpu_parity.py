@@ -189,6 +189,71 @@ def test_charge_map_exact_with_reused_grouping(hy, orc, case, prec):
     pl.free_slot(s)
 
 
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
+def test_scatter_policy_changes_no_result(hy, orc, case, prec):
+    """Every grouping policy of the charge scatter (rebuild interval, rebuild accumulated in the
+    old or the new grouping) gives bit-identical placements, maps and totals: the map is an
+    integer sum.  The overflow numerator is also checked against the oracle's map."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    saved = pl.scatter_policy()
+    snaps = {}
+    try:
+        for every, deferred in ((4, True), (4, False), (1, True), (3, False), (7, True)):
+            pl.set_scatter_policy(every, deferred)
+            assert pl.scatter_policy() == (every, deferred)
+            s = pl.new_slot()
+            pl.set_positions(s, nl.x0, nl.y0)
+            pl.set_schedule(s, 1e-4, 4.0, 200)
+            pl.iterate(s, gamma, 9, hpwl=True)
+            vx, vy = pl.eval_positions(s)
+            pl.eval(s, gamma, keep_maps=True)
+            rm, rf = o.density_q(vx, vy)
+            assert np.array_equal(pl.map(s, hy.HP_MAP_RHO_MOV), rm), (every, deferred)
+            st = pl.state(s)
+            assert st["overflow_num"] == o.overflow(rm, rf)[1]
+            x, y = pl.positions(s)
+            snaps[(every, deferred)] = (st["hpwl_q"], st["wl"], st["energy"], x.tobytes(),
+                                        y.tobytes())
+            pl.free_slot(s)
+    finally:
+        pl.set_scatter_policy(*saved)
+    first = next(iter(snaps.values()))
+    assert all(v == first for v in snaps.values())
+
+
+def test_scatter_policy_rejects_bad_values(hy, orc):
+    nl, pl, o = setup(hy, orc, "tiny", 64)
+    L = hy.lib()
+    for every, deferred in ((0, 1), (65, 1), (4, 2)):
+        assert L.hp_set_scatter_policy(pl.ctx, pl.netlist, every, deferred) == hy.HP_EINVAL
+    assert L.hp_set_scatter_policy(pl.ctx, 99, 4, 1) == hy.HP_ESTATE
+    assert pl.scatter_policy() == (4, True)  # unchanged
+
+
+def test_autotuner_picks_a_candidate_and_caches(hy, orc, tmp_path):
+    from paper_2402_18311_amd import autotune
+    nl, pl, o = setup(hy, orc, "small", 32)
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    x0, y0 = pl.positions(s)
+    saved = pl.scatter_policy()
+    cache = str(tmp_path / "tune.json")
+    try:
+        best, t = autotune.tune_scatter(pl, [s], gamma, warm=2, iters=4, repeats=1, cache=cache)
+        assert best in autotune.CANDIDATES and len(t) == len(autotune.CANDIDATES)
+        assert pl.scatter_policy() == best
+        pl.set_scatter_policy(*saved)
+        best2, _ = autotune.tune_scatter(pl, [s], gamma, cache=cache)  # from the cache
+        assert best2 == best and pl.scatter_policy() == best
+        x1, y1 = pl.positions(s)  # the tuned slot itself is untouched
+        assert np.array_equal(x0, x1) and np.array_equal(y0, y1)
+    finally:
+        pl.set_scatter_policy(*saved)
+        pl.free_slot(s)
+
+
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("tiny", 32), ("small", 32)])
 def test_lambda_init_and_nesterov_steps(hy, orc, case, prec):
     """First evaluation derives lambda_0; three [eval, step] iterations follow the oracle."""
