@@ -261,6 +261,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc output folders to the stored traffic "
                          "record and exit")
+    ap.add_argument("--scatter-policy", metavar="EVERY,DEFERRED",
+                    help="use this charge-scatter policy (e.g. 8,1) instead of timing the "
+                         "candidates before the round")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the round, copy 256 MiB device-to-device once: the reference "
                          "dispatch for scaling hardware byte counters")
@@ -318,10 +321,15 @@ def main():
 
     # the scatter's grouping policy, chosen by timing (untimed) from the state the timed round
     # starts in: the incumbent with a Gaussian perturbation
-    from paper_2402_18311_amd import autotune
-    restart_from_incumbent(K)
-    pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0x7E57, want_idx=False)
-    policy, tune_ms = autotune.tune_scatter(pl, [work], gamma)
+    if args.scatter_policy:
+        e, d = (int(v) for v in args.scatter_policy.split(","))
+        pl.set_scatter_policy(e, bool(d))
+        policy, tune_ms = pl.scatter_policy(), {}
+    else:
+        from paper_2402_18311_amd import autotune
+        restart_from_incumbent(K)
+        pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0x7E57, want_idx=False)
+        policy, tune_ms = autotune.tune_scatter(pl, [work], gamma)
     log(f"[bench] scatter policy {policy} ({tune_ms})")
 
     # kernel table: a short round with every launch bracketed by events
