@@ -249,7 +249,11 @@ template <typename T>
 __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ pos, T invg,
                          vec2<T> *__restrict__ pg, double &wl) {
     __shared__ T red[4 * 8];
-    __shared__ vec2<T> sp[kNetRegs * kBlock];
+    // the staged pins live in the launch's dynamic LDS, which the scatter's blocks of the same
+    // launch use for their histograms or windows (a block does one job), so a block reserves
+    // the larger of the two rather than their sum
+    extern __shared__ __align__(16) unsigned char sweep_lds[];
+    vec2<T> *sp = reinterpret_cast<vec2<T> *>(sweep_lds);  // [kNetRegs * kBlock]
     const int s = nd.net_start[net], d = nd.net_start[net + 1] - s;
     const T inf = pos_inf<T>();
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
 //                             loads.
 // nacc and ncnt are multiples of 8, so the sweep keeps the XCD striping of its own blocks.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
+__global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
                                                             SlotLayout L, T invg, int nacc,
                                                             int ncnt, uint32_t hmask) {
     char *base = sa.base[blockIdx.y];
@@ -557,7 +561,10 @@ hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs
                              bool accum, bool count, hipStream_t st) {
     const int nacc = accum ? (nd.max_chunks + kXcds - 1) / kXcds * kXcds : 0;
     const int ncnt = count ? (nd.sort_blocks + kXcds - 1) / kXcds * kXcds : 0;
-    const size_t lds = std::max(accum ? scatter_accum_lds(nd) : 0, count ? scatter_count_lds(nd) : 0);
+    // dynamic LDS: the largest need of the three jobs (a block does one of them)
+    const size_t big = (bk.n > 0 && bk.G[0] == 0) ? sizeof(vec2<T>) * kNetRegs * kBlock : 0;
+    const size_t lds = std::max({accum ? scatter_accum_lds(nd) : 0,
+                                 count ? scatter_count_lds(nd) : 0, big});
     dim3 grid(nacc + ncnt + bk.total_blocks, sa.n);
     HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
               L, (T)inv_gamma, nacc, ncnt, hpwl_mask);
