@@ -187,7 +187,10 @@ struct Slot {
     bool maps_valid = false;
     bool hpwl_requested = false; // hp_hpwl was called; its sweep is not launched yet
     bool hpwl_pending = false;  // an HPWL sweep was launched; its partials are not yet reduced
-    bool step_proposed = false; // the last evaluation formed the next step's proposal
+    bool step_proposed = false; // the last evaluation formed the next step's proposal...
+    bool step_fused = false;    // ... or only its partials, for the fused step to reduce
+    bool totals_pending = false; // the last evaluation's WL / energy / overflow not yet reduced
+    int bank = 0;               // current bank of the optimiser state (Scalars::kb, ab, alphab)
     int since_group = -1;       // evaluations since the scatter's tile order was built (-1: none)
     bool rho_dirty = false;     // rho holds a kept map, not zeros
 };
@@ -652,6 +655,28 @@ int finish_hpwl(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
     return HP_OK;
 }
 
+// The WL / energy / overflow totals of evaluations that left them to be reduced when read
+// (fused steady state), from the partials the evaluation wrote (no later launch writes them
+// before the slot's next evaluation).
+int finish_totals(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
+    SlotArgs sa{};
+    auto flush = [&]() -> int {
+        HP_CHECK(launch_eval_finish(NL->nd, sa, NL->L, NL->bk.total_blocks, NL->e_parts,
+                                    spectral_overflow_parts(NL->nd), 0, false, 0.0, false, 0,
+                                    ctx->stream));
+        sa.n = 0;
+        return HP_OK;
+    };
+    for (Slot *s : ss) {
+        if (!s->totals_pending) continue;
+        s->totals_pending = false;
+        sa.base[sa.n++] = s->base;
+        if (sa.n == kMaxSlots) HP_TRY(flush());
+    }
+    if (sa.n) HP_TRY(flush());
+    return HP_OK;
+}
+
 int check_eval_params(const hp_eval_params *p) {
     if (!p) return fail(HP_EINVAL, "params is NULL");
     if (!(p->gamma > 0) || !std::isfinite(p->gamma)) return fail(HP_EINVAL, "gamma must be > 0");
@@ -685,6 +710,11 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
                 s->hpwl_pending = true;
             }
         }
+        uint32_t banks = 0;
+        for (int i = 0; i < sa.n; ++i) banks |= (uint32_t)ss[c * kMaxSlots + i]->bank << i;
+        // steady state with few enough cell-gradient partials: no closing reduction; the step
+        // derives its proposal itself and the totals are reduced when first read
+        const bool fused = !any_init && cell_parts(nd) <= kFusedStepParts;
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
         // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
         // a netlist whose policy is not deferred, counts for a new order in the first launch
@@ -704,13 +734,16 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
-                                     st));
+                                     !fused, banks, st));
         if (any_init) HP_CHECK(launch_combine<T>(nd, sa, L, st));
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];
             s->maps_valid = p->keep_maps != 0;
-            // a steady-state evaluation (lambda known) also proposed the next step
+            // a steady-state evaluation (lambda known) also proposed the next step (or, fused,
+            // left its partials for the step to reduce)
             s->step_proposed = use_fixed || s->lambda_valid;
+            s->step_fused = fused && s->step_proposed;
+            s->totals_pending = fused;
             if (!use_fixed) s->lambda_valid = true;
             s->since_group = count_now ? 1 : s->since_group + 1;
             s->rho_dirty = p->keep_maps != 0;
@@ -739,6 +772,7 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
                                         Nm * rs, hipMemcpyDeviceToDevice, st));
     }
     if (wl || energy || overflow) {
+        HP_TRY(finish_totals(ctx, NL, ss));
         std::vector<Scalars> h(n);
         for (int i = 0; i < n; ++i)
             HP_CHECK(hipMemcpyAsync(&h[i], ss[i]->base + L.scal, sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -754,7 +788,7 @@ int eval_impl(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params
 
 void init_scalars(Scalars &s, double scale, double decades, int iters) {
     std::memset(&s, 0, sizeof(s));
-    s.a = 1.0;
+    s.ab[0] = s.ab[1] = 1.0;
     s.lambda0_scale = scale;
     s.lambda_ratio = std::pow(10.0, decades / iters);
     s.best = -1;
@@ -798,14 +832,29 @@ int step_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
     HP_TRY(launch_requested_hpwl(ctx, NL, ss));  // the step changes u
     for (size_t c = 0; c < chunks.size(); ++c) {
         const SlotArgs &sa = chunks[c];
-        bool proposed = true;
-        for (int i = 0; i < sa.n; ++i) proposed &= ss[c * kMaxSlots + i]->step_proposed;
+        // all proposed by their closing reductions: update only; all fused: the update derives
+        // the proposals; otherwise (a second step on one gradient, or a mix): reductions and
+        // proposals again from the gradient
+        bool proposed = true, fused = true, any_fused = false;
+        uint32_t banks = 0;
+        for (int i = 0; i < sa.n; ++i) {
+            const Slot *s = ss[c * kMaxSlots + i];
+            proposed &= s->step_proposed;
+            fused &= s->step_fused;
+            any_fused |= s->step_fused;
+            banks |= (uint32_t)s->bank << i;
+        }
+        if (any_fused && !fused) proposed = false;
         if (ctx->precision == 32)
-            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, proposed, ctx->stream));
+            HP_CHECK(launch_step<float>(NL->nd, sa, NL->L, proposed, fused, banks, ctx->stream));
         else
-            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, proposed, ctx->stream));
+            HP_CHECK(launch_step<double>(NL->nd, sa, NL->L, proposed, fused, banks, ctx->stream));
     }
-    for (Slot *s : ss) s->step_proposed = false;
+    for (Slot *s : ss) {
+        s->step_proposed = false;
+        s->step_fused = false;
+        s->bank ^= 1;  // the step committed into the other bank
+    }
     return HP_OK;
 }
 
@@ -1012,9 +1061,11 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + L.scal, sizeof(h), hipMemcpyDeviceToHost, st));
     HP_CHECK(hipStreamSynchronize(st));
-    h.k = 0;
-    h.a = 1.0;
-    h.alpha = 0.0;
+    for (int b = 0; b < 2; ++b) {  // the optimiser restarts (both banks)
+        h.kb[b] = 0;
+        h.ab[b] = 1.0;
+        h.alphab[b] = 0.0;
+    }
     h.lambda_valid = 0;
     h.hpwl_valid = 0;
     HP_CHECK(hipMemcpyAsync(s->base + L.scal, &h, sizeof(h), hipMemcpyHostToDevice, st));
@@ -1022,6 +1073,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     s->lambda_valid = false;
     s->hpwl_pending = false;
     s->step_proposed = false;
+    s->step_fused = false;
     s->since_group = -1;
     return HP_OK;
 }
@@ -1205,6 +1257,7 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
                                         sigma_bins * n->nd.hb, seed, ctx->stream));
     s->lambda_valid = false;
     s->step_proposed = false;
+    s->step_fused = false;
     s->since_group = -1;
     s->hpwl_pending = false;  // the device cleared hpwl_valid
     if (out_idx && m)
@@ -1239,6 +1292,7 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbe
         HP_CHECK(launch_select_best<double>(NL->nd, chunks[0], inc->base, NL->L, ctx->stream));
     inc->lambda_valid = false;  // conservatively: the device resets it when a candidate wins
     inc->step_proposed = false;
+    inc->step_fused = false;
     inc->since_group = -1;
     if (out_best) {
         int64_t b = -1;
@@ -1294,14 +1348,15 @@ int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
     if (!out) return fail(HP_EINVAL, "out is NULL");
     rc = finish_hpwl(ctx, n, std::vector<Slot *>{s});
     if (rc) return rc;
+    HP_TRY(finish_totals(ctx, n, std::vector<Slot *>{s}));
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
-    out->k = h.k;
+    out->k = h.kb[s->bank];
     out->hpwl_q = h.hpwl_valid ? h.hpwl_q : -1;
     out->overflow_num = h.overflow_num;
-    out->a = h.a;
-    out->alpha = h.alpha;
+    out->a = h.ab[s->bank];
+    out->alpha = h.alphab[s->bank];
     out->lambda = h.lambda;
     out->wl = h.wl;
     out->energy = h.energy;

@@ -251,19 +251,29 @@ __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, c
 // Step proposal from the totals of the three reductions: alpha_0 = 0.1 bin / max|g~| on the
 // first step, else alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein, the previous
 // alpha when the gradient did not change); a' = (1 + sqrt(4 a^2 + 1)) / 2 and momentum
-// (a - 1) / a'.  The step kernel commits it (a = a', k + 1, lambda times the ratio).
-__device__ __forceinline__ void step_propose(Scalars *sc, double DV, double DG, double GM,
-                                             double wb) {
-    double alpha;
-    if (sc->k == 0)
-        alpha = 0.1 * wb / (GM > 1e-30 ? GM : 1e-30);
+// (a - 1) / a'.  k, a and the previous alpha are the optimiser state of the current bank.
+struct StepProposal {
+    double alpha, coef, a;
+};
+__device__ __forceinline__ StepProposal propose_step(int64_t k, double a, double alpha_prev,
+                                                     double DV, double DG, double GM, double wb) {
+    StepProposal p;
+    if (k == 0)
+        p.alpha = 0.1 * wb / (GM > 1e-30 ? GM : 1e-30);
     else
-        alpha = DG > 0.0 ? sqrt(DV) / sqrt(DG) : sc->alpha;
-    const double a = sc->a;
-    const double an = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
-    sc->step_alpha = alpha;
-    sc->step_coef = (a - 1.0) / an;
-    sc->step_a = an;
+        p.alpha = DG > 0.0 ? sqrt(DV) / sqrt(DG) : alpha_prev;
+    p.a = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
+    p.coef = (a - 1.0) / p.a;
+    return p;
+}
+// The proposal from bank b, stored for the step kernel, which commits it (bank 1 - b gets
+// a', alpha and k + 1).
+__device__ __forceinline__ void step_propose(Scalars *sc, double DV, double DG, double GM,
+                                             double wb, int b) {
+    const StepProposal p = propose_step(sc->kb[b], sc->ab[b], sc->alphab[b], DV, DG, GM, wb);
+    sc->step_alpha = p.alpha;
+    sc->step_coef = p.coef;
+    sc->step_a = p.a;
 }
 
 // Movable charge of bin (k, j) assembled from the binned scatter's chunk windows: the chunks

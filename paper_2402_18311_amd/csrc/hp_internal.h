@@ -100,11 +100,17 @@ enum { PART_WL = 0, PART_E = 1, PART_N1 = 2, PART_N2 = 3, PART_DV = 4, PART_DG =
        PART_GMAX = 6, PART_HPWL = 7, PART_OVF = 8, PART_COUNT = 9 };
 
 // Per-slot scalars in device memory.
+// The optimiser's own state (Nesterov a, the last step size alpha, the iteration count k) is
+// held in two banks: a step reads bank b and writes bank 1 - b, and the host tracks b per slot
+// (passed to kernels as one bit per slot of the launch).  So every block of a step may read
+// the state it proposes from while one of them commits the next, with no ordering between
+// them.  Resets write both banks.
 struct Scalars {
-    double a, alpha, lambda, lambda_step, lambda0_scale, lambda_ratio;
+    double ab[2], alphab[2];
+    double lambda, lambda_step, lambda0_scale, lambda_ratio;
     double wl, energy, overflow;
     double step_alpha, step_coef, step_a;  // proposal of the next step (see step_propose)
-    int64_t k;
+    int64_t kb[2];
     int64_t lambda_valid;   // 0 until lambda_0 is derived at the first evaluation
     int64_t init_this_eval; // the last evaluation derived lambda_0
     int64_t hpwl_q, hpwl_valid;
@@ -173,17 +179,23 @@ hipError_t launch_join_pairs(const void *x, const void *y, void *pairs, int n, s
 template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st);
-// The cell-gradient launch is followed by the evaluation's closing reduction (totals of nwl
-// sweep, ne energy and nov overflow partials; lambda_0 on a first evaluation).
+// The evaluation's closing reduction: totals of nwl sweep, ne energy and nov overflow
+// partials; with `full` also lambda_0 on a first evaluation, the step's lambda and, in steady
+// state, the step's proposal from the optimiser state in bank (banks >> slot) & 1.
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
-                              hipStream_t st);
+                              bool full, uint32_t banks, hipStream_t st);
+// At most this many cell-gradient partials let every block of the step reduce them itself
+// (the fused step: no closing reduction launch in steady state).
+constexpr int kFusedStepParts = 1024;
 hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, int nparts, hipStream_t st);
 // grad_mode 0: field force -sum q xi; 1: exact adjoint sum psi dq/dx (needs the psi map).
+// `finish`: launch the closing reduction after it (else the totals are left to a later
+// totals-only reduction and the proposal to the fused step).
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
-                            int nov, hipStream_t st);
+                            int nov, bool finish, uint32_t banks, hipStream_t st);
 template <typename T>
 hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                           hipStream_t st);
@@ -192,10 +204,12 @@ int spectral_overflow_parts(const NetDev &nd);
 template <typename T> size_t spectral_max_lds(const NetDev &nd);
 template <typename T> hipError_t spectral_prepare(int bytes);
 // One Nesterov step; `proposed`: every slot's evaluation already formed the step's
-// reductions and proposal (steady state), so only the update runs.
+// reductions and proposal (steady state), so only the update runs; `fused`: every slot's
+// evaluation formed the reductions' partials but no proposal, which each block of the update
+// then derives itself.  banks: the optimiser-state bank of each slot (bit s).
 template <typename T>
 hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool proposed,
-                       hipStream_t st);
+                       bool fused, uint32_t banks, hipStream_t st);
 template <typename T>
 hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,
                             int64_t *rho_fixed, hipStream_t st);

@@ -228,6 +228,9 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
     T *g = reinterpret_cast<T *>(base + L.g);
     if (!init) {
         const double lam_step = use_fixed ? lam_fixed : sc->lambda;
+        // the step's lambda (no block of this pass reads the field; the closing reduction, when
+        // it runs, writes the same value)
+        if (cb == 0 && threadIdx.x == 0) sc->lambda_step = lam_step;
         const T lam = (T)lam_step;
         const T g0 = gwx + lam * gdx, g1 = gwy + lam * gdy;
         if (i < nd.n_mov) {
@@ -317,14 +320,15 @@ hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayo
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
-                            int nov, hipStream_t st) {
+                            int nov, bool finish, uint32_t banks, hipStream_t st) {
     const int nb = std::max(1, cell_parts(nd));
     const int grid = (nb + kXcds - 1) / kXcds * kXcds;
     HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(grid, sa.n), dim3(kBlock), 0, st, nd,
               sa, L, lambda_fixed, (int)use_fixed, grad_mode, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, st);
+    if (!finish) return hipSuccess;
+    return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, true, banks, st);
 }
 
 template <typename T>
@@ -340,7 +344,7 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 #define HP_INST(T)                                                                          \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
                                             const SlotLayout &, double, bool, int, int, int, \
-                                            int, hipStream_t);                              \
+                                            int, bool, uint32_t, hipStream_t);                              \
     template hipError_t launch_fixed_map<T>(const NetDev &, const double *, const double *, \
                                             int64_t *, hipStream_t);
 HP_INST(float)

@@ -49,9 +49,11 @@ __global__ __launch_bounds__(kBlock) void perturb_init_kernel(NetDev nd, char *b
     const int i = blockIdx.x * kBlock + threadIdx.x;
     Scalars *sc = scalars(base, L);
     if (i == 0) {
-        sc->k = 0;
-        sc->a = 1.0;
-        sc->alpha = 0.0;
+        for (int b = 0; b < 2; ++b) {  // both banks of the optimiser state
+            sc->kb[b] = 0;
+            sc->ab[b] = 1.0;
+            sc->alphab[b] = 0.0;
+        }
         sc->lambda_valid = 0;
         sc->hpwl_valid = 0;
         sc->sel_prefix = 0;

@@ -17,14 +17,16 @@ constexpr int kFinWaves = kFinBlock / 64;
 
 __global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                                int nwl, int ne, int nov, int ncell,
-                                                               int use_fixed, double lam_fixed) {
+                                                               int use_fixed, double lam_fixed,
+                                                               int full, uint32_t banks) {
     __shared__ double rs[kFinWaves][4], rm[kFinWaves];
     __shared__ long long ri[kFinWaves];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
-    const bool init = !use_fixed && sc->lambda_valid == 0;
-    const bool prop = !init && ncell > 0;
+    // totals only (full = 0): the WL, energy and overflow of the last evaluation, nothing else
+    const bool init = full && !use_fixed && sc->lambda_valid == 0;
+    const bool prop = full && !init && ncell > 0;
     // One pass over all partial arrays with their loads in flight together (thread t takes
     // elements t, t + 1024, ... of each, in order), then a fixed tree over the waves.
     const double *pw = part + PART_WL * L.pstride, *pe = part + PART_E * L.pstride;
@@ -108,13 +110,15 @@ __global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nd, SlotA
         sc->energy = 0.5 * nd.wb * nd.hb * t[1];
         sc->overflow_num = OV;
         sc->overflow = (double)OV / (double)nd.total_charge;
-        sc->init_this_eval = init ? 1 : 0;
-        if (init) {
-            sc->lambda = sc->lambda0_scale * (t[3] > 0.0 ? t[2] / t[3] : 1.0);
-            sc->lambda_valid = 1;
+        if (full) {
+            sc->init_this_eval = init ? 1 : 0;
+            if (init) {
+                sc->lambda = sc->lambda0_scale * (t[3] > 0.0 ? t[2] / t[3] : 1.0);
+                sc->lambda_valid = 1;
+            }
+            sc->lambda_step = use_fixed ? lam_fixed : sc->lambda;
+            if (prop) step_propose(sc, t[2], t[3], GM, nd.wb, (banks >> blockIdx.y) & 1u);
         }
-        sc->lambda_step = use_fixed ? lam_fixed : sc->lambda;
-        if (prop) step_propose(sc, t[2], t[3], GM, nd.wb);
     }
 }
 
@@ -133,9 +137,9 @@ __global__ __launch_bounds__(kBlock) void hpwl_finish_kernel(SlotArgs sa, SlotLa
 
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
-                              hipStream_t st) {
+                              bool full, uint32_t banks, hipStream_t st) {
     HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kFinBlock), 0, st, nd, sa,
-              L, nwl, ne, nov, ncell, (int)use_fixed, lam_fixed);
+              L, nwl, ne, nov, full ? ncell : 0, (int)use_fixed, lam_fixed, (int)full, banks);
     return hipGetLastError();
 }
 
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void step_norms_kernel(NetDev nd, SlotArgs 
 
 // Totals of those reductions and the step proposal.
 __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                             int nb) {
+                                                             int nb, uint32_t banks) {
     __shared__ double red[4];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
@@ -184,28 +188,88 @@ __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArg
     const double DV = sum_parts(part + PART_DV * L.pstride, nb, red);
     const double DG = sum_parts(part + PART_DG * L.pstride, nb, red);
     const double GM = max_parts(part + PART_GMAX * L.pstride, nb, red);
-    if (threadIdx.x == 0) step_propose(sc, DV, DG, GM, nd.wb);
+    if (threadIdx.x == 0) step_propose(sc, DV, DG, GM, nd.wb, (banks >> blockIdx.y) & 1u);
 }
 
-// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~.  One
-// thread commits the proposal (a = a', alpha, k + 1, lambda times the schedule's ratio); the
-// other blocks read only the proposal's own fields.
+// Totals of the step's three reductions over the cell-gradient pass's n partials, formed by
+// one block (every thread gets them): thread t takes partials t, t + 256, ... of the three
+// arrays in one pass, then the wave butterflies and the tree of block_sum / block_max.
+__device__ __forceinline__ void step_totals(const double *part, const SlotLayout &L, int n,
+                                            double *red, double &DV, double &DG, double &GM) {
+    const double *pv = part + PART_DV * L.pstride, *pg = part + PART_DG * L.pstride;
+    const double *pm = part + PART_GMAX * L.pstride;
+    double v = 0.0, g = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 4 * kBlock) {
+        double a[4], b[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = i + u * kBlock;
+            a[u] = j < n ? pv[j] : 0.0;
+            b[u] = j < n ? pg[j] : 0.0;
+            c[u] = j < n ? pm[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v += a[u];
+            g += b[u];
+            m = fmax(m, c[u]);
+        }
+    }
+    v = group_sum<64>(v);
+    g = group_sum<64>(g);
+    m = group_max<64>(m);
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        red[w] = v;
+        red[4 + w] = g;
+        red[8 + w] = m;
+    }
+    __syncthreads();
+    DV = (red[0] + red[1]) + (red[2] + red[3]);
+    DG = (red[4] + red[5]) + (red[6] + red[7]);
+    GM = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
+}
+
+// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~.  The
+// step (alpha, coef, a') is the proposal stored by the evaluation's closing reduction or the
+// step-scalars kernel, or (fused) derived by every block itself from the cell-gradient pass's
+// nc partials and the optimiser state of bank b.  One thread commits it into bank 1 - b
+// (a = a', alpha, k + 1) and multiplies lambda by the schedule's ratio; no block reads what
+// that thread writes.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+__global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                             int fused, int nc, uint32_t banks) {
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
+    const int b = (banks >> blockIdx.y) & 1u;
     const int n = nd.n_mov;
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    StepProposal pr;
+    if (fused) {
+        __shared__ double red[12];
+        double DV, DG, GM;
+        step_totals(reinterpret_cast<const double *>(base + L.part), L, nc, red, DV, DG, GM);
+        pr = propose_step(sc->kb[b], sc->ab[b], sc->alphab[b], DV, DG, GM, nd.wb);
+    } else {
+        pr.alpha = sc->step_alpha;
+        pr.coef = sc->step_coef;
+        pr.a = sc->step_a;
+    }
     if (i == 0) {
-        sc->a = sc->step_a;
-        sc->alpha = sc->step_alpha;
-        sc->k += 1;
+        if (fused) {
+            sc->step_alpha = pr.alpha;
+            sc->step_coef = pr.coef;
+            sc->step_a = pr.a;
+        }
+        sc->ab[1 - b] = pr.a;
+        sc->alphab[1 - b] = pr.alpha;
+        sc->kb[1 - b] = sc->kb[b] + 1;
         if (sc->lambda_valid) sc->lambda *= sc->lambda_ratio;
     }
     if (i >= n) return;
     const T *cs = reinterpret_cast<const T *>(nd.cstep);
     const double P = precond(cs, n, i, sc->lambda_step);
-    const double alpha = sc->step_alpha, coef = sc->step_coef;
+    const double alpha = pr.alpha, coef = pr.coef;
     vec2<T> *u = reinterpret_cast<vec2<T> *>(base + L.u);
     vec2<T> *v = reinterpret_cast<vec2<T> *>(base + L.v);
     vec2<T> *vp = reinterpret_cast<vec2<T> *>(base + L.vprev);
@@ -253,9 +317,11 @@ __global__ void select_best_kernel(SlotArgs sa, char *inc, SlotLayout L) {
     if (best >= 0) {
         is->hpwl_q = bv;
         is->hpwl_valid = 1;
-        is->k = 0;
-        is->a = 1.0;
-        is->alpha = 0.0;
+        for (int b = 0; b < 2; ++b) {  // the optimiser restarts (both banks)
+            is->kb[b] = 0;
+            is->ab[b] = 1.0;
+            is->alphab[b] = 0.0;
+        }
         is->lambda_valid = 0;
     }
 }
@@ -285,22 +351,23 @@ hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout
 
 template <typename T>
 hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, bool proposed,
-                       hipStream_t st) {
+                       bool fused, uint32_t banks, hipStream_t st) {
     const int nc = cell_parts(nd);
     if (nc == 0) return hipSuccess;
     hipError_t e;
+    fused = fused && proposed && nc <= kFusedStepParts;
     if (!proposed) {
         HP_LAUNCH("step_norms_kernel", step_norms_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd,
                   sa, L);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         HP_LAUNCH("step_scalars_kernel", step_scalars_kernel, dim3(1, sa.n), dim3(kBlock), 0, st, nd,
-                  sa, L, nc);
+                  sa, L, nc, banks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa,
-              L);
+              L, (int)fused, nc, banks);
     return hipGetLastError();
 }
 
@@ -319,7 +386,7 @@ hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumb
     template hipError_t launch_combine<T>(const NetDev &, const SlotArgs &, const SlotLayout &,  \
                                           hipStream_t);                                         \
     template hipError_t launch_step<T>(const NetDev &, const SlotArgs &, const SlotLayout &,     \
-                                       bool, hipStream_t);                                      \
+                                       bool, bool, uint32_t, hipStream_t);                      \
     template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \
                                               const SlotLayout &, hipStream_t);
 HP_INST(float)
