@@ -662,8 +662,8 @@ int finish_totals(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
     SlotArgs sa{};
     auto flush = [&]() -> int {
         HP_CHECK(launch_eval_finish(NL->nd, sa, NL->L, NL->bk.total_blocks, NL->e_parts,
-                                    spectral_overflow_parts(NL->nd), 0, false, 0.0, false, 0,
-                                    ctx->stream));
+                                    spectral_overflow_parts(NL->nd), 0, false, 0.0, FIN_TOTALS,
+                                    0, ctx->stream));
         sa.n = 0;
         return HP_OK;
     };
@@ -712,9 +712,11 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         }
         uint32_t banks = 0;
         for (int i = 0; i < sa.n; ++i) banks |= (uint32_t)ss[c * kMaxSlots + i]->bank << i;
-        // steady state with few enough cell-gradient partials: no closing reduction; the step
-        // derives its proposal itself and the totals are reduced when first read
+        // steady state: the totals are reduced when first read; with few enough cell-gradient
+        // partials there is no closing reduction at all (the step derives its proposal itself),
+        // else it forms the step only
         const bool fused = !any_init && cell_parts(nd) <= kFusedStepParts;
+        const int finish = any_init ? FIN_FULL : (fused ? -1 : FIN_STEP);
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
         // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
         // a netlist whose policy is not deferred, counts for a new order in the first launch
@@ -734,7 +736,7 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
-                                     !fused, banks, st));
+                                     finish, banks, st));
         if (any_init) HP_CHECK(launch_combine<T>(nd, sa, L, st));
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];
@@ -743,7 +745,7 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
             // left its partials for the step to reduce)
             s->step_proposed = use_fixed || s->lambda_valid;
             s->step_fused = fused && s->step_proposed;
-            s->totals_pending = fused;
+            s->totals_pending = finish != FIN_FULL;
             if (!use_fixed) s->lambda_valid = true;
             s->since_group = count_now ? 1 : s->since_group + 1;
             s->rho_dirty = p->keep_maps != 0;

@@ -179,23 +179,25 @@ hipError_t launch_join_pairs(const void *x, const void *y, void *pairs, int n, s
 template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st);
-// The evaluation's closing reduction: totals of nwl sweep, ne energy and nov overflow
-// partials; with `full` also lambda_0 on a first evaluation, the step's lambda and, in steady
-// state, the step's proposal from the optimiser state in bank (banks >> slot) & 1.
+// The evaluation's closing reduction: FIN_TOTALS, the totals of nwl sweep, ne energy and nov
+// overflow partials; FIN_STEP, the step's lambda and, in steady state, its proposal from the
+// optimiser state in bank (banks >> slot) & 1; FIN_FULL, both and lambda_0 on a first
+// evaluation.
+enum { FIN_TOTALS = 0, FIN_FULL = 1, FIN_STEP = 2 };
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
-                              bool full, uint32_t banks, hipStream_t st);
+                              int mode, uint32_t banks, hipStream_t st);
 // At most this many cell-gradient partials let every block of the step reduce them itself
 // (the fused step: no closing reduction launch in steady state).
 constexpr int kFusedStepParts = 1024;
 hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, int nparts, hipStream_t st);
 // grad_mode 0: field force -sum q xi; 1: exact adjoint sum psi dq/dx (needs the psi map).
-// `finish`: launch the closing reduction after it (else the totals are left to a later
-// totals-only reduction and the proposal to the fused step).
+// finish: the closing reduction's mode after it (FIN_*), or -1 for none (the totals are then
+// left to a later totals-only reduction and the proposal to the fused step).
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
-                            int nov, bool finish, uint32_t banks, hipStream_t st);
+                            int nov, int finish, uint32_t banks, hipStream_t st);
 template <typename T>
 hipError_t launch_combine(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                           hipStream_t st);

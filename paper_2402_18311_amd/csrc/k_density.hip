@@ -320,15 +320,15 @@ hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayo
 template <typename T>
 hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             double lambda_fixed, bool use_fixed, int grad_mode, int nwl, int ne,
-                            int nov, bool finish, uint32_t banks, hipStream_t st) {
+                            int nov, int finish, uint32_t banks, hipStream_t st) {
     const int nb = std::max(1, cell_parts(nd));
     const int grid = (nb + kXcds - 1) / kXcds * kXcds;
     HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(grid, sa.n), dim3(kBlock), 0, st, nd,
               sa, L, lambda_fixed, (int)use_fixed, grad_mode, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (!finish) return hipSuccess;
-    return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, true, banks, st);
+    if (finish < 0) return hipSuccess;
+    return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, finish, banks, st);
 }
 
 template <typename T>
@@ -344,7 +344,7 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 #define HP_INST(T)                                                                          \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
                                             const SlotLayout &, double, bool, int, int, int, \
-                                            int, bool, uint32_t, hipStream_t);                              \
+                                            int, int, uint32_t, hipStream_t);                              \
     template hipError_t launch_fixed_map<T>(const NetDev &, const double *, const double *, \
                                             int64_t *, hipStream_t);
 HP_INST(float)

@@ -18,13 +18,16 @@ constexpr int kFinWaves = kFinBlock / 64;
 __global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                                int nwl, int ne, int nov, int ncell,
                                                                int use_fixed, double lam_fixed,
-                                                               int full, uint32_t banks) {
+                                                               int mode, uint32_t banks) {
     __shared__ double rs[kFinWaves][4], rm[kFinWaves];
     __shared__ long long ri[kFinWaves];
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
-    // totals only (full = 0): the WL, energy and overflow of the last evaluation, nothing else
+    // mode FIN_TOTALS: the WL, energy and overflow of the last evaluation only; FIN_STEP: the
+    // step's lambda and proposal only (the totals are reduced when read); FIN_FULL: both, and
+    // lambda_0 on a first evaluation
+    const bool totals = mode != FIN_STEP, full = mode != FIN_TOTALS;
     const bool init = full && !use_fixed && sc->lambda_valid == 0;
     const bool prop = full && !init && ncell > 0;
     // One pass over all partial arrays with their loads in flight together (thread t takes
@@ -106,10 +109,12 @@ __global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nd, SlotA
             GM = q[0];
             OV = qi[0];
         }
-        sc->wl = t[0];
-        sc->energy = 0.5 * nd.wb * nd.hb * t[1];
-        sc->overflow_num = OV;
-        sc->overflow = (double)OV / (double)nd.total_charge;
+        if (totals) {
+            sc->wl = t[0];
+            sc->energy = 0.5 * nd.wb * nd.hb * t[1];
+            sc->overflow_num = OV;
+            sc->overflow = (double)OV / (double)nd.total_charge;
+        }
         if (full) {
             sc->init_this_eval = init ? 1 : 0;
             if (init) {
@@ -137,9 +142,11 @@ __global__ __launch_bounds__(kBlock) void hpwl_finish_kernel(SlotArgs sa, SlotLa
 
 hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L, int nwl,
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
-                              bool full, uint32_t banks, hipStream_t st) {
+                              int mode, uint32_t banks, hipStream_t st) {
+    const bool totals = mode != FIN_STEP, full = mode != FIN_TOTALS;
     HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kFinBlock), 0, st, nd, sa,
-              L, nwl, ne, nov, full ? ncell : 0, (int)use_fixed, lam_fixed, (int)full, banks);
+              L, totals ? nwl : 0, totals ? ne : 0, totals ? nov : 0, full ? ncell : 0,
+              (int)use_fixed, lam_fixed, mode, banks);
     return hipGetLastError();
 }
 
