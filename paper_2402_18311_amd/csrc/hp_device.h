@@ -199,9 +199,13 @@ __device__ inline double max_parts(const double *p, int n, double *red) {
 // Preconditioner of the Nesterov step (ePlace reading): P_i = max(1, pins_i + lambda area_i),
 // with the lambda of the evaluation that produced the gradient.
 template <typename T>
-__device__ __forceinline__ double precond(const T *cs, int n, int i, double lam) {
-    const double P = (double)cs[i] + lam * (double)cs[n + i];
+__device__ __forceinline__ double precond_of(T pins, T area, double lam) {
+    const double P = (double)pins + lam * (double)area;
     return P < 1.0 ? 1.0 : P;
+}
+template <typename T>
+__device__ __forceinline__ double precond(const T *cs, int n, int i, double lam) {
+    return precond_of<T>(cs[i], cs[n + i], lam);
 }
 
 // The step's three reductions for cell block cb (cell i = cb * 256 + threadIdx.x, gradient

@@ -251,6 +251,16 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
     const int b = (banks >> blockIdx.y) & 1u;
     const int n = nd.n_mov;
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    // the cell's own inputs first (clamped index), so that their loads are in flight while a
+    // fused step reduces the partials
+    const int ic = i < n ? i : max(n - 1, 0);  // the launcher skips n = 0
+    const T *cs = reinterpret_cast<const T *>(nd.cstep);
+    vec2<T> *u = reinterpret_cast<vec2<T> *>(base + L.u);
+    vec2<T> *v = reinterpret_cast<vec2<T> *>(base + L.v);
+    const T *g = reinterpret_cast<const T *>(base + L.g);
+    const vec2<T> v0 = v[ic], u0 = u[ic];
+    const T g0 = g[ic], g1 = g[(size_t)n + ic];
+    const T c0 = cs[ic], c1 = cs[(size_t)n + ic], hx = cs[(size_t)2 * n + ic], hy = cs[(size_t)3 * n + ic];
     StepProposal pr;
     if (fused) {
         __shared__ double red[12];
@@ -274,21 +284,16 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
         if (sc->lambda_valid) sc->lambda *= sc->lambda_ratio;
     }
     if (i >= n) return;
-    const T *cs = reinterpret_cast<const T *>(nd.cstep);
-    const double P = precond(cs, n, i, sc->lambda_step);
+    const double P = precond_of<T>(c0, c1, sc->lambda_step);
     const double alpha = pr.alpha, coef = pr.coef;
-    vec2<T> *u = reinterpret_cast<vec2<T> *>(base + L.u);
-    vec2<T> *v = reinterpret_cast<vec2<T> *>(base + L.v);
     vec2<T> *vp = reinterpret_cast<vec2<T> *>(base + L.vprev);
-    const T *g = reinterpret_cast<const T *>(base + L.g);
     T *gp = reinterpret_cast<T *>(base + L.gprev);
-    const vec2<T> v0 = v[i], u0 = u[i];
     T un2[2], vn2[2];
 #pragma unroll
     for (int ax = 0; ax < 2; ++ax) {
         const size_t ig = (size_t)ax * n + i;  // gradients: [2][n_mov]
-        const double hi = (double)cs[(2 + ax) * n + i];
-        const double gt = (double)g[ig] / P;
+        const double hi = (double)(ax ? hy : hx);
+        const double gt = (double)(ax ? g1 : g0) / P;
         double un = (double)(ax ? v0.y : v0.x) - alpha * gt;
         un = un < 0.0 ? 0.0 : (un > hi ? hi : un);
         const T unt = (T)un;
