@@ -131,6 +131,24 @@ __device__ void exact_adjoint(const NetDev &nd, const T *psi, int i, double x, d
     gdy = (T)sy;
 }
 
+// Four consecutive (xi_x, xi_y) pairs of a field row: two 16-byte loads in FP32 (the row
+// start is 8-byte aligned; the part reads 16 bytes at any 4-byte alignment), four in FP64.
+template <typename T>
+__device__ __forceinline__ void load_row4(const vec2<T> *src, vec2<T> (&r)[4]) {
+    if constexpr (sizeof(T) == 4) {
+        float4 a, b;
+        __builtin_memcpy(&a, src, 16);
+        __builtin_memcpy(&b, src + 2, 16);
+        r[0] = cmk2<T>(a.x, a.y);
+        r[1] = cmk2<T>(a.z, a.w);
+        r[2] = cmk2<T>(b.x, b.y);
+        r[3] = cmk2<T>(b.z, b.w);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = src[k];
+    }
+}
+
 // Fused cell gradient.  Wirelength part: the sum of the cell's pin gradients (fixed pin
 // order -> deterministic).  Density part: the field force, dN/dx_i = -sum_b q_ib xi_x(b),
 // with q_ib the cell's integer charge in bin b.  Steady state writes g = gWL + lambda gD;
@@ -171,13 +189,13 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
         constexpr int KR = 3, JC = 4;
         const bool small = grad_mode == 0 && has && k1 - k0 < KR && j1 - j0 < JC;
+        // the window: rows ks .. ks+2 and columns js .. js+3 of the field, inside the grid
+        // (sides >= 8 bins) and covering the footprint; each row is read as wide loads
+        const int js = min(j0, nd.mx - JC), ks = min(k0, nd.my - KR);
         vec2<T> f[KR][JC];
         if (small) {
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk)
-#pragma unroll
-                for (int jj = 0; jj < JC; ++jj)
-                    f[kk][jj] = exy[(size_t)min(k0 + kk, k1) * nd.mx + min(j0 + jj, j1)];
+            for (int kk = 0; kk < KR; ++kk) load_row4<T>(exy + (size_t)(ks + kk) * nd.mx + js, f[kk]);
         }
         for (; j + 4 <= e; j += 4) {  // four gathers in flight, summed in pin order
             const int p0 = nd.cell_pins[j], p1 = nd.cell_pins[j + 1];
@@ -200,15 +218,17 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         if (grad_mode == 1) {  // exact adjoint of the continuous charge rectangle
             exact_adjoint<T>(nd, reinterpret_cast<const T *>(base + L.psi), i, (double)p.x,
                              (double)p.y, gdx, gdy);
-        } else if (small) {
+        } else if (small) {  // the footprint's bins of the window, row-major
 #pragma unroll
             for (int kk = 0; kk < KR; ++kk) {
-                if (k0 + kk > k1) continue;
-                const T oy = (T)overlap(q.b, q.t, k0 + kk, nd.hq) * rqt;
+                const int k = ks + kk;
+                if (k < k0 || k > k1) continue;
+                const T oy = (T)overlap(q.b, q.t, k, nd.hq) * rqt;
 #pragma unroll
                 for (int jj = 0; jj < JC; ++jj) {
-                    if (j0 + jj > j1) continue;
-                    const T qq = (T)overlap(q.l, q.r, j0 + jj, nd.bq) * oy;
+                    const int jx = js + jj;
+                    if (jx < j0 || jx > j1) continue;
+                    const T qq = (T)overlap(q.l, q.r, jx, nd.bq) * oy;
                     gdx -= qq * f[kk][jj].x;
                     gdy -= qq * f[kk][jj].y;
                 }
