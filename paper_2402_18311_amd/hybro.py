@@ -296,6 +296,14 @@ class Placer:
         self.tdtype = torch.float32 if precision == 32 else torch.float64
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
         self.ctx = hp_create(device, C.c_void_p(self.stream.cuda_stream), precision)
+        try:
+            self._load(nl, target_density, stretch, fd5, net_weight)
+        except BaseException:
+            hp_destroy(self.ctx)  # a refused netlist leaves no context behind
+            self.ctx = None
+            raise
+
+    def _load(self, nl, target_density, stretch, fd5, net_weight):
         self.shape = hp_shape(nl.n_cells, nl.n_movable, int(len(nl.net_start) - 1),
                               int(len(nl.pin_cell)))
         self.die = hp_die(float(nl.W), float(nl.H), int(nl.mx), int(nl.my),

@@ -100,3 +100,41 @@ def test_degenerate_netlists_match_oracle(orc, case, prec):
     finally:
         pl.free_slot(s)
         pl.close()
+
+
+def _bad(kind):
+    nl = netgen.make_netlist("tiny", 0)
+    if kind == "net_start_decreasing":
+        ns = nl.net_start.copy()
+        ns[5], ns[6] = ns[6], ns[5]
+        return dataclasses.replace(nl, net_start=ns)
+    if kind == "pin_cell_out_of_range":
+        pc = nl.pin_cell.copy()
+        pc[17] = nl.n_cells
+        return dataclasses.replace(nl, pin_cell=pc)
+    if kind == "offset_not_finite":
+        ox = nl.pin_ox.copy()
+        ox[3] = np.nan
+        return dataclasses.replace(nl, pin_ox=ox)
+    if kind == "bins_not_power_of_two":
+        return dataclasses.replace(nl, mx=48)
+    if kind == "die_too_large":
+        return dataclasses.replace(nl, W=20000.0, H=20000.0)
+    if kind == "cell_wider_than_die":
+        w = nl.cell_w.copy()
+        w[0] = nl.W * 2
+        return dataclasses.replace(nl, cell_w=w)
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("kind", ["net_start_decreasing", "pin_cell_out_of_range",
+                                  "offset_not_finite", "bins_not_power_of_two", "die_too_large",
+                                  "cell_wider_than_die"])
+def test_invalid_netlists_are_rejected(kind):
+    """Load-time validation on the host: a bad netlist or die is refused with HP_EINVAL and a
+    message, before any device work."""
+    from paper_2402_18311_amd import hybro as hy
+    with pytest.raises(hy.HybroError) as e:
+        hy.Placer(_bad(kind), precision=32)
+    assert e.value.code == hy.HP_EINVAL
+    assert str(e.value)
