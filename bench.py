@@ -272,7 +272,7 @@ def main():
         pmc_summary(*args.pmc_summary)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs the placer on a single MI355X; "
+        print("bench.py measures one GPU: the placer runs on a single MI355X; "
               "--gpus must be 1", file=sys.stderr)
         sys.exit(2)
 

@@ -1221,7 +1221,7 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
     // Graph replay is switched off: its first run on the device stalled (a stream
     // synchronisation after the replays never returned) and the cause is not established.
     if (p->flags & HP_ITER_GRAPH)
-        return fail(HP_ENOTIMPL, "HP_ITER_GRAPH is disabled in this build (replay stalled; cause open)");
+        return fail(HP_ENOTIMPL, "HP_ITER_GRAPH is switched off (its replay stalled; cause open)");
     const hp_eval_params ep{p->gamma, -1.0, 0, 0};
     HP_TRY(check_eval_params(&ep));
     const bool with_hpwl = (p->flags & HP_ITER_HPWL) != 0;

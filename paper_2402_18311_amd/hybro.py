@@ -414,7 +414,7 @@ class Placer:
 
     def iterate(self, slots, gamma, iters, hpwl=True, graph=False):
         """iters x [evaluate at v, Nesterov step, HPWL sweep] in one call (the loop runs in the
-        library; `graph` asks for HIP graph replay, which this build rejects)."""
+        library; `graph` asks for HIP graph replay, which the library rejects)."""
         flags = (HP_ITER_HPWL if hpwl else 0) | (HP_ITER_GRAPH if graph else 0)
         hp_iterate(self.ctx, list(np.atleast_1d(slots)), gamma, iters, flags)
 
