@@ -51,10 +51,17 @@ __device__ __forceinline__ void count_body(const NetDev &nd, char *base, const S
     for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) hist[t] = 0;
     __syncthreads();
     const int i0 = blk * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        const int t = cell_tile<T>(nd, pos, i);
-        tile[i] = t;
-        atomicAdd(&hist[t], 1);
+    // four cells per thread and round, their loads (clamped in range) all in flight first
+    for (int i = i0 + threadIdx.x; i < i1; i += 4 * kBlock) {
+        int t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = cell_tile<T>(nd, pos, min(i + u * kBlock, i1 - 1));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i + u * kBlock >= i1) break;
+            tile[i + u * kBlock] = t[u];
+            atomicAdd(&hist[t[u]], 1);
+        }
     }
     __syncthreads();
     int *cnt = reinterpret_cast<int *>(base + L.scnt) + (size_t)blk * nd.ntiles;

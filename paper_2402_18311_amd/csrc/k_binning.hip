@@ -137,10 +137,19 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nd, SlotArgs s
     const int *tstart = reinterpret_cast<const int *>(base + L.tstart);
     int *sorted = reinterpret_cast<int *>(base + L.sorted);
     const int i0 = blockIdx.x * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        const int t = tile[i];
-        const int r = atomicAdd(&rank[t], 1);
-        sorted[tstart[t] + cnt[t] + r] = i;
+    // four cells per thread and round: tiles, then ranks, then offsets, each step's accesses
+    // all in flight together (indices clamped in range; only valid cells take a rank)
+    for (int i = i0 + threadIdx.x; i < i1; i += 4 * kBlock) {
+        int t[4], r[4], o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = tile[min(i + u * kBlock, i1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r[u] = i + u * kBlock < i1 ? atomicAdd(&rank[t[u]], 1) : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o[u] = tstart[t[u]] + cnt[t[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * kBlock < i1) sorted[o[u] + r[u]] = i + u * kBlock;
     }
 }
 
