@@ -52,7 +52,8 @@ enum {
 
 /* Die and bin grid.  W, H: at most 16384 (the exact HPWL works on 32-bit pin coordinates in
  * 2^-16 units, so pin coordinates must stay within (-2^15, 2^15); positions the library
- * produces stay inside the die).  mx, my: number of bins, powers of two in [8, 4096]; the bin
+ * produces stay inside the die).  mx, my: number of bins, powers of two in [8, 2048] in FP32
+ * and [8, 1024] in FP64 (the spectral passes hold rows and columns in LDS); the bin
  * width W/mx and height H/my must be multiples of 2^-12 (so bin edges are exact in the 2^-12
  * integer coordinates of the density map).  target_density: the rho_t of the overflow measure.
  * stretch: 1 spreads a small cell's charge over at least sqrt(2) bins per side (ePlace local
@@ -138,7 +139,8 @@ int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, 
  *   force -sum_b q_ib xi_b (ePlace); 1: the exact adjoint sum_b psi_b dq_ib/dx_i of the
  *   continuous charge rectangle (also computes the potential map).  keep_maps 1 keeps the charge,
  *   potential and field maps for hp_get_map.  wl/energy/overflow: host double [n_slots] or
- *   NULL (then nothing is synchronised).  grad_x/grad_y: device real [n_slots][n_movable] or
+ *   NULL (then nothing is synchronised, and in steady state the totals are reduced only when
+ *   first read, by hp_get_state).  grad_x/grad_y: device real [n_slots][n_movable] or
  *   NULL (the gradient always stays in the slot for hp_nesterov_step). */
 typedef struct {
     double gamma;
@@ -158,14 +160,11 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n_slots);
 
 /* `iters` iterations of the placer (Sec. 3.1) on every listed slot, all on the device: each is
  * hp_eval_objective_grad with the slots' scheduled lambda and the given gamma (nothing returned
- * to the host), hp_nesterov_step and, with HP_ITER_HPWL, hp_hpwl without outputs.  With
- * HP_ITER_GRAPH, once every slot is in steady state (lambda derived) the iterations run as
- * replays of a HIP graph of a fixed block of them, captured at the first such call for this
- * slot list, gamma and flags and kept until one of the slots is freed; results are
- * bit-identical with and without it.  While per-kernel timing is enabled no graph is used.
- * Leftover iterations (fewer than a block, or before steady state) run as plain launches.
- * HP_ITER_GRAPH is currently disabled and returns HP_ENOTIMPL: the first device run of the
- * replay stalled in a later stream synchronisation, and the cause is not yet established. */
+ * to the host), hp_nesterov_step and, with HP_ITER_HPWL, hp_hpwl without outputs.  Does not
+ * synchronise.  HP_ITER_GRAPH (HIP-graph replay of the steady-state iterations) is switched
+ * off and returns HP_ENOTIMPL before any launch: its first device run stalled in a later
+ * stream synchronisation, and the cause is not established.  Unknown flags or iters < 0:
+ * HP_EINVAL. */
 enum { HP_ITER_HPWL = 1, HP_ITER_GRAPH = 2 };
 typedef struct {
     double gamma;
@@ -204,6 +203,11 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, int32_t i
 enum { HP_MAP_RHO_MOV = 0, HP_MAP_RHO_FIXED = 1, HP_MAP_PSI = 2, HP_MAP_EX = 3, HP_MAP_EY = 4 };
 int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *host_dst);
 
+/* A slot's device state: iterations taken k, the last exact HPWL (2^-16 units; -1 if none
+ * since the last restart), the overflow numerator (2^-40 area units) and, in the same order
+ * as hp_eval_objective_grad reports them, Nesterov's a, the last step alpha, lambda and the
+ * last evaluation's totals.  Reduces any pending HPWL or totals first (small launches) and
+ * synchronises. */
 typedef struct {
     int64_t k, hpwl_q, overflow_num;
     double a, alpha, lambda, wl, energy, overflow;
