@@ -16,9 +16,10 @@
  *     used here (bin grid, charge stretching, cosine-basis Poisson solve, preconditioned
  *     Nesterov with a Barzilai-Borwein step, a log-linear lambda ramp) are listed with the
  *     functions that implement them.
- *   - Perturbation, Alg. 1 step "Perturb" and Sec. 4.2: select p% of the cells and shuffle
- *     their locations (Shuffle (all)); a seeded Gaussian displacement of a subset; and the
- *     fully random restart that Sec. 4.2 identifies with multiple-restart gradient descent.
+ *   - Perturbation, Alg. 1 step "Perturb" and Sec. 4.2: select p% of the cells, or of the
+ *     macros only, and shuffle their locations (Shuffle (all), Shuffle); a seeded Gaussian
+ *     displacement of a subset; and the fully random restart that Sec. 4.2 identifies with
+ *     multiple-restart gradient descent.
  *   - Best solution, Alg. 1 return step: the candidate with the smallest HPWL.
  *
  * Integer contracts (so that the FP32 device path can be compared bit for bit):
@@ -886,10 +887,16 @@ static int cmp_i32(const void *a, const void *b)
 
 enum { ORC_GAUSS = 0, ORC_SHUFFLE = 1, ORC_UNIFORM = 2 };
 
-int32_t orc_perturb(const orc_netlist *n, double *x, double *y, int mode, double fraction,
-                    double sigma_bins, uint64_t seed, int32_t *idx)
+/* Perturbation among a pool of movable cells: every movable cell (cells == NULL), or the
+ * n_pool distinct cells listed in `cells` (the macros of Hybro-Shuffle, Sec. 4.2: p% of the
+ * macros are selected and shuffled).  A pooled cell's key is its SplitMix64 draw shifted right
+ * by one bit, so that no key of the pool can equal the all-ones key of a cell outside it. */
+int32_t orc_perturb_among(const orc_netlist *n, double *x, double *y, int mode, double fraction,
+                          double sigma_bins, uint64_t seed, const int32_t *cells, int32_t n_pool,
+                          int32_t *idx)
 {
     int N = n->n_movable;
+    int P = cells ? n_pool : N;
     double wb = n->W / n->mx, hb = n->H / n->my;
     int32_t m;
     int32_t *sel = malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
@@ -897,15 +904,16 @@ int32_t orc_perturb(const orc_netlist *n, double *x, double *y, int mode, double
         m = N;
         for (int i = 0; i < N; ++i) sel[i] = i;
     } else {
-        m = (int32_t)floor(fraction * N + 0.5);
-        if (m > N) m = N;
+        m = (int32_t)floor(fraction * P + 0.5);
+        if (m > P) m = P;
         if (m < 0) m = 0;
-        keyidx *ki = malloc(sizeof(keyidx) * (size_t)(N > 0 ? N : 1));
-        for (int i = 0; i < N; ++i) {
-            ki[i].key = orc_splitmix(seed, (uint64_t)i);
-            ki[i].idx = i;
+        keyidx *ki = malloc(sizeof(keyidx) * (size_t)(P > 0 ? P : 1));
+        for (int j = 0; j < P; ++j) {
+            int c = cells ? cells[j] : j;
+            ki[j].key = cells ? orc_splitmix(seed, (uint64_t)c) >> 1 : orc_splitmix(seed, (uint64_t)c);
+            ki[j].idx = c;
         }
-        qsort(ki, (size_t)N, sizeof(keyidx), cmp_keyidx);
+        qsort(ki, (size_t)P, sizeof(keyidx), cmp_keyidx);
         for (int j = 0; j < m; ++j) sel[j] = ki[j].idx;
         qsort(sel, (size_t)m, sizeof(int32_t), cmp_i32);
         free(ki);
@@ -951,6 +959,12 @@ int32_t orc_perturb(const orc_netlist *n, double *x, double *y, int mode, double
     }
     free(sel);
     return m;
+}
+
+int32_t orc_perturb(const orc_netlist *n, double *x, double *y, int mode, double fraction,
+                    double sigma_bins, uint64_t seed, int32_t *idx)
+{
+    return orc_perturb_among(n, x, y, mode, fraction, sigma_bins, seed, NULL, 0, idx);
 }
 
 /* Best of Alg. 1: index of the smallest HPWL; ties go to the lowest index. */

@@ -89,6 +89,7 @@ def lib():
             "orc_splitmix": (u64, [u64, u64]),
             "orc_shuffle_perm": (u64, [u64, u64, u64]),
             "orc_perturb": (i32, [P, P, P, C.c_int, d, d, u64, P]),
+            "orc_perturb_among": (i32, [P, P, P, C.c_int, d, d, u64, P, i32, P]),
             "orc_argmin_i64": (i32, [P, i32]),
             "orc_num_threads": (C.c_int, []),
         }
@@ -265,6 +266,17 @@ class Oracle:
         idx = np.zeros(max(1, self.nl.n_movable), dtype=np.int32)
         m = self.L.orc_perturb(self.ref, _p(x), _p(y), int(mode), float(fraction),
                                float(sigma_bins), C.c_uint64(seed & (2**64 - 1)).value, _p(idx))
+        return x, y, idx[:m].copy()
+
+    def perturb_among(self, x, y, mode, fraction, sigma_bins, seed, cells):
+        """Perturbation restricted to the distinct movable cells `cells` (e.g. the macros)."""
+        x = _f64(x).copy()
+        y = _f64(y).copy()
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        idx = np.zeros(max(1, self.nl.n_movable), dtype=np.int32)
+        m = self.L.orc_perturb_among(self.ref, _p(x), _p(y), int(mode), float(fraction),
+                                     float(sigma_bins), C.c_uint64(seed & (2**64 - 1)).value,
+                                     _p(cells), len(cells), _p(idx))
         return x, y, idx[:m].copy()
 
 

@@ -48,6 +48,7 @@ class Netlist:
     x0: np.ndarray  # float64 [n_movable] initial lower-left x
     y0: np.ndarray
     seed: int = 0
+    macros: np.ndarray | None = None  # int32 ids of the movable macros, when there are any
 
     @property
     def n_nets(self) -> int:
@@ -95,6 +96,7 @@ class Config:
     macro_frac: float = 0.0
     locality: bool = True
     max_degree: int = 5000
+    movable_macros: bool = False  # the macros are movable cells [n_movable, n_movable + n_fixed)
 
 
 # The five workload shapes; sizes mirror Table 1 (adaptec1 for "mid", the largest
@@ -103,7 +105,10 @@ TINY = Config("tiny", 1_000, 1_100, 64, "pads", 40, "mix")
 MID = Config("mid", 210_000, 220_000, 512, "macros", 500, "mix_big", macro_frac=0.20)
 LARGE = Config("large", 2_200_000, 2_300_000, 1024, "macros", 8_000, "powerlaw",
                macro_frac=0.20)
-CONFIGS = {c.name: c for c in (TINY, MID, LARGE)}
+# "mid" with its 500 macros movable (the mixed-size case of Hybro-Shuffle, Sec. 4.2): the same
+# draws as "mid", the macros starting at their legal, non-overlapping places.
+MID_MM = dataclasses.replace(MID, name="mid_mm", movable_macros=True)
+CONFIGS = {c.name: c for c in (TINY, MID, LARGE, MID_MM)}
 
 
 def scaled_config(n_movable: int, name: str | None = None, bins: int | None = None) -> Config:
@@ -233,21 +238,31 @@ def make_netlist(cfg: Config | str, seed: int = 0) -> Netlist:
 
     x0 = rng.random(n) * (side - w_mov)
     y0 = rng.random(n) * (side - h_mov)
+    x0 = x0.astype(np.float32).astype(np.float64)
+    y0 = y0.astype(np.float32).astype(np.float64)
+    macros = None
+    if cfg.movable_macros and cfg.fixed == "macros":
+        # fixed ids already follow the movable ones, so pins keep their cells
+        macros = np.arange(n, n_cells, dtype=np.int32)
+        x0 = np.concatenate([x0, fx])
+        y0 = np.concatenate([y0, fy])
+        n, fx, fy = n_cells, np.zeros(0), np.zeros(0)
     nl = Netlist(
         name=cfg.name, n_movable=n, n_cells=n_cells,
         cell_w=cell_w.astype(np.float64), cell_h=cell_h.astype(np.float64),
         fixed_x=fx.astype(np.float64), fixed_y=fy.astype(np.float64),
         net_start=net_start.astype(np.int32), pin_cell=pin_cell.astype(np.int32),
         pin_ox=pin_ox, pin_oy=pin_oy, W=float(side), H=float(side), mx=M, my=M,
-        x0=x0.astype(np.float32).astype(np.float64), y0=y0.astype(np.float32).astype(np.float64),
-        seed=seed)
+        x0=x0, y0=y0, seed=seed, macros=macros)
     return nl
 
 
 def make_small(n_movable: int, n_nets: int, bins: int, seed: int = 0, fixed: str = "macros",
-               n_fixed: int = 8, degrees: str = "mix_big") -> Netlist:
-    """A reduced netlist for parity tests (spans several tiles and ragged tails)."""
+               n_fixed: int = 8, degrees: str = "mix_big", movable_macros: bool = False,
+               macro_frac: float = 0.20) -> Netlist:
+    """A reduced netlist for parity tests (spans several tiles and ragged tails).  With
+    movable_macros the n_fixed macros become movable cells after the standard cells."""
     cfg = Config(f"small{n_movable}", n_movable, n_nets, bins, fixed, n_fixed, degrees,
-                 macro_frac=0.20 if fixed == "macros" else 0.0,
-                 max_degree=min(5000, n_movable))
+                 macro_frac=macro_frac if fixed == "macros" else 0.0,
+                 max_degree=min(5000, n_movable), movable_macros=movable_macros)
     return make_netlist(cfg, seed)

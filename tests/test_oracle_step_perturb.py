@@ -95,6 +95,47 @@ def test_perturb_selection_is_m_smallest_keys(orc, tiny):
     assert not np.array_equal(a[2], c[2])
 
 
+def test_perturb_among_selects_within_the_pool(orc, tiny):
+    """Shuffle of Sec. 4.2 selects p% of the macros only: the round(p * |pool|) pool cells with
+    the smallest (draw >> 1, id), found here by brute force; nothing outside the pool moves, and
+    the pool's order does not matter."""
+    nl, o = tiny
+    rng = np.random.default_rng(4)
+    pool = rng.choice(nl.n_movable, 137, replace=False).astype(np.int32)
+    for mode, frac, seed in [(orc.GAUSS, 0.5, 3), (orc.SHUFFLE, 0.5, 8), (orc.GAUSS, 0.1, 2**64 - 1),
+                             (orc.SHUFFLE, 1.0, 5)]:
+        x, y, idx = o.perturb_among(nl.x0, nl.y0, mode, frac, 8.0, seed, pool)
+        m = int(math.floor(frac * len(pool) + 0.5))
+        keys = np.array([orc.splitmix(seed, int(c)) >> 1 for c in pool], dtype=np.uint64)
+        order = np.lexsort((pool, keys))
+        assert np.array_equal(idx, np.sort(pool[order[:m]]))
+        moved = (x != nl.x0) | (y != nl.y0)
+        assert not moved[np.setdiff1d(np.arange(nl.n_movable), idx)].any()
+        x2, y2, idx2 = o.perturb_among(nl.x0, nl.y0, mode, frac, 8.0, seed, pool[::-1].copy())
+        assert np.array_equal(idx2, idx) and np.array_equal(x2, x) and np.array_equal(y2, y)
+    x, y, idx = o.perturb_among(nl.x0, nl.y0, orc.SHUFFLE, 0.5, 0.0, 1, np.zeros(0, np.int32))
+    assert len(idx) == 0 and np.array_equal(x, nl.x0) and np.array_equal(y, nl.y0)
+
+
+def test_shuffle_among_macros_keeps_their_places(orc):
+    """Shuffling equal macros among themselves permutes their places exactly; the standard
+    cells stay where they are."""
+    n_std, n_mac = 300, 40
+    W = 400.0
+    rng = np.random.default_rng(6)
+    w = np.concatenate([np.full(n_std, 2.0), np.full(n_mac, 24.0)])
+    h = np.concatenate([np.ones(n_std), np.full(n_mac, 16.0)])
+    x = np.round(rng.uniform(0, W - w) * 256) / 256
+    y = np.round(rng.uniform(0, W - h) * 256) / 256
+    nl = cells_only(w, h, W, W, 64, x, y)
+    o = orc.Oracle(nl)
+    macros = np.arange(n_std, n_std + n_mac, dtype=np.int32)
+    nx, ny, idx = o.perturb_among(nl.x0, nl.y0, orc.SHUFFLE, 0.5, 0.0, 21, macros)
+    assert len(idx) == 20 and np.all(idx >= n_std)
+    assert sorted(zip(nx[idx], ny[idx])) == sorted(zip(x[idx], y[idx]))
+    assert np.array_equal(nx[:n_std], x[:n_std]) and np.array_equal(ny[:n_std], y[:n_std])
+
+
 def test_gauss_displacements_are_normal(orc):
     n = 100_000
     W = 1e6
