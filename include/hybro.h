@@ -85,8 +85,11 @@ size_t hp_slot_bytes(const hp_ctx *ctx, const hp_shape *shape, const hp_die *die
  * fixed cells are pads); fixed_x/fixed_y [n_cells - n_movable] lower-left of fixed cells;
  * net_start [n_nets + 1] non-decreasing, net_start[0] = 0, net_start[n_nets] = n_pins;
  * pin_cell [n_pins] in [0, n_cells); pin_ox/pin_oy [n_pins]; net_weight [n_nets] or NULL
- * (all 1).  Nets with fewer than two pins add nothing to Eq. 1 or Eq. 3.  Validates
- * everything above (HP_EINVAL) and dev_bytes (HP_ENOMEM).  Synchronises the stream. */
+ * (all 1).  Nets with fewer than two pins add nothing to Eq. 1 or Eq. 3.  Movable cells may
+ * be of any size up to the die, macros included: a movable cell whose charge can span more
+ * than 9 bins on an axis is scattered and gathered by a block of its own (mixed-size
+ * placement; the results are those of any other cell).  Validates everything above
+ * (HP_EINVAL) and dev_bytes (HP_ENOMEM).  Synchronises the stream. */
 int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die,
                         const double *cell_w, const double *cell_h,
                         const double *fixed_x, const double *fixed_y,
@@ -183,6 +186,17 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const hp_iter
 enum { HP_PERTURB_GAUSS = 0, HP_PERTURB_SHUFFLE = 1, HP_PERTURB_UNIFORM = 2 };
 int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins,
                uint64_t seed, int32_t *out_idx, int32_t *out_count);
+
+/* hp_perturb restricted to a pool of movable cells, as in "Shuffle" of Sec. 4.2 (p% of the
+ * macros are selected and shuffled): cells (host int32 [n_pool], distinct ids in
+ * [0, n_movable), any order; read during the call) is the pool, round(fraction * n_pool) of
+ * them move, the ones with the smallest (key, id) where a pooled cell's key is its SplitMix64
+ * draw shifted right by one bit.  GAUSS and SHUFFLE as in hp_perturb; UNIFORM, an id out of
+ * range or repeated, or cells NULL with n_pool > 0: HP_EINVAL with nothing changed.
+ * Synchronises when n_pool > 0 or an output is requested. */
+int hp_perturb_among(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins,
+                     uint64_t seed, const int32_t *cells, int32_t n_pool, int32_t *out_idx,
+                     int32_t *out_count);
 
 /* Exact HPWL (Eq. 1) of the slots' major solutions u on pin coordinates quantized to 2^-16:
  * out_q (host int64 [n_slots], units of 2^-16) and/or out (host double) or both NULL (the

@@ -53,7 +53,8 @@ static bool q16_exact(double v) {
 
 struct NetBuf {
     size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
-        cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh, total;
+        cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh,
+        big_ids, total;
 };
 
 NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
@@ -86,6 +87,7 @@ NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     put(b.fixed_pos, 2 * rs * Nf);
     put(b.fxy, 16 * Nf);
     put(b.fwh, 16 * Nf);
+    put(b.big_ids, 4 * Nm);
     b.total = o;
     return b;
 }
@@ -431,6 +433,11 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     std::vector<T> h_cs(4 * (size_t)Nm), h_wh(2 * (size_t)Nm);
     int64_t total_charge = 0;
     long long halo = 0;
+    // big cells: a footprint that can span more than kBigHalo + 1 bins on an axis, i.e.
+    // (b + w'q - 2) / b > kBigHalo for bin size b (all in 2^-12 units)
+    nd.big_wq = kBigHalo * nd.bq + 2;
+    nd.big_hq = kBigHalo * nd.hq + 2;
+    std::vector<int32_t> h_big;
     {
 #pragma clang fp contract(off)
         for (int i = 0; i < Nm; ++i) {
@@ -457,10 +464,15 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             h_cs[3 * (size_t)Nm + i] = (T)(D.H - h);
             h_wh[i] = (T)w;
             h_wh[(size_t)Nm + i] = (T)h;
-            // bins a rectangle of this width can span, minus one
-            halo = std::max<long long>(halo, std::max((nd.bq + wq - 2) / nd.bq, (nd.hq + hq - 2) / nd.hq));
+            // bins a rectangle of this width can span, minus one (big cells stay out of the
+            // tile windows)
+            if (wq >= nd.big_wq || hq >= nd.big_hq)
+                h_big.push_back(i);
+            else
+                halo = std::max<long long>(halo, std::max((nd.bq + wq - 2) / nd.bq, (nd.hq + hq - 2) / nd.hq));
         }
     }
+    nd.n_big = (int32_t)h_big.size();
     nd.total_charge = total_charge > 0 ? total_charge : 1;
     nd.stretch = D.stretch;
     {
@@ -545,6 +557,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     HP_CHECK(up(B.fixed_pos, h_fp.data(), sizeof(T) * h_fp.size()));
     HP_CHECK(up(B.fxy, h_fxy.data(), 8 * h_fxy.size()));
     HP_CHECK(up(B.fwh, h_fwh.data(), 8 * h_fwh.size()));
+    HP_CHECK(up(B.big_ids, h_big.data(), 4 * h_big.size()));
     HP_CHECK(hipMemsetAsync(buf + B.rho_fixed, 0, 8 * (size_t)D.mx * D.my, st));
 
     nd.net_start = reinterpret_cast<const int32_t *>(buf + B.net_start);
@@ -566,6 +579,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.omega = reinterpret_cast<const double *>(buf + B.omega);
     nd.den1 = reinterpret_cast<const double *>(buf + B.den1);
     nd.fixed_pos = buf + B.fixed_pos;
+    nd.big_ids = reinterpret_cast<const int32_t *>(buf + B.big_ids);
     HP_CHECK(launch_fixed_map<T>(nd, reinterpret_cast<const double *>(buf + B.fxy),
                                  reinterpret_cast<const double *>(buf + B.fwh),
                                  reinterpret_cast<int64_t *>(buf + B.rho_fixed), st));
@@ -718,6 +732,7 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         const bool fused = !any_init && cell_parts(nd) <= kFusedStepParts;
         const int finish = any_init ? FIN_FULL : (fused ? -1 : FIN_STEP);
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
+        HP_CHECK(launch_big_scatter<T>(nd, sa, L, st));
         // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
         // a netlist whose policy is not deferred, counts for a new order in the first launch
         // and accumulates in it right after (regroup tail with accumulation).  A deferred
@@ -734,6 +749,7 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0,
                                     p->keep_maps != 0 || p->grad_mode == 1, st));
         if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, st));
+        HP_CHECK(launch_big_grad<T>(nd, sa, L, p->grad_mode, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
                                      NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
                                      finish, banks, st));
@@ -1237,8 +1253,10 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
     return HP_OK;
 }
 
-int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins, uint64_t seed,
-               int32_t *out_idx, int32_t *out_count) {
+// Shared by hp_perturb (pool == NULL: every movable cell) and hp_perturb_among.
+static int perturb_impl(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins,
+                        uint64_t seed, const int32_t *pool, int32_t n_pool, int32_t *out_idx,
+                        int32_t *out_count) {
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1248,15 +1266,31 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
     if (mode == 0 && !(sigma_bins >= 0 && std::isfinite(sigma_bins)))
         return fail(HP_EINVAL, "sigma must be finite and >= 0");
     const int Nm = n->nd.n_mov;
-    int64_t m = mode == 2 ? Nm : (int64_t)std::floor(fraction * Nm + 0.5);
-    if (m > Nm) m = Nm;
+    if (pool) {
+        if (mode == 2) return fail(HP_EINVAL, "a uniform restart redraws every cell: no pool");
+        if (n_pool < 0 || n_pool > Nm) return fail(HP_EINVAL, "pool size out of range");
+        std::vector<char> seen(Nm, 0);
+        for (int32_t j = 0; j < n_pool; ++j) {
+            const int32_t c = pool[j];
+            if (c < 0 || c >= Nm) return fail(HP_EINVAL, "pool cell is not a movable cell");
+            if (seen[c]) return fail(HP_EINVAL, "pool cells must be distinct");
+            seen[c] = 1;
+        }
+    }
+    const int64_t P = pool ? n_pool : Nm;
+    int64_t m = mode == 2 ? Nm : (int64_t)std::floor(fraction * P + 0.5);
+    if (m > P) m = P;
     HP_TRY(launch_requested_hpwl(ctx, n, std::vector<Slot *>{s}));  // before u changes
+    if (pool && n_pool)
+        HP_CHECK(hipMemcpyAsync(s->base + n->L.work, pool, 4 * (size_t)n_pool,
+                                hipMemcpyHostToDevice, ctx->stream));
+    const int np = pool ? n_pool : -1;
     if (ctx->precision == 32)
         HP_CHECK(launch_perturb<float>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
-                                       sigma_bins * n->nd.hb, seed, ctx->stream));
+                                       sigma_bins * n->nd.hb, seed, np, ctx->stream));
     else
         HP_CHECK(launch_perturb<double>(n->nd, s->base, n->L, mode, m, sigma_bins * n->nd.wb,
-                                        sigma_bins * n->nd.hb, seed, ctx->stream));
+                                        sigma_bins * n->nd.hb, seed, np, ctx->stream));
     s->lambda_valid = false;
     s->step_proposed = false;
     s->step_fused = false;
@@ -1266,8 +1300,23 @@ int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigm
         HP_CHECK(hipMemcpyAsync(out_idx, s->base + n->L.sel, 4 * (size_t)m, hipMemcpyDeviceToHost,
                                 ctx->stream));
     if (out_count) *out_count = (int32_t)m;
-    if (out_idx || out_count) HP_CHECK(hipStreamSynchronize(ctx->stream));
+    // (a pool was read from caller memory that is only guaranteed until return)
+    if (out_idx || out_count || (pool && n_pool)) HP_CHECK(hipStreamSynchronize(ctx->stream));
     return HP_OK;
+}
+
+int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins, uint64_t seed,
+               int32_t *out_idx, int32_t *out_count) {
+    return perturb_impl(ctx, slot, mode, fraction, sigma_bins, seed, nullptr, 0, out_idx, out_count);
+}
+
+int hp_perturb_among(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins,
+                     uint64_t seed, const int32_t *cells, int32_t n_pool, int32_t *out_idx,
+                     int32_t *out_count) {
+    if (!cells && n_pool) return fail(HP_EINVAL, "cells is NULL");
+    static const int32_t none = 0;
+    return perturb_impl(ctx, slot, mode, fraction, sigma_bins, seed, cells ? cells : &none, n_pool,
+                        out_idx, out_count);
 }
 
 int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbent, int32_t *out_best) {

@@ -87,7 +87,9 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
     for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
         const int i = sorted[s];
         const vec2<T> p = pos[i];
-        const RectQ q = cell_rect_b<T>(nd, p.x, p.y, nd.cq[i]);
+        const int4 cc = nd.cq[i];
+        if (is_big(nd, cc)) continue;  // scattered by a block of its own
+        const RectQ q = cell_rect_b<T>(nd, p.x, p.y, cc);
         if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
         const long long rq = nd.rq[i];
         const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;

@@ -13,6 +13,9 @@ constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
 constexpr int kChunk = 2048;     // cells per accumulation block of the binned scatter
 constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
 constexpr int kNetsPerLane = 2;  // nets each lane group sweeps (their loads issued together)
+constexpr int kBigHalo = 8;      // movable cells whose charge can span more than kBigHalo + 1
+                                 // bins on an axis are "big" (the macros): scattered and
+                                 // gathered one block per cell, outside the tile grouping
 
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };
@@ -69,7 +72,15 @@ struct NetDev {
     int32_t stretch;               // small cells' charge spread over >= sqrt(2) bins per side
     int32_t offq_exact;            // every pin_off (in T) is a multiple of 2^-16: pin_offq is
                                    // pin_off * 2^16 exactly, and the sweeps form it from pin_off
+    // big cells: w'q >= big_wq or h'q >= big_hq (their footprint can span more than
+    // kBigHalo + 1 bins); the halo above covers the other cells only
+    const int32_t *big_ids;        // [n_big] ascending movable ids
+    int32_t n_big, big_wq, big_hq;
 };
+
+__host__ __device__ inline bool is_big(const NetDev &nd, int4 c) {
+    return c.x >= nd.big_wq || c.y >= nd.big_hq;
+}
 
 // Byte offsets of a slot's arrays inside its buffer (identical for all slots of a netlist).
 struct SlotLayout {
@@ -171,6 +182,14 @@ hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotL
                                bool accum, hipStream_t st);
 size_t scatter_count_lds(const NetDev &nd);
 size_t scatter_accum_lds(const NetDev &nd);
+// Big cells (one block per cell and slot): their charge added to rho, and the density part
+// of their gradient written to gd (read back by the cell gradient pass).  No-ops without any.
+template <typename T>
+hipError_t launch_big_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_big_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                           int grad_mode, hipStream_t st);
 hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             hipStream_t st);
 // Device-to-device (x, y) pair splitting / joining, rs = element bytes (4 or 8).
@@ -216,8 +235,9 @@ template <typename T>
 hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *fwh,
                             int64_t *rho_fixed, hipStream_t st);
 template <typename T>
+// n_pool >= 0: select among the n_pool distinct cells whose ids the caller put in L.work
 hipError_t launch_perturb(const NetDev &nd, char *slot, const SlotLayout &L, int mode,
-                          int64_t m, double sigma_x, double sigma_y, uint64_t seed,
+                          int64_t m, double sigma_x, double sigma_y, uint64_t seed, int n_pool,
                           hipStream_t st);
 size_t perturb_work_bytes(int n_mov);
 template <typename T>

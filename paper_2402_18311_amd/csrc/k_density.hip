@@ -98,37 +98,138 @@ __device__ __forceinline__ double overlap_d(double lo, double hi, double a, doub
 // its stretched size and charge scale in FP64 — so the gradient is that of the continuous
 // map's energy, with psi from the integer map.  Bins in row-major order over the rectangle and
 // the bins touching it.
+struct ExactRect {
+    double L, B, ws, hs, sc, l, r, b, t;
+    int j0, j1, k0, k1;  // the bins touching the rectangle
+};
+template <typename T>
+__device__ __forceinline__ ExactRect exact_rect(const NetDev &nd, int i, double x, double y) {
+    const T *wh = reinterpret_cast<const T *>(nd.cell_wh);
+    const double w = (double)wh[i], h = (double)wh[nd.n_mov + i];
+    ExactRect e;
+    e.ws = w;
+    e.hs = h;
+    e.sc = 1.0;
+    if (nd.stretch) {
+        e.ws = fmax(w, M_SQRT2 * nd.wb);
+        e.hs = fmax(h, M_SQRT2 * nd.hb);
+        e.sc = (w * h) / (e.ws * e.hs);
+    }
+    e.L = x + (w - e.ws) * 0.5;
+    e.B = y + (h - e.hs) * 0.5;
+    e.l = fmin(fmax(e.L, 0.0), nd.W);
+    e.r = fmin(fmax(e.L + e.ws, 0.0), nd.W);
+    e.b = fmin(fmax(e.B, 0.0), nd.H);
+    e.t = fmin(fmax(e.B + e.hs, 0.0), nd.H);
+    e.j0 = max(0, (int)floor(e.l / nd.wb) - 1);
+    e.j1 = min(nd.mx - 1, (int)floor(e.r / nd.wb) + 1);
+    e.k0 = max(0, (int)floor(e.b / nd.hb) - 1);
+    e.k1 = min(nd.my - 1, (int)floor(e.t / nd.hb) + 1);
+    return e;
+}
+// bin (j, k)'s terms psi_b dq/dx and psi_b dq/dy
+template <typename T>
+__device__ __forceinline__ void exact_term(const NetDev &nd, const ExactRect &e, const T *psi,
+                                           int j, int k, double &sx, double &sy) {
+    const double oy = overlap_d(e.b, e.t, k * nd.hb, (k + 1) * nd.hb);
+    const double doy = d_overlap(e.B, e.B + e.hs, k * nd.hb, (k + 1) * nd.hb, nd.H);
+    const double ox = overlap_d(e.l, e.r, j * nd.wb, (j + 1) * nd.wb);
+    const double dox = d_overlap(e.L, e.L + e.ws, j * nd.wb, (j + 1) * nd.wb, nd.W);
+    const double ps = (double)psi[(size_t)k * nd.mx + j];
+    sx += ps * e.sc * dox * oy;
+    sy += ps * e.sc * ox * doy;
+}
 template <typename T>
 __device__ void exact_adjoint(const NetDev &nd, const T *psi, int i, double x, double y, T &gdx,
                               T &gdy) {
-    const int n = nd.n_mov;
-    const T *wh = reinterpret_cast<const T *>(nd.cell_wh);
-    const double w = (double)wh[i], h = (double)wh[n + i];
-    double ws = w, hs = h, sc = 1.0;
-    if (nd.stretch) {
-        ws = fmax(w, M_SQRT2 * nd.wb);
-        hs = fmax(h, M_SQRT2 * nd.hb);
-        sc = (w * h) / (ws * hs);
-    }
-    const double L = x + (w - ws) * 0.5, B = y + (h - hs) * 0.5;
-    const double l = fmin(fmax(L, 0.0), nd.W), r = fmin(fmax(L + ws, 0.0), nd.W);
-    const double b = fmin(fmax(B, 0.0), nd.H), t = fmin(fmax(B + hs, 0.0), nd.H);
-    const int j0 = max(0, (int)floor(l / nd.wb) - 1), j1 = min(nd.mx - 1, (int)floor(r / nd.wb) + 1);
-    const int k0 = max(0, (int)floor(b / nd.hb) - 1), k1 = min(nd.my - 1, (int)floor(t / nd.hb) + 1);
+    const ExactRect e = exact_rect<T>(nd, i, x, y);
     double sx = 0.0, sy = 0.0;
-    for (int k = k0; k <= k1; ++k) {
-        const double oy = overlap_d(b, t, k * nd.hb, (k + 1) * nd.hb);
-        const double doy = d_overlap(B, B + hs, k * nd.hb, (k + 1) * nd.hb, nd.H);
-        for (int j = j0; j <= j1; ++j) {
-            const double ox = overlap_d(l, r, j * nd.wb, (j + 1) * nd.wb);
-            const double dox = d_overlap(L, L + ws, j * nd.wb, (j + 1) * nd.wb, nd.W);
-            const double ps = (double)psi[(size_t)k * nd.mx + j];
-            sx += ps * sc * dox * oy;
-            sy += ps * sc * ox * doy;
-        }
-    }
+    for (int k = e.k0; k <= e.k1; ++k)
+        for (int j = e.j0; j <= e.j1; ++j) exact_term<T>(nd, e, psi, j, k, sx, sy);
     gdx = (T)sx;
     gdy = (T)sy;
+}
+
+// ---- big cells (the movable macros): one block per cell and slot --------------------------
+// Their footprints span up to the whole grid, so the per-thread loops of the tiled scatter and
+// of the cell gradient would serialise hundreds of bins in one lane.  Instead the bins of one
+// cell are dealt over a block: the scatter adds each bin's integer charge to rho with global
+// atomics (integer sums: order-free, so the map stays bit-exact), and the gradient pass reduces
+// the footprint's field (or exact-adjoint) terms over the block in FP64 and stores the density
+// gradient in gd, where the cell gradient pass picks it up.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void big_scatter_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+    char *base = sa.base[blockIdx.y];
+    const int i = nd.big_ids[blockIdx.x];
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+    const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
+    if (q.r <= q.l || q.t <= q.b) return;  // clipped away: no charge
+    const long long rq = nd.rq[i];
+    const int j0 = q.l / nd.bq, nj = (q.r - 1) / nd.bq - j0 + 1;
+    const int k0 = q.b / nd.hq, nk = (q.t - 1) / nd.hq - k0 + 1;
+    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
+    for (int b = threadIdx.x; b < nj * nk; b += kBlock) {
+        const int k = k0 + b / nj, j = j0 + b % nj;
+        const long long c = rq * overlap(q.l, q.r, j, nd.bq) * overlap(q.b, q.t, k, nd.hq);
+        atomicAdd(&rho[(size_t)k * nd.mx + j], (unsigned long long)c);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                          int grad_mode) {
+    char *base = sa.base[blockIdx.y];
+    const int i = nd.big_ids[blockIdx.x];
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+    double s[2] = {0.0, 0.0};
+    if (grad_mode == 1) {
+        const ExactRect e = exact_rect<T>(nd, i, (double)p.x, (double)p.y);
+        const T *psi = reinterpret_cast<const T *>(base + L.psi);
+        const int nj = e.j1 - e.j0 + 1, nk = e.k1 - e.k0 + 1;
+        for (int b = threadIdx.x; b < nj * nk; b += kBlock)
+            exact_term<T>(nd, e, psi, e.j0 + b % nj, e.k0 + b / nj, s[0], s[1]);
+    } else {
+        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
+        if (q.r > q.l && q.t > q.b) {
+            const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
+            const double rqd = (double)nd.rq[i] * 0x1p-40;
+            const int j0 = q.l / nd.bq, nj = (q.r - 1) / nd.bq - j0 + 1;
+            const int k0 = q.b / nd.hq, nk = (q.t - 1) / nd.hq - k0 + 1;
+            for (int b = threadIdx.x; b < nj * nk; b += kBlock) {
+                const int k = k0 + b / nj, j = j0 + b % nj;
+                const double qq = rqd * (double)overlap(q.l, q.r, j, nd.bq) *
+                                  (double)overlap(q.b, q.t, k, nd.hq);
+                const vec2<T> ev = exy[(size_t)k * nd.mx + j];
+                s[0] -= qq * (double)ev.x;
+                s[1] -= qq * (double)ev.y;
+            }
+        }
+    }
+    __shared__ double red[4 * 2];
+    block_sum_n<2>(s, red);
+    if (threadIdx.x == 0) {
+        T *gd = reinterpret_cast<T *>(base + L.gd);
+        gd[i] = (T)s[0];
+        gd[nd.n_mov + i] = (T)s[1];
+    }
+}
+
+template <typename T>
+hipError_t launch_big_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                              hipStream_t st) {
+    if (nd.n_big == 0) return hipSuccess;
+    HP_LAUNCH("big_scatter_kernel", big_scatter_kernel<T>, dim3(nd.n_big, sa.n), dim3(kBlock), 0,
+              st, nd, sa, L);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_big_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
+                           int grad_mode, hipStream_t st) {
+    if (nd.n_big == 0) return hipSuccess;
+    HP_LAUNCH("big_grad_kernel", big_grad_kernel<T>, dim3(nd.n_big, sa.n), dim3(kBlock), 0, st,
+              nd, sa, L, grad_mode);
+    return hipGetLastError();
 }
 
 // Four consecutive (xi_x, xi_y) pairs of a field row: two 16-byte loads in FP32 (the row
@@ -183,8 +284,10 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         // charge weight of a bin: rq ox oy 2^-40, formed in the compute type (exact in FP64;
         // in FP32 a relative rounding of ~1e-7, far inside the gradient tolerance)
         const T rqt = (T)nd.rq[i] * (T)0x1p-40;
-        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
-        const bool has = q.r > q.l && q.t > q.b;
+        const int4 cc = nd.cq[i];
+        const bool big = is_big(nd, cc);  // density part already reduced by its own block
+        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, cc);
+        const bool has = !big && q.r > q.l && q.t > q.b;
         const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
         const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
         constexpr int KR = 3, JC = 4;
@@ -215,7 +318,11 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             gwx += g.x;
             gwy += g.y;
         }
-        if (grad_mode == 1) {  // exact adjoint of the continuous charge rectangle
+        if (big) {
+            const T *gd = reinterpret_cast<const T *>(base + L.gd);
+            gdx = gd[i];
+            gdy = gd[nd.n_mov + i];
+        } else if (grad_mode == 1) {  // exact adjoint of the continuous charge rectangle
             exact_adjoint<T>(nd, reinterpret_cast<const T *>(base + L.psi), i, (double)p.x,
                              (double)p.y, gdx, gdy);
         } else if (small) {  // the footprint's bins of the window, row-major
@@ -362,6 +469,10 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 }
 
 #define HP_INST(T)                                                                          \
+    template hipError_t launch_big_scatter<T>(const NetDev &, const SlotArgs &,             \
+                                              const SlotLayout &, hipStream_t);             \
+    template hipError_t launch_big_grad<T>(const NetDev &, const SlotArgs &,                \
+                                           const SlotLayout &, int, hipStream_t);           \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
                                             const SlotLayout &, double, bool, int, int, int, \
                                             int, int, uint32_t, hipStream_t);                              \

@@ -1,11 +1,13 @@
 // Perturbation of Alg. 1 ("Perturb", Sec. 4.2) on one slot's major solution u.
 //
 // Keys: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) as a counter-based generator, draw i of
-// stream `seed` = mix64(seed + (i + 1) * 0x9e3779b97f4a7c15).  The moved subset is the m cells
-// with the smallest (key, index): an exact radix select finds the m-th smallest key T (eight
-// 8-bit digit passes, each a block-privatised histogram), then a stable compaction in index
-// order takes every key < T and the lowest-index keys == T.  GAUSS displaces them by a
-// Box-Muller Gaussian from the two halves of mix64(key); SHUFFLE permutes their centres with a
+// stream `seed` = mix64(seed + (i + 1) * 0x9e3779b97f4a7c15), the key of cell i (shifted right
+// by one bit when the selection is restricted to a pool of cells, such as the macros).  The
+// moved subset is the m cells with the smallest (key, index): an exact radix select finds the
+// m-th smallest key T (eight 8-bit digit passes, each a block-privatised histogram), then a
+// stable compaction in index order takes every key < T and the lowest-index keys == T.  GAUSS
+// displaces them by a Box-Muller Gaussian from the two halves of mix64(draw); SHUFFLE
+// permutes their centres with a
 // keyed 4-round Feistel permutation of [0, m) with cycle walking (Black & Rogaway, CT-RSA
 // 2002); UNIFORM redraws every cell.  The optimiser restarts at the result.
 #include "hp_device.h"
@@ -42,10 +44,11 @@ __device__ uint64_t shuffle_perm(uint64_t j, uint64_t m, uint64_t seed) {
     return y;
 }
 
-// restart the optimiser at u; keys for the selection
+// restart the optimiser at u; keys for the selection (with a pool, every key is all ones
+// here and the pool's keys are written next)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void perturb_init_kernel(NetDev nd, char *base, SlotLayout L,
-                                                              uint64_t seed, int64_t m) {
+                                                              uint64_t seed, int64_t m, int pooled) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     Scalars *sc = scalars(base, L);
     if (i == 0) {
@@ -66,7 +69,17 @@ __global__ __launch_bounds__(kBlock) void perturb_init_kernel(NetDev nd, char *b
     const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.u)[i];
     reinterpret_cast<vec2<T> *>(base + L.v)[i] = p;
     reinterpret_cast<vec2<T> *>(base + L.vprev)[i] = p;
-    reinterpret_cast<uint64_t *>(base + L.keys)[i] = splitmix(seed, (uint64_t)i);
+    reinterpret_cast<uint64_t *>(base + L.keys)[i] = pooled ? ~0ULL : splitmix(seed, (uint64_t)i);
+}
+
+// Keys of a pool of cells (its ids in `work`): the draw shifted right by one bit, so that it
+// stays below the all-ones key of every cell outside the pool.
+__global__ __launch_bounds__(kBlock) void pool_keys_kernel(char *base, SlotLayout L, int n_pool,
+                                                           uint64_t seed) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n_pool) return;
+    const int c = reinterpret_cast<const int32_t *>(base + L.work)[j];
+    reinterpret_cast<uint64_t *>(base + L.keys)[c] = splitmix(seed, (uint64_t)c) >> 1;
 }
 
 __global__ __launch_bounds__(kBlock) void select_hist_kernel(NetDev nd, char *base, SlotLayout L,
@@ -255,10 +268,16 @@ size_t perturb_work_bytes(int n_mov) {
 
 template <typename T>
 hipError_t launch_perturb(const NetDev &nd, char *base, const SlotLayout &L, int mode, int64_t m,
-                          double sigma_x, double sigma_y, uint64_t seed, hipStream_t st) {
+                          double sigma_x, double sigma_y, uint64_t seed, int n_pool,
+                          hipStream_t st) {
     const int nblk = (nd.n_mov + kBlock - 1) / kBlock;
     const int gb = nblk > 0 ? nblk : 1;
-    HP_LAUNCH("perturb_init_kernel", perturb_init_kernel<T>, dim3(gb), dim3(kBlock), 0, st, nd, base, L, seed, m);
+    const int pooled = n_pool >= 0;
+    HP_LAUNCH("perturb_init_kernel", perturb_init_kernel<T>, dim3(gb), dim3(kBlock), 0, st, nd, base, L, seed, m,
+              pooled);
+    if (pooled && n_pool > 0)
+        HP_LAUNCH("pool_keys_kernel", pool_keys_kernel, dim3((n_pool + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                  st, base, L, n_pool, seed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || m == 0) return e;
     const int mb = (int)((m + kBlock - 1) / kBlock);
@@ -288,8 +307,8 @@ hipError_t launch_perturb(const NetDev &nd, char *base, const SlotLayout &L, int
 }
 
 template hipError_t launch_perturb<float>(const NetDev &, char *, const SlotLayout &, int, int64_t,
-                                          double, double, uint64_t, hipStream_t);
+                                          double, double, uint64_t, int, hipStream_t);
 template hipError_t launch_perturb<double>(const NetDev &, char *, const SlotLayout &, int, int64_t,
-                                           double, double, uint64_t, hipStream_t);
+                                           double, double, uint64_t, int, hipStream_t);
 
 }  // namespace hp

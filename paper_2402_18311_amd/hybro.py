@@ -77,6 +77,8 @@ _SIGS = {
     "hp_nesterov_step": [_P, _P, C.c_int32],
     "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
     "hp_perturb": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P, _P],
+    "hp_perturb_among": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P,
+                         C.c_int32, _P, _P],
     "hp_hpwl": [_P, _P, C.c_int32, _P, _P],
     "hp_select_best": [_P, _P, C.c_int32, C.c_int32, _P],
     "hp_get_map": [_P, C.c_int32, C.c_int, _P],
@@ -250,6 +252,18 @@ def hp_perturb(ctx, slot, mode, fraction, sigma_bins, seed, n_movable, want_idx=
     return buf[: cnt.value].copy() if want_idx else cnt.value
 
 
+def hp_perturb_among(ctx, slot, mode, fraction, sigma_bins, seed, cells, n_movable,
+                     want_idx=True):
+    """hp_perturb over the pool `cells` (distinct movable ids, e.g. the macros)."""
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    cnt = C.c_int32()
+    buf = np.zeros(max(1, n_movable), dtype=np.int32) if want_idx else None
+    _chk(lib().hp_perturb_among(ctx, slot, int(mode), float(fraction), float(sigma_bins),
+                                C.c_uint64(int(seed) & (2**64 - 1)), _ptr(cells), len(cells),
+                                _ptr(buf), C.byref(cnt)))
+    return buf[: cnt.value].copy() if want_idx else cnt.value
+
+
 def hp_hpwl(ctx, slots, want_host=True):
     a, p, n = _slots(slots)
     q = np.zeros(n, dtype=np.int64) if want_host else None
@@ -380,7 +394,11 @@ class Placer:
     def hpwl(self, slots, want_host=True):
         return hp_hpwl(self.ctx, list(np.atleast_1d(slots)), want_host)
 
-    def perturb(self, s, mode, fraction, sigma_bins, seed, want_idx=True):
+    def perturb(self, s, mode, fraction, sigma_bins, seed, want_idx=True, cells=None):
+        """Perturb slot s; with `cells`, only among those movable cells (e.g. the macros)."""
+        if cells is not None:
+            return hp_perturb_among(self.ctx, s, mode, fraction, sigma_bins, seed, cells,
+                                    self.nl.n_movable, want_idx)
         return hp_perturb(self.ctx, s, mode, fraction, sigma_bins, seed, self.nl.n_movable,
                           want_idx)
 
