@@ -87,8 +87,8 @@ size_t hp_slot_bytes(const hp_ctx *ctx, const hp_shape *shape, const hp_die *die
  * pin_cell [n_pins] in [0, n_cells); pin_ox/pin_oy [n_pins]; net_weight [n_nets] or NULL
  * (all 1).  Nets with fewer than two pins add nothing to Eq. 1 or Eq. 3.  Movable cells may
  * be of any size up to the die, macros included: a movable cell whose charge can span more
- * than 9 bins on an axis is scattered and gathered by a block of its own (mixed-size
- * placement; the results are those of any other cell).  Validates everything above
+ * than 9 bins on an axis or covers 8 bin areas or more is scattered and gathered by a block of
+ * its own (mixed-size placement; the results are those of any other cell).  Validates everything above
  * (HP_EINVAL) and dev_bytes (HP_ENOMEM).  Synchronises the stream. */
 int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die,
                         const double *cell_w, const double *cell_h,

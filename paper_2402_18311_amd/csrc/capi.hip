@@ -434,9 +434,11 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     int64_t total_charge = 0;
     long long halo = 0;
     // big cells: a footprint that can span more than kBigHalo + 1 bins on an axis, i.e.
-    // (b + w'q - 2) / b > kBigHalo for bin size b (all in 2^-12 units)
+    // (b + w'q - 2) / b > kBigHalo for bin size b (all in 2^-12 units), or an area of
+    // kBigArea bins or more
     nd.big_wq = kBigHalo * nd.bq + 2;
     nd.big_hq = kBigHalo * nd.hq + 2;
+    nd.big_aq = (int64_t)kBigArea * nd.bq * nd.hq;
     std::vector<int32_t> h_big;
     {
 #pragma clang fp contract(off)
@@ -466,7 +468,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             h_wh[(size_t)Nm + i] = (T)h;
             // bins a rectangle of this width can span, minus one (big cells stay out of the
             // tile windows)
-            if (wq >= nd.big_wq || hq >= nd.big_hq)
+            if (is_big(nd, make_int4((int)wq, (int)hq, 0, 0)))
                 h_big.push_back(i);
             else
                 halo = std::max<long long>(halo, std::max((nd.bq + wq - 2) / nd.bq, (nd.hq + hq - 2) / nd.hq));
@@ -732,7 +734,6 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         const bool fused = !any_init && cell_parts(nd) <= kFusedStepParts;
         const int finish = any_init ? FIN_FULL : (fused ? -1 : FIN_STEP);
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
-        HP_CHECK(launch_big_scatter<T>(nd, sa, L, st));
         // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
         // a netlist whose policy is not deferred, counts for a new order in the first launch
         // and accumulates in it right after (regroup tail with accumulation).  A deferred

@@ -112,4 +112,25 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
     for (int b = threadIdx.x; b < nw; b += kBlock) out[b] = win[b];
 }
 
+// Charge of big cell big_ids[k] (a macro) added to rho by the whole block, one bin per thread
+// and round, with global atomics (an integer sum: order-free and bit-exact).
+template <typename T>
+__device__ __forceinline__ void big_scatter_body(const NetDev &nd, char *base, const SlotLayout &L,
+                                                 int k) {
+    if (k >= nd.n_big) return;  // block-uniform (the range is rounded up)
+    const int i = nd.big_ids[k];
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+    const RectQ q = cell_rect_b<T>(nd, p.x, p.y, nd.cq[i]);
+    if (q.r <= q.l || q.t <= q.b) return;  // clipped away: no charge
+    const long long rq = nd.rq[i];
+    const int j0 = q.l / nd.bq, nj = (q.r - 1) / nd.bq - j0 + 1;
+    const int k0 = q.b / nd.hq, nk = (q.t - 1) / nd.hq - k0 + 1;
+    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
+    for (int b = threadIdx.x; b < nj * nk; b += kBlock) {
+        const int kk = k0 + b / nj, j = j0 + b % nj;
+        const long long c = rq * overlap_b(q.l, q.r, j, nd.bq) * overlap_b(q.b, q.t, kk, nd.hq);
+        atomicAdd(&rho[(size_t)kk * nd.mx + j], (unsigned long long)c);
+    }
+}
+
 }  // namespace hp

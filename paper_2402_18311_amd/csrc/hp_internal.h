@@ -14,8 +14,9 @@ constexpr int kChunk = 2048;     // cells per accumulation block of the binned s
 constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
 constexpr int kNetsPerLane = 2;  // nets each lane group sweeps (their loads issued together)
 constexpr int kBigHalo = 8;      // movable cells whose charge can span more than kBigHalo + 1
-                                 // bins on an axis are "big" (the macros): scattered and
-                                 // gathered one block per cell, outside the tile grouping
+constexpr int kBigArea = 8;      // bins on an axis, or covers kBigArea bin areas or more, are
+                                 // "big" (the macros): scattered and gathered one block per
+                                 // cell, outside the tile grouping
 
 template <typename T> struct V2;
 template <> struct V2<float> { using type = float2; };
@@ -73,13 +74,14 @@ struct NetDev {
     int32_t offq_exact;            // every pin_off (in T) is a multiple of 2^-16: pin_offq is
                                    // pin_off * 2^16 exactly, and the sweeps form it from pin_off
     // big cells: w'q >= big_wq or h'q >= big_hq (their footprint can span more than
-    // kBigHalo + 1 bins); the halo above covers the other cells only
+    // kBigHalo + 1 bins) or w'q h'q >= big_aq; the halo above covers the other cells only
     const int32_t *big_ids;        // [n_big] ascending movable ids
     int32_t n_big, big_wq, big_hq;
+    int64_t big_aq;
 };
 
 __host__ __device__ inline bool is_big(const NetDev &nd, int4 c) {
-    return c.x >= nd.big_wq || c.y >= nd.big_hq;
+    return c.x >= nd.big_wq || c.y >= nd.big_hq || (int64_t)c.x * c.y >= nd.big_aq;
 }
 
 // Byte offsets of a slot's arrays inside its buffer (identical for all slots of a netlist).
@@ -182,11 +184,9 @@ hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotL
                                bool accum, hipStream_t st);
 size_t scatter_count_lds(const NetDev &nd);
 size_t scatter_accum_lds(const NetDev &nd);
-// Big cells (one block per cell and slot): their charge added to rho, and the density part
-// of their gradient written to gd (read back by the cell gradient pass).  No-ops without any.
-template <typename T>
-hipError_t launch_big_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                              hipStream_t st);
+// Big cells (one block per cell and slot; their charge is scattered in the first launch):
+// the wirelength and density parts of their gradient written to g and gd (read back by the
+// cell gradient pass).  No-op without any.
 template <typename T>
 hipError_t launch_big_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            int grad_mode, hipStream_t st);

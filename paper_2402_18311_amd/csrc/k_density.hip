@@ -151,43 +151,32 @@ __device__ void exact_adjoint(const NetDev &nd, const T *psi, int i, double x, d
 }
 
 // ---- big cells (the movable macros): one block per cell and slot --------------------------
-// Their footprints span up to the whole grid, so the per-thread loops of the tiled scatter and
-// of the cell gradient would serialise hundreds of bins in one lane.  Instead the bins of one
-// cell are dealt over a block: the scatter adds each bin's integer charge to rho with global
-// atomics (integer sums: order-free, so the map stays bit-exact), and the gradient pass reduces
-// the footprint's field (or exact-adjoint) terms over the block in FP64 and stores the density
-// gradient in gd, where the cell gradient pass picks it up.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void big_scatter_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
-    char *base = sa.base[blockIdx.y];
-    const int i = nd.big_ids[blockIdx.x];
-    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-    const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
-    if (q.r <= q.l || q.t <= q.b) return;  // clipped away: no charge
-    const long long rq = nd.rq[i];
-    const int j0 = q.l / nd.bq, nj = (q.r - 1) / nd.bq - j0 + 1;
-    const int k0 = q.b / nd.hq, nk = (q.t - 1) / nd.hq - k0 + 1;
-    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
-    for (int b = threadIdx.x; b < nj * nk; b += kBlock) {
-        const int k = k0 + b / nj, j = j0 + b % nj;
-        const long long c = rq * overlap(q.l, q.r, j, nd.bq) * overlap(q.b, q.t, k, nd.hq);
-        atomicAdd(&rho[(size_t)k * nd.mx + j], (unsigned long long)c);
-    }
-}
-
+// Their footprints span up to the whole grid and they carry many pins, so the per-thread loops
+// of the tiled scatter and of the cell gradient would serialise hundreds of loads in one lane.
+// Instead the bins and pins of one cell are dealt over a block: the scatter (a block range of
+// the first launch of an evaluation) adds each bin's integer charge to rho with global atomics,
+// and the gradient pass reduces the cell's pin gradients and its footprint's field (or
+// exact-adjoint) terms over the block in FP64 and stores the wirelength part in g and the
+// density part in gd, where the cell gradient pass picks them up.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                           int grad_mode) {
     char *base = sa.base[blockIdx.y];
     const int i = nd.big_ids[blockIdx.x];
     const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-    double s[2] = {0.0, 0.0};
+    double s[4] = {0.0, 0.0, 0.0, 0.0};  // wirelength x, y; density x, y
+    const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
+    for (int j = nd.cell_pin_start[i] + threadIdx.x; j < nd.cell_pin_start[i + 1]; j += kBlock) {
+        const vec2<T> gp = pg[nd.cell_pins[j]];
+        s[0] += (double)gp.x;
+        s[1] += (double)gp.y;
+    }
     if (grad_mode == 1) {
         const ExactRect e = exact_rect<T>(nd, i, (double)p.x, (double)p.y);
         const T *psi = reinterpret_cast<const T *>(base + L.psi);
         const int nj = e.j1 - e.j0 + 1, nk = e.k1 - e.k0 + 1;
         for (int b = threadIdx.x; b < nj * nk; b += kBlock)
-            exact_term<T>(nd, e, psi, e.j0 + b % nj, e.k0 + b / nj, s[0], s[1]);
+            exact_term<T>(nd, e, psi, e.j0 + b % nj, e.k0 + b / nj, s[2], s[3]);
     } else {
         const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
         if (q.r > q.l && q.t > q.b) {
@@ -200,27 +189,21 @@ __global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nd, SlotArgs sa
                 const double qq = rqd * (double)overlap(q.l, q.r, j, nd.bq) *
                                   (double)overlap(q.b, q.t, k, nd.hq);
                 const vec2<T> ev = exy[(size_t)k * nd.mx + j];
-                s[0] -= qq * (double)ev.x;
-                s[1] -= qq * (double)ev.y;
+                s[2] -= qq * (double)ev.x;
+                s[3] -= qq * (double)ev.y;
             }
         }
     }
-    __shared__ double red[4 * 2];
-    block_sum_n<2>(s, red);
+    __shared__ double red[4 * 4];
+    block_sum_n<4>(s, red);
     if (threadIdx.x == 0) {
+        T *g = reinterpret_cast<T *>(base + L.g);
         T *gd = reinterpret_cast<T *>(base + L.gd);
-        gd[i] = (T)s[0];
-        gd[nd.n_mov + i] = (T)s[1];
+        g[i] = (T)s[0];
+        g[nd.n_mov + i] = (T)s[1];
+        gd[i] = (T)s[2];
+        gd[nd.n_mov + i] = (T)s[3];
     }
-}
-
-template <typename T>
-hipError_t launch_big_scatter(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                              hipStream_t st) {
-    if (nd.n_big == 0) return hipSuccess;
-    HP_LAUNCH("big_scatter_kernel", big_scatter_kernel<T>, dim3(nd.n_big, sa.n), dim3(kBlock), 0,
-              st, nd, sa, L);
-    return hipGetLastError();
 }
 
 template <typename T>
@@ -278,14 +261,14 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         // row-major bin order.
         const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
         const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
+        const int4 cc = nd.cq[i];
+        const bool big = is_big(nd, cc);  // both parts already reduced by its own block
         const int e = nd.cell_pin_start[i + 1];
-        int j = nd.cell_pin_start[i];
+        int j = big ? e : nd.cell_pin_start[i];
         const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
         // charge weight of a bin: rq ox oy 2^-40, formed in the compute type (exact in FP64;
         // in FP32 a relative rounding of ~1e-7, far inside the gradient tolerance)
         const T rqt = (T)nd.rq[i] * (T)0x1p-40;
-        const int4 cc = nd.cq[i];
-        const bool big = is_big(nd, cc);  // density part already reduced by its own block
         const RectQ q = cell_rect_i<T>(nd, p.x, p.y, cc);
         const bool has = !big && q.r > q.l && q.t > q.b;
         const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
@@ -319,7 +302,10 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             gwy += g.y;
         }
         if (big) {
+            const T *gw = reinterpret_cast<const T *>(base + L.g);
             const T *gd = reinterpret_cast<const T *>(base + L.gd);
+            gwx = gw[i];
+            gwy = gw[nd.n_mov + i];
             gdx = gd[i];
             gdy = gd[nd.n_mov + i];
         } else if (grad_mode == 1) {  // exact adjoint of the continuous charge rectangle
@@ -469,8 +455,6 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 }
 
 #define HP_INST(T)                                                                          \
-    template hipError_t launch_big_scatter<T>(const NetDev &, const SlotArgs &,             \
-                                              const SlotLayout &, hipStream_t);             \
     template hipError_t launch_big_grad<T>(const NetDev &, const SlotArgs &,                \
                                            const SlotLayout &, int, hipStream_t);           \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \

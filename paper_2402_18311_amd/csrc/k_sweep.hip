@@ -531,25 +531,30 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
 //                             (nacc = 0 when the slot has no grouping yet);
 //   [nacc, nacc + ncnt)       the counting pass of a new grouping from v (ncnt = 0 between
 //                             rebuilds);
-//   [nacc + ncnt, ... + nw)   the WA sweep of v (nw = the sweep's block count; its
+//   [.., .. + nbig)           the charge of the big cells (macros), one block per cell (nbig =
+//                             0 without any);
+//   [.., .. + nw)             the WA sweep of v (nw = the sweep's block count; its
 //                             block-per-net bucket leads); for the slots in hmask (a deferred
 //                             hp_hpwl) the same blocks also sweep the HPWL of u, sharing the pin
 //                             loads.
-// nacc and ncnt are multiples of 8, so the sweep keeps the XCD striping of its own blocks.
+// nacc, ncnt and nbig are multiples of 8, so the sweep keeps the XCD striping of its own blocks.
 template <typename T>
 __global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
                                                             SlotLayout L, T invg, int nacc,
-                                                            int ncnt, uint32_t hmask) {
+                                                            int ncnt, int nbig, uint32_t hmask) {
     char *base = sa.base[blockIdx.y];
     const int bx = blockIdx.x;
+    const int s0 = nacc + ncnt + nbig;
     if (bx < nacc) {
         accum_body<T>(nd, base, L, bx);
     } else if (bx < nacc + ncnt) {
         count_body<T>(nd, base, L, bx - nacc);
+    } else if (bx < s0) {
+        big_scatter_body<T>(nd, base, L, bx - nacc - ncnt);
     } else if ((hmask >> blockIdx.y) & 1u) {
-        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - nacc - ncnt);
+        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - s0);
     } else {
-        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - nacc - ncnt);
+        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - s0);
     }
 }
 
@@ -561,13 +566,14 @@ hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs
                              bool accum, bool count, hipStream_t st) {
     const int nacc = accum ? (nd.max_chunks + kXcds - 1) / kXcds * kXcds : 0;
     const int ncnt = count ? (nd.sort_blocks + kXcds - 1) / kXcds * kXcds : 0;
-    // dynamic LDS: the largest need of the three jobs (a block does one of them)
+    const int nbig = (nd.n_big + kXcds - 1) / kXcds * kXcds;
+    // dynamic LDS: the largest need of the jobs (a block does one of them; big cells need none)
     const size_t big = (bk.n > 0 && bk.G[0] == 0) ? sizeof(vec2<T>) * kNetRegs * kBlock : 0;
     const size_t lds = std::max({accum ? scatter_accum_lds(nd) : 0,
                                  count ? scatter_count_lds(nd) : 0, big});
-    dim3 grid(nacc + ncnt + bk.total_blocks, sa.n);
+    dim3 grid(nacc + ncnt + nbig + bk.total_blocks, sa.n);
     HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
-              L, (T)inv_gamma, nacc, ncnt, hpwl_mask);
+              L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask);
     return hipGetLastError();
 }
 

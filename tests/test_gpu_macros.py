@@ -1,7 +1,8 @@
 """Movable macros on the HIP path (mixed-size placement, the setting of Shuffle in Sec. 4.2).
 
-Macros whose charge spans more than nine bins on an axis take their own scatter and gather
-(one block per cell); smaller ones stay in the tiled scatter.  Against the FP64 oracle:
+Macros whose charge spans more than nine bins on an axis or covers eight bin areas take their
+own scatter and gather (one block per cell: its bins and its pins); the others stay in the
+tiled scatter.  Against the FP64 oracle:
 charge maps, overflow numerators and HPWL bit for bit; wirelength and energy to 1e-5
 relative and gradients to 1e-4 relative L2 in FP32 (1e-10 in FP64); perturbation among the
 macros with the oracle's indices bit for bit.
@@ -47,11 +48,11 @@ _CASES = {
     # 6 movable macros of up to 25 x 18 bins among 1000 standard cells, 64^2 bins
     "tiny_mm": lambda: netgen.make_small(1000, 1100, 64, seed=1, n_fixed=6, movable_macros=True,
                                          macro_frac=0.3),
-    # 40 movable macros (25 of them past nine bins), 20 k cells, 128^2 bins
+    # 40 movable macros, 20 k cells, 128^2 bins
     "small_mm": lambda: netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40,
                                           movable_macros=True),
     "huge": _huge,
-    # the 210 k-cell netlist with its 500 macros movable (352 past nine bins)
+    # the 210 k-cell netlist with its 500 macros movable
     "mid_mm": lambda: netgen.make_netlist("mid_mm", 0),
 }
 _cache = {}
