@@ -241,6 +241,48 @@ def large_run(hy, netgen, seed, warm, steps):
     return out
 
 
+def macros_run(hy, netgen, seed, warm, steps):
+    """The mid netlist with its 500 macros movable (mixed-size placement; the macros take the
+    block-per-cell charge path): iterations/s over `steps` plain-method iterations after
+    `warm`, then one Hybro-Shuffle round (half of the macros exchange places, Sec. 4.2, and
+    `steps` iterations follow) timed on its own."""
+    import torch
+    nl = netgen.make_netlist("mid_mm", seed)
+    pl = hy.Placer(nl, precision=32)
+    g = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    pl.set_schedule(s, 1e-4, 4.0, warm + steps)
+    pl.iterate(s, g, warm, hpwl=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.iterate(s, g, steps, hpwl=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h0 = pl.hpwl(s)[0]
+    w = pl.new_slot()
+    ix = torch.empty(nl.n_movable, dtype=torch.float32, device="cuda")
+    iy = torch.empty_like(ix)
+    hy.hp_get_positions(pl.ctx, s, ix, iy, True)
+    pl.set_positions(w, ix, iy)
+    pl.set_schedule(w, 1e-4, 4.0, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    moved = pl.perturb(w, hy.HP_PERTURB_SHUFFLE, 0.5, 0.0, 0x5EED, want_idx=False,
+                       cells=nl.macros)
+    pl.iterate(w, g, steps, hpwl=True)
+    h1 = pl.hpwl(w)[0]  # synchronises
+    dr = time.perf_counter() - t1
+    out = {"workload": f"mid_mm: {nl.n_movable} movable cells of which {len(nl.macros)} macros, "
+                       f"{nl.n_nets} nets / {nl.n_pins} pins, {nl.mx}x{nl.my} bins, FP32",
+           "iter_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
+           "steps": steps, "warmup": warm, "hpwl": h0 / 65536,
+           "shuffle_round": {"macros_moved": int(moved), "iterations": steps,
+                             "seconds": round(dr, 4), "hpwl": h1 / 65536}}
+    pl.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +296,8 @@ def main():
                     help="time without the per-launch events (no roofline)")
     ap.add_argument("--large-steps", type=int, default=500,
                     help="timed iterations on the large netlist (0 skips it)")
+    ap.add_argument("--macro-steps", type=int, default=1000,
+                    help="timed iterations on mid with movable macros (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=16,
                     help="jobs of the serving-mix trace (0 skips it)")
     ap.add_argument("--batch", type=int, default=32,
@@ -413,6 +457,9 @@ def main():
     if args.large_steps > 0:
         log(f"[bench] large netlist: 300 + {args.large_steps} iterations")
         out["large"] = large_run(hy, netgen, args.seed, 300, args.large_steps)
+    if args.macro_steps > 0:
+        log(f"[bench] movable macros: 600 + {args.macro_steps} iterations, one shuffle round")
+        out["movable_macros"] = macros_run(hy, netgen, args.seed, 600, args.macro_steps)
     if args.serve_jobs > 0:
         from paper_2402_18311_amd import serve
         log(f"[bench] serving mix: {args.serve_jobs} jobs, 10 k - 2.2 M cells, 500 iterations")

@@ -6,7 +6,7 @@ then each round perturbs the best solution (Sec. 4.2), places again and keeps th
 HPWL (Eq. 1).  The placer's schedules and stopping rule are the ePlace-style reading recorded
 in the design notes:
   * stop when the overflow (the D(s) <= eps measure of Eq. 1) is at most 0.10 and the HPWL
-    moved by at most 0.1% of itself over the last 10 iterations, or after max_iters
+    fell by at most 0.1% of itself over the last 10 iterations (or rose), or after max_iters
     iterations; overflow and HPWL are looked at every 10 iterations (a look happens before
     the first stop);
   * smoothing gamma = 4 bins x 10^((20/9) tau - 11/9) for the next 10 iterations, from the
@@ -53,18 +53,22 @@ def place_to_convergence(o, nl, x, y, max_iters):
             tau = r["overflow"]
             k += 1
         h = o.hpwl_q(st["u"][:n], st["u"][n:])
-        level = abs(h - h_prev) <= 0.001 * h_prev
+        level = h - h_prev >= -0.001 * h_prev
         ratio = _mu(h, h_prev)
         h_prev = h
     return st["u"][:n].copy(), st["u"][n:].copy(), k, h_prev, tau
 
 
-def hybro(o, nl, rounds, mode, fraction, sigma_bins, seed, max_iters):
-    """Per-round trace: iterations, HPWL_q of the round's placement, best HPWL_q so far."""
+def hybro(o, nl, rounds, mode, fraction, sigma_bins, seed, max_iters, pool=None):
+    """Per-round trace: iterations, HPWL_q of the round's placement, best HPWL_q so far.  With
+    `pool` (e.g. the movable macros) the perturbation selects among those cells only."""
     bx, by, k, best, tau = place_to_convergence(o, nl, nl.x0, nl.y0, max_iters)
     trace = [(k, best, best)]
     for r in range(rounds):
-        px, py, _ = o.perturb(bx, by, mode, fraction, sigma_bins, seed + r)
+        if pool is None:
+            px, py, _ = o.perturb(bx, by, mode, fraction, sigma_bins, seed + r)
+        else:
+            px, py, _ = o.perturb_among(bx, by, mode, fraction, sigma_bins, seed + r, pool)
         x, y, k, h, tau = place_to_convergence(o, nl, px, py, max_iters)
         if h < best:
             bx, by, best = x, y, h

@@ -4,8 +4,9 @@ re-place it and keep the one with the smallest exact HPWL (Eq. 1).
 The paper leaves the analytical placer's schedules and stopping rule to the placer it builds
 on (Sec. 3.1).  This driver uses the ePlace-style rules (a reading):
   * the placer runs until the density overflow tau (the D(s) <= eps measure of Eq. 1) is at
-    most TAU_STOP and the HPWL has levelled off (it moved by at most PLATEAU of itself over the
-    last CHECK iterations), or for at most `max_iters` iterations;
+    most TAU_STOP and the HPWL has stopped falling (it fell by at most PLATEAU of itself over
+    the last CHECK iterations, or rose: past that point the growing penalty only spreads the
+    cells further at the cost of wirelength), or for at most `max_iters` iterations;
   * every CHECK iterations the smoothing of Eq. 3 follows the overflow,
         gamma(tau) = GAMMA_BINS * bin * 10^((20/9) tau - 11/9),
     and the penalty weight of Eq. 2 is multiplied at every following step by
@@ -15,7 +16,8 @@ on (Sec. 3.1).  This driver uses the ePlace-style rules (a reading):
   * the decisions read only the exact integer HPWL and overflow numerator.
 
 Perturbations (Sec. 4.2): Gaussian moves of a fraction of the cells, Shuffle (all) of a
-fraction, or a uniform random restart (the Multiple-restart baseline).  Every iteration runs
+fraction, Shuffle of a fraction of the macros (netlists with movable macros), or a uniform
+random restart (the Multiple-restart baseline).  Every iteration runs
 on the device (hp_iterate); the host reads two integers every CHECK iterations.
 
     python -m paper_2402_18311_amd.alg1 --workload mid --rounds 5
@@ -38,7 +40,8 @@ DH_REF = 3.5e-3
 LAMBDA0_SCALE = 1e-4
 
 MODES = {"gauss": hy.HP_PERTURB_GAUSS, "shuffle": hy.HP_PERTURB_SHUFFLE,
-         "restart": hy.HP_PERTURB_UNIFORM}
+         "shuffle-macros": hy.HP_PERTURB_SHUFFLE, "restart": hy.HP_PERTURB_UNIFORM}
+FRACTIONS = {"gauss": 0.05, "shuffle": 0.5, "shuffle-macros": 0.5, "restart": 1.0}
 
 
 def gamma_of(tau: float, bin_w: float) -> float:
@@ -68,7 +71,7 @@ def global_place(pl, slot: int, max_iters: int) -> dict:
         st = pl.state(slot)
         tau = float(st["overflow"])
         h = int(st["hpwl_q"])
-        settled = abs(h - h_prev) <= PLATEAU * h_prev
+        settled = h - h_prev >= -PLATEAU * h_prev
         hy.hp_set_lambda_ratio(pl.ctx, slot, mu_of(h, h_prev))
         h_prev = h
     return {"iters": k, "hpwl_q": h_prev, "overflow": tau}
@@ -93,7 +96,9 @@ def hybro(pl, rounds: int, mode: str = "gauss", fraction: float = 0.05, sigma_bi
         for r in range(rounds):
             hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
             pl.set_positions(work, ix, iy)
-            pl.perturb(work, MODES[mode], fraction, sigma_bins, seed + r, want_idx=False)
+            pool = nl.macros if mode == "shuffle-macros" else None
+            pl.perturb(work, MODES[mode], fraction, sigma_bins, seed + r, want_idx=False,
+                       cells=pool)
             res = global_place(pl, work, max_iters)
             won = pl.select_best([work], inc)
             best = min(best, res["hpwl_q"])
@@ -116,7 +121,9 @@ def main():
     pl = hy.Placer(nl, precision=32)
     out = {"workload": a.workload, "rounds": a.rounds, "max_iters": a.max_iters, "runs": []}
     for mode in a.modes.split(","):
-        frac = {"gauss": 0.05, "shuffle": 0.5, "restart": 1.0}[mode]
+        if mode == "shuffle-macros" and nl.macros is None:
+            raise SystemExit(f"{a.workload} has no movable macros (try mid_mm)")
+        frac = FRACTIONS[mode]
         t0 = time.perf_counter()
         r = hybro(pl, a.rounds, mode, frac, 8.0, a.seed, a.max_iters)
         r["seconds"] = round(time.perf_counter() - t0, 3)

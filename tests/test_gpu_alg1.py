@@ -29,6 +29,25 @@ def test_alg1_matches_oracle_fp64(orc, mode, frac):
     pl.close()
 
 
+def test_alg1_shuffle_macros_matches_oracle_fp64(orc):
+    """Hybro-Shuffle (Sec. 4.2): half of the movable macros exchange places each round; the
+    device driver follows the oracle's round by round (tiny netlist with six macros, FP64)."""
+    from oracle import alg1_oracle
+    from paper_2402_18311_amd import alg1, hybro
+    nl = netgen.make_small(1000, 1100, 64, seed=1, n_fixed=6, movable_macros=True,
+                           macro_frac=0.3)
+    pl = hybro.Placer(nl, precision=64)
+    res = alg1.hybro(pl, 2, "shuffle-macros", 0.5, 0.0, seed=5, max_iters=120)
+    o = orc.Oracle(nl)
+    ref = alg1_oracle.hybro(o, nl, 2, hybro.HP_PERTURB_SHUFFLE, 0.5, 0.0, 5, 120, pool=nl.macros)
+    for t, (k, h, best) in zip(res["trace"], ref):
+        print(t["iters"], k, t["hpwl_q"], h)
+        assert t["iters"] == k
+        assert abs(t["hpwl_q"] - h) <= 1e-6 * h
+        assert abs(t["best_hpwl_q"] - best) <= 1e-6 * best
+    pl.close()
+
+
 def test_alg1_invariants_mid():
     """mid in FP32: the best HPWL never rises, equals the smallest round result, and every
     placement stops at the overflow target or the iteration cap."""
