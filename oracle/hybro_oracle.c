@@ -763,6 +763,89 @@ void orc_nesterov_step(const orc_netlist *n, double lambda, const double *g, dou
     free(gt);
 }
 
+/* The same step with ePlace's backtracking on the predicted step length (Lu et al., ePlace,
+ * TODAES 2015: Nesterov's method with Lipschitz-constant prediction).  alpha above is the step
+ * length predicted at the reached point v; the step that reached v had length s->alpha.  When
+ * k >= 1 and the new prediction is below 0.95 of that length, the step that reached v was too
+ * long: it is redone from its own start with the new length,
+ *   u = clamp(v_prev - alpha gp_prev),  v = clamp(u + (a_prev - 1)/a (u - u_prev)),
+ * leaving v_prev, gp_prev, u_prev, a, a_prev and k as they were (s->rejected = 1; the gradient
+ * taken at the rejected point is dropped).  Otherwise the step is the plain one above, and
+ * u_prev, a_prev keep the start of this step for a later redo.  s->alpha is the length used. */
+typedef struct {
+    int32_t k;
+    double a, a_prev, alpha;
+    int32_t rejected;
+} orc_nesterov_bt_scalars;
+
+void orc_nesterov_step_bt(const orc_netlist *n, double lambda, const double *g, double *u,
+                          double *v, double *v_prev, double *gp_prev, double *u_prev,
+                          orc_nesterov_bt_scalars *s)
+{
+    int N = n->n_movable;
+    double wb = n->W / n->mx;
+    int32_t *pins = calloc((size_t)(N > 0 ? N : 1), sizeof(int32_t));
+    for (int p = 0; p < n->n_pins; ++p)
+        if (n->pin_cell[p] < N) pins[n->pin_cell[p]]++;
+    double *gt = malloc(sizeof(double) * 2 * (size_t)(N > 0 ? N : 1));
+    for (int i = 0; i < N; ++i) {
+        double P = pins[i] + lambda * n->cell_w[i] * n->cell_h[i];
+        if (P < 1.0) P = 1.0;
+        gt[i] = g[i] / P;
+        gt[N + i] = g[N + i] / P;
+    }
+    double alpha;
+    if (s->k == 0) {
+        double gmax = 0.0;
+        for (int i = 0; i < 2 * N; ++i)
+            if (fabs(gt[i]) > gmax) gmax = fabs(gt[i]);
+        alpha = 0.1 * wb / (gmax > 1e-30 ? gmax : 1e-30);
+    } else {
+        double dv = 0.0, dg = 0.0;
+        for (int i = 0; i < 2 * N; ++i) {
+            dv += (v[i] - v_prev[i]) * (v[i] - v_prev[i]);
+            dg += (gt[i] - gp_prev[i]) * (gt[i] - gp_prev[i]);
+        }
+        alpha = dg > 0.0 ? sqrt(dv) / sqrt(dg) : s->alpha;
+    }
+    s->rejected = s->k >= 1 && alpha < 0.95 * s->alpha;
+    if (s->rejected) {
+        double coef = (s->a_prev - 1.0) / s->a;
+        for (int i = 0; i < 2 * N; ++i) {
+            int c = i < N ? i : i - N;
+            double hi = i < N ? n->W - n->cell_w[c] : n->H - n->cell_h[c];
+            double un = v_prev[i] - alpha * gp_prev[i];
+            un = un < 0.0 ? 0.0 : (un > hi ? hi : un);
+            double vn = un + coef * (un - u_prev[i]);
+            vn = vn < 0.0 ? 0.0 : (vn > hi ? hi : vn);
+            u[i] = un;
+            v[i] = vn;
+        }
+    } else {
+        double a_next = (1.0 + sqrt(4.0 * s->a * s->a + 1.0)) * 0.5;
+        double coef = (s->a - 1.0) / a_next;
+        for (int i = 0; i < 2 * N; ++i) {
+            int c = i < N ? i : i - N;
+            double hi = i < N ? n->W - n->cell_w[c] : n->H - n->cell_h[c];
+            double un = v[i] - alpha * gt[i];
+            un = un < 0.0 ? 0.0 : (un > hi ? hi : un);
+            double vn = un + coef * (un - u[i]);
+            vn = vn < 0.0 ? 0.0 : (vn > hi ? hi : vn);
+            u_prev[i] = u[i];
+            v_prev[i] = v[i];
+            gp_prev[i] = gt[i];
+            u[i] = un;
+            v[i] = vn;
+        }
+        s->a_prev = s->a;
+        s->a = a_next;
+        s->k += 1;
+    }
+    s->alpha = alpha;
+    free(pins);
+    free(gt);
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* The placer: T iterations of [objective + gradient at v, Nesterov step], from (x, y).
  * lambda_0 = scale * |g_wl|_1 / |g_d|_1 at the first evaluation, then multiplied by

@@ -51,6 +51,11 @@ class _NestScalars(C.Structure):
     _fields_ = [("k", C.c_int32), ("a", C.c_double), ("alpha", C.c_double)]
 
 
+class _NestBtScalars(C.Structure):
+    _fields_ = [("k", C.c_int32), ("a", C.c_double), ("a_prev", C.c_double),
+                ("alpha", C.c_double), ("rejected", C.c_int32)]
+
+
 class _PlaceParams(C.Structure):
     _fields_ = [("ev", _EvalParams), ("iters", C.c_int32), ("lambda0_scale", C.c_double),
                 ("lambda_decades", C.c_double)]
@@ -84,6 +89,7 @@ def lib():
             "orc_density_energy_float": (d, [P, P, P, C.c_int]),
             "orc_eval": (None, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
             "orc_nesterov_step": (None, [P, d, P, P, P, P, P, P]),
+            "orc_nesterov_step_bt": (None, [P, d, P, P, P, P, P, P, P]),
             "orc_lambda_ratio": (d, [d, C.c_int]),
             "orc_place": (None, [P, P, P, P, P, P, P]),
             "orc_splitmix": (u64, [u64, u64]),
@@ -237,11 +243,23 @@ class Oracle:
         state.update(k=s.k, a=s.a, alpha=s.alpha)
         return state
 
+    def nesterov_step_bt(self, lam, g, state):
+        """The step with backtracking; state as new_state(..., backtracking=True) (mutated);
+        returns whether the step was rejected and redone."""
+        s = _NestBtScalars(int(state["k"]), float(state["a"]), float(state["a_prev"]),
+                           float(state["alpha"]), 0)
+        g = _f64(g)
+        self.L.orc_nesterov_step_bt(self.ref, float(lam), _p(g), _p(state["u"]), _p(state["v"]),
+                                    _p(state["v_prev"]), _p(state["gp_prev"]),
+                                    _p(state["u_prev"]), C.byref(s))
+        state.update(k=s.k, a=s.a, a_prev=s.a_prev, alpha=s.alpha)
+        return bool(s.rejected)
+
     @staticmethod
     def new_state(x, y):
         u = np.concatenate([_f64(x), _f64(y)])
         return dict(u=u.copy(), v=u.copy(), v_prev=u.copy(), gp_prev=np.zeros_like(u), k=0,
-                    a=1.0, alpha=0.0)
+                    a=1.0, alpha=0.0, u_prev=u.copy(), a_prev=1.0)
 
     def lambda_ratio(self, decades, iters):
         return self.L.orc_lambda_ratio(float(decades), int(iters))

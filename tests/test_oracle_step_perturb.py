@@ -195,3 +195,77 @@ def test_placer_reduces_hpwl_and_spreads(orc, tiny):
     assert tr["overflow"][-1] <= 0.10  # the density constraint D(s) <= eps of Eq. 1
     w = nl.cell_w[: nl.n_movable]
     assert np.all(x >= 0) and np.all(x <= nl.W - w)
+
+
+def _quadratic(n, seed, W=1e6):
+    """n pinless cells in the middle of a huge die (no clamping; preconditioner 1 at lambda 0)
+    and the gradient of f(x) = 1/2 sum c_i (x_i - t_i)^2 over both axes."""
+    rng = np.random.default_rng(seed)
+    x = W / 2 + rng.uniform(-50, 50, n)
+    y = W / 2 + rng.uniform(-50, 50, n)
+    nl = cells_only(np.ones(n), np.ones(n), W, W, 64, x, y)
+    t = np.concatenate([x, y]) + rng.uniform(-20, 20, 2 * n)
+    return nl, t
+
+
+def test_backtracking_step_equals_plain_step_without_rejections(orc):
+    """On a linear objective (a constant gradient) the gradient difference is zero, the step
+    length stays the first one, no step is rejected, and the backtracking method is the plain
+    one, bit for bit."""
+    nl, _ = _quadratic(40, 1)
+    o = orc.Oracle(nl)
+    g = np.random.default_rng(5).uniform(-1, 1, 2 * nl.n_movable)
+    a = o.new_state(nl.x0, nl.y0)
+    b = o.new_state(nl.x0, nl.y0)
+    for _ in range(10):
+        o.nesterov_step(0.0, g, a)
+        assert not o.nesterov_step_bt(0.0, g, b)
+        for key in ("u", "v", "v_prev", "gp_prev"):
+            assert np.array_equal(a[key], b[key])
+        assert (a["k"], a["a"], a["alpha"]) == (b["k"], b["a"], b["alpha"])
+
+
+def test_backtracking_redoes_the_last_step_shorter(orc):
+    """A curvature that jumps after a step makes the prediction at the reached point shorter
+    than the step that reached it: the step is redone from its own start along the same
+    direction, scaled by the ratio of the two lengths, and nothing else of the state moves."""
+    nl, t = _quadratic(30, 2)
+    o = orc.Oracle(nl)
+    st = o.new_state(nl.x0, nl.y0)
+    c = np.random.default_rng(7).uniform(0.02, 0.05, 2 * nl.n_movable)
+    rejected = [o.nesterov_step_bt(0.0, c * (st["v"] - t), st) for _ in range(6)]
+    while rejected[-1]:  # end on an accepted step with some momentum
+        rejected.append(o.nesterov_step_bt(0.0, c * (st["v"] - t), st))
+    assert st["k"] >= 4
+    before = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    c2 = 8.0 * c  # stiffer: the reached point predicts a much shorter step
+    assert o.nesterov_step_bt(0.0, c2 * (st["v"] - t), st)
+    assert st["alpha"] < 0.95 * before["alpha"]
+    for key in ("v_prev", "gp_prev", "u_prev"):
+        assert np.array_equal(st[key], before[key])
+    assert (st["k"], st["a"], st["a_prev"]) == (before["k"], before["a"], before["a_prev"])
+    # the redo moves from the step's start along the same direction, shorter by alpha'/alpha
+    d_old = before["u"] - before["v_prev"]
+    d_new = st["u"] - before["v_prev"]
+    np.testing.assert_allclose(d_new, d_old * (st["alpha"] / before["alpha"]), rtol=1e-9,
+                               atol=1e-9)
+    # and the momentum term is the one of that step: v - u is parallel to u - u_prev
+    m_old = before["v"] - before["u"]
+    m_new = st["v"] - st["u"]
+    ratio_u = (st["u"] - before["u_prev"]) / (before["u"] - before["u_prev"])
+    np.testing.assert_allclose(m_new, m_old * ratio_u, rtol=1e-6, atol=1e-8)  # 5e5 coordinates
+
+
+def test_backtracking_first_redo_has_no_momentum(orc):
+    """Redoing the very first step (a_prev = 1) leaves no momentum: v = u."""
+    nl, t = _quadratic(20, 3)
+    o = orc.Oracle(nl)
+    st = o.new_state(nl.x0, nl.y0)
+    assert not o.nesterov_step_bt(0.0, 0.2 * (st["v"] - t), st)
+    u1 = st["u"].copy()
+    assert o.nesterov_step_bt(0.0, 50.0 * (st["v"] - t), st)
+    assert np.array_equal(st["u"], st["v"]) and st["k"] == 1
+    np.testing.assert_allclose(st["u"] - st["v_prev"],
+                               (u1 - st["v_prev"]) * st["alpha"] / (0.1 * nl.bin_w / np.max(
+                                   np.abs(0.2 * (np.concatenate([nl.x0, nl.y0]) - t)))),
+                               rtol=1e-9, atol=1e-9)
