@@ -155,6 +155,16 @@ int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n_slots,
                            const hp_eval_params *p, double *wl, double *energy,
                            double *overflow, void *grad_x, void *grad_y);
 
+/* Backtracking of the Nesterov step for one slot (ePlace's Nesterov method with Lipschitz
+ * prediction, the accelerated form of the descent of Sec. 3.1): on = 1 checks every step
+ * after the first following a restart: when the step length predicted at the point the last
+ * step reached, |v - v_prev| / |g~ - g~_prev|, is below 0.95 of that step's length, that step
+ * is redone from its start with the new length (the gradient just taken is dropped; k, a and
+ * lambda do not advance), else the step proceeds as usual.  Checks begin after the first
+ * step taken with on = 1.  on = 0 (the default) is the plain method.  Resets the slot's count
+ * of redone steps.  HP_EINVAL unless on is 0 or 1.  Synchronises. */
+int hp_set_backtracking(hp_ctx *ctx, int32_t slot, int32_t on);
+
 /* One preconditioned Nesterov step per slot from the gradient of the last evaluation:
  * P_i = max(1, pins_i + lambda area_i), g~ = g / P, step alpha_0 = 0.1 bin / max|g~| then
  * Barzilai-Borwein |v - v_prev| / |g~ - g~_prev|, u' = clamp(v - alpha g~),
@@ -217,14 +227,16 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, int32_t i
 enum { HP_MAP_RHO_MOV = 0, HP_MAP_RHO_FIXED = 1, HP_MAP_PSI = 2, HP_MAP_EX = 3, HP_MAP_EY = 4 };
 int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *host_dst);
 
-/* A slot's device state: iterations taken k, the last exact HPWL (2^-16 units; -1 if none
- * since the last restart), the overflow numerator (2^-40 area units) and, in the same order
- * as hp_eval_objective_grad reports them, Nesterov's a, the last step alpha, lambda and the
- * last evaluation's totals.  Reduces any pending HPWL or totals first (small launches) and
+/* A slot's device state: iterations taken k (accepted steps), the last exact HPWL (2^-16
+ * units; -1 if none since the last restart), the overflow numerator (2^-40 area units) and, in
+ * the same order as hp_eval_objective_grad reports them, Nesterov's a, the last step alpha,
+ * lambda and the last evaluation's totals; then the steps redone under backtracking since
+ * hp_set_backtracking.  Reduces any pending HPWL or totals first (small launches) and
  * synchronises. */
 typedef struct {
     int64_t k, hpwl_q, overflow_num;
     double a, alpha, lambda, wl, energy, overflow;
+    int64_t rejects;
 } hp_slot_state;
 int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out);
 

@@ -137,6 +137,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.u, 2 * rs * Nc);
     put(L.v, 2 * rs * Nc);
     put(L.vprev, 2 * rs * Nm);
+    put(L.uprev, 2 * rs * Nm);
     put(L.gprev, 2 * rs * Nm);
     put(L.g, 2 * rs * Nm);
     put(L.gd, 2 * rs * Nm);
@@ -1185,6 +1186,20 @@ int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio) {
     return HP_OK;
 }
 
+int hp_set_backtracking(hp_ctx *ctx, int32_t slot, int32_t on) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (on != 0 && on != 1) return fail(HP_EINVAL, "on must be 0 or 1");
+    const int64_t vals[2] = {on, 0};  // backtrack, rejects (adjacent fields)
+    static_assert(offsetof(Scalars, rejects) == offsetof(Scalars, backtrack) + 8, "layout");
+    HP_CHECK(hipMemcpyAsync(s->base + n->L.scal + offsetof(Scalars, backtrack), vals, sizeof(vals),
+                            hipMemcpyHostToDevice, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
 int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p,
                            double *wl, double *energy, double *overflow, void *gx, void *gy) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
@@ -1413,6 +1428,7 @@ int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
     out->wl = h.wl;
     out->energy = h.energy;
     out->overflow = h.overflow;
+    out->rejects = h.rejects;
     return HP_OK;
 }
 

@@ -255,29 +255,55 @@ __device__ __forceinline__ void step_block_norms(const NetDev &nd, char *base, c
 // Step proposal from the totals of the three reductions: alpha_0 = 0.1 bin / max|g~| on the
 // first step, else alpha_k = |v - v_prev| / |g~ - g~_prev| (Barzilai-Borwein, the previous
 // alpha when the gradient did not change); a' = (1 + sqrt(4 a^2 + 1)) / 2 and momentum
-// (a - 1) / a'.  k, a and the previous alpha are the optimiser state of the current bank.
+// (a - 1) / a'.  k, a, a_prev and the previous alpha are the optimiser state of the current
+// bank.  With backtracking (ePlace's Nesterov method with Lipschitz prediction, Lu et al.,
+// TODAES 2015) and a start saved by the last accepted step: if alpha_k, the length predicted
+// at the reached point, is below 0.95 of the length that reached it, that step is redone from
+// its start with alpha_k (momentum (a_prev - 1) / a; k and a unchanged).
 struct StepProposal {
-    double alpha, coef, a;
+    double alpha, coef, a, aprev;
+    int64_t k;
+    int reject;
 };
-__device__ __forceinline__ StepProposal propose_step(int64_t k, double a, double alpha_prev,
+__device__ __forceinline__ StepProposal propose_step(int64_t k, double a, double aprev,
+                                                     double alpha_prev, bool ready, bool backtrack,
                                                      double DV, double DG, double GM, double wb) {
     StepProposal p;
     if (k == 0)
         p.alpha = 0.1 * wb / (GM > 1e-30 ? GM : 1e-30);
     else
         p.alpha = DG > 0.0 ? sqrt(DV) / sqrt(DG) : alpha_prev;
-    p.a = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
-    p.coef = (a - 1.0) / p.a;
+    p.reject = backtrack && ready && k > 0 && p.alpha < 0.95 * alpha_prev;
+    if (p.reject) {
+        p.a = a;
+        p.aprev = aprev;
+        p.coef = (aprev - 1.0) / a;
+        p.k = k;
+    } else {
+        p.a = (1.0 + sqrt(4.0 * a * a + 1.0)) * 0.5;
+        p.aprev = a;
+        p.coef = (a - 1.0) / p.a;
+        p.k = k + 1;
+    }
     return p;
 }
-// The proposal from bank b, stored for the step kernel, which commits it (bank 1 - b gets
-// a', alpha and k + 1).
-__device__ __forceinline__ void step_propose(Scalars *sc, double DV, double DG, double GM,
-                                             double wb, int b) {
-    const StepProposal p = propose_step(sc->kb[b], sc->ab[b], sc->alphab[b], DV, DG, GM, wb);
+__device__ __forceinline__ StepProposal propose_from_bank(const Scalars *sc, int b, double DV,
+                                                          double DG, double GM, double wb) {
+    return propose_step(sc->kb[b], sc->ab[b], sc->aprevb[b], sc->alphab[b], sc->readyb[b] != 0,
+                        sc->backtrack != 0, DV, DG, GM, wb);
+}
+// The proposal from bank b, stored for the step kernel, which commits it into bank 1 - b.
+__device__ __forceinline__ void store_proposal(Scalars *sc, const StepProposal &p) {
     sc->step_alpha = p.alpha;
     sc->step_coef = p.coef;
     sc->step_a = p.a;
+    sc->step_aprev = p.aprev;
+    sc->step_k = p.k;
+    sc->step_reject = p.reject;
+}
+__device__ __forceinline__ void step_propose(Scalars *sc, double DV, double DG, double GM,
+                                             double wb, int b) {
+    store_proposal(sc, propose_from_bank(sc, b, DV, DG, GM, wb));
 }
 
 // Movable charge of bin (k, j) assembled from the binned scatter's chunk windows: the chunks

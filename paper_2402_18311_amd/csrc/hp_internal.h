@@ -88,6 +88,7 @@ __host__ __device__ inline bool is_big(const NetDev &nd, int4 c) {
 struct SlotLayout {
     size_t u, v;          // vec2<T> [n_cells] (x, y) pairs (fixed cells in the tail, unchanged)
     size_t vprev;         // vec2<T> [n_mov]
+    size_t uprev;         // vec2<T> [n_mov] u at the start of the last accepted step
     size_t gprev;         // T [2][n_mov]
     size_t g, gd;         // T [2][n_mov] raw gradient; density part (first evaluation)
     size_t pin_grad;      // vec2<T> [ps]
@@ -120,10 +121,15 @@ enum { PART_WL = 0, PART_E = 1, PART_N1 = 2, PART_N2 = 3, PART_DV = 4, PART_DG =
 // them.  Resets write both banks.
 struct Scalars {
     double ab[2], alphab[2];
+    double aprevb[2];       // a at the start of the last accepted step (for a redo)
     double lambda, lambda_step, lambda0_scale, lambda_ratio;
     double wl, energy, overflow;
-    double step_alpha, step_coef, step_a;  // proposal of the next step (see step_propose)
+    double step_alpha, step_coef, step_a, step_aprev;  // proposal of the next step
+    int64_t step_k, step_reject;                       // (see step_propose)
     int64_t kb[2];
+    int64_t readyb[2];      // the last accepted step saved its start (u_prev, a_prev)
+    int64_t backtrack;      // 1: steps are checked and redone (ePlace backtracking)
+    int64_t rejects;        // steps redone since backtracking was last set
     int64_t lambda_valid;   // 0 until lambda_0 is derived at the first evaluation
     int64_t init_this_eval; // the last evaluation derived lambda_0
     int64_t hpwl_q, hpwl_valid;

@@ -237,12 +237,15 @@ __device__ __forceinline__ void step_totals(const double *part, const SlotLayout
     GM = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
 }
 
-// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~.  The
-// step (alpha, coef, a') is the proposal stored by the evaluation's closing reduction or the
+// u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~ (and
+// u_prev = u with backtracking on).  A redo (a rejected step under backtracking) instead
+// recomputes the last step from its start: u' = clamp(v_prev - alpha g~_prev),
+// v' = clamp(u' + coef (u' - u_prev)), with v_prev, g~_prev, u_prev kept.  The proposal
+// (alpha, coef, a', ...) is the one stored by the evaluation's closing reduction or the
 // step-scalars kernel, or (fused) derived by every block itself from the cell-gradient pass's
-// nc partials and the optimiser state of bank b.  One thread commits it into bank 1 - b
-// (a = a', alpha, k + 1) and multiplies lambda by the schedule's ratio; no block reads what
-// that thread writes.
+// nc partials and the optimiser state of bank b.  One thread commits it into bank 1 - b and,
+// for an accepted step, multiplies lambda by the schedule's ratio; no block reads what that
+// thread writes.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
                                                              int fused, int nc, uint32_t banks) {
@@ -266,29 +269,53 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
         __shared__ double red[12];
         double DV, DG, GM;
         step_totals(reinterpret_cast<const double *>(base + L.part), L, nc, red, DV, DG, GM);
-        pr = propose_step(sc->kb[b], sc->ab[b], sc->alphab[b], DV, DG, GM, nd.wb);
+        pr = propose_from_bank(sc, b, DV, DG, GM, nd.wb);
     } else {
         pr.alpha = sc->step_alpha;
         pr.coef = sc->step_coef;
         pr.a = sc->step_a;
+        pr.aprev = sc->step_aprev;
+        pr.k = sc->step_k;
+        pr.reject = (int)sc->step_reject;
     }
+    const bool save_start = sc->backtrack != 0;
     if (i == 0) {
-        if (fused) {
-            sc->step_alpha = pr.alpha;
-            sc->step_coef = pr.coef;
-            sc->step_a = pr.a;
-        }
+        if (fused) store_proposal(sc, pr);
         sc->ab[1 - b] = pr.a;
+        sc->aprevb[1 - b] = pr.aprev;
         sc->alphab[1 - b] = pr.alpha;
-        sc->kb[1 - b] = sc->kb[b] + 1;
-        if (sc->lambda_valid) sc->lambda *= sc->lambda_ratio;
+        sc->kb[1 - b] = pr.k;
+        sc->readyb[1 - b] = pr.reject ? 1 : (save_start ? 1 : 0);
+        if (pr.reject)
+            sc->rejects += 1;
+        else if (sc->lambda_valid)
+            sc->lambda *= sc->lambda_ratio;
     }
     if (i >= n) return;
-    const double P = precond_of<T>(c0, c1, sc->lambda_step);
     const double alpha = pr.alpha, coef = pr.coef;
     vec2<T> *vp = reinterpret_cast<vec2<T> *>(base + L.vprev);
+    vec2<T> *up = reinterpret_cast<vec2<T> *>(base + L.uprev);
     T *gp = reinterpret_cast<T *>(base + L.gprev);
     T un2[2], vn2[2];
+    if (pr.reject) {  // redo the step that reached v, from its start, with the shorter alpha
+        const vec2<T> vs = vp[i], us = up[i];
+        const T gs[2] = {gp[i], gp[(size_t)n + i]};
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            const double hi = (double)(ax ? hy : hx);
+            double un = (double)(ax ? vs.y : vs.x) - alpha * (double)gs[ax];
+            un = un < 0.0 ? 0.0 : (un > hi ? hi : un);
+            const T unt = (T)un;
+            double vn = (double)unt + coef * ((double)unt - (double)(ax ? us.y : us.x));
+            vn = vn < 0.0 ? 0.0 : (vn > hi ? hi : vn);
+            un2[ax] = unt;
+            vn2[ax] = (T)vn;
+        }
+        u[i] = cmk2<T>(un2[0], un2[1]);
+        v[i] = cmk2<T>(vn2[0], vn2[1]);
+        return;
+    }
+    const double P = precond_of<T>(c0, c1, sc->lambda_step);
 #pragma unroll
     for (int ax = 0; ax < 2; ++ax) {
         const size_t ig = (size_t)ax * n + i;  // gradients: [2][n_mov]
@@ -304,6 +331,7 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
         vn2[ax] = (T)vn;
     }
     vp[i] = v0;
+    if (save_start) up[i] = u0;
     u[i] = cmk2<T>(un2[0], un2[1]);
     v[i] = cmk2<T>(vn2[0], vn2[1]);
 }

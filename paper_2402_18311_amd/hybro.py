@@ -45,7 +45,8 @@ class hp_iter_params(C.Structure):
 class hp_slot_state(C.Structure):
     _fields_ = [("k", C.c_int64), ("hpwl_q", C.c_int64), ("overflow_num", C.c_int64),
                 ("a", C.c_double), ("alpha", C.c_double), ("lambda_", C.c_double),
-                ("wl", C.c_double), ("energy", C.c_double), ("overflow", C.c_double)]
+                ("wl", C.c_double), ("energy", C.c_double), ("overflow", C.c_double),
+                ("rejects", C.c_int64)]
 
 
 class HybroError(RuntimeError):
@@ -71,6 +72,7 @@ _SIGS = {
     "hp_get_eval_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
     "hp_set_lambda_ratio": [_P, C.c_int32, C.c_double],
+    "hp_set_backtracking": [_P, C.c_int32, C.c_int32],
     "hp_set_scatter_policy": [_P, C.c_int32, C.c_int32, C.c_int32],
     "hp_get_scatter_policy": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
@@ -199,6 +201,10 @@ def hp_get_eval_positions(ctx, slot, x, y, on_device):
 
 def hp_set_lambda_ratio(ctx, slot, ratio):
     _chk(lib().hp_set_lambda_ratio(ctx, slot, float(ratio)))
+
+
+def hp_set_backtracking(ctx, slot, on):
+    _chk(lib().hp_set_backtracking(ctx, slot, int(bool(on))))
 
 
 def hp_set_scatter_policy(ctx, netlist, regroup_every, deferred):
@@ -374,6 +380,10 @@ class Placer:
 
     def set_schedule(self, s, lambda0_scale=1e-4, decades=4.0, total_iters=1000):
         hp_set_schedule(self.ctx, s, lambda0_scale, decades, total_iters)
+
+    def set_backtracking(self, s, on=True):
+        """ePlace backtracking of the Nesterov step for slot s (see hybro.h)."""
+        hp_set_backtracking(self.ctx, s, on)
 
     def eval(self, slots, gamma, lam=-1.0, keep_maps=False, grads=False, want_host=True,
              grad_mode=0):

@@ -32,7 +32,7 @@ def test_binding_struct_layouts_match_header():
     assert C.sizeof(hybro.hp_die) == 40
     assert C.sizeof(hybro.hp_shape) == 16
     assert C.sizeof(hybro.hp_eval_params) == 24
-    assert C.sizeof(hybro.hp_slot_state) == 72
+    assert C.sizeof(hybro.hp_slot_state) == 80  # 3 int64, 6 doubles, 1 int64
 
 
 def test_null_context_is_rejected_without_gpu():
