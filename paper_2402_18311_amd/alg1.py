@@ -78,15 +78,19 @@ def global_place(pl, slot: int, max_iters: int) -> dict:
 
 
 def hybro(pl, rounds: int, mode: str = "gauss", fraction: float = 0.05, sigma_bins: float = 8.0,
-          seed: int = 0, max_iters: int = 1000, x0=None, y0=None) -> dict:
+          seed: int = 0, max_iters: int = 1000, x0=None, y0=None,
+          backtracking: bool = False) -> dict:
     """Alg. 1: the incumbent is the placement of (x0, y0); each round perturbs it (`mode`),
-    re-places and keeps the better.  Returns the per-round trace."""
+    re-places and keeps the better.  With `backtracking` the placer's Nesterov steps are
+    checked and redone as in ePlace.  Returns the per-round trace."""
     nl = pl.nl
     inc, work = pl.new_slot(), pl.new_slot()
     try:
         pl.set_positions(inc, nl.x0 if x0 is None else x0, nl.y0 if y0 is None else y0)
         pl.set_schedule(inc, LAMBDA0_SCALE, 4.0, 1000)
         pl.set_schedule(work, LAMBDA0_SCALE, 4.0, 1000)
+        pl.set_backtracking(inc, backtracking)
+        pl.set_backtracking(work, backtracking)
         first = global_place(pl, inc, max_iters)
         best = first["hpwl_q"]
         trace = [{"round": 0, **first, "best_hpwl_q": best}]
@@ -116,16 +120,20 @@ def main():
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--modes", default="gauss,shuffle,restart")
+    ap.add_argument("--backtracking", action="store_true",
+                    help="ePlace backtracking of the placer's Nesterov steps")
     a = ap.parse_args()
     nl = netgen.make_netlist(a.workload, a.seed)
     pl = hy.Placer(nl, precision=32)
-    out = {"workload": a.workload, "rounds": a.rounds, "max_iters": a.max_iters, "runs": []}
+    out = {"workload": a.workload, "rounds": a.rounds, "max_iters": a.max_iters,
+           "backtracking": a.backtracking, "runs": []}
     for mode in a.modes.split(","):
         if mode == "shuffle-macros" and nl.macros is None:
             raise SystemExit(f"{a.workload} has no movable macros (try mid_mm)")
         frac = FRACTIONS[mode]
         t0 = time.perf_counter()
-        r = hybro(pl, a.rounds, mode, frac, 8.0, a.seed, a.max_iters)
+        r = hybro(pl, a.rounds, mode, frac, 8.0, a.seed, a.max_iters,
+                  backtracking=a.backtracking)
         r["seconds"] = round(time.perf_counter() - t0, 3)
         r["gp_iterations"] = sum(t["iters"] for t in r["trace"])
         out["runs"].append(r)
