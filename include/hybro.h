@@ -155,6 +155,17 @@ int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n_slots,
                            const hp_eval_params *p, double *wl, double *energy,
                            double *overflow, void *grad_x, void *grad_y);
 
+/* Overflow (the D(s) <= eps measure of Eq. 1, as hp_eval_objective_grad reports it) of the
+ * charge of movable cells [0, n_counted) alone, at the slot's evaluation point v: out_num the
+ * exact numerator (2^-40 area units), out the numerator over those cells' total charge (either
+ * may be NULL).  For netlists whose last movable cells are ePlace filler cells (pinless cells
+ * that fill the free area to a target density below 1), the overflow of the real cells; with
+ * n_counted = n_movable it is the evaluation's own.  Off the iteration path (two launches, the
+ * map is rebuilt with atomics); a map kept by the last evaluation is dropped.  HP_EINVAL if
+ * n_counted is outside [0, n_movable].  Synchronises. */
+int hp_overflow_of_cells(hp_ctx *ctx, int32_t slot, int32_t n_counted, int64_t *out_num,
+                         double *out);
+
 /* Backtracking of the Nesterov step for one slot (ePlace's Nesterov method with Lipschitz
  * prediction, the accelerated form of the descent of Sec. 3.1): on = 1 checks every step
  * after the first following a restart: when the step length predicted at the point the last

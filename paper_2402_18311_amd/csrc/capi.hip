@@ -180,6 +180,7 @@ struct Netlist {
     // evaluations; `deferred`: the rebuilding evaluation accumulates in the existing order
     int regroup_every = kRegroupEvery;
     bool deferred = true;
+    std::vector<int64_t> charge_prefix;  // [n_mov + 1] integer charge of cells [0, i)
 };
 
 struct Slot {
@@ -441,6 +442,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.big_hq = kBigHalo * nd.hq + 2;
     nd.big_aq = (int64_t)kBigArea * nd.bq * nd.hq;
     std::vector<int32_t> h_big;
+    NL.charge_prefix.assign((size_t)Nm + 1, 0);
     {
 #pragma clang fp contract(off)
         for (int i = 0; i < Nm; ++i) {
@@ -461,6 +463,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             h_cq[4 * (size_t)i + 3] = (int32_t)dyq;
             h_rq[i] = (int32_t)rq;
             total_charge += rq * wq * hq;
+            NL.charge_prefix[(size_t)i + 1] = total_charge;
             h_cs[i] = (T)cnt_all[i];
             h_cs[(size_t)Nm + i] = (T)(w * h);
             h_cs[2 * (size_t)Nm + i] = (T)(D.W - w);
@@ -1183,6 +1186,36 @@ int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio) {
     HP_CHECK(hipMemcpyAsync(s->base + n->L.scal + offsetof(Scalars, lambda_ratio), &ratio,
                             sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_overflow_of_cells(hp_ctx *ctx, int32_t slot, int32_t n_counted, int64_t *out_num,
+                         double *out) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    if (n_counted < 0 || n_counted > n->nd.n_mov) return fail(HP_EINVAL, "n_counted out of range");
+    hipStream_t st = ctx->stream;
+    if (s->rho_dirty) {  // a kept map: clear it first (the pass needs zeros)
+        SlotArgs sa{};
+        sa.base[0] = s->base;
+        sa.n = 1;
+        HP_CHECK(launch_clear_rho(n->nd, sa, n->L, st));
+        s->rho_dirty = false;
+        s->maps_valid = false;
+    }
+    if (ctx->precision == 32)
+        HP_CHECK(launch_overflow_of_cells<float>(n->nd, s->base, n->L, n_counted, st));
+    else
+        HP_CHECK(launch_overflow_of_cells<double>(n->nd, s->base, n->L, n_counted, st));
+    int64_t num = 0;
+    HP_CHECK(hipMemcpyAsync(&num, s->base + n->L.scal + offsetof(Scalars, ovf_tmp), sizeof(num),
+                            hipMemcpyDeviceToHost, st));
+    HP_CHECK(hipStreamSynchronize(st));
+    const int64_t den = n->charge_prefix[(size_t)n_counted];
+    if (out_num) *out_num = num;
+    if (out) *out = den > 0 ? (double)num / (double)den : 0.0;
     return HP_OK;
 }
 

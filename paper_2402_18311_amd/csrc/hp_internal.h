@@ -130,6 +130,7 @@ struct Scalars {
     int64_t readyb[2];      // the last accepted step saved its start (u_prev, a_prev)
     int64_t backtrack;      // 1: steps are checked and redone (ePlace backtracking)
     int64_t rejects;        // steps redone since backtracking was last set
+    int64_t ovf_tmp;        // overflow numerator of hp_overflow_of_cells
     int64_t lambda_valid;   // 0 until lambda_0 is derived at the first evaluation
     int64_t init_this_eval; // the last evaluation derived lambda_0
     int64_t hpwl_q, hpwl_valid;
@@ -196,6 +197,11 @@ size_t scatter_accum_lds(const NetDev &nd);
 template <typename T>
 hipError_t launch_big_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            int grad_mode, hipStream_t st);
+// Overflow numerator of the charge of movable cells [0, n_counted) at v, into ovf_tmp of the
+// slot's scalars; rho must be zero before and is zero after.
+template <typename T>
+hipError_t launch_overflow_of_cells(const NetDev &nd, char *base, const SlotLayout &L,
+                                    int n_counted, hipStream_t st);
 hipError_t launch_clear_rho(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                             hipStream_t st);
 // Device-to-device (x, y) pair splitting / joining, rs = element bytes (4 or 8).

@@ -416,6 +416,63 @@ hipError_t launch_join_pairs(const void *x, const void *y, void *pairs, int n, s
     return hipGetLastError();
 }
 
+// ---- overflow of a prefix of the movable cells (filler cells excluded) ---------------------
+// The overflow of Eq. 1's density constraint counts the real cells only when the last movable
+// cells are ePlace fillers.  Off the iteration path: the counted cells' charge goes into the
+// (zero) movable map with global atomics, then each bin's excess over the free capacity is
+// summed (int64, order-free, so exact) and the map is zeroed again.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void counted_scatter_kernel(NetDev nd, char *base, SlotLayout L,
+                                                                 int n_counted) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) scalars(base, L)->ovf_tmp = 0;
+    if (i >= n_counted) return;
+    const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+    const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
+    if (q.r <= q.l || q.t <= q.b) return;
+    const long long rq = nd.rq[i];
+    unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
+    for (int k = q.b / nd.hq; k <= (q.t - 1) / nd.hq; ++k) {
+        const long long oy = overlap(q.b, q.t, k, nd.hq);
+        for (int j = q.l / nd.bq; j <= (q.r - 1) / nd.bq; ++j)
+            atomicAdd(&rho[(size_t)k * nd.mx + j],
+                      (unsigned long long)(rq * overlap(q.l, q.r, j, nd.bq) * oy));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void counted_overflow_kernel(NetDev nd, char *base,
+                                                                  SlotLayout L) {
+    __shared__ long long red[4];
+    long long *rho = reinterpret_cast<long long *>(base + L.rho);
+    const size_t nb = (size_t)nd.mx * nd.my;
+    long long s = 0;
+    for (size_t b = (size_t)blockIdx.x * kBlock + threadIdx.x; b < nb; b += (size_t)gridDim.x * kBlock) {
+        const long long cap = __double2ll_rn(nd.target_density * (double)(nd.area_q - nd.rho_fixed[b]));
+        const long long over = rho[b] - cap;
+        if (over > 0) s += over;
+        rho[b] = 0;
+    }
+    s = group_sum<64>(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = (red[0] + red[1]) + (red[2] + red[3]);
+        if (t) atomicAdd(reinterpret_cast<unsigned long long *>(&scalars(base, L)->ovf_tmp),
+                         (unsigned long long)t);
+    }
+}
+
+template <typename T>
+hipError_t launch_overflow_of_cells(const NetDev &nd, char *base, const SlotLayout &L,
+                                    int n_counted, hipStream_t st) {
+    const int g = std::max(1, (n_counted + kBlock - 1) / kBlock);
+    HP_LAUNCH("counted_scatter_kernel", counted_scatter_kernel<T>, dim3(g), dim3(kBlock), 0, st, nd,
+              base, L, n_counted);
+    HP_LAUNCH("counted_overflow_kernel", counted_overflow_kernel, dim3(256), dim3(kBlock), 0, st, nd,
+              base, L);
+    return hipGetLastError();
+}
+
 // Zero the slots' movable charge maps (after an evaluation that kept them for inspection).
 __global__ __launch_bounds__(kBlock) void clear_rho_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
     long long *rho = reinterpret_cast<long long *>(sa.base[blockIdx.y] + L.rho);
@@ -457,6 +514,8 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
 #define HP_INST(T)                                                                          \
     template hipError_t launch_big_grad<T>(const NetDev &, const SlotArgs &,                \
                                            const SlotLayout &, int, hipStream_t);           \
+    template hipError_t launch_overflow_of_cells<T>(const NetDev &, char *, const SlotLayout &, \
+                                                    int, hipStream_t);                      \
     template hipError_t launch_cell_grad<T>(const NetDev &, const SlotArgs &,               \
                                             const SlotLayout &, double, bool, int, int, int, \
                                             int, int, uint32_t, hipStream_t);                              \

@@ -73,6 +73,7 @@ _SIGS = {
     "hp_set_schedule": [_P, C.c_int32, C.c_double, C.c_double, C.c_int32],
     "hp_set_lambda_ratio": [_P, C.c_int32, C.c_double],
     "hp_set_backtracking": [_P, C.c_int32, C.c_int32],
+    "hp_overflow_of_cells": [_P, C.c_int32, C.c_int32, _P, _P],
     "hp_set_scatter_policy": [_P, C.c_int32, C.c_int32, C.c_int32],
     "hp_get_scatter_policy": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
@@ -205,6 +206,14 @@ def hp_set_lambda_ratio(ctx, slot, ratio):
 
 def hp_set_backtracking(ctx, slot, on):
     _chk(lib().hp_set_backtracking(ctx, slot, int(bool(on))))
+
+
+def hp_overflow_of_cells(ctx, slot, n_counted):
+    """(numerator, overflow) of the charge of movable cells [0, n_counted) at v."""
+    num = C.c_int64()
+    ov = C.c_double()
+    _chk(lib().hp_overflow_of_cells(ctx, slot, int(n_counted), C.byref(num), C.byref(ov)))
+    return num.value, ov.value
 
 
 def hp_set_scatter_policy(ctx, netlist, regroup_every, deferred):
@@ -380,6 +389,12 @@ class Placer:
 
     def set_schedule(self, s, lambda0_scale=1e-4, decades=4.0, total_iters=1000):
         hp_set_schedule(self.ctx, s, lambda0_scale, decades, total_iters)
+
+    def overflow_of_cells(self, s, n_counted=None):
+        """Overflow of the first n_counted movable cells (default: all but the fillers)."""
+        if n_counted is None:
+            n_counted = self.nl.n_movable - getattr(self.nl, "n_fillers", 0)
+        return hp_overflow_of_cells(self.ctx, s, n_counted)
 
     def set_backtracking(self, s, on=True):
         """ePlace backtracking of the Nesterov step for slot s (see hybro.h)."""

@@ -49,6 +49,7 @@ class Netlist:
     y0: np.ndarray
     seed: int = 0
     macros: np.ndarray | None = None  # int32 ids of the movable macros, when there are any
+    n_fillers: int = 0  # the last n_fillers movable cells are fillers (charge, no pins)
 
     @property
     def n_nets(self) -> int:
@@ -255,6 +256,33 @@ def make_netlist(cfg: Config | str, seed: int = 0) -> Netlist:
         pin_ox=pin_ox, pin_oy=pin_oy, W=float(side), H=float(side), mx=M, my=M,
         x0=x0, y0=y0, seed=seed, macros=macros)
     return nl
+
+
+def with_fillers(nl: Netlist, target_density: float, seed: int = 0) -> Netlist:
+    """The netlist with ePlace filler cells for a target density below 1: pinless movable cells
+    of the standard cells' mean width and unit height, appended after the movable cells (fixed
+    ids shift up, pins follow), as many as fill target_density x (die - fixed area) minus the
+    movable area, at uniform random starting places."""
+    n = nl.n_movable
+    fixed_area = float((nl.cell_w[n:] * nl.cell_h[n:]).sum())
+    mov_area = float((nl.cell_w[:n] * nl.cell_h[:n]).sum())
+    std = np.ones(n, bool)
+    if nl.macros is not None:
+        std[nl.macros] = False
+    fw = float(_snap(nl.cell_w[:n][std].mean()))
+    room = target_density * (nl.W * nl.H - fixed_area) - mov_area
+    k = max(0, int(room // fw))
+    rng = np.random.default_rng([seed, n, k])
+    fx = _snap(rng.random(k) * (nl.W - fw)).astype(np.float32).astype(np.float64)
+    fy = _snap(rng.random(k) * (nl.H - 1.0)).astype(np.float32).astype(np.float64)
+    pin_cell = nl.pin_cell.astype(np.int64)
+    pin_cell = np.where(pin_cell >= n, pin_cell + k, pin_cell).astype(np.int32)
+    return dataclasses.replace(
+        nl, name=f"{nl.name}+fill", n_movable=n + k, n_cells=nl.n_cells + k,
+        cell_w=np.concatenate([nl.cell_w[:n], np.full(k, fw), nl.cell_w[n:]]),
+        cell_h=np.concatenate([nl.cell_h[:n], np.ones(k), nl.cell_h[n:]]),
+        pin_cell=pin_cell, x0=np.concatenate([nl.x0, fx]), y0=np.concatenate([nl.y0, fy]),
+        n_fillers=k)
 
 
 def make_small(n_movable: int, n_nets: int, bins: int, seed: int = 0, fixed: str = "macros",
