@@ -17,7 +17,9 @@ on (Sec. 3.1).  This driver uses the ePlace-style rules (a reading):
 
 Perturbations (Sec. 4.2): Gaussian moves of a fraction of the cells, Shuffle (all) of a
 fraction, Shuffle of a fraction of the macros (netlists with movable macros), or a uniform
-random restart (the Multiple-restart baseline).  Every iteration runs
+random restart (the Multiple-restart baseline).  With filler cells (a target density below 1)
+the perturbations other than the restart select among the real cells, and the stopping rule
+reads the real cells' overflow.  Every iteration runs
 on the device (hp_iterate); the host reads two integers every CHECK iterations.
 
     python -m paper_2402_18311_amd.alg1 --workload mid --rounds 5
@@ -27,6 +29,8 @@ from __future__ import annotations
 import argparse
 import json
 import time
+
+import numpy as np
 
 from . import hybro as hy
 from . import netgen
@@ -54,12 +58,19 @@ def mu_of(h: int, h_prev: int) -> float:
     return min(MU_MAX, max(MU_MIN, m))
 
 
+def _tau(pl, slot: int, st=None) -> float:
+    """Overflow at the slot's evaluation point; with filler cells, that of the real cells."""
+    if getattr(pl.nl, "n_fillers", 0):
+        return float(pl.overflow_of_cells(slot)[1])
+    return float((st or pl.state(slot))["overflow"])
+
+
 def global_place(pl, slot: int, max_iters: int) -> dict:
     """One run of the placer from the slot's current positions: returns iterations, the final
-    HPWL_q of u and the final overflow."""
+    HPWL_q of u and the final overflow (of the real cells when the netlist has fillers)."""
     nl = pl.nl
-    _, _, ov = pl.eval(slot, gamma_of(1.0, nl.bin_w), lam=0.0)  # overflow at the start
-    tau = float(ov[0])
+    pl.eval(slot, gamma_of(1.0, nl.bin_w), lam=0.0)  # overflow at the start
+    tau = _tau(pl, slot)
     h_prev = int(pl.hpwl(slot)[0])
     hy.hp_set_lambda_ratio(pl.ctx, slot, MU_MAX)
     k = 0
@@ -69,7 +80,7 @@ def global_place(pl, slot: int, max_iters: int) -> dict:
         pl.iterate(slot, gamma_of(tau, nl.bin_w), n, hpwl=True)
         k += n
         st = pl.state(slot)
-        tau = float(st["overflow"])
+        tau = _tau(pl, slot, st)
         h = int(st["hpwl_q"])
         settled = h - h_prev >= -PLATEAU * h_prev
         hy.hp_set_lambda_ratio(pl.ctx, slot, mu_of(h, h_prev))
@@ -101,6 +112,8 @@ def hybro(pl, rounds: int, mode: str = "gauss", fraction: float = 0.05, sigma_bi
             hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
             pl.set_positions(work, ix, iy)
             pool = nl.macros if mode == "shuffle-macros" else None
+            if pool is None and getattr(nl, "n_fillers", 0) and mode != "restart":
+                pool = np.arange(nl.n_movable - nl.n_fillers, dtype=np.int32)  # real cells
             pl.perturb(work, MODES[mode], fraction, sigma_bins, seed + r, want_idx=False,
                        cells=pool)
             res = global_place(pl, work, max_iters)
@@ -122,11 +135,16 @@ def main():
     ap.add_argument("--modes", default="gauss,shuffle,restart")
     ap.add_argument("--backtracking", action="store_true",
                     help="ePlace backtracking of the placer's Nesterov steps")
+    ap.add_argument("--target-density", type=float, default=1.0,
+                    help="below 1: add filler cells and stop on the real cells' overflow")
     a = ap.parse_args()
     nl = netgen.make_netlist(a.workload, a.seed)
-    pl = hy.Placer(nl, precision=32)
+    if a.target_density < 1.0:
+        nl = netgen.with_fillers(nl, a.target_density, a.seed)
+    pl = hy.Placer(nl, precision=32, target_density=a.target_density)
     out = {"workload": a.workload, "rounds": a.rounds, "max_iters": a.max_iters,
-           "backtracking": a.backtracking, "runs": []}
+           "backtracking": a.backtracking, "target_density": a.target_density,
+           "fillers": nl.n_fillers, "runs": []}
     for mode in a.modes.split(","):
         if mode == "shuffle-macros" and nl.macros is None:
             raise SystemExit(f"{a.workload} has no movable macros (try mid_mm)")
