@@ -17,9 +17,10 @@
  *     Nesterov with a Barzilai-Borwein step, a log-linear lambda ramp) are listed with the
  *     functions that implement them.
  *   - Perturbation, Alg. 1 step "Perturb" and Sec. 4.2: select p% of the cells, or of the
- *     macros only, and shuffle their locations (Shuffle (all), Shuffle); a seeded Gaussian
- *     displacement of a subset; and the fully random restart that Sec. 4.2 identifies with
- *     multiple-restart gradient descent.
+ *     macros only, and shuffle their locations (Shuffle (all), Shuffle); move each macro to
+ *     the grid position of least HPWL increment (WireMask); a seeded Gaussian displacement of
+ *     a subset; and the fully random restart that Sec. 4.2 identifies with multiple-restart
+ *     gradient descent.
  *   - Best solution, Alg. 1 return step: the candidate with the smallest HPWL.
  *
  * Integer contracts (so that the FP32 device path can be compared bit for bit):
@@ -1048,6 +1049,112 @@ int32_t orc_perturb(const orc_netlist *n, double *x, double *y, int mode, double
                     double sigma_bins, uint64_t seed, int32_t *idx)
 {
     return orc_perturb_among(n, x, y, mode, fraction, sigma_bins, seed, NULL, 0, idx);
+}
+
+/* WireMask perturbation (Alg. 1 "Perturb", Sec. 4.2): the macros, in the given order, each move
+ * to the bin-grid position with the least increment of HPWL (Eq. 1), given every other cell
+ * where it is (macros earlier in the order already moved), among the positions where the macro
+ * overlaps none of the other listed macros and no fixed cell of nonzero area.  Readings:
+ *   - candidates are lower-left corners on bin corners, (i wb, j hb), with the macro inside the
+ *     die;
+ *   - the increment is the HPWL of the macro's nets with its pins at the candidate minus their
+ *     HPWL without its pins, on the 2^-16 grid of the exact HPWL (nets whose only pins are the
+ *     macro's add a constant and are left out);
+ *   - ties go to the smaller displacement |dx| + |dy| from the macro's position, then to the
+ *     lower index j * (candidates per row) + i; a macro with no free candidate stays.
+ * Returns how many macros changed position. */
+int32_t orc_wiremask(const orc_netlist *n, double *x, double *y, const int32_t *macros,
+                     int32_t n_macros)
+{
+    int64_t bw = q16(n->W / n->mx), bh = q16(n->H / n->my), Wq = q16(n->W), Hq = q16(n->H);
+    int32_t moved = 0;
+    int64_t *X = malloc(sizeof(int64_t) * (size_t)n->mx);
+    int64_t *Y = malloc(sizeof(int64_t) * (size_t)n->my);
+    for (int k = 0; k < n_macros; ++k) {
+        int m = macros[k];
+        int64_t wq = q16(n->cell_w[m]), hq = q16(n->cell_h[m]);
+        if (wq > Wq || hq > Hq) continue;
+        int nci = (int)((Wq - wq) / bw) + 1, ncj = (int)((Hq - hq) / bh) + 1;
+        if (nci > n->mx) nci = n->mx;
+        if (ncj > n->my) ncj = n->my;
+        memset(X, 0, sizeof(int64_t) * (size_t)nci);
+        memset(Y, 0, sizeof(int64_t) * (size_t)ncj);
+        for (int e = 0; e < n->n_nets; ++e) {
+            int s = n->net_start[e], t = n->net_start[e + 1];
+            if (t - s < 2) continue;
+            int has_m = 0, has_other = 0;
+            int64_t lox = INT64_MAX, hix = INT64_MIN, loy = INT64_MAX, hiy = INT64_MIN;
+            int64_t omnx = INT64_MAX, omxx = INT64_MIN, omny = INT64_MAX, omxy = INT64_MIN;
+            for (int p = s; p < t; ++p) {
+                int c = n->pin_cell[p];
+                int64_t ox = q16(n->pin_ox[p]), oy = q16(n->pin_oy[p]);
+                if (c == m) {
+                    has_m = 1;
+                    if (ox < omnx) omnx = ox;
+                    if (ox > omxx) omxx = ox;
+                    if (oy < omny) omny = oy;
+                    if (oy > omxy) omxy = oy;
+                } else {
+                    has_other = 1;
+                    int64_t px = q16(cx(n, x, c)) + ox, py = q16(cy(n, y, c)) + oy;
+                    if (px < lox) lox = px;
+                    if (px > hix) hix = px;
+                    if (py < loy) loy = py;
+                    if (py > hiy) hiy = py;
+                }
+            }
+            if (!has_m || !has_other) continue;
+            for (int i = 0; i < nci; ++i) {
+                int64_t a = (int64_t)i * bw;
+                int64_t hi = a + omxx > hix ? a + omxx : hix, lo = a + omnx < lox ? a + omnx : lox;
+                X[i] += (hi - lo) - (hix - lox);
+            }
+            for (int j = 0; j < ncj; ++j) {
+                int64_t a = (int64_t)j * bh;
+                int64_t hi = a + omxy > hiy ? a + omxy : hiy, lo = a + omny < loy ? a + omny : loy;
+                Y[j] += (hi - lo) - (hiy - loy);
+            }
+        }
+        int64_t xm = q16(x[m]), ym = q16(y[m]);
+        int64_t b_inc = 0, b_disp = 0, b_idx = -1;
+        for (int j = 0; j < ncj; ++j) {
+            for (int i = 0; i < nci; ++i) {
+                int64_t a = (int64_t)i * bw, b = (int64_t)j * bh;
+                int legal = 1;
+                for (int k2 = 0; k2 < n_macros && legal; ++k2) {
+                    int o = macros[k2];
+                    if (o == m) continue;
+                    int64_t ox = q16(x[o]), oy = q16(y[o]), ow = q16(n->cell_w[o]), oh = q16(n->cell_h[o]);
+                    if (a < ox + ow && ox < a + wq && b < oy + oh && oy < b + hq) legal = 0;
+                }
+                for (int f = 0; f < n->n_cells - n->n_movable && legal; ++f) {
+                    int c = n->n_movable + f;
+                    if (!(n->cell_w[c] > 0.0) || !(n->cell_h[c] > 0.0)) continue;
+                    int64_t ox = q16(n->fixed_x[f]), oy = q16(n->fixed_y[f]);
+                    int64_t ow = q16(n->cell_w[c]), oh = q16(n->cell_h[c]);
+                    if (a < ox + ow && ox < a + wq && b < oy + oh && oy < b + hq) legal = 0;
+                }
+                if (!legal) continue;
+                int64_t inc = X[i] + Y[j];
+                int64_t disp = (a > xm ? a - xm : xm - a) + (b > ym ? b - ym : ym - b);
+                int64_t idx = (int64_t)j * nci + i;
+                if (b_idx < 0 || inc < b_inc || (inc == b_inc && (disp < b_disp ||
+                                                                  (disp == b_disp && idx < b_idx)))) {
+                    b_inc = inc;
+                    b_disp = disp;
+                    b_idx = idx;
+                }
+            }
+        }
+        if (b_idx < 0) continue;
+        double nx = (double)((b_idx % nci) * bw) / 65536.0, ny = (double)((b_idx / nci) * bh) / 65536.0;
+        if (nx != x[m] || ny != y[m]) moved++;
+        x[m] = nx;
+        y[m] = ny;
+    }
+    free(X);
+    free(Y);
+    return moved;
 }
 
 /* Best of Alg. 1: index of the smallest HPWL; ties go to the lowest index. */

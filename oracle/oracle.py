@@ -96,6 +96,7 @@ def lib():
             "orc_shuffle_perm": (u64, [u64, u64, u64]),
             "orc_perturb": (i32, [P, P, P, C.c_int, d, d, u64, P]),
             "orc_perturb_among": (i32, [P, P, P, C.c_int, d, d, u64, P, i32, P]),
+            "orc_wiremask": (i32, [P, P, P, P, i32]),
             "orc_argmin_i64": (i32, [P, i32]),
             "orc_num_threads": (C.c_int, []),
         }
@@ -285,6 +286,14 @@ class Oracle:
         m = self.L.orc_perturb(self.ref, _p(x), _p(y), int(mode), float(fraction),
                                float(sigma_bins), C.c_uint64(seed & (2**64 - 1)).value, _p(idx))
         return x, y, idx[:m].copy()
+
+    def wiremask(self, x, y, macros):
+        """WireMask perturbation of the listed macros, in order; returns (x, y, moved)."""
+        x = _f64(x).copy()
+        y = _f64(y).copy()
+        macros = np.ascontiguousarray(macros, dtype=np.int32)
+        moved = self.L.orc_wiremask(self.ref, _p(x), _p(y), _p(macros), len(macros))
+        return x, y, moved
 
     def perturb_among(self, x, y, mode, fraction, sigma_bins, seed, cells):
         """Perturbation restricted to the distinct movable cells `cells` (e.g. the macros)."""

@@ -269,3 +269,70 @@ def test_backtracking_first_redo_has_no_momentum(orc):
                                (u1 - st["v_prev"]) * st["alpha"] / (0.1 * nl.bin_w / np.max(
                                    np.abs(0.2 * (np.concatenate([nl.x0, nl.y0]) - t)))),
                                rtol=1e-9, atol=1e-9)
+
+
+@pytest.fixture(scope="module")
+def mm(orc):
+    nl = netgen.make_small(1000, 1100, 64, seed=1, n_fixed=6, movable_macros=True, macro_frac=0.3)
+    return nl, orc.Oracle(nl)
+
+
+def test_wiremask_single_macro_is_brute_force_hpwl_argmin(orc, mm):
+    """One macro alone: its new place is the bin-corner position that minimises the whole
+    netlist's exact HPWL (Eq. 1), found by evaluating the HPWL at every candidate, ties to the
+    smaller displacement and then the lower index."""
+    nl, o = mm
+    x0, y0 = nl.random_positions(3)
+    for m in nl.macros[:3]:
+        x, y, moved = o.wiremask(x0, y0, [m])
+        bw, bh = nl.bin_w, nl.bin_h
+        w, h = nl.cell_w[m], nl.cell_h[m]
+        nci = int((round(nl.W * 65536) - round(w * 65536)) // round(bw * 65536)) + 1
+        ncj = int((round(nl.H * 65536) - round(h * 65536)) // round(bh * 65536)) + 1
+        best = None
+        tx, ty = x0.copy(), y0.copy()
+        for j in range(ncj):
+            for i in range(nci):
+                tx[m], ty[m] = i * bw, j * bh
+                key = (o.hpwl_q(tx, ty), abs(round(i * bw * 65536) - round(x0[m] * 65536)) +
+                       abs(round(j * bh * 65536) - round(y0[m] * 65536)), j * nci + i)
+                best = key if best is None or key < best else best
+        idx = best[2]
+        assert (x[m], y[m]) == ((idx % nci) * bw, (idx // nci) * bh)
+        assert moved == int((x[m], y[m]) != (x0[m], y0[m]))
+        others = np.arange(nl.n_movable) != m
+        assert np.array_equal(x[others], x0[others]) and np.array_equal(y[others], y0[others])
+
+
+def test_wiremask_leaves_listed_macros_apart(orc, mm):
+    """All six macros in turn: none overlaps another afterwards (free places exist), every new
+    place is a bin corner inside the die, and the HPWL changes only through the macros."""
+    nl, o = mm
+    x0, y0 = nl.random_positions(5)
+    x, y, moved = o.wiremask(x0, y0, nl.macros)
+    assert moved > 0
+    ms = nl.macros
+    for a in ms:
+        assert x[a] + nl.cell_w[a] <= nl.W and y[a] + nl.cell_h[a] <= nl.H
+        assert abs(x[a] / nl.bin_w - round(x[a] / nl.bin_w)) < 1e-12
+        for b in ms:
+            if a < b:
+                assert not (x[a] < x[b] + nl.cell_w[b] and x[b] < x[a] + nl.cell_w[a] and
+                            y[a] < y[b] + nl.cell_h[b] and y[b] < y[a] + nl.cell_h[a]), (a, b)
+    rest = np.setdiff1d(np.arange(nl.n_movable), ms)
+    assert np.array_equal(x[rest], x0[rest])
+
+
+def test_wiremask_macro_without_room_stays(orc):
+    """Two listed 40 x 60 macros on a 64 x 64 die: wherever one goes it overlaps the other, so
+    neither has a free candidate and both stay."""
+    W = 64.0
+    nl = cells_only([40.0, 40.0, 1.0], [60.0, 60.0, 1.0], W, W, 16, [0.0, 20.0, 30.0],
+                    [0.0, 2.0, 30.0], nets=[[(0, 1.0, 1.0), (2, 0.5, 0.5)],
+                                            [(1, 2.0, 2.0), (2, 0.5, 0.5)]])
+    o = orc.Oracle(nl)
+    x, y, moved = o.wiremask(nl.x0, nl.y0, [0, 1])
+    assert moved == 0 and np.array_equal(x, nl.x0) and np.array_equal(y, nl.y0)
+    # with the second macro out of the list it is no obstacle, and the first one moves
+    x, y, moved = o.wiremask(nl.x0, nl.y0, [0])
+    assert moved == 1 and (x[0], y[0]) != (0.0, 0.0)
