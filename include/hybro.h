@@ -219,6 +219,18 @@ int hp_perturb_among(hp_ctx *ctx, int32_t slot, int mode, double fraction, doubl
                      uint64_t seed, const int32_t *cells, int32_t n_pool, int32_t *out_idx,
                      int32_t *out_count);
 
+/* WireMask perturbation (Sec. 4.2): the optimiser restarts at u, then the listed macros
+ * (host int32 [n_macros], distinct movable ids; the order is the order of the pass, read during
+ * the call) each move in turn to the bin-corner position with the least increment of the exact
+ * HPWL of Eq. 1 (2^-16 grid) given every other cell where it is, among the positions inside the
+ * die where the macro overlaps neither another listed macro nor a fixed cell of nonzero area;
+ * ties to the smaller displacement |dx| + |dy|, then the lower candidate index (row-major over
+ * the candidates); a macro with no free position stays.  out_moved: host, how many macros
+ * changed position, or NULL.  Three launches per macro.  An id out of range or repeated, or
+ * macros NULL with n_macros > 0: HP_EINVAL with nothing changed.  Synchronises. */
+int hp_perturb_wiremask(hp_ctx *ctx, int32_t slot, const int32_t *macros, int32_t n_macros,
+                        int32_t *out_moved);
+
 /* Exact HPWL (Eq. 1) of the slots' major solutions u on pin coordinates quantized to 2^-16:
  * out_q (host int64 [n_slots], units of 2^-16) and/or out (host double) or both NULL (the
  * value stays in the slot for hp_select_best). */

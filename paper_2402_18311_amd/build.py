@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhybro.so")
 SOURCES = ["capi.hip", "k_sweep.hip", "k_binning.hip", "k_density.hip", "k_spectral.hip",
-           "k_step.hip", "k_perturb.hip"]
+           "k_step.hip", "k_perturb.hip", "k_wiremask.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

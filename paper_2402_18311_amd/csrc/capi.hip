@@ -154,7 +154,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.part, 8 * PART_COUNT * L.pstride);
     put(L.keys, 8 * Nm);
     put(L.sel, 4 * Nm);
-    put(L.work, perturb_work_bytes((int)Nm));
+    put(L.work, perturb_work_bytes((int)Nm, d.mx, d.my));
     put(L.tile, 4 * Nm);
     put(L.sorted, 4 * Nm);
     put(L.scnt, 4 * (size_t)g.sort_blocks * g.ntiles);
@@ -586,6 +586,8 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.den1 = reinterpret_cast<const double *>(buf + B.den1);
     nd.fixed_pos = buf + B.fixed_pos;
     nd.big_ids = reinterpret_cast<const int32_t *>(buf + B.big_ids);
+    nd.fixed_xy = reinterpret_cast<const double *>(buf + B.fxy);
+    nd.fixed_wh = reinterpret_cast<const double *>(buf + B.fwh);
     HP_CHECK(launch_fixed_map<T>(nd, reinterpret_cast<const double *>(buf + B.fxy),
                                  reinterpret_cast<const double *>(buf + B.fwh),
                                  reinterpret_cast<int64_t *>(buf + B.rho_fixed), st));
@@ -1351,6 +1353,44 @@ static int perturb_impl(hp_ctx *ctx, int32_t slot, int mode, double fraction, do
     if (out_count) *out_count = (int32_t)m;
     // (a pool was read from caller memory that is only guaranteed until return)
     if (out_idx || out_count || (pool && n_pool)) HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+
+int hp_perturb_wiremask(hp_ctx *ctx, int32_t slot, const int32_t *macros, int32_t n_macros,
+                        int32_t *out_moved) {
+    Slot *s;
+    Netlist *n;
+    int rc = get_slot(ctx, slot, &s, &n);
+    if (rc) return rc;
+    const int Nm = n->nd.n_mov;
+    if (n_macros < 0 || n_macros > Nm) return fail(HP_EINVAL, "macro count out of range");
+    if (n_macros > 0 && !macros) return fail(HP_EINVAL, "macros is NULL");
+    std::vector<char> seen(Nm, 0);
+    for (int32_t j = 0; j < n_macros; ++j) {
+        const int32_t c = macros[j];
+        if (c < 0 || c >= Nm) return fail(HP_EINVAL, "a listed macro is not a movable cell");
+        if (seen[c]) return fail(HP_EINVAL, "listed macros must be distinct");
+        seen[c] = 1;
+    }
+    HP_TRY(launch_requested_hpwl(ctx, n, std::vector<Slot *>{s}));  // before u changes
+    hipStream_t st = ctx->stream;
+    if (n_macros)
+        HP_CHECK(hipMemcpyAsync(s->base + n->L.work + wiremask_pool_offset(n->nd), macros,
+                                4 * (size_t)n_macros, hipMemcpyHostToDevice, st));
+    if (ctx->precision == 32)
+        HP_CHECK(launch_wiremask<float>(n->nd, s->base, n->L, macros, n_macros, st));
+    else
+        HP_CHECK(launch_wiremask<double>(n->nd, s->base, n->L, macros, n_macros, st));
+    s->lambda_valid = false;
+    s->step_proposed = false;
+    s->step_fused = false;
+    s->since_group = -1;
+    s->hpwl_pending = false;  // the device cleared hpwl_valid
+    int64_t moved = 0;
+    HP_CHECK(hipMemcpyAsync(&moved, s->base + n->L.scal + offsetof(Scalars, sel_count), sizeof(moved),
+                            hipMemcpyDeviceToHost, st));
+    HP_CHECK(hipStreamSynchronize(st));
+    if (out_moved) *out_moved = (int32_t)moved;
     return HP_OK;
 }
 

@@ -56,6 +56,8 @@ struct NetDev {
     const double *omega;           // [mx + my] pi u / W, then pi v / H
     const double *den1;            // [mx + my] per-axis Laplacian symbol (den = dx[u] + dy[v])
     const void *fixed_pos;         // T [2][n_fixed]
+    const double *fixed_xy;        // [2][n_fixed] lower-left x..., y... of the fixed cells
+    const double *fixed_wh;        // [2][n_fixed] their widths..., heights...
     const void *cell_wh;           // T [2][n_mov] movable cell sizes
     int32_t n_cells, n_mov, n_fixed, ns, ps;
     int32_t lds_budget;            // dynamic LDS bytes a block may use on this device
@@ -251,7 +253,14 @@ template <typename T>
 hipError_t launch_perturb(const NetDev &nd, char *slot, const SlotLayout &L, int mode,
                           int64_t m, double sigma_x, double sigma_y, uint64_t seed, int n_pool,
                           hipStream_t st);
-size_t perturb_work_bytes(int n_mov);
+size_t perturb_work_bytes(int n_mov, int mx, int my);
+// WireMask perturbation of the n_pool macros `pool` (host ids, in that order), whose device
+// copy the caller put at wiremask_pool_offset of L.work (the optimiser restarts first); the
+// moved count goes to sel_count.
+template <typename T>
+hipError_t launch_wiremask(const NetDev &nd, char *base, const SlotLayout &L, const int32_t *pool,
+                           int n_pool, hipStream_t st);
+size_t wiremask_pool_offset(const NetDev &nd);
 template <typename T>
 hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumbent,
                               const SlotLayout &L, hipStream_t st);

@@ -10,6 +10,8 @@
 // permutes their centres with a
 // keyed 4-round Feistel permutation of [0, m) with cycle walking (Black & Rogaway, CT-RSA
 // 2002); UNIFORM redraws every cell.  The optimiser restarts at the result.
+#include <algorithm>
+
 #include "hp_device.h"
 
 namespace hp {
@@ -260,11 +262,26 @@ __global__ __launch_bounds__(kBlock) void shuffle_apply_kernel(NetDev nd, char *
     put<T>(base, nd, L, c, cen[2 * j] - 0.5 * (double)wh[c], cen[2 * j + 1] - 0.5 * (double)wh[nd.n_mov + c]);
 }
 
-size_t perturb_work_bytes(int n_mov) {
+size_t perturb_work_bytes(int n_mov, int mx, int my) {
     const size_t nblk = ((size_t)n_mov + kBlock - 1) / kBlock;
     const size_t a = 8 * nblk, b = 16 * (size_t)n_mov;
-    return (a > b ? a : b) + 256;
+    // WireMask: per-axis increments, per-block candidate minima, the macro list
+    const size_t cand_blocks = ((size_t)mx * my + kBlock - 1) / kBlock;
+    const size_t c = 8 * ((size_t)mx + my) + 24 * cand_blocks + 256 + 4 * (size_t)n_mov;
+    return std::max({a, b, c}) + 256;
 }
+
+// restart hook shared with the WireMask pass (k_wiremask.hip)
+template <typename T>
+hipError_t launch_perturb_restart(const NetDev &nd, char *base, const SlotLayout &L,
+                                  hipStream_t st) {
+    const int nblk = (nd.n_mov + kBlock - 1) / kBlock;
+    HP_LAUNCH("perturb_init_kernel", perturb_init_kernel<T>, dim3(nblk > 0 ? nblk : 1), dim3(kBlock), 0, st,
+              nd, base, L, 0ULL, (int64_t)0, 0);
+    return hipGetLastError();
+}
+template hipError_t launch_perturb_restart<float>(const NetDev &, char *, const SlotLayout &, hipStream_t);
+template hipError_t launch_perturb_restart<double>(const NetDev &, char *, const SlotLayout &, hipStream_t);
 
 template <typename T>
 hipError_t launch_perturb(const NetDev &nd, char *base, const SlotLayout &L, int mode, int64_t m,

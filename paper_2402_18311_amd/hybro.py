@@ -74,6 +74,7 @@ _SIGS = {
     "hp_set_lambda_ratio": [_P, C.c_int32, C.c_double],
     "hp_set_backtracking": [_P, C.c_int32, C.c_int32],
     "hp_overflow_of_cells": [_P, C.c_int32, C.c_int32, _P, _P],
+    "hp_perturb_wiremask": [_P, C.c_int32, _P, C.c_int32, _P],
     "hp_set_scatter_policy": [_P, C.c_int32, C.c_int32, C.c_int32],
     "hp_get_scatter_policy": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
@@ -206,6 +207,23 @@ def hp_set_lambda_ratio(ctx, slot, ratio):
 
 def hp_set_backtracking(ctx, slot, on):
     _chk(lib().hp_set_backtracking(ctx, slot, int(bool(on))))
+
+
+def wiremask_order(nl):
+    """The movable macros by decreasing area, ties by id (the order of the WireMask pass)."""
+    m = np.asarray(nl.macros if nl.macros is not None else [], dtype=np.int64)
+    area = nl.cell_w[m] * nl.cell_h[m]
+    return m[np.lexsort((m, -area))].astype(np.int32)
+
+
+def hp_perturb_wiremask(ctx, slot, macros):
+    """WireMask pass over `macros` (distinct movable ids, in pass order); returns the number
+    of macros that moved."""
+    macros = np.ascontiguousarray(macros, dtype=np.int32)
+    moved = C.c_int32()
+    _chk(lib().hp_perturb_wiremask(ctx, slot, _ptr(macros) if len(macros) else None, len(macros),
+                                   C.byref(moved)))
+    return moved.value
 
 
 def hp_overflow_of_cells(ctx, slot, n_counted):
@@ -389,6 +407,13 @@ class Placer:
 
     def set_schedule(self, s, lambda0_scale=1e-4, decades=4.0, total_iters=1000):
         hp_set_schedule(self.ctx, s, lambda0_scale, decades, total_iters)
+
+    def wiremask(self, s, macros=None):
+        """WireMask perturbation of slot s over `macros` (default: the netlist's movable
+        macros, largest area first, ties by id); returns how many moved."""
+        if macros is None:
+            macros = wiremask_order(self.nl)
+        return hp_perturb_wiremask(self.ctx, s, macros)
 
     def overflow_of_cells(self, s, n_counted=None):
         """Overflow of the first n_counted movable cells (default: all but the fillers)."""

@@ -1,0 +1,89 @@
+"""WireMask perturbation (Sec. 4.2) on the device against the FP64 oracle.
+
+Every decision is integer (increments, displacements and overlaps on the 2^-16 grid of the
+exact HPWL), so the macros' new places match the oracle's bit for bit, in FP64 and FP32.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_18311_amd import netgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hy():
+    from paper_2402_18311_amd import hybro
+    return hybro
+
+
+_cache = {}
+
+
+def setup(hy, orc, case, prec):
+    key = (case, prec)
+    if key not in _cache:
+        nl = {"tiny_mm": lambda: netgen.make_small(1000, 1100, 64, seed=1, n_fixed=6,
+                                                   movable_macros=True, macro_frac=0.3),
+              "small_mm": lambda: netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40,
+                                                    movable_macros=True),
+              # fixed macros as obstacles; standard cells listed as the "macros"
+              "small": lambda: netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40)}[case]()
+        _cache[key] = (nl, hy.Placer(nl, precision=prec), orc.Oracle(nl))
+    return _cache[key]
+
+
+@pytest.mark.parametrize("case,prec", [("tiny_mm", 64), ("tiny_mm", 32), ("small_mm", 32),
+                                       ("small_mm", 64)])
+@pytest.mark.parametrize("start", ["initial", "random"])
+def test_wiremask_parity(hy, orc, case, prec, start):
+    nl, pl, o = setup(hy, orc, case, prec)
+    x0, y0 = (nl.x0, nl.y0) if start == "initial" else nl.random_positions(21)
+    order = hy.wiremask_order(nl)
+    s = pl.new_slot()
+    pl.set_positions(s, x0, y0)
+    moved = pl.wiremask(s)
+    x, y = pl.positions(s)
+    rx, ry, rmoved = o.wiremask(x0, y0, order)
+    assert moved == rmoved and moved > 0
+    assert np.array_equal(np.asarray(x, np.float64), rx)
+    assert np.array_equal(np.asarray(y, np.float64), ry)
+    st = pl.state(s)
+    assert st["k"] == 0  # the optimiser restarted
+    assert pl.hpwl(s)[0] == o.hpwl_q(rx, ry)
+    pl.free_slot(s)
+
+
+def test_wiremask_fixed_obstacles_parity(hy, orc):
+    """Standard cells listed as the movable set, fixed macros in the way: the overlap test
+    against fixed cells of nonzero area, in an order that is not by area."""
+    nl, pl, o = setup(hy, orc, "small", 32)
+    pool = np.random.default_rng(4).choice(nl.n_movable, 60, replace=False).astype(np.int32)
+    s = pl.new_slot()
+    x0, y0 = nl.random_positions(2)
+    pl.set_positions(s, x0, y0)
+    moved = pl.wiremask(s, pool)
+    x, y = pl.positions(s)
+    rx, ry, rmoved = o.wiremask(x0, y0, pool)
+    assert moved == rmoved > 0
+    assert np.array_equal(np.asarray(x, np.float64), rx)
+    assert np.array_equal(np.asarray(y, np.float64), ry)
+    pl.free_slot(s)
+
+
+def test_wiremask_rejects_bad_lists(hy, orc):
+    nl, pl, o = setup(hy, orc, "tiny_mm", 64)
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    L = hy.lib()
+    import ctypes as C
+    for bad in ([1, 1], [-1], [nl.n_movable]):
+        a = np.asarray(bad, np.int32)
+        assert L.hp_perturb_wiremask(pl.ctx, s, a.ctypes.data, len(a), None) == hy.HP_EINVAL
+    assert L.hp_perturb_wiremask(pl.ctx, s, None, 2, None) == hy.HP_EINVAL
+    x, y = pl.positions(s)
+    assert np.array_equal(x, nl.x0) and np.array_equal(y, nl.y0)
+    moved = C.c_int32(-1)
+    assert L.hp_perturb_wiremask(pl.ctx, s, None, 0, C.byref(moved)) == hy.HP_OK
+    assert moved.value == 0
+    pl.free_slot(s)
