@@ -16,8 +16,8 @@ on (Sec. 3.1).  This driver uses the ePlace-style rules (a reading):
   * the decisions read only the exact integer HPWL and overflow numerator.
 
 Perturbations (Sec. 4.2): Gaussian moves of a fraction of the cells, Shuffle (all) of a
-fraction, Shuffle of a fraction of the macros (netlists with movable macros), or a uniform
-random restart (the Multiple-restart baseline).  With filler cells (a target density below 1)
+fraction, Shuffle of a fraction of the macros or WireMask over all of them (netlists with
+movable macros), or a uniform random restart (the Multiple-restart baseline).  With filler cells (a target density below 1)
 the perturbations other than the restart select among the real cells, and the stopping rule
 reads the real cells' overflow.  Every iteration runs
 on the device (hp_iterate); the host reads two integers every CHECK iterations.
@@ -44,8 +44,10 @@ DH_REF = 3.5e-3
 LAMBDA0_SCALE = 1e-4
 
 MODES = {"gauss": hy.HP_PERTURB_GAUSS, "shuffle": hy.HP_PERTURB_SHUFFLE,
-         "shuffle-macros": hy.HP_PERTURB_SHUFFLE, "restart": hy.HP_PERTURB_UNIFORM}
-FRACTIONS = {"gauss": 0.05, "shuffle": 0.5, "shuffle-macros": 0.5, "restart": 1.0}
+         "shuffle-macros": hy.HP_PERTURB_SHUFFLE, "restart": hy.HP_PERTURB_UNIFORM,
+         "wiremask": None}
+FRACTIONS = {"gauss": 0.05, "shuffle": 0.5, "shuffle-macros": 0.5, "restart": 1.0,
+             "wiremask": 1.0}
 
 
 def gamma_of(tau: float, bin_w: float) -> float:
@@ -111,11 +113,14 @@ def hybro(pl, rounds: int, mode: str = "gauss", fraction: float = 0.05, sigma_bi
         for r in range(rounds):
             hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
             pl.set_positions(work, ix, iy)
-            pool = nl.macros if mode == "shuffle-macros" else None
-            if pool is None and getattr(nl, "n_fillers", 0) and mode != "restart":
-                pool = np.arange(nl.n_movable - nl.n_fillers, dtype=np.int32)  # real cells
-            pl.perturb(work, MODES[mode], fraction, sigma_bins, seed + r, want_idx=False,
-                       cells=pool)
+            if mode == "wiremask":  # every macro, largest first (no fraction, no seed)
+                pl.wiremask(work)
+            else:
+                pool = nl.macros if mode == "shuffle-macros" else None
+                if pool is None and getattr(nl, "n_fillers", 0) and mode != "restart":
+                    pool = np.arange(nl.n_movable - nl.n_fillers, dtype=np.int32)  # real cells
+                pl.perturb(work, MODES[mode], fraction, sigma_bins, seed + r, want_idx=False,
+                           cells=pool)
             res = global_place(pl, work, max_iters)
             won = pl.select_best([work], inc)
             best = min(best, res["hpwl_q"])
@@ -146,7 +151,7 @@ def main():
            "backtracking": a.backtracking, "target_density": a.target_density,
            "fillers": nl.n_fillers, "runs": []}
     for mode in a.modes.split(","):
-        if mode == "shuffle-macros" and nl.macros is None:
+        if mode in ("shuffle-macros", "wiremask") and nl.macros is None:
             raise SystemExit(f"{a.workload} has no movable macros (try mid_mm)")
         frac = FRACTIONS[mode]
         t0 = time.perf_counter()

@@ -54,7 +54,7 @@ static bool q16_exact(double v) {
 struct NetBuf {
     size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
         cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh,
-        big_ids, total;
+        big_ids, cell_pin_net, total;
 };
 
 NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
@@ -88,6 +88,7 @@ NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     put(b.fxy, 16 * Nf);
     put(b.fwh, 16 * Nf);
     put(b.big_ids, 4 * Nm);
+    put(b.cell_pin_net, 4 * P);
     b.total = o;
     return b;
 }
@@ -423,11 +424,15 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     for (int q = 0; q < ps; ++q)
         if (h_pc[q] >= 0 && h_pc[q] < Nm) h_cps[h_pc[q] + 1]++;
     for (int i = 0; i < Nm; ++i) h_cps[i + 1] += h_cps[i];
-    std::vector<int32_t> h_cp(h_cps[Nm]);
+    std::vector<int32_t> h_cp(h_cps[Nm]), h_cpn(h_cps[Nm]);
     {
         std::vector<int32_t> fill(h_cps.begin(), h_cps.end() - 1);
-        for (int q = 0; q < ps; ++q)
-            if (h_pc[q] >= 0 && h_pc[q] < Nm) h_cp[fill[h_pc[q]]++] = q;
+        for (int e = 0; e < ns; ++e)  // the sweep net of each of those pin slots
+            for (int q = h_ns[e]; q < h_ns[e + 1]; ++q)
+                if (h_pc[q] >= 0 && h_pc[q] < Nm) {
+                    h_cpn[fill[h_pc[q]]] = e;
+                    h_cp[fill[h_pc[q]]++] = q;
+                }
     }
 
     // per-cell charge constants (2^-12 / 2^-16 integers, computed in FP64 once)
@@ -549,6 +554,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     if (any_w) HP_CHECK(up(B.net_w, h_w.data(), sizeof(T) * h_w.size()));
     HP_CHECK(up(B.cell_pin_start, h_cps.data(), 4 * h_cps.size()));
     HP_CHECK(up(B.cell_pins, h_cp.data(), 4 * h_cp.size()));
+    HP_CHECK(up(B.cell_pin_net, h_cpn.data(), 4 * h_cpn.size()));
     HP_CHECK(up(B.cq, h_cq.data(), 4 * h_cq.size()));
     HP_CHECK(up(B.rq, h_rq.data(), 4 * h_rq.size()));
     HP_CHECK(up(B.cstep, h_cs.data(), sizeof(T) * h_cs.size()));
@@ -586,6 +592,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.den1 = reinterpret_cast<const double *>(buf + B.den1);
     nd.fixed_pos = buf + B.fixed_pos;
     nd.big_ids = reinterpret_cast<const int32_t *>(buf + B.big_ids);
+    nd.cell_pin_net = reinterpret_cast<const int32_t *>(buf + B.cell_pin_net);
     nd.fixed_xy = reinterpret_cast<const double *>(buf + B.fxy);
     nd.fixed_wh = reinterpret_cast<const double *>(buf + B.fwh);
     HP_CHECK(launch_fixed_map<T>(nd, reinterpret_cast<const double *>(buf + B.fxy),

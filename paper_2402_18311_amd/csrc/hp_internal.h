@@ -47,6 +47,7 @@ struct NetDev {
     const void *net_w;             // T [ns] or nullptr (all weights 1)
     const int32_t *cell_pin_start; // [n_mov + 1]
     const int32_t *cell_pins;      // sweep-order pins of each movable cell
+    const int32_t *cell_pin_net;   // the sweep-order net of each of those pins
     const int4 *cq;                // [n_mov] (w'q, h'q, dxq, dyq) in 2^-12
     const int32_t *rq;             // [n_mov] charge scale in 2^-16
     const void *cstep;             // T [4][n_mov]: pins, area, x max, y max

@@ -10,11 +10,12 @@
 //   max(hi, a + omax) - min(lo, a + omin) - (hi - lo),
 // so the mask over the nci x ncj candidates is X[i] + Y[j] with X and Y sums over m's nets.
 // Per macro three launches on one stream:
-//   wm_mask_kernel   one block: m's pins in chunks of 256 (a lane per pin slot; the lane of
-//                    the first slot of each net scans the net), then X[i] and Y[j] over the
-//                    chunk's nets, all in int64 (exact, order-free);
+//   wm_mask_kernel   one block of 16 waves: m's pins 16 at a time, a wave scanning each pin's
+//                    net (a net counts at the first of m's pins in it), then X[i] and Y[j]
+//                    over those nets, all in int64 (exact, order-free);
 //   wm_cand_kernel   a lane per candidate: the overlap test against the listed macros and the
-//                    fixed cells, the key (increment, displacement, index), block minimum;
+//                    fixed cells that meet the area the block's candidates span (staged in
+//                    LDS), the key (increment, displacement, index), block minimum;
 //   wm_pick_kernel   one block: the minimum of the block minima; the macro moves there (u, v
 //                    and v_prev), and the moved count in the slot's scalars goes up.
 #include "hp_device.h"
@@ -81,87 +82,104 @@ __device__ __forceinline__ void cell_q16(const NetDev &nd, const vec2<T> *u, int
     }
 }
 
+__device__ __forceinline__ int64_t wave_min64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (int64_t)__shfl_xor((long long)v, o));
+    return v;
+}
+__device__ __forceinline__ int64_t wave_max64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (int64_t)__shfl_xor((long long)v, o));
+    return v;
+}
+
+constexpr int kMaskWaves = 16;  // nets of the macro scanned at once, one wave each
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void wm_mask_kernel(NetDev nd, char *base, SlotLayout L, int m) {
-    // per net of the chunk: other pins' extent and m's offsets, both axes (valid: has others)
-    __shared__ int64_t lox[kBlock], hix[kBlock], omnx[kBlock], omxx[kBlock];
-    __shared__ int64_t loy[kBlock], hiy[kBlock], omny[kBlock], omxy[kBlock];
-    __shared__ int valid[kBlock];
+__global__ __launch_bounds__(64 * kMaskWaves) void wm_mask_kernel(NetDev nd, char *base, SlotLayout L,
+                                                                  int m) {
+    // per net of the round: other pins' extent and m's offsets, both axes (valid: a first
+    // occurrence of the net among m's pins, with pins of other cells)
+    __shared__ int64_t tup[kMaskWaves][8];
+    __shared__ int valid[kMaskWaves];
     const WmScratch S = wm_scratch(nd, base, L);
     const WmGeom G = wm_geom<T>(nd, m);
     const vec2<T> *u = reinterpret_cast<const vec2<T> *>(base + L.u);
-    for (int i = threadIdx.x; i < G.nci; i += kBlock) S.X[i] = 0;
-    for (int j = threadIdx.x; j < G.ncj; j += kBlock) S.Y[j] = 0;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nt = 64 * kMaskWaves;
+    for (int i = threadIdx.x; i < G.nci; i += nt) S.X[i] = 0;
+    for (int j = threadIdx.x; j < G.ncj; j += nt) S.Y[j] = 0;
     const int p0 = nd.cell_pin_start[m], p1 = nd.cell_pin_start[m + 1];
-    for (int c0 = p0; c0 < p1; c0 += kBlock) {
-        const int t = threadIdx.x;
-        valid[t] = 0;
-        if (c0 + t < p1) {
-            const int slot = nd.cell_pins[c0 + t];
-            // the net holding this pin slot: the last e with net_start[e] <= slot
-            int a = 0, b = nd.ns;
-            while (b - a > 1) {
-                const int mid = (a + b) >> 1;
-                if (nd.net_start[mid] <= slot) a = mid; else b = mid;
-            }
-            const int s0 = nd.net_start[a], s1 = nd.net_start[a + 1];
-            bool first = true;
-            for (int q = s0; q < slot && first; ++q) first = nd.pin_cell[q] != m;
-            if (first) {
-                int64_t lx = INT64_MAX, hx = INT64_MIN, ly = INT64_MAX, hy = INT64_MIN;
-                int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
-                bool other = false;
-                for (int q = s0; q < s1; ++q) {
-                    const int c = nd.pin_cell[q];
-                    if (c < 0) continue;  // padding of the net's slot range
-                    const int2 o = nd.pin_offq[q];
-                    if (c == m) {
-                        mnx = min(mnx, (int64_t)o.x);
-                        mxx = max(mxx, (int64_t)o.x);
-                        mny = min(mny, (int64_t)o.y);
-                        mxy = max(mxy, (int64_t)o.y);
-                    } else {
-                        int64_t cx, cy;
-                        cell_q16<T>(nd, u, c, cx, cy);
-                        lx = min(lx, cx + o.x);
-                        hx = max(hx, cx + o.x);
-                        ly = min(ly, cy + o.y);
-                        hy = max(hy, cy + o.y);
-                        other = true;
-                    }
-                }
-                if (other) {
-                    lox[t] = lx;
-                    hix[t] = hx;
-                    omnx[t] = mnx;
-                    omxx[t] = mxx;
-                    loy[t] = ly;
-                    hiy[t] = hy;
-                    omny[t] = mny;
-                    omxy[t] = mxy;
-                    valid[t] = 1;
+    for (int c0 = p0; c0 < p1; c0 += kMaskWaves) {
+        if (c0 + w < p1) {  // wave-uniform
+            const int slot = nd.cell_pins[c0 + w], e = nd.cell_pin_net[c0 + w];
+            const int s0 = nd.net_start[e], s1 = nd.net_start[e + 1];
+            int64_t lx = INT64_MAX, hx = INT64_MIN, ly = INT64_MAX, hy = INT64_MIN;
+            int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
+            int dup = 0, other = 0;
+            for (int q = s0 + lane; q < s1; q += 64) {
+                const int c = nd.pin_cell[q];
+                if (c < 0) continue;  // padding of the net's slot range
+                const int2 o = nd.pin_offq[q];
+                if (c == m) {
+                    dup |= q < slot;  // m has an earlier pin in this net: that one counts it
+                    mnx = min(mnx, (int64_t)o.x);
+                    mxx = max(mxx, (int64_t)o.x);
+                    mny = min(mny, (int64_t)o.y);
+                    mxy = max(mxy, (int64_t)o.y);
+                } else {
+                    int64_t cx, cy;
+                    cell_q16<T>(nd, u, c, cx, cy);
+                    lx = min(lx, cx + o.x);
+                    hx = max(hx, cx + o.x);
+                    ly = min(ly, cy + o.y);
+                    hy = max(hy, cy + o.y);
+                    other = 1;
                 }
             }
+            lx = wave_min64(lx);
+            hx = wave_max64(hx);
+            ly = wave_min64(ly);
+            hy = wave_max64(hy);
+            mnx = wave_min64(mnx);
+            mxx = wave_max64(mxx);
+            mny = wave_min64(mny);
+            mxy = wave_max64(mxy);
+            dup = __any(dup);
+            other = __any(other);
+            if (lane == 0) {
+                tup[w][0] = lx;
+                tup[w][1] = hx;
+                tup[w][2] = mnx;
+                tup[w][3] = mxx;
+                tup[w][4] = ly;
+                tup[w][5] = hy;
+                tup[w][6] = mny;
+                tup[w][7] = mxy;
+                valid[w] = !dup && other;
+            }
+        } else if (lane == 0) {
+            valid[w] = 0;
         }
         __syncthreads();
-        const int nk = min(kBlock, p1 - c0);
-        for (int i = threadIdx.x; i < G.nci; i += kBlock) {
+        for (int i = threadIdx.x; i < G.nci; i += nt) {
             const int64_t a = (int64_t)i * G.bw;
             int64_t acc = 0;
-            for (int k = 0; k < nk; ++k) {
+#pragma unroll 4
+            for (int k = 0; k < kMaskWaves; ++k) {
                 if (!valid[k]) continue;
-                const int64_t hi = max(hix[k], a + omxx[k]), lo = min(lox[k], a + omnx[k]);
-                acc += (hi - lo) - (hix[k] - lox[k]);
+                const int64_t hi = max(tup[k][1], a + tup[k][3]), lo = min(tup[k][0], a + tup[k][2]);
+                acc += (hi - lo) - (tup[k][1] - tup[k][0]);
             }
             S.X[i] += acc;
         }
-        for (int j = threadIdx.x; j < G.ncj; j += kBlock) {
+        for (int j = threadIdx.x; j < G.ncj; j += nt) {
             const int64_t a = (int64_t)j * G.bh;
             int64_t acc = 0;
-            for (int k = 0; k < nk; ++k) {
+#pragma unroll 4
+            for (int k = 0; k < kMaskWaves; ++k) {
                 if (!valid[k]) continue;
-                const int64_t hi = max(hiy[k], a + omxy[k]), lo = min(loy[k], a + omny[k]);
-                acc += (hi - lo) - (hiy[k] - loy[k]);
+                const int64_t hi = max(tup[k][5], a + tup[k][7]), lo = min(tup[k][4], a + tup[k][6]);
+                acc += (hi - lo) - (tup[k][5] - tup[k][4]);
             }
             S.Y[j] += acc;
         }
@@ -200,40 +218,87 @@ __device__ void block_min_key(int64_t &inc, int64_t &disp, int64_t &idx) {
     idx = rx[0];
 }
 
+constexpr int kObstChunk = 512;  // obstacle rectangles staged in LDS at a time
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void wm_cand_kernel(NetDev nd, char *base, SlotLayout L, int m,
                                                          int n_pool) {
+    __shared__ int64_t ob[4][kObstChunk];  // x, y, x + w, y + h of the kept obstacles (q16)
+    __shared__ int n_kept;
     const WmScratch S = wm_scratch(nd, base, L);
     const WmGeom G = wm_geom<T>(nd, m);
     const vec2<T> *u = reinterpret_cast<const vec2<T> *>(base + L.u);
     const T *wh = reinterpret_cast<const T *>(nd.cell_wh);
+    const int64_t ncand = (int64_t)G.nci * G.ncj;
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = c < ncand;
+    const int i = live ? (int)(c % G.nci) : 0, j = live ? (int)(c / G.nci) : 0;
+    const int64_t a = (int64_t)i * G.bw, b = (int64_t)j * G.bh;
+    bool legal = live;
+    // the area the block's candidates can cover: an obstacle outside it is dropped (legality
+    // is an AND over obstacles, so the order in which the kept ones are staged is immaterial)
+    int64_t bx0 = 0, bx1 = 0, by0 = 0, by1 = 0;
+    {
+        const int64_t c0 = (int64_t)blockIdx.x * kBlock;
+        const int64_t c1 = min(c0 + kBlock, ncand) - 1;
+        if (c1 >= c0) {
+            const int j0 = (int)(c0 / G.nci), j1 = (int)(c1 / G.nci);
+            const int i0 = j0 == j1 ? (int)(c0 % G.nci) : 0;
+            const int i1 = j0 == j1 ? (int)(c1 % G.nci) : G.nci - 1;
+            bx0 = (int64_t)i0 * G.bw;
+            bx1 = (int64_t)i1 * G.bw + G.wq;
+            by0 = (int64_t)j0 * G.bh;
+            by1 = (int64_t)j1 * G.bh + G.hq;
+        }
+    }
+    // obstacles: the other listed macros, then the fixed cells of nonzero area (a zero-area
+    // rectangle overlaps nothing, so those are staged as empty)
+    const int n_obst = n_pool + nd.n_fixed;
+    for (int k0 = 0; k0 < n_obst; k0 += kObstChunk) {
+        __syncthreads();
+        if (threadIdx.x == 0) n_kept = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < kObstChunk && k0 + k < n_obst; k += kBlock) {
+            const int kk = k0 + k;
+            int64_t ox = 0, oy = 0, ow = 0, oh = 0;
+            if (kk < n_pool) {
+                const int o = S.pool[kk];
+                if (o != m) {
+                    cell_q16<T>(nd, u, o, ox, oy);
+                    ow = q16d((double)wh[o]);
+                    oh = q16d((double)wh[nd.n_mov + o]);
+                }
+            } else {
+                const int f = kk - n_pool;
+                const double fw = nd.fixed_wh[f], fh = nd.fixed_wh[nd.n_fixed + f];
+                if (fw > 0.0 && fh > 0.0) {
+                    ox = q16d(nd.fixed_xy[f]);
+                    oy = q16d(nd.fixed_xy[nd.n_fixed + f]);
+                    ow = q16d(fw);
+                    oh = q16d(fh);
+                }
+            }
+            // keep a nonempty obstacle that meets the block's area
+            if (ow > 0 && oh > 0 && bx0 < ox + ow && ox < bx1 && by0 < oy + oh && oy < by1) {
+                const int at = atomicAdd(&n_kept, 1);
+                ob[0][at] = ox;
+                ob[1][at] = oy;
+                ob[2][at] = ox + ow;
+                ob[3][at] = oy + oh;
+            }
+        }
+        __syncthreads();
+        const int nk = n_kept;
+        for (int k = 0; k < nk && legal; ++k)
+            legal = !(a < ob[2][k] && ob[0][k] < a + G.wq && b < ob[3][k] && ob[1][k] < b + G.hq);
+    }
     int64_t inc = 0, disp = 0, idx = -1;
-    if (c < (int64_t)G.nci * G.ncj) {
-        const int i = (int)(c % G.nci), j = (int)(c / G.nci);
-        const int64_t a = (int64_t)i * G.bw, b = (int64_t)j * G.bh;
-        bool legal = true;
-        for (int k = 0; k < n_pool && legal; ++k) {
-            const int o = S.pool[k];
-            if (o == m) continue;
-            int64_t ox, oy;
-            cell_q16<T>(nd, u, o, ox, oy);
-            const int64_t ow = q16d((double)wh[o]), oh = q16d((double)wh[nd.n_mov + o]);
-            legal = !(a < ox + ow && ox < a + G.wq && b < oy + oh && oy < b + G.hq);
-        }
-        for (int f = 0; f < nd.n_fixed && legal; ++f) {
-            const double fw = nd.fixed_wh[f], fh = nd.fixed_wh[nd.n_fixed + f];
-            if (!(fw > 0.0) || !(fh > 0.0)) continue;
-            const int64_t ox = q16d(nd.fixed_xy[f]), oy = q16d(nd.fixed_xy[nd.n_fixed + f]);
-            legal = !(a < ox + q16d(fw) && ox < a + G.wq && b < oy + q16d(fh) && oy < b + G.hq);
-        }
-        if (legal) {
-            int64_t xm, ym;
-            cell_q16<T>(nd, u, m, xm, ym);
-            inc = S.X[i] + S.Y[j];
-            disp = (a > xm ? a - xm : xm - a) + (b > ym ? b - ym : ym - b);
-            idx = c;
-        }
+    if (legal) {
+        int64_t xm, ym;
+        cell_q16<T>(nd, u, m, xm, ym);
+        inc = S.X[i] + S.Y[j];
+        disp = (a > xm ? a - xm : xm - a) + (b > ym ? b - ym : ym - b);
+        idx = c;
     }
     block_min_key(inc, disp, idx);
     if (threadIdx.x == 0) {
@@ -284,7 +349,8 @@ hipError_t launch_wiremask(const NetDev &nd, char *base, const SlotLayout &L, co
     const int nblk = (int)wm_cand_blocks(nd);
     for (int k = 0; k < n_pool; ++k) {
         const int m = pool[k];
-        HP_LAUNCH("wm_mask_kernel", wm_mask_kernel<T>, dim3(1), dim3(kBlock), 0, st, nd, base, L, m);
+        HP_LAUNCH("wm_mask_kernel", wm_mask_kernel<T>, dim3(1), dim3(64 * kMaskWaves), 0, st, nd, base,
+                  L, m);
         HP_LAUNCH("wm_cand_kernel", wm_cand_kernel<T>, dim3(nblk), dim3(kBlock), 0, st, nd, base, L, m,
                   n_pool);
         HP_LAUNCH("wm_pick_kernel", wm_pick_kernel<T>, dim3(1), dim3(kBlock), 0, st, nd, base, L, m, nblk);

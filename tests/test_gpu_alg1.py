@@ -48,6 +48,22 @@ def test_alg1_shuffle_macros_matches_oracle_fp64(orc):
     pl.close()
 
 
+def test_alg1_wiremask_rounds_keep_invariants():
+    """Hybro-WireMask on the 20 k-cell netlist with 40 movable macros: every round starts from
+    the WireMask pass over the incumbent, the best HPWL never rises and is the smallest round
+    result."""
+    from paper_2402_18311_amd import alg1, hybro
+    nl = netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40, movable_macros=True)
+    pl = hybro.Placer(nl, precision=32)
+    res = alg1.hybro(pl, 2, "wiremask", 1.0, 0.0, seed=0, max_iters=400)
+    tr = res["trace"]
+    bests = [t["best_hpwl_q"] for t in tr]
+    assert all(b1 <= b0 for b0, b1 in zip(bests, bests[1:]))
+    assert bests[-1] == min(t["hpwl_q"] for t in tr)
+    print([(t["iters"], t["hpwl_q"] / 65536, t.get("kept")) for t in tr])
+    pl.close()
+
+
 def test_alg1_invariants_mid():
     """mid in FP32: the best HPWL never rises, equals the smallest round result, and every
     placement stops at the overflow target or the iteration cap."""
