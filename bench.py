@@ -116,10 +116,12 @@ def sources_hash(files=FRONT_SOURCES):
     return h.hexdigest()[:16]
 
 
-def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel"):
+def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel", last=None):
     """Per-launch HBM traffic of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for the 256 MiB
-    calibration copy of the same run (--copy-calibration).  Writes TRAFFIC_FILE."""
+    calibration copy of the same run (--copy-calibration).  With `last`, the average is over
+    the kernel's last `last` dispatches (the timed round of the profiled run) and the average
+    over all of them is recorded beside it.  Writes TRAFFIC_FILE."""
     import csv
     import glob
 
@@ -131,18 +133,21 @@ def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel"):
                 continue
             v = float(r["Counter_Value"])
             if kernel in r["Kernel_Name"]:
-                vals.append(v)
+                vals.append((int(r.get("Dispatch_Id") or r.get("Correlation_Id") or 0), v))
             elif "copyBuffer" in r["Kernel_Name"]:
                 calib.append(v)
-        return sum(vals) / len(vals), max(calib), len(vals)
+        vals = [v for _, v in sorted(vals)]
+        tail = vals[-last:] if last else vals
+        return sum(tail) / len(tail), max(calib), len(tail), sum(vals) / len(vals)
 
-    fe, fc, n1 = load(fetch_dir, "FETCH_SIZE")
-    wr, wc, n2 = load(write_dir, "WRITE_SIZE")
+    fe, fc, n1, fe_all = load(fetch_dir, "FETCH_SIZE")
+    wr, wc, n2, wr_all = load(write_dir, "WRITE_SIZE")
     kib = CALIB_BYTES / 1024
     ff, wf = kib / fc, kib / wc
     traffic = (fe * ff + wr * wf) * 1024
     rec = {"kernel": kernel, "workload": "mid", "fetch_kib_per_launch": round(fe, 1),
            "write_kib_per_launch": round(wr, 1), "launches": [n1, n2],
+           "all_launches_fetch_write_kib": [round(fe_all, 1), round(wr_all, 1)],
            "calibration_copy_kib": [round(fc, 1), round(wc, 1)],
            "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
            "traffic_bytes_per_launch": int(traffic), "sources_hash": sources_hash()}
@@ -302,6 +307,8 @@ def main():
                     help="jobs of the serving-mix trace (0 skips it)")
     ap.add_argument("--batch", type=int, default=32,
                     help="restarts of the batched-round measurement (0 skips it)")
+    ap.add_argument("--pmc-last", type=int, default=None,
+                    help="with --pmc-summary: average the kernel's last N dispatches only")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc output folders to the stored traffic "
                          "record and exit")
@@ -313,7 +320,7 @@ def main():
                          "dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary)
+        pmc_summary(*args.pmc_summary, last=args.pmc_last)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the placer runs on a single MI355X; "
