@@ -87,3 +87,28 @@ def test_wiremask_rejects_bad_lists(hy, orc):
     assert L.hp_perturb_wiremask(pl.ctx, s, None, 0, C.byref(moved)) == hy.HP_OK
     assert moved.value == 0
     pl.free_slot(s)
+
+
+def test_wiremask_mid_mm_fp32_equals_fp64_and_separates(hy, orc):
+    """The full-size pass (500 macros on 512^2 bins; the oracle is too slow there): every
+    decision is an integer one, so FP32 and FP64 move every macro to the same place, and the
+    macros end apart."""
+    nl = netgen.make_netlist("mid_mm", 0)
+    res = {}
+    for prec in (32, 64):
+        pl = hy.Placer(nl, precision=prec)
+        s = pl.new_slot()
+        pl.set_positions(s, nl.x0, nl.y0)
+        moved = pl.wiremask(s)
+        x, y = pl.positions(s)
+        res[prec] = (moved, np.asarray(x, np.float64), np.asarray(y, np.float64), pl.hpwl(s)[0])
+        pl.close()
+    assert res[32][0] == res[64][0] > 0 and res[32][3] == res[64][3]
+    assert np.array_equal(res[32][1], res[64][1]) and np.array_equal(res[32][2], res[64][2])
+    m = nl.macros
+    x, y = res[64][1][m], res[64][2][m]
+    w, h = nl.cell_w[m], nl.cell_h[m]
+    ov = ((x[:, None] < x[None, :] + w[None, :]) & (x[None, :] < x[:, None] + w[:, None]) &
+          (y[:, None] < y[None, :] + h[None, :]) & (y[None, :] < y[:, None] + h[:, None]))
+    np.fill_diagonal(ov, False)
+    assert not ov.any()
