@@ -116,24 +116,41 @@ __global__ __launch_bounds__(64 * kMaskWaves) void wm_mask_kernel(NetDev nd, cha
             int64_t lx = INT64_MAX, hx = INT64_MIN, ly = INT64_MAX, hy = INT64_MIN;
             int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
             int dup = 0, other = 0;
-            for (int q = s0 + lane; q < s1; q += 64) {
-                const int c = nd.pin_cell[q];
-                if (c < 0) continue;  // padding of the net's slot range
-                const int2 o = nd.pin_offq[q];
-                if (c == m) {
-                    dup |= q < slot;  // m has an earlier pin in this net: that one counts it
-                    mnx = min(mnx, (int64_t)o.x);
-                    mxx = max(mxx, (int64_t)o.x);
-                    mny = min(mny, (int64_t)o.y);
-                    mxy = max(mxy, (int64_t)o.y);
-                } else {
-                    int64_t cx, cy;
-                    cell_q16<T>(nd, u, c, cx, cy);
-                    lx = min(lx, cx + o.x);
-                    hx = max(hx, cx + o.x);
-                    ly = min(ly, cy + o.y);
-                    hy = max(hy, cy + o.y);
-                    other = 1;
+            // four slots per lane and round, their loads (on clamped, in-range indices) all in
+            // flight before any is used
+            for (int q0 = s0 + lane; q0 < s1; q0 += 256) {
+                int cc[4];
+                int2 oo[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int q = min(q0 + 64 * k, s1 - 1);
+                    cc[k] = q0 + 64 * k < s1 ? nd.pin_cell[q] : -1;
+                    oo[k] = nd.pin_offq[q];
+                }
+                int64_t px[4], py[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = cc[k] < 0 ? m : cc[k];
+                    cell_q16<T>(nd, u, c, px[k], py[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = cc[k];
+                    if (c < 0) continue;  // padding of the net's slot range, or past its end
+                    const int2 o = oo[k];
+                    if (c == m) {
+                        dup |= q0 + 64 * k < slot;  // an earlier pin of m in this net counts it
+                        mnx = min(mnx, (int64_t)o.x);
+                        mxx = max(mxx, (int64_t)o.x);
+                        mny = min(mny, (int64_t)o.y);
+                        mxy = max(mxy, (int64_t)o.y);
+                    } else {
+                        lx = min(lx, px[k] + o.x);
+                        hx = max(hx, px[k] + o.x);
+                        ly = min(ly, py[k] + o.y);
+                        hy = max(hy, py[k] + o.y);
+                        other = 1;
+                    }
                 }
             }
             lx = wave_min64(lx);
