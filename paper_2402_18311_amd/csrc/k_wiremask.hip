@@ -10,9 +10,9 @@
 //   max(hi, a + omax) - min(lo, a + omin) - (hi - lo),
 // so the mask over the nci x ncj candidates is X[i] + Y[j] with X and Y sums over m's nets.
 // Per macro three launches on one stream:
-//   wm_mask_kernel   one block of 16 waves: m's pins 16 at a time, a wave scanning each pin's
-//                    net (a net counts at the first of m's pins in it), then X[i] and Y[j]
-//                    over those nets, all in int64 (exact, order-free);
+//   wm_mask_kernel   a wave per pin of m over the grid, scanning the pin's net (a net counts
+//                    at the first of m's pins in it) and adding its increments to X[i] and Y[j]
+//                    with int64 atomics (exact, order-free);
 //   wm_cand_kernel   a lane per candidate: the overlap test against the listed macros and the
 //                    fixed cells that meet the area the block's candidates span (staged in
 //                    LDS), the key (increment, displacement, index), block minimum;
@@ -93,114 +93,90 @@ __device__ __forceinline__ int64_t wave_max64(int64_t v) {
     return v;
 }
 
-constexpr int kMaskWaves = 16;  // nets of the macro scanned at once, one wave each
+constexpr int kMaskBlocks = 128;  // waves over the macro's pins: kMaskBlocks * kBlock / 64
 
+// X and Y start at zero for each macro: zeroed once before the pass, and by the pick kernel
+// after each macro's candidates have read them.
+__global__ __launch_bounds__(kBlock) void wm_zero_kernel(NetDev nd, char *base, SlotLayout L) {
+    const WmScratch S = wm_scratch(nd, base, L);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nd.mx + nd.my; i += gridDim.x * kBlock)
+        S.X[i] = 0;  // X and Y are adjacent
+}
+
+// A wave per pin of macro m (all of m's pins at once over the grid): the wave scans the pin's
+// net four slots per lane and round (a net counts at the first of m's pins in it), reduces the
+// other pins' extent and m's offsets, and adds the net's increment at every candidate column
+// and row to X and Y with int64 atomics (exact and order-free).
 template <typename T>
-__global__ __launch_bounds__(64 * kMaskWaves) void wm_mask_kernel(NetDev nd, char *base, SlotLayout L,
-                                                                  int m) {
-    // per net of the round: other pins' extent and m's offsets, both axes (valid: a first
-    // occurrence of the net among m's pins, with pins of other cells)
-    __shared__ int64_t tup[kMaskWaves][8];
-    __shared__ int valid[kMaskWaves];
+__global__ __launch_bounds__(kBlock) void wm_mask_kernel(NetDev nd, char *base, SlotLayout L, int m) {
     const WmScratch S = wm_scratch(nd, base, L);
     const WmGeom G = wm_geom<T>(nd, m);
     const vec2<T> *u = reinterpret_cast<const vec2<T> *>(base + L.u);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nt = 64 * kMaskWaves;
-    for (int i = threadIdx.x; i < G.nci; i += nt) S.X[i] = 0;
-    for (int j = threadIdx.x; j < G.ncj; j += nt) S.Y[j] = 0;
+    const int lane = threadIdx.x & 63;
+    const int gw = (blockIdx.x * kBlock + threadIdx.x) >> 6, nw = gridDim.x * (kBlock / 64);
     const int p0 = nd.cell_pin_start[m], p1 = nd.cell_pin_start[m + 1];
-    for (int c0 = p0; c0 < p1; c0 += kMaskWaves) {
-        if (c0 + w < p1) {  // wave-uniform
-            const int slot = nd.cell_pins[c0 + w], e = nd.cell_pin_net[c0 + w];
-            const int s0 = nd.net_start[e], s1 = nd.net_start[e + 1];
-            int64_t lx = INT64_MAX, hx = INT64_MIN, ly = INT64_MAX, hy = INT64_MIN;
-            int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
-            int dup = 0, other = 0;
-            // four slots per lane and round, their loads (on clamped, in-range indices) all in
-            // flight before any is used
-            for (int q0 = s0 + lane; q0 < s1; q0 += 256) {
-                int cc[4];
-                int2 oo[4];
+    for (int pi = p0 + gw; pi < p1; pi += nw) {  // wave-uniform
+        const int slot = nd.cell_pins[pi], e = nd.cell_pin_net[pi];
+        const int s0 = nd.net_start[e], s1 = nd.net_start[e + 1];
+        int64_t lx = INT64_MAX, hx = INT64_MIN, ly = INT64_MAX, hy = INT64_MIN;
+        int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
+        int dup = 0, other = 0;
+        // four slots per lane and round, their loads (on clamped, in-range indices) all in
+        // flight before any is used
+        for (int q0 = s0 + lane; q0 < s1; q0 += 256) {
+            int cc[4];
+            int2 oo[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int q = min(q0 + 64 * k, s1 - 1);
-                    cc[k] = q0 + 64 * k < s1 ? nd.pin_cell[q] : -1;
-                    oo[k] = nd.pin_offq[q];
-                }
-                int64_t px[4], py[4];
+            for (int k = 0; k < 4; ++k) {
+                const int q = min(q0 + 64 * k, s1 - 1);
+                cc[k] = q0 + 64 * k < s1 ? nd.pin_cell[q] : -1;
+                oo[k] = nd.pin_offq[q];
+            }
+            int64_t px[4], py[4];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = cc[k] < 0 ? m : cc[k];
-                    cell_q16<T>(nd, u, c, px[k], py[k]);
-                }
+            for (int k = 0; k < 4; ++k) {
+                const int c = cc[k] < 0 ? m : cc[k];
+                cell_q16<T>(nd, u, c, px[k], py[k]);
+            }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = cc[k];
-                    if (c < 0) continue;  // padding of the net's slot range, or past its end
-                    const int2 o = oo[k];
-                    if (c == m) {
-                        dup |= q0 + 64 * k < slot;  // an earlier pin of m in this net counts it
-                        mnx = min(mnx, (int64_t)o.x);
-                        mxx = max(mxx, (int64_t)o.x);
-                        mny = min(mny, (int64_t)o.y);
-                        mxy = max(mxy, (int64_t)o.y);
-                    } else {
-                        lx = min(lx, px[k] + o.x);
-                        hx = max(hx, px[k] + o.x);
-                        ly = min(ly, py[k] + o.y);
-                        hy = max(hy, py[k] + o.y);
-                        other = 1;
-                    }
+            for (int k = 0; k < 4; ++k) {
+                const int c = cc[k];
+                if (c < 0) continue;  // padding of the net's slot range, or past its end
+                const int2 o = oo[k];
+                if (c == m) {
+                    dup |= q0 + 64 * k < slot;  // an earlier pin of m in this net counts it
+                    mnx = min(mnx, (int64_t)o.x);
+                    mxx = max(mxx, (int64_t)o.x);
+                    mny = min(mny, (int64_t)o.y);
+                    mxy = max(mxy, (int64_t)o.y);
+                } else {
+                    lx = min(lx, px[k] + o.x);
+                    hx = max(hx, px[k] + o.x);
+                    ly = min(ly, py[k] + o.y);
+                    hy = max(hy, py[k] + o.y);
+                    other = 1;
                 }
             }
-            lx = wave_min64(lx);
-            hx = wave_max64(hx);
-            ly = wave_min64(ly);
-            hy = wave_max64(hy);
-            mnx = wave_min64(mnx);
-            mxx = wave_max64(mxx);
-            mny = wave_min64(mny);
-            mxy = wave_max64(mxy);
-            dup = __any(dup);
-            other = __any(other);
-            if (lane == 0) {
-                tup[w][0] = lx;
-                tup[w][1] = hx;
-                tup[w][2] = mnx;
-                tup[w][3] = mxx;
-                tup[w][4] = ly;
-                tup[w][5] = hy;
-                tup[w][6] = mny;
-                tup[w][7] = mxy;
-                valid[w] = !dup && other;
-            }
-        } else if (lane == 0) {
-            valid[w] = 0;
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < G.nci; i += nt) {
+        lx = wave_min64(lx);
+        hx = wave_max64(hx);
+        ly = wave_min64(ly);
+        hy = wave_max64(hy);
+        mnx = wave_min64(mnx);
+        mxx = wave_max64(mxx);
+        mny = wave_min64(mny);
+        mxy = wave_max64(mxy);
+        if (__any(dup) || !__any(other)) continue;  // wave-uniform
+        for (int i = lane; i < G.nci; i += 64) {
             const int64_t a = (int64_t)i * G.bw;
-            int64_t acc = 0;
-#pragma unroll 4
-            for (int k = 0; k < kMaskWaves; ++k) {
-                if (!valid[k]) continue;
-                const int64_t hi = max(tup[k][1], a + tup[k][3]), lo = min(tup[k][0], a + tup[k][2]);
-                acc += (hi - lo) - (tup[k][1] - tup[k][0]);
-            }
-            S.X[i] += acc;
+            const int64_t d = (max(hx, a + mxx) - min(lx, a + mnx)) - (hx - lx);
+            if (d) atomicAdd(reinterpret_cast<unsigned long long *>(&S.X[i]), (unsigned long long)d);
         }
-        for (int j = threadIdx.x; j < G.ncj; j += nt) {
+        for (int j = lane; j < G.ncj; j += 64) {
             const int64_t a = (int64_t)j * G.bh;
-            int64_t acc = 0;
-#pragma unroll 4
-            for (int k = 0; k < kMaskWaves; ++k) {
-                if (!valid[k]) continue;
-                const int64_t hi = max(tup[k][5], a + tup[k][7]), lo = min(tup[k][4], a + tup[k][6]);
-                acc += (hi - lo) - (tup[k][5] - tup[k][4]);
-            }
-            S.Y[j] += acc;
+            const int64_t d = (max(hy, a + mxy) - min(ly, a + mny)) - (hy - ly);
+            if (d) atomicAdd(reinterpret_cast<unsigned long long *>(&S.Y[j]), (unsigned long long)d);
         }
-        __syncthreads();
     }
 }
 
@@ -339,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void wm_pick_kernel(NetDev nd, char *base, 
             idx = S.part[2 * nb + k];
         }
     block_min_key(inc, disp, idx);
+    for (int k = threadIdx.x; k < nd.mx + nd.my; k += kBlock) S.X[k] = 0;  // for the next macro
     if (threadIdx.x != 0 || idx < 0) return;
     const WmGeom G = wm_geom<T>(nd, m);
     const T nx = (T)((double)((idx % G.nci) * G.bw) / 65536.0);
@@ -364,9 +341,10 @@ hipError_t launch_wiremask(const NetDev &nd, char *base, const SlotLayout &L, co
     hipError_t e = launch_perturb_restart<T>(nd, base, L, st);  // also zeroes the moved count
     if (e != hipSuccess) return e;
     const int nblk = (int)wm_cand_blocks(nd);
+    HP_LAUNCH("wm_zero_kernel", wm_zero_kernel, dim3(8), dim3(kBlock), 0, st, nd, base, L);
     for (int k = 0; k < n_pool; ++k) {
         const int m = pool[k];
-        HP_LAUNCH("wm_mask_kernel", wm_mask_kernel<T>, dim3(1), dim3(64 * kMaskWaves), 0, st, nd, base,
+        HP_LAUNCH("wm_mask_kernel", wm_mask_kernel<T>, dim3(kMaskBlocks), dim3(kBlock), 0, st, nd, base,
                   L, m);
         HP_LAUNCH("wm_cand_kernel", wm_cand_kernel<T>, dim3(nblk), dim3(kBlock), 0, st, nd, base, L, m,
                   n_pool);
