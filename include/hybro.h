@@ -112,7 +112,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
 int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device);
 int hp_get_eval_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device);
 
-/* lambda schedule of Eq. 2 ("small at the beginning", Sec. 3): at the first evaluation after
+/* lambda schedule of Eq. 2 (it starts small, Sec. 3): at the first evaluation after
  * hp_set_positions / hp_perturb, lambda_0 = lambda0_scale * |grad WL|_1 / |grad N|_1; every
  * Nesterov step multiplies it by 10^(decades / total_iters).  Defaults: 1e-4, 4, 1000. */
 int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double decades,

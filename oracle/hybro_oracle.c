@@ -17,7 +17,7 @@
  *     Nesterov with a Barzilai-Borwein step, a log-linear lambda ramp) are listed with the
  *     functions that implement them.
  *   - Perturbation, Alg. 1 step "Perturb" and Sec. 4.2: select p% of the cells, or of the
- *     macros only, and shuffle their locations (Shuffle (all), Shuffle); move each macro to
+ *     macros only, and exchange their places (Shuffle (all), Shuffle); move each macro to
  *     the grid position of least HPWL increment (WireMask); a seeded Gaussian displacement of
  *     a subset; and the fully random restart that Sec. 4.2 identifies with multiple-restart
  *     gradient descent.
@@ -701,7 +701,7 @@ void orc_eval(const orc_netlist *n, const double *x, const double *y, const orc_
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Preconditioned Nesterov step (the "classical gradient descent" of Sec. 3.1, in ePlace's
+/* Preconditioned Nesterov step (the gradient descent of Sec. 3.1, in ePlace's
  * accelerated form).  State over the 2*n_movable coordinates (x block then y block):
  *   u (major solution), v (reference point where the gradient is taken), v_prev, gp_prev
  *   (preconditioned gradient at v_prev), a (momentum), alpha (last step length), k.
@@ -914,7 +914,7 @@ void orc_place(const orc_netlist *n, const orc_place_params *pp, double *x, doub
  * Random numbers: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) used as a counter-based
  * generator: draw i of stream `seed` is mix64(seed + (i + 1) * 0x9e3779b97f4a7c15).
  * Subset: the m = floor(p * n_movable + 1/2) movable cells with the smallest (key_i, i).
- * SHUFFLE ("shuffle their locations"): the selected cells, in ascending index order
+ * SHUFFLE (the selected cells exchange places): the selected cells, in ascending index order
  *   S[0..m-1], exchange centres by a keyed permutation pi of [0, m): S[j] takes the centre of
  *   S[pi(j)].  pi is a 4-round balanced Feistel network on the smallest even bit width
  *   covering m, with cycle walking back into [0, m) (Black & Rogaway, CT-RSA 2002).
