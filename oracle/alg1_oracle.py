@@ -32,11 +32,22 @@ def _mu(h, h_prev):
     return min(1.05, max(0.95, m))
 
 
-def place_to_convergence(o, nl, x, y, max_iters):
-    """Returns the final (x, y) of the major solution, iterations run, HPWL_q and overflow."""
+def place_to_convergence(o, nl, x, y, max_iters, real=None):
+    """Returns the final (x, y) of the major solution, iterations run, HPWL_q and overflow.
+    With `real` = (oracle of the netlist without its filler cells, target density), the
+    overflow the rules read is that of the real cells (the first movable cells) alone."""
     n = nl.n_movable
     st = o.new_state(x, y)
-    tau = o.eval(st["v"][:n], st["v"][n:], _gamma(1.0, nl.bin_w))["overflow"]
+
+    def real_tau(r):
+        if real is None:
+            return r["overflow"]
+        o_real, rho_t = real
+        k = o_real.nl.n_movable
+        rm, rf = o_real.density_q(st["v"][:k], st["v"][n:n + k])
+        return o_real.overflow(rm, rf, rho_t)[0]
+
+    tau = real_tau(o.eval(st["v"][:n], st["v"][n:], _gamma(1.0, nl.bin_w)))
     h_prev = o.hpwl_q(st["u"][:n], st["u"][n:])
     lam, ratio, k = None, 1.05, 0
     level = False
@@ -50,8 +61,10 @@ def place_to_convergence(o, nl, x, y, max_iters):
                 lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum()
             o.nesterov_step(lam, gw + lam * gd, st)
             lam *= ratio
-            tau = r["overflow"]
+            tau = real_tau(r) if real is None else None
             k += 1
+        if real is not None:  # the real cells' overflow at v, where the next evaluation is taken
+            tau = real_tau(None)
         h = o.hpwl_q(st["u"][:n], st["u"][n:])
         level = h - h_prev >= -0.001 * h_prev
         ratio = _mu(h, h_prev)
@@ -59,17 +72,18 @@ def place_to_convergence(o, nl, x, y, max_iters):
     return st["u"][:n].copy(), st["u"][n:].copy(), k, h_prev, tau
 
 
-def hybro(o, nl, rounds, mode, fraction, sigma_bins, seed, max_iters, pool=None):
+def hybro(o, nl, rounds, mode, fraction, sigma_bins, seed, max_iters, pool=None, real=None):
     """Per-round trace: iterations, HPWL_q of the round's placement, best HPWL_q so far.  With
-    `pool` (e.g. the movable macros) the perturbation selects among those cells only."""
-    bx, by, k, best, tau = place_to_convergence(o, nl, nl.x0, nl.y0, max_iters)
+    `pool` (e.g. the movable macros, or the real cells beside fillers) the perturbation selects
+    among those cells only; `real` as in place_to_convergence."""
+    bx, by, k, best, tau = place_to_convergence(o, nl, nl.x0, nl.y0, max_iters, real)
     trace = [(k, best, best)]
     for r in range(rounds):
         if pool is None:
             px, py, _ = o.perturb(bx, by, mode, fraction, sigma_bins, seed + r)
         else:
             px, py, _ = o.perturb_among(bx, by, mode, fraction, sigma_bins, seed + r, pool)
-        x, y, k, h, tau = place_to_convergence(o, nl, px, py, max_iters)
+        x, y, k, h, tau = place_to_convergence(o, nl, px, py, max_iters, real)
         if h < best:
             bx, by, best = x, y, h
         trace.append((k, h, best))

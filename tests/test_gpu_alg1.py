@@ -48,6 +48,31 @@ def test_alg1_shuffle_macros_matches_oracle_fp64(orc):
     pl.close()
 
 
+@pytest.mark.parametrize("mode,frac", [("shuffle", 0.5), ("gauss", 0.05)])
+def test_alg1_with_fillers_matches_oracle_fp64(orc, mode, frac):
+    """Filler cells at target density 0.9 on the tiny netlist in FP64: the device driver reads
+    the real cells' overflow and perturbs real cells only; the oracle driver, given the
+    filler-free netlist for that overflow and the real cells as the pool, takes the same
+    iterations and reaches the same HPWL round by round."""
+    import numpy as np
+    from oracle import alg1_oracle
+    from paper_2402_18311_amd import alg1, hybro
+    real = netgen.make_netlist("tiny", 0)
+    nl = netgen.with_fillers(real, 0.9, seed=2)
+    pl = hybro.Placer(nl, precision=64, target_density=0.9)
+    res = alg1.hybro(pl, 2, mode, frac, 8.0, seed=13, max_iters=200)
+    o = orc.Oracle(nl)
+    pool = np.arange(real.n_movable, dtype=np.int32)
+    ref = alg1_oracle.hybro(o, nl, 2, alg1.MODES[mode], frac, 8.0, 13, 200, pool=pool,
+                            real=(orc.Oracle(real), 0.9))
+    for t, (k, h, best) in zip(res["trace"], ref):
+        print(mode, t["iters"], k, t["hpwl_q"], h, round(t["overflow"], 4))
+        assert t["iters"] == k
+        assert abs(t["hpwl_q"] - h) <= 1e-6 * h
+        assert abs(t["best_hpwl_q"] - best) <= 1e-6 * best
+    pl.close()
+
+
 def test_alg1_wiremask_rounds_keep_invariants():
     """Hybro-WireMask on the 20 k-cell netlist with 40 movable macros: every round starts from
     the WireMask pass over the incumbent, the best HPWL never rises and is the smallest round
