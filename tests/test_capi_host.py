@@ -58,3 +58,29 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(hybro, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         hybro.lib()
+
+
+def test_header_is_plain_c_and_sizes_match_binding(tmp_path):
+    """include/hybro.h compiles as pedantic C99 on its own, and its struct sizes are the
+    binding's."""
+    import shutil
+    import subprocess
+    from paper_2402_18311_amd import hybro
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "h.c"
+    src.write_text('#include <stdio.h>\n#include "hybro.h"\nint main(void) {\n'
+                   '  printf("%zu %zu %zu %zu %zu\\n", sizeof(hp_die), sizeof(hp_shape),\n'
+                   '         sizeof(hp_eval_params), sizeof(hp_slot_state), sizeof(hp_iter_params));\n'
+                   '  return 0;\n}\n')
+    exe = tmp_path / "h"
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    sizes = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                            check=True).stdout.split()]
+    assert sizes == [C.sizeof(hybro.hp_die), C.sizeof(hybro.hp_shape),
+                     C.sizeof(hybro.hp_eval_params), C.sizeof(hybro.hp_slot_state),
+                     C.sizeof(hybro.hp_iter_params)]
