@@ -21,7 +21,7 @@
 // phases and per-axis symbols (tables built on the host in FP64) to LDS.
 //
 // With M <= 1024 each pass has only M/2 blocks (one per CU or fewer), so a block's latency is
-// the pass's time: blocks are wide (1024 threads for R1, 512 for C and R2) and every global
+// the pass's time: blocks are wide (1024 threads in every pass) and every global
 // load of a block, tables included, is issued before the first one is waited for.
 #include "hp_device.h"
 
@@ -240,7 +240,7 @@ __host__ __device__ inline size_t cols_lds(int M) {
            2 * al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
 }
 
-constexpr int kColsThreads = 512;
+constexpr int kColsThreads = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L,
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa
 
 // ---- R2 ---------------------------------------------------------------------------------
 // lds: tw [M/2] | ph [M] | stage [nst][2][M] | work [nst][M]
-constexpr int kRowsInvThreads = 512;
+constexpr int kRowsInvThreads = 1024;
 
 template <typename T>
 __global__ __launch_bounds__(kRowsInvThreads) void spec_rows_inv(NetDev nd, SlotArgs sa,
