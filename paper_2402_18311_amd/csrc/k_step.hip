@@ -199,18 +199,21 @@ __global__ __launch_bounds__(kBlock) void step_scalars_kernel(NetDev nd, SlotArg
 }
 
 // Totals of the step's three reductions over the cell-gradient pass's n partials, formed by
-// one block (every thread gets them): thread t takes partials t, t + 256, ... of the three
-// arrays in one pass, then the wave butterflies and the tree of block_sum / block_max.
+// one block of NT threads (every thread gets them): thread t takes partials t, t + NT, ... of
+// the three arrays in one pass, then the wave butterflies and a pairwise tree over the waves.
+// red: >= 3 * NT / 64 doubles.
+template <int NT>
 __device__ __forceinline__ void step_totals(const double *part, const SlotLayout &L, int n,
                                             double *red, double &DV, double &DG, double &GM) {
+    constexpr int W = NT / 64;
     const double *pv = part + PART_DV * L.pstride, *pg = part + PART_DG * L.pstride;
     const double *pm = part + PART_GMAX * L.pstride;
     double v = 0.0, g = 0.0, m = 0.0;
-    for (int i = threadIdx.x; i < n; i += 4 * kBlock) {
+    for (int i = threadIdx.x; i < n; i += 4 * NT) {
         double a[4], b[4], c[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int j = i + u * kBlock;
+            const int j = i + u * NT;
             a[u] = j < n ? pv[j] : 0.0;
             b[u] = j < n ? pg[j] : 0.0;
             c[u] = j < n ? pm[j] : 0.0;
@@ -228,14 +231,32 @@ __device__ __forceinline__ void step_totals(const double *part, const SlotLayout
     if ((threadIdx.x & 63) == 0) {
         const int w = threadIdx.x >> 6;
         red[w] = v;
-        red[4 + w] = g;
-        red[8 + w] = m;
+        red[W + w] = g;
+        red[2 * W + w] = m;
     }
     __syncthreads();
-    DV = (red[0] + red[1]) + (red[2] + red[3]);
-    DG = (red[4] + red[5]) + (red[6] + red[7]);
-    GM = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
+    double qv[W], qg[W], qm[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        qv[k] = red[k];
+        qg[k] = red[W + k];
+        qm[k] = red[2 * W + k];
+    }
+#pragma unroll
+    for (int h = W / 2; h > 0; h >>= 1)
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+            qv[k] += qv[k + h];
+            qg[k] += qg[k + h];
+            qm[k] = fmax(qm[k], qm[k + h]);
+        }
+    DV = qv[0];
+    DG = qg[0];
+    GM = qm[0];
 }
+
+constexpr int kStepThreads = 1024;  // cells per block of the update (fewer blocks, each of
+                                    // which reduces the step's partials itself)
 
 // u' = clamp(v - alpha g~), v' = clamp(u' + coef (u' - u)); v_prev = v, g~_prev = g~ (and
 // u_prev = u with backtracking on).  A redo (a rejected step under backtracking) instead
@@ -247,13 +268,13 @@ __device__ __forceinline__ void step_totals(const double *part, const SlotLayout
 // for an accepted step, multiplies lambda by the schedule's ratio; no block reads what that
 // thread writes.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                             int fused, int nc, uint32_t banks) {
+__global__ __launch_bounds__(kStepThreads) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                                   int fused, int nc, uint32_t banks) {
     char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const int b = (banks >> blockIdx.y) & 1u;
     const int n = nd.n_mov;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = blockIdx.x * kStepThreads + threadIdx.x;
     // the cell's own inputs first (clamped index), so that their loads are in flight while a
     // fused step reduces the partials
     const int ic = i < n ? i : max(n - 1, 0);  // the launcher skips n = 0
@@ -266,9 +287,10 @@ __global__ __launch_bounds__(kBlock) void step_update_kernel(NetDev nd, SlotArgs
     const T c0 = cs[ic], c1 = cs[(size_t)n + ic], hx = cs[(size_t)2 * n + ic], hy = cs[(size_t)3 * n + ic];
     StepProposal pr;
     if (fused) {
-        __shared__ double red[12];
+        __shared__ double red[3 * kStepThreads / 64];
         double DV, DG, GM;
-        step_totals(reinterpret_cast<const double *>(base + L.part), L, nc, red, DV, DG, GM);
+        step_totals<kStepThreads>(reinterpret_cast<const double *>(base + L.part), L, nc, red, DV,
+                                  DG, GM);
         pr = propose_from_bank(sc, b, DV, DG, GM, nd.wb);
     } else {
         pr.alpha = sc->step_alpha;
@@ -406,8 +428,9 @@ hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nc, sa.n), dim3(kBlock), 0, st, nd, sa,
-              L, (int)fused, nc, banks);
+    const int nu = (nd.n_mov + kStepThreads - 1) / kStepThreads;
+    HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nu, sa.n), dim3(kStepThreads), 0, st, nd,
+              sa, L, (int)fused, nc, banks);
     return hipGetLastError();
 }
 
