@@ -21,8 +21,9 @@
 // phases and per-axis symbols (tables built on the host in FP64) to LDS.
 //
 // With M <= 1024 each pass has only M/2 blocks (one per CU or fewer), so a block's latency is
-// the pass's time: blocks are wide (1024 threads in every pass) and every global
-// load of a block, tables included, is issued before the first one is waited for.
+// the pass's time: blocks are wide (1024 threads; 512 for C and R2 in launches with more
+// blocks than CUs) and every global load of a block, tables included, is issued before the
+// first one is waited for.
 #include "hp_device.h"
 
 namespace hp {
@@ -240,12 +241,11 @@ __host__ __device__ inline size_t cols_lds(int M) {
            2 * al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
 }
 
-constexpr int kColsThreads = 1024;
-
-template <typename T>
-__global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                          int want_psi) {
-    constexpr int NT = kColsThreads;
+// C and R2 run 1024-thread blocks when a launch has at most one block per CU (a single slot:
+// the block's latency is the pass's time), 512-thread blocks when it has more (batched slots:
+// smaller blocks interleave better); see spectral_threads.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L, int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.my, logM = nd.logmy, mx = nd.mx;
     size_t o = 0;
@@ -365,12 +365,9 @@ __global__ __launch_bounds__(kColsThreads) void spec_cols(NetDev nd, SlotArgs sa
 
 // ---- R2 ---------------------------------------------------------------------------------
 // lds: tw [M/2] | ph [M] | stage [nst][2][M] | work [nst][M]
-constexpr int kRowsInvThreads = 1024;
-
-template <typename T>
-__global__ __launch_bounds__(kRowsInvThreads) void spec_rows_inv(NetDev nd, SlotArgs sa,
-                                                                 SlotLayout L, int want_psi) {
-    constexpr int NT = kRowsInvThreads;
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nd, SlotArgs sa, SlotLayout L,
+                                                    int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int M = nd.mx, logM = nd.logmx;
     const int nst = want_psi ? 3 : 2;
@@ -470,6 +467,11 @@ static size_t rows_inv_lds(const NetDev &nd, int nst) {
            al16(sizeof(T) * (size_t)nst * 2 * nd.mx) + sizeof(vec2<T>) * (size_t)nst * nd.mx;
 }
 
+// 1024-thread C and R2 blocks while a launch has at most one block per CU
+static bool wide_spectral(const NetDev &nd, const SlotArgs &sa) {
+    return (size_t)std::max(nd.mx, nd.my) / 2 * sa.n <= 256;
+}
+
 template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st) {
@@ -478,13 +480,22 @@ hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayou
               rows_fwd_lds<T>(nd), st, nd, sa, L, lpb, (int)keep_maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("spec_cols", spec_cols<T>, dim3(nd.mx / 2, sa.n), dim3(kColsThreads), cols_lds<T>(nd.my),
-              st, nd, sa, L, (int)want_psi);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const int nst = want_psi ? 3 : 2;
-    HP_LAUNCH("spec_rows_inv", spec_rows_inv<T>, dim3(nd.my / 2, sa.n), dim3(kRowsInvThreads),
-              rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
+    if (wide_spectral(nd, sa)) {
+        HP_LAUNCH("spec_cols", (spec_cols<T, 1024>), dim3(nd.mx / 2, sa.n), dim3(1024),
+                  cols_lds<T>(nd.my), st, nd, sa, L, (int)want_psi);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 1024>), dim3(nd.my / 2, sa.n), dim3(1024),
+                  rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
+    } else {
+        HP_LAUNCH("spec_cols", (spec_cols<T, 512>), dim3(nd.mx / 2, sa.n), dim3(512),
+                  cols_lds<T>(nd.my), st, nd, sa, L, (int)want_psi);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 512>), dim3(nd.my / 2, sa.n), dim3(512),
+                  rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
+    }
     return hipGetLastError();
 }
 
@@ -502,11 +513,13 @@ hipError_t spectral_prepare(int bytes) {
     hipError_t e = hipFuncSetAttribute((const void *)spec_rows_fwd<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)spec_cols<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)spec_rows_inv<T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *fs[4] = {(const void *)spec_cols<T, 512>, (const void *)spec_cols<T, 1024>,
+                         (const void *)spec_rows_inv<T, 512>, (const void *)spec_rows_inv<T, 1024>};
+    for (const void *f : fs) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #define HP_INST(T)                                                                            \
