@@ -32,6 +32,32 @@ def _mu(h, h_prev):
     return min(1.05, max(0.95, m))
 
 
+def _plateau(h, h_prev):
+    """The HPWL has stopped falling: it fell by at most 0.1% of its previous value, or rose."""
+    return h - h_prev >= -0.001 * h_prev
+
+
+def _stop(tau, level):
+    """Stop once the overflow is at most 0.10 and the HPWL has stopped falling."""
+    return tau <= 0.10 and level
+
+
+def schedule_loop(block, tau0, h0, max_iters, bin_w):
+    """The placer's control loop.  block(gamma, ratio, n) runs n placer iterations with
+    smoothing gamma, multiplying lambda by ratio after every step, and returns the exact HPWL
+    of the major solution and the overflow after them.  Looks happen every 10 iterations (the
+    last block may be shorter, at the cap); returns (iterations, last HPWL, last overflow)."""
+    tau, h_prev, ratio, k, level = tau0, h0, 1.05, 0, False
+    while k < max_iters and not _stop(tau, level):
+        n = min(10, max_iters - k)
+        h, tau = block(_gamma(tau, bin_w), ratio, n)
+        k += n
+        level = _plateau(h, h_prev)
+        ratio = _mu(h, h_prev)
+        h_prev = h
+    return k, h_prev, tau
+
+
 def place_to_convergence(o, nl, x, y, max_iters, real=None):
     """Returns the final (x, y) of the major solution, iterations run, HPWL_q and overflow.
     With `real` = (oracle of the netlist without its filler cells, target density), the
@@ -47,29 +73,28 @@ def place_to_convergence(o, nl, x, y, max_iters, real=None):
         rm, rf = o_real.density_q(st["v"][:k], st["v"][n:n + k])
         return o_real.overflow(rm, rf, rho_t)[0]
 
-    tau = real_tau(o.eval(st["v"][:n], st["v"][n:], _gamma(1.0, nl.bin_w)))
-    h_prev = o.hpwl_q(st["u"][:n], st["u"][n:])
-    lam, ratio, k = None, 1.05, 0
-    level = False
-    while k < max_iters and not (tau <= 0.10 and level):
-        g = _gamma(tau, nl.bin_w)
-        for _ in range(min(10, max_iters - k)):
+    lam = [None]
+
+    def block(g, ratio, steps):
+        tau = None
+        for _ in range(steps):
             r = o.eval(st["v"][:n], st["v"][n:], g)
             gw = np.concatenate([r["gwx"], r["gwy"]])
             gd = np.concatenate([r["gdx"], r["gdy"]])
-            if lam is None:
-                lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum()
-            o.nesterov_step(lam, gw + lam * gd, st)
-            lam *= ratio
-            tau = real_tau(r) if real is None else None
-            k += 1
+            if lam[0] is None:
+                lam[0] = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum()
+            o.nesterov_step(lam[0], gw + lam[0] * gd, st)
+            lam[0] *= ratio
+            if real is None:
+                tau = r["overflow"]
         if real is not None:  # the real cells' overflow at v, where the next evaluation is taken
             tau = real_tau(None)
-        h = o.hpwl_q(st["u"][:n], st["u"][n:])
-        level = h - h_prev >= -0.001 * h_prev
-        ratio = _mu(h, h_prev)
-        h_prev = h
-    return st["u"][:n].copy(), st["u"][n:].copy(), k, h_prev, tau
+        return o.hpwl_q(st["u"][:n], st["u"][n:]), tau
+
+    tau0 = real_tau(o.eval(st["v"][:n], st["v"][n:], _gamma(1.0, nl.bin_w)))
+    h0 = o.hpwl_q(st["u"][:n], st["u"][n:])
+    k, h, tau = schedule_loop(block, tau0, h0, max_iters, nl.bin_w)
+    return st["u"][:n].copy(), st["u"][n:].copy(), k, h, tau
 
 
 def hybro(o, nl, rounds, mode, fraction, sigma_bins, seed, max_iters, pool=None, real=None):

@@ -31,6 +31,7 @@
  * OpenMP is used only on loops whose iterations own disjoint outputs; every floating-point
  * sum is accumulated serially in a fixed order, so results do not depend on the thread count.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -480,6 +481,117 @@ void orc_dct2(int mx, int my, const double *rho, double *a)
     free(t);
 }
 
+/* ---- FFT path of the same transforms (for timing; cross-checked against the sums above) ----
+ * fft_inplace: X_k = sum_n x_n exp(sign 2 pi i k n / n_len), n_len a power of two (iterative
+ * radix-2 decimation in time: bit-reversal permutation, then butterflies of doubling span).
+ * dct_makhoul: X_u = sum_j x_j cos(pi u (2 j + 1) / (2 M)) by Makhoul's reordering (IEEE
+ *   Trans. ASSP 1980): v_n = x_{2n}, v_{M-1-n} = x_{2n+1}, V = FFT_M(v), X_u = Re(e^{-i pi u/(2M)} V_u).
+ * synth_fft: z_j = sum_{u<M} A_u e^{i pi u (2 j + 1)/(2 M)} as the 2M-point inverse DFT of
+ *   A_u e^{i pi u/(2M)} padded with M zeros; Re z_j is the cosine synthesis, Im z_j the sine
+ *   synthesis sum_u A_u sin(pi u (2 j + 1)/(2 M)). */
+static void fft_inplace(double complex *x, int n, int sign)
+{
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j |= bit;
+        if (i < j) {
+            double complex t = x[i];
+            x[i] = x[j];
+            x[j] = t;
+        }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        for (int i = 0; i < n; i += len)
+            for (int k = 0; k < len / 2; ++k) {
+                double ang = sign * 2.0 * M_PI * k / len;
+                double complex w = cos(ang) + I * sin(ang);
+                double complex a = x[i + k], b = x[i + k + len / 2] * w;
+                x[i + k] = a + b;
+                x[i + k + len / 2] = a - b;
+            }
+    }
+}
+
+static void dct_makhoul(const double *x, int M, double *X, double complex *work)
+{
+    for (int n = 0; n < M / 2; ++n) {
+        work[n] = x[2 * n];
+        work[M - 1 - n] = x[2 * n + 1];
+    }
+    if (M == 1) work[0] = x[0];
+    fft_inplace(work, M, -1);
+    for (int u = 0; u < M; ++u) {
+        double ang = -M_PI * u / (2.0 * M);
+        X[u] = creal((cos(ang) + I * sin(ang)) * work[u]);
+    }
+}
+
+static void synth_fft(const double *A, int M, int want_sin, double *y, double complex *work)
+{
+    for (int u = 0; u < M; ++u) {
+        double ang = M_PI * u / (2.0 * M);
+        work[u] = A[u] * (cos(ang) + I * sin(ang));
+        work[M + u] = 0.0;
+    }
+    fft_inplace(work, 2 * M, +1);
+    for (int j = 0; j < M; ++j) y[j] = want_sin ? cimag(work[j]) : creal(work[j]);
+}
+
+/* a_uv of orc_dct2, rows then columns through dct_makhoul. */
+void orc_dct2_fft(int mx, int my, const double *rho, double *a)
+{
+    double *t = malloc(sizeof(double) * (size_t)mx * my);
+#pragma omp parallel
+    {
+        double *in = malloc(sizeof(double) * (size_t)(mx > my ? mx : my));
+        double *out = malloc(sizeof(double) * (size_t)(mx > my ? mx : my));
+        double complex *w = malloc(sizeof(double complex) * (size_t)(mx > my ? mx : my));
+#pragma omp for
+        for (int k = 0; k < my; ++k) dct_makhoul(rho + (size_t)k * mx, mx, t + (size_t)k * mx, w);
+#pragma omp for
+        for (int u = 0; u < mx; ++u) {
+            for (int k = 0; k < my; ++k) in[k] = t[(size_t)k * mx + u];
+            dct_makhoul(in, my, out, w);
+            for (int v = 0; v < my; ++v)
+                a[(size_t)v * mx + u] = (u ? 2.0 : 1.0) * (v ? 2.0 : 1.0) / ((double)mx * my) * out[v];
+        }
+        free(in);
+        free(out);
+        free(w);
+    }
+    free(t);
+}
+
+/* out_kj = sum_{u,v} A_vu Bx(u, j) By(v, k) (as synth2) through synth_fft: rows, then columns. */
+static void synth2_fft(int mx, int my, const double *A, int sin_x, int sin_y, double *out)
+{
+    double *s = malloc(sizeof(double) * (size_t)mx * my);
+#pragma omp parallel
+    {
+        int mm = mx > my ? mx : my;
+        double *in = malloc(sizeof(double) * (size_t)mm);
+        double *o = malloc(sizeof(double) * (size_t)mm);
+        double complex *w = malloc(sizeof(double complex) * 2 * (size_t)mm);
+#pragma omp for
+        for (int v = 0; v < my; ++v) synth_fft(A + (size_t)v * mx, mx, sin_x, s + (size_t)v * mx, w);
+#pragma omp for
+        for (int j = 0; j < mx; ++j) {
+            for (int v = 0; v < my; ++v) in[v] = s[(size_t)v * mx + j];
+            synth_fft(in, my, sin_y, o, w);
+            for (int k = 0; k < my; ++k) out[(size_t)k * mx + j] = o[k];
+        }
+        free(in);
+        free(o);
+        free(w);
+    }
+    free(s);
+}
+
+/* Cosine synthesis (inverse of orc_dct2 up to its scale) and the sine variants, exposed for
+ * the cross-checks: mode 0 cos-cos, 1 sin(x)-cos(y), 2 cos(x)-sin(y); fft selects the path. */
+void orc_synth2(int mx, int my, const double *A, int mode, int fft, double *out);
+
 /* out_kj = sum_{u,v} A_vu Bx(u, j) By(v, k) where Bx, By are cos or sin of pi u (j+1/2)/M. */
 static void synth2(int mx, int my, const double *A, int sin_x, int sin_y, double *out)
 {
@@ -513,16 +625,27 @@ static void synth2(int mx, int my, const double *A, int sin_x, int sin_y, double
     free(s);
 }
 
+void orc_synth2(int mx, int my, const double *A, int mode, int fft, double *out)
+{
+    if (fft)
+        synth2_fft(mx, my, A, mode == 1, mode == 2, out);
+    else
+        synth2(mx, my, A, mode == 1, mode == 2, out);
+}
+
 /* Solve for psi / xi_x / xi_y (each may be NULL) from rho_bar; returns the energy N.
  * a_out (may be NULL) receives the cosine coefficients a_uv. */
-double orc_poisson(int mx, int my, double W, double H, const double *rho_bar, int fd5,
+double orc_poisson(int mx, int my, double W, double H, const double *rho_bar, int fd5, int fft,
                    double *a_out, double *psi, double *ex, double *ey)
 {
     size_t nb = (size_t)mx * my;
     double wb = W / mx, hb = H / my;
     double *a = malloc(sizeof(double) * nb);
     double *A = malloc(sizeof(double) * nb);
-    orc_dct2(mx, my, rho_bar, a);
+    if (fft)
+        orc_dct2_fft(mx, my, rho_bar, a);
+    else
+        orc_dct2(mx, my, rho_bar, a);
     double energy = 0.0;
     for (int v = 0; v < my; ++v)
         for (int u = 0; u < mx; ++u) {
@@ -550,7 +673,10 @@ double orc_poisson(int mx, int my, double W, double H, const double *rho_bar, in
                 }
                 A[v * mx + u] = val;
             }
-        synth2(mx, my, A, pass == 1, pass == 2, out);
+        if (fft)
+            synth2_fft(mx, my, A, pass == 1, pass == 2, out);
+        else
+            synth2(mx, my, A, pass == 1, pass == 2, out);
     }
     if (a_out) memcpy(a_out, a, sizeof(double) * nb);
     free(a);
@@ -647,7 +773,7 @@ double orc_density_energy_float(const orc_netlist *n, const double *x, const dou
     double *rho = malloc(sizeof(double) * nb);
     orc_density_float(n, x, y, rho);
     for (size_t b = 0; b < nb; ++b) rho[b] /= wb * hb;
-    double e = orc_poisson(n->mx, n->my, n->W, n->H, rho, fd5, NULL, NULL, NULL, NULL);
+    double e = orc_poisson(n->mx, n->my, n->W, n->H, rho, fd5, 0, NULL, NULL, NULL, NULL);
     free(rho);
     return e;
 }
@@ -662,6 +788,7 @@ typedef struct {
     double target_density;
     int32_t grad_mode; /* 0 field, 1 exact */
     int32_t fd5;
+    int32_t fft;       /* 1: the Poisson solve's transforms through the FFT path (timing) */
 } orc_eval_params;
 
 void orc_eval(const orc_netlist *n, const double *x, const double *y, const orc_eval_params *p,
@@ -679,7 +806,7 @@ void orc_eval(const orc_netlist *n, const double *x, const double *y, const orc_
     orc_density_q(n, x, y, rm, rf);
     const double unit = ldexp(1.0, -40);
     for (size_t b = 0; b < nb; ++b) rb[b] = (double)(rm[b] + rf[b]) * unit / (wb * hb);
-    *energy = orc_poisson(n->mx, n->my, n->W, n->H, rb, p->fd5, NULL, psi, ex, ey);
+    *energy = orc_poisson(n->mx, n->my, n->W, n->H, rb, p->fd5, p->fft, NULL, psi, ex, ey);
     *overflow = orc_overflow(n, rm, rf, p->target_density, overflow_num);
     if (gdx) {
         if (p->grad_mode == 1)
@@ -851,7 +978,8 @@ void orc_nesterov_step_bt(const orc_netlist *n, double lambda, const double *g, 
 /* The placer: T iterations of [objective + gradient at v, Nesterov step], from (x, y).
  * lambda_0 = scale * |g_wl|_1 / |g_d|_1 at the first evaluation, then multiplied by
  * ratio = 10^(decades / T) each iteration (Eq. 2's lambda starts small and grows, Sec. 3).
- * On return x, y hold u_T; hpwl_trace[k] (may be NULL) is HPWL_q(u_{k+1}). */
+ * On return x, y hold u_T; hpwl_trace[k] (may be NULL) is HPWL_q(u_{k+1}), lambda_trace[k]
+ * the lambda of step k. */
 typedef struct {
     orc_eval_params ev;
     int32_t iters;
@@ -862,7 +990,7 @@ typedef struct {
 double orc_lambda_ratio(double decades, int iters) { return pow(10.0, decades / iters); }
 
 void orc_place(const orc_netlist *n, const orc_place_params *pp, double *x, double *y,
-               int64_t *hpwl_trace, double *wl_trace, double *ovf_trace)
+               int64_t *hpwl_trace, double *wl_trace, double *ovf_trace, double *lambda_trace)
 {
     int N = n->n_movable;
     size_t N2 = 2 * (size_t)(N > 0 ? N : 1);
@@ -892,6 +1020,7 @@ void orc_place(const orc_netlist *n, const orc_place_params *pp, double *x, doub
         }
         for (size_t i = 0; i < 2 * (size_t)N; ++i) g[i] += lambda * gd[i];
         orc_nesterov_step(n, lambda, g, u, v, vp, gp, &s);
+        if (lambda_trace) lambda_trace[it] = lambda;
         if (wl_trace) wl_trace[it] = wl;
         if (ovf_trace) ovf_trace[it] = ovf;
         if (hpwl_trace) hpwl_trace[it] = orc_hpwl_q(n, u, u + N, NULL);
@@ -1170,6 +1299,9 @@ int32_t orc_argmin_i64(const int64_t *v, int32_t n)
 #ifdef _OPENMP
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+/* Thread count of later parallel loops (timing only; results do not depend on it). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int orc_num_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif

@@ -44,7 +44,7 @@ class _Net(C.Structure):
 
 class _EvalParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("target_density", C.c_double),
-                ("grad_mode", C.c_int32), ("fd5", C.c_int32)]
+                ("grad_mode", C.c_int32), ("fd5", C.c_int32), ("fft", C.c_int32)]
 
 
 class _NestScalars(C.Structure):
@@ -83,7 +83,9 @@ def lib():
             "orc_density_float": (None, [P, P, P, P]),
             "orc_dct2_brute": (None, [C.c_int, C.c_int, P, P]),
             "orc_dct2": (None, [C.c_int, C.c_int, P, P]),
-            "orc_poisson": (d, [C.c_int, C.c_int, d, d, P, C.c_int, P, P, P, P]),
+            "orc_dct2_fft": (None, [C.c_int, C.c_int, P, P]),
+            "orc_synth2": (None, [C.c_int, C.c_int, P, C.c_int, C.c_int, P]),
+            "orc_poisson": (d, [C.c_int, C.c_int, d, d, P, C.c_int, C.c_int, P, P, P, P]),
             "orc_density_grad_field": (None, [P, P, P, P, P, P, P]),
             "orc_density_grad_exact": (None, [P, P, P, P, P, P]),
             "orc_density_energy_float": (d, [P, P, P, C.c_int]),
@@ -91,7 +93,7 @@ def lib():
             "orc_nesterov_step": (None, [P, d, P, P, P, P, P, P]),
             "orc_nesterov_step_bt": (None, [P, d, P, P, P, P, P, P, P]),
             "orc_lambda_ratio": (d, [d, C.c_int]),
-            "orc_place": (None, [P, P, P, P, P, P, P]),
+            "orc_place": (None, [P, P, P, P, P, P, P, P]),
             "orc_splitmix": (u64, [u64, u64]),
             "orc_shuffle_perm": (u64, [u64, u64, u64]),
             "orc_perturb": (i32, [P, P, P, C.c_int, d, d, u64, P]),
@@ -99,6 +101,7 @@ def lib():
             "orc_wiremask": (i32, [P, P, P, P, i32]),
             "orc_argmin_i64": (i32, [P, i32]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -213,12 +216,16 @@ class Oracle:
         return self.L.orc_density_energy_float(self.ref, _p(x), _p(y), int(fd5))
 
     # -- objective ----------------------------------------------------------------------
-    def eval(self, x, y, gamma, target_density=1.0, grad_mode=0, fd5=False, maps=False):
+    def eval(self, x, y, gamma, target_density=1.0, grad_mode=0, fd5=False, maps=False,
+             fft=False):
+        """fft: the Poisson solve's transforms through the FFT path (same values to rounding;
+        used for timing) instead of the plain cosine sums."""
         # float64 copies held for the duration of the call (ctypes keeps only addresses)
         x, y = _f64(x), _f64(y)
         N = self.nl.n_movable
         nb = self.nb
-        pr = _EvalParams(float(gamma), float(target_density), int(grad_mode), int(fd5))
+        pr = _EvalParams(float(gamma), float(target_density), int(grad_mode), int(fd5),
+                         int(fft))
         wl, en, ov, on = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
         gwx, gwy, gdx, gdy = (np.zeros(N) for _ in range(4))
         rm = np.zeros(nb, dtype=np.int64) if maps else None
@@ -266,17 +273,18 @@ class Oracle:
         return self.L.orc_lambda_ratio(float(decades), int(iters))
 
     def place(self, x, y, iters, gamma, lambda0_scale, lambda_decades, target_density=1.0,
-              grad_mode=0, fd5=False):
+              grad_mode=0, fd5=False, fft=False):
         x = _f64(x).copy()
         y = _f64(y).copy()
         pp = _PlaceParams(_EvalParams(float(gamma), float(target_density), int(grad_mode),
-                                      int(fd5)), int(iters), float(lambda0_scale),
+                                      int(fd5), int(fft)), int(iters), float(lambda0_scale),
                           float(lambda_decades))
         hp = np.zeros(iters, dtype=np.int64)
         wl = np.zeros(iters)
         ov = np.zeros(iters)
-        self.L.orc_place(self.ref, C.byref(pp), _p(x), _p(y), _p(hp), _p(wl), _p(ov))
-        return x, y, dict(hpwl_q=hp, wl=wl, overflow=ov)
+        lam = np.zeros(iters)
+        self.L.orc_place(self.ref, C.byref(pp), _p(x), _p(y), _p(hp), _p(wl), _p(ov), _p(lam))
+        return x, y, dict(hpwl_q=hp, wl=wl, overflow=ov, lam=lam)
 
     # -- perturbation -------------------------------------------------------------------
     def perturb(self, x, y, mode, fraction, sigma_bins, seed):
@@ -308,20 +316,32 @@ class Oracle:
 
 
 # -- grid-level functions (no netlist) ----------------------------------------------------
-def dct2(rho, brute=False):
+def dct2(rho, brute=False, fft=False):
+    """Cosine coefficients a_uv: the O(M^4) double sum (brute), the FFT path (fft), or the
+    two 1-D cosine sums (default)."""
     rho = _f64(rho)
     my, mx = rho.shape
     a = np.zeros_like(rho)
-    (lib().orc_dct2_brute if brute else lib().orc_dct2)(mx, my, _p(rho), _p(a))
+    f = lib().orc_dct2_brute if brute else (lib().orc_dct2_fft if fft else lib().orc_dct2)
+    f(mx, my, _p(rho), _p(a))
     return a
 
 
-def poisson(rho_bar, W, H, fd5=False):
+def synth2(A, mode=0, fft=False):
+    """sum_uv A_vu Bx(u, j) By(v, k); mode 0 cos-cos, 1 sin-cos, 2 cos-sin (x-y)."""
+    A = _f64(A)
+    my, mx = A.shape
+    out = np.zeros_like(A)
+    lib().orc_synth2(mx, my, _p(A), int(mode), int(fft), _p(out))
+    return out
+
+
+def poisson(rho_bar, W, H, fd5=False, fft=False):
     rho_bar = _f64(rho_bar)
     my, mx = rho_bar.shape
     a, psi, ex, ey = (np.zeros_like(rho_bar) for _ in range(4))
-    e = lib().orc_poisson(mx, my, float(W), float(H), _p(rho_bar), int(fd5), _p(a), _p(psi),
-                          _p(ex), _p(ey))
+    e = lib().orc_poisson(mx, my, float(W), float(H), _p(rho_bar), int(fd5), int(fft), _p(a),
+                          _p(psi), _p(ex), _p(ey))
     return dict(energy=e, a=a, psi=psi, ex=ex, ey=ey)
 
 
@@ -347,6 +367,11 @@ def shuffle_perm(j, m, seed):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_threads(n):
+    """Thread count of the oracle's later parallel loops (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def argmin_i64(v):
