@@ -1,20 +1,21 @@
 """Benchmark of the placer hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large] [--no-cpu-baseline]
 
-Workload: the "mid" synthetic netlist (210,000 movable unit-height cells, 500 fixed macros on
-20% of the die, 220,000 nets with 0.1% of 200-2000 pins, 512 x 512 bins, FP32), shaped like
-the adaptec1 design of Table 1.  One step is one iteration of the placer: the objective and
-gradient of Eq. 2 (WA wirelength of Eq. 3, charge scatter, Poisson solve, field gather), the
-preconditioned Nesterov step, and the exact HPWL of Eq. 1 with the overflow.  The untimed
-warmup places the netlist from random positions (W iterations) to give the incumbent; the
-timed region is one Hybro round (Alg. 1) on it: perturb the incumbent (Gaussian, 5% of the
-cells, sigma = 8 bins), K placer iterations, then keep the better of the result and the
-incumbent.
+Headline workload: the "large" synthetic netlist (2.2 M movable unit-height cells, 8,000 fixed
+macros on 20% of the die, 2.3 M nets with a power-law degree mix up to 5,000 pins, 1024 x 1024
+bins, FP32 with the int64 charge map), the largest configuration that fits one GPU.  One step
+is one iteration of the plain placer (Sec. 3.1): the objective and gradient of Eq. 2 (WA
+wirelength of Eq. 3, charge scatter, Poisson solve, field gather), the preconditioned Nesterov
+step, and the exact HPWL of Eq. 1 with the overflow.  W untimed iterations from the initial
+positions, then K timed ones of the same placement (its lambda schedule spans the
+configuration's 2,000 iterations).
 
 Prints one JSON line: iterations/s, per-step milliseconds, the roofline of the dominant kernel
-(algorithmic bytes / its average duration from HIP events recorded around every launch in the
-timed region) and the CPU oracle's rate on a bounded sample of the same workload.
+(its share of the compulsory bytes per iteration / its average duration from HIP events on its
+launches in the timed region) and the CPU oracle's rate on a bounded sample of the same
+workload; secondary lines: a Hybro round on "mid" (adaptec1-sized), the batched round of 32
+restarts, mid with movable macros, and the serving mix.
 """
 from __future__ import annotations
 
@@ -30,81 +31,109 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Sources that define the first launch of an evaluation (the dominant kernel); the stored HBM
-# traffic is used only while their hash matches the one it was measured with.
+CONFIG_ITERS = {"large": 2000, "mid": 1000, "tiny": 200}
+# Sources that define the first launch of an evaluation (the dominant kernel); a stored HBM
+# traffic record is used only while their hash matches the one it was measured with.
 FRONT_SOURCES = ["paper_2402_18311_amd/csrc/k_sweep.hip", "paper_2402_18311_amd/csrc/hp_binning.h",
                  "paper_2402_18311_amd/csrc/hp_device.h", "paper_2402_18311_amd/csrc/hp_internal.h"]
-TRAFFIC_FILE = os.path.join("profiles", "eval_front_kernel_mid_traffic.json")
 CALIB_BYTES = 256 << 20  # the calibration copy: 256 MiB read and 256 MiB written
 METRIC = ("placer iters/sec + HBM GB/s; batched-vs-plain restarts/sec, p50/p99 at equal HPWL")
+
+
+def traffic_file(kernel, workload):
+    return os.path.join("profiles", f"{kernel}_{workload}_traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(nl, rs=4):
-    """Compulsory bytes each kernel must move per launch (each input read once, each output
-    written once), for one slot.  Intermediates count for the kernel that produces or consumes
-    them."""
-    deg = np.diff(nl.net_start)
-    E2 = int(np.sum(deg >= 2))
-    P2 = int(np.sum(deg[deg >= 2]))
+def compulsory_bytes(nl, rs=4):
+    """Compulsory HBM bytes of one iteration, one slot: each static or state array read once,
+    each output written once, intermediates (pin gradients, charge maps, field maps, spectral
+    work arrays, partial sums) not counted.  Returns the evaluation's and the step's totals
+    and each kernel's share:
+      B_eval = 4 (E + 1) + 12 P + 8 N_all + 16 N_mov + 8 N_mov + 8 M^2
+        (net offsets; pin cell ids and two FP32 offsets; every position; the movable cells'
+        static charge geometry; the gradient out; the fixed cells' int64 charge map),
+      B_step = 64 N_mov
+        (v, u, g, v_prev, g~_prev read, 8 bytes of preconditioner inputs, u and v written).
+    Shares: the first launch of an evaluation (net sweep and charge scatter) reads the
+    topology, the positions and the charge geometry; the row pass of the Poisson solve reads
+    the fixed map; the gradient pass writes the gradient; the update does the step."""
+    E, P = nl.n_nets, nl.n_pins
     N, Nall = nl.n_movable, nl.n_cells
-    Pm = int(np.sum(nl.pin_cell[np.repeat(deg >= 2, deg)] < N))
     M2 = nl.mx * nl.my
-    wa = 4 * (E2 + 1) + 4 * P2 + 2 * rs * P2 + 2 * rs * Nall + 2 * rs * P2
-    hpwl = 4 * (E2 + 1) + 4 * P2 + 8 * P2 + 2 * rs * Nall
-    scatter = 2 * rs * N + 20 * N + 8 * M2
-    return {
-        # the first launch of an evaluation: WA sweep of v (net_start, pin cell ids, pin
-        # offsets, every position once, pin gradients out), HPWL sweep of u (quantized offsets,
-        # u; the topology is shared), and the charge scatter of v (charge constants in, the
-        # int64 map out; v already counted); the grouping and tile windows are intermediates
-        "eval_front_kernel": wa + (8 * P2 + 2 * rs * Nall) + (20 * N + 8 * M2),
-        "sweep_wa": wa,
-        "sweep_hpwl": hpwl,
-        "bin_accum_kernel": scatter,
-        # cell CSR, pin gradients, positions, charge constants, the field map, gradient out;
-        # for the next step's reductions also v_prev, g_prev and the preconditioner's inputs
-        "cell_grad_kernel": 4 * (N + 1) + 4 * Pm + 2 * rs * Pm + 2 * rs * N + 20 * N
-        + 2 * rs * M2 + 2 * rs * N + 3 * 2 * rs * N,
-        # fixed int64 map in, row transform out (the movable map is the scatter's output)
-        "spec_rows_fwd": 8 * M2 + rs * M2,
-        "spec_cols": rs * M2 + 2 * rs * M2,
-        "spec_rows_inv": 2 * rs * M2 + 2 * rs * M2,
-        # v, v_prev, g, g_prev, pins + area
-        "step_norms_kernel": 4 * 2 * rs * N + 2 * rs * N,
-        # pins, area, clamp bounds, v, u, g in; u, v, v_prev, g_prev out
-        "step_update_kernel": 4 * rs * N + 3 * 2 * rs * N + 4 * 2 * rs * N,
+    share = {
+        "eval_front_kernel": 4 * (E + 1) + 12 * P + 8 * Nall + 16 * N,
+        "spec_rows_fwd": 8 * M2,
+        "cell_grad_kernel": 8 * N,
+        "step_update_kernel": 64 * N,
     }
+    b_eval = 4 * (E + 1) + 12 * P + 8 * Nall + 24 * N + 8 * M2
+    return b_eval, 64 * N, share
 
 
-def cpu_baseline(nl, gamma, budget_s=15.0, max_iters=400):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload: whole placer
-    iterations (objective + gradient, Nesterov step, exact HPWL) from the initial positions."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(nl, gamma, iters=5, label="large"):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: `iters` whole
+    placer iterations (objective + gradient with the FFT path of the Poisson transforms,
+    Nesterov step, exact HPWL) from the initial positions, once on one thread and once on all
+    the threads OpenMP is given; the rate is from the median iteration."""
     from oracle import oracle as O
     o = O.Oracle(nl)
     n = nl.n_movable
-    st = o.new_state(nl.x0, nl.y0)
-    ratio = o.lambda_ratio(4.0, 1000)
-    lam = None
-    t0 = time.perf_counter()
-    it = 0
-    while it < max_iters:
-        r = o.eval(st["v"][:n], st["v"][n:], gamma)
-        gw = np.concatenate([r["gwx"], r["gwy"]])
-        gd = np.concatenate([r["gdx"], r["gdy"]])
-        lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum() if lam is None else lam * ratio
-        o.nesterov_step(lam, gw + lam * gd, st)
-        o.hpwl_q(st["u"][:n], st["u"][n:])
-        it += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": it / dt, "unit": "iter/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{it} placer iterations (objective+gradient, Nesterov step, exact HPWL) "
-                      f"of the mid workload from its initial placement, FP64, {dt:.1f} s"}
+    all_threads = O.num_threads()
+    nproc = os.cpu_count()
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    ratio = o.lambda_ratio(4.0, CONFIG_ITERS.get(label, 1000))
+
+    def run(threads):
+        O.set_threads(threads)
+        st = o.new_state(nl.x0, nl.y0)
+        lam = None
+        times = []
+        for _ in range(iters):
+            t0 = time.perf_counter()
+            r = o.eval(st["v"][:n], st["v"][n:], gamma, fft=True)
+            gw = np.concatenate([r["gwx"], r["gwy"]])
+            gd = np.concatenate([r["gdx"], r["gdy"]])
+            lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum() if lam is None else lam * ratio
+            o.nesterov_step(lam, gw + lam * gd, st)
+            o.hpwl_q(st["u"][:n], st["u"][n:])
+            times.append(time.perf_counter() - t0)
+        return float(np.median(times))
+
+    t1 = run(1)
+    tn = run(all_threads)
+    O.set_threads(all_threads)
+    total = CONFIG_ITERS.get(label, 1000)
+    return {"value": round(1.0 / tn, 4), "unit": "iter/s", "cores": all_threads,
+            "kind": "oracle",
+            "sample": f"median of {iters} placer iterations (objective + gradient with the FFT "
+                      f"path of the Poisson transforms, Nesterov step, exact HPWL) of the "
+                      f"{label} workload from its initial placement, FP64, on {all_threads} "
+                      f"threads; a {total}-iteration run extrapolates to {total * tn:.0f} s "
+                      f"(extrapolated, not run)",
+            "cpu_model": _cpu_model(), "nproc": nproc, "cpus_available": avail,
+            "threads_all": all_threads,
+            "iter_per_s_1_thread": round(1.0 / t1, 4),
+            "iter_per_s_all_threads": round(1.0 / tn, 4),
+            "extrapolated_run_s": {"1_thread": round(total * t1, 1),
+                                   "all_threads": round(total * tn, 1), "iterations": total}}
 
 
 def sources_hash(files=FRONT_SOURCES):
@@ -116,12 +145,12 @@ def sources_hash(files=FRONT_SOURCES):
     return h.hexdigest()[:16]
 
 
-def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel", last=None):
+def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel", last=None, workload="large"):
     """Per-launch HBM traffic of `kernel` from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for the 256 MiB
     calibration copy of the same run (--copy-calibration).  With `last`, the average is over
     the kernel's last `last` dispatches (the timed round of the profiled run) and the average
-    over all of them is recorded beside it.  Writes TRAFFIC_FILE."""
+    over all of them is recorded beside it.  Writes traffic_file(kernel, workload)."""
     import csv
     import glob
 
@@ -145,21 +174,22 @@ def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel", last=None):
     kib = CALIB_BYTES / 1024
     ff, wf = kib / fc, kib / wc
     traffic = (fe * ff + wr * wf) * 1024
-    rec = {"kernel": kernel, "workload": "mid", "fetch_kib_per_launch": round(fe, 1),
+    rec = {"kernel": kernel, "workload": workload, "fetch_kib_per_launch": round(fe, 1),
            "write_kib_per_launch": round(wr, 1), "launches": [n1, n2],
            "all_launches_fetch_write_kib": [round(fe_all, 1), round(wr_all, 1)],
            "calibration_copy_kib": [round(fc, 1), round(wc, 1)],
            "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
            "traffic_bytes_per_launch": int(traffic), "sources_hash": sources_hash()}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as fh:
+    with open(os.path.join(ROOT, traffic_file(kernel, workload)), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of `kernel` measured by counters, or None if absent or stale."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` measured by counters, or None if absent
+    or stale (the kernel's sources changed since)."""
+    path = os.path.join(ROOT, traffic_file(kernel, workload))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -206,42 +236,66 @@ def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
             "best_hpwl": min(res["batched"][2]) / 65536}
 
 
-def large_run(hy, netgen, seed, warm, steps):
-    """Plain-method iterations on the large synthetic netlist (2.2 M cells, 1024 x 1024 bins,
-    FP32 with the int64 charge map): iterations/s over `steps` iterations after `warm`, and the
-    first launch's HBM rate from HIP events on its launches in that timed region."""
+def mid_lines(hy, netgen, args):
+    """Secondary lines on the "mid" netlist (adaptec1-sized, 512 x 512 bins, FP32): the
+    incumbent from a full placement (untimed), then one timed Hybro round (Gaussian-perturb 5%
+    of the cells by 8 bins, mid_steps placer iterations, keep the better), and the batched
+    round of `batch` restarts against the same restarts one slot at a time."""
     import torch
-    nl = netgen.make_netlist("large", seed)
+    nl = netgen.make_netlist("mid", args.seed)
+    gamma = 4 * nl.bin_w
+    K, W = args.mid_steps, args.mid_warmup
     pl = hy.Placer(nl, precision=32)
-    g = 4 * nl.bin_w
-    s = pl.new_slot()
-    pl.set_positions(s, nl.x0, nl.y0)
-    pl.set_schedule(s, 1e-4, 4.0, warm + steps)
-    pl.iterate(s, g, warm, hpwl=True)
+    work, inc = pl.new_slot(), pl.new_slot()
+    pl.set_positions(work, nl.x0, nl.y0)
+    pl.set_schedule(work, 1e-4, 4.0, max(W, 1))
+    pl.iterate(work, gamma, W, hpwl=True)
+    pl.hpwl(work)
+    pl.select_best([work], inc)
+    ix = torch.empty(nl.n_movable, dtype=torch.float32, device="cuda")
+    iy = torch.empty_like(ix)
+    hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
+
+    def restart(iters):
+        pl.set_positions(work, ix, iy)
+        pl.set_schedule(work, 1e-4, 4.0, iters)
+
     from paper_2402_18311_amd import autotune
-    policy, _ = autotune.tune_scatter(pl, [s], g)  # untimed; scratch slots from s's positions
+    restart(K)
+    pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0x7E57, want_idx=False)
+    policy, _ = autotune.tune_scatter(pl, [work], gamma)
+    restart(K)
+    b_eval, b_step, share = compulsory_bytes(nl)
     hy.hp_profile_enable(pl.ctx, True, "eval_front_kernel")
     hy.hp_profile_read(pl.ctx, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pl.iterate(s, g, steps, hpwl=True)
+    pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0xC0FFEE, want_idx=False)
+    pl.iterate(work, gamma, K, hpwl=True)
+    pl.select_best([work], inc, want_host=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = hy.hp_profile_read(pl.ctx, reset=True)
+    c, ms = hy.hp_profile_read(pl.ctx, reset=True).get("eval_front_kernel", (0, 0.0))
     hy.hp_profile_enable(pl.ctx, False)
-    c, ms = prof.get("eval_front_kernel", (0, 0.0))
-    ab = algorithmic_bytes(nl)["eval_front_kernel"]
     avg = ms * 1e-3 / max(c, 1)
-    hq = pl.hpwl(s)[0]
-    out = {"workload": f"large: {nl.n_movable} movable cells, {nl.n_fixed} fixed macros, "
-                       f"{nl.n_nets} nets / {nl.n_pins} pins, {nl.mx}x{nl.my} bins, FP32, "
-                       f"int64 charge map",
-           "iter_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
-           "steps": steps, "warmup": warm, "hpwl": hq / 65536,
-           "scatter_policy": {"regroup_every": policy[0], "deferred": policy[1]},
-           "front_kernel_avg_us": round(avg * 1e6, 3),
-           "front_kernel_gbs": round(ab / avg / 1e9, 1) if c else None,
-           "front_kernel_frac": round(ab / avg / 1e9 / HBM_PEAK_GBS, 4) if c else None}
+    out = {"mid": {
+        "workload": f"mid: {nl.n_movable} movable cells, {nl.n_fixed} fixed macros, "
+                    f"{nl.n_nets} nets / {nl.n_pins} pins, {nl.mx}x{nl.my} bins, FP32; one Hybro "
+                    f"round (Gaussian perturb 5%, sigma 8 bins) of {K} iterations after a "
+                    f"{W}-iteration placement",
+        "iter_per_s": round(K / dt, 2), "ms_per_step": round(1e3 * dt / K, 5), "steps": K,
+        "warmup": W, "final_hpwl": pl.state(inc)["hpwl_q"] / 65536,
+        "scatter_policy": {"regroup_every": policy[0], "deferred": policy[1]},
+        "compulsory_bytes_per_iter": b_eval + b_step,
+        "compulsory_gbs": round((b_eval + b_step) / (dt / K) / 1e9, 1),
+        "front_kernel_avg_us": round(avg * 1e6, 3) if c else None,
+        "front_kernel_frac": round(share["eval_front_kernel"] / avg / 1e9 / HBM_PEAK_GBS, 4)
+        if c else None,
+        "note": "the mid working set fits the 256 MB Infinity Cache: reported, not the "
+                "HBM roofline case"}}
+    if args.batch > 0:
+        log(f"[bench] batched round: {args.batch} restarts x {args.batch_iters} iterations")
+        out["batched"] = batched_round(pl, hy, nl, gamma, inc, args.batch, args.batch_iters, 0xB00)
     pl.close()
     return out
 
@@ -301,22 +355,26 @@ def macros_run(hy, netgen, seed, warm, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=1000,
-                    help="untimed iterations that place the incumbent (a full placement run)")
-    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--steps", type=int, default=200, help="timed placer iterations")
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed iterations of the same placement before the timed ones")
+    ap.add_argument("--workload", default="large")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=5,
+                    help="oracle iterations per thread setting of the CPU baseline")
     ap.add_argument("--no-profile", action="store_true",
                     help="time without the per-launch events (no roofline)")
-    ap.add_argument("--large-steps", type=int, default=500,
-                    help="timed iterations on the large netlist (0 skips it)")
+    ap.add_argument("--mid-steps", type=int, default=1000,
+                    help="timed iterations of the Hybro round on mid (0 skips the mid lines)")
+    ap.add_argument("--mid-warmup", type=int, default=1000)
     ap.add_argument("--macro-steps", type=int, default=1000,
                     help="timed iterations on mid with movable macros (0 skips it)")
     ap.add_argument("--serve-jobs", type=int, default=16,
                     help="jobs of the serving-mix trace (0 skips it)")
     ap.add_argument("--batch", type=int, default=32,
                     help="restarts of the batched-round measurement (0 skips it)")
+    ap.add_argument("--batch-iters", type=int, default=1000)
     ap.add_argument("--pmc-last", type=int, default=None,
                     help="with --pmc-summary: average the kernel's last N dispatches only")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -326,11 +384,11 @@ def main():
                     help="use this charge-scatter policy (e.g. 8,1) instead of timing the "
                          "candidates before the round")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the round, copy 256 MiB device-to-device once: the reference "
-                         "dispatch for scaling hardware byte counters")
+                    help="after the timed region, copy 256 MiB device-to-device once: the "
+                         "reference dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, last=args.pmc_last)
+        pmc_summary(*args.pmc_summary, last=args.pmc_last, workload=args.workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the placer runs on a single MI355X; "
@@ -348,83 +406,66 @@ def main():
     nl = netgen.make_netlist(args.workload, args.seed)
     gamma = 4 * nl.bin_w
     K, W = args.steps, args.warmup
+    total = CONFIG_ITERS.get(args.workload, W + K)
     pl = hy.Placer(nl, precision=32)
-    work, inc = pl.new_slot(), pl.new_slot()
-
-    def round_(iters, seed):
-        """One Hybro round on `work`: perturb, iters placer iterations (objective + gradient,
-        Nesterov step, exact HPWL; one library call), keep the best."""
-        pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, seed, want_idx=False)
-        pl.iterate(work, gamma, iters, hpwl=True)
-        pl.select_best([work], inc, want_host=False)
-
-    def restart_from_incumbent(iters):
-        ix = torch.empty(nl.n_movable, dtype=torch.float32, device="cuda")
-        iy = torch.empty_like(ix)
-        hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
-        pl.set_positions(work, ix, iy)
-        pl.set_schedule(work, 1e-4, 4.0, iters)
-
+    s = pl.new_slot()
     log(f"[bench] {nl.name}: {nl.n_movable} movable, {nl.n_fixed} fixed, {nl.n_nets} nets, "
         f"{nl.n_pins} pins, {nl.mx}x{nl.my} bins; warmup {W}, steps {K}")
-    # every kernel once (code objects load lazily on first launch), then the incumbent: a full
-    # placement from the random initial positions
-    pl.set_positions(work, nl.x0, nl.y0)
-    pl.perturb(work, hy.HP_PERTURB_SHUFFLE, 0.5, 0.0, 1, want_idx=False)
-    pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.5, 8.0, 2, want_idx=False)
-    pl.set_positions(work, nl.x0, nl.y0)
-    pl.set_schedule(work, 1e-4, 4.0, max(W, 1))
-    pl.iterate(work, gamma, W, hpwl=True)
-    pl.hpwl(work)
-    pl.select_best([work], inc)
+    pl.set_positions(s, nl.x0, nl.y0)
+    pl.set_schedule(s, 1e-4, 4.0, total)
+    pl.iterate(s, gamma, W, hpwl=True)
+    pl.hpwl(s)
     torch.cuda.synchronize()
     log("[bench] warmup done")
 
-    # the scatter's grouping policy, chosen by timing (untimed) from the state the timed round
-    # starts in: the incumbent with a Gaussian perturbation
+    # untimed: the scatter's grouping policy, timed on scratch slots from the current positions
     if args.scatter_policy:
         e, d = (int(v) for v in args.scatter_policy.split(","))
         pl.set_scatter_policy(e, bool(d))
         policy, tune_ms = pl.scatter_policy(), {}
     else:
         from paper_2402_18311_amd import autotune
-        restart_from_incumbent(K)
-        pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0x7E57, want_idx=False)
-        policy, tune_ms = autotune.tune_scatter(pl, [work], gamma)
+        policy, tune_ms = autotune.tune_scatter(pl, [s], gamma)
     log(f"[bench] scatter policy {policy} ({tune_ms})")
 
-    # kernel table: a short round with every launch bracketed by events
+    # untimed: the kernel table, a scratch slot from the current positions with events on
+    # every launch
     prof = {}
     if not args.no_profile:
-        P = min(K, 200)
-        restart_from_incumbent(P)
+        P = min(K, 100)
+        x, y = pl.positions(s)
+        t = pl.new_slot()
+        pl.set_positions(t, x, y)
+        pl.set_schedule(t, 1e-4, 4.0, total)
+        pl.iterate(t, gamma, 2, hpwl=True)
         hy.hp_profile_enable(pl.ctx, True)
         hy.hp_profile_read(pl.ctx, reset=True)
-        round_(P, 0xBEEF)
+        pl.iterate(t, gamma, P, hpwl=True)
+        pl.hpwl(t)
         prof = hy.hp_profile_read(pl.ctx, reset=True)
         hy.hp_profile_enable(pl.ctx, False)
-    ab = algorithmic_bytes(nl)
+        pl.free_slot(t)
+    b_eval, b_step, share = compulsory_bytes(nl)
     kernels = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1), "total_ms": ms}
                for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
-    dom = next((k for k in kernels if k in ab), None)
+    dom = next((k for k in kernels if share.get(k, 0) > 0), None)
 
-    # the timed round; only the dominant kernel's launches carry events
-    restart_from_incumbent(K)
+    # the timed region: K iterations of the placement; only the dominant kernel's launches
+    # carry events
     if dom:
         hy.hp_profile_enable(pl.ctx, True, dom)
         hy.hp_profile_read(pl.ctx, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    round_(K, 0xC0FFEE)
+    pl.iterate(s, gamma, K, hpwl=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     live = {}
     if dom:
         live = hy.hp_profile_read(pl.ctx, reset=True)
         hy.hp_profile_enable(pl.ctx, False)
-    final = pl.state(inc)
-    log(f"[bench] timed {K} iterations in {dt:.3f} s; incumbent HPWL "
-        f"{final['hpwl_q'] / 65536:.1f}")
+    final = pl.state(s)
+    log(f"[bench] timed {K} iterations in {dt:.3f} s; HPWL {final['hpwl_q'] / 65536:.1f}")
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
         dst = torch.empty_like(src)
@@ -436,17 +477,15 @@ def main():
     if dom and dom in live:
         c, ms = live[dom]
         avg_s = ms * 1e-3 / max(c, 1)
-        achieved = ab[dom] / avg_s / 1e9
+        achieved = share[dom] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(dom),
-                "kernel": dom, "algorithmic_bytes": int(ab[dom]), "launches": c,
+                "traffic": stored_traffic(dom, args.workload),
+                "kernel": dom, "compulsory_bytes_per_launch": int(share[dom]), "launches": c,
                 "avg_us": round(avg_s * 1e6, 3)}
     for k, v in kernels.items():
-        if k in ab:
-            v["algorithmic_gbs"] = round(ab[k] / (v["avg_us"] * 1e-6) / 1e9, 1)
-    it_bytes = sum(ab[k] for k in ("eval_front_kernel", "cell_grad_kernel", "spec_rows_fwd",
-                                   "spec_cols", "spec_rows_inv", "step_update_kernel"))
+        if share.get(k, 0) > 0:
+            v["compulsory_gbs"] = round(share[k] / (v["avg_us"] * 1e-6) / 1e9, 1)
     ms_step = 1e3 * dt / K
     out = {
         "metric": METRIC, "value": round(K / dt, 2), "unit": "iter/s", "n_gpus": 1, "steps": K,
@@ -454,13 +493,17 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{nl.name}: {nl.n_movable} movable cells, {nl.n_fixed} fixed "
                                f"macros (20% of die), {nl.n_nets} nets / {nl.n_pins} pins, "
-                               f"{nl.mx}x{nl.my} bins, gamma = 4 bins, one Hybro round "
-                               f"(Gaussian perturb 5%, sigma 8 bins) of {K} iterations",
+                               f"{nl.mx}x{nl.my} bins, FP32 with the int64 charge map, "
+                               f"gamma = 4 bins; plain placer iterations {W}..{W + K} of a "
+                               f"{total}-iteration schedule from the initial positions",
                    "global_batch": 1, "parallelism": "single-gpu"},
-        "hbm_gbps_algorithmic": round(it_bytes / (ms_step * 1e-3) / 1e9, 1),
-        "timing": ("value: wall clock of the timed round, GPU synchronised on both sides; "
+        "compulsory_bytes_per_iter": {"eval": b_eval, "step": b_step},
+        "hbm_gbps_compulsory": round((b_eval + b_step) / (ms_step * 1e-3) / 1e9, 1),
+        "hbm_frac_compulsory": round((b_eval + b_step) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "timing": ("value: wall clock of the timed iterations, GPU synchronised on both sides; "
                    "roofline: HIP events around every launch of the dominant kernel in that "
-                   "round; kernels: a separate 200-iteration round with events on every launch"),
+                   "region; kernels: a separate run on a scratch slot from the same positions "
+                   "with events on every launch"),
         "final_hpwl": final["hpwl_q"] / 65536,
         "tuning": {"scatter_policy": {"regroup_every": policy[0], "deferred": policy[1]},
                    "ms_per_iter": {k: round(v, 4) for k, v in tune_ms.items()}},
@@ -468,12 +511,15 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kernels.items()},
     }
-    if args.batch > 0:
-        log(f"[bench] batched round: {args.batch} restarts x {K} iterations, batched vs plain")
-        out["batched"] = batched_round(pl, hy, nl, gamma, inc, args.batch, K, 0xB00)
-    if args.large_steps > 0:
-        log(f"[bench] large netlist: 300 + {args.large_steps} iterations")
-        out["large"] = large_run(hy, netgen, args.seed, 300, args.large_steps)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        cpu = cpu_baseline(nl, gamma, iters=args.cpu_iters, label=args.workload)
+    pl.close()
+    del pl
+    if args.mid_steps > 0:
+        log(f"[bench] mid: {args.mid_warmup} + {args.mid_steps} iterations (Hybro round)")
+        out.update(mid_lines(hy, netgen, args))
     if args.macro_steps > 0:
         log(f"[bench] movable macros: 600 + {args.macro_steps} iterations, one shuffle round")
         out["movable_macros"] = macros_run(hy, netgen, args.seed, 600, args.macro_steps)
@@ -482,10 +528,8 @@ def main():
         log(f"[bench] serving mix: {args.serve_jobs} jobs, 10 k - 2.2 M cells, 500 iterations")
         out["serving"] = serve.measure(args.serve_jobs, 10_000, 2_200_000, 500, 8.0, 0.8,
                                        args.seed, log=log)
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(nl, gamma)
-    pl.close()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

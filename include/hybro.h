@@ -133,6 +133,22 @@ int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio);
 int hp_set_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t regroup_every, int32_t deferred);
 int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, int32_t *deferred);
 
+/* Launch-shape settings of a loaded netlist, for tuners and tests; they change speed only.
+ *   HP_TUNE_FUSED_STEP_PARTS: the largest number of cell-gradient block partials (one per 256
+ *     movable cells) for which every block of the Nesterov update reduces the step's norms
+ *     itself; above it a one-block closing reduction forms the step before the update.  Both
+ *     forms reduce the partials in the same order, so positions are bit-identical.  [0, 1024],
+ *     default 1024 (0: always the closing reduction).
+ *   HP_TUNE_SPECTRAL_THREADS: threads per block of the Poisson solve's column and inverse-row
+ *     passes, 512 or 1024, or 0 (default: 1024 while a launch has at most one block per
+ *     compute unit, else 512).  The field maps are the same; the energy total may differ in
+ *     its last bits (its per-block reduction tree changes).
+ * Takes effect at the next launch.  HP_EINVAL for an unknown setting or a value out of range
+ * (nothing changed), HP_ESTATE for an unknown netlist.  No device work. */
+enum { HP_TUNE_FUSED_STEP_PARTS = 0, HP_TUNE_SPECTRAL_THREADS = 1 };
+int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value);
+int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value);
+
 /* Objective of Eq. 2 and its gradient at the slots' reference points v:
  *   wl = sum_e w_e WL_e (Eq. 3, both axes), energy = electrostatic energy N of the charge
  *   map, overflow = sum_b max(0, movable charge - target * free area) / total movable charge

@@ -181,6 +181,8 @@ struct Netlist {
     // evaluations; `deferred`: the rebuilding evaluation accumulates in the existing order
     int regroup_every = kRegroupEvery;
     bool deferred = true;
+    // hp_set_tunable: most cell-gradient partials for which the update reduces them itself
+    int fused_parts = kFusedStepParts;
     std::vector<int64_t> charge_prefix;  // [n_mov + 1] integer charge of cells [0, i)
 };
 
@@ -214,6 +216,7 @@ struct hp_ctx {
     hipStream_t stream = nullptr;
     int precision = 32;
     int lds_budget = 65536;
+    int n_cu = 256;  // compute units of the device
     std::vector<Netlist> nets;
     std::vector<Slot> slots;
 };
@@ -307,6 +310,8 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.area_q = (int64_t)nd.bq * nd.hq * 65536;
     nd.target_density = D.target_density;
     nd.lds_budget = ctx->lds_budget;
+    nd.n_cu = ctx->n_cu;
+    nd.spec_threads = 0;
     if (spectral_max_lds<T>(nd) > (size_t)nd.lds_budget)
         return fail(HP_EINVAL, "bin grid too large for this device's LDS at this precision");
 
@@ -744,7 +749,7 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         // steady state: the totals are reduced when first read; with few enough cell-gradient
         // partials there is no closing reduction at all (the step derives its proposal itself),
         // else it forms the step only
-        const bool fused = !any_init && cell_parts(nd) <= kFusedStepParts;
+        const bool fused = !any_init && cell_parts(nd) <= NL->fused_parts;
         const int finish = any_init ? FIN_FULL : (fused ? -1 : FIN_STEP);
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
         // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
@@ -966,8 +971,11 @@ int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
             lds = 65536;
         }
     }
+    int n_cu = 256;
+    HP_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
     hp_ctx *c = new hp_ctx;
     c->device = device;
+    c->n_cu = n_cu > 0 ? n_cu : 1;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->precision = precision;
     c->lds_budget = lds;
@@ -1175,6 +1183,40 @@ int hp_set_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t regroup_every, i
     ctx->nets[netlist].regroup_every = regroup_every;
     ctx->nets[netlist].deferred = deferred != 0;
     return HP_OK;
+}
+
+int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    Netlist &NL = ctx->nets[netlist];
+    switch (which) {
+        case HP_TUNE_FUSED_STEP_PARTS:
+            if (value < 0 || value > kFusedStepParts)
+                return fail(HP_EINVAL, "fused step partials must be in [0, " +
+                                           std::to_string(kFusedStepParts) + "]");
+            NL.fused_parts = value;
+            return HP_OK;
+        case HP_TUNE_SPECTRAL_THREADS:
+            if (value != 0 && value != 512 && value != 1024)
+                return fail(HP_EINVAL, "spectral threads must be 0, 512 or 1024");
+            NL.nd.spec_threads = value;
+            return HP_OK;
+        default:
+            return fail(HP_EINVAL, "unknown tunable");
+    }
+}
+
+int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value) {
+    if (!ctx || !value) return fail(HP_EINVAL, "ctx/out is NULL");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    const Netlist &NL = ctx->nets[netlist];
+    switch (which) {
+        case HP_TUNE_FUSED_STEP_PARTS: *value = NL.fused_parts; return HP_OK;
+        case HP_TUNE_SPECTRAL_THREADS: *value = NL.nd.spec_threads; return HP_OK;
+        default: return fail(HP_EINVAL, "unknown tunable");
+    }
 }
 
 int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, int32_t *deferred) {

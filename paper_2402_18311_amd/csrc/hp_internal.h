@@ -6,7 +6,9 @@
 
 namespace hp {
 
-constexpr int kBlock = 256;      // threads per block for every kernel
+constexpr int kBlock = 256;      // threads per block of the sweep, scatter, gradient and
+                                 // perturbation kernels (the spectral passes, the Nesterov
+                                 // update and the closing reductions choose their own)
 constexpr int kMaxSlots = 32;    // slots per launch (longer lists are chunked)
 constexpr int kMaxBuckets = 12;
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
@@ -62,6 +64,10 @@ struct NetDev {
     const void *cell_wh;           // T [2][n_mov] movable cell sizes
     int32_t n_cells, n_mov, n_fixed, ns, ps;
     int32_t lds_budget;            // dynamic LDS bytes a block may use on this device
+    int32_t n_cu;                  // compute units of the device
+    int32_t spec_threads;          // threads per block of the spectral column and inverse-row
+                                   // passes: 512, 1024, or 0 (1024 while a launch has at most
+                                   // one block per compute unit)
     // tile-binned charge scatter: ts x ts bin tiles (ts = 1 << log_ts), ntx x nty of them;
     // halo = widest charge footprint in bins - 1; windows of win_side = ts + halo bins
     int32_t log_ts, ntx, nty, ntiles, halo, win_side;

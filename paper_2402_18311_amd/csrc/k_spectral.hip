@@ -243,7 +243,7 @@ __host__ __device__ inline size_t cols_lds(int M) {
 
 // C and R2 run 1024-thread blocks when a launch has at most one block per CU (a single slot:
 // the block's latency is the pass's time), 512-thread blocks when it has more (batched slots:
-// smaller blocks interleave better); see spectral_threads.
+// smaller blocks interleave better); see wide_spectral.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L, int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -467,9 +467,11 @@ static size_t rows_inv_lds(const NetDev &nd, int nst) {
            al16(sizeof(T) * (size_t)nst * 2 * nd.mx) + sizeof(vec2<T>) * (size_t)nst * nd.mx;
 }
 
-// 1024-thread C and R2 blocks while a launch has at most one block per CU
+// 1024-thread C and R2 blocks while a launch has at most one block per CU, unless the
+// netlist's tunable fixes the width
 static bool wide_spectral(const NetDev &nd, const SlotArgs &sa) {
-    return (size_t)std::max(nd.mx, nd.my) / 2 * sa.n <= 256;
+    if (nd.spec_threads) return nd.spec_threads == 1024;
+    return (size_t)std::max(nd.mx, nd.my) / 2 * sa.n <= (size_t)nd.n_cu;
 }
 
 template <typename T>

@@ -21,6 +21,7 @@ HP_OK, HP_EINVAL, HP_ENOMEM, HP_EDEVICE, HP_ESTATE, HP_ENOTIMPL = 0, -1, -2, -3,
 HP_PERTURB_GAUSS, HP_PERTURB_SHUFFLE, HP_PERTURB_UNIFORM = 0, 1, 2
 HP_MAP_RHO_MOV, HP_MAP_RHO_FIXED, HP_MAP_PSI, HP_MAP_EX, HP_MAP_EY = 0, 1, 2, 3, 4
 HP_ITER_HPWL, HP_ITER_GRAPH = 1, 2
+HP_TUNE_FUSED_STEP_PARTS, HP_TUNE_SPECTRAL_THREADS = 0, 1
 
 
 class hp_die(C.Structure):
@@ -77,6 +78,8 @@ _SIGS = {
     "hp_perturb_wiremask": [_P, C.c_int32, _P, C.c_int32, _P],
     "hp_set_scatter_policy": [_P, C.c_int32, C.c_int32, C.c_int32],
     "hp_get_scatter_policy": [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    "hp_set_tunable": [_P, C.c_int32, C.c_int32, C.c_int32],
+    "hp_get_tunable": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int32)],
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
     "hp_nesterov_step": [_P, _P, C.c_int32],
     "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
@@ -242,6 +245,16 @@ def hp_get_scatter_policy(ctx, netlist):
     r, d = C.c_int32(), C.c_int32()
     _chk(lib().hp_get_scatter_policy(ctx, netlist, C.byref(r), C.byref(d)))
     return int(r.value), bool(d.value)
+
+
+def hp_set_tunable(ctx, netlist, which, value):
+    _chk(lib().hp_set_tunable(ctx, netlist, int(which), int(value)))
+
+
+def hp_get_tunable(ctx, netlist, which):
+    v = C.c_int32()
+    _chk(lib().hp_get_tunable(ctx, netlist, int(which), C.byref(v)))
+    return int(v.value)
 
 
 def hp_set_schedule(ctx, slot, lambda0_scale, decades, total_iters):
@@ -469,6 +482,13 @@ class Placer:
 
     def scatter_policy(self):
         return hp_get_scatter_policy(self.ctx, self.netlist)
+
+    def set_tunable(self, which, value):
+        """A launch-shape setting of the netlist (speed only; see hybro.h)."""
+        hp_set_tunable(self.ctx, self.netlist, which, value)
+
+    def tunable(self, which):
+        return hp_get_tunable(self.ctx, self.netlist, which)
 
     def run(self, slots, iters, gamma, hpwl_every=0):
         """iters x [evaluate at v, Nesterov step] on the slots; returns HPWL_q trace if asked."""
