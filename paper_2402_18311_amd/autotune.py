@@ -17,7 +17,9 @@ import json
 import os
 import time
 
-CANDIDATES = ((4, True), (4, False), (8, True), (2, True))
+# (regroup_every, deferred); rebuilding at every evaluation pays off while cells still move by
+# many bins per step (the first iterations from random positions, when they clump)
+CANDIDATES = ((4, True), (4, False), (8, True), (2, True), (2, False), (1, False))
 
 
 def _key(pl, k):
