@@ -252,6 +252,21 @@ int hp_perturb_wiremask(hp_ctx *ctx, int32_t slot, const int32_t *macros, int32_
  * value stays in the slot for hp_select_best). */
 int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, int64_t *out_q, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the exact HPWL of Eq. 1, as hp_hpwl computes it, of
+ * positions the caller holds, with no slot and no allocation of any kind.
+ *   xy: device real pairs [n_cells] (x, y) of every cell of the netlist, movable cells then
+ *       fixed ones (the fixed cells at their fixed positions), lower-left corners; aligned to
+ *       a pair.
+ *   out_q: device int64 [1], the HPWL in 2^-16 units.
+ * The sweep's per-block partial sums live in a static device array of the library, 1 MiB
+ * (131072 partials) per GPU, held until the process ends: a netlist whose sweep has more
+ * blocks than that gets HP_ENOMEM (about 40 M pins in nets of two).  Every call on a GPU
+ * uses that GPU's one array, so calls that overlap on one GPU (from different streams or
+ * threads) race and must be ordered by the caller.  Enqueued on the context's stream, does
+ * not synchronise.  NULL pointers or misalignment: HP_EINVAL; unknown netlist: HP_ESTATE. */
+int hp_hpwl_noalloc(hp_ctx *ctx, int32_t netlist, const void *xy, int64_t *out_q);
+
 /* Best solution of Alg. 1: among the slots' last hp_hpwl values (and the incumbent's, if
  * incumbent >= 0 and it has one), the smallest wins, ties to the lowest list position and
  * then to the incumbent; the winner's u is copied into the incumbent's u and v (incumbent

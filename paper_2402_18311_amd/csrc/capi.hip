@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -38,6 +39,33 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---- static scratch of the allocation-free entry point (hp_hpwl_noalloc) --------------------
+// Per-block partial sums of the exact-HPWL sweep live in this file-scope device array, one
+// copy per GPU, held until the process ends.  In host code its name is only a stand-in: the
+// device address of each GPU's copy is looked up once per device (with that device current) at
+// context creation and kept in g_scratch, and only that address is handed to kernels.
+constexpr int kNoAllocParts = 131072;  // 1 MiB of int64 partials
+static __device__ __align__(256) long long scratch[kNoAllocParts];
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch;  // [device] address of that device's copy, or null
+
+int scratch_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= device) g_scratch.resize(device + 1, nullptr);
+    if (g_scratch[device]) return HP_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(HP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = ptr;
+    return HP_OK;
+}
+
+void *scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device < (int)g_scratch.size() ? g_scratch[device] : nullptr;
+}
 
 // Pin slots of the sweep order: a net of d <= 64 pins takes G = nextpow2(d) < 2d slots (the
 // unused ones padded), a larger net exactly d, so 2 * n_pins bounds them.
@@ -973,6 +1001,7 @@ int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
     }
     int n_cu = 256;
     HP_CHECK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+    HP_TRY(scratch_setup(device));  // the device is current here
     hp_ctx *c = new hp_ctx;
     c->device = device;
     c->n_cu = n_cu > 0 ? n_cu : 1;
@@ -1298,6 +1327,29 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n) {
     int rc = resolve(ctx, slots, n, &NL, chunks, ss);
     if (rc) return rc;
     return step_resolved(ctx, NL, chunks, ss);
+}
+
+int hp_hpwl_noalloc(hp_ctx *ctx, int32_t netlist, const void *xy, int64_t *out_q) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (!xy || !out_q) return fail(HP_EINVAL, "xy and out_q must be device pointers");
+    if (((uintptr_t)xy & (2 * rsize(ctx) - 1)) || ((uintptr_t)out_q & 7))
+        return fail(HP_EINVAL, "xy must be aligned to a position pair, out_q to 8 bytes");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    const Netlist &NL = ctx->nets[netlist];
+    if (NL.bk.total_blocks > kNoAllocParts)
+        return fail(HP_ENOMEM, "the netlist's sweep has " + std::to_string(NL.bk.total_blocks) +
+                                   " blocks; the static scratch holds " +
+                                   std::to_string(kNoAllocParts) + " partials");
+    long long *part = static_cast<long long *>(scratch_of(ctx->device));
+    if (!part) return fail(HP_EDEVICE, "no static scratch address for this device");
+    if (ctx->precision == 32)
+        HP_CHECK(launch_hpwl_positions<float>(NL.nd, NL.bk, xy, part,
+                                              reinterpret_cast<long long *>(out_q), ctx->stream));
+    else
+        HP_CHECK(launch_hpwl_positions<double>(NL.nd, NL.bk, xy, part,
+                                               reinterpret_cast<long long *>(out_q), ctx->stream));
+    return HP_OK;
 }
 
 int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double *out) {

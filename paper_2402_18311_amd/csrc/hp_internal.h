@@ -194,6 +194,11 @@ hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st);
+// Exact HPWL of caller-held positions `pos` (real pairs over all cells): per-block partials
+// into part[bk.total_blocks], their sum into out[0].
+template <typename T>
+hipError_t launch_hpwl_positions(const NetDev &nd, const Buckets &bk, const void *pos,
+                                 long long *part, long long *out, hipStream_t st);
 // Scan, place and accumulate of a regroup whose counting pass the first launch ran.
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,

@@ -452,6 +452,24 @@ __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restri
 
 enum { MODE_WA = 0, MODE_HPWL = 1 };
 
+// This lane's share of the exact HPWL of block-local index `local` of bucket b.
+template <typename T>
+__device__ __forceinline__ int64_t hpwl_bucket(const NetDev &nd, const Buckets &bk, int b,
+                                               int local, const vec2<T> *__restrict__ pos) {
+    switch (bk.G[b]) {
+        case 2: return hpwl_groups<T, 2>(nd, bk, b, local, pos);
+        case 4: return hpwl_groups<T, 4>(nd, bk, b, local, pos);
+        case 8: return hpwl_groups<T, 8>(nd, bk, b, local, pos);
+        case 16: return hpwl_groups<T, 16>(nd, bk, b, local, pos);
+        case 32: return hpwl_groups<T, 32>(nd, bk, b, local, pos);
+        case 64: return hpwl_groups<T, 64>(nd, bk, b, local, pos);
+        case 128: return hpwl_wave<T, 2>(nd, bk, b, local, pos);
+        case 256: return hpwl_wave<T, 4>(nd, bk, b, local, pos);
+        default:
+            return bk.net0[b] + local < bk.net1[b] ? hpwl_block<T>(nd, bk.net0[b] + local, pos) : 0;
+    }
+}
+
 // Block `bx` (0 <= bx < bk.total_blocks) of a sweep of one slot: WA over v, or HPWL over u.
 // MODE_WA with H: the WA sweep of v and the HPWL sweep of u in the same blocks, both partials
 // written.
@@ -495,22 +513,8 @@ __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, 
                 (reinterpret_cast<long long *>(base + L.part) + PART_HPWL * L.pstride)[bx] = th;
         }
     } else {
-        int64_t h = 0;
-        switch (bk.G[b]) {
-            case 2: h = hpwl_groups<T, 2>(nd, bk, b, local, pos); break;
-            case 4: h = hpwl_groups<T, 4>(nd, bk, b, local, pos); break;
-            case 8: h = hpwl_groups<T, 8>(nd, bk, b, local, pos); break;
-            case 16: h = hpwl_groups<T, 16>(nd, bk, b, local, pos); break;
-            case 32: h = hpwl_groups<T, 32>(nd, bk, b, local, pos); break;
-            case 64: h = hpwl_groups<T, 64>(nd, bk, b, local, pos); break;
-            case 128: h = hpwl_wave<T, 2>(nd, bk, b, local, pos); break;
-            case 256: h = hpwl_wave<T, 4>(nd, bk, b, local, pos); break;
-            default:
-                if (net0 + local < net1) h = hpwl_block<T>(nd, net0 + local, pos);
-                break;
-        }
         __shared__ long long red[4];
-        const long long tot = block_sum((long long)h, red);
+        const long long tot = block_sum((long long)hpwl_bucket<T>(nd, bk, b, local, pos), red);
         if (threadIdx.x == 0)
             (reinterpret_cast<long long *>(base + L.part) + PART_HPWL * L.pstride)[bx] = tot;
     }
@@ -560,6 +564,42 @@ __global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Bucket
 
 int sweep_parts(const Buckets &bk) { return bk.total_blocks; }
 
+// Exact HPWL of positions the caller holds (pairs over all cells): one partial per block into
+// `part`, then one block sums them into out[0].  Every partial is written, so `part` needs no
+// clearing.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void hpwl_pos_kernel(NetDev nd, Buckets bk, const vec2<T> *pos,
+                                                          long long *part) {
+    const int bx = blockIdx.x;
+    int b = 0;
+    while (b + 1 < bk.n && bx >= bk.blk0[b + 1]) ++b;
+    const int local = xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
+    __shared__ long long red[4];
+    const long long tot = block_sum((long long)hpwl_bucket<T>(nd, bk, b, local, pos), red);
+    if (threadIdx.x == 0) part[bx] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void hpwl_pos_finish_kernel(const long long *part, int n,
+                                                                 long long *out) {
+    __shared__ long long red[4];
+    const long long h = sum_parts(part, n, red);
+    if (threadIdx.x == 0) out[0] = h;
+}
+
+template <typename T>
+hipError_t launch_hpwl_positions(const NetDev &nd, const Buckets &bk, const void *pos,
+                                 long long *part, long long *out, hipStream_t st) {
+    if (bk.total_blocks > 0) {
+        HP_LAUNCH("hpwl_pos_kernel", hpwl_pos_kernel<T>, dim3(bk.total_blocks), dim3(kBlock), 0, st,
+                  nd, bk, reinterpret_cast<const vec2<T> *>(pos), part);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    HP_LAUNCH("hpwl_pos_finish_kernel", hpwl_pos_finish_kernel, dim3(1), dim3(kBlock), 0, st, part,
+              bk.total_blocks, out);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
@@ -590,7 +630,9 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
                                              const SlotLayout &, double, uint32_t, bool, bool,  \
                                              hipStream_t);                                      \
     template hipError_t launch_sweep_hpwl<T>(const NetDev &, const Buckets &, const SlotArgs &, \
-                                             const SlotLayout &, hipStream_t);
+                                             const SlotLayout &, hipStream_t);                  \
+    template hipError_t launch_hpwl_positions<T>(const NetDev &, const Buckets &, const void *, \
+                                                 long long *, long long *, hipStream_t);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

@@ -87,6 +87,7 @@ _SIGS = {
     "hp_perturb_among": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P,
                          C.c_int32, _P, _P],
     "hp_hpwl": [_P, _P, C.c_int32, _P, _P],
+    "hp_hpwl_noalloc": [_P, C.c_int32, _P, _P],
     "hp_select_best": [_P, _P, C.c_int32, C.c_int32, _P],
     "hp_get_map": [_P, C.c_int32, C.c_int, _P],
     "hp_get_state": [_P, C.c_int32, C.POINTER(hp_slot_state)],
@@ -315,6 +316,12 @@ def hp_hpwl(ctx, slots, want_host=True):
     q = np.zeros(n, dtype=np.int64) if want_host else None
     _chk(lib().hp_hpwl(ctx, p, n, _ptr(q), None))
     return q
+
+
+def hp_hpwl_noalloc(ctx, netlist, xy, out_q):
+    """Exact HPWL of device pairs xy [n_cells, 2] into device int64 out_q [1] (no slot, no
+    allocation; the library's static scratch holds the partial sums)."""
+    _chk(lib().hp_hpwl_noalloc(ctx, int(netlist), _ptr(xy), _ptr(out_q)))
 
 
 def hp_select_best(ctx, slots, incumbent, want_host=True):
