@@ -344,15 +344,18 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
         return fail(HP_EINVAL, "bin grid too large for this device's LDS at this precision");
 
     // ---- degree buckets -------------------------------------------------------------------
-    // order: block-per-net (largest first), then waves with 256 and 128 slots per net, then
-    // groups of 64, 32, ..., 2 lanes
+    // G = 0: nets over 256 pins, a block each; G = 256, 128, ..., 4: G = next power of two >= d
+    // (d >= 3) slots per net, spread over G / 4 lanes; G = 2: two-pin nets, a lane each.
     constexpr int NB = 9;
     const int Gs[NB] = {0, 256, 128, 64, 32, 16, 8, 4, 2};
     // Every bucket but the first is laid out padded: net j of the bucket owns pin slots
     // [pin0 + j G, pin0 + (j + 1) G), its pins first, the rest marked by cell -1, so a lane
-    // finds its pin slots from its index alone (G < 2d, so at most 2P slots).  Each block
-    // takes kNetsPerLane x (256 / G) nets of a group bucket, 4 nets (one per wave) of a wave
-    // bucket, one net of the first.
+    // finds its pin slots from its index alone (G < 2d, so at most 2P slots).  The padded
+    // buckets come first in memory, largest G first, so every net's slots start at a multiple
+    // of 4 (of 2 for G = 2) and lanes load four slots at once; the block-per-net bucket comes
+    // last in memory but first in the grid (its long nets start early).  Each block takes
+    // 4 kBlock / G nets of a padded bucket with G >= 4, kPairNets kBlock two-pin nets, or one
+    // net of the first bucket.
     std::vector<std::vector<int>> members(NB);
     for (int e = 0; e < E; ++e) {
         const int d = net_start[e + 1] - net_start[e];
@@ -368,7 +371,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     std::stable_sort(members[0].begin(), members[0].end(), [&](int a, int b) {
         return net_start[a + 1] - net_start[a] > net_start[b + 1] - net_start[b];
     });
-    // group-per-net buckets: order nets by their lowest cell, so neighbouring lanes gather
+    // padded buckets: order nets by their lowest cell, so neighbouring lanes gather
     // neighbouring cells and each XCD's share of a bucket covers a compact cell range
     {
         std::vector<int32_t> minc(E, 0);
@@ -381,19 +384,27 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
             std::stable_sort(members[b].begin(), members[b].end(),
                              [&](int a, int c) { return minc[a] < minc[c]; });
     }
-    std::vector<int> order;
+    // sweep order of the nets (memory order): padded buckets by decreasing G, then the
+    // block-per-net bucket
+    const int mem_order[NB] = {1, 2, 3, 4, 5, 6, 7, 8, 0};
+    std::vector<int> order, first(NB, 0);
+    for (int m = 0; m < NB; ++m) {
+        const int b = mem_order[m];
+        first[b] = (int)order.size();
+        order.insert(order.end(), members[b].begin(), members[b].end());
+    }
+    // bucket entries in grid order: the block-per-net bucket, then G = 256 ... 2
     Buckets bk{};
     int blk = 0;
     for (int b = 0; b < NB; ++b) {
         if (members[b].empty()) continue;
         const int G = Gs[b];
-        const int npb = G == 0 ? 1 : G > 64 ? kBlock / 64 : kNetsPerLane * (kBlock / G);
+        const int npb = G == 0 ? 1 : G == 2 ? kPairNets * kBlock : 4 * kBlock / G;
         int nblk = ((int)members[b].size() + npb - 1) / npb;
         nblk = (nblk + kXcds - 1) / kXcds * kXcds;
         bk.G[bk.n] = G;
-        bk.net0[bk.n] = (int)order.size();
-        order.insert(order.end(), members[b].begin(), members[b].end());
-        bk.net1[bk.n] = (int)order.size();
+        bk.net0[bk.n] = first[b];
+        bk.net1[bk.n] = first[b] + (int)members[b].size();
         bk.blk0[bk.n] = blk;
         bk.nblk[bk.n] = nblk;
         blk += nblk;
@@ -419,7 +430,12 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     bool any_w = false, offq_exact = true;
     if (net_weight)
         for (int e = 0; e < E; ++e) any_w |= net_weight[e] != 1.0;
-    for (int b = 0, i = 0; b < bk.n; ++b) {
+    // entries in memory order (by their first sweep net)
+    std::vector<int> by_mem(bk.n);
+    std::iota(by_mem.begin(), by_mem.end(), 0);
+    std::sort(by_mem.begin(), by_mem.end(), [&](int a, int c) { return bk.net0[a] < bk.net0[c]; });
+    for (int m = 0, i = 0; m < bk.n; ++m) {
+        const int b = by_mem[m];
         const int G = bk.G[b];
         bk.pin0[b] = (int32_t)h_pc.size();
         for (; i < bk.net1[b]; ++i) {

@@ -14,7 +14,7 @@ constexpr int kMaxBuckets = 12;
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
 constexpr int kChunk = 2048;     // cells per accumulation block of the binned scatter
 constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
-constexpr int kNetsPerLane = 2;  // nets each lane group sweeps (their loads issued together)
+constexpr int kPairNets = 2;     // two-pin nets each lane sweeps (their loads issued together)
 constexpr int kBigHalo = 8;      // movable cells whose charge can span more than kBigHalo + 1
 constexpr int kBigArea = 8;      // bins on an axis, or covers kBigArea bin areas or more, are
                                  // "big" (the macros): scattered and gathered one block per
@@ -25,14 +25,13 @@ template <> struct V2<float> { using type = float2; };
 template <> struct V2<double> { using type = double2; };
 template <typename T> using vec2 = typename V2<T>::type;
 
-// Degree buckets of the net sweep: nets with 2..64 pins are processed by a group of G
-// lanes (G = next power of two >= degree; kNetsPerLane nets per group), nets with 65..256
-// pins by one wave each (G = next power of two >= degree slots, G / 64 pins per lane), larger
-// ones by a whole block.
+// Degree buckets of the net sweep: two-pin nets take a lane each (kPairNets per lane); nets
+// with 3..256 pins own G = next power of two >= degree slots (at least 4) and span G / 4 lanes,
+// four slots per lane; larger nets take a whole block.
 struct Buckets {
     int32_t n;
-    int32_t G[kMaxBuckets];      // pin slots per net (group size up to 64), 0: block-per-net
-    int32_t net0[kMaxBuckets];   // first (sorted) net of the bucket
+    int32_t G[kMaxBuckets];      // pin slots per net (2 .. 256), 0: block-per-net
+    int32_t net0[kMaxBuckets];   // first (sorted) net of the bucket; entries are in grid order
     int32_t net1[kMaxBuckets];
     int32_t blk0[kMaxBuckets];   // first block; every bucket has a multiple of 8 blocks
     int32_t nblk[kMaxBuckets];

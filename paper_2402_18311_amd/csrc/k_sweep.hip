@@ -1,18 +1,18 @@
 // Net sweeps over the pin CSR: the weighted-average wirelength of Eq. 3 with its per-pin
 // gradient, and the exact HPWL of Eq. 1.
 //
-// Nets are grouped at load time by degree.  A net with d <= 64 pins is handled by an aligned
-// group of G = nextpow2(d) lanes, one pin per lane, in a padded layout (G pin slots per net)
-// so that a lane finds its pin without reading the net's start: the pin loads of a wave are
-// contiguous (coalesced), the cell-position loads (one interleaved (x, y) pair per pin) are
-// the only gathers, and the max/min/exp-sum reductions are xor butterflies inside the group.
-// A net with 65..256 pins gets one wave, in the same padded layout with S = 64 PPL slots
-// (PPL = 2 or 4 pins per lane, lane l holding slots l, l + 64, ...), its reductions within the
-// wave; a larger net gets a whole block, which stages up to 2048 of its pin coordinates in
-// LDS for its three passes (max/min, exp sums, gradients).  Within a bucket nets are ordered by their
-// lowest cell, and the blocks of each bucket are remapped so that every XCD walks one
-// contiguous eighth of it: neighbouring lanes then gather neighbouring cells, and each XCD's
-// gathers stay in a compact cell range.
+// Nets are grouped at load time by degree into buckets laid out padded: a net of a bucket of
+// G slots (G = next power of two >= its degree, at least 4 from three pins up) owns G
+// consecutive pin slots, its pins first and the rest marked by cell -1, so a lane finds its
+// slots from its index alone.  Two-pin nets (the largest bucket) take one lane each and the
+// closed form of Eq. 3 for two pins; a net of G >= 4 slots spans LP = G / 4 consecutive lanes,
+// each owning four consecutive slots that it loads with single 16-byte loads (cell ids,
+// offsets), so every pin's exponentials are formed exactly once and the max / min / exp-sum
+// reductions run over log2(LP) lane steps.  Nets over 256 pins get a whole block, which
+// stages up to 2048 of its pin coordinates in LDS for its three passes (max/min, exp sums,
+// gradients).  Within a bucket nets are ordered by their lowest cell, and the blocks of each
+// bucket are remapped so that every XCD walks one contiguous eighth of it: neighbouring
+// lanes then gather neighbouring cells, and each XCD's gathers stay in a compact cell range.
 #include "hp_binning.h"
 
 namespace hp {
@@ -24,143 +24,197 @@ namespace hp {
 //   r+ = sum (x_i - m+) a+_i / sum a+_i,  r- = sum (x_i - m-) a-_i / sum a-_i
 //   WL = (m+ - m-) + r+ - r-                                          (Eq. 3, rescaled)
 //   dWL/dx_i = a+_i/b+ (1 + (x_i - m+ - r+)/gamma) - a-_i/b- (1 - (x_i - m- - r-)/gamma)
-// Group buckets: nets of the bucket are laid out padded (net j owns pin slots pin0 + j G ...,
-// padding lanes hold cell -1), so a lane's pin slot follows from its index: one round of
-// loads (cell index, offset) and one of gathers (position).  A block takes R = kNetsPerLane
-// consecutive runs of 256 / G nets; every lane issues the loads of its R nets before using any.
+// For two pins at distance D this is WL = D tanh(t), t = D / (2 gamma), and the pin further
+// along the axis gets dWL/dx = tanh(t) + t (1 - tanh(t)^2), the other its negative.
+//
 // With H, the same lanes also form the exact HPWL (Eq. 1) of the positions `posu` over the
-// same nets (the pin loads are shared; see hpwl_groups for the arithmetic), added to h.  When
-// every offset is a multiple of 2^-16 (nd.offq_exact), the quantized offset is formed from the
-// float one (the same integer) instead of being loaded.
-template <typename T, int G, bool H>
-__device__ __forceinline__ void wa_groups(const NetDev &nd, const Buckets &bk, int b, int local,
-                                          const vec2<T> *__restrict__ pos, T invg,
-                                          vec2<T> *__restrict__ pg, double &wl,
-                                          const vec2<T> *__restrict__ posu, int64_t &h) {
-    constexpr int NPB = kBlock / G, R = kNetsPerLane;
-    const int lane = threadIdx.x & (G - 1);
-    const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
-    const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
-    // all loads issued on clamped in-range indices before any use: a net past the bucket's end
-    // reads the bucket's first slot, a padding lane's cell -1 reads cell 0; both are ignored
-    int net[R], p[R], c[R];
-    vec2<T> o[R];
-    int2 oq[R];
+// same nets (the pin loads are shared): per pin q16(cell) + q16(offset) in integers, per net
+// the x and y extents, added to h by the net's first lane.  When every offset is a multiple of
+// 2^-16 (nd.offq_exact), the quantized offset is formed from the float one (the same integer)
+// instead of being loaded.
+
+// Four consecutive pin slots (slot a multiple of 4): cell ids and offsets by 16-byte loads.
+template <typename T>
+__device__ __forceinline__ void load_slots4(const NetDev &nd, int slot, int (&c)[4],
+                                            vec2<T> (&o)[4]) {
+    const int4 cc = *reinterpret_cast<const int4 *>(nd.pin_cell + slot);
+    c[0] = cc.x;
+    c[1] = cc.y;
+    c[2] = cc.z;
+    c[3] = cc.w;
+    const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off) + slot;
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(off);
+        const float4 b = *reinterpret_cast<const float4 *>(off + 2);
+        o[0] = cmk2<T>(a.x, a.y);
+        o[1] = cmk2<T>(a.z, a.w);
+        o[2] = cmk2<T>(b.x, b.y);
+        o[3] = cmk2<T>(b.z, b.w);
+    } else {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        net[r] = net0 + (local * R + r) * NPB + (int)threadIdx.x / G;
-        p[r] = net[r] < net1 ? pin0 + (net[r] - net0) * G + lane : pin0;
-        c[r] = nd.pin_cell[p[r]];
-        o[r] = off[p[r]];
-        if constexpr (H)
-            oq[r] = nd.offq_exact ? make_int2(q16i<T>(o[r].x), q16i<T>(o[r].y)) : nd.pin_offq[p[r]];
+        for (int k = 0; k < 4; ++k) o[k] = off[k];
     }
-    vec2<T> q[R], qu[R];
+}
+__device__ __forceinline__ void load_offq4(const NetDev &nd, int slot, int2 (&q)[4]) {
+    const int4 a = *reinterpret_cast<const int4 *>(nd.pin_offq + slot);
+    const int4 b = *reinterpret_cast<const int4 *>(nd.pin_offq + slot + 2);
+    q[0] = make_int2(a.x, a.y);
+    q[1] = make_int2(a.z, a.w);
+    q[2] = make_int2(b.x, b.y);
+    q[3] = make_int2(b.z, b.w);
+}
+// Four gradient pairs to four consecutive slots.
+template <typename T>
+__device__ __forceinline__ void store_grad4(vec2<T> *pg, const T (&gx)[4], const T (&gy)[4]) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(pg) = make_float4(gx[0], gy[0], gx[1], gy[1]);
+        *reinterpret_cast<float4 *>(pg + 2) = make_float4(gx[2], gy[2], gx[3], gy[3]);
+    } else {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        q[r] = pos[max(c[r], 0)];
-        if constexpr (H) qu[r] = posu[max(c[r], 0)];
-    }
-    if constexpr (H) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const bool act = c[r] >= 0 && net[r] < net1;
-            const int ux = act ? q16i<T>(qu[r].x) + oq[r].x : 0;
-            const int uy = act ? q16i<T>(qu[r].y) + oq[r].y : 0;
-            const int xM = group_max<G>(act ? ux : INT_MIN), xm = group_min<G>(act ? ux : INT_MAX);
-            const int yM = group_max<G>(act ? uy : INT_MIN), ym = group_min<G>(act ? uy : INT_MAX);
-            if (act && lane == 0) h += ((int64_t)xM - xm) + ((int64_t)yM - ym);
-        }
-    }
-    T px[R], py[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (net[r] >= net1) c[r] = -1;
-        px[r] = c[r] >= 0 ? q[r].x + o[r].x : T(0);
-        py[r] = c[r] >= 0 ? q[r].y + o[r].y : T(0);
-    }
-    const T inf = pos_inf<T>();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const bool act = c[r] >= 0, vnet = net[r] < net1;
-        const T xmax = group_max<G>(act ? px[r] : -inf), xmin = group_min<G>(act ? px[r] : inf);
-        const T ymax = group_max<G>(act ? py[r] : -inf), ymin = group_min<G>(act ? py[r] : inf);
-        const T dxp = act ? px[r] - xmax : T(0), dxm = act ? px[r] - xmin : T(0);
-        const T dyp = act ? py[r] - ymax : T(0), dym = act ? py[r] - ymin : T(0);
-        const T axp = act ? wa_exp<T>(dxp * invg) : T(0), axm = act ? wa_exp<T>(-dxm * invg) : T(0);
-        const T ayp = act ? wa_exp<T>(dyp * invg) : T(0), aym = act ? wa_exp<T>(-dym * invg) : T(0);
-        // b >= 1 for a real net (its extreme pin contributes exp(0)); padding-only groups are
-        // never written or counted
-        const T ibxp = wa_rcp<T>(group_sum<G>(axp)), ibxm = wa_rcp<T>(group_sum<G>(axm));
-        const T ibyp = wa_rcp<T>(group_sum<G>(ayp)), ibym = wa_rcp<T>(group_sum<G>(aym));
-        const T rxp = group_sum<G>(dxp * axp) * ibxp, rxm = group_sum<G>(dxm * axm) * ibxm;
-        const T ryp = group_sum<G>(dyp * ayp) * ibyp, rym = group_sum<G>(dym * aym) * ibym;
-        const T w = (vnet && nd.net_w) ? reinterpret_cast<const T *>(nd.net_w)[net[r]] : T(1);
-        if (act) {
-            const T gx = axp * ibxp * (T(1) + (dxp - rxp) * invg) - axm * ibxm * (T(1) - (dxm - rxm) * invg);
-            const T gy = ayp * ibyp * (T(1) + (dyp - ryp) * invg) - aym * ibym * (T(1) - (dym - rym) * invg);
-            pg[p[r]] = cmk2<T>(w * gx, w * gy);
-        }
-        if (vnet && lane == 0)
-            wl += (double)(w * (((xmax - xmin) + (rxp - rxm)) + ((ymax - ymin) + (ryp - rym))));
+        for (int k = 0; k < 4; ++k) pg[k] = cmk2<T>(gx[k], gy[k]);
     }
 }
 
-// Wave-per-net sweep of a padded bucket with S = 64 PPL slots per net: each wave takes one net
-// and each lane PPL of its pins (all loads issued before use), sums over them in slot order,
-// then the wave's butterflies.
-template <typename T, int PPL, bool H>
-__device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int b, int local,
-                                        const vec2<T> *__restrict__ pos, T invg,
-                                        vec2<T> *__restrict__ pg, double &wl,
-                                        const vec2<T> *__restrict__ posu, int64_t &h) {
-    constexpr int S = 64 * PPL;
-    const int lane = threadIdx.x & 63;
-    const int net0 = bk.net0[b], net1 = bk.net1[b];
-    const int net = net0 + local * (kBlock / 64) + (int)threadIdx.x / 64;
-    const bool vnet = net < net1;
-    const int p0 = bk.pin0[b] + (vnet ? (net - net0) * S : 0) + lane;
+// tanh(t) of t = D / (2 gamma) >= 0 as (1 - e) / (1 + e), e = exp(-D / gamma), with 1 - e
+// formed by expm1 so that short nets keep their relative accuracy.
+template <typename T> __device__ __forceinline__ T wa_tanh2(T d_over_gamma);
+template <> __device__ __forceinline__ float wa_tanh2<float>(float u) {
+    return -expm1f(-u) * __builtin_amdgcn_rcpf(1.0f + __expf(-u));
+}
+template <> __device__ __forceinline__ double wa_tanh2<double>(double u) {
+    return -expm1(-u) / (1.0 + exp(-u));
+}
+
+// Two-pin nets, one lane each, kPairNets per lane (net = net0 + (local kPairNets + r) kBlock +
+// lane, so a wave's loads are contiguous): WL = D tanh(D / 2 gamma) per axis.
+template <typename T, bool H>
+__device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, int b, int local,
+                                         const vec2<T> *__restrict__ pos, T invg,
+                                         vec2<T> *__restrict__ pg, double &wl,
+                                         const vec2<T> *__restrict__ posu, int64_t &h) {
+    constexpr int R = kPairNets;
+    const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
-    int c[PPL];
-    vec2<T> o[PPL];
-    int2 oq[PPL];
+    int net[R], slot[R];
+    int2 c[R];
+    vec2<T> o0[R], o1[R];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        c[k] = nd.pin_cell[p0 + 64 * k];
-        o[k] = off[p0 + 64 * k];
-        if constexpr (H)
-            oq[k] = nd.offq_exact ? make_int2(q16i<T>(o[k].x), q16i<T>(o[k].y)) : nd.pin_offq[p0 + 64 * k];
+    for (int r = 0; r < R; ++r) {  // loads on clamped in-range slots first
+        net[r] = net0 + (local * R + r) * kBlock + (int)threadIdx.x;
+        slot[r] = pin0 + (net[r] < net1 ? 2 * (net[r] - net0) : 0);
+        c[r] = *reinterpret_cast<const int2 *>(nd.pin_cell + slot[r]);
+        if constexpr (sizeof(T) == 4) {
+            const float4 a = *reinterpret_cast<const float4 *>(off + slot[r]);
+            o0[r] = cmk2<T>(a.x, a.y);
+            o1[r] = cmk2<T>(a.z, a.w);
+        } else {
+            o0[r] = off[slot[r]];
+            o1[r] = off[slot[r] + 1];
+        }
     }
-    vec2<T> q[PPL], qu[PPL];
+    vec2<T> q0[R], q1[R], u0[R], u1[R];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
+    for (int r = 0; r < R; ++r) {
+        q0[r] = pos[c[r].x];
+        q1[r] = pos[c[r].y];
+        if constexpr (H) {
+            u0[r] = posu[c[r].x];
+            u1[r] = posu[c[r].y];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (net[r] >= net1) continue;
+        if constexpr (H) {
+            int2 oq0, oq1;
+            if (nd.offq_exact) {
+                oq0 = make_int2(q16i<T>(o0[r].x), q16i<T>(o0[r].y));
+                oq1 = make_int2(q16i<T>(o1[r].x), q16i<T>(o1[r].y));
+            } else {
+                const int4 a = *reinterpret_cast<const int4 *>(nd.pin_offq + slot[r]);
+                oq0 = make_int2(a.x, a.y);
+                oq1 = make_int2(a.z, a.w);
+            }
+            const int dx = (q16i<T>(u0[r].x) + oq0.x) - (q16i<T>(u1[r].x) + oq1.x);
+            const int dy = (q16i<T>(u0[r].y) + oq0.y) - (q16i<T>(u1[r].y) + oq1.y);
+            h += (int64_t)abs(dx) + (int64_t)abs(dy);
+        }
+        const T dx = (q0[r].x + o0[r].x) - (q1[r].x + o1[r].x);
+        const T dy = (q0[r].y + o0[r].y) - (q1[r].y + o1[r].y);
+        const T ax = fabs(dx), ay = fabs(dy);
+        const T thx = wa_tanh2<T>(ax * invg), thy = wa_tanh2<T>(ay * invg);
+        const T tx = T(0.5) * ax * invg, ty = T(0.5) * ay * invg;
+        const T w = nd.net_w ? reinterpret_cast<const T *>(nd.net_w)[net[r]] : T(1);
+        const T gx = w * (thx + tx * (T(1) - thx * thx)), gy = w * (thy + ty * (T(1) - thy * thy));
+        const T sx = dx >= T(0) ? gx : -gx, sy = dy >= T(0) ? gy : -gy;
+        if constexpr (sizeof(T) == 4)
+            *reinterpret_cast<float4 *>(pg + slot[r]) = make_float4(sx, sy, -sx, -sy);
+        else {
+            pg[slot[r]] = cmk2<T>(sx, sy);
+            pg[slot[r] + 1] = cmk2<T>(-sx, -sy);
+        }
+        wl += (double)(w * (ax * thx + ay * thy));
+    }
+}
+
+// Nets of G = 4 LP slots, LP lanes each (LP = 1 .. 64), one net per lane group and block row:
+// lane l of the group owns slots 4 l .. 4 l + 3 of its net.
+template <typename T, int LP, bool H>
+__device__ __forceinline__ void wa_lanes(const NetDev &nd, const Buckets &bk, int b, int local,
+                                         const vec2<T> *__restrict__ pos, T invg,
+                                         vec2<T> *__restrict__ pg, double &wl,
+                                         const vec2<T> *__restrict__ posu, int64_t &h) {
+    constexpr int G = 4 * LP, NPB = kBlock / LP;
+    const int l = threadIdx.x & (LP - 1);
+    const int net0 = bk.net0[b], net1 = bk.net1[b];
+    const int net = net0 + local * NPB + (int)threadIdx.x / LP;
+    const bool vnet = net < net1;
+    const int slot = bk.pin0[b] + (vnet ? (net - net0) * G : 0) + 4 * l;
+    // every load issued on in-range slots before any use (a net past the bucket's end reads
+    // its first net's slots, a padding slot's cell -1 reads cell 0; both are ignored)
+    int c[4];
+    vec2<T> o[4];
+    load_slots4<T>(nd, slot, c, o);
+    int2 oq[4];
+    if constexpr (H) {
+        if (nd.offq_exact) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) oq[k] = make_int2(q16i<T>(o[k].x), q16i<T>(o[k].y));
+        } else {
+            load_offq4(nd, slot, oq);
+        }
+    }
+    vec2<T> q[4], qu[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
         q[k] = pos[max(c[k], 0)];
         if constexpr (H) qu[k] = posu[max(c[k], 0)];
     }
-    if constexpr (H) {  // exact HPWL of posu over the same pins (see hpwl_wave)
-        int uM = INT_MIN, um = INT_MAX, vM = INT_MIN, vm = INT_MAX;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            if (vnet && c[k] >= 0) {
-                const int ux = q16i<T>(qu[k].x) + oq[k].x, uy = q16i<T>(qu[k].y) + oq[k].y;
-                uM = max(uM, ux);
-                um = min(um, ux);
-                vM = max(vM, uy);
-                vm = min(vm, uy);
-            }
+    for (int k = 0; k < 4; ++k)
+        if (!vnet) c[k] = -1;
+    if constexpr (H) {
+        int xM = INT_MIN, xm = INT_MAX, yM = INT_MIN, ym = INT_MAX;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (c[k] < 0) continue;
+            const int ux = q16i<T>(qu[k].x) + oq[k].x, uy = q16i<T>(qu[k].y) + oq[k].y;
+            xM = max(xM, ux);
+            xm = min(xm, ux);
+            yM = max(yM, uy);
+            ym = min(ym, uy);
         }
-        uM = group_max<64>(uM);
-        um = group_min<64>(um);
-        vM = group_max<64>(vM);
-        vm = group_min<64>(vm);
-        if (vnet && lane == 0) h += ((int64_t)uM - um) + ((int64_t)vM - vm);
+        xM = group_max<LP>(xM);
+        xm = group_min<LP>(xm);
+        yM = group_max<LP>(yM);
+        ym = group_min<LP>(ym);
+        if (vnet && l == 0) h += ((int64_t)xM - xm) + ((int64_t)yM - ym);
     }
     const T inf = pos_inf<T>();
-    T px[PPL], py[PPL];
+    T px[4], py[4];
     T xM = -inf, xm = inf, yM = -inf, ym = inf;
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        if (!vnet) c[k] = -1;
+    for (int k = 0; k < 4; ++k) {
         px[k] = c[k] >= 0 ? q[k].x + o[k].x : T(0);
         py[k] = c[k] >= 0 ? q[k].y + o[k].y : T(0);
         if (c[k] >= 0) {
@@ -170,15 +224,15 @@ __device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int
             ym = min(ym, py[k]);
         }
     }
-    xM = group_max<64>(xM);
-    xm = group_min<64>(xm);
-    yM = group_max<64>(yM);
-    ym = group_min<64>(ym);
+    xM = group_max<LP>(xM);
+    xm = group_min<LP>(xm);
+    yM = group_max<LP>(yM);
+    ym = group_min<LP>(ym);
     // the exponentials are formed again in the gradient pass rather than held (register
     // pressure sets the occupancy of the whole first launch)
     T sm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
+    for (int k = 0; k < 4; ++k) {
         const bool act = c[k] >= 0;
         const T dxp = act ? px[k] - xM : T(0), dxm = act ? px[k] - xm : T(0);
         const T dyp = act ? py[k] - yM : T(0), dym = act ? py[k] - ym : T(0);
@@ -194,23 +248,28 @@ __device__ __forceinline__ void wa_wave(const NetDev &nd, const Buckets &bk, int
         sm[7] += dym * aym;
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) sm[j] = group_sum<64>(sm[j]);
-    // an invalid wave (past the bucket's end) has only zero sums; it writes nothing
+    for (int j = 0; j < 8; ++j) sm[j] = group_sum<LP>(sm[j]);
+    // b >= 1 for a real net (its extreme pin contributes exp(0)); an invalid group has only
+    // zero sums and writes nothing
     const T ibxp = wa_rcp<T>(sm[0]), ibxm = wa_rcp<T>(sm[1]);
     const T ibyp = wa_rcp<T>(sm[2]), ibym = wa_rcp<T>(sm[3]);
     const T rxp = sm[4] * ibxp, rxm = sm[5] * ibxm, ryp = sm[6] * ibyp, rym = sm[7] * ibym;
     const T w = (vnet && nd.net_w) ? reinterpret_cast<const T *>(nd.net_w)[net] : T(1);
+    T gx[4], gy[4];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        if (c[k] < 0) continue;
+    for (int k = 0; k < 4; ++k) {
         const T dxp = px[k] - xM, dxm = px[k] - xm, dyp = py[k] - yM, dym = py[k] - ym;
         const T axp = wa_exp<T>(dxp * invg), axm = wa_exp<T>(-dxm * invg);
         const T ayp = wa_exp<T>(dyp * invg), aym = wa_exp<T>(-dym * invg);
-        const T gx = axp * ibxp * (T(1) + (dxp - rxp) * invg) - axm * ibxm * (T(1) - (dxm - rxm) * invg);
-        const T gy = ayp * ibyp * (T(1) + (dyp - ryp) * invg) - aym * ibym * (T(1) - (dym - rym) * invg);
-        pg[p0 + 64 * k] = cmk2<T>(w * gx, w * gy);
+        gx[k] = c[k] < 0 ? T(0)
+                         : w * (axp * ibxp * (T(1) + (dxp - rxp) * invg) -
+                                axm * ibxm * (T(1) - (dxm - rxm) * invg));
+        gy[k] = c[k] < 0 ? T(0)
+                         : w * (ayp * ibyp * (T(1) + (dyp - ryp) * invg) -
+                                aym * ibym * (T(1) - (dym - rym) * invg));
     }
-    if (vnet && lane == 0)
+    if (vnet) store_grad4<T>(pg + slot, gx, gy);
+    if (vnet && l == 0)
         wl += (double)(w * (((xM - xm) + (rxp - rxm)) + ((yM - ym) + (ryp - rym))));
 }
 
@@ -327,80 +386,69 @@ __device__ void wa_block(const NetDev &nd, int net, const vec2<T> *__restrict__ 
 
 // ---- exact HPWL ----------------------------------------------------------------------------
 // Pin coordinate q16(cell) + q16(offset), both exact integers; per net the x and y extents.
-template <typename T, int G>
-__device__ __forceinline__ int64_t hpwl_groups(const NetDev &nd, const Buckets &bk, int b, int local,
-                                               const vec2<T> *__restrict__ pos) {
-    constexpr int NPB = kBlock / G, R = kNetsPerLane;
-    const int lane = threadIdx.x & (G - 1);
+template <typename T>
+__device__ __forceinline__ int64_t hpwl_pairs(const NetDev &nd, const Buckets &bk, int b, int local,
+                                              const vec2<T> *__restrict__ pos) {
+    constexpr int R = kPairNets;
     const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
-    int p[R], c[R];
-    int2 o[R];
-    bool vn[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {  // loads on clamped indices first (see wa_groups)
-        const int net = net0 + (local * R + r) * NPB + (int)threadIdx.x / G;
-        vn[r] = net < net1;
-        p[r] = vn[r] ? pin0 + (net - net0) * G + lane : pin0;
-        c[r] = nd.pin_cell[p[r]];
-        o[r] = nd.pin_offq[p[r]];
-    }
-    vec2<T> q[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) q[r] = pos[max(c[r], 0)];
-    int px[R], py[R];
+    int net[R];
+    int2 c[R];
+    int4 oq[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        if (!vn[r]) c[r] = -1;
-        px[r] = c[r] >= 0 ? q16i<T>(q[r].x) + o[r].x : 0;
-        py[r] = c[r] >= 0 ? q16i<T>(q[r].y) + o[r].y : 0;
+        net[r] = net0 + (local * R + r) * kBlock + (int)threadIdx.x;
+        const int slot = pin0 + (net[r] < net1 ? 2 * (net[r] - net0) : 0);
+        c[r] = *reinterpret_cast<const int2 *>(nd.pin_cell + slot);
+        oq[r] = *reinterpret_cast<const int4 *>(nd.pin_offq + slot);
+    }
+    vec2<T> q0[R], q1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        q0[r] = pos[c[r].x];
+        q1[r] = pos[c[r].y];
     }
     int64_t h = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const bool act = c[r] >= 0;
-        const int xM = group_max<G>(act ? px[r] : INT_MIN), xm = group_min<G>(act ? px[r] : INT_MAX);
-        const int yM = group_max<G>(act ? py[r] : INT_MIN), ym = group_min<G>(act ? py[r] : INT_MAX);
-        if (act && lane == 0) h += ((int64_t)xM - xm) + ((int64_t)yM - ym);
+        if (net[r] >= net1) continue;
+        const int dx = (q16i<T>(q0[r].x) + oq[r].x) - (q16i<T>(q1[r].x) + oq[r].z);
+        const int dy = (q16i<T>(q0[r].y) + oq[r].y) - (q16i<T>(q1[r].y) + oq[r].w);
+        h += (int64_t)abs(dx) + (int64_t)abs(dy);
     }
     return h;
 }
 
-// Wave-per-net HPWL of a padded bucket with S = 64 PPL slots per net (see wa_wave).
-template <typename T, int PPL>
-__device__ __forceinline__ int64_t hpwl_wave(const NetDev &nd, const Buckets &bk, int b, int local,
-                                             const vec2<T> *__restrict__ pos) {
-    constexpr int S = 64 * PPL;
-    const int lane = threadIdx.x & 63;
+template <typename T, int LP>
+__device__ __forceinline__ int64_t hpwl_lanes(const NetDev &nd, const Buckets &bk, int b, int local,
+                                              const vec2<T> *__restrict__ pos) {
+    constexpr int G = 4 * LP, NPB = kBlock / LP;
+    const int l = threadIdx.x & (LP - 1);
     const int net0 = bk.net0[b], net1 = bk.net1[b];
-    const int net = net0 + local * (kBlock / 64) + (int)threadIdx.x / 64;
+    const int net = net0 + local * NPB + (int)threadIdx.x / LP;
     const bool vnet = net < net1;
-    const int p0 = bk.pin0[b] + (vnet ? (net - net0) * S : 0) + lane;
-    int c[PPL];
-    int2 o[PPL];
+    const int slot = bk.pin0[b] + (vnet ? (net - net0) * G : 0) + 4 * l;
+    const int4 cc = *reinterpret_cast<const int4 *>(nd.pin_cell + slot);
+    const int c[4] = {cc.x, cc.y, cc.z, cc.w};
+    int2 oq[4];
+    load_offq4(nd, slot, oq);
+    vec2<T> q[4];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        c[k] = nd.pin_cell[p0 + 64 * k];
-        o[k] = nd.pin_offq[p0 + 64 * k];
-    }
-    vec2<T> q[PPL];
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) q[k] = pos[max(c[k], 0)];
+    for (int k = 0; k < 4; ++k) q[k] = pos[max(c[k], 0)];
     int xM = INT_MIN, xm = INT_MAX, yM = INT_MIN, ym = INT_MAX;
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) {
-        if (vnet && c[k] >= 0) {
-            const int px = q16i<T>(q[k].x) + o[k].x, py = q16i<T>(q[k].y) + o[k].y;
-            xM = max(xM, px);
-            xm = min(xm, px);
-            yM = max(yM, py);
-            ym = min(ym, py);
-        }
+    for (int k = 0; k < 4; ++k) {
+        if (!vnet || c[k] < 0) continue;
+        const int px = q16i<T>(q[k].x) + oq[k].x, py = q16i<T>(q[k].y) + oq[k].y;
+        xM = max(xM, px);
+        xm = min(xm, px);
+        yM = max(yM, py);
+        ym = min(ym, py);
     }
-    xM = group_max<64>(xM);
-    xm = group_min<64>(xm);
-    yM = group_max<64>(yM);
-    ym = group_min<64>(ym);
-    return (vnet && lane == 0) ? ((int64_t)xM - xm) + ((int64_t)yM - ym) : 0;
+    xM = group_max<LP>(xM);
+    xm = group_min<LP>(xm);
+    yM = group_max<LP>(yM);
+    ym = group_min<LP>(ym);
+    return (vnet && l == 0) ? ((int64_t)xM - xm) + ((int64_t)yM - ym) : 0;
 }
 
 template <typename T>
@@ -457,14 +505,14 @@ template <typename T>
 __device__ __forceinline__ int64_t hpwl_bucket(const NetDev &nd, const Buckets &bk, int b,
                                                int local, const vec2<T> *__restrict__ pos) {
     switch (bk.G[b]) {
-        case 2: return hpwl_groups<T, 2>(nd, bk, b, local, pos);
-        case 4: return hpwl_groups<T, 4>(nd, bk, b, local, pos);
-        case 8: return hpwl_groups<T, 8>(nd, bk, b, local, pos);
-        case 16: return hpwl_groups<T, 16>(nd, bk, b, local, pos);
-        case 32: return hpwl_groups<T, 32>(nd, bk, b, local, pos);
-        case 64: return hpwl_groups<T, 64>(nd, bk, b, local, pos);
-        case 128: return hpwl_wave<T, 2>(nd, bk, b, local, pos);
-        case 256: return hpwl_wave<T, 4>(nd, bk, b, local, pos);
+        case 2: return hpwl_pairs<T>(nd, bk, b, local, pos);
+        case 4: return hpwl_lanes<T, 1>(nd, bk, b, local, pos);
+        case 8: return hpwl_lanes<T, 2>(nd, bk, b, local, pos);
+        case 16: return hpwl_lanes<T, 4>(nd, bk, b, local, pos);
+        case 32: return hpwl_lanes<T, 8>(nd, bk, b, local, pos);
+        case 64: return hpwl_lanes<T, 16>(nd, bk, b, local, pos);
+        case 128: return hpwl_lanes<T, 32>(nd, bk, b, local, pos);
+        case 256: return hpwl_lanes<T, 64>(nd, bk, b, local, pos);
         default:
             return bk.net0[b] + local < bk.net1[b] ? hpwl_block<T>(nd, bk.net0[b] + local, pos) : 0;
     }
@@ -487,14 +535,14 @@ __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, 
         double wl = 0.0;
         int64_t h = 0;
         switch (bk.G[b]) {
-            case 2: wa_groups<T, 2, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 4: wa_groups<T, 4, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 8: wa_groups<T, 8, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 16: wa_groups<T, 16, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 32: wa_groups<T, 32, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 64: wa_groups<T, 64, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 128: wa_wave<T, 2, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 256: wa_wave<T, 4, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 2: wa_pairs<T, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 4: wa_lanes<T, 1, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 8: wa_lanes<T, 2, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 16: wa_lanes<T, 4, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 32: wa_lanes<T, 8, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 64: wa_lanes<T, 16, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 128: wa_lanes<T, 32, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 256: wa_lanes<T, 64, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
             default:
                 if (net0 + local < net1) {
                     wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
