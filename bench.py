@@ -6,10 +6,11 @@ Headline workload: the "large" synthetic netlist (2.2 M movable unit-height cell
 macros on 20% of the die, 2.3 M nets with a power-law degree mix up to 5,000 pins, 1024 x 1024
 bins, FP32 with the int64 charge map), the largest configuration that fits one GPU.  One step
 is one iteration of the plain placer (Sec. 3.1): the objective and gradient of Eq. 2 (WA
-wirelength of Eq. 3, charge scatter, Poisson solve, field gather), the preconditioned Nesterov
-step, and the exact HPWL of Eq. 1 with the overflow.  W untimed iterations from the initial
-positions, then K timed ones of the same placement (its lambda schedule spans the
-configuration's 2,000 iterations).
+wirelength of Eq. 3, charge scatter, Poisson solve, field gather, overflow) and the
+preconditioned Nesterov step, with the exact HPWL of Eq. 1 taken every 10 iterations (the
+cadence at which the Alg. 1 driver reads it; the rate with the HPWL after every iteration is
+reported beside it).  W untimed iterations from the initial positions, then K timed ones of
+the same placement (its lambda schedule spans the configuration's 2,000 iterations).
 
 Prints one JSON line: iterations/s, per-step milliseconds, the roofline of the dominant kernel
 (its share of the compulsory bytes per iteration / its average duration from HIP events on its
@@ -32,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 CONFIG_ITERS = {"large": 2000, "mid": 1000, "tiny": 200}
+HPWL_EVERY = 10  # the Alg. 1 driver reads the exact HPWL and the overflow every 10 iterations
 # Sources that define the first launch of an evaluation (the dominant kernel); a stored HBM
 # traffic record is used only while their hash matches the one it was measured with.
 FRONT_SOURCES = ["paper_2402_18311_amd/csrc/k_sweep.hip", "paper_2402_18311_amd/csrc/hp_binning.h",
@@ -186,6 +188,31 @@ def pmc_summary(fetch_dir, write_dir, kernel="eval_front_kernel", last=None, wor
     print(json.dumps(rec))
 
 
+def trace_summary(trace_dir, last):
+    """Per-kernel launch counts and average durations from a rocprofv3 --kernel-trace CSV:
+    over all launches and over each kernel's last `last` launches (the timed region of a
+    bench run whose timed iterations come last)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)[0]
+    rows = []
+    for r in csv.DictReader(open(f)):
+        name = r["Kernel_Name"].split("(")[0]
+        rows.append((int(r["Start_Timestamp"]), name,
+                     (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3))
+    rows.sort()
+    per = {}
+    for _, name, us in rows:
+        per.setdefault(name, []).append(us)
+    out = {}
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        tail = v[-last:] if last else v
+        out[name] = {"launches": len(v), "avg_us": round(sum(v) / len(v), 2),
+                     "last_launches": len(tail), "last_avg_us": round(sum(tail) / len(tail), 2)}
+    print(json.dumps(out, indent=1))
+    return out
+
+
 def stored_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` on `workload` measured by counters, or None if absent
     or stale (the kernel's sources changed since)."""
@@ -200,15 +227,17 @@ def stored_traffic(kernel, workload):
 
 def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
     """One batched Hybro round (K perturbed restarts of the incumbent, each Gaussian 5%,
-    sigma 8 bins, then T iterations) as one K-slot launch sequence, against the same K
-    restarts solved one slot at a time.  Returns restarts/s of both and whether every
-    restart's final HPWL_q agrees bit for bit."""
+    sigma 8 bins, then T iterations and the exact HPWL of the result): the K restarts one slot
+    at a time, as one K-slot launch sequence, and as K slots with steady-state blocks replayed
+    from a captured HIP graph.  Returns restarts/s of each and whether every restart's final
+    HPWL_q agrees bit for bit across the three."""
     import torch
     ix = torch.empty(nl.n_movable, dtype=torch.float32, device="cuda")
     iy = torch.empty_like(ix)
     hy.hp_get_positions(pl.ctx, inc, ix, iy, True)
     res = {}
-    for mode in ("plain", "batched"):
+    c0, r0 = hy.hp_graph_stats(pl.ctx)
+    for mode in ("plain", "batched", "graph"):
         slots = [pl.new_slot() for _ in range(K)]
         for s in slots:
             pl.set_positions(s, ix, iy)
@@ -218,22 +247,27 @@ def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
         for k, s in enumerate(slots):
             pl.perturb(s, hy.HP_PERTURB_GAUSS, 0.05, 8.0, seed0 + k, want_idx=False)
             if mode == "plain":
-                pl.iterate(s, gamma, T, hpwl=True)
-        if mode == "batched":
-            pl.iterate(slots, gamma, T, hpwl=True)
+                pl.iterate(s, gamma, T, hpwl="last")
+        if mode != "plain":
+            pl.iterate(slots, gamma, T, hpwl="last", graph=mode == "graph")
         q = pl.hpwl(slots)  # reduces the last sweeps (synchronises)
         dt = time.perf_counter() - t0
         res[mode] = (K / dt, dt, [int(v) for v in q])
         for s in slots:
             pl.free_slot(s)
+    c1, r1 = hy.hp_graph_stats(pl.ctx)
     return {"restarts": K, "iterations": T,
             "batched_restarts_per_s": round(res["batched"][0], 3),
+            "graph_restarts_per_s": round(res["graph"][0], 3),
             "plain_restarts_per_s": round(res["plain"][0], 3),
-            "speedup": round(res["batched"][0] / res["plain"][0], 3),
+            "speedup": round(max(res["batched"][0], res["graph"][0]) / res["plain"][0], 3),
             "batched_round_s": round(res["batched"][1], 4),
+            "graph_round_s": round(res["graph"][1], 4),
             "plain_rounds_s": round(res["plain"][1], 4),
-            "equal_hpwl": res["batched"][2] == res["plain"][2],
-            "best_hpwl": min(res["batched"][2]) / 65536}
+            "graph_blocks": {"captured": c1 - c0, "replayed": r1 - r0},
+            "equal_hpwl": res["batched"][2] == res["plain"][2] == res["graph"][2],
+            "best_hpwl": min(res["batched"][2]) / 65536,
+            "hpwl": "exact HPWL of each restart after its last iteration (Alg. 1)"}
 
 
 def mid_lines(hy, netgen, args):
@@ -245,11 +279,11 @@ def mid_lines(hy, netgen, args):
     nl = netgen.make_netlist("mid", args.seed)
     gamma = 4 * nl.bin_w
     K, W = args.mid_steps, args.mid_warmup
-    pl = hy.Placer(nl, precision=32)
+    pl = hy.Placer(nl, precision=32, stream=torch.cuda.Stream())  # capturable stream
     work, inc = pl.new_slot(), pl.new_slot()
     pl.set_positions(work, nl.x0, nl.y0)
     pl.set_schedule(work, 1e-4, 4.0, max(W, 1))
-    pl.iterate(work, gamma, W, hpwl=True)
+    pl.iterate(work, gamma, W, hpwl="last")
     pl.hpwl(work)
     pl.select_best([work], inc)
     ix = torch.empty(nl.n_movable, dtype=torch.float32, device="cuda")
@@ -271,7 +305,7 @@ def mid_lines(hy, netgen, args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     pl.perturb(work, hy.HP_PERTURB_GAUSS, 0.05, 8.0, 0xC0FFEE, want_idx=False)
-    pl.iterate(work, gamma, K, hpwl=True)
+    pl.iterate(work, gamma, K, hpwl="last", graph=True)
     pl.select_best([work], inc, want_host=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -281,7 +315,8 @@ def mid_lines(hy, netgen, args):
     out = {"mid": {
         "workload": f"mid: {nl.n_movable} movable cells, {nl.n_fixed} fixed macros, "
                     f"{nl.n_nets} nets / {nl.n_pins} pins, {nl.mx}x{nl.my} bins, FP32; one Hybro "
-                    f"round (Gaussian perturb 5%, sigma 8 bins) of {K} iterations after a "
+                    f"round (Gaussian perturb 5%, sigma 8 bins) of {K} iterations (HIP-graph "
+                    f"replay of steady-state blocks) and the exact HPWL after them, after a "
                     f"{W}-iteration placement",
         "iter_per_s": round(K / dt, 2), "ms_per_step": round(1e3 * dt / K, 5), "steps": K,
         "warmup": W, "final_hpwl": pl.state(inc)["hpwl_q"] / 65536,
@@ -380,6 +415,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc output folders to the stored traffic "
                          "record and exit")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="reduce a rocprofv3 --kernel-trace output folder to per-kernel "
+                         "averages (all launches and the last --pmc-last of each) and exit")
     ap.add_argument("--scatter-policy", metavar="EVERY,DEFERRED",
                     help="use this charge-scatter policy (e.g. 8,1) instead of timing the "
                          "candidates before the round")
@@ -389,6 +427,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, last=args.pmc_last, workload=args.workload)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.pmc_last)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the placer runs on a single MI355X; "
@@ -411,9 +452,18 @@ def main():
     s = pl.new_slot()
     log(f"[bench] {nl.name}: {nl.n_movable} movable, {nl.n_fixed} fixed, {nl.n_nets} nets, "
         f"{nl.n_pins} pins, {nl.mx}x{nl.my} bins; warmup {W}, steps {K}")
+    def run(slot, iters):
+        """iters placer iterations with the exact HPWL (Eq. 1) and overflow read every
+        HPWL_EVERY iterations, the cadence at which the Alg. 1 driver looks at them."""
+        done = 0
+        while done < iters:
+            c = min(HPWL_EVERY, iters - done)
+            pl.iterate(slot, gamma, c, hpwl="last")
+            done += c
+
     pl.set_positions(s, nl.x0, nl.y0)
     pl.set_schedule(s, 1e-4, 4.0, total)
-    pl.iterate(s, gamma, W, hpwl=True)
+    run(s, W)
     pl.hpwl(s)
     torch.cuda.synchronize()
     log("[bench] warmup done")
@@ -431,19 +481,29 @@ def main():
     # untimed: the kernel table, a scratch slot from the current positions with events on
     # every launch
     prof = {}
+    every_iter_ms = None
     if not args.no_profile:
         P = min(K, 100)
         x, y = pl.positions(s)
         t = pl.new_slot()
         pl.set_positions(t, x, y)
         pl.set_schedule(t, 1e-4, 4.0, total)
-        pl.iterate(t, gamma, 2, hpwl=True)
+        run(t, 2)
         hy.hp_profile_enable(pl.ctx, True)
         hy.hp_profile_read(pl.ctx, reset=True)
-        pl.iterate(t, gamma, P, hpwl=True)
+        run(t, P)
         pl.hpwl(t)
         prof = hy.hp_profile_read(pl.ctx, reset=True)
         hy.hp_profile_enable(pl.ctx, False)
+        # the same iterations with the exact HPWL after every one (for comparison)
+        pl.set_positions(t, x, y)
+        pl.set_schedule(t, 1e-4, 4.0, total)
+        pl.iterate(t, gamma, 2, hpwl=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pl.iterate(t, gamma, P, hpwl=True)
+        pl.hpwl(t)
+        every_iter_ms = 1e3 * (time.perf_counter() - t1) / P
         pl.free_slot(t)
     b_eval, b_step, share = compulsory_bytes(nl)
     kernels = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1), "total_ms": ms}
@@ -457,7 +517,7 @@ def main():
         hy.hp_profile_read(pl.ctx, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pl.iterate(s, gamma, K, hpwl=True)
+    run(s, K)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     live = {}
@@ -495,7 +555,8 @@ def main():
                                f"macros (20% of die), {nl.n_nets} nets / {nl.n_pins} pins, "
                                f"{nl.mx}x{nl.my} bins, FP32 with the int64 charge map, "
                                f"gamma = 4 bins; plain placer iterations {W}..{W + K} of a "
-                               f"{total}-iteration schedule from the initial positions",
+                               f"{total}-iteration schedule from the initial positions, the "
+                               f"exact HPWL and overflow read every {HPWL_EVERY} iterations",
                    "global_batch": 1, "parallelism": "single-gpu"},
         "compulsory_bytes_per_iter": {"eval": b_eval, "step": b_step},
         "hbm_gbps_compulsory": round((b_eval + b_step) / (ms_step * 1e-3) / 1e9, 1),
@@ -505,6 +566,7 @@ def main():
                    "region; kernels: a separate run on a scratch slot from the same positions "
                    "with events on every launch"),
         "final_hpwl": final["hpwl_q"] / 65536,
+        "ms_per_step_hpwl_every_iteration": round(every_iter_ms, 5) if every_iter_ms else None,
         "tuning": {"scatter_policy": {"regroup_every": policy[0], "deferred": policy[1]},
                    "ms_per_iter": {k: round(v, 4) for k, v in tune_ms.items()}},
         "roofline": roof,

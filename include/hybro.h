@@ -200,18 +200,27 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n_slots);
 
 /* `iters` iterations of the placer (Sec. 3.1) on every listed slot, all on the device: each is
  * hp_eval_objective_grad with the slots' scheduled lambda and the given gamma (nothing returned
- * to the host), hp_nesterov_step and, with HP_ITER_HPWL, hp_hpwl without outputs.  Does not
- * synchronise.  HP_ITER_GRAPH (HIP-graph replay of the steady-state iterations) is switched
- * off and returns HP_ENOTIMPL before any launch: its first device run stalled in a later
- * stream synchronisation, and the cause is not established.  Unknown flags or iters < 0:
- * HP_EINVAL. */
-enum { HP_ITER_HPWL = 1, HP_ITER_GRAPH = 2 };
+ * to the host) and hp_nesterov_step; with HP_ITER_HPWL every iteration is followed by hp_hpwl
+ * without outputs, with HP_ITER_HPWL_LAST only the last one (the exact HPWL of Eq. 1 as a
+ * driver reads it, e.g. every 10 iterations).  Does not synchronise.
+ * HP_ITER_GRAPH replays steady-state blocks of 2 x (the scatter's rebuild interval)
+ * iterations from a captured HIP graph: a block is captured once the slots are in steady
+ * state and is replayed whenever the slots' state is the one it was captured from, which
+ * every block returns to; leftover iterations run as usual, and results are bit-identical to
+ * eager iterations.  The graph is kept with the context until another block replaces it, a
+ * slot of it is freed or the context is destroyed.  It needs a context stream other than the
+ * null stream (HP_EINVAL); while per-kernel timing is enabled nothing is captured.  Unknown
+ * flags or iters < 0: HP_EINVAL. */
+enum { HP_ITER_HPWL = 1, HP_ITER_GRAPH = 2, HP_ITER_HPWL_LAST = 4 };
 typedef struct {
     double gamma;
     int32_t flags;
 } hp_iter_params;
 int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const hp_iter_params *p,
                int32_t iters);
+/* Graph blocks captured and replayed by hp_iterate on this context so far (inspection; either
+ * output may be NULL).  No device work. */
+int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays);
 
 /* Perturbation of Alg. 1 / Sec. 4.2 on slot's major solution u, which also restarts the
  * optimiser there.  mode HP_PERTURB_GAUSS: the round(fraction * n_movable) cells with the

@@ -230,6 +230,37 @@ struct Slot {
     bool rho_dirty = false;     // rho holds a kept map, not zeros
 };
 
+// Every field of the host state of a slot that decides the launches of its next iterations.
+bool same_state(const Slot &a, const Slot &b) {
+    return a.alive == b.alive && a.netlist == b.netlist && a.base == b.base &&
+           a.lambda_valid == b.lambda_valid && a.maps_valid == b.maps_valid &&
+           a.hpwl_requested == b.hpwl_requested && a.hpwl_pending == b.hpwl_pending &&
+           a.step_proposed == b.step_proposed && a.step_fused == b.step_fused &&
+           a.totals_pending == b.totals_pending && a.bank == b.bank &&
+           a.since_group == b.since_group && a.rho_dirty == b.rho_dirty;
+}
+
+// A captured block of hp_iterate (HP_ITER_GRAPH): its launches, the call's slots, smoothing and
+// flags, the netlist's launch settings, and the host state of the slots at the block's start,
+// which the block returns them to.
+struct GraphBlock {
+    bool valid = false;
+    std::vector<int32_t> slots;
+    double gamma = 0.0;
+    int flags = 0, regroup_every = 0, fused_parts = 0, spec_threads = 0;
+    bool deferred = false;
+    int len = 0;
+    std::vector<Slot> start;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void drop_graph(GraphBlock &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = GraphBlock{};
+}
+
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
     int l = 0;
@@ -247,6 +278,8 @@ struct hp_ctx {
     int n_cu = 256;  // compute units of the device
     std::vector<Netlist> nets;
     std::vector<Slot> slots;
+    GraphBlock graph;  // the last captured block of hp_iterate (HP_ITER_GRAPH)
+    int64_t graph_captures = 0, graph_replays = 0;
 };
 
 namespace {
@@ -1031,6 +1064,7 @@ int hp_create(hp_ctx **out, int device, void *hip_stream, int precision) {
 int hp_destroy(hp_ctx *ctx) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     const hipError_t e = hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx->graph);
     delete ctx;
     if (e != hipSuccess) return fail(HP_EDEVICE, hipGetErrorString(e));
     return HP_OK;
@@ -1111,6 +1145,8 @@ int hp_slot_free(hp_ctx *ctx, int32_t slot) {
     HP_CHECK(hipStreamSynchronize(ctx->stream));
     s->alive = false;
     s->base = nullptr;
+    const auto &gs = ctx->graph.slots;
+    if (std::find(gs.begin(), gs.end(), slot) != gs.end()) drop_graph(ctx->graph);
     return HP_OK;
 }
 
@@ -1401,11 +1437,12 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
     if (rc) return rc;
     if (!p) return fail(HP_EINVAL, "params is NULL");
     if (iters < 0) return fail(HP_EINVAL, "iters must be >= 0");
-    if (p->flags & ~(HP_ITER_HPWL | HP_ITER_GRAPH)) return fail(HP_EINVAL, "unknown flags");
-    // Graph replay is switched off: its first run on the device stalled (a stream
-    // synchronisation after the replays never returned) and the cause is not established.
-    if (p->flags & HP_ITER_GRAPH)
-        return fail(HP_ENOTIMPL, "HP_ITER_GRAPH is switched off (its replay stalled; cause open)");
+    if (p->flags & ~(HP_ITER_HPWL | HP_ITER_GRAPH | HP_ITER_HPWL_LAST))
+        return fail(HP_EINVAL, "unknown flags");
+    const bool graph = (p->flags & HP_ITER_GRAPH) != 0;
+    if (graph && ctx->stream == nullptr)
+        return fail(HP_EINVAL, "HP_ITER_GRAPH needs a context stream other than the null stream "
+                               "(the legacy default stream cannot be captured)");
     const hp_eval_params ep{p->gamma, -1.0, 0, 0};
     HP_TRY(check_eval_params(&ep));
     const bool with_hpwl = (p->flags & HP_ITER_HPWL) != 0;
@@ -1417,7 +1454,105 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
         return HP_OK;
     };
     int done = 0;
+    // Graph replay: a block of L iterations (L = twice the scatter's rebuild interval, so that
+    // the optimiser-state banks and the rebuild phase come back to where they were) is
+    // captured by running the same launch logic under stream capture, and replayed while every
+    // slot's host state (the only input of that logic besides the call's parameters) equals
+    // the state the block was captured from.  A block whose end state differs from its start
+    // (not yet steady) is thrown away and the iterations run eagerly.  Launches with
+    // per-kernel timing events are never captured.
+    if (graph && !hp::g_prof_on) {
+        GraphBlock &G = ctx->graph;
+        const int L = 2 * NL->regroup_every;
+        const std::vector<int32_t> sl(slots, slots + n);
+        auto state_is = [&](const std::vector<Slot> &st) {
+            for (int i = 0; i < n; ++i)
+                if (!same_state(*ss[i], st[i])) return false;
+            return true;
+        };
+        // the cached block was captured for this call's slots, parameters and launch settings
+        const bool key_ok = G.valid && G.slots == sl && G.gamma == p->gamma &&
+                            G.flags == p->flags && G.len == L &&
+                            G.regroup_every == NL->regroup_every && G.deferred == NL->deferred &&
+                            G.fused_parts == NL->fused_parts &&
+                            G.spec_threads == NL->nd.spec_threads;
+        bool have = key_ok;
+        int attempts = 0, eager_run = 0;
+        while (iters - done >= L) {
+            if (have && state_is(G.start)) {
+                HP_CHECK(hipGraphLaunch(G.exec, ctx->stream));
+                ++ctx->graph_replays;
+                done += L;
+                eager_run = 0;
+                continue;
+            }
+            // A call starts in the state left by whatever read the slots last (pending
+            // reductions done), which no block returns to: one eager iteration brings the
+            // slots into the steady cycle.  With a block for these parameters at hand, eager
+            // iterations run until the slots reach its start (at most L); capture only without
+            // one, or when that does not happen.
+            bool steady = true;
+            for (const Slot *s : ss) steady &= s->lambda_valid && !s->rho_dirty && s->since_group >= 0;
+            if (steady && eager_run >= 1 && attempts < 2 && (!have || eager_run > L)) {
+                ++attempts;
+                std::vector<Slot> snap;
+                for (const Slot *s : ss) snap.push_back(*s);
+                HP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                int crc = HP_OK;
+                for (int k = 0; k < L && crc == HP_OK; ++k) crc = iteration();
+                hipGraph_t g = nullptr;
+                const hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
+                const bool periodic = crc == HP_OK && ce == hipSuccess && state_is(snap);
+                for (int i = 0; i < n; ++i) *ss[i] = snap[i];  // the capture ran nothing
+                if (crc != HP_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return crc;
+                }
+                if (ce != hipSuccess) return fail(HP_EDEVICE, std::string("hipStreamEndCapture: ") +
+                                                                  hipGetErrorString(ce));
+                if (periodic) {
+                    hipGraphExec_t ex = nullptr;
+                    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                    if (ie != hipSuccess) {
+                        (void)hipGraphDestroy(g);
+                        return fail(HP_EDEVICE, std::string("hipGraphInstantiate: ") +
+                                                    hipGetErrorString(ie));
+                    }
+                    if (G.valid) HP_CHECK(hipStreamSynchronize(ctx->stream));  // no replay pending
+                    drop_graph(G);
+                    G.valid = true;
+                    G.slots = sl;
+                    G.gamma = p->gamma;
+                    G.flags = p->flags;
+                    G.len = L;
+                    G.regroup_every = NL->regroup_every;
+                    G.deferred = NL->deferred;
+                    G.fused_parts = NL->fused_parts;
+                    G.spec_threads = NL->nd.spec_threads;
+                    G.start = snap;
+                    G.graph = g;
+                    G.exec = ex;
+                    ++ctx->graph_captures;
+                    have = true;
+                    continue;  // the next pass finds the state matching and replays
+                }
+                (void)hipGraphDestroy(g);
+            }
+            HP_TRY(iteration());
+            ++done;
+            ++eager_run;
+        }
+    }
     for (; done < iters; ++done) HP_TRY(iteration());
+    if (iters > 0 && !with_hpwl && (p->flags & HP_ITER_HPWL_LAST))
+        HP_TRY(hpwl_resolved(ctx, NL, chunks, ss));
+    return HP_OK;
+}
+
+int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (captures) *captures = ctx->graph_captures;
+    if (replays) *replays = ctx->graph_replays;
     return HP_OK;
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libhybro.so")
 HP_OK, HP_EINVAL, HP_ENOMEM, HP_EDEVICE, HP_ESTATE, HP_ENOTIMPL = 0, -1, -2, -3, -4, -5
 HP_PERTURB_GAUSS, HP_PERTURB_SHUFFLE, HP_PERTURB_UNIFORM = 0, 1, 2
 HP_MAP_RHO_MOV, HP_MAP_RHO_FIXED, HP_MAP_PSI, HP_MAP_EX, HP_MAP_EY = 0, 1, 2, 3, 4
-HP_ITER_HPWL, HP_ITER_GRAPH = 1, 2
+HP_ITER_HPWL, HP_ITER_GRAPH, HP_ITER_HPWL_LAST = 1, 2, 4
 HP_TUNE_FUSED_STEP_PARTS, HP_TUNE_SPECTRAL_THREADS = 0, 1
 
 
@@ -83,6 +83,7 @@ _SIGS = {
     "hp_eval_objective_grad": [_P, _P, C.c_int32, C.POINTER(hp_eval_params), _P, _P, _P, _P, _P],
     "hp_nesterov_step": [_P, _P, C.c_int32],
     "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
+    "hp_graph_stats": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
     "hp_perturb": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P, _P],
     "hp_perturb_among": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P,
                          C.c_int32, _P, _P],
@@ -288,6 +289,13 @@ def hp_iterate(ctx, slots, gamma, iters, flags):
     a, p, n = _slots(slots)
     prm = hp_iter_params(float(gamma), int(flags))
     _chk(lib().hp_iterate(ctx, p, n, C.byref(prm), int(iters)))
+
+
+def hp_graph_stats(ctx):
+    """(captured blocks, replayed blocks) of hp_iterate's graph mode on this context."""
+    c, r = C.c_int64(), C.c_int64()
+    _chk(lib().hp_graph_stats(ctx, C.byref(c), C.byref(r)))
+    return int(c.value), int(r.value)
 
 
 def hp_perturb(ctx, slot, mode, fraction, sigma_bins, seed, n_movable, want_idx=True):
@@ -508,9 +516,12 @@ class Placer:
         return trace
 
     def iterate(self, slots, gamma, iters, hpwl=True, graph=False):
-        """iters x [evaluate at v, Nesterov step, HPWL sweep] in one call (the loop runs in the
-        library; `graph` asks for HIP graph replay, which the library rejects)."""
-        flags = (HP_ITER_HPWL if hpwl else 0) | (HP_ITER_GRAPH if graph else 0)
+        """iters x [evaluate at v, Nesterov step] in one call (the loop runs in the library),
+        with the exact HPWL after every iteration (hpwl=True), after the last one only
+        (hpwl="last") or never; `graph` replays steady-state blocks from a captured HIP graph
+        (the placer's stream must not be the null stream)."""
+        flags = ((HP_ITER_HPWL_LAST if hpwl == "last" else HP_ITER_HPWL if hpwl else 0) |
+                 (HP_ITER_GRAPH if graph else 0))
         hp_iterate(self.ctx, list(np.atleast_1d(slots)), gamma, iters, flags)
 
     def close(self):

@@ -324,15 +324,16 @@ def test_iterate_matches_single_calls(hy, orc, case, prec):
         pl.free_slot(s)
 
 
-@pytest.mark.skip(reason="HP_ITER_GRAPH is disabled: its first device run stalled in a later "
-                         "stream synchronisation and the cause is not established")
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32), ("mid", 32)])
 def test_iterate_graph_matches_single_calls(hy, orc, case, prec):
-    """hp_iterate (device-side loop; steady-state blocks replayed from a captured HIP graph)
-    is bit-identical to the same iterations issued one entry point at a time, alone and with
-    two slots batched, across several calls (so the graph is replayed many times, with host
-    synchronisations and other work between the replays)."""
-    nl, pl, o = setup(hy, orc, case, prec)
+    """hp_iterate with HIP-graph replay of steady-state blocks is bit-identical to the same
+    iterations issued one entry point at a time, alone and with two slots batched, across
+    several calls (so the graph is replayed many times, with host synchronisations, reads and
+    other work between the replays).  The placer runs on a stream of its own (the null stream
+    cannot be captured)."""
+    import torch
+    nl = _CASES[case]()
+    pl = hy.Placer(nl, precision=prec, stream=torch.cuda.Stream())
     gamma = 4 * nl.bin_w
     ref, eager, graph, b1, b2 = (pl.new_slot() for _ in range(5))
     for s in (ref, eager, graph, b1, b2):
@@ -347,7 +348,8 @@ def test_iterate_graph_matches_single_calls(hy, orc, case, prec):
                 st["energy"], st["overflow_num"], x.tobytes(), y.tobytes(), vx.tobytes(),
                 vy.tobytes())
 
-    for chunk in (3, 9, 13, 8):  # warm-up into steady state, several replays, leftovers
+    print(f"graph test {case} fp{prec}", flush=True)
+    for chunk in (3, 9, 13, 8, 17, 24):  # warm-up into steady state, replays, leftovers
         for _ in range(chunk):
             pl.eval(ref, gamma, want_host=False)
             pl.step(ref)
@@ -358,8 +360,32 @@ def test_iterate_graph_matches_single_calls(hy, orc, case, prec):
         want = snap(ref)
         for s in (eager, graph, b1, b2):
             assert snap(s) == want, (chunk, s)
-    for s in (ref, eager, graph, b1, b2):
-        pl.free_slot(s)
+        print(f"  chunk {chunk} ok", flush=True)
+    captures, replays = hy.hp_graph_stats(pl.ctx)
+    print(f"  graph blocks captured {captures}, replayed {replays}")
+    assert captures >= 1 and replays >= 4
+    pl.close()
+
+
+@pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32)])
+def test_iterate_hpwl_last_matches_every(hy, orc, case, prec):
+    """HPWL after the last iteration only: the same placement and the same final HPWL as the
+    HPWL after every iteration."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    a, b = pl.new_slot(), pl.new_slot()
+    for s in (a, b):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+    for _ in range(3):
+        pl.iterate(a, gamma, 10, hpwl=True)
+        pl.iterate(b, gamma, 10, hpwl="last")
+        assert pl.hpwl(a)[0] == pl.hpwl(b)[0]
+        xa, ya = pl.positions(a)
+        xb, yb = pl.positions(b)
+        assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    pl.free_slot(a)
+    pl.free_slot(b)
 
 
 def test_tiny_fp64_placement_matches_oracle(hy, orc):
@@ -483,7 +509,8 @@ def test_errors(hy, orc):
     with pytest.raises(hy.HybroError) as e:
         hy.hp_iterate(pl.ctx, [s], 1.0, -1, 0)
     assert e.value.code == hy.HP_EINVAL
-    with pytest.raises(hy.HybroError) as e:  # switched off; rejected before any launch
-        hy.hp_iterate(pl.ctx, [s], 1.0, 1, hy.HP_ITER_GRAPH)
-    assert e.value.code == hy.HP_ENOTIMPL
+    if pl.stream.cuda_stream == 0:  # the null stream cannot be captured
+        with pytest.raises(hy.HybroError) as e:
+            hy.hp_iterate(pl.ctx, [s], 1.0, 1, hy.HP_ITER_GRAPH)
+        assert e.value.code == hy.HP_EINVAL
     pl.free_slot(s)
