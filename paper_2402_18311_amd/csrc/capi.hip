@@ -191,7 +191,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.tstart, 4 * ((size_t)g.ntiles + 1));
     put(L.cstart, 4 * ((size_t)g.ntiles + 1));
     put(L.chunk, 16 * (size_t)g.max_chunks);
-    put(L.wins, 8 * (size_t)g.max_chunks * ws * ws);
+    put(L.wins, 8 * (size_t)g.ntiles * ws * ws);
     L.total = o;
     return L;
 }

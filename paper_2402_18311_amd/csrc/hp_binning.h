@@ -69,7 +69,8 @@ __device__ __forceinline__ void count_body(const NetDev &nd, char *base, const S
 }
 
 // Accumulation of chunk c of the grouped order into its LDS window (dynamic LDS: uint64
-// [win_side^2]); cells outside the window add to rho with global atomics.
+// [win_side^2]), added into its tile's window; cells outside the window add to rho with global
+// atomics.
 template <typename T>
 __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const SlotLayout &L, int c) {
     extern __shared__ unsigned long long win[];  // [win_side^2]
@@ -108,8 +109,16 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
         }
     }
     __syncthreads();
-    unsigned long long *out = reinterpret_cast<unsigned long long *>(base + L.wins) + (size_t)c * nw;
-    for (int b = threadIdx.x; b < nw; b += kBlock) out[b] = win[b];
+    // one window per tile: the tile's only chunk stores it, several chunks add theirs (integer
+    // sums, order-free); the row pass clears every element it reads, so the windows are zero
+    // at the next accumulation
+    unsigned long long *out = reinterpret_cast<unsigned long long *>(base + L.wins) + (size_t)t * nw;
+    if (cstart[t + 1] - cstart[t] == 1) {
+        for (int b = threadIdx.x; b < nw; b += kBlock) out[b] = win[b];
+    } else {
+        for (int b = threadIdx.x; b < nw; b += kBlock)
+            if (win[b]) atomicAdd(&out[b], win[b]);
+    }
 }
 
 // Charge of big cell big_ids[k] (a macro) added to rho by the whole block, one bin per thread

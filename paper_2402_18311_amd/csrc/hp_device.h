@@ -306,35 +306,30 @@ __device__ __forceinline__ void step_propose(Scalars *sc, double DV, double DG, 
     store_proposal(sc, propose_from_bank(sc, b, DV, DG, GM, wb));
 }
 
-// Movable charge of bin (k, j) assembled from the binned scatter's chunk windows: the chunks
-// of the bin's own tile, and of the tiles to its left / below / below-left whose windows
-// reach into it (the bin lies within the halo of their far edges).
-__device__ __forceinline__ long long binned_charge(const NetDev &nd, const char *base,
-                                                   const SlotLayout &L, int k, int j) {
-    const int *cstart = reinterpret_cast<const int *>(base + L.cstart);
-    const unsigned long long *W = reinterpret_cast<const unsigned long long *>(base + L.wins);
+// Movable charge of bin (k, j) assembled from the binned scatter's tile windows: its own
+// tile's, and those of the tiles to its left / below / below-left that reach into it (the bin
+// lies within the halo of their far edges).  Every window element inside the die belongs to
+// exactly one bin, whose reader clears it (the next scatter adds into zeros).
+__device__ __forceinline__ long long take_binned_charge(const NetDev &nd, char *base,
+                                                        const SlotLayout &L, int k, int j) {
+    unsigned long long *W = reinterpret_cast<unsigned long long *>(base + L.wins);
     const int ts = 1 << nd.log_ts, ws = nd.win_side, nw = ws * ws;
     const int ty = k >> nd.log_ts, tx = j >> nd.log_ts, kk = k & (ts - 1), jj = j & (ts - 1);
-    unsigned long long s = 0;
-#pragma unroll
-    for (int dy = 0; dy < 2; ++dy) {
-        if (dy && (kk >= nd.halo || ty == 0)) continue;
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-            if (dx && (jj >= nd.halo || tx == 0)) continue;
-            const int t = (ty - dy) * nd.ntx + (tx - dx);
-            const int off = (kk + dy * ts) * ws + jj + dx * ts;
-            const int c1 = cstart[t + 1];
-            int c = cstart[t];
-            for (; c + 4 <= c1; c += 4) {  // independent loads in flight when a tile is crowded
-                const unsigned long long a0 = W[(size_t)c * nw + off], a1 = W[(size_t)(c + 1) * nw + off];
-                const unsigned long long a2 = W[(size_t)(c + 2) * nw + off], a3 = W[(size_t)(c + 3) * nw + off];
-                s += (a0 + a1) + (a2 + a3);
-            }
-            for (; c < c1; ++c) s += W[(size_t)c * nw + off];
-        }
-    }
-    return (long long)s;
+    const bool left = jj < nd.halo && tx > 0, below = kk < nd.halo && ty > 0;
+    // own tile, left, below, below-left (an absent one reads the own element again, unused)
+    const size_t a0 = (size_t)(ty * nd.ntx + tx) * nw + kk * ws + jj;
+    const size_t a1 = left ? (size_t)(ty * nd.ntx + tx - 1) * nw + kk * ws + jj + ts : a0;
+    const size_t a2 = below ? (size_t)((ty - 1) * nd.ntx + tx) * nw + (kk + ts) * ws + jj : a0;
+    const size_t a3 = left && below
+                          ? (size_t)((ty - 1) * nd.ntx + tx - 1) * nw + (kk + ts) * ws + jj + ts
+                          : a0;
+    const unsigned long long v0 = W[a0], v1 = left ? W[a1] : 0ull, v2 = below ? W[a2] : 0ull,
+                             v3 = (left && below) ? W[a3] : 0ull;
+    if (v0) W[a0] = 0;
+    if (v1) W[a1] = 0;
+    if (v2) W[a2] = 0;
+    if (v3) W[a3] = 0;
+    return (long long)((v0 + v1) + (v2 + v3));
 }
 
 // Map a block index inside a bucket of nb blocks (nb a multiple of kXcds) so that each XCD

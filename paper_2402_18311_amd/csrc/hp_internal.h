@@ -111,7 +111,8 @@ struct SlotLayout {
     size_t scnt, soff;    // int32 [sort_blocks][ntiles] histograms; their column offsets
     size_t tstart, cstart;// int32 [ntiles + 1]: tile cell ranges, tile chunk ranges
     size_t chunk;         // int4 [max_chunks]: each chunk's (tile, first, end) in the order
-    size_t wins;          // int64 [max_chunks][win_side^2] per-chunk charge windows
+    size_t wins;          // int64 [ntiles][win_side^2] per-tile charge windows (zero between
+                          // evaluations: the row pass clears what it reads)
     size_t pstride;       // doubles per reduction in `part` (max blocks of any reduction)
     size_t total;
 };

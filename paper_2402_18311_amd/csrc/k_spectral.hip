@@ -201,10 +201,11 @@ __global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nd, Slot
         const int rl = e >> logM, j = e & (M - 1);  // row within the block (line rl / 2)
         const size_t ia = g0 + e;
         const int row = (int)(ia >> logM);
-        // windows of the binned scatter, plus the charge its out-of-window cells added to rho
+        // tile windows of the binned scatter (cleared as they are read), plus the charge its
+        // out-of-window cells added to rho
         const int64_t oa = rho[ia];
         const int64_t fa = nd.rho_fixed[ia];
-        const int64_t ma = binned_charge(nd, base, L, row, j) + oa;
+        const int64_t ma = take_binned_charge(nd, base, L, row, j) + oa;
         const int64_t ca = __double2ll_rn(nd.target_density * (double)(nd.area_q - fa));
         if (ma > ca) over += ma - ca;
         if (keep)  // the whole movable map, for inspection (cleared before the next scatter)
