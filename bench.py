@@ -421,6 +421,8 @@ def main():
     ap.add_argument("--scatter-policy", metavar="EVERY,DEFERRED",
                     help="use this charge-scatter policy (e.g. 8,1) instead of timing the "
                          "candidates before the round")
+    ap.add_argument("--launch-shape", metavar="INTERLEAVE,SPECTRAL_THREADS",
+                    help="use these launch shapes (e.g. 1,0) instead of timing the candidates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB device-to-device once: the "
                          "reference dispatch for scaling hardware byte counters")
@@ -477,6 +479,15 @@ def main():
         from paper_2402_18311_amd import autotune
         policy, tune_ms = autotune.tune_scatter(pl, [s], gamma)
     log(f"[bench] scatter policy {policy} ({tune_ms})")
+    launch = {}
+    if args.launch_shape:
+        i, sp = (int(v) for v in args.launch_shape.split(","))
+        pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, i)
+        pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, sp)
+        launch = {"interleave": i, "spectral_threads": sp}
+    elif not args.scatter_policy:
+        launch, _ = autotune.tune_launch(pl, [s], gamma)
+    log(f"[bench] launch shape {launch}")
 
     # untimed: the kernel table, a scratch slot from the current positions with events on
     # every launch
@@ -568,7 +579,10 @@ def main():
         "final_hpwl": final["hpwl_q"] / 65536,
         "ms_per_step_hpwl_every_iteration": round(every_iter_ms, 5) if every_iter_ms else None,
         "tuning": {"scatter_policy": {"regroup_every": policy[0], "deferred": policy[1]},
-                   "ms_per_iter": {k: round(v, 4) for k, v in tune_ms.items()}},
+                   "ms_per_iter": {k: round(v, 4) for k, v in tune_ms.items()},
+                   "launch_shape": {k: (v if not isinstance(v, dict) else
+                                        {kk: round(vv, 4) for kk, vv in v.items()})
+                                    for k, v in launch.items()}},
         "roofline": roof,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kernels.items()},

@@ -143,9 +143,13 @@ int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, 
  *     passes, 512 or 1024, or 0 (default: 1024 while a launch has at most one block per
  *     compute unit, else 512).  The field maps are the same; the energy total may differ in
  *     its last bits (its per-block reduction tree changes).
+ *   HP_TUNE_SWEEP_INTERLEAVE: order of the net sweep's blocks.  0 (default): degree bucket
+ *     after degree bucket; 1: the buckets' blocks interleaved by their progress through the
+ *     cell range, so that every bucket gathers the same cells at the same time.  The exact
+ *     HPWL is the same; the wirelength total may differ in its last bits.
  * Takes effect at the next launch.  HP_EINVAL for an unknown setting or a value out of range
  * (nothing changed), HP_ESTATE for an unknown netlist.  No device work. */
-enum { HP_TUNE_FUSED_STEP_PARTS = 0, HP_TUNE_SPECTRAL_THREADS = 1 };
+enum { HP_TUNE_FUSED_STEP_PARTS = 0, HP_TUNE_SPECTRAL_THREADS = 1, HP_TUNE_SWEEP_INTERLEAVE = 2 };
 int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value);
 int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value);
 

@@ -1,5 +1,7 @@
-"""Timing-based choice of the charge scatter's grouping policy for a netlist and a batch of
-slots (the tunable of the batched path; results never depend on it, only speed).
+"""Timing-based choice of the launch settings of a netlist for a batch of slots: the charge
+scatter's grouping policy, then the launch shapes (the net sweep's block order and the
+Poisson solve's block width).  Results never depend on them beyond the documented last-bit
+differences of reduced totals; only speed does.
 
 The scatter groups cells by bin tile and rebuilds the grouping every few evaluations; how
 often, and whether the rebuilding evaluation accumulates in the old grouping (one launch
@@ -10,6 +12,7 @@ optimiser restarts there) and keeps the fastest.  A JSON cache keyed by the netl
 and the batch size skips the timing.
 
     best = tune_scatter(pl, slots, gamma)            # applies and returns (every, deferred)
+    shape = tune_launch(pl, slots, gamma)            # applies and returns {tunable: value}
 """
 from __future__ import annotations
 
@@ -72,3 +75,58 @@ def tune_scatter(pl, slots, gamma, candidates=CANDIDATES, warm=8, iters=24, repe
         with open(cache, "w") as fh:
             json.dump(data, fh, indent=1)
     return (every, deferred), timings
+
+
+# (sweep interleave, spectral threads per block: 0 = by launch size)
+LAUNCH_CANDIDATES = ((0, 0), (1, 0), (0, 512), (0, 1024), (1, 512), (1, 1024))
+
+
+def tune_launch(pl, slots, gamma, candidates=LAUNCH_CANDIDATES, warm=4, iters=16, repeats=3,
+                cache=None):
+    """Time the launch-shape candidates as tune_scatter does (scratch slots from the slots'
+    positions, median of `repeats`), apply the fastest and return it with the timings."""
+    import torch
+    from . import hybro as hy
+    slots = [int(s) for s in (slots if isinstance(slots, (list, tuple)) else [slots])]
+    key = "launch_" + _key(pl, len(slots))
+    if cache and os.path.exists(cache):
+        rec = json.load(open(cache)).get(key)
+        if rec:
+            pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, rec["interleave"])
+            pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, rec["spectral_threads"])
+            return rec, rec.get("ms_per_iter", {})
+    saved = (pl.tunable(hy.HP_TUNE_SWEEP_INTERLEAVE), pl.tunable(hy.HP_TUNE_SPECTRAL_THREADS))
+    pos = [pl.positions(s) for s in slots]
+    scratch = [pl.new_slot() for _ in slots]
+    timings = {}
+    try:
+        for inter, spec in candidates:
+            pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, inter)
+            pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, spec)
+            runs = []
+            for _ in range(repeats):
+                for sc, (x, y) in zip(scratch, pos):
+                    pl.set_positions(sc, x, y)
+                pl.iterate(scratch, gamma, warm, hpwl=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pl.iterate(scratch, gamma, iters, hpwl=True)
+                torch.cuda.synchronize()
+                runs.append((time.perf_counter() - t0) * 1e3 / iters)
+            timings[f"{inter},{spec}"] = sorted(runs)[len(runs) // 2]
+    finally:
+        for sc in scratch:
+            pl.free_slot(sc)
+        pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, saved[0])
+        pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, saved[1])
+    best = min(timings, key=timings.get)
+    inter, spec = (int(v) for v in best.split(","))
+    pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, inter)
+    pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, spec)
+    rec = {"interleave": inter, "spectral_threads": spec, "ms_per_iter": timings}
+    if cache:
+        data = json.load(open(cache)) if os.path.exists(cache) else {}
+        data[key] = rec
+        with open(cache, "w") as fh:
+            json.dump(data, fh, indent=1)
+    return rec, timings

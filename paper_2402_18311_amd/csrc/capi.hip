@@ -82,8 +82,10 @@ static bool q16_exact(double v) {
 struct NetBuf {
     size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
         cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh,
-        big_ids, cell_pin_net, total;
+        big_ids, cell_pin_net, sweep_map, total;
 };
+
+size_t part_stride(const hp_shape &s, const hp_die &d);
 
 NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     NetBuf b{};
@@ -117,6 +119,7 @@ NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     put(b.fwh, 16 * Nf);
     put(b.big_ids, 4 * Nm);
     put(b.cell_pin_net, 4 * P);
+    put(b.sweep_map, 4 * (part_stride(s, d) / kXcds + 1));
     b.total = o;
     return b;
 }
@@ -247,7 +250,7 @@ struct GraphBlock {
     bool valid = false;
     std::vector<int32_t> slots;
     double gamma = 0.0;
-    int flags = 0, regroup_every = 0, fused_parts = 0, spec_threads = 0;
+    int flags = 0, regroup_every = 0, fused_parts = 0, spec_threads = 0, interleave = 0;
     bool deferred = false;
     int len = 0;
     std::vector<Slot> start;
@@ -451,6 +454,28 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     }
     bk.total_blocks = blk;
     if ((size_t)blk > part_stride(S, D)) return fail(HP_EINVAL, "internal: sweep block bound");
+    // Interleaved block order of the padded buckets (hp_set_tunable HP_TUNE_SWEEP_INTERLEAVE):
+    // an XCD's blocks of every bucket merged by their progress through the bucket, so that all
+    // buckets sweep the same cell range at the same time.  Entry (bucket << 24 | i): the i-th
+    // of that bucket's blocks on the XCD.  The block-per-net bucket leads, in its own order.
+    std::vector<int32_t> h_smap;
+    int lead = 0;
+    {
+        std::vector<std::pair<double, int32_t>> keys;
+        for (int b = 0; b < bk.n; ++b) {
+            if (bk.G[b] == 0) {
+                lead += bk.nblk[b];
+                continue;
+            }
+            const int q = bk.nblk[b] / kXcds;
+            for (int i = 0; i < q; ++i) keys.push_back({(i + 0.5) / q, (b << 24) | i});
+        }
+        std::stable_sort(keys.begin(), keys.end(),
+                         [](const auto &a, const auto &c) { return a.first < c.first; });
+        for (const auto &k : keys) h_smap.push_back(k.second);
+    }
+    nd.sweep_lead = lead;
+    nd.sweep_interleave = 0;
     const int ns = (int)order.size();
     nd.ns = ns;
 
@@ -652,6 +677,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     HP_CHECK(up(B.fxy, h_fxy.data(), 8 * h_fxy.size()));
     HP_CHECK(up(B.fwh, h_fwh.data(), 8 * h_fwh.size()));
     HP_CHECK(up(B.big_ids, h_big.data(), 4 * h_big.size()));
+    if (!h_smap.empty()) HP_CHECK(up(B.sweep_map, h_smap.data(), 4 * h_smap.size()));
     HP_CHECK(hipMemsetAsync(buf + B.rho_fixed, 0, 8 * (size_t)D.mx * D.my, st));
 
     nd.net_start = reinterpret_cast<const int32_t *>(buf + B.net_start);
@@ -675,6 +701,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.fixed_pos = buf + B.fixed_pos;
     nd.big_ids = reinterpret_cast<const int32_t *>(buf + B.big_ids);
     nd.cell_pin_net = reinterpret_cast<const int32_t *>(buf + B.cell_pin_net);
+    nd.sweep_map = reinterpret_cast<const int32_t *>(buf + B.sweep_map);
     nd.fixed_xy = reinterpret_cast<const double *>(buf + B.fxy);
     nd.fixed_wh = reinterpret_cast<const double *>(buf + B.fwh);
     HP_CHECK(launch_fixed_map<T>(nd, reinterpret_cast<const double *>(buf + B.fxy),
@@ -1283,6 +1310,10 @@ int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
                 return fail(HP_EINVAL, "spectral threads must be 0, 512 or 1024");
             NL.nd.spec_threads = value;
             return HP_OK;
+        case HP_TUNE_SWEEP_INTERLEAVE:
+            if (value != 0 && value != 1) return fail(HP_EINVAL, "sweep interleave must be 0 or 1");
+            NL.nd.sweep_interleave = value;
+            return HP_OK;
         default:
             return fail(HP_EINVAL, "unknown tunable");
     }
@@ -1296,6 +1327,7 @@ int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value) 
     switch (which) {
         case HP_TUNE_FUSED_STEP_PARTS: *value = NL.fused_parts; return HP_OK;
         case HP_TUNE_SPECTRAL_THREADS: *value = NL.nd.spec_threads; return HP_OK;
+        case HP_TUNE_SWEEP_INTERLEAVE: *value = NL.nd.sweep_interleave; return HP_OK;
         default: return fail(HP_EINVAL, "unknown tunable");
     }
 }
@@ -1475,7 +1507,8 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
                             G.flags == p->flags && G.len == L &&
                             G.regroup_every == NL->regroup_every && G.deferred == NL->deferred &&
                             G.fused_parts == NL->fused_parts &&
-                            G.spec_threads == NL->nd.spec_threads;
+                            G.spec_threads == NL->nd.spec_threads &&
+                            G.interleave == NL->nd.sweep_interleave;
         bool have = key_ok;
         int attempts = 0, eager_run = 0;
         while (iters - done >= L) {
@@ -1529,6 +1562,7 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
                     G.deferred = NL->deferred;
                     G.fused_parts = NL->fused_parts;
                     G.spec_threads = NL->nd.spec_threads;
+                    G.interleave = NL->nd.sweep_interleave;
                     G.start = snap;
                     G.graph = g;
                     G.exec = ex;

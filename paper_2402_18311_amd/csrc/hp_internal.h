@@ -64,6 +64,10 @@ struct NetDev {
     int32_t n_cells, n_mov, n_fixed, ns, ps;
     int32_t lds_budget;            // dynamic LDS bytes a block may use on this device
     int32_t n_cu;                  // compute units of the device
+    const int32_t *sweep_map;      // interleaved order of the padded buckets' blocks (see
+                                   // sweep_block)
+    int32_t sweep_lead;            // blocks of the block-per-net bucket, which lead the sweep
+    int32_t sweep_interleave;      // 1: padded buckets' blocks in sweep_map order
     int32_t spec_threads;          // threads per block of the spectral column and inverse-row
                                    // passes: 512, 1024, or 0 (1024 while a launch has at most
                                    // one block per compute unit)

@@ -500,6 +500,25 @@ __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restri
 
 enum { MODE_WA = 0, MODE_HPWL = 1 };
 
+// Bucket b and bucket-local block index of sweep block bx.  Default order: bucket after bucket,
+// each one's blocks remapped so that XCD x (blocks bx with bx % 8 == x) walks one contiguous
+// eighth of it.  Interleaved order: the block-per-net bucket first, then on every XCD the
+// blocks of the padded buckets merged by their progress through their eighth (nd.sweep_map),
+// so all buckets sweep the same cell range at the same time.
+__device__ __forceinline__ void sweep_block(const NetDev &nd, const Buckets &bk, int bx, int &b,
+                                            int &local) {
+    if (nd.sweep_interleave && bx >= nd.sweep_lead) {
+        const int r = bx - nd.sweep_lead;
+        const int e = nd.sweep_map[r / kXcds];
+        b = e >> 24;
+        local = (r % kXcds) * (bk.nblk[b] / kXcds) + (e & 0xffffff);
+        return;
+    }
+    b = 0;
+    while (b + 1 < bk.n && bx >= bk.blk0[b + 1]) ++b;
+    local = xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
+}
+
 // This lane's share of the exact HPWL of block-local index `local` of bucket b.
 template <typename T>
 __device__ __forceinline__ int64_t hpwl_bucket(const NetDev &nd, const Buckets &bk, int b,
@@ -524,9 +543,8 @@ __device__ __forceinline__ int64_t hpwl_bucket(const NetDev &nd, const Buckets &
 template <typename T, int MODE, bool H = false>
 __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, char *base,
                                            const SlotLayout &L, T invg, int bx) {
-    int b = 0;
-    while (b + 1 < bk.n && bx >= bk.blk0[b + 1]) ++b;
-    const int local = xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
+    int b, local;
+    sweep_block(nd, bk, bx, b, local);
     const int net0 = bk.net0[b], net1 = bk.net1[b];
     const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + (MODE == MODE_WA ? L.v : L.u));
     if constexpr (MODE == MODE_WA) {
@@ -618,13 +636,11 @@ int sweep_parts(const Buckets &bk) { return bk.total_blocks; }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void hpwl_pos_kernel(NetDev nd, Buckets bk, const vec2<T> *pos,
                                                           long long *part) {
-    const int bx = blockIdx.x;
-    int b = 0;
-    while (b + 1 < bk.n && bx >= bk.blk0[b + 1]) ++b;
-    const int local = xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
+    int b, local;
+    sweep_block(nd, bk, blockIdx.x, b, local);
     __shared__ long long red[4];
     const long long tot = block_sum((long long)hpwl_bucket<T>(nd, bk, b, local, pos), red);
-    if (threadIdx.x == 0) part[bx] = tot;
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kBlock) void hpwl_pos_finish_kernel(const long long *part, int n,

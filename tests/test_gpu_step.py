@@ -178,3 +178,38 @@ def test_mid_fp32_placement_lands_on_the_oracle(hy, orc):
     print("oracle fp64           :", [t / 65536 for t in ref["hpwl_q_every_100"]])
     assert abs(trace[-1] - want) <= 0.005 * want, (trace[-1] / 65536, want / 65536)
     pl.free_slot(s)
+
+
+@pytest.mark.parametrize("case,prec", [("small", 32), ("tiny", 64)])
+def test_interleaved_sweep_order_is_bit_identical(hy, orc, case, prec):
+    """The interleaved block order of the net sweep moves no pin's work between lanes: the
+    same gradients, steps and exact HPWL, bit for bit."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    a, b = pl.new_slot(), pl.new_slot()
+    for s in (a, b):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+    try:
+        for chunk in (1, 6, 10):
+            pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, 0)
+            _, gxa, gya = pl.eval(a, gamma, grads=True)
+            pl.step(a)
+            pl.iterate(a, gamma, chunk, hpwl=True)
+            pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, 1)
+            _, gxb, gyb = pl.eval(b, gamma, grads=True)
+            pl.step(b)
+            pl.iterate(b, gamma, chunk, hpwl=True)
+            assert torch_equal(gxa, gxb) and torch_equal(gya, gyb)
+            assert pl.hpwl(a)[0] == pl.hpwl(b)[0]
+            xa, ya = pl.positions(a)
+            xb, yb = pl.positions(b)
+            assert np.array_equal(xa, xb) and np.array_equal(ya, yb), chunk
+    finally:
+        pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, 0)
+        pl.free_slot(a)
+        pl.free_slot(b)
+
+
+def torch_equal(a, b):
+    return bool((a.cpu() == b.cpu()).all())
