@@ -158,13 +158,17 @@ int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value);
  *   map, overflow = sum_b max(0, movable charge - target * free area) / total movable charge
  *   (the D(s) <= eps measure of Eq. 1), gradient = grad WL + lambda * grad N over movable
  *   cells.  gamma: the smoothing length of Eq. 3 (same units as positions).  lambda >= 0 is
- *   used as given; lambda < 0 uses each slot's scheduled lambda.  grad_mode 0: the field
- *   force -sum_b q_ib xi_b (ePlace); 1: the exact adjoint sum_b psi_b dq_ib/dx_i of the
- *   continuous charge rectangle (also computes the potential map).  keep_maps 1 keeps the charge,
+ *   used as given; lambda < 0 uses each slot's scheduled lambda.  grad_mode bit 0: 0 the field
+ *   force -sum_b q_ib xi_b (ePlace), 1 the exact adjoint sum_b psi_b dq_ib/dx_i of the
+ *   continuous charge rectangle (also computes the potential map); bit 1 (HP_GRAD_DENSITY_ONLY):
+ *   the density term alone -- the net sweep does not run, wl is 0 and the gradient is
+ *   lambda * grad N, for callers that need the density adjoint by itself (needs lambda >= 0,
+ *   HP_EINVAL otherwise).  keep_maps 1 keeps the charge,
  *   potential and field maps for hp_get_map.  wl/energy/overflow: host double [n_slots] or
  *   NULL (then nothing is synchronised, and in steady state the totals are reduced only when
  *   first read, by hp_get_state).  grad_x/grad_y: device real [n_slots][n_movable] or
  *   NULL (the gradient always stays in the slot for hp_nesterov_step). */
+enum { HP_GRAD_FIELD = 0, HP_GRAD_EXACT = 1, HP_GRAD_DENSITY_ONLY = 2 };
 typedef struct {
     double gamma;
     double lambda;

@@ -40,14 +40,14 @@ class _Objective(torch.autograd.Function):
 
 
 class _Density(torch.autograd.Function):
-    """N at (x, y); its gradient is g(lam = 1) - g(lam = 0) of two evaluations."""
+    """N at (x, y), with its gradient from one density-only evaluation (the library's density
+    adjoint launch with lambda = 1; the net sweep does not run)."""
 
     @staticmethod
     def forward(ctx, x, y, pl, slot, gamma, grad_mode):
-        _, en, g1x, g1y = _eval(pl, slot, x, y, gamma, 1.0, grad_mode)
-        g1x, g1y = g1x.clone(), g1y.clone()
-        (_, _, _), g0x, g0y = pl.eval(slot, gamma, lam=0.0, grads=True, grad_mode=grad_mode)
-        ctx.save_for_backward(g1x - g0x[0], g1y - g0y[0])
+        from .hybro import HP_GRAD_DENSITY_ONLY
+        _, en, gx, gy = _eval(pl, slot, x, y, gamma, 1.0, grad_mode | HP_GRAD_DENSITY_ONLY)
+        ctx.save_for_backward(gx.clone(), gy.clone())
         return x.new_tensor(en)
 
     @staticmethod

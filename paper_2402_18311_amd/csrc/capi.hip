@@ -818,7 +818,9 @@ int finish_totals(hp_ctx *ctx, Netlist *NL, const std::vector<Slot *> &ss) {
 int check_eval_params(const hp_eval_params *p) {
     if (!p) return fail(HP_EINVAL, "params is NULL");
     if (!(p->gamma > 0) || !std::isfinite(p->gamma)) return fail(HP_EINVAL, "gamma must be > 0");
-    if (p->grad_mode != 0 && p->grad_mode != 1) return fail(HP_EINVAL, "grad_mode must be 0 or 1");
+    if (p->grad_mode < 0 || p->grad_mode > 3) return fail(HP_EINVAL, "grad_mode must be 0..3");
+    if ((p->grad_mode & GRAD_DENSITY_ONLY) && !(p->lambda >= 0))
+        return fail(HP_EINVAL, "a density-only evaluation needs lambda >= 0 given");
     if (p->lambda >= 0 && !std::isfinite(p->lambda)) return fail(HP_EINVAL, "lambda must be finite");
     return HP_OK;
 }
@@ -828,9 +830,12 @@ template <typename T>
 int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
                   const std::vector<Slot *> &ss, const hp_eval_params *p) {
     const bool use_fixed = p->lambda >= 0;
+    const bool wl_on = !(p->grad_mode & GRAD_DENSITY_ONLY);
     hipStream_t st = ctx->stream;
     const NetDev &nd = NL->nd;
     const SlotLayout &L = NL->L;
+    // a density-only evaluation has no sweep for a pending HPWL request to ride in
+    if (!wl_on) HP_TRY(launch_requested_hpwl(ctx, NL, ss));
     for (size_t c = 0; c < chunks.size(); ++c) {
         const SlotArgs &sa = chunks[c];
         bool any_init = false;
@@ -853,8 +858,10 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         // steady state: the totals are reduced when first read; with few enough cell-gradient
         // partials there is no closing reduction at all (the step derives its proposal itself),
         // else it forms the step only
-        const bool fused = !any_init && cell_parts(nd) <= NL->fused_parts;
-        const int finish = any_init ? FIN_FULL : (fused ? -1 : FIN_STEP);
+        // (density only: the totals now, with no wirelength partials)
+        const bool fused = !any_init && wl_on && cell_parts(nd) <= NL->fused_parts;
+        const int finish = (any_init || !wl_on) ? FIN_FULL : (fused ? -1 : FIN_STEP);
+        const int nwl = wl_on ? NL->bk.total_blocks : 0;
         if (dirty) HP_CHECK(launch_clear_rho(nd, sa, L, st));
         // The scatter's grouping.  A slot without one (fresh), or a periodic rebuild (due) of
         // a netlist whose policy is not deferred, counts for a new order in the first launch
@@ -867,15 +874,15 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         const bool accum_now = !rebuild_now, count_now = fresh || due;
         // WA sweep, HPWL sweep and the scatter's accumulation and/or counting in one launch
         HP_CHECK(launch_eval_front<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, hmask, accum_now,
-                                      count_now, st));
+                                      count_now, wl_on, st));
         if (rebuild_now) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, true, st));
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0,
-                                    p->keep_maps != 0 || p->grad_mode == 1, st));
+                                    p->keep_maps != 0 || (p->grad_mode & GRAD_EXACT), st));
         if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, st));
         HP_CHECK(launch_big_grad<T>(nd, sa, L, p->grad_mode, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
-                                     NL->bk.total_blocks, NL->e_parts, spectral_overflow_parts(nd),
-                                     finish, banks, st));
+                                     nwl, NL->e_parts, spectral_overflow_parts(nd), finish, banks,
+                                     st));
         if (any_init) HP_CHECK(launch_combine<T>(nd, sa, L, st));
         for (int i = 0; i < sa.n; ++i) {
             Slot *s = ss[c * kMaxSlots + i];

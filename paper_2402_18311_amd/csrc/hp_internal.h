@@ -191,10 +191,11 @@ void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
 // ---- launchers (each returns hipError_t of the launch) -----------------------------------
 // First launch of an evaluation (WA sweep of v, charge accumulation or the counting pass of a
 // regroup, and the HPWL sweep of u for the slots in hpwl_mask, bit i = slot i of the launch).
+// sweep = false leaves the net sweep out (a density-only evaluation; hpwl_mask must be 0).
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
-                             bool accum, bool count, hipStream_t st);
+                             bool accum, bool count, bool sweep, hipStream_t st);
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st);
@@ -240,7 +241,9 @@ hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLa
 // (the fused step: no closing reduction launch in steady state).
 constexpr int kFusedStepParts = 1024;
 hipError_t launch_hpwl_finish(const SlotArgs &sa, const SlotLayout &L, int nparts, hipStream_t st);
-// grad_mode 0: field force -sum q xi; 1: exact adjoint sum psi dq/dx (needs the psi map).
+// grad_mode bits: GRAD_EXACT, the exact adjoint sum psi dq/dx (needs the psi map) instead of
+// the field force -sum q xi; GRAD_DENSITY_ONLY, no wirelength part (the sweep did not run).
+enum { GRAD_EXACT = 1, GRAD_DENSITY_ONLY = 2 };
 // finish: the closing reduction's mode after it (FIN_*), or -1 for none (the totals are then
 // left to a later totals-only reduction and the proposal to the fused step).
 template <typename T>

@@ -166,12 +166,13 @@ __global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nd, SlotArgs sa
     const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
     double s[4] = {0.0, 0.0, 0.0, 0.0};  // wirelength x, y; density x, y
     const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
-    for (int j = nd.cell_pin_start[i] + threadIdx.x; j < nd.cell_pin_start[i + 1]; j += kBlock) {
+    const int jend = (grad_mode & GRAD_DENSITY_ONLY) ? 0 : nd.cell_pin_start[i + 1];
+    for (int j = nd.cell_pin_start[i] + threadIdx.x; j < jend; j += kBlock) {
         const vec2<T> gp = pg[nd.cell_pins[j]];
         s[0] += (double)gp.x;
         s[1] += (double)gp.y;
     }
-    if (grad_mode == 1) {
+    if (grad_mode & GRAD_EXACT) {
         const ExactRect e = exact_rect<T>(nd, i, (double)p.x, (double)p.y);
         const T *psi = reinterpret_cast<const T *>(base + L.psi);
         const int nj = e.j1 - e.j0 + 1, nk = e.k1 - e.k0 + 1;
@@ -264,7 +265,8 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         const int4 cc = nd.cq[i];
         const bool big = is_big(nd, cc);  // both parts already reduced by its own block
         const int e = nd.cell_pin_start[i + 1];
-        int j = big ? e : nd.cell_pin_start[i];
+        // no wirelength part in a density-only evaluation (the sweep did not run)
+        int j = (big || (grad_mode & GRAD_DENSITY_ONLY)) ? e : nd.cell_pin_start[i];
         const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
         // charge weight of a bin: rq ox oy 2^-40, formed in the compute type (exact in FP64;
         // in FP32 a relative rounding of ~1e-7, far inside the gradient tolerance)
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
         const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
         const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
         constexpr int KR = 3, JC = 4;
-        const bool small = grad_mode == 0 && has && k1 - k0 < KR && j1 - j0 < JC;
+        const bool small = !(grad_mode & GRAD_EXACT) && has && k1 - k0 < KR && j1 - j0 < JC;
         // the window: rows ks .. ks+2 and columns js .. js+3 of the field, inside the grid
         // (sides >= 8 bins) and covering the footprint; each row is read as wide loads
         const int js = min(j0, nd.mx - JC), ks = min(k0, nd.my - KR);
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
             gwy = gw[nd.n_mov + i];
             gdx = gd[i];
             gdy = gd[nd.n_mov + i];
-        } else if (grad_mode == 1) {  // exact adjoint of the continuous charge rectangle
+        } else if (grad_mode & GRAD_EXACT) {  // exact adjoint of the continuous charge rectangle
             exact_adjoint<T>(nd, reinterpret_cast<const T *>(base + L.psi), i, (double)p.x,
                              (double)p.y, gdx, gdy);
         } else if (small) {  // the footprint's bins of the window, row-major

@@ -667,15 +667,16 @@ hipError_t launch_hpwl_positions(const NetDev &nd, const Buckets &bk, const void
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
-                             bool accum, bool count, hipStream_t st) {
+                             bool accum, bool count, bool sweep, hipStream_t st) {
     const int nacc = accum ? (nd.max_chunks + kXcds - 1) / kXcds * kXcds : 0;
     const int ncnt = count ? (nd.sort_blocks + kXcds - 1) / kXcds * kXcds : 0;
     const int nbig = (nd.n_big + kXcds - 1) / kXcds * kXcds;
     // dynamic LDS: the largest need of the jobs (a block does one of them; big cells need none)
-    const size_t big = (bk.n > 0 && bk.G[0] == 0) ? sizeof(vec2<T>) * kNetRegs * kBlock : 0;
+    const size_t big = (sweep && bk.n > 0 && bk.G[0] == 0) ? sizeof(vec2<T>) * kNetRegs * kBlock : 0;
     const size_t lds = std::max({accum ? scatter_accum_lds(nd) : 0,
                                  count ? scatter_count_lds(nd) : 0, big});
-    dim3 grid(nacc + ncnt + nbig + bk.total_blocks, sa.n);
+    dim3 grid(nacc + ncnt + nbig + (sweep ? bk.total_blocks : 0), sa.n);
+    if (grid.x == 0) return hipSuccess;
     HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
               L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask);
     return hipGetLastError();
@@ -692,7 +693,7 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
 #define HP_INST(T)                                                                             \
     template hipError_t launch_eval_front<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, double, uint32_t, bool, bool,  \
-                                             hipStream_t);                                      \
+                                             bool, hipStream_t);                                \
     template hipError_t launch_sweep_hpwl<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, hipStream_t);                  \
     template hipError_t launch_hpwl_positions<T>(const NetDev &, const Buckets &, const void *, \

@@ -78,3 +78,35 @@ def test_objective_is_wirelength_plus_lambda_energy(setup):
     g2 = torch.cat([x.grad, y.grad])
     assert float(f) == pytest.approx(float(w) + lam * float(d), rel=1e-12)
     assert torch.linalg.norm(gf - g2) / torch.linalg.norm(gf) < 1e-10
+
+
+@pytest.mark.parametrize("prec,grad_mode", [(32, 1), (32, 0), (64, 0)])
+def test_density_only_evaluation_matches_oracle(orc, prec, grad_mode):
+    """One density-only evaluation (no net sweep) gives lambda * grad N: the oracle's density
+    gradient (exact adjoint or field force) to the parity bar, with wirelength 0, in FP32 too,
+    where the former difference of two full evaluations cancelled."""
+    from paper_2402_18311_amd import hybro
+    nl = netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40)
+    pl = hybro.Placer(nl, precision=prec)
+    s = pl.new_slot()
+    x, y = nl.random_positions(4)
+    pl.set_positions(s, x, y)
+    px, py = pl.positions(s)
+    lam = 0.7
+    (wl, en, ov), gx, gy = pl.eval(s, 4 * nl.bin_w, lam=lam, grads=True,
+                                   grad_mode=grad_mode | hybro.HP_GRAD_DENSITY_ONLY)
+    o = orc.Oracle(nl)
+    ref = o.eval(px.astype(np.float64), py.astype(np.float64), 4 * nl.bin_w, grad_mode=grad_mode)
+    g = np.concatenate([gx.cpu().numpy()[0], gy.cpu().numpy()[0]]).astype(np.float64)
+    gref = lam * np.concatenate([ref["gdx"], ref["gdy"]])
+    tol = 1e-4 if prec == 32 else 1e-10
+    assert wl[0] == 0.0
+    assert en[0] == pytest.approx(ref["energy"], rel=1e-5 if prec == 32 else 1e-10)
+    assert ov[0] == ref["overflow"]
+    assert np.linalg.norm(g - gref) / np.linalg.norm(gref) < tol
+    # a following full evaluation is unaffected (its sweep and totals are its own)
+    (wl2, _, _), _, _ = pl.eval(s, 4 * nl.bin_w, lam=lam, grads=True, grad_mode=grad_mode)
+    assert wl2[0] == pytest.approx(ref["wl"], rel=1e-5 if prec == 32 else 1e-10)
+    with pytest.raises(hybro.HybroError):
+        pl.eval(s, 4 * nl.bin_w, lam=-1.0, grad_mode=hybro.HP_GRAD_DENSITY_ONLY)
+    pl.close()

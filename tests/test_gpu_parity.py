@@ -495,7 +495,7 @@ def test_errors(hy, orc):
         pl.eval(s, -1.0)
     assert e.value.code == hy.HP_EINVAL
     with pytest.raises(hy.HybroError) as e:
-        hy.hp_eval_objective_grad(pl.ctx, [s], 1.0, grad_mode=2)
+        hy.hp_eval_objective_grad(pl.ctx, [s], 1.0, grad_mode=4)
     assert e.value.code == hy.HP_EINVAL
     with pytest.raises(hy.HybroError) as e:
         pl.map(s, hy.HP_MAP_PSI)  # no kept maps yet
