@@ -3,11 +3,13 @@
 // launch sequences of every C-ABI entry point.  No device memory is allocated here: all of
 // it lives in buffers the caller lends.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hp_internal.h"
@@ -39,6 +41,23 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// f(lo, hi) over [0, n) split into contiguous ranges on up to 16 host threads (a single call
+// for small n); the ranges own disjoint outputs.
+template <typename F>
+void parallel_ranges(int64_t n, F &&f) {
+    const int64_t grain = 1 << 16;
+    int nt = (int)std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())),
+                                    (n + grain - 1) / grain);
+    if (nt <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] { f(n * t / nt, n * (t + 1) / nt); });
+    for (auto &x : th) x.join();
+}
 
 // ---- static scratch of the allocation-free entry point (hp_hpwl_noalloc) --------------------
 // Per-block partial sums of the exact-HPWL sweep live in this file-scope device array, one
@@ -330,13 +349,32 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     if (net_start[0] != 0 || net_start[E] != P) return fail(HP_EINVAL, "net_start[0] must be 0 and net_start[n_nets] == n_pins");
     for (int e = 0; e < E; ++e)
         if (net_start[e + 1] < net_start[e]) return fail(HP_EINVAL, "net_start must be non-decreasing");
-    for (int p = 0; p < P; ++p) {
-        if (pin_cell[p] < 0 || pin_cell[p] >= Nc)
-            return fail(HP_EINVAL, "pin_cell[" + std::to_string(p) + "] out of range");
-        if (!std::isfinite(pin_ox[p]) || !std::isfinite(pin_oy[p]))
-            return fail(HP_EINVAL, "pin offsets must be finite");
-        if (std::fabs(pin_ox[p]) * 65536.0 >= 2147483647.0 || std::fabs(pin_oy[p]) * 65536.0 >= 2147483647.0)
+    {
+        // the first bad pin in each range (ranges in order, so the first bad pin overall wins)
+        std::vector<std::pair<int64_t, int>> bad;
+        std::mutex mu;
+        parallel_ranges(P, [&](int64_t lo, int64_t hi) {
+            for (int64_t p = lo; p < hi; ++p) {
+                int why = 0;
+                if (pin_cell[p] < 0 || pin_cell[p] >= Nc) why = 1;
+                else if (!std::isfinite(pin_ox[p]) || !std::isfinite(pin_oy[p])) why = 2;
+                else if (std::fabs(pin_ox[p]) * 65536.0 >= 2147483647.0 ||
+                         std::fabs(pin_oy[p]) * 65536.0 >= 2147483647.0)
+                    why = 3;
+                if (why) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    bad.push_back({p, why});
+                    return;
+                }
+            }
+        });
+        if (!bad.empty()) {
+            const auto first = *std::min_element(bad.begin(), bad.end());
+            if (first.second == 1)
+                return fail(HP_EINVAL, "pin_cell[" + std::to_string(first.first) + "] out of range");
+            if (first.second == 2) return fail(HP_EINVAL, "pin offsets must be finite");
             return fail(HP_EINVAL, "pin offset too large");
+        }
     }
     for (int i = 0; i < Nc; ++i) {
         const double w = cell_w[i], h = cell_h[i];
@@ -408,17 +446,30 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
         return net_start[a + 1] - net_start[a] > net_start[b + 1] - net_start[b];
     });
     // padded buckets: order nets by their lowest cell, so neighbouring lanes gather
-    // neighbouring cells and each XCD's share of a bucket covers a compact cell range
+    // neighbouring cells and each XCD's share of a bucket covers a compact cell range (a
+    // stable counting sort by lowest cell: ties keep net order)
     {
         std::vector<int32_t> minc(E, 0);
-        for (int e = 0; e < E; ++e) {
-            int32_t m = INT32_MAX;
-            for (int p = net_start[e]; p < net_start[e + 1]; ++p) m = std::min(m, pin_cell[p]);
-            minc[e] = m;
-        }
+        parallel_ranges(E, [&](int64_t lo, int64_t hi) {
+            for (int64_t e = lo; e < hi; ++e) {
+                int32_t m = INT32_MAX;
+                for (int p = net_start[e]; p < net_start[e + 1]; ++p) m = std::min(m, pin_cell[p]);
+                minc[e] = m;
+            }
+        });
+        std::vector<int32_t> start((size_t)Nc + 1, 0), sorted;
         for (int b = 1; b < NB; ++b)
-            std::stable_sort(members[b].begin(), members[b].end(),
-                             [&](int a, int c) { return minc[a] < minc[c]; });
+            for (int e : members[b]) ++start[(size_t)minc[e] + 1];
+        for (int c = 0; c < Nc; ++c) start[c + 1] += start[c];
+        sorted.resize(start[Nc]);
+        for (int b = 1; b < NB; ++b)  // nets of every padded bucket, in net order
+            for (int e : members[b]) sorted[start[minc[e]]++] = e;
+        std::vector<int> bucket_of(E, -1);
+        for (int b = 1; b < NB; ++b) {
+            for (int e : members[b]) bucket_of[e] = b;
+            members[b].clear();
+        }
+        for (int e : sorted) members[bucket_of[e]].push_back(e);
     }
     // sweep order of the nets (memory order): padded buckets by decreasing G, then the
     // block-per-net bucket
@@ -479,46 +530,57 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     const int ns = (int)order.size();
     nd.ns = ns;
 
-    std::vector<int32_t> h_ns(ns + 1), h_pc;
-    std::vector<T> h_po, h_w;
-    std::vector<int32_t> h_pq;
-    h_pc.reserve(P);
-    h_po.reserve(2 * (size_t)P);
-    h_pq.reserve(2 * (size_t)P);
-    bool any_w = false, offq_exact = true;
+    std::vector<int32_t> h_ns(ns + 1);
+    std::vector<T> h_w;
+    bool any_w = false;
     if (net_weight)
         for (int e = 0; e < E; ++e) any_w |= net_weight[e] != 1.0;
-    // entries in memory order (by their first sweep net)
+    // entries in memory order (by their first sweep net); each sweep net's first pin slot: its
+    // G slots in a padded bucket, its own pins in the block-per-net bucket
     std::vector<int> by_mem(bk.n);
     std::iota(by_mem.begin(), by_mem.end(), 0);
     std::sort(by_mem.begin(), by_mem.end(), [&](int a, int c) { return bk.net0[a] < bk.net0[c]; });
-    for (int m = 0, i = 0; m < bk.n; ++m) {
-        const int b = by_mem[m];
-        const int G = bk.G[b];
-        bk.pin0[b] = (int32_t)h_pc.size();
-        for (; i < bk.net1[b]; ++i) {
-            const int e = order[i];
-            h_ns[i] = (int32_t)h_pc.size();
-            for (int p = net_start[e]; p < net_start[e + 1]; ++p) {
-                offq_exact = offq_exact && q16_exact<T>(pin_ox[p]) && q16_exact<T>(pin_oy[p]);
-                h_pc.push_back(pin_cell[p]);
-                h_po.push_back((T)pin_ox[p]);
-                h_po.push_back((T)pin_oy[p]);
-                h_pq.push_back((int32_t)std::llrint(pin_ox[p] * 65536.0));
-                h_pq.push_back((int32_t)std::llrint(pin_oy[p] * 65536.0));
+    {
+        int32_t slot = 0;
+        for (int m = 0, i = 0; m < bk.n; ++m) {
+            const int b = by_mem[m];
+            bk.pin0[b] = slot;
+            for (; i < bk.net1[b]; ++i) {
+                h_ns[i] = slot;
+                const int d = net_start[order[i] + 1] - net_start[order[i]];
+                slot += bk.G[b] ? bk.G[b] : d;
             }
-            for (int k = net_start[e + 1] - net_start[e]; k < G; ++k) {  // padding lanes
-                h_pc.push_back(-1);
-                h_po.push_back(T(0));
-                h_po.push_back(T(0));
-                h_pq.push_back(0);
-                h_pq.push_back(0);
-            }
-            if (any_w) h_w.push_back((T)net_weight[e]);
         }
+        h_ns[ns] = slot;
     }
-    h_ns[ns] = (int32_t)h_pc.size();
-    const int ps = (int)h_pc.size();
+    const int ps = h_ns[ns];
+    std::vector<int32_t> h_pc(ps), h_pq(2 * (size_t)ps);
+    std::vector<T> h_po(2 * (size_t)ps);
+    std::atomic<bool> all_exact{true};
+    parallel_ranges(ns, [&](int64_t lo, int64_t hi) {
+        bool ex = true;
+        for (int64_t i = lo; i < hi; ++i) {
+            const int e = order[i];
+            int32_t q = h_ns[i];
+            for (int p = net_start[e]; p < net_start[e + 1]; ++p, ++q) {
+                ex = ex && q16_exact<T>(pin_ox[p]) && q16_exact<T>(pin_oy[p]);
+                h_pc[q] = pin_cell[p];
+                h_po[2 * (size_t)q] = (T)pin_ox[p];
+                h_po[2 * (size_t)q + 1] = (T)pin_oy[p];
+                h_pq[2 * (size_t)q] = (int32_t)std::llrint(pin_ox[p] * 65536.0);
+                h_pq[2 * (size_t)q + 1] = (int32_t)std::llrint(pin_oy[p] * 65536.0);
+            }
+            for (; q < h_ns[i + 1]; ++q) {  // padding slots
+                h_pc[q] = -1;
+                h_po[2 * (size_t)q] = h_po[2 * (size_t)q + 1] = T(0);
+                h_pq[2 * (size_t)q] = h_pq[2 * (size_t)q + 1] = 0;
+            }
+        }
+        if (!ex) all_exact = false;
+    });
+    const bool offq_exact = all_exact;
+    if (any_w)
+        for (int i = 0; i < ns; ++i) h_w.push_back((T)net_weight[order[i]]);
     nd.ps = ps;
     nd.offq_exact = offq_exact ? 1 : 0;
     if ((size_t)ps > sweep_slots_bound(S)) return fail(HP_EINVAL, "internal: sweep slot bound");
