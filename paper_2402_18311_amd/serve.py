@@ -1,8 +1,8 @@
 """Serving loop: placement jobs of uneven size, admitted by HBM budget and run concurrently.
 
 A job is one synthetic netlist placed by the plain method: `iters` iterations (objective and
-gradient of Eq. 2, Nesterov step, exact HPWL of Eq. 1) from its initial positions; its result
-is the final HPWL_q.  Jobs arrive on a trace.  The server admits them in arrival order as long
+gradient of Eq. 2, Nesterov step) from its initial positions; its result is the exact HPWL of
+Eq. 1 after the last one (HPWL_q).  Jobs arrive on a trace.  The server admits them in arrival order as long
 as their device buffers (netlist + one slot) fit in the budget — a job larger than the whole
 budget is admitted alone — keeps their state resident while they run, and runs every admitted
 job on its own HIP stream from its own host thread, so the kernels of concurrent jobs overlap
@@ -162,7 +162,9 @@ def run_on_gpu(job: Job) -> None:
         nl = job.netlist
         pl.set_positions(s, nl.x0, nl.y0)
         pl.set_schedule(s, 1e-4, 4.0, job.iters)
-        pl.iterate(s, 4 * nl.bin_w, job.iters, hpwl=True)
+        # the job's result is the exact HPWL after its last iteration; steady-state blocks are
+        # replayed from a captured HIP graph on the job's stream
+        pl.iterate(s, 4 * nl.bin_w, job.iters, hpwl="last", graph=True)
         job.hpwl_q = int(pl.hpwl(s)[0])
         pl.free_slot(s)
     finally:
@@ -170,16 +172,25 @@ def run_on_gpu(job: Job) -> None:
         del pl
 
 
-def make_jobs(n: int, lo: int, hi: int, iters: int, seed: int) -> list[Job]:
+def _make_one(args):
+    c, s = args
+    return netgen.make_netlist(netgen.scaled_config(int(c)), s)
+
+
+def make_jobs(n: int, lo: int, hi: int, iters: int, seed: int, workers: int = 0) -> list[Job]:
     """n netlists shaped like the mid workload with log-uniform sizes in [lo, hi] cells
-    (arrival times are set by `poisson_arrivals`)."""
+    (arrival times are set by `poisson_arrivals`), drawn on `workers` processes (0: in this
+    one).  Each netlist has its own seed, so the draws do not depend on the worker count."""
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), n)).round().astype(int)
-    jobs = []
-    for i, c in enumerate(sizes):
-        nl = netgen.make_netlist(netgen.scaled_config(int(c)), seed * 1000 + i)
-        jobs.append(Job(i, nl, iters, 0.0))
-    return jobs
+    args = [(int(c), seed * 1000 + i) for i, c in enumerate(sizes)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            nls = pool.map(_make_one, args, chunksize=1)
+    else:
+        nls = [_make_one(a) for a in args]
+    return [Job(i, nl, iters, 0.0) for i, nl in enumerate(nls)]
 
 
 def poisson_arrivals(jobs: list[Job], rate: float, seed: int) -> None:
@@ -194,10 +205,10 @@ def fresh(jobs: list[Job]) -> list[Job]:
 
 
 def measure(n_jobs=200, lo=10_000, hi=2_200_000, iters=500, budget_gb=8.0, rate_frac=0.8,
-            seed=0, log=print) -> dict:
+            seed=0, log=print, workers=0) -> dict:
     """Config 5: capacity of sequential plain solves (all jobs queued at t = 0), then a Poisson
     trace at rate_frac x that capacity served sequentially and by the server."""
-    jobs = make_jobs(n_jobs, lo, hi, iters, seed)
+    jobs = make_jobs(n_jobs, lo, hi, iters, seed, workers)
     for j in jobs:
         j.nbytes = device_bytes(j.netlist)
     log(f"[serve] {n_jobs} jobs, {sum(j.netlist.n_movable for j in jobs)} cells in all")
@@ -233,8 +244,11 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=8.0)
     ap.add_argument("--rate-frac", type=float, default=0.8)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workers", type=int, default=8,
+                    help="processes drawing the synthetic netlists")
     a = ap.parse_args()
-    print(json.dumps(measure(a.jobs, a.lo, a.hi, a.iters, a.budget_gb, a.rate_frac, a.seed)))
+    print(json.dumps(measure(a.jobs, a.lo, a.hi, a.iters, a.budget_gb, a.rate_frac, a.seed,
+                             workers=a.workers)))
 
 
 if __name__ == "__main__":

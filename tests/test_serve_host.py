@@ -2,6 +2,7 @@
 import threading
 import time
 
+import numpy as np
 import pytest
 
 from paper_2402_18311_amd import serve
@@ -70,3 +71,13 @@ def test_worker_error_propagates():
         raise RuntimeError("boom")
     with pytest.raises(RuntimeError):
         serve.Scheduler(8, bad).serve(_jobs([1], [0.0]))
+
+
+def test_job_netlists_do_not_depend_on_worker_count():
+    from paper_2402_18311_amd import serve
+    a = serve.make_jobs(3, 1_000, 4_000, 10, 5, workers=0)
+    b = serve.make_jobs(3, 1_000, 4_000, 10, 5, workers=2)
+    for ja, jb in zip(a, b):
+        assert ja.netlist.n_movable == jb.netlist.n_movable
+        assert np.array_equal(ja.netlist.pin_cell, jb.netlist.pin_cell)
+        assert np.array_equal(ja.netlist.x0, jb.netlist.x0)
