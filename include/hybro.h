@@ -102,6 +102,10 @@ int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die,
 int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
                   int32_t *out_slot);
 int hp_slot_free(hp_ctx *ctx, int32_t slot);
+/* Release a netlist whose slots are all freed (HP_ESTATE while one is alive, or for an unknown
+ * id): the context forgets it and waits for its stream, after which the caller may free the
+ * netlist's device buffer.  Its id is not reused. */
+int hp_netlist_free(hp_ctx *ctx, int32_t netlist);
 
 /* Set the movable cells' positions (real [n_movable] each; host or device memory) and
  * restart the optimiser there: u = v = v_prev = (x, y), k = 0, a = 1, lambda re-derived at
@@ -229,6 +233,18 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const hp_iter
 /* Graph blocks captured and replayed by hp_iterate on this context so far (inspection; either
  * output may be NULL).  No device work. */
 int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays);
+
+/* `iters` iterations of the placer (Sec. 3.1) on slots of different netlists of this context,
+ * each with its own smoothing gammas[i] (> 0, host array [n_slots]), in shared launches: one
+ * launch per pass of an iteration covers every listed slot (the batched evaluation of several
+ * placement jobs at once).  Each iteration is, per slot, what hp_iterate does with that gamma;
+ * results are bit-identical to running each slot alone with hp_iterate.  Every slot must be
+ * in steady state: its lambda derived and its charge grouping built by an earlier iteration
+ * (one hp_iterate call), and no map kept by an evaluation since (HP_ESTATE otherwise).
+ * flags: HP_ITER_HPWL and HP_ITER_HPWL_LAST as for hp_iterate (no graph replay).  At most 32
+ * slots, each listed once (HP_EINVAL); iters < 0: HP_EINVAL.  Does not synchronise. */
+int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const double *gammas,
+                     int32_t flags, int32_t iters);
 
 /* Perturbation of Alg. 1 / Sec. 4.2 on slot's major solution u, which also restarts the
  * optimiser there.  mode HP_PERTURB_GAUSS: the round(fraction * n_movable) cells with the

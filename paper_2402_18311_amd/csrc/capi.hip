@@ -179,7 +179,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     const BinGeom g = bin_geom(s, d);
     if (halo < 0) halo = 1 << g.log_ts;
     const size_t ws = (size_t)(1 << g.log_ts) + halo;
-    size_t o = 0;
+    size_t o = kDescBytes;  // the slot's descriptor (SlotDesc) first
     auto put = [&](size_t &f, size_t bytes) {
         f = o;
         o = align256(o + bytes);
@@ -790,6 +790,22 @@ int get_slot(hp_ctx *ctx, int32_t id, Slot **s, Netlist **n) {
     return HP_OK;
 }
 
+// Write the descriptor (SlotDesc) of NL into the head of every listed slot buffer, on the
+// context's stream, and wait for it: slot allocation and launch-setting changes only.
+int write_descs(hp_ctx *ctx, const Netlist &NL, const std::vector<char *> &bases) {
+    const SlotDesc d{NL.nd, NL.bk, NL.L};
+    for (char *b : bases)
+        HP_CHECK(hipMemcpyAsync(b, &d, sizeof(d), hipMemcpyHostToDevice, ctx->stream));
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    return HP_OK;
+}
+int rewrite_descs(hp_ctx *ctx, int netlist) {
+    std::vector<char *> bases;
+    for (const Slot &s : ctx->slots)
+        if (s.alive && s.netlist == netlist) bases.push_back(s.base);
+    return write_descs(ctx, ctx->nets[netlist], bases);
+}
+
 // Resolve a slot list into launch chunks (all on one netlist).
 int resolve(hp_ctx *ctx, const int32_t *slots, int32_t n, Netlist **net,
             std::vector<SlotArgs> &chunks, std::vector<Slot *> &ss) {
@@ -1080,6 +1096,89 @@ int hpwl_resolved(hp_ctx *, Netlist *, const std::vector<SlotArgs> &,
 }  // namespace
 
 // ============================================================================================
+namespace {
+// Iterations over slots of different netlists in shared launches: every launch of an
+// iteration covers all slots (blockIdx.y), each block finding its slot's netlist, layout and
+// sizes in the descriptor at the head of the slot buffer.  The launches and their arithmetic
+// are those of hp_iterate's steady state in its closing-reduction step form with the scatter's
+// grouping rebuilt inside the rebuilding evaluation (both bit-identical to the other forms).
+template <typename T>
+int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<Netlist *> &nls,
+                  const SlotGammas &g, int32_t flags, int32_t iters) {
+    hipStream_t st = ctx->stream;
+    const int n = (int)ss.size();
+    SlotArgs sa{};
+    for (Slot *s : ss) sa.base[sa.n++] = s->base;
+    // grids of the passes whose sizes do not change between iterations: the largest slot's
+    int big_x = 0, cg_x = 0, rows_x = 0, cols_x = 0, inv_x = 0, step_x = 0;
+    size_t l_rows = 0, l_cols = 0, l_inv = 0;
+    for (const Netlist *N : nls) {
+        const NetDev &nd = N->nd;
+        big_x = std::max(big_x, nd.n_big);
+        cg_x = std::max(cg_x, round8(std::max(1, cell_parts(nd))));
+        rows_x = std::max(rows_x, rows_fwd_blocks(nd));
+        cols_x = std::max(cols_x, nd.mx / 2);
+        inv_x = std::max(inv_x, nd.my / 2);
+        step_x = std::max(step_x, step_blocks(nd));
+        l_rows = std::max(l_rows, rows_fwd_lds_of<T>(nd));
+        l_cols = std::max(l_cols, cols_lds_of<T>(nd));
+        l_inv = std::max(l_inv, rows_inv_lds_of<T>(nd));
+    }
+    for (int it = 0; it < iters; ++it) {
+        uint32_t accm = 0, cntm = 0, hmask = 0, banks = 0;
+        int front_x = 0, cs_x = 0, pl_x = 0, ac_x = 0;
+        size_t l_front = 0, l_pl = 0, l_ac = 0;
+        SlotArgs due{};  // slots whose grouping is rebuilt in this evaluation
+        for (int i = 0; i < n; ++i) {
+            Slot *s = ss[i];
+            const Netlist &N = *nls[i];
+            const bool rebuild = s->since_group >= N.regroup_every;
+            if (rebuild) {
+                cntm |= 1u << i;
+                due.base[due.n++] = s->base;
+                cs_x = std::max(cs_x, colscan_blocks(N.nd));
+                pl_x = std::max(pl_x, N.nd.sort_blocks);
+                ac_x = std::max(ac_x, N.nd.max_chunks);
+                l_pl = std::max(l_pl, scatter_count_lds(N.nd));
+                l_ac = std::max(l_ac, scatter_accum_lds(N.nd));
+            } else {
+                accm |= 1u << i;
+            }
+            if (s->hpwl_requested) {  // rides in this evaluation's sweep
+                hmask |= 1u << i;
+                s->hpwl_requested = false;
+                s->hpwl_pending = true;
+            }
+            banks |= (uint32_t)s->bank << i;
+            front_x = std::max(front_x, front_blocks(N.nd, N.bk, !rebuild, rebuild));
+            l_front = std::max(l_front, front_lds<T>(N.nd, N.bk, !rebuild, rebuild));
+        }
+        HP_CHECK(rag_front<T>(sa, g, accm, cntm, hmask, front_x, l_front, st));
+        if (due.n) HP_CHECK(rag_regroup_tail<T>(due, cs_x, pl_x, ac_x, l_pl, l_ac, st));
+        HP_CHECK(rag_spectral<T>(sa, rows_x, cols_x, inv_x, l_rows, l_cols, l_inv, st));
+        HP_CHECK(rag_big_grad<T>(sa, big_x, st));
+        HP_CHECK(rag_cell_grad<T>(sa, cg_x, st));
+        HP_CHECK(rag_eval_finish(sa, banks, st));
+        HP_CHECK(rag_step<T>(sa, step_x, banks, st));
+        for (int i = 0; i < n; ++i) {
+            Slot *s = ss[i];
+            s->since_group = (cntm >> i) & 1u ? 1 : s->since_group + 1;
+            s->maps_valid = false;
+            s->rho_dirty = false;
+            s->step_proposed = false;
+            s->step_fused = false;
+            s->totals_pending = true;
+            s->bank ^= 1;  // the step committed into the other bank
+            if (flags & HP_ITER_HPWL) s->hpwl_requested = true;
+        }
+    }
+    if (iters > 0 && !(flags & HP_ITER_HPWL) && (flags & HP_ITER_HPWL_LAST))
+        for (Slot *s : ss) s->hpwl_requested = true;
+    return HP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int hp_profile_enable(hp_ctx *ctx, int on, const char *only_kernel) {
@@ -1223,7 +1322,7 @@ int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
     Scalars s;
     init_scalars(s, 1e-4, 4.0, 1000);
     HP_CHECK(hipMemcpyAsync(base + NL.L.scal, &s, sizeof(s), hipMemcpyHostToDevice, st));
-    HP_CHECK(hipStreamSynchronize(st));
+    HP_TRY(write_descs(ctx, NL, {base}));  // waits for the stream
     Slot sl;
     sl.alive = true;
     sl.netlist = netlist;
@@ -1378,11 +1477,11 @@ int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
             if (value != 0 && value != 512 && value != 1024)
                 return fail(HP_EINVAL, "spectral threads must be 0, 512 or 1024");
             NL.nd.spec_threads = value;
-            return HP_OK;
+            return rewrite_descs(ctx, netlist);
         case HP_TUNE_SWEEP_INTERLEAVE:
             if (value != 0 && value != 1) return fail(HP_EINVAL, "sweep interleave must be 0 or 1");
             NL.nd.sweep_interleave = value;
-            return HP_OK;
+            return rewrite_descs(ctx, netlist);
         default:
             return fail(HP_EINVAL, "unknown tunable");
     }
@@ -1656,6 +1755,50 @@ int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (captures) *captures = ctx->graph_captures;
     if (replays) *replays = ctx->graph_replays;
+    return HP_OK;
+}
+
+int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n, const double *gammas,
+                     int32_t flags, int32_t iters) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (!slots || n <= 0) return fail(HP_EINVAL, "empty slot list");
+    if (n > kMaxSlots) return fail(HP_EINVAL, "at most " + std::to_string(kMaxSlots) + " slots per call");
+    if (!gammas) return fail(HP_EINVAL, "gammas is NULL");
+    if (iters < 0) return fail(HP_EINVAL, "iters must be >= 0");
+    if (flags & ~(HP_ITER_HPWL | HP_ITER_HPWL_LAST))
+        return fail(HP_EINVAL, "unknown flags (HP_ITER_HPWL and HP_ITER_HPWL_LAST only)");
+    std::vector<Slot *> ss;
+    std::vector<Netlist *> nls;
+    SlotGammas g{};
+    for (int i = 0; i < n; ++i) {
+        Slot *s;
+        Netlist *nl;
+        HP_TRY(get_slot(ctx, slots[i], &s, &nl));
+        for (const Slot *o : ss)
+            if (o == s) return fail(HP_EINVAL, "slot " + std::to_string(slots[i]) + " listed twice");
+        if (!(gammas[i] > 0) || !std::isfinite(gammas[i]))
+            return fail(HP_EINVAL, "gamma must be > 0 (slot " + std::to_string(slots[i]) + ")");
+        // steady state: lambda derived (a first evaluation ran), a scatter grouping, no kept map
+        if (!s->lambda_valid || s->since_group < 0 || s->rho_dirty)
+            return fail(HP_ESTATE, "slot " + std::to_string(slots[i]) +
+                                       " is not in steady state (run one hp_iterate on it first)");
+        ss.push_back(s);
+        nls.push_back(nl);
+        g.inv[i] = 1.0 / gammas[i];
+    }
+    return ctx->precision == 32 ? iterate_multi<float>(ctx, ss, nls, g, flags, iters)
+                                : iterate_multi<double>(ctx, ss, nls, g, flags, iters);
+}
+
+int hp_netlist_free(hp_ctx *ctx, int32_t netlist) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
+        return fail(HP_ESTATE, "unknown netlist");
+    for (const Slot &s : ctx->slots)
+        if (s.alive && s.netlist == netlist)
+            return fail(HP_ESTATE, "netlist " + std::to_string(netlist) + " still has live slots");
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    ctx->nets[netlist] = Netlist{};  // alive = false; host arrays released
     return HP_OK;
 }
 

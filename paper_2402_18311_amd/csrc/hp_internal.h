@@ -160,6 +160,44 @@ struct SlotArgs {
     int32_t n;
 };
 
+// Descriptor at the head of every slot buffer: the device view of the slot's netlist, its
+// sweep buckets and the slot's layout, so that a launch over slots of different netlists
+// (hp_iterate_multi) finds each slot's netlist in the slot's own buffer.  Kernels of such
+// launches take RAG = true and read it per block; the slot's arrays start after it.  Written
+// when the slot is allocated and when a launch setting of its netlist changes.
+struct SlotDesc {
+    NetDev nd;
+    Buckets bk;
+    SlotLayout L;
+};
+// 1 / smoothing of each slot of such a launch (kernel argument)
+struct SlotGammas {
+    double inv[kMaxSlots];
+};
+constexpr size_t kDescBytes = 4096;
+static_assert(sizeof(SlotDesc) <= kDescBytes, "slot descriptor exceeds its reserved bytes");
+__host__ __device__ inline const SlotDesc *slot_desc(const char *base) {
+    return reinterpret_cast<const SlotDesc *>(base);
+}
+// The netlist view / layout of a block's slot: the kernel arguments, or (RAG) the slot's
+// descriptor.
+template <bool RAG>
+__device__ __forceinline__ const NetDev &view_nd(const NetDev &arg, const char *base) {
+    if constexpr (RAG) return slot_desc(base)->nd;
+    else return arg;
+}
+template <bool RAG>
+__device__ __forceinline__ const SlotLayout &view_L(const SlotLayout &arg, const char *base) {
+    if constexpr (RAG) return slot_desc(base)->L;
+    else return arg;
+}
+template <bool RAG>
+__device__ __forceinline__ const Buckets &view_bk(const Buckets &arg, const char *base) {
+    if constexpr (RAG) return slot_desc(base)->bk;
+    else return arg;
+}
+__host__ __device__ inline int round8(int v) { return (v + kXcds - 1) / kXcds * kXcds; }
+
 __host__ __device__ inline Scalars *scalars(char *base, const SlotLayout &L) {
     return reinterpret_cast<Scalars *>(base + L.scal);
 }
@@ -285,6 +323,41 @@ hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumb
                               const SlotLayout &L, hipStream_t st);
 
 int sweep_parts(const Buckets &bk);
-int cell_parts(const NetDev &nd);
+__host__ __device__ inline int cell_parts(const NetDev &nd) { return (nd.n_mov + kBlock - 1) / kBlock; }
+
+// ---- launches over steady-state slots of different netlists (hp_iterate_multi) -------------
+// Each slot's netlist, layout and smoothing come from its descriptor; grid.x is the largest
+// need over the slots (blocks past a slot's own count return); dynamic LDS the largest need.
+// Bit s of a mask is slot s of the launch.  accm / cntm: the first launch accumulates the
+// charge in the slot's existing grouping / counts for a new one; hmask: its HPWL sweep rides
+// along; banks: optimiser-state banks.
+template <typename T>
+hipError_t rag_front(const SlotArgs &sa, const SlotGammas &g, uint32_t accm, uint32_t cntm,
+                     uint32_t hmask, int grid_x, size_t lds, hipStream_t st);
+int front_blocks(const NetDev &nd, const Buckets &bk, bool accum, bool count);
+template <typename T> size_t front_lds(const NetDev &nd, const Buckets &bk, bool accum, bool count);
+// The rest of a rebuild of the scatter's grouping for every slot of sa (scans, placement and
+// the accumulation in the new order); grids from the largest slot.
+template <typename T>
+hipError_t rag_regroup_tail(const SlotArgs &sa, int colscan_x, int place_x, int accum_x,
+                            size_t place_lds, size_t accum_lds, hipStream_t st);
+int colscan_blocks(const NetDev &nd);
+template <typename T>
+hipError_t rag_spectral(const SlotArgs &sa, int rows_x, int cols_x, int inv_x, size_t lds_rows,
+                        size_t lds_cols, size_t lds_inv, hipStream_t st);
+template <typename T>
+hipError_t rag_big_grad(const SlotArgs &sa, int grid_x, hipStream_t st);
+template <typename T>
+hipError_t rag_cell_grad(const SlotArgs &sa, int grid_x, hipStream_t st);
+// The closing reduction in steady state (FIN_STEP) of every slot, then the update.
+hipError_t rag_eval_finish(const SlotArgs &sa, uint32_t banks, hipStream_t st);
+template <typename T>
+hipError_t rag_step(const SlotArgs &sa, int grid_x, uint32_t banks, hipStream_t st);
+// host-side sizes the launches above need for one netlist
+int rows_fwd_blocks(const NetDev &nd);
+template <typename T> size_t rows_fwd_lds_of(const NetDev &nd);
+template <typename T> size_t cols_lds_of(const NetDev &nd);
+template <typename T> size_t rows_inv_lds_of(const NetDev &nd);
+int step_blocks(const NetDev &nd);
 
 }  // namespace hp

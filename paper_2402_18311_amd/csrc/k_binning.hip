@@ -34,9 +34,13 @@ namespace hp {
 //    (ceil(cells / kChunk) per tile) give the tile starts, chunk starts and each chunk's tile
 //    and cell range.
 constexpr int kColTiles = 16, kColBands = kBlock / kColTiles, kColRows = 32;
-__global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+template <bool RAG>
+__global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
     __shared__ int band[kColBands][kColTiles];
     char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    if (RAG && blockIdx.x * kColTiles >= nd.ntiles) return;  // past the slot's own tiles
     const int *__restrict__ cnt = reinterpret_cast<const int *>(base + L.scnt);
     int *__restrict__ off = reinterpret_cast<int *>(base + L.soff);
     int *tot = reinterpret_cast<int *>(base + L.tstart);
@@ -76,9 +80,13 @@ __global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nd, SlotArgs
 }
 
 constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void bin_tilescan_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+template <bool RAG>
+__global__ __launch_bounds__(kScanThreads) void bin_tilescan_kernel(NetDev nda, SlotArgs sa,
+                                                                    SlotLayout La) {
     __shared__ int ws[kScanThreads / 64][2];
     char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
     int *tstart = reinterpret_cast<int *>(base + L.tstart);
     int *cstart = reinterpret_cast<int *>(base + L.cstart);
     int4 *chunk = reinterpret_cast<int4 *>(base + L.chunk);
@@ -127,9 +135,13 @@ __global__ __launch_bounds__(kScanThreads) void bin_tilescan_kernel(NetDev nd, S
     }
 }
 
-__global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
+template <bool RAG>
+__global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
     extern __shared__ int rank[];  // [ntiles]
     char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    if (RAG && (int)blockIdx.x >= nd.sort_blocks) return;  // past the slot's own blocks
     for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) rank[t] = 0;
     __syncthreads();
     const int *tile = reinterpret_cast<const int *>(base + L.tile);
@@ -153,9 +165,11 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nd, SlotArgs s
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nd, SlotArgs sa, SlotLayout L) {
-    accum_body<T>(nd, sa.base[blockIdx.y], L, blockIdx.x);
+template <typename T, bool RAG>
+__global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
+    char *base = sa.base[blockIdx.y];
+    // accum_body returns for chunks past the slot's own
+    accum_body<T>(view_nd<RAG>(nda, base), base, view_L<RAG>(La, base), blockIdx.x);
 }
 
 size_t scatter_count_lds(const NetDev &nd) { return sizeof(int) * (size_t)nd.ntiles; }
@@ -168,23 +182,52 @@ size_t scatter_accum_lds(const NetDev &nd) {
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                                bool accum, hipStream_t st) {
-    HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel, dim3((nd.ntiles + kColTiles - 1) / kColTiles, sa.n),
+    HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel<false>, dim3((nd.ntiles + kColTiles - 1) / kColTiles, sa.n),
               dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_tilescan_kernel", bin_tilescan_kernel, dim3(1, sa.n), dim3(kScanThreads), 0, st, nd,
+    HP_LAUNCH("bin_tilescan_kernel", bin_tilescan_kernel<false>, dim3(1, sa.n), dim3(kScanThreads), 0, st, nd,
               sa, L);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_place_kernel", bin_place_kernel, dim3(nd.sort_blocks, sa.n), dim3(kBlock),
+    HP_LAUNCH("bin_place_kernel", bin_place_kernel<false>, dim3(nd.sort_blocks, sa.n), dim3(kBlock),
               scatter_count_lds(nd), st, nd, sa, L);
     e = hipGetLastError();
     if (e != hipSuccess || !accum) return e;
-    HP_LAUNCH("bin_accum_kernel", bin_accum_kernel<T>, dim3(nd.max_chunks, sa.n), dim3(kBlock),
+    HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, false>), dim3(nd.max_chunks, sa.n), dim3(kBlock),
               scatter_accum_lds(nd), st, nd, sa, L);
     return hipGetLastError();
 }
 
+// The same over slots of different netlists (each slot's sizes and layout from its
+// descriptor); grid.x from the largest slot, dynamic LDS the largest need.
+template <typename T>
+hipError_t rag_regroup_tail(const SlotArgs &sa, int colscan_x, int place_x, int accum_x,
+                            size_t place_lds, size_t accum_lds, hipStream_t st) {
+    const NetDev nd0{};
+    const SlotLayout L0{};
+    HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel<true>, dim3(colscan_x, sa.n), dim3(kBlock),
+              0, st, nd0, sa, L0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    HP_LAUNCH("bin_tilescan_kernel", bin_tilescan_kernel<true>, dim3(1, sa.n), dim3(kScanThreads),
+              0, st, nd0, sa, L0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    HP_LAUNCH("bin_place_kernel", bin_place_kernel<true>, dim3(place_x, sa.n), dim3(kBlock),
+              place_lds, st, nd0, sa, L0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, true>), dim3(accum_x, sa.n), dim3(kBlock),
+              accum_lds, st, nd0, sa, L0);
+    return hipGetLastError();
+}
+int colscan_blocks(const NetDev &nd) { return (nd.ntiles + kColTiles - 1) / kColTiles; }
+
+template hipError_t rag_regroup_tail<float>(const SlotArgs &, int, int, int, size_t, size_t,
+                                            hipStream_t);
+template hipError_t rag_regroup_tail<double>(const SlotArgs &, int, int, int, size_t, size_t,
+                                             hipStream_t);
 template hipError_t launch_regroup_tail<float>(const NetDev &, const SlotArgs &, const SlotLayout &,
                                                bool, hipStream_t);
 template hipError_t launch_regroup_tail<double>(const NetDev &, const SlotArgs &,

@@ -158,10 +158,13 @@ __device__ void exact_adjoint(const NetDev &nd, const T *psi, int i, double x, d
 // and the gradient pass reduces the cell's pin gradients and its footprint's field (or
 // exact-adjoint) terms over the block in FP64 and stores the wirelength part in g and the
 // density part in gd, where the cell gradient pass picks them up.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+template <typename T, bool RAG>
+__global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
                                                           int grad_mode) {
     char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    if (RAG && (int)blockIdx.x >= nd.n_big) return;  // past the slot's own big cells
     const int i = nd.big_ids[blockIdx.x];
     const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
     double s[4] = {0.0, 0.0, 0.0, 0.0};  // wirelength x, y; density x, y
@@ -211,7 +214,7 @@ template <typename T>
 hipError_t launch_big_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            int grad_mode, hipStream_t st) {
     if (nd.n_big == 0) return hipSuccess;
-    HP_LAUNCH("big_grad_kernel", big_grad_kernel<T>, dim3(nd.n_big, sa.n), dim3(kBlock), 0, st,
+    HP_LAUNCH("big_grad_kernel", (big_grad_kernel<T, false>), dim3(nd.n_big, sa.n), dim3(kBlock), 0, st,
               nd, sa, L, grad_mode);
     return hipGetLastError();
 }
@@ -240,16 +243,20 @@ __device__ __forceinline__ void load_row4(const vec2<T> *src, vec2<T> (&r)[4]) {
 // on a slot's first evaluation (lambda not yet derived) it writes gWL to g and gD to gd and
 // the per-block L1 norms of both, from which lambda_0 is derived.  In steady state the block
 // also forms its partials of the following Nesterov step's reductions.
-template <typename T>
 // Cell block cb = xcd_remap(blockIdx.x) of nb blocks (the grid is nb rounded up to a multiple
 // of 8), so that each XCD walks one contiguous eighth of the cells: the pin gradients that
-// neighbouring cells share stay in that XCD's L2.
-__global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+// neighbouring cells share stay in that XCD's L2.  RAG: the slot's netlist and layout from its
+// descriptor and nb its own block count (the grid: the largest slot's, rounded up).
+template <typename T, bool RAG>
+__global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
                                                            double lam_fixed, int use_fixed,
-                                                           int grad_mode, int nb) {
+                                                           int grad_mode, int nb_arg) {
+    char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    const int nb = RAG ? max(1, cell_parts(nd)) : nb_arg;  // as launch_cell_grad
     const int cb = xcd_remap(blockIdx.x, gridDim.x);
     if (cb >= nb) return;  // whole block: no barrier is skipped by part of it
-    char *base = sa.base[blockIdx.y];
     Scalars *sc = scalars(base, L);
     const bool init = !use_fixed && sc->lambda_valid == 0;
     const int i = cb * kBlock + threadIdx.x;
@@ -374,8 +381,6 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nd, SlotArgs s
     }
 }
 
-int cell_parts(const NetDev &nd) { return (nd.n_mov + kBlock - 1) / kBlock; }
-
 // (x, y) pairs <-> separate x and y arrays of n elements of `rs` bytes, device to device (a
 // strided 2-D copy with one tiny row per element is far slower).  Either of x, y may be null
 // when splitting.
@@ -495,12 +500,28 @@ hipError_t launch_cell_grad(const NetDev &nd, const SlotArgs &sa, const SlotLayo
                             int nov, int finish, uint32_t banks, hipStream_t st) {
     const int nb = std::max(1, cell_parts(nd));
     const int grid = (nb + kXcds - 1) / kXcds * kXcds;
-    HP_LAUNCH("cell_grad_kernel", cell_grad_kernel<T>, dim3(grid, sa.n), dim3(kBlock), 0, st, nd,
+    HP_LAUNCH("cell_grad_kernel", (cell_grad_kernel<T, false>), dim3(grid, sa.n), dim3(kBlock), 0, st, nd,
               sa, L, lambda_fixed, (int)use_fixed, grad_mode, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (finish < 0) return hipSuccess;
     return launch_eval_finish(nd, sa, L, nwl, ne, nov, nb, use_fixed, lambda_fixed, finish, banks, st);
+}
+
+// Over slots of different netlists in steady state: big cells, then the cell gradients with
+// each slot's own lambda, grids from the largest slot.
+template <typename T>
+hipError_t rag_big_grad(const SlotArgs &sa, int grid_x, hipStream_t st) {
+    if (grid_x == 0) return hipSuccess;
+    HP_LAUNCH("big_grad_kernel", (big_grad_kernel<T, true>), dim3(grid_x, sa.n), dim3(kBlock), 0, st,
+              NetDev{}, sa, SlotLayout{}, 0);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t rag_cell_grad(const SlotArgs &sa, int grid_x, hipStream_t st) {
+    HP_LAUNCH("cell_grad_kernel", (cell_grad_kernel<T, true>), dim3(grid_x, sa.n), dim3(kBlock), 0,
+              st, NetDev{}, sa, SlotLayout{}, 0.0, 0, 0, 0);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -522,7 +543,9 @@ hipError_t launch_fixed_map(const NetDev &nd, const double *fxy, const double *f
                                             const SlotLayout &, double, bool, int, int, int, \
                                             int, int, uint32_t, hipStream_t);                              \
     template hipError_t launch_fixed_map<T>(const NetDev &, const double *, const double *, \
-                                            int64_t *, hipStream_t);
+                                            int64_t *, hipStream_t);                        \
+    template hipError_t rag_big_grad<T>(const SlotArgs &, int, hipStream_t);                \
+    template hipError_t rag_cell_grad<T>(const SlotArgs &, int, hipStream_t);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

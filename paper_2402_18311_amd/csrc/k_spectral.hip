@@ -163,8 +163,10 @@ __device__ __forceinline__ T block_sum_nt(T v, T *red) {
 // contiguous eighth of the grid when the grid is a multiple of 8), so the column pass's 8-byte
 // reads and writes of neighbouring columns meet in one L2 and leave it as whole lines, and the
 // row passes' neighbouring rows share their tiles' charge windows.
-__device__ __forceinline__ int spec_block() {
-    return (gridDim.x % kXcds) ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+// nb: the slot's block count (the grid's, except in a launch over slots of different
+// netlists, whose blocks past nb return first).
+__device__ __forceinline__ int spec_block(int nb) {
+    return (nb % kXcds) ? (int)blockIdx.x : xcd_remap(blockIdx.x, nb);
 }
 
 // LDS layout helpers (16-byte aligned sections)
@@ -175,18 +177,32 @@ __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~size_t(15)
 // A block takes 2 lpb consecutive rows (lpb complex lines), one bin per thread and round.
 constexpr int kRowsFwdThreads = 1024;
 
-template <typename T>
-__global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                                 int lpb, int keep) {
+// R1 takes lpb complex lines (2 rows each) per block
+__host__ __device__ inline int rows_fwd_lines(const NetDev &nd) {
+    int lpb = 512 / nd.mx;
+    if (lpb < 1) lpb = 1;
+    if (lpb > nd.my / 2) lpb = nd.my / 2;
+    return lpb;
+}
+
+// RAG: the slot's netlist, layout and lpb from its descriptor (every pass below likewise)
+template <typename T, bool RAG>
+__global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nda, SlotArgs sa, SlotLayout La,
+                                                                 int lpb_arg, int keep) {
     constexpr int NT = kRowsFwdThreads;
     extern __shared__ __align__(16) unsigned char smem[];
+    char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    const int lpb = RAG ? rows_fwd_lines(nd) : lpb_arg;
+    const int nb = RAG ? nd.my / 2 / lpb : (int)gridDim.x;
+    if ((int)blockIdx.x >= nb) return;
     const int M = nd.mx, logM = nd.logmx;
     vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem);
     vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + al16(sizeof(vec2<T>) * (M / 2)));
     vec2<T> *buf = reinterpret_cast<vec2<T> *>(smem + al16(sizeof(vec2<T>) * (M / 2)) +
                                                al16(sizeof(vec2<T>) * M));
     T *bufr = reinterpret_cast<T *>(buf);  // line l, element n: real part 2 (l M + n), imag + 1
-    char *base = sa.base[blockIdx.y];
     Prefetch<vec2<T>, NT, 1> ptw;  // M / 2 <= 1024
     Prefetch<vec2<T>, NT, 2> pph;  // M <= 2048
     ptw.get(reinterpret_cast<const vec2<T> *>(nd.tw_x), M / 2);
@@ -194,7 +210,7 @@ __global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nd, Slot
     int64_t *rho = reinterpret_cast<int64_t *>(base + L.rho);
     T *t1 = reinterpret_cast<T *>(base + L.t1);
     const int nel = 2 * lpb * M;
-    const int bid = spec_block();
+    const int bid = spec_block(nb);
     const size_t g0 = (size_t)bid * nel;  // first bin: row 2 lpb bid, column 0
     long long over = 0;
     for (int e = threadIdx.x; e < nel; e += NT) {
@@ -245,9 +261,14 @@ __host__ __device__ inline size_t cols_lds(int M) {
 // C and R2 run 1024-thread blocks when a launch has at most one block per CU (a single slot:
 // the block's latency is the pass's time), 512-thread blocks when it has more (batched slots:
 // smaller blocks interleave better); see wide_spectral.
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void spec_cols(NetDev nd, SlotArgs sa, SlotLayout L, int want_psi) {
+template <typename T, int NT, bool RAG>
+__global__ __launch_bounds__(NT) void spec_cols(NetDev nda, SlotArgs sa, SlotLayout La, int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
+    char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    const int nb = RAG ? nd.mx / 2 : (int)gridDim.x;
+    if ((int)blockIdx.x >= nb) return;
     const int M = nd.my, logM = nd.logmy, mx = nd.mx;
     size_t o = 0;
     vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem + o);
@@ -263,8 +284,7 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nd, SlotArgs sa, SlotLayo
     T *inv = reinterpret_cast<T *>(smem + o);  // [2][M]
     o += al16(sizeof(T) * 2 * M);
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M]
-    char *base = sa.base[blockIdx.y];
-    const int bid = spec_block();
+    const int bid = spec_block(nb);
     const int u0 = bid * 2;
     // every global load first: the two columns (as one complex line), the y tables and
     // symbols (M <= 2048: at most 4 elements of each per thread)
@@ -366,10 +386,15 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nd, SlotArgs sa, SlotLayo
 
 // ---- R2 ---------------------------------------------------------------------------------
 // lds: tw [M/2] | ph [M] | stage [nst][2][M] | work [nst][M]
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nd, SlotArgs sa, SlotLayout L,
+template <typename T, int NT, bool RAG>
+__global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nda, SlotArgs sa, SlotLayout La,
                                                     int want_psi) {
     extern __shared__ __align__(16) unsigned char smem[];
+    char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    const int nb = RAG ? nd.my / 2 : (int)gridDim.x;
+    if ((int)blockIdx.x >= nb) return;
     const int M = nd.mx, logM = nd.logmx;
     const int nst = want_psi ? 3 : 2;
     size_t o = 0;
@@ -380,8 +405,7 @@ __global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nd, SlotArgs sa, Slot
     T *stage = reinterpret_cast<T *>(smem + o);  // [nst][2][M]
     o += al16(sizeof(T) * (size_t)nst * 2 * M);
     vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);
-    char *base = sa.base[blockIdx.y];
-    const int k0 = spec_block() * 2;
+    const int k0 = spec_block(nb) * 2;
     // every global load first: the two rows of Bx, By (and Bp) and the x tables; the rows in
     // rounds of 8 elements per thread (one round for M <= 1024 without psi)
     const T *src[3] = {reinterpret_cast<const T *>(base + L.bx), reinterpret_cast<const T *>(base + L.by),
@@ -447,14 +471,6 @@ __global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nd, SlotArgs sa, Slot
     }
 }
 
-// R1 takes lpb complex lines (2 rows each) per block
-static int rows_fwd_lines(const NetDev &nd) {
-    int lpb = 512 / nd.mx;
-    if (lpb < 1) lpb = 1;
-    if (lpb > nd.my / 2) lpb = nd.my / 2;
-    return lpb;
-}
-
 int spectral_overflow_parts(const NetDev &nd) { return nd.my / 2 / rows_fwd_lines(nd); }
 
 template <typename T>
@@ -479,28 +495,52 @@ template <typename T>
 hipError_t launch_spectral(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                            bool keep_maps, bool want_psi, hipStream_t st) {
     const int lpb = rows_fwd_lines(nd);
-    HP_LAUNCH("spec_rows_fwd", spec_rows_fwd<T>, dim3(nd.my / 2 / lpb, sa.n), dim3(kRowsFwdThreads),
+    HP_LAUNCH("spec_rows_fwd", (spec_rows_fwd<T, false>), dim3(nd.my / 2 / lpb, sa.n), dim3(kRowsFwdThreads),
               rows_fwd_lds<T>(nd), st, nd, sa, L, lpb, (int)keep_maps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nst = want_psi ? 3 : 2;
     if (wide_spectral(nd, sa)) {
-        HP_LAUNCH("spec_cols", (spec_cols<T, 1024>), dim3(nd.mx / 2, sa.n), dim3(1024),
+        HP_LAUNCH("spec_cols", (spec_cols<T, 1024, false>), dim3(nd.mx / 2, sa.n), dim3(1024),
                   cols_lds<T>(nd.my), st, nd, sa, L, (int)want_psi);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 1024>), dim3(nd.my / 2, sa.n), dim3(1024),
+        HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 1024, false>), dim3(nd.my / 2, sa.n), dim3(1024),
                   rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
     } else {
-        HP_LAUNCH("spec_cols", (spec_cols<T, 512>), dim3(nd.mx / 2, sa.n), dim3(512),
+        HP_LAUNCH("spec_cols", (spec_cols<T, 512, false>), dim3(nd.mx / 2, sa.n), dim3(512),
                   cols_lds<T>(nd.my), st, nd, sa, L, (int)want_psi);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 512>), dim3(nd.my / 2, sa.n), dim3(512),
+        HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 512, false>), dim3(nd.my / 2, sa.n), dim3(512),
                   rows_inv_lds<T>(nd, nst), st, nd, sa, L, (int)want_psi);
     }
     return hipGetLastError();
 }
+
+// The three passes over slots of different netlists (no kept maps, no potential): 512-thread
+// column and inverse-row blocks (many slots share the launch); grids from the largest slot.
+template <typename T>
+hipError_t rag_spectral(const SlotArgs &sa, int rows_x, int cols_x, int inv_x, size_t lds_rows,
+                        size_t lds_cols, size_t lds_inv, hipStream_t st) {
+    const NetDev nd0{};
+    const SlotLayout L0{};
+    HP_LAUNCH("spec_rows_fwd", (spec_rows_fwd<T, true>), dim3(rows_x, sa.n), dim3(kRowsFwdThreads),
+              lds_rows, st, nd0, sa, L0, 0, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    HP_LAUNCH("spec_cols", (spec_cols<T, 512, true>), dim3(cols_x, sa.n), dim3(512), lds_cols, st,
+              nd0, sa, L0, 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    HP_LAUNCH("spec_rows_inv", (spec_rows_inv<T, 512, true>), dim3(inv_x, sa.n), dim3(512), lds_inv,
+              st, nd0, sa, L0, 0);
+    return hipGetLastError();
+}
+int rows_fwd_blocks(const NetDev &nd) { return nd.my / 2 / rows_fwd_lines(nd); }
+template <typename T> size_t rows_fwd_lds_of(const NetDev &nd) { return rows_fwd_lds<T>(nd); }
+template <typename T> size_t cols_lds_of(const NetDev &nd) { return cols_lds<T>(nd.my); }
+template <typename T> size_t rows_inv_lds_of(const NetDev &nd) { return rows_inv_lds<T>(nd, 2); }
 
 template <typename T>
 int spectral_energy_parts(const NetDev &nd) { return nd.mx / 2; }
@@ -513,11 +553,12 @@ size_t spectral_max_lds(const NetDev &nd) {
 // Ask for `bytes` of dynamic LDS per block on the three passes (above the 64 KB default).
 template <typename T>
 hipError_t spectral_prepare(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)spec_rows_fwd<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    const void *fs[4] = {(const void *)spec_cols<T, 512>, (const void *)spec_cols<T, 1024>,
-                         (const void *)spec_rows_inv<T, 512>, (const void *)spec_rows_inv<T, 1024>};
+    const void *fs[] = {(const void *)spec_rows_fwd<T, false>, (const void *)spec_rows_fwd<T, true>,
+                        (const void *)spec_cols<T, 512, false>, (const void *)spec_cols<T, 1024, false>,
+                        (const void *)spec_rows_inv<T, 512, false>,
+                        (const void *)spec_rows_inv<T, 1024, false>,
+                        (const void *)spec_cols<T, 512, true>, (const void *)spec_rows_inv<T, 512, true>};
+    hipError_t e = hipSuccess;
     for (const void *f : fs) {
         e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -530,7 +571,12 @@ hipError_t spectral_prepare(int bytes) {
                                            bool, bool, hipStream_t);                          \
     template int spectral_energy_parts<T>(const NetDev &);                                    \
     template size_t spectral_max_lds<T>(const NetDev &);                                      \
-    template hipError_t spectral_prepare<T>(int);
+    template hipError_t spectral_prepare<T>(int);                                             \
+    template hipError_t rag_spectral<T>(const SlotArgs &, int, int, int, size_t, size_t, size_t, \
+                                        hipStream_t);                                         \
+    template size_t rows_fwd_lds_of<T>(const NetDev &);                                       \
+    template size_t cols_lds_of<T>(const NetDev &);                                           \
+    template size_t rows_inv_lds_of<T>(const NetDev &);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

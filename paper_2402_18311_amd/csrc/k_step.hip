@@ -15,13 +15,19 @@ namespace hp {
 constexpr int kFinBlock = 1024;
 constexpr int kFinWaves = kFinBlock / 64;
 
-__global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
-                                                               int nwl, int ne, int nov, int ncell,
+// RAG: the slot's netlist and layout from its descriptor, ncell its own cell-gradient block
+// count (the steady-state step form only: nwl = ne = nov = 0).
+template <bool RAG>
+__global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
+                                                               int nwl, int ne, int nov, int ncell_arg,
                                                                int use_fixed, double lam_fixed,
                                                                int mode, uint32_t banks) {
     __shared__ double rs[kFinWaves][4], rm[kFinWaves];
     __shared__ long long ri[kFinWaves];
     char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    const int ncell = RAG ? max(1, cell_parts(nd)) : ncell_arg;  // as launch_cell_grad
     Scalars *sc = scalars(base, L);
     const double *part = reinterpret_cast<const double *>(base + L.part);
     // mode FIN_TOTALS: the WL, energy and overflow of the last evaluation only; FIN_STEP: the
@@ -144,7 +150,7 @@ hipError_t launch_eval_finish(const NetDev &nd, const SlotArgs &sa, const SlotLa
                               int ne, int nov, int ncell, bool use_fixed, double lam_fixed,
                               int mode, uint32_t banks, hipStream_t st) {
     const bool totals = mode != FIN_STEP, full = mode != FIN_TOTALS;
-    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel, dim3(1, sa.n), dim3(kFinBlock), 0, st, nd, sa,
+    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel<false>, dim3(1, sa.n), dim3(kFinBlock), 0, st, nd, sa,
               L, totals ? nwl : 0, totals ? ne : 0, totals ? nov : 0, full ? ncell : 0,
               (int)use_fixed, lam_fixed, mode, banks);
     return hipGetLastError();
@@ -267,10 +273,15 @@ constexpr int kStepThreads = 1024;  // cells per block of the update (fewer bloc
 // nc partials and the optimiser state of bank b.  One thread commits it into bank 1 - b and,
 // for an accepted step, multiplies lambda by the schedule's ratio; no block reads what that
 // thread writes.
-template <typename T>
-__global__ __launch_bounds__(kStepThreads) void step_update_kernel(NetDev nd, SlotArgs sa, SlotLayout L,
+// RAG: the slot's netlist and layout from its descriptor, the update of a proposed step only
+// (fused = 0); blocks past the slot's own cells return.
+template <typename T, bool RAG>
+__global__ __launch_bounds__(kStepThreads) void step_update_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
                                                                    int fused, int nc, uint32_t banks) {
     char *base = sa.base[blockIdx.y];
+    const NetDev &nd = view_nd<RAG>(nda, base);
+    const SlotLayout &L = view_L<RAG>(La, base);
+    if (RAG && (int)blockIdx.x * kStepThreads >= nd.n_mov) return;
     Scalars *sc = scalars(base, L);
     const int b = (banks >> blockIdx.y) & 1u;
     const int n = nd.n_mov;
@@ -429,10 +440,26 @@ hipError_t launch_step(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L
         if (e != hipSuccess) return e;
     }
     const int nu = (nd.n_mov + kStepThreads - 1) / kStepThreads;
-    HP_LAUNCH("step_update_kernel", step_update_kernel<T>, dim3(nu, sa.n), dim3(kStepThreads), 0, st, nd,
+    HP_LAUNCH("step_update_kernel", (step_update_kernel<T, false>), dim3(nu, sa.n), dim3(kStepThreads), 0, st, nd,
               sa, L, (int)fused, nc, banks);
     return hipGetLastError();
 }
+
+// Steady state over slots of different netlists: the closing reduction forms every slot's
+// step (its lambda and proposal), then the update.
+hipError_t rag_eval_finish(const SlotArgs &sa, uint32_t banks, hipStream_t st) {
+    HP_LAUNCH("eval_finish_kernel", eval_finish_kernel<true>, dim3(1, sa.n), dim3(kFinBlock), 0, st,
+              NetDev{}, sa, SlotLayout{}, 0, 0, 0, 0, 0, 0.0, FIN_STEP, banks);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t rag_step(const SlotArgs &sa, int grid_x, uint32_t banks, hipStream_t st) {
+    if (grid_x == 0) return hipSuccess;
+    HP_LAUNCH("step_update_kernel", (step_update_kernel<T, true>), dim3(grid_x, sa.n),
+              dim3(kStepThreads), 0, st, NetDev{}, sa, SlotLayout{}, 0, 0, banks);
+    return hipGetLastError();
+}
+int step_blocks(const NetDev &nd) { return (nd.n_mov + kStepThreads - 1) / kStepThreads; }
 
 template <typename T>
 hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumbent,
@@ -451,7 +478,8 @@ hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumb
     template hipError_t launch_step<T>(const NetDev &, const SlotArgs &, const SlotLayout &,     \
                                        bool, bool, uint32_t, hipStream_t);                      \
     template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \
-                                              const SlotLayout &, hipStream_t);
+                                              const SlotLayout &, hipStream_t);                 \
+    template hipError_t rag_step<T>(const SlotArgs &, int, uint32_t, hipStream_t);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

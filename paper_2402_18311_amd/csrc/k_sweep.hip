@@ -628,6 +628,57 @@ __global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Bucket
     }
 }
 
+// The first launch over steady-state slots of different netlists: each slot's netlist,
+// buckets, layout and smoothing from its descriptor, its block ranges as above from its own
+// sizes and the masks (bit blockIdx.y); blocks past the slot's own range return.
+template <typename T>
+__global__ __launch_bounds__(kBlock, 8) void rag_front_kernel(SlotArgs sa, SlotGammas g,
+                                                              uint32_t accm, uint32_t cntm,
+                                                              uint32_t hmask) {
+    char *base = sa.base[blockIdx.y];
+    const SlotDesc *d = slot_desc(base);
+    const NetDev &nd = d->nd;
+    const Buckets &bk = d->bk;
+    const SlotLayout &L = d->L;
+    const int nacc = ((accm >> blockIdx.y) & 1u) ? round8(nd.max_chunks) : 0;
+    const int ncnt = ((cntm >> blockIdx.y) & 1u) ? round8(nd.sort_blocks) : 0;
+    const int nbig = round8(nd.n_big);
+    const int s0 = nacc + ncnt + nbig;
+    const int bx = blockIdx.x;
+    if (bx >= s0 + bk.total_blocks) return;  // whole block
+    const T invg = (T)g.inv[blockIdx.y];
+    if (bx < nacc) {
+        accum_body<T>(nd, base, L, bx);
+    } else if (bx < nacc + ncnt) {
+        count_body<T>(nd, base, L, bx - nacc);
+    } else if (bx < s0) {
+        big_scatter_body<T>(nd, base, L, bx - nacc - ncnt);
+    } else if ((hmask >> blockIdx.y) & 1u) {
+        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - s0);
+    } else {
+        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - s0);
+    }
+}
+
+template <typename T>
+hipError_t rag_front(const SlotArgs &sa, const SlotGammas &g, uint32_t accm, uint32_t cntm,
+                     uint32_t hmask, int grid_x, size_t lds, hipStream_t st) {
+    HP_LAUNCH("eval_front_kernel", rag_front_kernel<T>, dim3(grid_x, sa.n), dim3(kBlock), lds, st,
+              sa, g, accm, cntm, hmask);
+    return hipGetLastError();
+}
+
+// Blocks and dynamic LDS of one slot's share of a first launch (as launch_eval_front sizes them)
+int front_blocks(const NetDev &nd, const Buckets &bk, bool accum, bool count) {
+    return (accum ? round8(nd.max_chunks) : 0) + (count ? round8(nd.sort_blocks) : 0) +
+           round8(nd.n_big) + bk.total_blocks;
+}
+template <typename T>
+size_t front_lds(const NetDev &nd, const Buckets &bk, bool accum, bool count) {
+    const size_t big = (bk.n > 0 && bk.G[0] == 0) ? sizeof(vec2<T>) * kNetRegs * kBlock : 0;
+    return std::max({accum ? scatter_accum_lds(nd) : 0, count ? scatter_count_lds(nd) : 0, big});
+}
+
 int sweep_parts(const Buckets &bk) { return bk.total_blocks; }
 
 // Exact HPWL of positions the caller holds (pairs over all cells): one partial per block into
@@ -697,7 +748,10 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
     template hipError_t launch_sweep_hpwl<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, hipStream_t);                  \
     template hipError_t launch_hpwl_positions<T>(const NetDev &, const Buckets &, const void *, \
-                                                 long long *, long long *, hipStream_t);
+                                                 long long *, long long *, hipStream_t);        \
+    template size_t front_lds<T>(const NetDev &, const Buckets &, bool, bool);                  \
+    template hipError_t rag_front<T>(const SlotArgs &, const SlotGammas &, uint32_t, uint32_t,  \
+                                     uint32_t, int, size_t, hipStream_t);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

@@ -69,6 +69,7 @@ _SIGS = {
                             _P, _P, _P, _P, C.c_size_t, C.POINTER(C.c_int32)],
     "hp_slot_alloc": [_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32)],
     "hp_slot_free": [_P, C.c_int32],
+    "hp_netlist_free": [_P, C.c_int32],
     "hp_set_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_get_positions": [_P, C.c_int32, _P, _P, C.c_int],
     "hp_get_eval_positions": [_P, C.c_int32, _P, _P, C.c_int],
@@ -85,6 +86,7 @@ _SIGS = {
     "hp_nesterov_step": [_P, _P, C.c_int32],
     "hp_iterate": [_P, _P, C.c_int32, C.POINTER(hp_iter_params), C.c_int32],
     "hp_graph_stats": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "hp_iterate_multi": [_P, _P, C.c_int32, _P, C.c_int32, C.c_int32],
     "hp_perturb": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P, _P],
     "hp_perturb_among": [_P, C.c_int32, C.c_int, C.c_double, C.c_double, C.c_uint64, _P,
                          C.c_int32, _P, _P],
@@ -195,6 +197,10 @@ def hp_slot_free(ctx, slot):
     _chk(lib().hp_slot_free(ctx, slot))
 
 
+def hp_netlist_free(ctx, netlist):
+    _chk(lib().hp_netlist_free(ctx, netlist))
+
+
 def hp_set_positions(ctx, slot, x, y, on_device):
     _chk(lib().hp_set_positions(ctx, slot, _ptr(x), _ptr(y), int(on_device)))
 
@@ -292,6 +298,12 @@ def hp_iterate(ctx, slots, gamma, iters, flags):
     _chk(lib().hp_iterate(ctx, p, n, C.byref(prm), int(iters)))
 
 
+def hp_iterate_multi(ctx, slots, gammas, iters, flags):
+    a, p, n = _slots(slots)
+    g = np.ascontiguousarray(np.broadcast_to(np.asarray(gammas, dtype=np.float64), (n,)))
+    _chk(lib().hp_iterate_multi(ctx, p, n, g.ctypes.data, int(flags), int(iters)))
+
+
 def hp_graph_stats(ctx):
     """(captured blocks, replayed blocks) of hp_iterate's graph mode on this context."""
     c, r = C.c_int64(), C.c_int64()
@@ -360,22 +372,28 @@ class Placer:
     of that device at construction time."""
 
     def __init__(self, nl, precision=32, device=0, stretch=True, fd5=False,
-                 target_density=1.0, net_weight=None, stream=None):
+                 target_density=1.0, net_weight=None, stream=None, context=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libhybro needs a ROCm GPU; none is visible")
         self.torch = torch
-        self.dev = torch.device("cuda", device)
         self.nl = nl
+        self.context = context
+        if context is not None:  # a netlist of a shared context (its precision, device, stream)
+            precision, self.dev, self.stream = context.precision, context.dev, context.stream
+        else:
+            self.dev = torch.device("cuda", device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
         self.precision = precision
         self.dtype = np.float32 if precision == 32 else np.float64
         self.tdtype = torch.float32 if precision == 32 else torch.float64
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
-        self.ctx = hp_create(device, C.c_void_p(self.stream.cuda_stream), precision)
+        self.ctx = (context.ctx if context is not None else
+                    hp_create(self.dev.index or 0, C.c_void_p(self.stream.cuda_stream), precision))
         try:
             self._load(nl, target_density, stretch, fd5, net_weight)
         except BaseException:
-            hp_destroy(self.ctx)  # a refused netlist leaves no context behind
+            if context is None:
+                hp_destroy(self.ctx)  # a refused netlist leaves no context behind
             self.ctx = None
             raise
 
@@ -526,9 +544,45 @@ class Placer:
         hp_iterate(self.ctx, list(np.atleast_1d(slots)), gamma, iters, flags)
 
     def close(self):
-        """Synchronise and destroy the context, then drop the device buffers."""
+        """Synchronise and destroy the context (on a shared context: free this netlist's slots
+        and the netlist), then drop the device buffers."""
         if self.ctx is not None:
-            hp_destroy(self.ctx)
+            if self.context is None:
+                hp_destroy(self.ctx)
+            else:
+                for s in list(self._slotbufs):
+                    hp_slot_free(self.ctx, s)
+                hp_netlist_free(self.ctx, self.netlist)
             self.ctx = None
         self._slotbufs = {}
         self._netbuf = None
+
+
+class Context:
+    """A library context holding several netlists (one Placer each, made by `placer`), whose
+    slots iterate together in shared launches (`iterate`): the batched iterations of several
+    placement jobs.  Placers of one context share its precision, device and stream."""
+
+    def __init__(self, precision=32, device=0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libhybro needs a ROCm GPU; none is visible")
+        self.precision = precision
+        self.dev = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
+        self.ctx = hp_create(device, C.c_void_p(self.stream.cuda_stream), precision)
+
+    def placer(self, nl, **kw):
+        return Placer(nl, context=self, **kw)
+
+    def iterate(self, slots, gammas, iters, hpwl="last"):
+        """iters placer iterations of every listed slot (slots of any of this context's
+        netlists, each in steady state: one Placer.iterate on it first) with its own gamma,
+        each pass of an iteration one launch over all of them; hpwl as for Placer.iterate."""
+        flags = HP_ITER_HPWL_LAST if hpwl == "last" else HP_ITER_HPWL if hpwl else 0
+        hp_iterate_multi(self.ctx, list(np.atleast_1d(slots)), gammas, iters, flags)
+
+    def close(self):
+        if self.ctx is not None:
+            hp_destroy(self.ctx)
+            self.ctx = None

@@ -34,10 +34,18 @@ _CASES = {
     "mid": lambda: netgen.make_netlist("mid", 0),
     # 2.2 M cells, 10.7 M pins (54 nets over 2048 pins), 1024 x 1024 bins
     "large": lambda: netgen.make_netlist("large", 0),
+    # non-square bin grids: 128 x 32 and 64 x 16 bins (bins four times as tall as wide)
+    "rect": lambda: _rows(netgen.make_small(9_000, 9_400, 128, seed=6, n_fixed=20), 32),
+    "rect_t": lambda: _rows(netgen.make_small(3_000, 3_150, 64, seed=8, n_fixed=10), 16),
     # pin offsets that are not multiples of 2^-16 (the sweeps then load the quantized ones)
     "small_offs": lambda: _offsets_off_grid(netgen.make_small(20_011, 21_003, 128, seed=3,
                                                               n_fixed=40)),
 }
+
+
+def _rows(nl, my):
+    import dataclasses
+    return dataclasses.replace(nl, my=my)
 
 
 def _offsets_off_grid(nl):
@@ -55,7 +63,8 @@ def setup(hy, orc, case, prec):
     return _cache[key]
 
 
-PARAMS = [("tiny", 64), ("tiny", 32), ("small", 32), ("small", 64), ("mid", 32), ("large", 32)]
+PARAMS = [("tiny", 64), ("tiny", 32), ("small", 32), ("small", 64), ("mid", 32), ("large", 32),
+          ("rect", 32), ("rect_t", 64)]
 
 
 @pytest.mark.parametrize("case,prec", PARAMS)
