@@ -71,7 +71,11 @@ typedef struct {
     int32_t n_cells, n_movable, n_nets, n_pins;
 } hp_shape;
 
-/* precision: 32 or 64.  hip_stream: a hipStream_t (NULL = the null stream). */
+/* precision: 32 or 64.  hip_stream: a hipStream_t (NULL = the null stream).  Threads may
+ * share a context: each call holds the context's lock while it runs (a netlist load only
+ * while it registers the netlist; hp_slot_free and hp_netlist_free not while they wait for
+ * the stream), so e.g. one thread can load arriving jobs while another iterates the resident
+ * ones.  hp_destroy must not overlap any other call on the context. */
 int hp_create(hp_ctx **out, int device, void *hip_stream, int precision);
 int hp_destroy(hp_ctx *ctx);
 const char *hp_last_error(void);

@@ -44,6 +44,11 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // f(lo, hi) over [0, n) split into contiguous ranges on up to 16 host threads (a single call
 // for small n); the ranges own disjoint outputs.
+// The context lock of an entry point (see hp_ctx::mu).
+#define HP_GUARD(ctx)                                                          \
+    if (!(ctx)) return fail(HP_EINVAL, "ctx is NULL");                         \
+    std::lock_guard<std::recursive_mutex> hp_guard_((ctx)->mu)
+
 template <typename F>
 void parallel_ranges(int64_t n, F &&f) {
     const int64_t grain = 1 << 16;
@@ -302,6 +307,10 @@ struct hp_ctx {
     std::vector<Slot> slots;
     GraphBlock graph;  // the last captured block of hp_iterate (HP_ITER_GRAPH)
     int64_t graph_captures = 0, graph_replays = 0;
+    // Entry points hold it for their whole call (a netlist load only while it registers the
+    // netlist), so that threads may share a context: e.g. one loads arriving jobs while another
+    // iterates the resident ones.
+    std::recursive_mutex mu;
 };
 
 namespace {
@@ -1297,12 +1306,14 @@ int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die, c
              : load_netlist<double>(ctx, *shape, *die, cell_w, cell_h, fixed_x, fixed_y, net_start,
                                     pin_cell, pin_ox, pin_oy, net_weight, (char *)dev_buf, NL);
     if (rc) return rc;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->nets.push_back(NL);
     *out_netlist = (int32_t)ctx->nets.size() - 1;
     return HP_OK;
 }
 
 int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes, int32_t *out_slot) {
+    HP_GUARD(ctx);
     if (!ctx || !out_slot) return fail(HP_EINVAL, "ctx/out is NULL");
     if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
         return fail(HP_ESTATE, "unknown netlist");
@@ -1333,19 +1344,28 @@ int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
 }
 
 int hp_slot_free(hp_ctx *ctx, int32_t slot) {
+    if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    std::unique_lock<std::recursive_mutex> lk(ctx->mu);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
     if (rc) return rc;
-    HP_CHECK(hipStreamSynchronize(ctx->stream));
-    s->alive = false;
-    s->base = nullptr;
     const auto &gs = ctx->graph.slots;
-    if (std::find(gs.begin(), gs.end(), slot) != gs.end()) drop_graph(ctx->graph);
+    if (std::find(gs.begin(), gs.end(), slot) != gs.end()) {
+        HP_CHECK(hipStreamSynchronize(ctx->stream));  // no replay of its graph pending
+        drop_graph(ctx->graph);
+    }
+    s->alive = false;  // no further work for it can be queued ...
+    s->base = nullptr;
+    lk.unlock();
+    // ... and once the work queued so far has finished, its buffer may be released (the wait
+    // holds no lock, so other threads keep queueing work meanwhile)
+    HP_CHECK(hipStreamSynchronize(ctx->stream));
     return HP_OK;
 }
 
 int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, int on_device) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1419,6 +1439,7 @@ int get_pos(hp_ctx *ctx, int32_t slot, size_t which, void *x, void *y, int on_de
 }  // namespace
 
 int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (slot < 0 || slot >= (int)ctx->slots.size() || !ctx->slots[slot].alive)
         return fail(HP_ESTATE, "unknown slot " + std::to_string(slot));
@@ -1426,6 +1447,7 @@ int hp_get_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device)
 }
 
 int hp_get_eval_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_device) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (slot < 0 || slot >= (int)ctx->slots.size() || !ctx->slots[slot].alive)
         return fail(HP_ESTATE, "unknown slot " + std::to_string(slot));
@@ -1433,6 +1455,7 @@ int hp_get_eval_positions(hp_ctx *ctx, int32_t slot, void *x, void *y, int on_de
 }
 
 int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double decades, int32_t total_iters) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1450,6 +1473,7 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
 }
 
 int hp_set_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t regroup_every, int32_t deferred) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
         return fail(HP_ESTATE, "unknown netlist");
@@ -1462,6 +1486,7 @@ int hp_set_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t regroup_every, i
 }
 
 int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
         return fail(HP_ESTATE, "unknown netlist");
@@ -1488,6 +1513,7 @@ int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
 }
 
 int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value) {
+    HP_GUARD(ctx);
     if (!ctx || !value) return fail(HP_EINVAL, "ctx/out is NULL");
     if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
         return fail(HP_ESTATE, "unknown netlist");
@@ -1501,6 +1527,7 @@ int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value) 
 }
 
 int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, int32_t *deferred) {
+    HP_GUARD(ctx);
     if (!ctx || !regroup_every || !deferred) return fail(HP_EINVAL, "ctx/out is NULL");
     if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
         return fail(HP_ESTATE, "unknown netlist");
@@ -1510,6 +1537,7 @@ int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, 
 }
 
 int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1523,6 +1551,7 @@ int hp_set_lambda_ratio(hp_ctx *ctx, int32_t slot, double ratio) {
 
 int hp_overflow_of_cells(hp_ctx *ctx, int32_t slot, int32_t n_counted, int64_t *out_num,
                          double *out) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1552,6 +1581,7 @@ int hp_overflow_of_cells(hp_ctx *ctx, int32_t slot, int32_t n_counted, int64_t *
 }
 
 int hp_set_backtracking(hp_ctx *ctx, int32_t slot, int32_t on) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1567,12 +1597,14 @@ int hp_set_backtracking(hp_ctx *ctx, int32_t slot, int32_t on) {
 
 int hp_eval_objective_grad(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_eval_params *p,
                            double *wl, double *energy, double *overflow, void *gx, void *gy) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     return ctx->precision == 32 ? eval_impl<float>(ctx, slots, n, p, wl, energy, overflow, gx, gy)
                                 : eval_impl<double>(ctx, slots, n, p, wl, energy, overflow, gx, gy);
 }
 
 int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n) {
+    HP_GUARD(ctx);
     Netlist *NL;
     std::vector<SlotArgs> chunks;
     std::vector<Slot *> ss;
@@ -1582,6 +1614,7 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n) {
 }
 
 int hp_hpwl_noalloc(hp_ctx *ctx, int32_t netlist, const void *xy, int64_t *out_q) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (!xy || !out_q) return fail(HP_EINVAL, "xy and out_q must be device pointers");
     if (((uintptr_t)xy & (2 * rsize(ctx) - 1)) || ((uintptr_t)out_q & 7))
@@ -1605,6 +1638,7 @@ int hp_hpwl_noalloc(hp_ctx *ctx, int32_t netlist, const void *xy, int64_t *out_q
 }
 
 int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double *out) {
+    HP_GUARD(ctx);
     Netlist *NL;
     std::vector<SlotArgs> chunks;
     std::vector<Slot *> ss;
@@ -1630,6 +1664,7 @@ int hp_hpwl(hp_ctx *ctx, const int32_t *slots, int32_t n, int64_t *out_q, double
 
 int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_params *p,
                int32_t iters) {
+    HP_GUARD(ctx);
     Netlist *NL;
     std::vector<SlotArgs> chunks;
     std::vector<Slot *> ss;
@@ -1752,6 +1787,7 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
 }
 
 int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (captures) *captures = ctx->graph_captures;
     if (replays) *replays = ctx->graph_replays;
@@ -1760,6 +1796,7 @@ int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays) {
 
 int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n, const double *gammas,
                      int32_t flags, int32_t iters) {
+    HP_GUARD(ctx);
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
     if (!slots || n <= 0) return fail(HP_EINVAL, "empty slot list");
     if (n > kMaxSlots) return fail(HP_EINVAL, "at most " + std::to_string(kMaxSlots) + " slots per call");
@@ -1792,13 +1829,15 @@ int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n, const double 
 
 int hp_netlist_free(hp_ctx *ctx, int32_t netlist) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
+    std::unique_lock<std::recursive_mutex> lk(ctx->mu);
     if (netlist < 0 || netlist >= (int)ctx->nets.size() || !ctx->nets[netlist].alive)
         return fail(HP_ESTATE, "unknown netlist");
     for (const Slot &s : ctx->slots)
         if (s.alive && s.netlist == netlist)
             return fail(HP_ESTATE, "netlist " + std::to_string(netlist) + " still has live slots");
-    HP_CHECK(hipStreamSynchronize(ctx->stream));
     ctx->nets[netlist] = Netlist{};  // alive = false; host arrays released
+    lk.unlock();
+    HP_CHECK(hipStreamSynchronize(ctx->stream));  // as hp_slot_free
     return HP_OK;
 }
 
@@ -1856,6 +1895,7 @@ static int perturb_impl(hp_ctx *ctx, int32_t slot, int mode, double fraction, do
 
 int hp_perturb_wiremask(hp_ctx *ctx, int32_t slot, const int32_t *macros, int32_t n_macros,
                         int32_t *out_moved) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1894,12 +1934,14 @@ int hp_perturb_wiremask(hp_ctx *ctx, int32_t slot, const int32_t *macros, int32_
 
 int hp_perturb(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins, uint64_t seed,
                int32_t *out_idx, int32_t *out_count) {
+    HP_GUARD(ctx);
     return perturb_impl(ctx, slot, mode, fraction, sigma_bins, seed, nullptr, 0, out_idx, out_count);
 }
 
 int hp_perturb_among(hp_ctx *ctx, int32_t slot, int mode, double fraction, double sigma_bins,
                      uint64_t seed, const int32_t *cells, int32_t n_pool, int32_t *out_idx,
                      int32_t *out_count) {
+    HP_GUARD(ctx);
     if (!cells && n_pool) return fail(HP_EINVAL, "cells is NULL");
     static const int32_t none = 0;
     return perturb_impl(ctx, slot, mode, fraction, sigma_bins, seed, cells ? cells : &none, n_pool,
@@ -1907,6 +1949,7 @@ int hp_perturb_among(hp_ctx *ctx, int32_t slot, int mode, double fraction, doubl
 }
 
 int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbent, int32_t *out_best) {
+    HP_GUARD(ctx);
     Netlist *NL;
     std::vector<SlotArgs> chunks;
     std::vector<Slot *> ss;
@@ -1943,6 +1986,7 @@ int hp_select_best(hp_ctx *ctx, const int32_t *slots, int32_t n, int32_t incumbe
 }
 
 int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);
@@ -1979,6 +2023,7 @@ int hp_get_map(hp_ctx *ctx, int32_t slot, int which, void *dst) {
 }
 
 int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out) {
+    HP_GUARD(ctx);
     Slot *s;
     Netlist *n;
     int rc = get_slot(ctx, slot, &s, &n);

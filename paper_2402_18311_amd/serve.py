@@ -2,15 +2,24 @@
 
 A job is one synthetic netlist placed by the plain method: `iters` iterations (objective and
 gradient of Eq. 2, Nesterov step) from its initial positions; its result is the exact HPWL of
-Eq. 1 after the last one (HPWL_q).  Jobs arrive on a trace.  The server admits them in arrival order as long
-as their device buffers (netlist + one slot) fit in the budget — a job larger than the whole
-budget is admitted alone — keeps their state resident while they run, and runs every admitted
-job on its own HIP stream from its own host thread, so the kernels of concurrent jobs overlap
-on the device (jobs on different netlists cannot share launches; slots of one netlist do).
-A finished job releases its memory and the next arrivals are admitted at once.
+Eq. 1 after the last one (HPWL_q).  Jobs arrive on a trace.  The server admits them in arrival
+order as long as their device buffers (netlist + one slot) fit in the budget — a job larger
+than the whole budget is admitted alone — keeps their state resident while they run, and
+releases a finished job's memory so the next arrivals are admitted at once.  Two executors:
+
+* per-job streams (`run_on_gpu`): every admitted job runs on its own HIP stream from its own
+  host thread (steady-state blocks replayed from a HIP graph), so the kernels of concurrent
+  jobs overlap on the device;
+* shared launches (`SharedLaunchExecutor`): admitted jobs are loaded by their host threads
+  onto a shared library context of their size class and, after their first iteration, join
+  its resident set; the class's device thread advances every resident job by `tick`
+  iterations per round, each pass of an iteration one launch over all of their slots
+  (hp_iterate_multi, up to 32 slots a launch), so small jobs no longer cost a launch sequence
+  each; classes run on their own streams and overlap.
 
 The baseline is the same trace served sequentially: one job at a time, in arrival order.
-Every kernel is deterministic per slot, so each job's HPWL_q is identical alone and in the mix.
+Every kernel is deterministic per slot and the shared launches are bit-identical to a slot's
+own, so each job's HPWL_q is identical alone and in the mix, under either executor.
 
     python -m paper_2402_18311_amd.serve --jobs 200 --budget-gb 8
 
@@ -172,6 +181,146 @@ def run_on_gpu(job: Job) -> None:
         del pl
 
 
+class _LaunchGroup:
+    """One shared context and its device thread: the resident jobs of one size class."""
+
+    def __init__(self, tick: int, precision: int):
+        import torch
+
+        from . import hybro as hy
+        self.tick = tick
+        self.ctx = hy.Context(precision=precision, stream=torch.cuda.Stream())
+        self.cv = threading.Condition()
+        self.resident: list[dict] = []
+        self.rounds = 0
+        self.peak_resident = 0
+        self.stop = False
+        self.paused = False
+        self.thread = threading.Thread(target=self._loop, daemon=True)
+        self.thread.start()
+
+    def _loop(self) -> None:
+        while True:
+            with self.cv:
+                while (self.paused or not self.resident) and not self.stop:
+                    self.cv.wait()
+                if self.stop:
+                    return
+                batch = list(self.resident)
+            self.peak_resident = max(self.peak_resident, len(batch))
+            step = min(self.tick, min(e["left"] for e in batch))
+            try:
+                for c in range(0, len(batch), 32):
+                    part = batch[c:c + 32]
+                    self.ctx.iterate([e["slot"] for e in part], [e["gamma"] for e in part], step,
+                                     hpwl=False)
+                self.rounds += 1
+                done = []
+                for e in batch:
+                    e["left"] -= step
+                    if e["left"] == 0:
+                        e["job"].hpwl_q = int(e["pl"].hpwl(e["slot"])[0])
+                        done.append(e)
+            except BaseException as err:  # every resident job fails with it
+                done = batch
+                for e in batch:
+                    e["error"] = err
+            with self.cv:
+                for e in done:
+                    self.resident.remove(e)
+            for e in done:
+                e["done"].set()
+
+
+class SharedLaunchExecutor:
+    """Jobs on shared contexts, advanced together in shared launches.
+
+    Jobs are split into size classes by movable cells (`bounds`: class k holds jobs below
+    bounds[k], the last class the rest); each class has its own context, stream and device
+    thread, so a small job is not held to the iteration rate of a large one while the classes
+    still overlap on the device.  `run(job)` (called from the scheduler's per-job thread)
+    loads the job onto its class's context, runs its first iteration alone (lambda_0 and the
+    scatter grouping), hands it to the device thread and waits for its result; each device
+    thread advances its resident jobs by min(tick, fewest iterations left) per round and reads
+    a job's HPWL when it is done."""
+
+    def __init__(self, tick: int = 10, precision: int = 32,
+                 bounds: tuple = (40_000, 160_000, 640_000)):
+        self.bounds = tuple(bounds)
+        self.groups = [_LaunchGroup(int(tick), precision) for _ in range(len(self.bounds) + 1)]
+
+    def _group(self, job: Job) -> _LaunchGroup:
+        n = job.netlist.n_movable
+        return self.groups[sum(n >= b for b in self.bounds)]
+
+    @property
+    def rounds(self) -> int:
+        return sum(g.rounds for g in self.groups)
+
+    @property
+    def peak_resident(self) -> int:
+        """The most jobs one round of one class advanced together."""
+        return max(g.peak_resident for g in self.groups)
+
+    def reset_stats(self) -> None:
+        for g in self.groups:
+            g.rounds, g.peak_resident = 0, 0
+
+    def run(self, job: Job) -> None:
+        g = self._group(job)
+        nl = job.netlist
+        pl = g.ctx.placer(nl)
+        try:
+            s = pl.new_slot()
+            pl.set_positions(s, nl.x0, nl.y0)
+            pl.set_schedule(s, 1e-4, 4.0, job.iters)
+            gamma = 4 * nl.bin_w
+            first = min(1, job.iters)
+            pl.iterate(s, gamma, first, hpwl=False)
+            if job.iters == first:
+                job.hpwl_q = int(pl.hpwl(s)[0])
+                return
+            e = {"pl": pl, "slot": s, "gamma": gamma, "left": job.iters - first, "job": job,
+                 "done": threading.Event(), "error": None}
+            with g.cv:
+                g.resident.append(e)
+                g.cv.notify_all()
+            e["done"].wait()
+            if e["error"] is not None:
+                raise e["error"]
+        finally:
+            pl.close()
+
+    def pause(self) -> None:
+        """Hold the device threads after their current rounds (jobs still load and join)."""
+        for g in self.groups:
+            with g.cv:
+                g.paused = True
+
+    def resume(self) -> None:
+        for g in self.groups:
+            with g.cv:
+                g.paused = False
+                g.cv.notify_all()
+
+    def waiting(self) -> int:
+        """Jobs resident (loaded, first iteration done) and not yet finished."""
+        n = 0
+        for g in self.groups:
+            with g.cv:
+                n += len(g.resident)
+        return n
+
+    def close(self) -> None:
+        for g in self.groups:
+            with g.cv:
+                g.stop = True
+                g.cv.notify_all()
+        for g in self.groups:
+            g.thread.join()
+            g.ctx.close()
+
+
 def _make_one(args):
     c, s = args
     return netgen.make_netlist(netgen.scaled_config(int(c)), s)
@@ -205,9 +354,10 @@ def fresh(jobs: list[Job]) -> list[Job]:
 
 
 def measure(n_jobs=200, lo=10_000, hi=2_200_000, iters=500, budget_gb=8.0, rate_frac=0.8,
-            seed=0, log=print, workers=0) -> dict:
+            seed=0, log=print, workers=0, tick=10) -> dict:
     """Config 5: capacity of sequential plain solves (all jobs queued at t = 0), then a Poisson
-    trace at rate_frac x that capacity served sequentially and by the server."""
+    trace at rate_frac x that capacity served sequentially and by the server with each
+    executor."""
     jobs = make_jobs(n_jobs, lo, hi, iters, seed, workers)
     for j in jobs:
         j.nbytes = device_bytes(j.netlist)
@@ -224,14 +374,30 @@ def measure(n_jobs=200, lo=10_000, hi=2_200_000, iters=500, budget_gb=8.0, rate_
     srv = fresh(jobs)
     sch = Scheduler(int(budget_gb * 2**30), run_on_gpu)
     sch.serve(srv)
-    same = all(a.hpwl_q == b.hpwl_q for a, b in zip(sorted(seq, key=lambda j: j.jid),
-                                                    sorted(srv, key=lambda j: j.jid)))
+    log(f"[serve] per-job streams: {stats(srv)}")
+    ex = SharedLaunchExecutor(tick=tick)
+    try:
+        warm = fresh(jobs[:2])  # the shared-launch kernels' code objects load lazily too
+        Scheduler(int(budget_gb * 2**30), ex.run).serve(warm)
+        shr = fresh(jobs)
+        sch2 = Scheduler(int(budget_gb * 2**30), ex.run)
+        ex.reset_stats()
+        sch2.serve(shr)
+    finally:
+        ex.close()
+    log(f"[serve] shared launches: {stats(shr)}")
+    by_id = lambda js: sorted(js, key=lambda j: j.jid)  # noqa: E731
+    same = all(a.hpwl_q == b.hpwl_q == c.hpwl_q
+               for a, b, c in zip(by_id(seq), by_id(srv), by_id(shr)))
     return {"config": {"jobs": n_jobs, "cells": [lo, hi], "iters": iters, "budget_gb": budget_gb,
                        "arrival_rate_jobs_per_s": round(rate, 4), "rate_frac_of_capacity": rate_frac,
-                       "seed": seed},
+                       "seed": seed, "tick_iters": tick},
             "sequential_capacity_jobs_per_s": round(capacity, 4),
-            "sequential": stats(seq), "served": stats(srv),
+            "sequential": stats(seq), "served": stats(srv), "served_shared_launches": stats(shr),
             "peak_resident_gb": round(sch.peak_bytes / 2**30, 3), "peak_concurrent_jobs": sch.peak_jobs,
+            "shared_launches": {"peak_resident_gb": round(sch2.peak_bytes / 2**30, 3),
+                                "peak_concurrent_jobs": sch2.peak_jobs,
+                                "peak_jobs_per_launch": ex.peak_resident, "rounds": ex.rounds},
             "equal_hpwl": same}
 
 
@@ -246,9 +412,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=8,
                     help="processes drawing the synthetic netlists")
+    ap.add_argument("--tick", type=int, default=10,
+                    help="iterations per round of the shared-launch executor")
     a = ap.parse_args()
     print(json.dumps(measure(a.jobs, a.lo, a.hi, a.iters, a.budget_gb, a.rate_frac, a.seed,
-                             workers=a.workers)))
+                             workers=a.workers, tick=a.tick)))
 
 
 if __name__ == "__main__":

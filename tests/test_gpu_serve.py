@@ -22,3 +22,40 @@ def test_served_results_equal_alone():
         assert a.hpwl_q is not None and a.hpwl_q == b.hpwl_q, a.jid
     s = serve.stats(mixed)
     print("served", s, "sequential", serve.stats(alone))
+
+
+def test_shared_launch_executor_equals_alone():
+    """Jobs joining and leaving the shared launches at different rounds (uneven iteration
+    counts, a tick that does not divide them, one-iteration jobs that never join) end with
+    their alone HPWL_q.  The executor is held until 36 jobs are resident, so its rounds also
+    split over two launches of at most 32 slots."""
+    import threading
+    import time
+    jobs = serve.make_jobs(48, 2_000, 30_000, 23, seed=11)
+    for k, j in enumerate(jobs):
+        j.iters = (1, 7, 23, 40)[k % 4]
+        j.nbytes = serve.device_bytes(j.netlist)
+    alone = serve.fresh(jobs)
+    serve.serve_sequential(alone, serve.run_on_gpu)
+    ex = serve.SharedLaunchExecutor(tick=6)
+    try:
+        ex.pause()
+        mixed = serve.fresh(jobs)
+        sch = serve.Scheduler(sum(j.nbytes for j in jobs), ex.run)  # all admitted at once
+        t = threading.Thread(target=sch.serve, args=(mixed,))
+        t.start()
+        t_end = time.time() + 60
+        while ex.waiting() < 36 and time.time() < t_end and t.is_alive():
+            time.sleep(0.01)
+        assert ex.waiting() == 36
+        ex.resume()
+        t.join(timeout=120)
+        assert not t.is_alive()
+    finally:
+        ex.resume()
+        ex.close()
+    assert ex.peak_resident == 36
+    for a, b in zip(alone, mixed):
+        assert a.hpwl_q is not None and a.hpwl_q == b.hpwl_q, a.jid
+    print("shared launches", serve.stats(mixed), "rounds", ex.rounds,
+          "peak per round", ex.peak_resident)
