@@ -237,6 +237,35 @@ __device__ __forceinline__ void load_row4(const vec2<T> *src, vec2<T> (&r)[4]) {
     }
 }
 
+// The same, loading only the first pair (lo) and / or the second pair (hi) of bins.
+template <typename T>
+__device__ __forceinline__ void load_row4_part(const vec2<T> *src, bool lo, bool hi,
+                                               vec2<T> (&r)[4]) {
+    if constexpr (sizeof(T) == 4) {
+        if (lo) {
+            float4 a;
+            __builtin_memcpy(&a, src, 16);
+            r[0] = cmk2<T>(a.x, a.y);
+            r[1] = cmk2<T>(a.z, a.w);
+        }
+        if (hi) {
+            float4 b;
+            __builtin_memcpy(&b, src + 2, 16);
+            r[2] = cmk2<T>(b.x, b.y);
+            r[3] = cmk2<T>(b.z, b.w);
+        }
+    } else {
+        if (lo) {
+            r[0] = src[0];
+            r[1] = src[1];
+        }
+        if (hi) {
+            r[2] = src[2];
+            r[3] = src[3];
+        }
+    }
+}
+
 // Fused cell gradient.  Wirelength part: the sum of the cell's pin gradients (fixed pin
 // order -> deterministic).  Density part: the field force, dN/dx_i = -sum_b q_ib xi_x(b),
 // with q_ib the cell's integer charge in bin b.  Steady state writes g = gWL + lambda gD;
@@ -246,9 +275,11 @@ __device__ __forceinline__ void load_row4(const vec2<T> *src, vec2<T> (&r)[4]) {
 // Cell block cb = xcd_remap(blockIdx.x) of nb blocks (the grid is nb rounded up to a multiple
 // of 8), so that each XCD walks one contiguous eighth of the cells: the pin gradients that
 // neighbouring cells share stay in that XCD's L2.  RAG: the slot's netlist and layout from its
-// descriptor and nb its own block count (the grid: the largest slot's, rounded up).
+// descriptor and nb its own block count (the grid: the largest slot's, rounded up).  Six
+// waves per SIMD (80 registers): the pass waits on gathers, and at five it was 2-3% slower,
+// at eight (spilling) 20% slower.
 template <typename T, bool RAG>
-__global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
+__global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
                                                            double lam_fixed, int use_fixed,
                                                            int grad_mode, int nb_arg) {
     char *base = sa.base[blockIdx.y];
@@ -288,9 +319,14 @@ __global__ __launch_bounds__(kBlock) void cell_grad_kernel(NetDev nda, SlotArgs 
         // (sides >= 8 bins) and covering the footprint; each row is read as wide loads
         const int js = min(j0, nd.mx - JC), ks = min(k0, nd.my - KR);
         vec2<T> f[KR][JC];
-        if (small) {
+        if (small) {  // only the rows and bin pairs of the window that the footprint covers
+            const bool lo = j0 <= js + 1, hi = j1 >= js + 2;
 #pragma unroll
-            for (int kk = 0; kk < KR; ++kk) load_row4<T>(exy + (size_t)(ks + kk) * nd.mx + js, f[kk]);
+            for (int kk = 0; kk < KR; ++kk) {
+                f[kk][0] = f[kk][1] = f[kk][2] = f[kk][3] = cmk2<T>(T(0), T(0));
+                if (ks + kk >= k0 && ks + kk <= k1)
+                    load_row4_part<T>(exy + (size_t)(ks + kk) * nd.mx + js, lo, hi, f[kk]);
+            }
         }
         for (; j + 4 <= e; j += 4) {  // four gathers in flight, summed in pin order
             const int p0 = nd.cell_pins[j], p1 = nd.cell_pins[j + 1];
