@@ -155,9 +155,17 @@ int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, 
  *     after degree bucket; 1: the buckets' blocks interleaved by their progress through the
  *     cell range, so that every bucket gathers the same cells at the same time.  The exact
  *     HPWL is the same; the wirelength total may differ in its last bits.
+ *   HP_TUNE_CHARGE_RECORDS: 1 (default): when the charge scatter's grouping is rebuilt and
+ *     accumulated in the same evaluation, the counting pass also writes each cell's charge
+ *     rectangle and weight, which the accumulation then reads with one gather per cell instead
+ *     of three (it pays while cells are spread with no relation to their ids, e.g. from random
+ *     positions); 0: no records.  Results are bit-identical.
  * Takes effect at the next launch.  HP_EINVAL for an unknown setting or a value out of range
- * (nothing changed), HP_ESTATE for an unknown netlist.  No device work. */
-enum { HP_TUNE_FUSED_STEP_PARTS = 0, HP_TUNE_SPECTRAL_THREADS = 1, HP_TUNE_SWEEP_INTERLEAVE = 2 };
+ * (nothing changed), HP_ESTATE for an unknown netlist.  The spectral width and the sweep
+ * order also rewrite the descriptors of the netlist's slots (a small copy on the context's
+ * stream, waited for); the other settings do no device work. */
+enum { HP_TUNE_FUSED_STEP_PARTS = 0, HP_TUNE_SPECTRAL_THREADS = 1, HP_TUNE_SWEEP_INTERLEAVE = 2,
+       HP_TUNE_CHARGE_RECORDS = 3 };
 int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value);
 int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value);
 

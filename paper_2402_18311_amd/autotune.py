@@ -1,7 +1,8 @@
 """Timing-based choice of the launch settings of a netlist for a batch of slots: the charge
-scatter's grouping policy, then the launch shapes (the net sweep's block order and the
-Poisson solve's block width).  Results never depend on them beyond the documented last-bit
-differences of reduced totals; only speed does.
+scatter's grouping policy, then the launch shapes (the net sweep's block order, the Poisson
+solve's block width, and whether a rebuilt grouping's accumulation reads charge records).
+Results never depend on them beyond the documented last-bit differences of reduced totals;
+only speed does.
 
 The scatter groups cells by bin tile and rebuilds the grouping every few evaluations; how
 often, and whether the rebuilding evaluation accumulates in the old grouping (one launch
@@ -77,8 +78,10 @@ def tune_scatter(pl, slots, gamma, candidates=CANDIDATES, warm=8, iters=24, repe
     return (every, deferred), timings
 
 
-# (sweep interleave, spectral threads per block: 0 = by launch size)
-LAUNCH_CANDIDATES = ((0, 0), (1, 0), (0, 512), (0, 1024), (1, 512), (1, 1024))
+# (sweep interleave, spectral threads per block: 0 = by launch size, charge records)
+LAUNCH_CANDIDATES = tuple((i, t, r) for r in (1, 0) for i in (0, 1) for t in (0, 512, 1024))
+_LAUNCH_TUNABLES = ("HP_TUNE_SWEEP_INTERLEAVE", "HP_TUNE_SPECTRAL_THREADS", "HP_TUNE_CHARGE_RECORDS")
+_LAUNCH_KEYS = ("interleave", "spectral_threads", "charge_records")
 
 
 def tune_launch(pl, slots, gamma, candidates=LAUNCH_CANDIDATES, warm=4, iters=16, repeats=3,
@@ -89,20 +92,23 @@ def tune_launch(pl, slots, gamma, candidates=LAUNCH_CANDIDATES, warm=4, iters=16
     from . import hybro as hy
     slots = [int(s) for s in (slots if isinstance(slots, (list, tuple)) else [slots])]
     key = "launch_" + _key(pl, len(slots))
+    which = [getattr(hy, n) for n in _LAUNCH_TUNABLES]
+
+    def apply(values):
+        for w, v in zip(which, values):
+            pl.set_tunable(w, int(v))
     if cache and os.path.exists(cache):
         rec = json.load(open(cache)).get(key)
-        if rec:
-            pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, rec["interleave"])
-            pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, rec["spectral_threads"])
+        if rec and all(k in rec for k in _LAUNCH_KEYS):
+            apply([rec[k] for k in _LAUNCH_KEYS])
             return rec, rec.get("ms_per_iter", {})
-    saved = (pl.tunable(hy.HP_TUNE_SWEEP_INTERLEAVE), pl.tunable(hy.HP_TUNE_SPECTRAL_THREADS))
+    saved = [pl.tunable(w) for w in which]
     pos = [pl.positions(s) for s in slots]
     scratch = [pl.new_slot() for _ in slots]
     timings = {}
     try:
-        for inter, spec in candidates:
-            pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, inter)
-            pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, spec)
+        for cand in candidates:
+            apply(cand)
             runs = []
             for _ in range(repeats):
                 for sc, (x, y) in zip(scratch, pos):
@@ -113,17 +119,16 @@ def tune_launch(pl, slots, gamma, candidates=LAUNCH_CANDIDATES, warm=4, iters=16
                 pl.iterate(scratch, gamma, iters, hpwl=True)
                 torch.cuda.synchronize()
                 runs.append((time.perf_counter() - t0) * 1e3 / iters)
-            timings[f"{inter},{spec}"] = sorted(runs)[len(runs) // 2]
+            timings[",".join(str(int(v)) for v in cand)] = sorted(runs)[len(runs) // 2]
     finally:
         for sc in scratch:
             pl.free_slot(sc)
-        pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, saved[0])
-        pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, saved[1])
+        apply(saved)
     best = min(timings, key=timings.get)
-    inter, spec = (int(v) for v in best.split(","))
-    pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, inter)
-    pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, spec)
-    rec = {"interleave": inter, "spectral_threads": spec, "ms_per_iter": timings}
+    values = [int(v) for v in best.split(",")]
+    apply(values)
+    rec = dict(zip(_LAUNCH_KEYS, values))
+    rec["ms_per_iter"] = timings
     if cache:
         data = json.load(open(cache)) if os.path.exists(cache) else {}
         data[key] = rec

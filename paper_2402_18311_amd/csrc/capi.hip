@@ -213,6 +213,7 @@ SlotLayout slot_layout(const hp_shape &s, const hp_die &d, size_t rs, int halo =
     put(L.work, perturb_work_bytes((int)Nm, d.mx, d.my));
     put(L.tile, 4 * Nm);
     put(L.sorted, 4 * Nm);
+    put(L.crec, 16 * Nm);
     put(L.scnt, 4 * (size_t)g.sort_blocks * g.ntiles);
     put(L.soff, 4 * (size_t)g.sort_blocks * g.ntiles);
     put(L.tstart, 4 * ((size_t)g.ntiles + 1));
@@ -238,6 +239,8 @@ struct Netlist {
     bool deferred = true;
     // hp_set_tunable: most cell-gradient partials for which the update reduces them itself
     int fused_parts = kFusedStepParts;
+    // hp_set_tunable: a rebuild accumulated in the same evaluation reads charge records
+    bool charge_records = true;
     std::vector<int64_t> charge_prefix;  // [n_mov + 1] integer charge of cells [0, i)
 };
 
@@ -959,13 +962,14 @@ int eval_resolved(hp_ctx *ctx, Netlist *NL, const std::vector<SlotArgs> &chunks,
         // evaluation accumulates in the new order.
         const bool rebuild_now = fresh || (due && !NL->deferred);
         const bool accum_now = !rebuild_now, count_now = fresh || due;
+        const bool records = rebuild_now && NL->charge_records;
         // WA sweep, HPWL sweep and the scatter's accumulation and/or counting in one launch
         HP_CHECK(launch_eval_front<T>(nd, NL->bk, sa, L, 1.0 / p->gamma, hmask, accum_now,
-                                      count_now, wl_on, st));
-        if (rebuild_now) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, true, st));
+                                      count_now, records, wl_on, st));
+        if (rebuild_now) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, true, records, st));
         HP_CHECK(launch_spectral<T>(nd, sa, L, p->keep_maps != 0,
                                     p->keep_maps != 0 || (p->grad_mode & GRAD_EXACT), st));
-        if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, st));
+        if (!rebuild_now && due) HP_CHECK(launch_regroup_tail<T>(nd, sa, L, false, false, st));
         HP_CHECK(launch_big_grad<T>(nd, sa, L, p->grad_mode, st));
         HP_CHECK(launch_cell_grad<T>(nd, sa, L, use_fixed ? p->lambda : 0.0, use_fixed, p->grad_mode,
                                      nwl, NL->e_parts, spectral_overflow_parts(nd), finish, banks,
@@ -1507,6 +1511,10 @@ int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
             if (value != 0 && value != 1) return fail(HP_EINVAL, "sweep interleave must be 0 or 1");
             NL.nd.sweep_interleave = value;
             return rewrite_descs(ctx, netlist);
+        case HP_TUNE_CHARGE_RECORDS:
+            if (value != 0 && value != 1) return fail(HP_EINVAL, "charge records must be 0 or 1");
+            NL.charge_records = value != 0;
+            return HP_OK;
         default:
             return fail(HP_EINVAL, "unknown tunable");
     }
@@ -1522,6 +1530,7 @@ int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value) 
         case HP_TUNE_FUSED_STEP_PARTS: *value = NL.fused_parts; return HP_OK;
         case HP_TUNE_SPECTRAL_THREADS: *value = NL.nd.spec_threads; return HP_OK;
         case HP_TUNE_SWEEP_INTERLEAVE: *value = NL.nd.sweep_interleave; return HP_OK;
+        case HP_TUNE_CHARGE_RECORDS: *value = NL.charge_records ? 1 : 0; return HP_OK;
         default: return fail(HP_EINVAL, "unknown tunable");
     }
 }

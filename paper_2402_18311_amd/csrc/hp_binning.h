@@ -32,34 +32,47 @@ __device__ __forceinline__ int overlap_b(int lo, int hi, int idx, int w) {
 }
 
 // tile of cell i: the tile of its charge rectangle's lower-left bin (clamped into the die, so
-// that a cell whose rectangle is clipped away still has a place in the order)
+// that a cell whose rectangle is clipped away still has a place in the order).  Also the
+// cell's charge record for an accumulation in the same evaluation: (l, b, w | h << 16, rq)
+// of its clipped rectangle, or w | h << 16 = -1 for a big cell or sides that do not pack
+// (the accumulation then gathers the cell's data itself).
 template <typename T>
-__device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i) {
+__device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i, int4 &rec) {
     const vec2<T> p = pos[i];
-    const RectQ q = cell_rect_b<T>(nd, p.x, p.y, nd.cq[i]);
+    const int4 cc = nd.cq[i];
+    const RectQ q = cell_rect_b<T>(nd, p.x, p.y, cc);
     const int j = min(q.l / nd.bq, nd.mx - 1), k = min(q.b / nd.hq, nd.my - 1);
+    const int w = max(q.r - q.l, 0), h = max(q.t - q.b, 0);
+    rec = make_int4(q.l, q.b, (!is_big(nd, cc) && w < 65536 && h < 32768) ? (w | (h << 16)) : -1,
+                    nd.rq[i]);
     return (k >> nd.log_ts) * nd.ntx + (j >> nd.log_ts);
 }
 
-// Counting pass of the grouping for block `blk` of the cells (dynamic LDS: int [ntiles]).
+// Counting pass of the grouping for block `blk` of the cells (dynamic LDS: int [ntiles]);
+// `records`: also the cells' charge records, for an accumulation in the new order in the same
+// evaluation.
 template <typename T>
-__device__ __forceinline__ void count_body(const NetDev &nd, char *base, const SlotLayout &L, int blk) {
+__device__ __forceinline__ void count_body(const NetDev &nd, char *base, const SlotLayout &L, int blk,
+                                           bool records) {
     extern __shared__ int hist[];  // [ntiles]
     if (blk >= nd.sort_blocks) return;  // block-uniform (the launch may round the grid up)
     const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
     int *tile = reinterpret_cast<int *>(base + L.tile);
+    int4 *crec = reinterpret_cast<int4 *>(base + L.crec);
     for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) hist[t] = 0;
     __syncthreads();
     const int i0 = blk * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
     // four cells per thread and round, their loads (clamped in range) all in flight first
     for (int i = i0 + threadIdx.x; i < i1; i += 4 * kBlock) {
         int t[4];
+        int4 rec[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = cell_tile<T>(nd, pos, min(i + u * kBlock, i1 - 1));
+        for (int u = 0; u < 4; ++u) t[u] = cell_tile<T>(nd, pos, min(i + u * kBlock, i1 - 1), rec[u]);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (i + u * kBlock >= i1) break;
             tile[i + u * kBlock] = t[u];
+            if (records) crec[i + u * kBlock] = rec[u];
             atomicAdd(&hist[t[u]], 1);
         }
     }
@@ -70,8 +83,10 @@ __device__ __forceinline__ void count_body(const NetDev &nd, char *base, const S
 
 // Accumulation of chunk c of the grouped order into its LDS window (dynamic LDS: uint64
 // [win_side^2]), added into its tile's window; cells outside the window add to rho with global
-// atomics.
-template <typename T>
+// atomics.  REC: the order was counted in this evaluation, so each cell's charge record from
+// the counting pass is current and one gather replaces those of its position, rectangle
+// constants and charge.
+template <typename T, bool REC>
 __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const SlotLayout &L, int c) {
     extern __shared__ unsigned long long win[];  // [win_side^2]
     const int *cstart = reinterpret_cast<const int *>(base + L.cstart);
@@ -85,14 +100,26 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
     const vec2<T> *pos = reinterpret_cast<const vec2<T> *>(base + L.v);
     const int *sorted = reinterpret_cast<const int *>(base + L.sorted);
     unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
+    const int4 *crec = reinterpret_cast<const int4 *>(base + L.crec);
     for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
         const int i = sorted[s];
-        const vec2<T> p = pos[i];
-        const int4 cc = nd.cq[i];
-        if (is_big(nd, cc)) continue;  // scattered by a block of its own
-        const RectQ q = cell_rect_b<T>(nd, p.x, p.y, cc);
+        RectQ q;
+        long long rq;
+        const int4 rec = REC ? crec[i] : make_int4(0, 0, -1, 0);
+        if (rec.z >= 0) {
+            q.l = rec.x;
+            q.b = rec.y;
+            q.r = rec.x + (rec.z & 0xffff);
+            q.t = rec.y + (rec.z >> 16);
+            rq = rec.w;
+        } else {
+            const vec2<T> p = pos[i];
+            const int4 cc = nd.cq[i];
+            if (is_big(nd, cc)) continue;  // scattered by a block of its own
+            q = cell_rect_b<T>(nd, p.x, p.y, cc);
+            rq = nd.rq[i];
+        }
         if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
-        const long long rq = nd.rq[i];
         const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
         const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
         const bool inside = j0 >= j00 && j1 < j00 + ws && k0 >= k00 && k1 < k00 + ws;

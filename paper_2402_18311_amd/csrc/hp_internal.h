@@ -112,6 +112,7 @@ struct SlotLayout {
     size_t part;          // double partial sums, kPartStride per reduction
     size_t keys, sel, work; // perturbation scratch
     size_t tile, sorted;  // int32 [n_mov]: each cell's tile, cells in tile order
+    size_t crec;          // int4 [n_mov]: each cell's charge record from the counting pass
     size_t scnt, soff;    // int32 [sort_blocks][ntiles] histograms; their column offsets
     size_t tstart, cstart;// int32 [ntiles + 1]: tile cell ranges, tile chunk ranges
     size_t chunk;         // int4 [max_chunks]: each chunk's (tile, first, end) in the order
@@ -230,10 +231,12 @@ void prof_push(const char *name, hipEvent_t a, hipEvent_t b);
 // First launch of an evaluation (WA sweep of v, charge accumulation or the counting pass of a
 // regroup, and the HPWL sweep of u for the slots in hpwl_mask, bit i = slot i of the launch).
 // sweep = false leaves the net sweep out (a density-only evaluation; hpwl_mask must be 0).
+// records: the counting pass also writes the cells' charge records (the new order accumulates
+// in the same evaluation).
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
-                             bool accum, bool count, bool sweep, hipStream_t st);
+                             bool accum, bool count, bool records, bool sweep, hipStream_t st);
 template <typename T>
 hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, hipStream_t st);
@@ -242,10 +245,11 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
 template <typename T>
 hipError_t launch_hpwl_positions(const NetDev &nd, const Buckets &bk, const void *pos,
                                  long long *part, long long *out, hipStream_t st);
-// Scan, place and accumulate of a regroup whose counting pass the first launch ran.
+// Scan, place and accumulate of a regroup whose counting pass the first launch ran; records:
+// that pass wrote the cells' charge records for the accumulation to read.
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                               bool accum, hipStream_t st);
+                               bool accum, bool records, hipStream_t st);
 size_t scatter_count_lds(const NetDev &nd);
 size_t scatter_accum_lds(const NetDev &nd);
 // Big cells (one block per cell and slot; their charge is scattered in the first launch):

@@ -165,11 +165,13 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs 
     }
 }
 
-template <typename T, bool RAG>
+// The accumulation right after its order was counted and placed; REC: the counting pass of
+// this evaluation wrote the charge records.
+template <typename T, bool RAG, bool REC>
 __global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
     char *base = sa.base[blockIdx.y];
     // accum_body returns for chunks past the slot's own
-    accum_body<T>(view_nd<RAG>(nda, base), base, view_L<RAG>(La, base), blockIdx.x);
+    accum_body<T, REC>(view_nd<RAG>(nda, base), base, view_L<RAG>(La, base), blockIdx.x);
 }
 
 size_t scatter_count_lds(const NetDev &nd) { return sizeof(int) * (size_t)nd.ntiles; }
@@ -181,7 +183,7 @@ size_t scatter_accum_lds(const NetDev &nd) {
 // scan, place, then (accum) the accumulation of the fresh order.
 template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
-                               bool accum, hipStream_t st) {
+                               bool accum, bool records, hipStream_t st) {
     HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel<false>, dim3((nd.ntiles + kColTiles - 1) / kColTiles, sa.n),
               dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
@@ -194,8 +196,12 @@ hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotL
               scatter_count_lds(nd), st, nd, sa, L);
     e = hipGetLastError();
     if (e != hipSuccess || !accum) return e;
-    HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, false>), dim3(nd.max_chunks, sa.n), dim3(kBlock),
-              scatter_accum_lds(nd), st, nd, sa, L);
+    if (records)
+        HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, false, true>), dim3(nd.max_chunks, sa.n),
+                  dim3(kBlock), scatter_accum_lds(nd), st, nd, sa, L);
+    else
+        HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, false, false>), dim3(nd.max_chunks, sa.n),
+                  dim3(kBlock), scatter_accum_lds(nd), st, nd, sa, L);
     return hipGetLastError();
 }
 
@@ -218,8 +224,9 @@ hipError_t rag_regroup_tail(const SlotArgs &sa, int colscan_x, int place_x, int 
               place_lds, st, nd0, sa, L0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, true>), dim3(accum_x, sa.n), dim3(kBlock),
-              accum_lds, st, nd0, sa, L0);
+    // the first launch wrote every rebuilding slot's charge records
+    HP_LAUNCH("bin_accum_kernel", (bin_accum_kernel<T, true, true>), dim3(accum_x, sa.n),
+              dim3(kBlock), accum_lds, st, nd0, sa, L0);
     return hipGetLastError();
 }
 int colscan_blocks(const NetDev &nd) { return (nd.ntiles + kColTiles - 1) / kColTiles; }
@@ -229,8 +236,8 @@ template hipError_t rag_regroup_tail<float>(const SlotArgs &, int, int, int, siz
 template hipError_t rag_regroup_tail<double>(const SlotArgs &, int, int, int, size_t, size_t,
                                              hipStream_t);
 template hipError_t launch_regroup_tail<float>(const NetDev &, const SlotArgs &, const SlotLayout &,
-                                               bool, hipStream_t);
+                                               bool, bool, hipStream_t);
 template hipError_t launch_regroup_tail<double>(const NetDev &, const SlotArgs &,
-                                                const SlotLayout &, bool, hipStream_t);
+                                                const SlotLayout &, bool, bool, hipStream_t);
 
 }  // namespace hp

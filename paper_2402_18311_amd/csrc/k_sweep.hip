@@ -600,7 +600,8 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
 //   [0, nacc)                 the accumulation of v's charge in the existing grouped order
 //                             (nacc = 0 when the slot has no grouping yet);
 //   [nacc, nacc + ncnt)       the counting pass of a new grouping from v (ncnt = 0 between
-//                             rebuilds);
+//                             rebuilds), with the cells' charge records when `records` (the
+//                             new order accumulates in this evaluation);
 //   [.., .. + nbig)           the charge of the big cells (macros), one block per cell (nbig =
 //                             0 without any);
 //   [.., .. + nw)             the WA sweep of v (nw = the sweep's block count; its
@@ -611,14 +612,15 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
 template <typename T>
 __global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
                                                             SlotLayout L, T invg, int nacc,
-                                                            int ncnt, int nbig, uint32_t hmask) {
+                                                            int ncnt, int nbig, uint32_t hmask,
+                                                            int records) {
     char *base = sa.base[blockIdx.y];
     const int bx = blockIdx.x;
     const int s0 = nacc + ncnt + nbig;
     if (bx < nacc) {
-        accum_body<T>(nd, base, L, bx);
+        accum_body<T, false>(nd, base, L, bx);
     } else if (bx < nacc + ncnt) {
-        count_body<T>(nd, base, L, bx - nacc);
+        count_body<T>(nd, base, L, bx - nacc, records != 0);
     } else if (bx < s0) {
         big_scatter_body<T>(nd, base, L, bx - nacc - ncnt);
     } else if ((hmask >> blockIdx.y) & 1u) {
@@ -648,9 +650,9 @@ __global__ __launch_bounds__(kBlock, 8) void rag_front_kernel(SlotArgs sa, SlotG
     if (bx >= s0 + bk.total_blocks) return;  // whole block
     const T invg = (T)g.inv[blockIdx.y];
     if (bx < nacc) {
-        accum_body<T>(nd, base, L, bx);
+        accum_body<T, false>(nd, base, L, bx);
     } else if (bx < nacc + ncnt) {
-        count_body<T>(nd, base, L, bx - nacc);
+        count_body<T>(nd, base, L, bx - nacc, true);  // the new order accumulates right after
     } else if (bx < s0) {
         big_scatter_body<T>(nd, base, L, bx - nacc - ncnt);
     } else if ((hmask >> blockIdx.y) & 1u) {
@@ -718,7 +720,7 @@ hipError_t launch_hpwl_positions(const NetDev &nd, const Buckets &bk, const void
 template <typename T>
 hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs &sa,
                              const SlotLayout &L, double inv_gamma, uint32_t hpwl_mask,
-                             bool accum, bool count, bool sweep, hipStream_t st) {
+                             bool accum, bool count, bool records, bool sweep, hipStream_t st) {
     const int nacc = accum ? (nd.max_chunks + kXcds - 1) / kXcds * kXcds : 0;
     const int ncnt = count ? (nd.sort_blocks + kXcds - 1) / kXcds * kXcds : 0;
     const int nbig = (nd.n_big + kXcds - 1) / kXcds * kXcds;
@@ -729,7 +731,7 @@ hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs
     dim3 grid(nacc + ncnt + nbig + (sweep ? bk.total_blocks : 0), sa.n);
     if (grid.x == 0) return hipSuccess;
     HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
-              L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask);
+              L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask, (int)records);
     return hipGetLastError();
 }
 
@@ -744,7 +746,7 @@ hipError_t launch_sweep_hpwl(const NetDev &nd, const Buckets &bk, const SlotArgs
 #define HP_INST(T)                                                                             \
     template hipError_t launch_eval_front<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, double, uint32_t, bool, bool,  \
-                                             bool, hipStream_t);                                \
+                                             bool, bool, hipStream_t);                          \
     template hipError_t launch_sweep_hpwl<T>(const NetDev &, const Buckets &, const SlotArgs &, \
                                              const SlotLayout &, hipStream_t);                  \
     template hipError_t launch_hpwl_positions<T>(const NetDev &, const Buckets &, const void *, \

@@ -263,6 +263,30 @@ def test_autotuner_picks_a_candidate_and_caches(hy, orc, tmp_path):
         pl.free_slot(s)
 
 
+def test_launch_shape_tuner_picks_a_candidate_and_caches(hy, orc, tmp_path):
+    from paper_2402_18311_amd import autotune
+    nl, pl, o = setup(hy, orc, "small", 32)
+    gamma = 4 * nl.bin_w
+    s = pl.new_slot()
+    pl.set_positions(s, nl.x0, nl.y0)
+    names = (hy.HP_TUNE_SWEEP_INTERLEAVE, hy.HP_TUNE_SPECTRAL_THREADS, hy.HP_TUNE_CHARGE_RECORDS)
+    saved = [pl.tunable(w) for w in names]
+    cache = str(tmp_path / "tune.json")
+    try:
+        rec, t = autotune.tune_launch(pl, [s], gamma, warm=2, iters=4, repeats=1, cache=cache)
+        got = tuple(rec[k] for k in ("interleave", "spectral_threads", "charge_records"))
+        assert got in autotune.LAUNCH_CANDIDATES and len(t) == len(autotune.LAUNCH_CANDIDATES)
+        assert tuple(pl.tunable(w) for w in names) == got
+        for w, v in zip(names, saved):
+            pl.set_tunable(w, v)
+        rec2, _ = autotune.tune_launch(pl, [s], gamma, cache=cache)  # from the cache
+        assert tuple(pl.tunable(w) for w in names) == got and rec2["charge_records"] == got[2]
+    finally:
+        for w, v in zip(names, saved):
+            pl.set_tunable(w, v)
+        pl.free_slot(s)
+
+
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("tiny", 32), ("small", 32)])
 def test_lambda_init_and_nesterov_steps(hy, orc, case, prec):
     """First evaluation derives lambda_0; three [eval, step] iterations follow the oracle."""

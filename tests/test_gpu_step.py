@@ -131,11 +131,13 @@ def test_tunables_reject_bad_values(hy, orc):
     nl, pl, o = setup(hy, orc, "tiny", 64)
     L = hy.lib()
     for which, value in ((hy.HP_TUNE_FUSED_STEP_PARTS, -1), (hy.HP_TUNE_FUSED_STEP_PARTS, 1025),
-                         (hy.HP_TUNE_SPECTRAL_THREADS, 256), (7, 0)):
+                         (hy.HP_TUNE_SPECTRAL_THREADS, 256), (hy.HP_TUNE_CHARGE_RECORDS, 2),
+                         (7, 0)):
         assert L.hp_set_tunable(pl.ctx, pl.netlist, which, value) == hy.HP_EINVAL
     assert L.hp_set_tunable(pl.ctx, 99, hy.HP_TUNE_SPECTRAL_THREADS, 0) == hy.HP_ESTATE
     assert pl.tunable(hy.HP_TUNE_FUSED_STEP_PARTS) == 1024
     assert pl.tunable(hy.HP_TUNE_SPECTRAL_THREADS) == 0
+    assert pl.tunable(hy.HP_TUNE_CHARGE_RECORDS) == 1
 
 
 @pytest.mark.parametrize("threads", [512, 1024])
@@ -213,3 +215,39 @@ def test_interleaved_sweep_order_is_bit_identical(hy, orc, case, prec):
 
 def torch_equal(a, b):
     return bool((a.cpu() == b.cpu()).all())
+
+
+@pytest.mark.parametrize("case,prec", [("small", 32), ("tiny", 64)])
+def test_charge_records_are_bit_identical(hy, orc, case, prec):
+    """A rebuilt grouping's accumulation reading the counting pass's charge records, or
+    gathering each cell's data itself, sums the same integers: the same maps, steps and exact
+    HPWL, bit for bit (the grouping rebuilt at every evaluation, so every accumulation takes
+    the path under test)."""
+    nl, pl, o = setup(hy, orc, case, prec)
+    gamma = 4 * nl.bin_w
+    saved = pl.scatter_policy()
+    pl.set_scatter_policy(1, False)
+    a, b = pl.new_slot(), pl.new_slot()
+    for s in (a, b):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+    try:
+        for chunk in (1, 5, 9):
+            pl.set_tunable(hy.HP_TUNE_CHARGE_RECORDS, 1)
+            pl.eval(a, gamma, lam=0.5, keep_maps=True)
+            ra = pl.map(a, hy.HP_MAP_RHO_MOV)
+            pl.iterate(a, gamma, chunk, hpwl=True)
+            pl.set_tunable(hy.HP_TUNE_CHARGE_RECORDS, 0)
+            pl.eval(b, gamma, lam=0.5, keep_maps=True)
+            rb = pl.map(b, hy.HP_MAP_RHO_MOV)
+            pl.iterate(b, gamma, chunk, hpwl=True)
+            assert np.array_equal(ra, rb)
+            assert pl.hpwl(a)[0] == pl.hpwl(b)[0]
+            xa, ya = pl.positions(a)
+            xb, yb = pl.positions(b)
+            assert np.array_equal(xa, xb) and np.array_equal(ya, yb), chunk
+    finally:
+        pl.set_tunable(hy.HP_TUNE_CHARGE_RECORDS, 1)
+        pl.set_scatter_policy(*saved)
+        pl.free_slot(a)
+        pl.free_slot(b)
