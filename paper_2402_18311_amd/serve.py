@@ -184,12 +184,9 @@ def run_on_gpu(job: Job) -> None:
 class _LaunchGroup:
     """One shared context and its device thread: the resident jobs of one size class."""
 
-    def __init__(self, tick: int, precision: int):
-        import torch
-
-        from . import hybro as hy
+    def __init__(self, tick: int, make_context):
         self.tick = tick
-        self.ctx = hy.Context(precision=precision, stream=torch.cuda.Stream())
+        self.ctx = make_context()
         self.cv = threading.Condition()
         self.resident: list[dict] = []
         self.rounds = 0
@@ -245,9 +242,17 @@ class SharedLaunchExecutor:
     a job's HPWL when it is done."""
 
     def __init__(self, tick: int = 10, precision: int = 32,
-                 bounds: tuple = (40_000, 160_000, 640_000)):
+                 bounds: tuple = (40_000, 160_000, 640_000), make_context=None):
+        """make_context: () -> a context (hybro.Context: placer, iterate, close); by default
+        one of the given precision on a stream of its own."""
+        if make_context is None:
+            def make_context():
+                import torch
+
+                from . import hybro as hy
+                return hy.Context(precision=precision, stream=torch.cuda.Stream())
         self.bounds = tuple(bounds)
-        self.groups = [_LaunchGroup(int(tick), precision) for _ in range(len(self.bounds) + 1)]
+        self.groups = [_LaunchGroup(int(tick), make_context) for _ in range(len(self.bounds) + 1)]
 
     def _group(self, job: Job) -> _LaunchGroup:
         n = job.netlist.n_movable

@@ -81,3 +81,105 @@ def test_job_netlists_do_not_depend_on_worker_count():
         assert ja.netlist.n_movable == jb.netlist.n_movable
         assert np.array_equal(ja.netlist.pin_cell, jb.netlist.pin_cell)
         assert np.array_equal(ja.netlist.x0, jb.netlist.x0)
+
+
+class _FakePlacer:
+    """Stands in for a Placer on a shared context: counts each slot's iterations; its "HPWL"
+    is that count."""
+
+    def __init__(self, ctx, nl):
+        self.ctx, self.nl = ctx, nl
+        ctx.placers.append(self)
+
+    def new_slot(self):
+        s = self.ctx.next_slot
+        self.ctx.next_slot += 1
+        self.ctx.done[s] = 0
+        return s
+
+    def set_positions(self, s, x, y):
+        pass
+
+    def set_schedule(self, s, *a):
+        pass
+
+    def iterate(self, s, gamma, iters, hpwl=True):
+        with self.ctx.lock:
+            self.ctx.done[s] += iters
+
+    def hpwl(self, s):
+        return [self.ctx.done[s]]
+
+    def close(self):
+        self.ctx.closed += 1
+
+
+class _FakeContext:
+    def __init__(self, fail_after=None):
+        self.lock = threading.Lock()
+        self.done, self.placers, self.calls = {}, [], []
+        self.next_slot, self.closed, self.fail_after = 0, 0, fail_after
+
+    def placer(self, nl):
+        return _FakePlacer(self, nl)
+
+    def iterate(self, slots, gammas, iters, hpwl="last"):
+        assert len(slots) == len(gammas) and 1 <= len(slots) <= 32 and iters >= 1
+        with self.lock:
+            self.calls.append((len(slots), iters))
+            if self.fail_after is not None and len(self.calls) > self.fail_after:
+                raise RuntimeError("device error")
+            for s in slots:
+                self.done[s] += iters
+
+    def close(self):
+        pass
+
+
+class _Net:
+    def __init__(self, n):
+        self.n_movable, self.bin_w = n, 1.0
+        self.x0 = self.y0 = None
+
+
+def test_shared_launch_rounds_give_every_job_its_iterations():
+    """Jobs of every size class join and leave the rounds at their own counts: each ends
+    with exactly its iteration count, the rounds never pass a job's count, launches take at
+    most 32 slots, and every placer is closed."""
+    ctxs = []
+
+    def make():
+        ctxs.append(_FakeContext())
+        return ctxs[-1]
+    ex = serve.SharedLaunchExecutor(tick=7, bounds=(100, 1000), make_context=make)
+    rng = np.random.default_rng(4)
+    jobs = [serve.Job(i, _Net(int(n)), int(it), 0.0, nbytes=1)
+            for i, (n, it) in enumerate(zip(rng.integers(10, 5000, 80), rng.integers(1, 40, 80)))]
+    try:
+        ex.pause()  # let most jobs become resident before the first round
+        t = threading.Thread(target=serve.Scheduler(1 << 30, ex.run).serve, args=(jobs,))
+        t.start()
+        deadline = time.time() + 30
+        while ex.waiting() < sum(j.iters > 1 for j in jobs) and time.time() < deadline:
+            time.sleep(0.01)
+        ex.resume()
+        t.join(timeout=30)
+        assert not t.is_alive()
+    finally:
+        ex.resume()
+        ex.close()
+    assert all(j.hpwl_q == j.iters for j in jobs)
+    assert len(ctxs) == 3 and ex.peak_resident > 32
+    for c in ctxs:
+        assert c.closed == len(c.placers)
+        assert all(n <= 32 and it <= 7 for n, it in c.calls)
+
+
+def test_shared_launch_errors_reach_every_resident_job():
+    ex = serve.SharedLaunchExecutor(tick=5, bounds=(), make_context=lambda: _FakeContext(0))
+    jobs = [serve.Job(i, _Net(50), 20, 0.0, nbytes=1) for i in range(4)]
+    try:
+        with pytest.raises(RuntimeError, match="device error"):
+            serve.Scheduler(1 << 30, ex.run).serve(jobs)
+    finally:
+        ex.close()
