@@ -344,7 +344,8 @@ int hp_get_state(hp_ctx *ctx, int32_t slot, hp_slot_state *out);
  * cost per bracketed launch).  hp_profile_read synchronises, adds the elapsed times of all
  * bracketed launches since the last read to per-kernel totals, copies up to `max` totals to
  * `out` (host), sets *n_out to the number of kernels seen, and clears the totals if `reset`.
- * The profiler state is process-wide. */
+ * The profiler state is process-wide (guarded: threads may launch while it is on, and their
+ * launches are all timed together; launches are not captured into graphs while it is on). */
 typedef struct {
     char name[48];
     int64_t count;

@@ -1035,10 +1035,12 @@ void init_scalars(Scalars &s, double scale, double decades, int iters) {
 
 }  // namespace
 
-// ---- per-kernel timing (process-wide; used from one thread) --------------------------------
+// ---- per-kernel timing (process-wide; the on flag is read lock-free at every launch, the rest
+// is guarded so that threads sharing or not sharing a context may launch while it is on) ------
 namespace hp {
 namespace {
-bool g_prof_on = false;
+std::atomic<bool> g_prof_on{false};
+std::mutex g_prof_mu;      // guards everything below
 std::string g_prof_only;  // empty: every kernel
 std::vector<ProfRec> g_prof_pending;
 std::vector<hipEvent_t> g_prof_pool;
@@ -1050,19 +1052,27 @@ struct ProfAcc {
 std::vector<ProfAcc> g_prof_acc;
 }  // namespace
 bool prof_want(const char *name) {
-    return g_prof_on && (g_prof_only.empty() || g_prof_only == name);
+    if (!g_prof_on.load(std::memory_order_relaxed)) return false;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_only.empty() || g_prof_only == name;
 }
 hipEvent_t prof_event() {
-    if (!g_prof_pool.empty()) {
-        hipEvent_t e = g_prof_pool.back();
-        g_prof_pool.pop_back();
-        return e;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_pool.empty()) {
+            hipEvent_t e = g_prof_pool.back();
+            g_prof_pool.pop_back();
+            return e;
+        }
     }
     hipEvent_t e = nullptr;
     (void)hipEventCreate(&e);
     return e;
 }
-void prof_push(const char *name, hipEvent_t a, hipEvent_t b) { g_prof_pending.push_back({name, a, b}); }
+void prof_push(const char *name, hipEvent_t a, hipEvent_t b) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back({name, a, b});
+}
 }  // namespace hp
 
 namespace {
@@ -1196,8 +1206,9 @@ extern "C" {
 
 int hp_profile_enable(hp_ctx *ctx, int on, const char *only_kernel) {
     if (!ctx) return fail(HP_EINVAL, "ctx is NULL");
-    hp::g_prof_on = on != 0;
+    std::lock_guard<std::mutex> lk(hp::g_prof_mu);
     hp::g_prof_only = only_kernel ? only_kernel : "";
+    hp::g_prof_on.store(on != 0);
     return HP_OK;
 }
 
@@ -1205,6 +1216,7 @@ int hp_profile_read(hp_ctx *ctx, hp_kernel_time *out, int32_t max, int32_t *n_ou
     if (!ctx || !n_out) return fail(HP_EINVAL, "ctx/n_out is NULL");
     HP_CHECK(hipStreamSynchronize(ctx->stream));
     HP_CHECK(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(hp::g_prof_mu);
     for (const ProfRec &r : hp::g_prof_pending) {
         float ms = 0.f;
         HP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
