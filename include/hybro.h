@@ -231,8 +231,10 @@ int hp_nesterov_step(hp_ctx *ctx, const int32_t *slots, int32_t n_slots);
  * iterations from a captured HIP graph: a block is captured once the slots are in steady
  * state and is replayed whenever the slots' state is the one it was captured from, which
  * every block returns to; leftover iterations run as usual, and results are bit-identical to
- * eager iterations.  The graph is kept with the context until another block replaces it, a
- * slot of it is freed or the context is destroyed.  It needs a context stream other than the
+ * eager iterations.  No block is captured while another thread uses the context's stream
+ * outside the context's lock (a netlist load, or a call waiting for the stream): those
+ * iterations run eagerly.  The graph is kept with the context until another block replaces
+ * it, a slot of it is freed or the context is destroyed.  It needs a context stream other than the
  * null stream (HP_EINVAL); while per-kernel timing is enabled nothing is captured.  Unknown
  * flags or iters < 0: HP_EINVAL. */
 enum { HP_ITER_HPWL = 1, HP_ITER_GRAPH = 2, HP_ITER_HPWL_LAST = 4 };

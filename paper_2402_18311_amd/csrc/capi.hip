@@ -4,6 +4,7 @@
 // it lives in buffers the caller lends.
 #include <algorithm>
 #include <atomic>
+#include <deque>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -47,7 +48,21 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // The context lock of an entry point (see hp_ctx::mu).
 #define HP_GUARD(ctx)                                                          \
     if (!(ctx)) return fail(HP_EINVAL, "ctx is NULL");                         \
-    std::lock_guard<std::recursive_mutex> hp_guard_((ctx)->mu)
+    std::unique_lock<std::recursive_mutex> hp_guard_((ctx)->mu)
+// Wait for the context's stream without holding its lock (other threads keep queueing work
+// meanwhile); the caller's slot and netlist stay in place, as slots and netlists are only
+// appended or marked dead.
+#define HP_SYNC_UNLOCKED(ctx)                                                  \
+    do {                                                                       \
+        ++(ctx)->stream_users;                                                 \
+        hp_guard_.unlock();                                                    \
+        const hipError_t e_ = hipStreamSynchronize((ctx)->stream);             \
+        --(ctx)->stream_users;                                                 \
+        hp_guard_.lock();                                                      \
+        if (e_ != hipSuccess)                                                  \
+            return fail(HP_EDEVICE, std::string("hipStreamSynchronize: ") +    \
+                                        hipGetErrorString(e_));                \
+    } while (0)
 
 template <typename F>
 void parallel_ranges(int64_t n, F &&f) {
@@ -306,14 +321,20 @@ struct hp_ctx {
     int precision = 32;
     int lds_budget = 65536;
     int n_cu = 256;  // compute units of the device
-    std::vector<Netlist> nets;
-    std::vector<Slot> slots;
+    // deques: references to an element stay valid while other threads append (a call may
+    // release the lock while it waits for the stream, see HP_SYNC_UNLOCKED)
+    std::deque<Netlist> nets;
+    std::deque<Slot> slots;
     GraphBlock graph;  // the last captured block of hp_iterate (HP_ITER_GRAPH)
     int64_t graph_captures = 0, graph_replays = 0;
     // Entry points hold it for their whole call (a netlist load only while it registers the
     // netlist), so that threads may share a context: e.g. one loads arriving jobs while another
     // iterates the resident ones.
     std::recursive_mutex mu;
+    // Threads using the stream without holding mu (a netlist load's uploads, a wait for the
+    // stream), counted up while holding mu: no graph capture starts while it is non-zero, as
+    // the stream must not be used by another thread while it is being captured.
+    std::atomic<int> stream_users{0};
 };
 
 namespace {
@@ -1123,8 +1144,9 @@ namespace {
 // Iterations over slots of different netlists in shared launches: every launch of an
 // iteration covers all slots (blockIdx.y), each block finding its slot's netlist, layout and
 // sizes in the descriptor at the head of the slot buffer.  The launches and their arithmetic
-// are those of hp_iterate's steady state in its closing-reduction step form with the scatter's
-// grouping rebuilt inside the rebuilding evaluation (both bit-identical to the other forms).
+// are those of hp_iterate's steady state, with the scatter's grouping rebuilt inside the
+// rebuilding evaluation, and the step in its fused form when every slot's netlist takes it,
+// else in its closing-reduction form (all of these bit-identical to the other forms).
 template <typename T>
 int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<Netlist *> &nls,
                   const SlotGammas &g, int32_t flags, int32_t iters) {
@@ -1132,10 +1154,13 @@ int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<
     const int n = (int)ss.size();
     SlotArgs sa{};
     for (Slot *s : ss) sa.base[sa.n++] = s->base;
-    // grids of the passes whose sizes do not change between iterations: the largest slot's
+    // grids of the passes whose sizes do not change between iterations: the largest slot's;
+    // the fused step form when every slot's netlist takes it (no closing reduction launch)
     int big_x = 0, cg_x = 0, rows_x = 0, cols_x = 0, inv_x = 0, step_x = 0;
     size_t l_rows = 0, l_cols = 0, l_inv = 0;
+    bool fused = true;
     for (const Netlist *N : nls) {
+        fused &= cell_parts(N->nd) <= N->fused_parts;
         const NetDev &nd = N->nd;
         big_x = std::max(big_x, nd.n_big);
         cg_x = std::max(cg_x, round8(std::max(1, cell_parts(nd))));
@@ -1181,11 +1206,12 @@ int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<
         HP_CHECK(rag_spectral<T>(sa, rows_x, cols_x, inv_x, l_rows, l_cols, l_inv, st));
         HP_CHECK(rag_big_grad<T>(sa, big_x, st));
         HP_CHECK(rag_cell_grad<T>(sa, cg_x, st));
-        HP_CHECK(rag_eval_finish(sa, banks, st));
-        HP_CHECK(rag_step<T>(sa, step_x, banks, st));
+        if (!fused) HP_CHECK(rag_eval_finish(sa, banks, st));
+        HP_CHECK(rag_step<T>(sa, step_x, fused, banks, st));
         for (int i = 0; i < n; ++i) {
             Slot *s = ss[i];
             s->since_group = (cntm >> i) & 1u ? 1 : s->since_group + 1;
+            // (the fused update stored its proposal; either form leaves the same state)
             s->maps_valid = false;
             s->rho_dirty = false;
             s->step_proposed = false;
@@ -1315,6 +1341,14 @@ int hp_load_netlist_csr(hp_ctx *ctx, const hp_shape *shape, const hp_die *die, c
     if (dev_bytes < need)
         return fail(HP_ENOMEM, "netlist buffer needs " + std::to_string(need) + " bytes");
     HP_CHECK(hipSetDevice(ctx->device));
+    {  // the preparation and uploads below use the stream without the lock
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        ++ctx->stream_users;
+    }
+    struct Leave {
+        hp_ctx *c;
+        ~Leave() { --c->stream_users; }
+    } leave{ctx};
     Netlist NL;
     rc = ctx->precision == 32
              ? load_netlist<float>(ctx, *shape, *die, cell_w, cell_h, fixed_x, fixed_y, net_start,
@@ -1349,7 +1383,12 @@ int hp_slot_alloc(hp_ctx *ctx, int32_t netlist, void *dev_buf, size_t dev_bytes,
     Scalars s;
     init_scalars(s, 1e-4, 4.0, 1000);
     HP_CHECK(hipMemcpyAsync(base + NL.L.scal, &s, sizeof(s), hipMemcpyHostToDevice, st));
-    HP_TRY(write_descs(ctx, NL, {base}));  // waits for the stream
+    const SlotDesc d{NL.nd, NL.bk, NL.L};  // the descriptor at the head of the slot buffer
+    HP_CHECK(hipMemcpyAsync(base, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    HP_SYNC_UNLOCKED(ctx);  // s and d are read by then
+    if (!NL.alive) return fail(HP_ESTATE, "netlist released while a slot was being allocated");
+    if (NL.nd.spec_threads != d.nd.spec_threads || NL.nd.sweep_interleave != d.nd.sweep_interleave)
+        HP_TRY(write_descs(ctx, NL, {base}));  // a launch setting changed meanwhile
     Slot sl;
     sl.alive = true;
     sl.netlist = netlist;
@@ -1373,10 +1412,13 @@ int hp_slot_free(hp_ctx *ctx, int32_t slot) {
     }
     s->alive = false;  // no further work for it can be queued ...
     s->base = nullptr;
+    ++ctx->stream_users;
     lk.unlock();
     // ... and once the work queued so far has finished, its buffer may be released (the wait
     // holds no lock, so other threads keep queueing work meanwhile)
-    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    const hipError_t e = hipStreamSynchronize(ctx->stream);
+    --ctx->stream_users;
+    if (e != hipSuccess) return fail(HP_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
     return HP_OK;
 }
 
@@ -1412,7 +1454,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     }
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + L.scal, sizeof(h), hipMemcpyDeviceToHost, st));
-    HP_CHECK(hipStreamSynchronize(st));
+    HP_SYNC_UNLOCKED(ctx);
     for (int b = 0; b < 2; ++b) {  // the optimiser restarts (both banks)
         h.kb[b] = 0;
         h.ab[b] = 1.0;
@@ -1421,7 +1463,7 @@ int hp_set_positions(hp_ctx *ctx, int32_t slot, const void *x, const void *y, in
     h.lambda_valid = 0;
     h.hpwl_valid = 0;
     HP_CHECK(hipMemcpyAsync(s->base + L.scal, &h, sizeof(h), hipMemcpyHostToDevice, st));
-    HP_CHECK(hipStreamSynchronize(st));
+    HP_SYNC_UNLOCKED(ctx);
     s->lambda_valid = false;
     s->hpwl_pending = false;
     s->step_proposed = false;
@@ -1480,11 +1522,11 @@ int hp_set_schedule(hp_ctx *ctx, int32_t slot, double lambda0_scale, double deca
         return fail(HP_EINVAL, "bad schedule");
     Scalars h;
     HP_CHECK(hipMemcpyAsync(&h, s->base + n->L.scal, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    HP_SYNC_UNLOCKED(ctx);
     h.lambda0_scale = lambda0_scale;
     h.lambda_ratio = std::pow(10.0, decades / total_iters);
     HP_CHECK(hipMemcpyAsync(s->base + n->L.scal, &h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
-    HP_CHECK(hipStreamSynchronize(ctx->stream));
+    HP_SYNC_UNLOCKED(ctx);
     return HP_OK;
 }
 
@@ -1717,6 +1759,8 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
     // the state the block was captured from.  A block whose end state differs from its start
     // (not yet steady) is thrown away and the iterations run eagerly.  Launches with
     // per-kernel timing events are never captured.
+    // no capture while another thread uses the stream outside the lock (the iterations then run
+    // as they are; replays need no capture and stay allowed)
     if (graph && !hp::g_prof_on) {
         GraphBlock &G = ctx->graph;
         const int L = 2 * NL->regroup_every;
@@ -1750,7 +1794,8 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
             // one, or when that does not happen.
             bool steady = true;
             for (const Slot *s : ss) steady &= s->lambda_valid && !s->rho_dirty && s->since_group >= 0;
-            if (steady && eager_run >= 1 && attempts < 2 && (!have || eager_run > L)) {
+            if (steady && eager_run >= 1 && attempts < 2 && (!have || eager_run > L) &&
+                ctx->stream_users.load() == 0) {
                 ++attempts;
                 std::vector<Slot> snap;
                 for (const Slot *s : ss) snap.push_back(*s);
@@ -1857,8 +1902,11 @@ int hp_netlist_free(hp_ctx *ctx, int32_t netlist) {
         if (s.alive && s.netlist == netlist)
             return fail(HP_ESTATE, "netlist " + std::to_string(netlist) + " still has live slots");
     ctx->nets[netlist] = Netlist{};  // alive = false; host arrays released
+    ++ctx->stream_users;
     lk.unlock();
-    HP_CHECK(hipStreamSynchronize(ctx->stream));  // as hp_slot_free
+    const hipError_t e = hipStreamSynchronize(ctx->stream);  // as hp_slot_free
+    --ctx->stream_users;
+    if (e != hipSuccess) return fail(HP_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
     return HP_OK;
 }
 

@@ -353,10 +353,11 @@ template <typename T>
 hipError_t rag_big_grad(const SlotArgs &sa, int grid_x, hipStream_t st);
 template <typename T>
 hipError_t rag_cell_grad(const SlotArgs &sa, int grid_x, hipStream_t st);
-// The closing reduction in steady state (FIN_STEP) of every slot, then the update.
+// The closing reduction in steady state (FIN_STEP) of every slot, then the update (fused:
+// every block reduces its slot's step partials itself and no closing reduction ran).
 hipError_t rag_eval_finish(const SlotArgs &sa, uint32_t banks, hipStream_t st);
 template <typename T>
-hipError_t rag_step(const SlotArgs &sa, int grid_x, uint32_t banks, hipStream_t st);
+hipError_t rag_step(const SlotArgs &sa, int grid_x, bool fused, uint32_t banks, hipStream_t st);
 // host-side sizes the launches above need for one netlist
 int rows_fwd_blocks(const NetDev &nd);
 template <typename T> size_t rows_fwd_lds_of(const NetDev &nd);

@@ -273,15 +273,16 @@ constexpr int kStepThreads = 1024;  // cells per block of the update (fewer bloc
 // nc partials and the optimiser state of bank b.  One thread commits it into bank 1 - b and,
 // for an accepted step, multiplies lambda by the schedule's ratio; no block reads what that
 // thread writes.
-// RAG: the slot's netlist and layout from its descriptor, the update of a proposed step only
-// (fused = 0); blocks past the slot's own cells return.
+// RAG: the slot's netlist and layout from its descriptor and nc its own cell-gradient block
+// count; blocks past the slot's own cells return.
 template <typename T, bool RAG>
 __global__ __launch_bounds__(kStepThreads) void step_update_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
-                                                                   int fused, int nc, uint32_t banks) {
+                                                                   int fused, int nc_arg, uint32_t banks) {
     char *base = sa.base[blockIdx.y];
     const NetDev &nd = view_nd<RAG>(nda, base);
     const SlotLayout &L = view_L<RAG>(La, base);
-    if (RAG && (int)blockIdx.x * kStepThreads >= nd.n_mov) return;
+    if (RAG && (int)blockIdx.x * kStepThreads >= nd.n_mov) return;  // whole block
+    const int nc = RAG ? max(1, cell_parts(nd)) : nc_arg;  // as launch_cell_grad
     Scalars *sc = scalars(base, L);
     const int b = (banks >> blockIdx.y) & 1u;
     const int n = nd.n_mov;
@@ -453,10 +454,10 @@ hipError_t rag_eval_finish(const SlotArgs &sa, uint32_t banks, hipStream_t st) {
     return hipGetLastError();
 }
 template <typename T>
-hipError_t rag_step(const SlotArgs &sa, int grid_x, uint32_t banks, hipStream_t st) {
+hipError_t rag_step(const SlotArgs &sa, int grid_x, bool fused, uint32_t banks, hipStream_t st) {
     if (grid_x == 0) return hipSuccess;
     HP_LAUNCH("step_update_kernel", (step_update_kernel<T, true>), dim3(grid_x, sa.n),
-              dim3(kStepThreads), 0, st, NetDev{}, sa, SlotLayout{}, 0, 0, banks);
+              dim3(kStepThreads), 0, st, NetDev{}, sa, SlotLayout{}, (int)fused, 0, banks);
     return hipGetLastError();
 }
 int step_blocks(const NetDev &nd) { return (nd.n_mov + kStepThreads - 1) / kStepThreads; }
@@ -479,7 +480,7 @@ hipError_t launch_select_best(const NetDev &nd, const SlotArgs &sa, char *incumb
                                        bool, bool, uint32_t, hipStream_t);                      \
     template hipError_t launch_select_best<T>(const NetDev &, const SlotArgs &, char *,          \
                                               const SlotLayout &, hipStream_t);                 \
-    template hipError_t rag_step<T>(const SlotArgs &, int, uint32_t, hipStream_t);
+    template hipError_t rag_step<T>(const SlotArgs &, int, bool, uint32_t, hipStream_t);
 HP_INST(float)
 HP_INST(double)
 #undef HP_INST

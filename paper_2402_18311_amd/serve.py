@@ -207,7 +207,10 @@ class _LaunchGroup:
             self.peak_resident = max(self.peak_resident, len(batch))
             step = min(self.tick, min(e["left"] for e in batch))
             try:
-                for c in range(0, len(batch), 32):
+                if len(batch) == 1:  # alone: its own launches, steady blocks from a HIP graph
+                    e = batch[0]
+                    e["pl"].iterate(e["slot"], e["gamma"], step, hpwl=False, graph=True)
+                for c in range(0, len(batch) if len(batch) > 1 else 0, 32):
                     part = batch[c:c + 32]
                     self.ctx.iterate([e["slot"] for e in part], [e["gamma"] for e in part], step,
                                      hpwl=False)
@@ -238,8 +241,9 @@ class SharedLaunchExecutor:
     still overlap on the device.  `run(job)` (called from the scheduler's per-job thread)
     loads the job onto its class's context, runs its first iteration alone (lambda_0 and the
     scatter grouping), hands it to the device thread and waits for its result; each device
-    thread advances its resident jobs by min(tick, fewest iterations left) per round and reads
-    a job's HPWL when it is done."""
+    thread advances its resident jobs by min(tick, fewest iterations left) per round (a job
+    alone in its class with its own launches and HIP-graph replay, several in shared launches
+    of up to 32 slots; the results are the same) and reads a job's HPWL when it is done."""
 
     def __init__(self, tick: int = 10, precision: int = 32,
                  bounds: tuple = (40_000, 160_000, 640_000), make_context=None):

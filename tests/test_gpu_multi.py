@@ -58,8 +58,11 @@ def _start(pl, s, nl, seed):
     pl.set_schedule(s, 1e-4, 4.0, 300)
 
 
-@pytest.mark.parametrize("prec", [32, 64])
-def test_shared_launches_match_each_slot_alone(hy, prec):
+@pytest.mark.parametrize("prec,closing", [(32, False), (32, True), (64, False)])
+def test_shared_launches_match_each_slot_alone(hy, prec, closing):
+    """closing: one netlist takes the closing-reduction step form (as above 262,144 movable
+    cells), which puts the whole shared launch in that form; else every slot takes the fused
+    step."""
     nets = _NETS32 if prec == 32 else _NETS64
     built = {k: (make(), every) for k, (make, every) in nets.items()}
     ctx = hy.Context(precision=prec)
@@ -69,6 +72,8 @@ def test_shared_launches_match_each_slot_alone(hy, prec):
             for where in ("alone", "shared"):
                 pl = hy.Placer(nl, precision=prec) if where == "alone" else ctx.placer(nl)
                 pl.set_scatter_policy(every, every % 2 == 0)
+                if closing and k == "tiny" and where == "shared":
+                    pl.set_tunable(hy.HP_TUNE_FUSED_STEP_PARTS, 0)
                 # two slots of the first netlist, one of every other
                 ss = [pl.new_slot() for _ in range(2 if k == "small" or k == "tiny" else 1)]
                 for j, s in enumerate(ss):

@@ -103,9 +103,11 @@ class _FakePlacer:
     def set_schedule(self, s, *a):
         pass
 
-    def iterate(self, s, gamma, iters, hpwl=True):
+    def iterate(self, s, gamma, iters, hpwl=True, graph=False):
         with self.ctx.lock:
             self.ctx.done[s] += iters
+            if graph:
+                self.ctx.alone.append(iters)
 
     def hpwl(self, s):
         return [self.ctx.done[s]]
@@ -117,7 +119,7 @@ class _FakePlacer:
 class _FakeContext:
     def __init__(self, fail_after=None):
         self.lock = threading.Lock()
-        self.done, self.placers, self.calls = {}, [], []
+        self.done, self.placers, self.calls, self.alone = {}, [], [], []
         self.next_slot, self.closed, self.fail_after = 0, 0, fail_after
 
     def placer(self, nl):
@@ -172,14 +174,32 @@ def test_shared_launch_rounds_give_every_job_its_iterations():
     assert len(ctxs) == 3 and ex.peak_resident > 32
     for c in ctxs:
         assert c.closed == len(c.placers)
-        assert all(n <= 32 and it <= 7 for n, it in c.calls)
+        assert all(1 <= n <= 32 and it <= 7 for n, it in c.calls)
+        assert all(it <= 7 for it in c.alone)  # a job alone iterates on its own (graph replay)
 
 
 def test_shared_launch_errors_reach_every_resident_job():
     ex = serve.SharedLaunchExecutor(tick=5, bounds=(), make_context=lambda: _FakeContext(0))
     jobs = [serve.Job(i, _Net(50), 20, 0.0, nbytes=1) for i in range(4)]
-    try:
-        with pytest.raises(RuntimeError, match="device error"):
+    errors = []
+
+    def serve_all():
+        try:
             serve.Scheduler(1 << 30, ex.run).serve(jobs)
+        except RuntimeError as e:
+            errors.append(e)
+    try:
+        ex.pause()  # all four resident, so the first round is a shared launch, which fails
+        t = threading.Thread(target=serve_all)
+        t.start()
+        deadline = time.time() + 30
+        while ex.waiting() < 4 and time.time() < deadline:
+            time.sleep(0.01)
+        ex.resume()
+        t.join(timeout=30)
+        assert not t.is_alive()
     finally:
+        ex.resume()
         ex.close()
+    assert len(errors) == 1 and "device error" in str(errors[0])
+    assert all(j.hpwl_q is None for j in jobs)
