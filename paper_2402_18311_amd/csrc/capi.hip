@@ -293,7 +293,7 @@ struct GraphBlock {
     std::vector<int32_t> slots;
     double gamma = 0.0;
     int flags = 0, regroup_every = 0, fused_parts = 0, spec_threads = 0, interleave = 0;
-    bool deferred = false;
+    bool deferred = false, records = false;
     int len = 0;
     std::vector<Slot> start;
     hipGraph_t graph = nullptr;
@@ -1776,7 +1776,8 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
                             G.regroup_every == NL->regroup_every && G.deferred == NL->deferred &&
                             G.fused_parts == NL->fused_parts &&
                             G.spec_threads == NL->nd.spec_threads &&
-                            G.interleave == NL->nd.sweep_interleave;
+                            G.interleave == NL->nd.sweep_interleave &&
+                            G.records == NL->charge_records;
         bool have = key_ok;
         int attempts = 0, eager_run = 0;
         while (iters - done >= L) {
@@ -1832,6 +1833,7 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
                     G.fused_parts = NL->fused_parts;
                     G.spec_threads = NL->nd.spec_threads;
                     G.interleave = NL->nd.sweep_interleave;
+                    G.records = NL->charge_records;
                     G.start = snap;
                     G.graph = g;
                     G.exec = ex;

@@ -400,6 +400,33 @@ def test_iterate_graph_matches_single_calls(hy, orc, case, prec):
     pl.close()
 
 
+def test_graph_block_follows_launch_settings(hy, orc):
+    """A captured block is replayed only under the launch settings it was captured with: after
+    charge records are switched off (then on again) the next graph iterations capture a new
+    block, and the slot stays bit-identical to one iterated eagerly with the same switches."""
+    import torch
+    nl = _CASES["small"]()
+    pl = hy.Placer(nl, precision=32, stream=torch.cuda.Stream())
+    pl.set_scatter_policy(1, False)  # every evaluation rebuilds, so records are in every block
+    gamma = 4 * nl.bin_w
+    g, e = pl.new_slot(), pl.new_slot()
+    for s in (g, e):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+    seen = []
+    for rec in (1, 0, 1):
+        pl.set_tunable(hy.HP_TUNE_CHARGE_RECORDS, rec)
+        pl.iterate(g, gamma, 12, hpwl=True, graph=True)
+        pl.iterate(e, gamma, 12, hpwl=True, graph=False)
+        seen.append(hy.hp_graph_stats(pl.ctx)[0])
+        xg, yg = pl.positions(g)
+        xe, ye = pl.positions(e)
+        assert np.array_equal(xg, xe) and np.array_equal(yg, ye), rec
+        assert pl.hpwl(g)[0] == pl.hpwl(e)[0]
+    assert seen[0] >= 1 and seen[1] > seen[0] and seen[2] > seen[1], seen
+    pl.close()
+
+
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32)])
 def test_iterate_hpwl_last_matches_every(hy, orc, case, prec):
     """HPWL after the last iteration only: the same placement and the same final HPWL as the
