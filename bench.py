@@ -21,6 +21,7 @@ restarts, mid with movable macros, and the serving mix.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -87,6 +88,74 @@ def _cpu_model():
     return platform.processor() or "unknown"
 
 
+def _oracle_iterations(o, nl, gamma, iters, ratio):
+    """Seconds of each of `iters` oracle placer iterations from the initial positions:
+    objective and gradient (FFT path of the Poisson transforms), Nesterov step, exact HPWL."""
+    n = nl.n_movable
+    st = o.new_state(nl.x0, nl.y0)
+    lam = None
+    times = []
+    for _ in range(iters):
+        t0 = time.perf_counter()
+        r = o.eval(st["v"][:n], st["v"][n:], gamma, fft=True)
+        gw = np.concatenate([r["gwx"], r["gwy"]])
+        gd = np.concatenate([r["gdx"], r["gdy"]])
+        lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum() if lam is None else lam * ratio
+        o.nesterov_step(lam, gw + lam * gd, st)
+        o.hpwl_q(st["u"][:n], st["u"][n:])
+        times.append(time.perf_counter() - t0)
+    return times
+
+
+def cpu_extra(netgen, seed):
+    """The oracle on the other workloads (reported beside the headline's baseline, not part of
+    it): tiny, its full 200 iterations; mid, the median of 20 iterations, extrapolated to 1000;
+    the batched round, 32 mid slots advanced 2 iterations each with one slot per host thread at
+    a time, extrapolated to 1000 iterations per restart.  One thread and all threads each."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as O
+    all_threads = O.num_threads()
+    out = {"cpu_model": _cpu_model(), "threads_all": all_threads}
+    tiny = netgen.make_netlist("tiny", seed)
+    o = O.Oracle(tiny)
+    g = 4 * tiny.bin_w
+    row = {}
+    for th in (1, all_threads):
+        O.set_threads(th)
+        ts = _oracle_iterations(o, tiny, g, 200, o.lambda_ratio(4.0, 200))
+        row[f"{th}_threads"] = {"run_s": round(sum(ts), 3), "iter_per_s": round(200 / sum(ts), 2)}
+    out["tiny"] = dict(row, sample="the full 200-iteration placement from the initial positions")
+    mid = netgen.make_netlist("mid", seed)
+    o = O.Oracle(mid)
+    g = 4 * mid.bin_w
+    ratio = o.lambda_ratio(4.0, 1000)
+    row = {}
+    for th in (1, all_threads):
+        O.set_threads(th)
+        tm = float(np.median(_oracle_iterations(o, mid, g, 20, ratio)))
+        row[f"{th}_threads"] = {"iter_per_s": round(1 / tm, 3),
+                                "extrapolated_1000_iter_s": round(1000 * tm, 1)}
+    out["mid"] = dict(row, sample="median of 20 iterations from the initial positions; 1000 "
+                                  "iterations extrapolated, not run")
+    K, it = 32, 2
+
+    def slot(_):
+        O.set_threads(1)  # this worker's parallel loops on one thread
+        return sum(_oracle_iterations(o, mid, g, it, ratio))
+    with ThreadPoolExecutor(max_workers=all_threads) as ex:
+        t0 = time.perf_counter()
+        list(ex.map(slot, range(K)))
+        wall = time.perf_counter() - t0
+    O.set_threads(all_threads)
+    rate = K * it / wall
+    out["batched"] = {"slot_iter_per_s": round(rate, 3),
+                      "restarts_per_s_1000_iter": round(rate / 1000, 5),
+                      "sample": f"{K} mid slots x {it} iterations from the initial positions, "
+                                f"one slot per thread at a time on {all_threads} threads; 1000 "
+                                f"iterations per restart extrapolated, not run"}
+    return out
+
+
 def cpu_baseline(nl, gamma, iters=5, label="large"):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload: `iters` whole
     placer iterations (objective + gradient with the FFT path of the Poisson transforms,
@@ -105,19 +174,7 @@ def cpu_baseline(nl, gamma, iters=5, label="large"):
 
     def run(threads):
         O.set_threads(threads)
-        st = o.new_state(nl.x0, nl.y0)
-        lam = None
-        times = []
-        for _ in range(iters):
-            t0 = time.perf_counter()
-            r = o.eval(st["v"][:n], st["v"][n:], gamma, fft=True)
-            gw = np.concatenate([r["gwx"], r["gwy"]])
-            gd = np.concatenate([r["gdx"], r["gdy"]])
-            lam = 1e-4 * np.abs(gw).sum() / np.abs(gd).sum() if lam is None else lam * ratio
-            o.nesterov_step(lam, gw + lam * gd, st)
-            o.hpwl_q(st["u"][:n], st["u"][n:])
-            times.append(time.perf_counter() - t0)
-        return float(np.median(times))
+        return float(np.median(_oracle_iterations(o, nl, gamma, iters, ratio)))
 
     t1 = run(1)
     tn = run(all_threads)
@@ -395,7 +452,12 @@ def main():
                     help="untimed iterations of the same placement before the timed ones")
     ap.add_argument("--workload", default="large")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--locality", choices=("rent", "none"), default="rent",
+                    help="none: every net draws its cells from the whole index range (a "
+                         "sensitivity check of the synthetic netlists' index locality)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-extra", action="store_true",
+                    help="also time the oracle on tiny, mid and the batched round")
     ap.add_argument("--cpu-iters", type=int, default=5,
                     help="oracle iterations per thread setting of the CPU baseline")
     ap.add_argument("--no-profile", action="store_true",
@@ -446,7 +508,10 @@ def main():
         from paper_2402_18311_amd import build as b
         b.build()
 
-    nl = netgen.make_netlist(args.workload, args.seed)
+    cfg = netgen.CONFIGS[args.workload]
+    if args.locality == "none":
+        cfg = dataclasses.replace(cfg, locality=False, name=f"{cfg.name}_nolocality")
+    nl = netgen.make_netlist(cfg, args.seed)
     gamma = 4 * nl.bin_w
     K, W = args.steps, args.warmup
     total = CONFIG_ITERS.get(args.workload, W + K)
@@ -495,6 +560,7 @@ def main():
     # every launch
     prof = {}
     every_iter_ms = None
+    eval_us = None
     if not args.no_profile:
         P = min(K, 100)
         x, y = pl.positions(s)
@@ -517,6 +583,19 @@ def main():
         pl.iterate(t, gamma, P, hpwl=True)
         pl.hpwl(t)
         every_iter_ms = 1e3 * (time.perf_counter() - t1) / P
+        # the evaluation alone (objective and gradient at the slot's lambda, no step): events
+        # around 30 evaluations after 10 untimed ones
+        lam = pl.state(t)["lambda_"]
+        ev = []
+        for i in range(40):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pl.eval(t, gamma, lam=lam, want_host=False)
+            e1.record()
+            if i >= 10:
+                ev.append((e0, e1))
+        torch.cuda.synchronize()
+        eval_us = [1e3 * a.elapsed_time(b) for a, b in ev]
         pl.free_slot(t)
     b_eval, b_step, share = compulsory_bytes(nl)
     kernels = {k: {"launches": c, "avg_us": 1e3 * ms / max(c, 1), "total_ms": ms}
@@ -553,7 +632,7 @@ def main():
         achieved = share[dom] / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(dom, args.workload),
+                "traffic": stored_traffic(dom, args.workload if args.locality == "rent" else nl.name),
                 "kernel": dom, "compulsory_bytes_per_launch": int(share[dom]), "launches": c,
                 "avg_us": round(avg_s * 1e6, 3)}
     for k, v in kernels.items():
@@ -569,7 +648,9 @@ def main():
                                f"{nl.mx}x{nl.my} bins, FP32 with the int64 charge map, "
                                f"gamma = 4 bins; plain placer iterations {W}..{W + K} of a "
                                f"{total}-iteration schedule from the initial positions, the "
-                               f"exact HPWL and overflow read every {HPWL_EVERY} iterations",
+                               f"exact HPWL and overflow read every {HPWL_EVERY} iterations"
+                               + ("; nets draw their cells from the whole index range (no "
+                                  "index locality)" if args.locality == "none" else ""),
                    "global_batch": 1, "parallelism": "single-gpu"},
         "compulsory_bytes_per_iter": {"eval": b_eval, "step": b_step},
         "hbm_gbps_compulsory": round((b_eval + b_step) / (ms_step * 1e-3) / 1e9, 1),
@@ -580,6 +661,11 @@ def main():
                    "with events on every launch"),
         "final_hpwl": final["hpwl_q"] / 65536,
         "ms_per_step_hpwl_every_iteration": round(every_iter_ms, 5) if every_iter_ms else None,
+        "eval_us": ({"mean": round(float(np.mean(eval_us)), 2),
+                     "p50": round(float(np.median(eval_us)), 2), "evals": len(eval_us),
+                     "warmup": 10, "note": "objective and gradient at a fixed lambda, no step; "
+                                           "HIP events around each evaluation"}
+                    if eval_us else None),
         "tuning": {"scatter_policy": {"regroup_every": policy[0], "deferred": policy[1]},
                    "ms_per_iter": {k: round(v, 4) for k, v in tune_ms.items()},
                    "launch_shape": {k: (v if not isinstance(v, dict) else
@@ -608,6 +694,9 @@ def main():
                                        args.seed, log=log)
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if args.cpu_extra:
+        log("[bench] timing the CPU oracle on tiny, mid and the batched round ...")
+        out["cpu_extra"] = cpu_extra(netgen, args.seed)
     print(json.dumps(out), flush=True)
 
 
