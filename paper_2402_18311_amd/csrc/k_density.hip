@@ -296,8 +296,8 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
         // Loads are issued in dependency rounds, each round's loads all in flight before any
         // of them is used: (1) the cell's pin range, position and charge constants; (2) the
         // field at its charge footprint (a fixed 3 x 4 bin window on clamped in-footprint
-        // indices) and its first pin indices; (3) the pin gradients.  Sums keep pin order and
-        // row-major bin order.
+        // indices) and its first four pin indices; then the pin gradients four at a time, each
+        // batch with the next batch's indices.  Sums keep pin order and row-major bin order.
         const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
         const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
         const int4 cc = nd.cq[i];
@@ -328,23 +328,31 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
                     load_row4_part<T>(exy + (size_t)(ks + kk) * nd.mx + js, lo, hi, f[kk]);
             }
         }
-        for (; j + 4 <= e; j += 4) {  // four gathers in flight, summed in pin order
-            const int p0 = nd.cell_pins[j], p1 = nd.cell_pins[j + 1];
-            const int p2 = nd.cell_pins[j + 2], p3 = nd.cell_pins[j + 3];
-            const vec2<T> g0 = pg[p0], g1 = pg[p1], g2 = pg[p2], g3 = pg[p3];
-            gwx += g0.x;
-            gwy += g0.y;
-            gwx += g1.x;
-            gwy += g1.y;
-            gwx += g2.x;
-            gwy += g2.y;
-            gwx += g3.x;
-            gwy += g3.y;
-        }
-        for (; j < e; ++j) {
-            const vec2<T> g = pg[nd.cell_pins[j]];
-            gwx += g.x;
-            gwy += g.y;
+        // pins in batches of four, the last one masked (indices clamped into the cell's range):
+        // a batch's gradient gathers are in flight with the next batch's indices, and the sums
+        // keep pin order
+        if (j < e) {
+            int id[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) id[u] = nd.cell_pins[min(j + u, e - 1)];
+            for (;;) {
+                vec2<T> g4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) g4[u] = pg[id[u]];
+                const int jn = j + 4;
+                if (jn < e) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) id[u] = nd.cell_pins[min(jn + u, e - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j + u < e) {
+                        gwx += g4[u].x;
+                        gwy += g4[u].y;
+                    }
+                if (jn >= e) break;
+                j = jn;
+            }
         }
         if (big) {
             const T *gw = reinterpret_cast<const T *>(base + L.g);
