@@ -278,6 +278,9 @@ __device__ __forceinline__ void load_row4_part(const vec2<T> *src, bool lo, bool
 // descriptor and nb its own block count (the grid: the largest slot's, rounded up).  Six
 // waves per SIMD (80 registers): the pass waits on gathers, and at five it was 2-3% slower,
 // at eight (spilling) 20% slower.
+// pin gradients gathered per round of the gradient pass (at large, 6 per round was 0.4 us
+// slower and 8 was 3 us slower)
+constexpr int kPinBatch = 4;
 template <typename T, bool RAG>
 __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
                                                            double lam_fixed, int use_fixed,
@@ -332,23 +335,23 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
         // a batch's gradient gathers are in flight with the next batch's indices, and the sums
         // keep pin order
         if (j < e) {
-            int id[4];
+            int id[kPinBatch];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) id[u] = nd.cell_pins[min(j + u, e - 1)];
+            for (int u = 0; u < kPinBatch; ++u) id[u] = nd.cell_pins[min(j + u, e - 1)];
             for (;;) {
-                vec2<T> g4[4];
+                vec2<T> gb[kPinBatch];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) g4[u] = pg[id[u]];
-                const int jn = j + 4;
+                for (int u = 0; u < kPinBatch; ++u) gb[u] = pg[id[u]];
+                const int jn = j + kPinBatch;
                 if (jn < e) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) id[u] = nd.cell_pins[min(jn + u, e - 1)];
+                    for (int u = 0; u < kPinBatch; ++u) id[u] = nd.cell_pins[min(jn + u, e - 1)];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < kPinBatch; ++u)
                     if (j + u < e) {
-                        gwx += g4[u].x;
-                        gwy += g4[u].y;
+                        gwx += gb[u].x;
+                        gwy += gb[u].y;
                     }
                 if (jn >= e) break;
                 j = jn;
