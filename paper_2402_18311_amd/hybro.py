@@ -136,8 +136,43 @@ def lib():
         L.hp_last_error.restype = C.c_char_p
         L.hp_netlist_bytes.restype = C.c_size_t
         L.hp_slot_bytes.restype = C.c_size_t
+        # the HIP runtime the library binds to, for OwnStream
+        L.hipStreamCreateWithFlags.argtypes = [C.POINTER(C.c_void_p), C.c_uint]
+        L.hipStreamSynchronize.argtypes = [C.c_void_p]
+        L.hipStreamDestroy.argtypes = [C.c_void_p]
+        for f in (L.hipStreamCreateWithFlags, L.hipStreamSynchronize, L.hipStreamDestroy):
+            f.restype = C.c_int
         _lib = L
     return _lib
+
+
+class OwnStream:
+    """A HIP stream created for one placer or context and destroyed by close().
+
+    torch.cuda.Stream() hands out streams round-robin from a fixed pool per device, so placers
+    created far enough apart (a serving loop with many jobs in flight) can be given the same
+    stream, and one placer's graph capture then meets the other's work on it.  This stream
+    belongs to its user alone: default priority, non-blocking with respect to the null stream
+    as torch's are, created through the HIP runtime that the library itself calls.  The owner
+    closes it after the placer or context that uses it."""
+
+    def __init__(self, device=0):
+        import torch
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            rc = lib().hipStreamCreateWithFlags(C.byref(h), 1)  # hipStreamNonBlocking
+        if rc != 0 or not h.value:
+            raise HybroError(HP_EDEVICE, f"hipStreamCreateWithFlags returned {rc}")
+        self.device = device
+        self.cuda_stream = h.value
+
+    def close(self):
+        if self.cuda_stream:
+            h, self.cuda_stream = C.c_void_p(self.cuda_stream), 0
+            rc = lib().hipStreamSynchronize(h)
+            rc2 = lib().hipStreamDestroy(h)
+            if rc or rc2:
+                raise HybroError(HP_EDEVICE, f"stream sync/destroy returned {rc}/{rc2}")
 
 
 def _chk(rc):

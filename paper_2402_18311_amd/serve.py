@@ -161,11 +161,16 @@ def run_on_gpu(job: Job) -> None:
     import torch
 
     from . import hybro as hy
-    # The job's kernels run on its own stream; its buffers come from torch's pool on the
-    # default stream, and are dropped only after hp_destroy has synchronised the job's stream,
-    # so the next allocation may reuse them at once.
-    stream = torch.cuda.Stream()
-    pl = hy.Placer(job.netlist, precision=32, stream=stream)
+    # The job's kernels run on a stream of its own (not one of torch's pooled streams, which
+    # concurrent jobs could share); its buffers come from torch's pool on the default stream,
+    # and are dropped only after hp_destroy has synchronised the job's stream, so the next
+    # allocation may reuse them at once.
+    stream = hy.OwnStream(torch.cuda.current_device())
+    try:
+        pl = hy.Placer(job.netlist, precision=32, stream=stream)
+    except BaseException:
+        stream.close()
+        raise
     try:
         s = pl.new_slot()
         nl = job.netlist
@@ -179,6 +184,7 @@ def run_on_gpu(job: Job) -> None:
     finally:
         pl.close()
         del pl
+        stream.close()
 
 
 class _LaunchGroup:
@@ -249,12 +255,15 @@ class SharedLaunchExecutor:
                  bounds: tuple = (40_000, 160_000, 640_000), make_context=None):
         """make_context: () -> a context (hybro.Context: placer, iterate, close); by default
         one of the given precision on a stream of its own."""
+        self._streams = []  # the streams of the default contexts, closed after them
         if make_context is None:
             def make_context():
                 import torch
 
                 from . import hybro as hy
-                return hy.Context(precision=precision, stream=torch.cuda.Stream())
+                s = hy.OwnStream(torch.cuda.current_device())
+                self._streams.append(s)
+                return hy.Context(precision=precision, stream=s)
         self.bounds = tuple(bounds)
         self.groups = [_LaunchGroup(int(tick), make_context) for _ in range(len(self.bounds) + 1)]
 
@@ -328,6 +337,9 @@ class SharedLaunchExecutor:
         for g in self.groups:
             g.thread.join()
             g.ctx.close()
+        for s in self._streams:
+            s.close()
+        self._streams = []
 
 
 def _make_one(args):

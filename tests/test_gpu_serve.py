@@ -59,3 +59,31 @@ def test_shared_launch_executor_equals_alone():
         assert a.hpwl_q is not None and a.hpwl_q == b.hpwl_q, a.jid
     print("shared launches", serve.stats(mixed), "rounds", ex.rounds,
           "peak per round", ex.peak_resident)
+
+
+def test_many_jobs_in_flight_have_streams_of_their_own():
+    """Forty jobs in flight at once, each capturing graph blocks on its stream.  torch's
+    Stream() repeats its pooled streams after 32, so two live jobs would share one (and one's
+    capture would meet the other's work); each job's own stream is distinct from every other
+    live one, and every job still ends with its alone HPWL_q."""
+    import torch
+
+    from paper_2402_18311_amd import hybro as hy
+    assert len({torch.cuda.Stream().cuda_stream for _ in range(40)}) <= 32  # the pool
+    own = [hy.OwnStream() for _ in range(40)]
+    try:
+        assert len({s.cuda_stream for s in own}) == 40 and all(s.cuda_stream for s in own)
+    finally:
+        for s in own:
+            s.close()
+    jobs = serve.make_jobs(40, 2_000, 20_000, 40, seed=9)
+    for j in jobs:
+        j.nbytes = serve.device_bytes(j.netlist)
+    alone = serve.fresh(jobs)
+    serve.serve_sequential(alone, serve.run_on_gpu)
+    mixed = serve.fresh(jobs)
+    sch = serve.Scheduler(sum(j.nbytes for j in jobs), serve.run_on_gpu)  # all admitted at once
+    sch.serve(mixed)
+    assert sch.peak_jobs > 32, sch.peak_jobs
+    for a, b in zip(alone, mixed):
+        assert a.hpwl_q is not None and a.hpwl_q == b.hpwl_q, a.jid
