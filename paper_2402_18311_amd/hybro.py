@@ -404,8 +404,10 @@ def hp_get_state(ctx, slot):
 class Placer:
     """One netlist on the GPU with any number of slots (placement instances).
 
-    Buffers are torch uint8 tensors on `device`; the library runs on torch's current stream
-    of that device at construction time."""
+    Buffers are torch uint8 tensors on `device`; the library runs on `stream` (any object with
+    a `cuda_stream` handle), by default torch's current stream of that device at construction
+    time.  Placers in use at the same time from different threads each need a stream no other
+    placer uses: an OwnStream, not torch.cuda.Stream(), whose pooled streams repeat."""
 
     def __init__(self, nl, precision=32, device=0, stretch=True, fd5=False,
                  target_density=1.0, net_weight=None, stream=None, context=None):
