@@ -244,7 +244,8 @@ typedef struct {
 } hp_iter_params;
 int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const hp_iter_params *p,
                int32_t iters);
-/* Graph blocks captured and replayed by hp_iterate on this context so far (inspection; either
+/* Graph blocks captured and replayed by hp_iterate and hp_iterate_multi on this context so far
+ * (inspection; either
  * output may be NULL).  No device work. */
 int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays);
 
@@ -255,8 +256,11 @@ int hp_graph_stats(hp_ctx *ctx, int64_t *captures, int64_t *replays);
  * results are bit-identical to running each slot alone with hp_iterate.  Every slot must be
  * in steady state: its lambda derived and its charge grouping built by an earlier iteration
  * (one hp_iterate call), and no map kept by an evaluation since (HP_ESTATE otherwise).
- * flags: HP_ITER_HPWL and HP_ITER_HPWL_LAST as for hp_iterate (no graph replay).  At most 32
- * slots, each listed once (HP_EINVAL); iters < 0: HP_EINVAL.  Does not synchronise. */
+ * flags: HP_ITER_HPWL, HP_ITER_HPWL_LAST and HP_ITER_GRAPH as for hp_iterate (a block is the
+ * least common multiple of twice the slots' rebuild intervals, at most 64 iterations; longer
+ * cycles iterate eagerly; the context's one cached block is shared with hp_iterate).  At most
+ * 32 slots, each listed once (HP_EINVAL); iters < 0, an unknown flag, or HP_ITER_GRAPH on a
+ * context of the null stream: HP_EINVAL.  Does not synchronise. */
 int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n_slots, const double *gammas,
                      int32_t flags, int32_t iters);
 

@@ -285,15 +285,13 @@ bool same_state(const Slot &a, const Slot &b) {
            a.since_group == b.since_group && a.rho_dirty == b.rho_dirty;
 }
 
-// A captured block of hp_iterate (HP_ITER_GRAPH): its launches, the call's slots, smoothing and
-// flags, the netlist's launch settings, and the host state of the slots at the block's start,
-// which the block returns them to.
+// A captured block of hp_iterate or hp_iterate_multi (HP_ITER_GRAPH): its launches, the call's
+// slots, its key (which call; smoothing, flags and the launch settings of the slots' netlists),
+// and the host state of the slots at the block's start, which the block returns them to.
 struct GraphBlock {
     bool valid = false;
     std::vector<int32_t> slots;
-    double gamma = 0.0;
-    int flags = 0, regroup_every = 0, fused_parts = 0, spec_threads = 0, interleave = 0;
-    bool deferred = false, records = false;
+    std::vector<double> key;
     int len = 0;
     std::vector<Slot> start;
     hipGraph_t graph = nullptr;
@@ -1147,9 +1145,97 @@ namespace {
 // are those of hp_iterate's steady state, with the scatter's grouping rebuilt inside the
 // rebuilding evaluation, and the step in its fused form when every slot's netlist takes it,
 // else in its closing-reduction form (all of these bit-identical to the other forms).
+// Runs iterations of `one` (the launches of one iteration and the host-state updates that go with
+// them) from `done` towards `iters`, replaying steady blocks of L iterations from the context's
+// cached graph.  A block is captured by running the same launch logic under stream capture and
+// replayed while every slot's host state (the only input of that logic besides the call's
+// parameters, which `key` records with the slots) equals the state the block was captured
+// from; a block whose end state differs from its start (not yet steady) is thrown away and the
+// iterations run eagerly.  No capture while another thread uses the stream outside the lock
+// (the iterations then run as they are; replays need no capture and stay allowed).  Returns
+// with fewer than L iterations left; the caller runs those eagerly.
+// the longest block of iterations captured as one graph (longer cycles iterate eagerly)
+constexpr int kMaxGraphBlock = 64;
+
+template <class One>
+int run_graph_blocks(hp_ctx *ctx, const std::vector<int32_t> &sl, const std::vector<Slot *> &ss,
+                     const std::vector<double> &key, int L, int iters, int &done, One one) {
+    GraphBlock &G = ctx->graph;
+    const int n = (int)ss.size();
+    auto state_is = [&](const std::vector<Slot> &st) {
+        for (int i = 0; i < n; ++i)
+            if (!same_state(*ss[i], st[i])) return false;
+        return true;
+    };
+    bool have = G.valid && G.slots == sl && G.key == key && G.len == L;
+    int attempts = 0, eager_run = 0;
+    while (iters - done >= L) {
+        if (have && state_is(G.start)) {
+            HP_CHECK(hipGraphLaunch(G.exec, ctx->stream));
+            ++ctx->graph_replays;
+            done += L;
+            eager_run = 0;
+            continue;
+        }
+        // A call starts in the state left by whatever read the slots last (pending
+        // reductions done), which no block returns to: one eager iteration brings the
+        // slots into the steady cycle.  With a block for these parameters at hand, eager
+        // iterations run until the slots reach its start (at most L); capture only without
+        // one, or when that does not happen.
+        bool steady = true;
+        for (const Slot *s : ss) steady &= s->lambda_valid && !s->rho_dirty && s->since_group >= 0;
+        if (steady && eager_run >= 1 && attempts < 2 && (!have || eager_run > L) &&
+            ctx->stream_users.load() == 0) {
+            ++attempts;
+            std::vector<Slot> snap;
+            for (const Slot *s : ss) snap.push_back(*s);
+            HP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            int crc = HP_OK;
+            for (int k = 0; k < L && crc == HP_OK; ++k) crc = one();
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
+            const bool periodic = crc == HP_OK && ce == hipSuccess && state_is(snap);
+            for (int i = 0; i < n; ++i) *ss[i] = snap[i];  // the capture ran nothing
+            if (crc != HP_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return crc;
+            }
+            if (ce != hipSuccess) return fail(HP_EDEVICE, std::string("hipStreamEndCapture: ") +
+                                                              hipGetErrorString(ce));
+            if (periodic) {
+                hipGraphExec_t ex = nullptr;
+                const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                if (ie != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    return fail(HP_EDEVICE, std::string("hipGraphInstantiate: ") +
+                                                hipGetErrorString(ie));
+                }
+                if (G.valid) HP_CHECK(hipStreamSynchronize(ctx->stream));  // no replay pending
+                drop_graph(G);
+                G.valid = true;
+                G.slots = sl;
+                G.key = key;
+                G.len = L;
+                G.start = snap;
+                G.graph = g;
+                G.exec = ex;
+                ++ctx->graph_captures;
+                have = true;
+                continue;  // the next pass finds the state matching and replays
+            }
+            (void)hipGraphDestroy(g);
+        }
+        HP_TRY(one());
+        ++done;
+        ++eager_run;
+    }
+    return HP_OK;
+}
+
 template <typename T>
-int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<Netlist *> &nls,
-                  const SlotGammas &g, int32_t flags, int32_t iters) {
+int iterate_multi(hp_ctx *ctx, const std::vector<int32_t> &sl, const std::vector<Slot *> &ss,
+                  const std::vector<Netlist *> &nls, const SlotGammas &g, int32_t flags,
+                  int32_t iters) {
     hipStream_t st = ctx->stream;
     const int n = (int)ss.size();
     SlotArgs sa{};
@@ -1172,7 +1258,7 @@ int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<
         l_cols = std::max(l_cols, cols_lds_of<T>(nd));
         l_inv = std::max(l_inv, rows_inv_lds_of<T>(nd));
     }
-    for (int it = 0; it < iters; ++it) {
+    auto one = [&]() -> int {
         uint32_t accm = 0, cntm = 0, hmask = 0, banks = 0;
         int front_x = 0, cs_x = 0, pl_x = 0, ac_x = 0;
         size_t l_front = 0, l_pl = 0, l_ac = 0;
@@ -1220,7 +1306,23 @@ int iterate_multi(hp_ctx *ctx, const std::vector<Slot *> &ss, const std::vector<
             s->bank ^= 1;  // the step committed into the other bank
             if (flags & HP_ITER_HPWL) s->hpwl_requested = true;
         }
+        return HP_OK;
+    };
+    int done = 0;
+    // graph replay of steady blocks: each slot's state comes back after twice its netlist's
+    // rebuild interval, all of them after the least common multiple of those
+    if ((flags & HP_ITER_GRAPH) && !hp::g_prof_on) {
+        std::vector<double> key = {1.0, (double)flags};
+        int L = 2;
+        for (int i = 0; i < n; ++i) {
+            const Netlist &N = *nls[i];
+            key.insert(key.end(), {g.inv[i], (double)N.regroup_every, (double)N.fused_parts,
+                                   (double)N.nd.spec_threads, (double)N.nd.sweep_interleave});
+            L = std::lcm(L, 2 * N.regroup_every);
+        }
+        if (L <= kMaxGraphBlock) HP_TRY(run_graph_blocks(ctx, sl, ss, key, L, iters, done, one));
     }
+    for (; done < iters; ++done) HP_TRY(one());
     if (iters > 0 && !(flags & HP_ITER_HPWL) && (flags & HP_ITER_HPWL_LAST))
         for (Slot *s : ss) s->hpwl_requested = true;
     return HP_OK;
@@ -1752,101 +1854,16 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
         return HP_OK;
     };
     int done = 0;
-    // Graph replay: a block of L iterations (L = twice the scatter's rebuild interval, so that
-    // the optimiser-state banks and the rebuild phase come back to where they were) is
-    // captured by running the same launch logic under stream capture, and replayed while every
-    // slot's host state (the only input of that logic besides the call's parameters) equals
-    // the state the block was captured from.  A block whose end state differs from its start
-    // (not yet steady) is thrown away and the iterations run eagerly.  Launches with
-    // per-kernel timing events are never captured.
-    // no capture while another thread uses the stream outside the lock (the iterations then run
-    // as they are; replays need no capture and stay allowed)
+    // graph replay of steady blocks of twice the scatter's rebuild interval (the optimiser-state
+    // banks and the rebuild phase then come back to where they were)
     if (graph && !hp::g_prof_on) {
-        GraphBlock &G = ctx->graph;
-        const int L = 2 * NL->regroup_every;
-        const std::vector<int32_t> sl(slots, slots + n);
-        auto state_is = [&](const std::vector<Slot> &st) {
-            for (int i = 0; i < n; ++i)
-                if (!same_state(*ss[i], st[i])) return false;
-            return true;
-        };
-        // the cached block was captured for this call's slots, parameters and launch settings
-        const bool key_ok = G.valid && G.slots == sl && G.gamma == p->gamma &&
-                            G.flags == p->flags && G.len == L &&
-                            G.regroup_every == NL->regroup_every && G.deferred == NL->deferred &&
-                            G.fused_parts == NL->fused_parts &&
-                            G.spec_threads == NL->nd.spec_threads &&
-                            G.interleave == NL->nd.sweep_interleave &&
-                            G.records == NL->charge_records;
-        bool have = key_ok;
-        int attempts = 0, eager_run = 0;
-        while (iters - done >= L) {
-            if (have && state_is(G.start)) {
-                HP_CHECK(hipGraphLaunch(G.exec, ctx->stream));
-                ++ctx->graph_replays;
-                done += L;
-                eager_run = 0;
-                continue;
-            }
-            // A call starts in the state left by whatever read the slots last (pending
-            // reductions done), which no block returns to: one eager iteration brings the
-            // slots into the steady cycle.  With a block for these parameters at hand, eager
-            // iterations run until the slots reach its start (at most L); capture only without
-            // one, or when that does not happen.
-            bool steady = true;
-            for (const Slot *s : ss) steady &= s->lambda_valid && !s->rho_dirty && s->since_group >= 0;
-            if (steady && eager_run >= 1 && attempts < 2 && (!have || eager_run > L) &&
-                ctx->stream_users.load() == 0) {
-                ++attempts;
-                std::vector<Slot> snap;
-                for (const Slot *s : ss) snap.push_back(*s);
-                HP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-                int crc = HP_OK;
-                for (int k = 0; k < L && crc == HP_OK; ++k) crc = iteration();
-                hipGraph_t g = nullptr;
-                const hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
-                const bool periodic = crc == HP_OK && ce == hipSuccess && state_is(snap);
-                for (int i = 0; i < n; ++i) *ss[i] = snap[i];  // the capture ran nothing
-                if (crc != HP_OK) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return crc;
-                }
-                if (ce != hipSuccess) return fail(HP_EDEVICE, std::string("hipStreamEndCapture: ") +
-                                                                  hipGetErrorString(ce));
-                if (periodic) {
-                    hipGraphExec_t ex = nullptr;
-                    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                    if (ie != hipSuccess) {
-                        (void)hipGraphDestroy(g);
-                        return fail(HP_EDEVICE, std::string("hipGraphInstantiate: ") +
-                                                    hipGetErrorString(ie));
-                    }
-                    if (G.valid) HP_CHECK(hipStreamSynchronize(ctx->stream));  // no replay pending
-                    drop_graph(G);
-                    G.valid = true;
-                    G.slots = sl;
-                    G.gamma = p->gamma;
-                    G.flags = p->flags;
-                    G.len = L;
-                    G.regroup_every = NL->regroup_every;
-                    G.deferred = NL->deferred;
-                    G.fused_parts = NL->fused_parts;
-                    G.spec_threads = NL->nd.spec_threads;
-                    G.interleave = NL->nd.sweep_interleave;
-                    G.records = NL->charge_records;
-                    G.start = snap;
-                    G.graph = g;
-                    G.exec = ex;
-                    ++ctx->graph_captures;
-                    have = true;
-                    continue;  // the next pass finds the state matching and replays
-                }
-                (void)hipGraphDestroy(g);
-            }
-            HP_TRY(iteration());
-            ++done;
-            ++eager_run;
-        }
+        const std::vector<double> key = {0.0, p->gamma, (double)p->flags, (double)NL->regroup_every,
+                                         (double)NL->deferred, (double)NL->fused_parts,
+                                         (double)NL->nd.spec_threads,
+                                         (double)NL->nd.sweep_interleave,
+                                         (double)NL->charge_records};
+        HP_TRY(run_graph_blocks(ctx, std::vector<int32_t>(slots, slots + n), ss, key,
+                                2 * NL->regroup_every, iters, done, iteration));
     }
     for (; done < iters; ++done) HP_TRY(iteration());
     if (iters > 0 && !with_hpwl && (p->flags & HP_ITER_HPWL_LAST))
@@ -1870,8 +1887,10 @@ int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n, const double 
     if (n > kMaxSlots) return fail(HP_EINVAL, "at most " + std::to_string(kMaxSlots) + " slots per call");
     if (!gammas) return fail(HP_EINVAL, "gammas is NULL");
     if (iters < 0) return fail(HP_EINVAL, "iters must be >= 0");
-    if (flags & ~(HP_ITER_HPWL | HP_ITER_HPWL_LAST))
-        return fail(HP_EINVAL, "unknown flags (HP_ITER_HPWL and HP_ITER_HPWL_LAST only)");
+    if (flags & ~(HP_ITER_HPWL | HP_ITER_HPWL_LAST | HP_ITER_GRAPH)) return fail(HP_EINVAL, "unknown flags");
+    if ((flags & HP_ITER_GRAPH) && ctx->stream == nullptr)
+        return fail(HP_EINVAL, "HP_ITER_GRAPH needs a context stream other than the null stream "
+                               "(the legacy default stream cannot be captured)");
     std::vector<Slot *> ss;
     std::vector<Netlist *> nls;
     SlotGammas g{};
@@ -1891,8 +1910,9 @@ int hp_iterate_multi(hp_ctx *ctx, const int32_t *slots, int32_t n, const double 
         nls.push_back(nl);
         g.inv[i] = 1.0 / gammas[i];
     }
-    return ctx->precision == 32 ? iterate_multi<float>(ctx, ss, nls, g, flags, iters)
-                                : iterate_multi<double>(ctx, ss, nls, g, flags, iters);
+    const std::vector<int32_t> sl(slots, slots + n);
+    return ctx->precision == 32 ? iterate_multi<float>(ctx, sl, ss, nls, g, flags, iters)
+                                : iterate_multi<double>(ctx, sl, ss, nls, g, flags, iters);
 }
 
 int hp_netlist_free(hp_ctx *ctx, int32_t netlist) {

@@ -613,11 +613,13 @@ class Context:
     def placer(self, nl, **kw):
         return Placer(nl, context=self, **kw)
 
-    def iterate(self, slots, gammas, iters, hpwl="last"):
+    def iterate(self, slots, gammas, iters, hpwl="last", graph=False):
         """iters placer iterations of every listed slot (slots of any of this context's
         netlists, each in steady state: one Placer.iterate on it first) with its own gamma,
-        each pass of an iteration one launch over all of them; hpwl as for Placer.iterate."""
-        flags = HP_ITER_HPWL_LAST if hpwl == "last" else HP_ITER_HPWL if hpwl else 0
+        each pass of an iteration one launch over all of them; hpwl and graph as for
+        Placer.iterate (graph replay needs a stream other than the null stream)."""
+        flags = ((HP_ITER_HPWL_LAST if hpwl == "last" else HP_ITER_HPWL if hpwl else 0) |
+                 (HP_ITER_GRAPH if graph else 0))
         hp_iterate_multi(self.ctx, list(np.atleast_1d(slots)), gammas, iters, flags)
 
     def close(self):

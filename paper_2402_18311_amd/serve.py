@@ -9,13 +9,15 @@ releases a finished job's memory so the next arrivals are admitted at once.  Two
 
 * per-job streams (`run_on_gpu`): every admitted job runs on its own HIP stream from its own
   host thread (steady-state blocks replayed from a HIP graph), so the kernels of concurrent
-  jobs overlap on the device;
+  jobs interleave on the device (launches of different streams are not run side by side on
+  this stack: two half-machine kernels on two streams take as long as on one);
 * shared launches (`SharedLaunchExecutor`): admitted jobs are loaded by their host threads
   onto a shared library context of their size class and, after their first iteration, join
   its resident set; the class's device thread advances every resident job by `tick`
   iterations per round, each pass of an iteration one launch over all of their slots
-  (hp_iterate_multi, up to 32 slots a launch), so small jobs no longer cost a launch sequence
-  each; classes run on their own streams and overlap.
+  (hp_iterate_multi, up to 32 slots a launch, steady blocks replayed from a HIP graph while
+  the resident set stays the same), so small jobs no longer cost a launch sequence each;
+  classes run on their own streams and interleave.
 
 The baseline is the same trace served sequentially: one job at a time, in arrival order.
 Every kernel is deterministic per slot and the shared launches are bit-identical to a slot's
@@ -219,7 +221,7 @@ class _LaunchGroup:
                 for c in range(0, len(batch) if len(batch) > 1 else 0, 32):
                     part = batch[c:c + 32]
                     self.ctx.iterate([e["slot"] for e in part], [e["gamma"] for e in part], step,
-                                     hpwl=False)
+                                     hpwl=False, graph=True)
                 self.rounds += 1
                 done = []
                 for e in batch:
@@ -244,14 +246,16 @@ class SharedLaunchExecutor:
     Jobs are split into size classes by movable cells (`bounds`: class k holds jobs below
     bounds[k], the last class the rest); each class has its own context, stream and device
     thread, so a small job is not held to the iteration rate of a large one while the classes
-    still overlap on the device.  `run(job)` (called from the scheduler's per-job thread)
+    still interleave on the device.  `run(job)` (called from the scheduler's per-job thread)
     loads the job onto its class's context, runs its first iteration alone (lambda_0 and the
     scatter grouping), hands it to the device thread and waits for its result; each device
     thread advances its resident jobs by min(tick, fewest iterations left) per round (a job
-    alone in its class with its own launches and HIP-graph replay, several in shared launches
-    of up to 32 slots; the results are the same) and reads a job's HPWL when it is done."""
+    alone in its class with its own launches, several in shared launches of up to 32 slots,
+    both replaying steady blocks from a HIP graph; the results are the same) and reads a job's
+    HPWL when it is done.  The default tick, 16, is a multiple of the 8-iteration graph block
+    of the default scatter policy, so that rounds of an unchanged resident set replay it."""
 
-    def __init__(self, tick: int = 10, precision: int = 32,
+    def __init__(self, tick: int = 16, precision: int = 32,
                  bounds: tuple = (40_000, 160_000, 640_000), make_context=None):
         """make_context: () -> a context (hybro.Context: placer, iterate, close); by default
         one of the given precision on a stream of its own."""
@@ -375,7 +379,7 @@ def fresh(jobs: list[Job]) -> list[Job]:
 
 
 def measure(n_jobs=200, lo=10_000, hi=2_200_000, iters=500, budget_gb=8.0, rate_frac=0.8,
-            seed=0, log=print, workers=0, tick=10) -> dict:
+            seed=0, log=print, workers=0, tick=16) -> dict:
     """Config 5: capacity of sequential plain solves (all jobs queued at t = 0), then a Poisson
     trace at rate_frac x that capacity served sequentially and by the server with each
     executor."""
@@ -433,7 +437,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=8,
                     help="processes drawing the synthetic netlists")
-    ap.add_argument("--tick", type=int, default=10,
+    ap.add_argument("--tick", type=int, default=16,
                     help="iterations per round of the shared-launch executor")
     a = ap.parse_args()
     print(json.dumps(measure(a.jobs, a.lo, a.hi, a.iters, a.budget_gb, a.rate_frac, a.seed,

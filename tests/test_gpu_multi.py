@@ -58,14 +58,18 @@ def _start(pl, s, nl, seed):
     pl.set_schedule(s, 1e-4, 4.0, 300)
 
 
-@pytest.mark.parametrize("prec,closing", [(32, False), (32, True), (64, False)])
-def test_shared_launches_match_each_slot_alone(hy, prec, closing):
+@pytest.mark.parametrize("prec,closing,graph", [(32, False, False), (32, True, False),
+                                                (64, False, False), (32, False, True),
+                                                (64, False, True)])
+def test_shared_launches_match_each_slot_alone(hy, prec, closing, graph):
     """closing: one netlist takes the closing-reduction step form (as above 262,144 movable
     cells), which puts the whole shared launch in that form; else every slot takes the fused
-    step."""
+    step.  graph: the shared launches replay steady blocks from a captured HIP graph (the
+    slots' rebuild intervals make a 24-iteration block), in calls long enough to replay."""
     nets = _NETS32 if prec == 32 else _NETS64
     built = {k: (make(), every) for k, (make, every) in nets.items()}
-    ctx = hy.Context(precision=prec)
+    stream = hy.OwnStream() if graph else None
+    ctx = hy.Context(precision=prec, stream=stream)
     alone, shared = {}, {}
     try:
         for k, (nl, every) in built.items():
@@ -82,8 +86,11 @@ def test_shared_launches_match_each_slot_alone(hy, prec, closing):
                 (alone if where == "alone" else shared)[k] = (pl, ss)
         slots = [s for pl, ss in shared.values() for s in ss]
         gammas = [4 * pl.nl.bin_w for pl, ss in shared.values() for s in ss]
-        for chunk, hpwl in ((3, "last"), (5, True), (9, "last")):
-            ctx.iterate(slots, gammas, chunk, hpwl=hpwl)
+        chunks = ((3, "last"), (5, True), (9, "last"))
+        if graph:
+            chunks = ((3, "last"), (60, "last"), (5, True), (50, True), (9, "last"))
+        for chunk, hpwl in chunks:
+            ctx.iterate(slots, gammas, chunk, hpwl=hpwl, graph=graph)
             for k, (pl, ss) in alone.items():
                 for s in ss:
                     pl.iterate(s, 4 * pl.nl.bin_w, chunk, hpwl=hpwl)
@@ -95,12 +102,18 @@ def test_shared_launches_match_each_slot_alone(hy, prec, closing):
                         assert ra[f] == rb[f], (k, chunk, f)
             print(f"fp{prec} after +{chunk}: HPWL " + ", ".join(
                 f"{k} {_snap(shared[k][0], shared[k][1][0])['hpwl'] / 65536:.1f}" for k in built))
+        if graph:
+            captures, replays = hy.hp_graph_stats(ctx.ctx)
+            print(f"graph blocks captured {captures}, replayed {replays}")
+            assert captures >= 1 and replays >= 2
     finally:
         for pl, _ in alone.values():
             pl.close()
         for pl, _ in shared.values():
             pl.close()
         ctx.close()
+        if stream is not None:
+            stream.close()
 
 
 def test_shared_launch_errors(hy):
@@ -126,7 +139,9 @@ def test_shared_launch_errors(hy):
         assert call([sa, sa], [1.0, 1.0]) == hy.HP_EINVAL  # listed twice
         assert call([sa, sb], [1.0, 0.0]) == hy.HP_EINVAL  # gamma
         assert call([sa, sb], [1.0, float("nan")]) == hy.HP_EINVAL
+        # graph replay needs a stream other than the null stream; unknown flags
         assert call([sa, sb], [1.0, 1.0], flags=hy.HP_ITER_GRAPH) == hy.HP_EINVAL
+        assert call([sa, sb], [1.0, 1.0], flags=1 << 9) == hy.HP_EINVAL
         assert call([sa, sb], [1.0, 1.0], iters=-1) == hy.HP_EINVAL
         assert call([sa, 999], [1.0, 1.0]) == hy.HP_ESTATE
         assert call(list(range(33)), [1.0] * 33) == hy.HP_EINVAL

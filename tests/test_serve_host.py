@@ -125,7 +125,7 @@ class _FakeContext:
     def placer(self, nl):
         return _FakePlacer(self, nl)
 
-    def iterate(self, slots, gammas, iters, hpwl="last"):
+    def iterate(self, slots, gammas, iters, hpwl="last", graph=False):
         assert len(slots) == len(gammas) and 1 <= len(slots) <= 32 and iters >= 1
         with self.lock:
             self.calls.append((len(slots), iters))
