@@ -86,6 +86,7 @@ __device__ __forceinline__ void count_body(const NetDev &nd, char *base, const S
 // atomics.  REC: the order was counted in this evaluation, so each cell's charge record from
 // the counting pass is current and one gather replaces those of its position, rectangle
 // constants and charge.
+constexpr int kAccBatch = 2;  // cells per thread and round of the accumulation (4: no faster)
 template <typename T, bool REC>
 __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const SlotLayout &L, int c) {
     extern __shared__ unsigned long long win[];  // [win_side^2]
@@ -101,37 +102,48 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
     const int *sorted = reinterpret_cast<const int *>(base + L.sorted);
     unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
     const int4 *crec = reinterpret_cast<const int4 *>(base + L.crec);
-    for (int s = s0 + threadIdx.x; s < s1; s += kBlock) {
-        const int i = sorted[s];
-        RectQ q;
-        long long rq;
-        const int4 rec = REC ? crec[i] : make_int4(0, 0, -1, 0);
-        if (rec.z >= 0) {
-            q.l = rec.x;
-            q.b = rec.y;
-            q.r = rec.x + (rec.z & 0xffff);
-            q.t = rec.y + (rec.z >> 16);
-            rq = rec.w;
-        } else {
-            const vec2<T> p = pos[i];
-            const int4 cc = nd.cq[i];
-            if (is_big(nd, cc)) continue;  // scattered by a block of its own
-            q = cell_rect_b<T>(nd, p.x, p.y, cc);
-            rq = nd.rq[i];
-        }
-        if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
-        const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
-        const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
-        const bool inside = j0 >= j00 && j1 < j00 + ws && k0 >= k00 && k1 < k00 + ws;
-        for (int k = k0; k <= k1; ++k) {
-            const long long oy = overlap_b(q.b, q.t, k, nd.hq);
-            for (int j = j0; j <= j1; ++j) {
-                const long long ox = overlap_b(q.l, q.r, j, nd.bq);
-                const unsigned long long c = (unsigned long long)(rq * ox * oy);
-                if (inside)
-                    atomicAdd(&win[(k - k00) * ws + (j - j00)], c);
-                else  // moved out of the window since the order was built
-                    atomicAdd(&rho[(size_t)k * nd.mx + j], c);
+    // kAccBatch cells per thread and round: their ids, then their records, all in flight
+    // together (indices clamped into the chunk; only cells in it add charge)
+    for (int s = s0 + threadIdx.x; s < s1; s += kAccBatch * kBlock) {
+        int ids[kAccBatch];
+        int4 recs[kAccBatch];
+#pragma unroll
+        for (int u = 0; u < kAccBatch; ++u) ids[u] = sorted[min(s + u * kBlock, s1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kAccBatch; ++u) recs[u] = REC ? crec[ids[u]] : make_int4(0, 0, -1, 0);
+        for (int u = 0; u < kAccBatch; ++u) {
+            if (s + u * kBlock >= s1) break;
+            const int i = ids[u];
+            const int4 rec = recs[u];
+            RectQ q;
+            long long rq;
+            if (rec.z >= 0) {
+                q.l = rec.x;
+                q.b = rec.y;
+                q.r = rec.x + (rec.z & 0xffff);
+                q.t = rec.y + (rec.z >> 16);
+                rq = rec.w;
+            } else {
+                const vec2<T> p = pos[i];
+                const int4 cc = nd.cq[i];
+                if (is_big(nd, cc)) continue;  // scattered by a block of its own
+                q = cell_rect_b<T>(nd, p.x, p.y, cc);
+                rq = nd.rq[i];
+            }
+            if (q.r <= q.l || q.t <= q.b) continue;  // clipped away: no charge
+            const int j0 = q.l / nd.bq, j1 = (q.r - 1) / nd.bq;
+            const int k0 = q.b / nd.hq, k1 = (q.t - 1) / nd.hq;
+            const bool inside = j0 >= j00 && j1 < j00 + ws && k0 >= k00 && k1 < k00 + ws;
+            for (int k = k0; k <= k1; ++k) {
+                const long long oy = overlap_b(q.b, q.t, k, nd.hq);
+                for (int j = j0; j <= j1; ++j) {
+                    const long long ox = overlap_b(q.l, q.r, j, nd.bq);
+                    const unsigned long long c = (unsigned long long)(rq * ox * oy);
+                    if (inside)
+                        atomicAdd(&win[(k - k00) * ws + (j - j00)], c);
+                    else  // moved out of the window since the order was built
+                        atomicAdd(&rho[(size_t)k * nd.mx + j], c);
+                }
             }
         }
     }
