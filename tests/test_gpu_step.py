@@ -31,6 +31,8 @@ _NETS = {
     # grid keeps the oracle cheap
     "big300k": lambda: netgen.make_small(300_000, 313_500, 128, seed=5, n_fixed=40),
     "mid": lambda: netgen.make_netlist("mid", 0),
+    # the full large workload (2.2 M movable cells), in the closing-reduction form it runs in
+    "large": lambda: netgen.make_netlist("large", 0),
 }
 _cache = {}
 
@@ -50,7 +52,7 @@ def _ulp(v, prec):
 
 @pytest.mark.parametrize("case,prec,forced", [
     ("small", 32, False), ("small", 32, True), ("small", 64, True), ("tiny", 64, False),
-    ("big300k", 32, False), ("big300k", 64, False), ("mid", 32, False)])
+    ("big300k", 32, False), ("big300k", 64, False), ("mid", 32, False), ("large", 32, False)])
 def test_step_parity_on_device_gradient(hy, orc, case, prec, forced):
     nl, pl, o = setup(hy, orc, case, prec)
     n = nl.n_movable
