@@ -62,28 +62,46 @@ def test_shared_launch_executor_equals_alone():
 
 
 def test_many_jobs_in_flight_have_streams_of_their_own():
-    """Forty jobs in flight at once, each capturing graph blocks on its stream.  torch's
-    Stream() repeats its pooled streams after 32, so two live jobs would share one (and one's
-    capture would meet the other's work); each job's own stream is distinct from every other
-    live one, and every job still ends with its alone HPWL_q."""
+    """Forty placers alive at once, each on a stream of its own, iterating with graph capture
+    at the same time.  torch's Stream() repeats its pooled streams after 32, so two of them
+    would share one (and one's capture would meet the other's work); OwnStreams are distinct,
+    and every job ends with its alone HPWL_q."""
+    import threading
+
     import torch
 
     from paper_2402_18311_amd import hybro as hy
-    assert len({torch.cuda.Stream().cuda_stream for _ in range(40)}) <= 32  # the pool
-    own = [hy.OwnStream() for _ in range(40)]
-    try:
-        assert len({s.cuda_stream for s in own}) == 40 and all(s.cuda_stream for s in own)
-    finally:
-        for s in own:
-            s.close()
-    jobs = serve.make_jobs(40, 2_000, 20_000, 40, seed=9)
+    n = 40
+    assert len({torch.cuda.Stream().cuda_stream for _ in range(n)}) <= 32  # the pool
+    jobs = serve.make_jobs(n, 2_000, 20_000, 40, seed=9)
     for j in jobs:
         j.nbytes = serve.device_bytes(j.netlist)
     alone = serve.fresh(jobs)
     serve.serve_sequential(alone, serve.run_on_gpu)
+    barrier = threading.Barrier(n, timeout=120)
+    handles = []
+
+    def run(job):  # as serve.run_on_gpu, held until every placer exists
+        stream = hy.OwnStream()
+        try:
+            pl = hy.Placer(job.netlist, precision=32, stream=stream)
+            try:
+                nl = job.netlist
+                s = pl.new_slot()
+                pl.set_positions(s, nl.x0, nl.y0)
+                pl.set_schedule(s, 1e-4, 4.0, job.iters)
+                handles.append(stream.cuda_stream)
+                barrier.wait()
+                pl.iterate(s, 4 * nl.bin_w, job.iters, hpwl="last", graph=True)
+                job.hpwl_q = int(pl.hpwl(s)[0])
+                pl.free_slot(s)
+            finally:
+                pl.close()
+        finally:
+            stream.close()
     mixed = serve.fresh(jobs)
-    sch = serve.Scheduler(sum(j.nbytes for j in jobs), serve.run_on_gpu)  # all admitted at once
+    sch = serve.Scheduler(sum(j.nbytes for j in jobs), run)  # all admitted at once
     sch.serve(mixed)
-    assert sch.peak_jobs > 32, sch.peak_jobs
+    assert sch.peak_jobs == n and len(set(handles)) == n and all(handles)
     for a, b in zip(alone, mixed):
         assert a.hpwl_q is not None and a.hpwl_q == b.hpwl_q, a.jid
