@@ -85,7 +85,9 @@ size_t hp_netlist_bytes(const hp_ctx *ctx, const hp_shape *shape, const hp_die *
 size_t hp_slot_bytes(const hp_ctx *ctx, const hp_shape *shape, const hp_die *die);
 
 /* Netlist N = (V, E) of Sec. 3 as a net -> pin CSR.  Host arrays are read during the call
- * and not kept.  cell_w/cell_h [n_cells] (> 0 for movable cells, >= 0 for fixed; zero-area
+ * and not kept.  At least one movable cell (n_movable >= 1; a netlist with nothing to place
+ * is HP_EINVAL, and hp_netlist_bytes / hp_slot_bytes return 0 for its shape).
+ * cell_w/cell_h [n_cells] (> 0 for movable cells, >= 0 for fixed; zero-area
  * fixed cells are pads); fixed_x/fixed_y [n_cells - n_movable] lower-left of fixed cells;
  * net_start [n_nets + 1] non-decreasing, net_start[0] = 0, net_start[n_nets] = n_pins;
  * pin_cell [n_pins] in [0, n_cells); pin_ox/pin_oy [n_pins]; net_weight [n_nets] or NULL

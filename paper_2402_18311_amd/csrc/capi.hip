@@ -364,6 +364,7 @@ int check_shape(const hp_shape *s) {
     if (s->n_cells < 0 || s->n_movable < 0 || s->n_movable > s->n_cells || s->n_nets < 0 ||
         s->n_pins < 0)
         return fail(HP_EINVAL, "bad shape counts");
+    if (s->n_movable == 0) return fail(HP_EINVAL, "no movable cell: nothing to place");
     return HP_OK;
 }
 

@@ -1,6 +1,7 @@
 """Degenerate inputs through the C ABI, against the FP64 oracle: no net with two pins, the
-smallest bin grid (8 x 8), nets among fixed objects only, and one net over every movable cell
-(the block-per-net path).  Bars as in test_gpu_parity: integer outputs bit for bit; FP32 totals
+smallest bin grid (8 x 8), nets among fixed objects only, one net over every movable cell
+(the block-per-net path), and one cell on some fifty nets (its pin gradients over many
+batches).  An empty placement (no movable cell) is refused at load.  Bars as in test_gpu_parity: integer outputs bit for bit; FP32 totals
 to 1e-5 relative and gradients / fields to 1e-4 relative L2; FP64 to 1e-10."""
 import dataclasses
 
@@ -46,11 +47,22 @@ def _one_net_over_all(nl):
     return _with_nets(nl, [np.arange(nl.n_movable)], seed=12)
 
 
+def _hub_cell(nl):
+    """Cell 0 on 37 more two-pin nets and 4 wider ones: its pin gradients are gathered over
+    many batches with a ragged last one."""
+    rng = np.random.default_rng(13)
+    others = rng.choice(np.arange(1, nl.n_movable), size=37 + 4 * 5, replace=False)
+    nets = [[0, int(c)] for c in others[:37]]
+    nets += [[0] + [int(c) for c in others[37 + 5 * k:37 + 5 * k + 5]] for k in range(4)]
+    return _with_nets(nl, nets, seed=14)
+
+
 CASES = {
     "single_pin_nets": lambda: _single_pin_nets(netgen.make_netlist("tiny", 0)),
     "grid_8x8": lambda: netgen.make_small(300, 320, 8, seed=5, n_fixed=4),
     "fixed_only_nets": lambda: _fixed_only_nets(netgen.make_netlist("tiny", 0)),
     "one_net_over_all": lambda: _one_net_over_all(netgen.make_netlist("tiny", 0)),
+    "hub_cell": lambda: _hub_cell(netgen.make_netlist("tiny", 0)),
 }
 
 
@@ -91,6 +103,10 @@ def test_degenerate_netlists_match_oracle(orc, case, prec):
         g = np.concatenate([gx.cpu().numpy()[0], gy.cpu().numpy()[0]])
         gref = np.concatenate([ref["gwx"] + lam * ref["gdx"], ref["gwy"] + lam * ref["gdy"]])
         assert rel_l2(g, gref) < tol["l2"]
+        if case == "hub_cell":  # the cell with the most pins, on its own
+            n = nl.n_movable
+            for k in (0, n):
+                assert abs(g[k] - gref[k]) <= tol["l2"] * max(1.0, abs(gref[k])), (k, g[k], gref[k])
         # a few placer iterations, then the exact HPWL of the device's placement
         pl.set_schedule(s, 1e-4, 4.0, 50)
         pl.iterate(s, gamma, 7, hpwl=True)
@@ -120,6 +136,11 @@ def _bad(kind):
         return dataclasses.replace(nl, mx=48)
     if kind == "die_too_large":
         return dataclasses.replace(nl, W=20000.0, H=20000.0)
+    if kind == "no_movable_cells":  # every cell fixed where it starts: nothing to place
+        n = nl.n_movable
+        return dataclasses.replace(nl, n_movable=0, fixed_x=np.concatenate([nl.x0, nl.fixed_x]),
+                                   fixed_y=np.concatenate([nl.y0, nl.fixed_y]),
+                                   x0=np.zeros(0), y0=np.zeros(0)) if n else nl
     if kind == "cell_wider_than_die":
         w = nl.cell_w.copy()
         w[0] = nl.W * 2
@@ -129,7 +150,7 @@ def _bad(kind):
 
 @pytest.mark.parametrize("kind", ["net_start_decreasing", "pin_cell_out_of_range",
                                   "offset_not_finite", "bins_not_power_of_two", "die_too_large",
-                                  "cell_wider_than_die"])
+                                  "cell_wider_than_die", "no_movable_cells"])
 def test_invalid_netlists_are_rejected(kind):
     """Load-time validation on the host: a bad netlist or die is refused with HP_EINVAL and a
     message, before any device work."""
