@@ -313,6 +313,24 @@ def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
         for s in slots:
             pl.free_slot(s)
     c1, r1 = hy.hp_graph_stats(pl.ctx)
+    # the kernel split of a batched iteration: the same restarts, 20 iterations with events on
+    # every launch after 5 untimed ones (a separate pass; the timed modes above carry none)
+    slots = [pl.new_slot() for _ in range(K)]
+    for k, s in enumerate(slots):
+        pl.set_positions(s, ix, iy)
+        pl.set_schedule(s, 1e-4, 4.0, T)
+        pl.perturb(s, hy.HP_PERTURB_GAUSS, 0.05, 8.0, seed0 + k, want_idx=False)
+    pl.iterate(slots, gamma, 5, hpwl=False)
+    hy.hp_profile_enable(pl.ctx, True)
+    hy.hp_profile_read(pl.ctx, reset=True)
+    pl.iterate(slots, gamma, 20, hpwl=False)
+    prof = hy.hp_profile_read(pl.ctx, reset=True)
+    hy.hp_profile_enable(pl.ctx, False)
+    for s in slots:
+        pl.free_slot(s)
+    split = {k: {"launches": c, "avg_us": round(1e3 * ms / max(c, 1), 2),
+                 "us_per_iteration": round(1e3 * ms / 20, 2)}
+             for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
     return {"restarts": K, "iterations": T,
             "batched_restarts_per_s": round(res["batched"][0], 3),
             "graph_restarts_per_s": round(res["graph"][0], 3),
@@ -324,6 +342,7 @@ def batched_round(pl, hy, nl, gamma, inc, K, T, seed0):
             "graph_blocks": {"captured": c1 - c0, "replayed": r1 - r0},
             "equal_hpwl": res["batched"][2] == res["plain"][2] == res["graph"][2],
             "best_hpwl": min(res["batched"][2]) / 65536,
+            "kernels_per_batched_iteration": split,
             "hpwl": "exact HPWL of each restart after its last iteration (Alg. 1)"}
 
 
