@@ -1274,7 +1274,7 @@ int iterate_multi(hp_ctx *ctx, const std::vector<int32_t> &sl, const std::vector
                 cs_x = std::max(cs_x, colscan_blocks(N.nd));
                 pl_x = std::max(pl_x, N.nd.sort_blocks);
                 ac_x = std::max(ac_x, N.nd.max_chunks);
-                l_pl = std::max(l_pl, scatter_count_lds(N.nd));
+                l_pl = std::max(l_pl, scatter_place_lds(N.nd));
                 l_ac = std::max(l_ac, scatter_accum_lds(N.nd));
             } else {
                 accm |= 1u << i;

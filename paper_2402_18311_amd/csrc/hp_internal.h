@@ -251,6 +251,7 @@ template <typename T>
 hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotLayout &L,
                                bool accum, bool records, hipStream_t st);
 size_t scatter_count_lds(const NetDev &nd);
+size_t scatter_place_lds(const NetDev &nd);  // the placement pass: ranks and tile starts
 size_t scatter_accum_lds(const NetDev &nd);
 // Big cells (one block per cell and slot; their charge is scattered in the first launch):
 // the wirelength and density parts of their gradient written to g and gd (read back by the

@@ -23,16 +23,18 @@
 
 namespace hp {
 
-// The scan of a regroup, in two launches.
+// The scan of a regroup: column scans in a launch of their own, then the tile scan inside
+// every placement block.
 //
 // 1. Column scans (many blocks): a block takes 16 tiles; each tile's column of per-block counts
 //    (sort_blocks <= 512 rows) is split into 16 bands of <= 32 rows, one thread per band, whose
 //    counts are loaded in one round and kept in registers.  The band sums are scanned in LDS,
 //    every (block, tile) gets its exclusive offset within the tile, and the tile's total goes
 //    to tstart[t].
-// 2. Tile scan (one block): exclusive scans of the tile totals and of their chunk counts
-//    (ceil(cells / kChunk) per tile) give the tile starts, chunk starts and each chunk's tile
-//    and cell range.
+// 2. Tile scan (in each placement block, so no launch of its own): exclusive scans of the tile
+//    totals and of their chunk counts (ceil(cells / kChunk) per tile) give the tile starts,
+//    which the block places by, and the chunk starts and each chunk's tile and cell range,
+//    which each block writes for its share of the tiles.
 constexpr int kColTiles = 16, kColBands = kBlock / kColTiles, kColRows = 32;
 template <bool RAG>
 __global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
@@ -79,27 +81,42 @@ __global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nda, SlotArg
     }
 }
 
-constexpr int kScanThreads = 1024;
 template <bool RAG>
-__global__ __launch_bounds__(kScanThreads) void bin_tilescan_kernel(NetDev nda, SlotArgs sa,
-                                                                    SlotLayout La) {
-    __shared__ int ws[kScanThreads / 64][2];
+__global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
+    extern __shared__ int place_lds[];  // rank [ntiles], then the tile starts [ntiles]
+    __shared__ int ws[kBlock / 64][2];
     char *base = sa.base[blockIdx.y];
     const NetDev &nd = view_nd<RAG>(nda, base);
     const SlotLayout &L = view_L<RAG>(La, base);
-    int *tstart = reinterpret_cast<int *>(base + L.tstart);
+    if (RAG && (int)blockIdx.x >= nd.sort_blocks) return;  // past the slot's own blocks
+    const int T = nd.ntiles, nb = nd.sort_blocks, blk = blockIdx.x;
+    int *rank = place_lds, *hs = place_lds + T;
+    const int *tot = reinterpret_cast<const int *>(base + L.tstart);  // tile totals
     int *cstart = reinterpret_cast<int *>(base + L.cstart);
     int4 *chunk = reinterpret_cast<int4 *>(base + L.chunk);
-    const int T = nd.ntiles;
-    const int per = (T + kScanThreads - 1) / kScanThreads;
-    const int t0 = threadIdx.x * per, t1 = min(T, t0 + per);
-    int sc = 0, sk = 0;  // this thread's cells and chunks
+    // the totals in rounds of eight loads per thread, all in flight before any is stored
+    for (int t = threadIdx.x; t < T; t += 8 * kBlock) {
+        int v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = tot[min(t + u * kBlock, T - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t + u * kBlock < T) {
+                rank[t + u * kBlock] = 0;
+                hs[t + u * kBlock] = v[u];
+            }
+    }
+    __syncthreads();
+    // the tile scan: each thread a contiguous run of tiles, its (cells, chunks) sums scanned
+    // over the block
+    const int per = (T + kBlock - 1) / kBlock;
+    const int t0 = min(T, (int)threadIdx.x * per), t1 = min(T, t0 + per);
+    int sc = 0, sk = 0;
     for (int t = t0; t < t1; ++t) {
-        const int s = tstart[t];  // the tile's total (from the column scans)
+        const int s = hs[t];
         sc += s;
         sk += (s + kChunk - 1) / kChunk;
     }
-    // exclusive scan of (sc, sk) over the threads
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int ic = sc, ik = sk;
 #pragma unroll
@@ -120,45 +137,36 @@ __global__ __launch_bounds__(kScanThreads) void bin_tilescan_kernel(NetDev nda, 
         oc += ws[i][0];
         ok += ws[i][1];
     }
+    // tile starts for this block's placement; the chunk tables of this block's share of the
+    // tiles for the accumulation (every tile's entries written by exactly one block)
+    const int w0 = (int)((long long)blk * T / nb), w1 = (int)((long long)(blk + 1) * T / nb);
     for (int t = t0; t < t1; ++t) {
-        const int s = tstart[t], nck = (s + kChunk - 1) / kChunk;
-        tstart[t] = oc;
-        cstart[t] = ok;
-        for (int c = 0; c < nck; ++c)  // each chunk's tile and cell range, for the accumulation
-            chunk[ok + c] = make_int4(t, oc + c * kChunk, min(oc + s, oc + (c + 1) * kChunk), 0);
+        const int s = hs[t], nck = (s + kChunk - 1) / kChunk;
+        hs[t] = oc;
+        if (t >= w0 && t < w1) {
+            cstart[t] = ok;
+            for (int c = 0; c < nck; ++c)
+                chunk[ok + c] = make_int4(t, oc + c * kChunk, min(oc + s, oc + (c + 1) * kChunk), 0);
+        }
         oc += s;
         ok += nck;
     }
-    if (threadIdx.x == kScanThreads - 1) {
-        tstart[T] = oc;
-        cstart[T] = ok;
-    }
-}
-
-template <bool RAG>
-__global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
-    extern __shared__ int rank[];  // [ntiles]
-    char *base = sa.base[blockIdx.y];
-    const NetDev &nd = view_nd<RAG>(nda, base);
-    const SlotLayout &L = view_L<RAG>(La, base);
-    if (RAG && (int)blockIdx.x >= nd.sort_blocks) return;  // past the slot's own blocks
-    for (int t = threadIdx.x; t < nd.ntiles; t += kBlock) rank[t] = 0;
+    if (blk == nb - 1 && threadIdx.x == kBlock - 1) cstart[T] = ok;  // the chunk count
     __syncthreads();
     const int *tile = reinterpret_cast<const int *>(base + L.tile);
-    const int *cnt = reinterpret_cast<const int *>(base + L.soff) + (size_t)blockIdx.x * nd.ntiles;
-    const int *tstart = reinterpret_cast<const int *>(base + L.tstart);
+    const int *cnt = reinterpret_cast<const int *>(base + L.soff) + (size_t)blk * T;
     int *sorted = reinterpret_cast<int *>(base + L.sorted);
-    const int i0 = blockIdx.x * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
+    const int i0 = blk * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
     // four cells per thread and round: tiles, then ranks, then offsets, each step's accesses
     // all in flight together (indices clamped in range; only valid cells take a rank)
     for (int i = i0 + threadIdx.x; i < i1; i += 4 * kBlock) {
-        int t[4], r[4], o[4];
+        int tt[4], r[4], o[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = tile[min(i + u * kBlock, i1 - 1)];
+        for (int u = 0; u < 4; ++u) tt[u] = tile[min(i + u * kBlock, i1 - 1)];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = i + u * kBlock < i1 ? atomicAdd(&rank[t[u]], 1) : 0;
+        for (int u = 0; u < 4; ++u) r[u] = i + u * kBlock < i1 ? atomicAdd(&rank[tt[u]], 1) : 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) o[u] = tstart[t[u]] + cnt[t[u]];
+        for (int u = 0; u < 4; ++u) o[u] = hs[tt[u]] + cnt[tt[u]];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (i + u * kBlock < i1) sorted[o[u] + r[u]] = i + u * kBlock;
@@ -175,6 +183,7 @@ __global__ __launch_bounds__(kBlock) void bin_accum_kernel(NetDev nda, SlotArgs 
 }
 
 size_t scatter_count_lds(const NetDev &nd) { return sizeof(int) * (size_t)nd.ntiles; }
+size_t scatter_place_lds(const NetDev &nd) { return 2 * sizeof(int) * (size_t)nd.ntiles; }
 size_t scatter_accum_lds(const NetDev &nd) {
     return sizeof(unsigned long long) * (size_t)nd.win_side * nd.win_side;
 }
@@ -188,12 +197,8 @@ hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotL
               dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_tilescan_kernel", bin_tilescan_kernel<false>, dim3(1, sa.n), dim3(kScanThreads), 0, st, nd,
-              sa, L);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
     HP_LAUNCH("bin_place_kernel", bin_place_kernel<false>, dim3(nd.sort_blocks, sa.n), dim3(kBlock),
-              scatter_count_lds(nd), st, nd, sa, L);
+              scatter_place_lds(nd), st, nd, sa, L);
     e = hipGetLastError();
     if (e != hipSuccess || !accum) return e;
     if (records)
@@ -215,10 +220,6 @@ hipError_t rag_regroup_tail(const SlotArgs &sa, int colscan_x, int place_x, int 
     HP_LAUNCH("bin_colscan_kernel", bin_colscan_kernel<true>, dim3(colscan_x, sa.n), dim3(kBlock),
               0, st, nd0, sa, L0);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_tilescan_kernel", bin_tilescan_kernel<true>, dim3(1, sa.n), dim3(kScanThreads),
-              0, st, nd0, sa, L0);
-    e = hipGetLastError();
     if (e != hipSuccess) return e;
     HP_LAUNCH("bin_place_kernel", bin_place_kernel<true>, dim3(place_x, sa.n), dim3(kBlock),
               place_lds, st, nd0, sa, L0);
