@@ -81,6 +81,10 @@ __global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nda, SlotArg
     }
 }
 
+// tiles per thread of the placement pass's scan: the tile grid has at most 8192 tiles (the tile
+// side doubles until it does, or reaches the grid's short side, where at most 2048 / 8 remain)
+constexpr int kPlaceRun = 32;
+static_assert(kBlock * kPlaceRun >= 8192, "the placement pass's scan covers every tile");
 template <bool RAG>
 __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
     extern __shared__ int place_lds[];  // rank [ntiles], then the tile starts [ntiles]
@@ -94,28 +98,20 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs 
     const int *tot = reinterpret_cast<const int *>(base + L.tstart);  // tile totals
     int *cstart = reinterpret_cast<int *>(base + L.cstart);
     int4 *chunk = reinterpret_cast<int4 *>(base + L.chunk);
-    // the totals in rounds of eight loads per thread, all in flight before any is stored
-    for (int t = threadIdx.x; t < T; t += 8 * kBlock) {
-        int v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = tot[min(t + u * kBlock, T - 1)];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (t + u * kBlock < T) {
-                rank[t + u * kBlock] = 0;
-                hs[t + u * kBlock] = v[u];
-            }
-    }
-    __syncthreads();
-    // the tile scan: each thread a contiguous run of tiles, its (cells, chunks) sums scanned
-    // over the block
+    // the tile scan: each thread a contiguous run of at most kPlaceRun tiles (ntiles <= 8192),
+    // its totals loaded into registers in one round, its (cells, chunks) sums scanned over the
+    // block
     const int per = (T + kBlock - 1) / kBlock;
     const int t0 = min(T, (int)threadIdx.x * per), t1 = min(T, t0 + per);
+    int v[kPlaceRun];
+#pragma unroll
+    for (int k = 0; k < kPlaceRun; ++k) v[k] = (k < per && t0 + k < t1) ? tot[t0 + k] : 0;
+    for (int t = threadIdx.x; t < T; t += kBlock) rank[t] = 0;
     int sc = 0, sk = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int s = hs[t];
-        sc += s;
-        sk += (s + kChunk - 1) / kChunk;
+#pragma unroll
+    for (int k = 0; k < kPlaceRun; ++k) {
+        sc += v[k];
+        sk += (v[k] + kChunk - 1) / kChunk;
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int ic = sc, ik = sk;
@@ -140,13 +136,16 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs 
     // tile starts for this block's placement; the chunk tables of this block's share of the
     // tiles for the accumulation (every tile's entries written by exactly one block)
     const int w0 = (int)((long long)blk * T / nb), w1 = (int)((long long)(blk + 1) * T / nb);
-    for (int t = t0; t < t1; ++t) {
-        const int s = hs[t], nck = (s + kChunk - 1) / kChunk;
-        hs[t] = oc;
-        if (t >= w0 && t < w1) {
-            cstart[t] = ok;
+#pragma unroll
+    for (int k = 0; k < kPlaceRun; ++k) {
+        const int tk = t0 + k;
+        if (k >= per || tk >= t1) break;
+        const int s = v[k], nck = (s + kChunk - 1) / kChunk;
+        hs[tk] = oc;
+        if (tk >= w0 && tk < w1) {
+            cstart[tk] = ok;
             for (int c = 0; c < nck; ++c)
-                chunk[ok + c] = make_int4(t, oc + c * kChunk, min(oc + s, oc + (c + 1) * kChunk), 0);
+                chunk[ok + c] = make_int4(tk, oc + c * kChunk, min(oc + s, oc + (c + 1) * kChunk), 0);
         }
         oc += s;
         ok += nck;
