@@ -119,7 +119,7 @@ static bool q16_exact(double v) {
 }
 
 struct NetBuf {
-    size_t net_start, pin_cell, pin_off, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
+    size_t net_start, pin_cell, pin_off, pin_off16, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
         cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh,
         big_ids, cell_pin_net, sweep_map, total;
 };
@@ -139,6 +139,7 @@ NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     put(b.pin_cell, 4 * PS);
     put(b.pin_off, 2 * rs * PS);
     put(b.pin_offq, 8 * PS);
+    put(b.pin_off16, 4 * PS);
     put(b.net_w, rs * E);
     put(b.cell_pin_start, 4 * (Nm + 1));
     put(b.cell_pins, 4 * P);
@@ -611,10 +612,50 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
         if (!ex) all_exact = false;
     });
     const bool offq_exact = all_exact;
+    // the compact offsets: the finest power-of-two unit 2^-s (s <= 15) of which every offset is
+    // a multiple, if every offset then fits an int16; the sweeps decode them to the same values
+    int off16_shift = -1;
+    {
+        // per value: a multiple of 2^-15 of magnitude below 2^52 (else no compaction), needing
+        // 15 - (trailing zero bits of its 2^-15 count) fractional bits
+        std::mutex mu;
+        int need = 0;
+        double amax = 0.0;
+        std::atomic<bool> ok{true};
+        parallel_ranges(P, [&](int64_t lo, int64_t hi) {
+            int nd_ = 0;
+            double am = 0.0;
+            for (int64_t p = lo; p < hi && ok.load(std::memory_order_relaxed); ++p)
+                for (const double o : {pin_ox[p], pin_oy[p]}) {
+                    const double q = std::ldexp(o, 15);
+                    if (!(std::fabs(q) < 0x1p52) || q != std::nearbyint(q)) {
+                        ok = false;
+                        break;
+                    }
+                    const long long qi = std::llabs(std::llrint(q));
+                    if (qi) nd_ = std::max(nd_, 15 - std::min(15, __builtin_ctzll((unsigned long long)qi)));
+                    am = std::max(am, std::fabs(o));
+                }
+            std::lock_guard<std::mutex> lk(mu);
+            need = std::max(need, nd_);
+            amax = std::max(amax, am);
+        });
+        if (ok && std::ldexp(amax, need) <= 32767.0) off16_shift = need;
+    }
+    std::vector<int32_t> h_po16;
+    if (off16_shift >= 0) {
+        h_po16.assign(ps, 0);
+        for (int q = 0; q < ps; ++q) {
+            const int x = (int)std::llrint(std::ldexp((double)h_po[2 * (size_t)q], off16_shift));
+            const int y = (int)std::llrint(std::ldexp((double)h_po[2 * (size_t)q + 1], off16_shift));
+            h_po16[q] = (int32_t)(((uint32_t)(uint16_t)(int16_t)y << 16) | (uint16_t)(int16_t)x);
+        }
+    }
     if (any_w)
         for (int i = 0; i < ns; ++i) h_w.push_back((T)net_weight[order[i]]);
     nd.ps = ps;
     nd.offq_exact = offq_exact ? 1 : 0;
+    nd.off16_shift = off16_shift;
     if ((size_t)ps > sweep_slots_bound(S)) return fail(HP_EINVAL, "internal: sweep slot bound");
 
     // cell -> sweep-pin CSR (movable cells), and pin counts over all nets for the
@@ -752,6 +793,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     HP_CHECK(up(B.pin_cell, h_pc.data(), 4 * h_pc.size()));
     HP_CHECK(up(B.pin_off, h_po.data(), sizeof(T) * h_po.size()));
     HP_CHECK(up(B.pin_offq, h_pq.data(), 4 * h_pq.size()));
+    if (!h_po16.empty()) HP_CHECK(up(B.pin_off16, h_po16.data(), 4 * h_po16.size()));
     if (any_w) HP_CHECK(up(B.net_w, h_w.data(), sizeof(T) * h_w.size()));
     HP_CHECK(up(B.cell_pin_start, h_cps.data(), 4 * h_cps.size()));
     HP_CHECK(up(B.cell_pins, h_cp.data(), 4 * h_cp.size()));
@@ -778,6 +820,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.pin_cell = reinterpret_cast<const int32_t *>(buf + B.pin_cell);
     nd.pin_off = buf + B.pin_off;
     nd.pin_offq = reinterpret_cast<const int2 *>(buf + B.pin_offq);
+    nd.pin_off16 = reinterpret_cast<const int32_t *>(buf + B.pin_off16);
     nd.net_w = any_w ? buf + B.net_w : nullptr;
     nd.cell_pin_start = reinterpret_cast<const int32_t *>(buf + B.cell_pin_start);
     nd.cell_pins = reinterpret_cast<const int32_t *>(buf + B.cell_pins);

@@ -85,6 +85,9 @@ struct NetDev {
     int32_t stretch;               // small cells' charge spread over >= sqrt(2) bins per side
     int32_t offq_exact;            // every pin_off (in T) is a multiple of 2^-16: pin_offq is
                                    // pin_off * 2^16 exactly, and the sweeps form it from pin_off
+    const int32_t *pin_off16;      // [ps] the offsets as two int16 (x low, y high) in units of
+    int32_t off16_shift;           // 2^-off16_shift, when every offset is such a multiple that
+                                   // fits (-1 otherwise): the sweeps read 4 bytes a slot, not 8
     // big cells: w'q >= big_wq or h'q >= big_hq (their footprint can span more than
     // kBigHalo + 1 bins) or w'q h'q >= big_aq; the halo above covers the other cells only
     const int32_t *big_ids;        // [n_big] ascending movable ids

@@ -33,7 +33,15 @@ namespace hp {
 // 2^-16 (nd.offq_exact), the quantized offset is formed from the float one (the same integer)
 // instead of being loaded.
 
-// Four consecutive pin slots (slot a multiple of 4): cell ids and offsets by 16-byte loads.
+// One slot's compact offset (two int16 in units of 2^-off16_shift) as T: the same value as the
+// full-width offset, exactly (an int16 times a power of two).
+template <typename T>
+__device__ __forceinline__ vec2<T> off16(int32_t w, T unit) {
+    return cmk2<T>((T)(int)(int16_t)(w & 0xffff) * unit, (T)(w >> 16) * unit);
+}
+
+// Four consecutive pin slots (slot a multiple of 4): cell ids and offsets by 16-byte loads
+// (one for the offsets when they are compact).
 template <typename T>
 __device__ __forceinline__ void load_slots4(const NetDev &nd, int slot, int (&c)[4],
                                             vec2<T> (&o)[4]) {
@@ -42,6 +50,15 @@ __device__ __forceinline__ void load_slots4(const NetDev &nd, int slot, int (&c)
     c[1] = cc.y;
     c[2] = cc.z;
     c[3] = cc.w;
+    if (nd.off16_shift >= 0) {
+        const int4 w = *reinterpret_cast<const int4 *>(nd.pin_off16 + slot);
+        const T unit = (T)ldexp(1.0, -nd.off16_shift);
+        o[0] = off16<T>(w.x, unit);
+        o[1] = off16<T>(w.y, unit);
+        o[2] = off16<T>(w.z, unit);
+        o[3] = off16<T>(w.w, unit);
+        return;
+    }
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off) + slot;
     if constexpr (sizeof(T) == 4) {
         const float4 a = *reinterpret_cast<const float4 *>(off);
@@ -95,6 +112,7 @@ __device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, in
     constexpr int R = kPairNets;
     const int net0 = bk.net0[b], net1 = bk.net1[b], pin0 = bk.pin0[b];
     const vec2<T> *off = reinterpret_cast<const vec2<T> *>(nd.pin_off);
+    const T unit = (T)ldexp(1.0, -max(nd.off16_shift, 0));
     int net[R], slot[R];
     int2 c[R];
     vec2<T> o0[R], o1[R];
@@ -103,7 +121,11 @@ __device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, in
         net[r] = net0 + (local * R + r) * kBlock + (int)threadIdx.x;
         slot[r] = pin0 + (net[r] < net1 ? 2 * (net[r] - net0) : 0);
         c[r] = *reinterpret_cast<const int2 *>(nd.pin_cell + slot[r]);
-        if constexpr (sizeof(T) == 4) {
+        if (nd.off16_shift >= 0) {
+            const int2 w = *reinterpret_cast<const int2 *>(nd.pin_off16 + slot[r]);
+            o0[r] = off16<T>(w.x, unit);
+            o1[r] = off16<T>(w.y, unit);
+        } else if constexpr (sizeof(T) == 4) {
             const float4 a = *reinterpret_cast<const float4 *>(off + slot[r]);
             o0[r] = cmk2<T>(a.x, a.y);
             o1[r] = cmk2<T>(a.z, a.w);

@@ -1,7 +1,7 @@
 """Degenerate inputs through the C ABI, against the FP64 oracle: no net with two pins, the
 smallest bin grid (8 x 8), nets among fixed objects only, one net over every movable cell
-(the block-per-net path), and one cell on some fifty nets (its pin gradients over many
-batches).  An empty placement (no movable cell) is refused at load.  Bars as in test_gpu_parity: integer outputs bit for bit; FP32 totals
+(the block-per-net path), one cell on some fifty nets (its pin gradients over many
+batches), and pin offsets too fine for the sweep's compact offsets.  An empty placement (no movable cell) is refused at load.  Bars as in test_gpu_parity: integer outputs bit for bit; FP32 totals
 to 1e-5 relative and gradients / fields to 1e-4 relative L2; FP64 to 1e-10."""
 import dataclasses
 
@@ -47,6 +47,13 @@ def _one_net_over_all(nl):
     return _with_nets(nl, [np.arange(nl.n_movable)], seed=12)
 
 
+def _fine_offsets(nl):
+    """Pin offsets at 2^-17 steps: too fine for the sweep's compact (int16) offsets, so the
+    full-width ones are read."""
+    fx = np.minimum(nl.pin_ox + 2.0 ** -17, nl.cell_w[nl.pin_cell])
+    return dataclasses.replace(nl, pin_ox=fx)
+
+
 def _hub_cell(nl):
     """Cell 0 on 37 more two-pin nets and 4 wider ones: its pin gradients are gathered over
     many batches with a ragged last one."""
@@ -63,6 +70,7 @@ CASES = {
     "fixed_only_nets": lambda: _fixed_only_nets(netgen.make_netlist("tiny", 0)),
     "one_net_over_all": lambda: _one_net_over_all(netgen.make_netlist("tiny", 0)),
     "hub_cell": lambda: _hub_cell(netgen.make_netlist("tiny", 0)),
+    "fine_offsets": lambda: _fine_offsets(netgen.make_small(3_000, 3_150, 64, seed=15, n_fixed=8)),
 }
 
 
