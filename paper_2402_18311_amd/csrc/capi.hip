@@ -119,7 +119,7 @@ static bool q16_exact(double v) {
 }
 
 struct NetBuf {
-    size_t net_start, pin_cell, pin_off, pin_off16, pin_offq, net_w, cell_pin_start, cell_pins, cq, rq,
+    size_t net_start, pin_cell, pin_off, pin_off16, pin_offq, net_w, cell_pin_start, cell_pins, cq, cq16, rq,
         cstep, cell_wh, rho_fixed, tw_x, tw_y, ph_x, ph_y, omega, den1, fixed_pos, fxy, fwh,
         big_ids, cell_pin_net, sweep_map, total;
 };
@@ -144,6 +144,7 @@ NetBuf net_layout(const hp_shape &s, const hp_die &d, size_t rs) {
     put(b.cell_pin_start, 4 * (Nm + 1));
     put(b.cell_pins, 4 * P);
     put(b.cq, 16 * Nm);
+    put(b.cq16, 8 * Nm);
     put(b.rq, 4 * Nm);
     put(b.cstep, 4 * rs * Nm);
     put(b.cell_wh, 2 * rs * Nm);
@@ -799,6 +800,25 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     HP_CHECK(up(B.cell_pins, h_cp.data(), 4 * h_cp.size()));
     HP_CHECK(up(B.cell_pin_net, h_cpn.data(), 4 * h_cpn.size()));
     HP_CHECK(up(B.cq, h_cq.data(), 4 * h_cq.size()));
+    // the compact charge constants, when every cell's four values fit an int16 (the host
+    // copy lives to the end of the load, like the others)
+    std::vector<int32_t> h_cq16;
+    {
+        bool fits = true;
+        for (const int32_t v : h_cq) fits = fits && v >= -32768 && v <= 32767;
+        nd.cq_compact = fits ? 1 : 0;
+        if (fits) {
+            h_cq16.assign(2 * (size_t)Nm, 0);
+            for (int i = 0; i < Nm; ++i) {
+                const int32_t *c = &h_cq[4 * (size_t)i];
+                h_cq16[2 * (size_t)i] = (int32_t)(((uint32_t)(uint16_t)(int16_t)c[1] << 16) |
+                                                  (uint16_t)(int16_t)c[0]);
+                h_cq16[2 * (size_t)i + 1] = (int32_t)(((uint32_t)(uint16_t)(int16_t)c[3] << 16) |
+                                                      (uint16_t)(int16_t)c[2]);
+            }
+            HP_CHECK(up(B.cq16, h_cq16.data(), 4 * h_cq16.size()));
+        }
+    }
     HP_CHECK(up(B.rq, h_rq.data(), 4 * h_rq.size()));
     HP_CHECK(up(B.cstep, h_cs.data(), sizeof(T) * h_cs.size()));
     HP_CHECK(up(B.cell_wh, h_wh.data(), sizeof(T) * h_wh.size()));
@@ -825,6 +845,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     nd.cell_pin_start = reinterpret_cast<const int32_t *>(buf + B.cell_pin_start);
     nd.cell_pins = reinterpret_cast<const int32_t *>(buf + B.cell_pins);
     nd.cq = reinterpret_cast<const int4 *>(buf + B.cq);
+    nd.cq16 = reinterpret_cast<const int2 *>(buf + B.cq16);
     nd.rq = reinterpret_cast<const int32_t *>(buf + B.rq);
     nd.cstep = buf + B.cstep;
     nd.cell_wh = buf + B.cell_wh;

@@ -39,7 +39,7 @@ __device__ __forceinline__ int overlap_b(int lo, int hi, int idx, int w) {
 template <typename T>
 __device__ __forceinline__ int cell_tile(const NetDev &nd, const vec2<T> *pos, int i, int4 &rec) {
     const vec2<T> p = pos[i];
-    const int4 cc = nd.cq[i];
+    const int4 cc = cell_cq(nd, i);
     const RectQ q = cell_rect_b<T>(nd, p.x, p.y, cc);
     const int j = min(q.l / nd.bq, nd.mx - 1), k = min(q.b / nd.hq, nd.my - 1);
     const int w = max(q.r - q.l, 0), h = max(q.t - q.b, 0);
@@ -125,7 +125,7 @@ __device__ __forceinline__ void accum_body(const NetDev &nd, char *base, const S
                 rq = rec.w;
             } else {
                 const vec2<T> p = pos[i];
-                const int4 cc = nd.cq[i];
+                const int4 cc = cell_cq(nd, i);
                 if (is_big(nd, cc)) continue;  // scattered by a block of its own
                 q = cell_rect_b<T>(nd, p.x, p.y, cc);
                 rq = nd.rq[i];
@@ -168,7 +168,7 @@ __device__ __forceinline__ void big_scatter_body(const NetDev &nd, char *base, c
     if (k >= nd.n_big) return;  // block-uniform (the range is rounded up)
     const int i = nd.big_ids[k];
     const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-    const RectQ q = cell_rect_b<T>(nd, p.x, p.y, nd.cq[i]);
+    const RectQ q = cell_rect_b<T>(nd, p.x, p.y, cell_cq(nd, i));
     if (q.r <= q.l || q.t <= q.b) return;  // clipped away: no charge
     const long long rq = nd.rq[i];
     const int j0 = q.l / nd.bq, nj = (q.r - 1) / nd.bq - j0 + 1;

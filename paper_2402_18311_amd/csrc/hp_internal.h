@@ -50,6 +50,8 @@ struct NetDev {
     const int32_t *cell_pins;      // sweep-order pins of each movable cell
     const int32_t *cell_pin_net;   // the sweep-order net of each of those pins
     const int4 *cq;                // [n_mov] (w'q, h'q, dxq, dyq) in 2^-12
+    const int2 *cq16;              // [n_mov] the same as four int16 (w'q | h'q << 16, dxq |
+    int32_t cq_compact;            // dyq << 16) when every value fits (1), else 0: read by cell_cq
     const int32_t *rq;             // [n_mov] charge scale in 2^-16
     const void *cstep;             // T [4][n_mov]: pins, area, x max, y max
     const int64_t *rho_fixed;      // [my][mx]
@@ -94,6 +96,17 @@ struct NetDev {
     int32_t n_big, big_wq, big_hq;
     int64_t big_aq;
 };
+
+// Cell i's charge constants (w'q, h'q, dxq, dyq), from their compact form when the netlist has
+// one (8 bytes instead of 16; the same integers).
+__device__ __forceinline__ int4 cell_cq(const NetDev &nd, int i) {
+    if (nd.cq_compact) {
+        const int2 w = nd.cq16[i];
+        return make_int4((int)(int16_t)(w.x & 0xffff), w.x >> 16, (int)(int16_t)(w.y & 0xffff),
+                         w.y >> 16);
+    }
+    return nd.cq[i];
+}
 
 __host__ __device__ inline bool is_big(const NetDev &nd, int4 c) {
     return c.x >= nd.big_wq || c.y >= nd.big_hq || (int64_t)c.x * c.y >= nd.big_aq;

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void big_grad_kernel(NetDev nda, SlotArgs s
         for (int b = threadIdx.x; b < nj * nk; b += kBlock)
             exact_term<T>(nd, e, psi, e.j0 + b % nj, e.k0 + b / nj, s[2], s[3]);
     } else {
-        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
+        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, cell_cq(nd, i));
         if (q.r > q.l && q.t > q.b) {
             const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
             const double rqd = (double)nd.rq[i] * 0x1p-40;
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
         // batch with the next batch's indices.  Sums keep pin order and row-major bin order.
         const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
         const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
-        const int4 cc = nd.cq[i];
+        const int4 cc = cell_cq(nd, i);
         const bool big = is_big(nd, cc);  // both parts already reduced by its own block
         const int e = nd.cell_pin_start[i + 1];
         // no wirelength part in a density-only evaluation (the sweep did not run)
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void counted_scatter_kernel(NetDev nd, char
     if (i == 0) scalars(base, L)->ovf_tmp = 0;
     if (i >= n_counted) return;
     const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
-    const RectQ q = cell_rect_i<T>(nd, p.x, p.y, nd.cq[i]);
+    const RectQ q = cell_rect_i<T>(nd, p.x, p.y, cell_cq(nd, i));
     if (q.r <= q.l || q.t <= q.b) return;
     const long long rq = nd.rq[i];
     unsigned long long *rho = reinterpret_cast<unsigned long long *>(base + L.rho);
