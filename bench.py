@@ -502,8 +502,10 @@ def main():
     ap.add_argument("--scatter-policy", metavar="EVERY,DEFERRED",
                     help="use this charge-scatter policy (e.g. 8,1) instead of timing the "
                          "candidates before the round")
-    ap.add_argument("--launch-shape", metavar="INTERLEAVE,SPECTRAL_THREADS[,CHARGE_RECORDS]",
-                    help="use these launch shapes (e.g. 1,0,1) instead of timing the candidates")
+    ap.add_argument("--launch-shape",
+                    metavar="INTERLEAVE,SPECTRAL_THREADS[,CHARGE_RECORDS[,NONTEMPORAL]]",
+                    help="use these launch shapes (e.g. 1,0,1,0) instead of timing the "
+                         "candidates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, copy 256 MiB device-to-device once: the "
                          "reference dispatch for scaling hardware byte counters")
@@ -566,11 +568,14 @@ def main():
     launch = {}
     if args.launch_shape:
         v = [int(x) for x in args.launch_shape.split(",")]
-        i, sp, rec = v[0], v[1], (v[2] if len(v) > 2 else 1)
+        i, sp = v[0], v[1]
+        rec, nt = (v[2] if len(v) > 2 else 1), (v[3] if len(v) > 3 else 0)
         pl.set_tunable(hy.HP_TUNE_SWEEP_INTERLEAVE, i)
         pl.set_tunable(hy.HP_TUNE_SPECTRAL_THREADS, sp)
         pl.set_tunable(hy.HP_TUNE_CHARGE_RECORDS, rec)
-        launch = {"interleave": i, "spectral_threads": sp, "charge_records": rec}
+        pl.set_tunable(hy.HP_TUNE_NONTEMPORAL, nt)
+        launch = {"interleave": i, "spectral_threads": sp, "charge_records": rec,
+                  "nontemporal": nt}
     elif not args.scatter_policy:
         launch, _ = autotune.tune_launch(pl, [s], gamma)
     log(f"[bench] launch shape {launch}")

@@ -162,12 +162,18 @@ int hp_get_scatter_policy(hp_ctx *ctx, int32_t netlist, int32_t *regroup_every, 
  *     rectangle and weight, which the accumulation then reads with one gather per cell instead
  *     of three (it pays while cells are spread with no relation to their ids, e.g. from random
  *     positions); 0: no records.  Results are bit-identical.
+ *   HP_TUNE_NONTEMPORAL: 1: the net sweep of a launch over this netlist alone reads the pin
+ *     lists and writes the pin gradients with non-temporal hints (streamed data that is used
+ *     once per evaluation then competes less with the gathered positions for the caches;
+ *     it pays on netlists far larger than the last-level cache); 0 (default): plain loads
+ *     and stores.  Launches that mix netlists (hp_iterate_multi over several) use plain ones.
+ *     Results are bit-identical.
  * Takes effect at the next launch.  HP_EINVAL for an unknown setting or a value out of range
  * (nothing changed), HP_ESTATE for an unknown netlist.  The spectral width and the sweep
  * order also rewrite the descriptors of the netlist's slots (a small copy on the context's
  * stream, waited for); the other settings do no device work. */
 enum { HP_TUNE_FUSED_STEP_PARTS = 0, HP_TUNE_SPECTRAL_THREADS = 1, HP_TUNE_SWEEP_INTERLEAVE = 2,
-       HP_TUNE_CHARGE_RECORDS = 3 };
+       HP_TUNE_CHARGE_RECORDS = 3, HP_TUNE_NONTEMPORAL = 4 };
 int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value);
 int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value);
 

@@ -78,10 +78,13 @@ def tune_scatter(pl, slots, gamma, candidates=CANDIDATES, warm=8, iters=24, repe
     return (every, deferred), timings
 
 
-# (sweep interleave, spectral threads per block: 0 = by launch size, charge records)
-LAUNCH_CANDIDATES = tuple((i, t, r) for r in (1, 0) for i in (0, 1) for t in (0, 512, 1024))
-_LAUNCH_TUNABLES = ("HP_TUNE_SWEEP_INTERLEAVE", "HP_TUNE_SPECTRAL_THREADS", "HP_TUNE_CHARGE_RECORDS")
-_LAUNCH_KEYS = ("interleave", "spectral_threads", "charge_records")
+# (sweep interleave, spectral threads per block: 0 = by launch size, charge records,
+#  non-temporal sweep hints)
+LAUNCH_CANDIDATES = tuple((i, t, r, n) for n in (0, 1) for r in (1, 0) for i in (0, 1)
+                          for t in (0, 512, 1024))
+_LAUNCH_TUNABLES = ("HP_TUNE_SWEEP_INTERLEAVE", "HP_TUNE_SPECTRAL_THREADS", "HP_TUNE_CHARGE_RECORDS",
+                    "HP_TUNE_NONTEMPORAL")
+_LAUNCH_KEYS = ("interleave", "spectral_threads", "charge_records", "nontemporal")
 
 
 def tune_launch(pl, slots, gamma, candidates=LAUNCH_CANDIDATES, warm=4, iters=16, repeats=3,

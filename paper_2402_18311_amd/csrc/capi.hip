@@ -561,6 +561,7 @@ int load_netlist(hp_ctx *ctx, const hp_shape &S, const hp_die &D, const double *
     }
     nd.sweep_lead = lead;
     nd.sweep_interleave = 0;
+    nd.sweep_nt = 0;
     const int ns = (int)order.size();
     nd.ns = ns;
 
@@ -1382,7 +1383,8 @@ int iterate_multi(hp_ctx *ctx, const std::vector<int32_t> &sl, const std::vector
         for (int i = 0; i < n; ++i) {
             const Netlist &N = *nls[i];
             key.insert(key.end(), {g.inv[i], (double)N.regroup_every, (double)N.fused_parts,
-                                   (double)N.nd.spec_threads, (double)N.nd.sweep_interleave});
+                                   (double)N.nd.spec_threads, (double)N.nd.sweep_interleave,
+                                   (double)N.nd.sweep_nt});
             L = std::lcm(L, 2 * N.regroup_every);
         }
         if (L <= kMaxGraphBlock) HP_TRY(run_graph_blocks(ctx, sl, ss, key, L, iters, done, one));
@@ -1736,6 +1738,10 @@ int hp_set_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t value) {
             if (value != 0 && value != 1) return fail(HP_EINVAL, "charge records must be 0 or 1");
             NL.charge_records = value != 0;
             return HP_OK;
+        case HP_TUNE_NONTEMPORAL:
+            if (value != 0 && value != 1) return fail(HP_EINVAL, "non-temporal must be 0 or 1");
+            NL.nd.sweep_nt = value;  // chosen by the host at launch; descriptors do not carry it
+            return HP_OK;
         default:
             return fail(HP_EINVAL, "unknown tunable");
     }
@@ -1752,6 +1758,7 @@ int hp_get_tunable(hp_ctx *ctx, int32_t netlist, int32_t which, int32_t *value) 
         case HP_TUNE_SPECTRAL_THREADS: *value = NL.nd.spec_threads; return HP_OK;
         case HP_TUNE_SWEEP_INTERLEAVE: *value = NL.nd.sweep_interleave; return HP_OK;
         case HP_TUNE_CHARGE_RECORDS: *value = NL.charge_records ? 1 : 0; return HP_OK;
+        case HP_TUNE_NONTEMPORAL: *value = NL.nd.sweep_nt; return HP_OK;
         default: return fail(HP_EINVAL, "unknown tunable");
     }
 }
@@ -1926,7 +1933,8 @@ int hp_iterate(hp_ctx *ctx, const int32_t *slots, int32_t n, const hp_iter_param
                                          (double)NL->deferred, (double)NL->fused_parts,
                                          (double)NL->nd.spec_threads,
                                          (double)NL->nd.sweep_interleave,
-                                         (double)NL->charge_records};
+                                         (double)NL->charge_records,
+                                         (double)NL->nd.sweep_nt};
         HP_TRY(run_graph_blocks(ctx, std::vector<int32_t>(slots, slots + n), ss, key,
                                 2 * NL->regroup_every, iters, done, iteration));
     }

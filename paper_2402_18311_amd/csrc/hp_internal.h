@@ -70,6 +70,8 @@ struct NetDev {
                                    // sweep_block)
     int32_t sweep_lead;            // blocks of the block-per-net bucket, which lead the sweep
     int32_t sweep_interleave;      // 1: padded buckets' blocks in sweep_map order
+    int32_t sweep_nt;              // 1: the sweep's read-once pin loads and its pin-gradient
+                                   // stores carry non-temporal hints
     int32_t spec_threads;          // threads per block of the spectral column and inverse-row
                                    // passes: 512, 1024, or 0 (1024 while a launch has at most
                                    // one block per compute unit)

@@ -33,6 +33,43 @@ namespace hp {
 // 2^-16 (nd.offq_exact), the quantized offset is formed from the float one (the same integer)
 // instead of being loaded.
 
+// Native vector types for the non-temporal load and store builtins.
+typedef int nt_v2i __attribute__((ext_vector_type(2)));
+typedef int nt_v4i __attribute__((ext_vector_type(4)));
+typedef float nt_v4f __attribute__((ext_vector_type(4)));
+
+// 16 / 8 bytes of read-once pin data, with a non-temporal hint when NT.
+template <bool NT>
+__device__ __forceinline__ int4 ld4(const int32_t *p) {
+    if constexpr (NT) {
+        const nt_v4i v = __builtin_nontemporal_load(reinterpret_cast<const nt_v4i *>(p));
+        return make_int4(v.x, v.y, v.z, v.w);
+    }
+    return *reinterpret_cast<const int4 *>(p);
+}
+template <bool NT>
+__device__ __forceinline__ int2 ld2(const int32_t *p) {
+    if constexpr (NT) {
+        const nt_v2i v = __builtin_nontemporal_load(reinterpret_cast<const nt_v2i *>(p));
+        return make_int2(v.x, v.y);
+    }
+    return *reinterpret_cast<const int2 *>(p);
+}
+// 16 bytes of pin gradients, with a non-temporal hint when NT.
+template <bool NT>
+__device__ __forceinline__ void st4f(float *p, float a, float b, float c, float d) {
+    if constexpr (NT) {
+        nt_v4f v;
+        v.x = a;
+        v.y = b;
+        v.z = c;
+        v.w = d;
+        __builtin_nontemporal_store(v, reinterpret_cast<nt_v4f *>(p));
+    } else {
+        *reinterpret_cast<float4 *>(p) = make_float4(a, b, c, d);
+    }
+}
+
 // One slot's compact offset (two int16 in units of 2^-off16_shift) as T: the same value as the
 // full-width offset, exactly (an int16 times a power of two).
 template <typename T>
@@ -42,16 +79,16 @@ __device__ __forceinline__ vec2<T> off16(int32_t w, T unit) {
 
 // Four consecutive pin slots (slot a multiple of 4): cell ids and offsets by 16-byte loads
 // (one for the offsets when they are compact).
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void load_slots4(const NetDev &nd, int slot, int (&c)[4],
                                             vec2<T> (&o)[4]) {
-    const int4 cc = *reinterpret_cast<const int4 *>(nd.pin_cell + slot);
+    const int4 cc = ld4<NT>(nd.pin_cell + slot);
     c[0] = cc.x;
     c[1] = cc.y;
     c[2] = cc.z;
     c[3] = cc.w;
     if (nd.off16_shift >= 0) {
-        const int4 w = *reinterpret_cast<const int4 *>(nd.pin_off16 + slot);
+        const int4 w = ld4<NT>(nd.pin_off16 + slot);
         const T unit = (T)ldexp(1.0, -nd.off16_shift);
         o[0] = off16<T>(w.x, unit);
         o[1] = off16<T>(w.y, unit);
@@ -81,11 +118,11 @@ __device__ __forceinline__ void load_offq4(const NetDev &nd, int slot, int2 (&q)
     q[3] = make_int2(b.z, b.w);
 }
 // Four gradient pairs to four consecutive slots.
-template <typename T>
+template <typename T, bool NT>
 __device__ __forceinline__ void store_grad4(vec2<T> *pg, const T (&gx)[4], const T (&gy)[4]) {
     if constexpr (sizeof(T) == 4) {
-        *reinterpret_cast<float4 *>(pg) = make_float4(gx[0], gy[0], gx[1], gy[1]);
-        *reinterpret_cast<float4 *>(pg + 2) = make_float4(gx[2], gy[2], gx[3], gy[3]);
+        st4f<NT>(reinterpret_cast<float *>(pg), gx[0], gy[0], gx[1], gy[1]);
+        st4f<NT>(reinterpret_cast<float *>(pg + 2), gx[2], gy[2], gx[3], gy[3]);
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) pg[k] = cmk2<T>(gx[k], gy[k]);
@@ -104,7 +141,7 @@ template <> __device__ __forceinline__ double wa_tanh2<double>(double u) {
 
 // Two-pin nets, one lane each, kPairNets per lane (net = net0 + (local kPairNets + r) kBlock +
 // lane, so a wave's loads are contiguous): WL = D tanh(D / 2 gamma) per axis.
-template <typename T, bool H>
+template <typename T, bool H, bool NT>
 __device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, int b, int local,
                                          const vec2<T> *__restrict__ pos, T invg,
                                          vec2<T> *__restrict__ pg, double &wl,
@@ -120,9 +157,9 @@ __device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, in
     for (int r = 0; r < R; ++r) {  // loads on clamped in-range slots first
         net[r] = net0 + (local * R + r) * kBlock + (int)threadIdx.x;
         slot[r] = pin0 + (net[r] < net1 ? 2 * (net[r] - net0) : 0);
-        c[r] = *reinterpret_cast<const int2 *>(nd.pin_cell + slot[r]);
+        c[r] = ld2<NT>(nd.pin_cell + slot[r]);
         if (nd.off16_shift >= 0) {
-            const int2 w = *reinterpret_cast<const int2 *>(nd.pin_off16 + slot[r]);
+            const int2 w = ld2<NT>(nd.pin_off16 + slot[r]);
             o0[r] = off16<T>(w.x, unit);
             o1[r] = off16<T>(w.y, unit);
         } else if constexpr (sizeof(T) == 4) {
@@ -170,7 +207,7 @@ __device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, in
         const T gx = w * (thx + tx * (T(1) - thx * thx)), gy = w * (thy + ty * (T(1) - thy * thy));
         const T sx = dx >= T(0) ? gx : -gx, sy = dy >= T(0) ? gy : -gy;
         if constexpr (sizeof(T) == 4)
-            *reinterpret_cast<float4 *>(pg + slot[r]) = make_float4(sx, sy, -sx, -sy);
+            st4f<NT>(reinterpret_cast<float *>(pg + slot[r]), sx, sy, -sx, -sy);
         else {
             pg[slot[r]] = cmk2<T>(sx, sy);
             pg[slot[r] + 1] = cmk2<T>(-sx, -sy);
@@ -181,7 +218,7 @@ __device__ __forceinline__ void wa_pairs(const NetDev &nd, const Buckets &bk, in
 
 // Nets of G = 4 LP slots, LP lanes each (LP = 1 .. 64), one net per lane group and block row:
 // lane l of the group owns slots 4 l .. 4 l + 3 of its net.
-template <typename T, int LP, bool H>
+template <typename T, int LP, bool H, bool NT>
 __device__ __forceinline__ void wa_lanes(const NetDev &nd, const Buckets &bk, int b, int local,
                                          const vec2<T> *__restrict__ pos, T invg,
                                          vec2<T> *__restrict__ pg, double &wl,
@@ -196,7 +233,7 @@ __device__ __forceinline__ void wa_lanes(const NetDev &nd, const Buckets &bk, in
     // its first net's slots, a padding slot's cell -1 reads cell 0; both are ignored)
     int c[4];
     vec2<T> o[4];
-    load_slots4<T>(nd, slot, c, o);
+    load_slots4<T, NT>(nd, slot, c, o);
     int2 oq[4];
     if constexpr (H) {
         if (nd.offq_exact) {
@@ -290,7 +327,7 @@ __device__ __forceinline__ void wa_lanes(const NetDev &nd, const Buckets &bk, in
                          : w * (ayp * ibyp * (T(1) + (dyp - ryp) * invg) -
                                 aym * ibym * (T(1) - (dym - rym) * invg));
     }
-    if (vnet) store_grad4<T>(pg + slot, gx, gy);
+    if (vnet) store_grad4<T, NT>(pg + slot, gx, gy);
     if (vnet && l == 0)
         wl += (double)(w * (((xM - xm) + (rxp - rxm)) + ((yM - ym) + (ryp - rym))));
 }
@@ -562,7 +599,7 @@ __device__ __forceinline__ int64_t hpwl_bucket(const NetDev &nd, const Buckets &
 // Block `bx` (0 <= bx < bk.total_blocks) of a sweep of one slot: WA over v, or HPWL over u.
 // MODE_WA with H: the WA sweep of v and the HPWL sweep of u in the same blocks, both partials
 // written.
-template <typename T, int MODE, bool H = false>
+template <typename T, int MODE, bool H = false, bool NT = false>
 __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, char *base,
                                            const SlotLayout &L, T invg, int bx) {
     int b, local;
@@ -575,14 +612,14 @@ __device__ __forceinline__ void sweep_body(const NetDev &nd, const Buckets &bk, 
         double wl = 0.0;
         int64_t h = 0;
         switch (bk.G[b]) {
-            case 2: wa_pairs<T, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 4: wa_lanes<T, 1, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 8: wa_lanes<T, 2, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 16: wa_lanes<T, 4, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 32: wa_lanes<T, 8, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 64: wa_lanes<T, 16, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 128: wa_lanes<T, 32, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
-            case 256: wa_lanes<T, 64, H>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 2: wa_pairs<T, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 4: wa_lanes<T, 1, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 8: wa_lanes<T, 2, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 16: wa_lanes<T, 4, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 32: wa_lanes<T, 8, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 64: wa_lanes<T, 16, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 128: wa_lanes<T, 32, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
+            case 256: wa_lanes<T, 64, H, NT>(nd, bk, b, local, pos, invg, pg, wl, posu, h); break;
             default:
                 if (net0 + local < net1) {
                     wa_block<T>(nd, net0 + local, pos, invg, pg, wl);
@@ -631,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void sweep_hpwl_kernel(NetDev nd, Buckets b
 //                             hp_hpwl) the same blocks also sweep the HPWL of u, sharing the pin
 //                             loads.
 // nacc, ncnt and nbig are multiples of 8, so the sweep keeps the XCD striping of its own blocks.
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Buckets bk, SlotArgs sa,
                                                             SlotLayout L, T invg, int nacc,
                                                             int ncnt, int nbig, uint32_t hmask,
@@ -646,9 +683,9 @@ __global__ __launch_bounds__(kBlock, 8) void eval_front_kernel(NetDev nd, Bucket
     } else if (bx < s0) {
         big_scatter_body<T>(nd, base, L, bx - nacc - ncnt);
     } else if ((hmask >> blockIdx.y) & 1u) {
-        sweep_body<T, MODE_WA, true>(nd, bk, base, L, invg, bx - s0);
+        sweep_body<T, MODE_WA, true, NT>(nd, bk, base, L, invg, bx - s0);
     } else {
-        sweep_body<T, MODE_WA, false>(nd, bk, base, L, invg, bx - s0);
+        sweep_body<T, MODE_WA, false, NT>(nd, bk, base, L, invg, bx - s0);
     }
 }
 
@@ -752,8 +789,12 @@ hipError_t launch_eval_front(const NetDev &nd, const Buckets &bk, const SlotArgs
                                  count ? scatter_count_lds(nd) : 0, big});
     dim3 grid(nacc + ncnt + nbig + (sweep ? bk.total_blocks : 0), sa.n);
     if (grid.x == 0) return hipSuccess;
-    HP_LAUNCH("eval_front_kernel", eval_front_kernel<T>, grid, dim3(kBlock), lds, st, nd, bk, sa,
-              L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask, (int)records);
+    if (nd.sweep_nt)
+        HP_LAUNCH("eval_front_kernel", (eval_front_kernel<T, true>), grid, dim3(kBlock), lds, st,
+                  nd, bk, sa, L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask, (int)records);
+    else
+        HP_LAUNCH("eval_front_kernel", (eval_front_kernel<T, false>), grid, dim3(kBlock), lds, st,
+                  nd, bk, sa, L, (T)inv_gamma, nacc, ncnt, nbig, hpwl_mask, (int)records);
     return hipGetLastError();
 }
 

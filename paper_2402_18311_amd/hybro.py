@@ -23,7 +23,7 @@ HP_MAP_RHO_MOV, HP_MAP_RHO_FIXED, HP_MAP_PSI, HP_MAP_EX, HP_MAP_EY = 0, 1, 2, 3,
 HP_ITER_HPWL, HP_ITER_GRAPH, HP_ITER_HPWL_LAST = 1, 2, 4
 HP_GRAD_FIELD, HP_GRAD_EXACT, HP_GRAD_DENSITY_ONLY = 0, 1, 2
 HP_TUNE_FUSED_STEP_PARTS, HP_TUNE_SPECTRAL_THREADS, HP_TUNE_SWEEP_INTERLEAVE = 0, 1, 2
-HP_TUNE_CHARGE_RECORDS = 3
+HP_TUNE_CHARGE_RECORDS, HP_TUNE_NONTEMPORAL = 3, 4
 
 
 class hp_die(C.Structure):

@@ -269,12 +269,14 @@ def test_launch_shape_tuner_picks_a_candidate_and_caches(hy, orc, tmp_path):
     gamma = 4 * nl.bin_w
     s = pl.new_slot()
     pl.set_positions(s, nl.x0, nl.y0)
-    names = (hy.HP_TUNE_SWEEP_INTERLEAVE, hy.HP_TUNE_SPECTRAL_THREADS, hy.HP_TUNE_CHARGE_RECORDS)
+    names = (hy.HP_TUNE_SWEEP_INTERLEAVE, hy.HP_TUNE_SPECTRAL_THREADS, hy.HP_TUNE_CHARGE_RECORDS,
+             hy.HP_TUNE_NONTEMPORAL)
     saved = [pl.tunable(w) for w in names]
     cache = str(tmp_path / "tune.json")
     try:
         rec, t = autotune.tune_launch(pl, [s], gamma, warm=2, iters=4, repeats=1, cache=cache)
-        got = tuple(rec[k] for k in ("interleave", "spectral_threads", "charge_records"))
+        got = tuple(rec[k] for k in ("interleave", "spectral_threads", "charge_records",
+                                     "nontemporal"))
         assert got in autotune.LAUNCH_CANDIDATES and len(t) == len(autotune.LAUNCH_CANDIDATES)
         assert tuple(pl.tunable(w) for w in names) == got
         for w, v in zip(names, saved):

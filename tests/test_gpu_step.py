@@ -134,12 +134,13 @@ def test_tunables_reject_bad_values(hy, orc):
     L = hy.lib()
     for which, value in ((hy.HP_TUNE_FUSED_STEP_PARTS, -1), (hy.HP_TUNE_FUSED_STEP_PARTS, 1025),
                          (hy.HP_TUNE_SPECTRAL_THREADS, 256), (hy.HP_TUNE_CHARGE_RECORDS, 2),
-                         (7, 0)):
+                         (hy.HP_TUNE_NONTEMPORAL, 2), (hy.HP_TUNE_NONTEMPORAL, -1), (7, 0)):
         assert L.hp_set_tunable(pl.ctx, pl.netlist, which, value) == hy.HP_EINVAL
     assert L.hp_set_tunable(pl.ctx, 99, hy.HP_TUNE_SPECTRAL_THREADS, 0) == hy.HP_ESTATE
     assert pl.tunable(hy.HP_TUNE_FUSED_STEP_PARTS) == 1024
     assert pl.tunable(hy.HP_TUNE_SPECTRAL_THREADS) == 0
     assert pl.tunable(hy.HP_TUNE_CHARGE_RECORDS) == 1
+    assert pl.tunable(hy.HP_TUNE_NONTEMPORAL) == 0
 
 
 @pytest.mark.parametrize("threads", [512, 1024])
@@ -217,6 +218,39 @@ def test_interleaved_sweep_order_is_bit_identical(hy, orc, case, prec):
 
 def torch_equal(a, b):
     return bool((a.cpu() == b.cpu()).all())
+
+
+@pytest.mark.parametrize("case,prec", [("small", 32), ("tiny", 64)])
+def test_nontemporal_sweep_is_bit_identical(hy, orc, case, prec):
+    """Cache hints on the sweep's pin loads and gradient stores change no value: the same
+    gradients, steps and exact HPWL, bit for bit, eagerly and under graph replay (a placer on
+    a stream of its own, which graph replay needs)."""
+    import torch
+    nl = _NETS[case]()
+    pl = hy.Placer(nl, precision=prec, stream=torch.cuda.Stream())
+    gamma = 4 * nl.bin_w
+    a, b = pl.new_slot(), pl.new_slot()
+    for s in (a, b):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+    try:
+        for chunk, graph in ((1, False), (6, False), (24, True)):
+            pl.set_tunable(hy.HP_TUNE_NONTEMPORAL, 0)
+            _, gxa, gya = pl.eval(a, gamma, grads=True)
+            pl.step(a)
+            pl.iterate(a, gamma, chunk, hpwl=True, graph=graph)
+            pl.set_tunable(hy.HP_TUNE_NONTEMPORAL, 1)
+            assert pl.tunable(hy.HP_TUNE_NONTEMPORAL) == 1
+            _, gxb, gyb = pl.eval(b, gamma, grads=True)
+            pl.step(b)
+            pl.iterate(b, gamma, chunk, hpwl=True, graph=graph)
+            assert torch_equal(gxa, gxb) and torch_equal(gya, gyb)
+            assert pl.hpwl(a)[0] == pl.hpwl(b)[0]
+            xa, ya = pl.positions(a)
+            xb, yb = pl.positions(b)
+            assert np.array_equal(xa, xb) and np.array_equal(ya, yb), chunk
+    finally:
+        pl.close()
 
 
 @pytest.mark.parametrize("case,prec", [("small", 32), ("tiny", 64)])
