@@ -278,9 +278,25 @@ __device__ __forceinline__ void load_row4_part(const vec2<T> *src, bool lo, bool
 // descriptor and nb its own block count (the grid: the largest slot's, rounded up).  Six
 // waves per SIMD (80 registers): the pass waits on gathers, and at five it was 2-3% slower,
 // at eight (spilling) 20% slower.
-// pin gradients gathered per round of the gradient pass (at large, 6 per round was 0.4 us
-// slower and 8 was 3 us slower)
-constexpr int kPinBatch = 4;
+//
+// The pin gradients of a wave's 64 cells are one contiguous range of the cell-ordered pin
+// list.  The wave gathers that range in windows of kPinWin pins, every lane taking kPinPer of
+// them (index loads coalesced, every gather slot used), stages each window in LDS, and each
+// lane then adds its own cell's pins from LDS in pin order: the same additions in the same
+// order as a lane walking its own pins, without the wave waiting on its longest pin list.
+// At large, 8 pins a lane took the pass from 85 us (a lane per cell's own pins) to 75.5 us;
+// 4 gave 80 us, 2 gave 83 us, and 16 (LDS and registers then allow 4 waves per SIMD) 90 us.
+// FP64 (16 bytes a pin) stages 32 KB a block and runs at 3 waves per SIMD without spilling.
+constexpr int kPinPer = 8;
+constexpr int kPinWin = 64 * kPinPer;
+
+// LDS written by some lanes of a wave is read by others: order the accesses within the wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, bool RAG>
 __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
                                                            double lam_fixed, int use_fixed,
@@ -294,34 +310,61 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
     Scalars *sc = scalars(base, L);
     const bool init = !use_fixed && sc->lambda_valid == 0;
     const int i = cb * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     T gwx = 0, gwy = 0, gdx = 0, gdy = 0;
+    // the wave's pin range [p0, p1) (wave-uniform); none in a density-only evaluation (the
+    // sweep did not run)
+    const int c0 = __builtin_amdgcn_readfirstlane(cb * kBlock + (threadIdx.x & ~63));
+    int p0 = 0, p1 = 0;
+    if (!(grad_mode & GRAD_DENSITY_ONLY) && c0 < nd.n_mov) {
+        p0 = nd.cell_pin_start[c0];
+        p1 = nd.cell_pin_start[min(c0 + 64, nd.n_mov)];
+    }
+    const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
+    const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
+    // Loads are issued in dependency rounds, each round's loads all in flight before any of
+    // them is used: (1) the cell's pin range, position and charge constants, and the wave's
+    // first window of pin indices; (2) the field at its charge footprint (a fixed 3 x 4 bin
+    // window on clamped in-footprint indices) and the first window's pin gradients; then each
+    // window's gradients with the next window's indices.  Sums keep pin order and row-major
+    // bin order.
+    int id[kPinPer];
+    if (p1 > p0) {
+#pragma unroll
+        for (int u = 0; u < kPinPer; ++u) id[u] = nd.cell_pins[min(p0 + lane + 64 * u, p1 - 1)];
+    }
+    int j = 0, e = 0;  // the lane's own pins (none for a big cell or past the cells)
+    bool big = false, has = false, small = false;
+    int4 cc = make_int4(0, 0, 0, 0);
+    vec2<T> p = cmk2<T>(T(0), T(0));
+    T rqt = 0;
+    RectQ q{};
+    int j0 = 0, j1 = 0, k0 = 0, k1 = 0;
+    constexpr int KR = 3, JC = 4;
+    int js = 0, ks = 0;
+    vec2<T> f[KR][JC];
     if (i < nd.n_mov) {
-        // Loads are issued in dependency rounds, each round's loads all in flight before any
-        // of them is used: (1) the cell's pin range, position and charge constants; (2) the
-        // field at its charge footprint (a fixed 3 x 4 bin window on clamped in-footprint
-        // indices) and its first four pin indices; then the pin gradients four at a time, each
-        // batch with the next batch's indices.  Sums keep pin order and row-major bin order.
-        const vec2<T> *pg = reinterpret_cast<const vec2<T> *>(base + L.pin_grad);
-        const vec2<T> *exy = reinterpret_cast<const vec2<T> *>(base + L.exy);
-        const int4 cc = cell_cq(nd, i);
-        const bool big = is_big(nd, cc);  // both parts already reduced by its own block
-        const int e = nd.cell_pin_start[i + 1];
-        // no wirelength part in a density-only evaluation (the sweep did not run)
-        int j = (big || (grad_mode & GRAD_DENSITY_ONLY)) ? e : nd.cell_pin_start[i];
-        const vec2<T> p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
+        cc = cell_cq(nd, i);
+        big = is_big(nd, cc);  // both parts already reduced by its own block
+        if (!big && p1 > p0) {
+            j = nd.cell_pin_start[i];
+            e = nd.cell_pin_start[i + 1];
+        }
+        p = reinterpret_cast<const vec2<T> *>(base + L.v)[i];
         // charge weight of a bin: rq ox oy 2^-40, formed in the compute type (exact in FP64;
         // in FP32 a relative rounding of ~1e-7, far inside the gradient tolerance)
-        const T rqt = (T)nd.rq[i] * (T)0x1p-40;
-        const RectQ q = cell_rect_i<T>(nd, p.x, p.y, cc);
-        const bool has = !big && q.r > q.l && q.t > q.b;
-        const int j0 = q.l / nd.bq, j1 = has ? (q.r - 1) / nd.bq : j0;
-        const int k0 = q.b / nd.hq, k1 = has ? (q.t - 1) / nd.hq : k0;
-        constexpr int KR = 3, JC = 4;
-        const bool small = !(grad_mode & GRAD_EXACT) && has && k1 - k0 < KR && j1 - j0 < JC;
+        rqt = (T)nd.rq[i] * (T)0x1p-40;
+        q = cell_rect_i<T>(nd, p.x, p.y, cc);
+        has = !big && q.r > q.l && q.t > q.b;
+        j0 = q.l / nd.bq;
+        j1 = has ? (q.r - 1) / nd.bq : j0;
+        k0 = q.b / nd.hq;
+        k1 = has ? (q.t - 1) / nd.hq : k0;
+        small = !(grad_mode & GRAD_EXACT) && has && k1 - k0 < KR && j1 - j0 < JC;
         // the window: rows ks .. ks+2 and columns js .. js+3 of the field, inside the grid
         // (sides >= 8 bins) and covering the footprint; each row is read as wide loads
-        const int js = min(j0, nd.mx - JC), ks = min(k0, nd.my - KR);
-        vec2<T> f[KR][JC];
+        js = min(j0, nd.mx - JC);
+        ks = min(k0, nd.my - KR);
         if (small) {  // only the rows and bin pairs of the window that the footprint covers
             const bool lo = j0 <= js + 1, hi = j1 >= js + 2;
 #pragma unroll
@@ -331,32 +374,36 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
                     load_row4_part<T>(exy + (size_t)(ks + kk) * nd.mx + js, lo, hi, f[kk]);
             }
         }
-        // pins in batches of four, the last one masked (indices clamped into the cell's range):
-        // a batch's gradient gathers are in flight with the next batch's indices, and the sums
-        // keep pin order
-        if (j < e) {
-            int id[kPinBatch];
+    }
+    // the wave's pin windows (indices clamped into the range; staged slots past it are never
+    // read)
+    if (p1 > p0) {
+        __shared__ vec2<T> stage[kBlock / 64][kPinWin];
+        for (int wb = p0;;) {
+            vec2<T> gb[kPinPer];
 #pragma unroll
-            for (int u = 0; u < kPinBatch; ++u) id[u] = nd.cell_pins[min(j + u, e - 1)];
-            for (;;) {
-                vec2<T> gb[kPinBatch];
+            for (int u = 0; u < kPinPer; ++u) gb[u] = pg[id[u]];
+            const int wn = wb + kPinWin;
+            if (wn < p1) {
 #pragma unroll
-                for (int u = 0; u < kPinBatch; ++u) gb[u] = pg[id[u]];
-                const int jn = j + kPinBatch;
-                if (jn < e) {
-#pragma unroll
-                    for (int u = 0; u < kPinBatch; ++u) id[u] = nd.cell_pins[min(jn + u, e - 1)];
-                }
-#pragma unroll
-                for (int u = 0; u < kPinBatch; ++u)
-                    if (j + u < e) {
-                        gwx += gb[u].x;
-                        gwy += gb[u].y;
-                    }
-                if (jn >= e) break;
-                j = jn;
+                for (int u = 0; u < kPinPer; ++u)
+                    id[u] = nd.cell_pins[min(wn + lane + 64 * u, p1 - 1)];
             }
+            wave_lds_sync();  // the previous window's reads come first
+#pragma unroll
+            for (int u = 0; u < kPinPer; ++u) stage[wv][lane + 64 * u] = gb[u];
+            wave_lds_sync();
+            const int qe = min(e, wn);
+            for (int k = max(j, wb); k < qe; ++k) {
+                const vec2<T> g = stage[wv][k - wb];
+                gwx += g.x;
+                gwy += g.y;
+            }
+            if (wn >= p1) break;
+            wb = wn;
         }
+    }
+    if (i < nd.n_mov) {
         if (big) {
             const T *gw = reinterpret_cast<const T *>(base + L.g);
             const T *gd = reinterpret_cast<const T *>(base + L.gd);
