@@ -296,6 +296,12 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// The smallest v over the wave's 64 lanes, in every lane (as a scalar).
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
 
 template <typename T, bool RAG>
 __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotArgs sa, SlotLayout La,
@@ -376,10 +382,22 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
         }
     }
     // the wave's pin windows (indices clamped into the range; staged slots past it are never
-    // read)
+    // read).  A big cell's pins are summed by its own block, not here: a wave holding one
+    // trims its range to the first and last pin that its lanes add (a wave of big cells
+    // gathers nothing; the pins of a big cell between two others are gathered and not added).
     if (p1 > p0) {
         __shared__ vec2<T> stage[kBlock / 64][kPinWin];
-        for (int wb = p0;;) {
+        if (__ballot(big) != 0) {  // wave-uniform
+            const int b0 = wave_min(j < e ? j : p1), b1 = -wave_min(j < e ? -e : -p0);
+            if (b0 != p0 && b0 < b1) {
+#pragma unroll
+                for (int u = 0; u < kPinPer; ++u)
+                    id[u] = nd.cell_pins[min(b0 + lane + 64 * u, b1 - 1)];
+            }
+            p0 = b0;
+            p1 = b1;
+        }
+        for (int wb = p0; wb < p1;) {
             vec2<T> gb[kPinPer];
 #pragma unroll
             for (int u = 0; u < kPinPer; ++u) gb[u] = pg[id[u]];
@@ -399,7 +417,6 @@ __global__ __launch_bounds__(kBlock, 6) void cell_grad_kernel(NetDev nda, SlotAr
                 gwx += g.x;
                 gwy += g.y;
             }
-            if (wn >= p1) break;
             wb = wn;
         }
     }

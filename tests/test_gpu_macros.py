@@ -44,6 +44,25 @@ def _huge():
     return nl
 
 
+def _shuffled(nl, seed):
+    """The same netlist with its movable cells renumbered at random, so that the macros sit
+    among standard cells of neighbouring ids (the generator numbers them last)."""
+    import dataclasses
+    assert nl.n_fillers == 0
+    nm = nl.n_movable
+    order = np.random.default_rng(seed).permutation(nm)
+    inv = np.empty(nm, np.int64)
+    inv[order] = np.arange(nm)
+    pc = nl.pin_cell.astype(np.int64)
+    mov = pc < nm
+    pc[mov] = inv[pc[mov]]
+    return dataclasses.replace(
+        nl, cell_w=np.concatenate([nl.cell_w[:nm][order], nl.cell_w[nm:]]),
+        cell_h=np.concatenate([nl.cell_h[:nm][order], nl.cell_h[nm:]]),
+        pin_cell=pc.astype(nl.pin_cell.dtype), x0=nl.x0[order], y0=nl.y0[order],
+        macros=np.sort(inv[nl.macros]).astype(np.int32))
+
+
 _CASES = {
     # 6 movable macros of up to 25 x 18 bins among 1000 standard cells, 64^2 bins
     "tiny_mm": lambda: netgen.make_small(1000, 1100, 64, seed=1, n_fixed=6, movable_macros=True,
@@ -51,6 +70,9 @@ _CASES = {
     # 40 movable macros, 20 k cells, 128^2 bins
     "small_mm": lambda: netgen.make_small(20_011, 21_003, 128, seed=3, n_fixed=40,
                                           movable_macros=True),
+    # the same with the cells renumbered: macros between standard cells of one 64-cell group
+    "small_mm_shuffled": lambda: _shuffled(netgen.make_small(20_011, 21_003, 128, seed=3,
+                                                             n_fixed=40, movable_macros=True), 7),
     "huge": _huge,
     # the 210 k-cell netlist with its 500 macros movable
     "mid_mm": lambda: netgen.make_netlist("mid_mm", 0),
@@ -72,8 +94,9 @@ def setup(hy, orc, case, prec):
     return _cache[key]
 
 
-EVAL = [("tiny_mm", 64), ("tiny_mm", 32), ("small_mm", 32), ("small_mm", 64), ("huge", 64),
-        ("huge", 32), ("mid_mm", 32)]
+EVAL = [("tiny_mm", 64), ("tiny_mm", 32), ("small_mm", 32), ("small_mm", 64),
+        ("small_mm_shuffled", 32), ("small_mm_shuffled", 64), ("huge", 64), ("huge", 32),
+        ("mid_mm", 32)]
 
 
 @pytest.mark.parametrize("case,prec", EVAL)
