@@ -18,7 +18,10 @@
 // and a sine sum is a cosine sum of the reversed coefficients times (-1)^j.  Two real lines
 // share one complex FFT.  The FFT is a decimation-in-time transform in LDS (radix-4 passes,
 // one radix-2 pass for odd log M) over a batch of lines.  Each block copies the twiddles, DCT
-// phases and per-axis symbols (tables built on the host in FP64) to LDS.
+// phases and per-axis symbols (tables built on the host in FP64) to LDS.  In the column and
+// inverse-row passes the complex line buffers and the twiddles are stored with one spare slot
+// after every 32 elements (fpad): the bit-reversed and power-of-two-strided accesses of a
+// transform then spread over the LDS banks instead of meeting in a few of them.
 //
 // With M <= 1024 each pass has only M/2 blocks (one per CU or fewer), so a block's latency is
 // the pass's time: blocks are wide (1024 threads; 512 for C and R2 in launches with more
@@ -44,14 +47,21 @@ __device__ __forceinline__ vec2<T> cadd(vec2<T> a, vec2<T> b) { return cmk<T>(a.
 template <typename T>
 __device__ __forceinline__ vec2<T> csub(vec2<T> a, vec2<T> b) { return cmk<T>(a.x - b.x, a.y - b.y); }
 
+// LDS position of element i of a padded array (one spare slot after every 32 elements), and
+// the elements such an array of n needs; lpos: the position in a padded (PAD) or plain array.
+__host__ __device__ inline int fpad(int i) { return i + (i >> 5); }
+__host__ __device__ inline size_t fpad_n(size_t n) { return n + (n >> 5) + 1; }
+template <bool PAD> __device__ __forceinline__ int lpos(int i) { return PAD ? fpad(i) : i; }
+
 __device__ __forceinline__ int brev(int n, int logM) { return (int)(__brev((unsigned)n) >> (32 - logM)); }
 // position of element j in Makhoul's reordered sequence (and of output j in the inverse)
 __device__ __forceinline__ int mperm(int j, int M) { return (j & 1) ? (M - 1 - (j >> 1)) : (j >> 1); }
 
-// In-place FFT of nlines lines of length M held in bit-reversed order; tw[k] = exp(-2 pi i k/M)
-// (conjugated for the inverse).  A radix-4 pass performs DIT stages s and s+1 at once: with
+// In-place FFT of nlines lines of length M held in bit-reversed order, line l's element i at
+// buf[lpos<PAD>(l M + i)]; tw[lpos<PAD>(k)] = exp(-2 pi i k/M) (conjugated for the inverse).
+// A radix-4 pass performs DIT stages s and s+1 at once: with
 // h = 2^s, w1 = W_{2h}^pos and w2 = W_{4h}^pos, and W_{4h}^h = -i (forward) or +i (inverse).
-template <typename T, int NT>
+template <typename T, int NT, bool PAD>
 __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T> *tw, bool inverse) {
     int s = 0;
     for (; s + 1 < logM; s += 2) {
@@ -64,22 +74,24 @@ __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T>
             const int t = b & (q - 1);
             const int pos = t & (h - 1);
             const int i0 = ((t >> s) << (s + 2)) | pos;
-            vec2<T> w1 = tw[pos << sh1], w2 = tw[pos << sh2];
+            vec2<T> w1 = tw[lpos<PAD>(pos << sh1)], w2 = tw[lpos<PAD>(pos << sh2)];
             if (inverse) {
                 w1.y = -w1.y;
                 w2.y = -w2.y;
             }
-            vec2<T> *Lb = buf + (size_t)line * M;
-            const vec2<T> x0 = Lb[i0], x1 = Lb[i0 + h], x2 = Lb[i0 + 2 * h], x3 = Lb[i0 + 3 * h];
+            const int g = line * M + i0;
+            const int a0 = lpos<PAD>(g), a1 = lpos<PAD>(g + h), a2 = lpos<PAD>(g + 2 * h),
+                      a3 = lpos<PAD>(g + 3 * h);
+            const vec2<T> x0 = buf[a0], x1 = buf[a1], x2 = buf[a2], x3 = buf[a3];
             const vec2<T> c1 = cmul<T>(w1, x1), c3 = cmul<T>(w1, x3);
             const vec2<T> b0 = cadd<T>(x0, c1), b1 = csub<T>(x0, c1);
             const vec2<T> b2 = cadd<T>(x2, c3), b3 = csub<T>(x2, c3);
             const vec2<T> d2 = cmul<T>(w2, b2), d3 = cmul<T>(w2, b3);
             const vec2<T> e3 = inverse ? cmk<T>(-d3.y, d3.x) : cmk<T>(d3.y, -d3.x);
-            Lb[i0] = cadd<T>(b0, d2);
-            Lb[i0 + 2 * h] = csub<T>(b0, d2);
-            Lb[i0 + h] = cadd<T>(b1, e3);
-            Lb[i0 + 3 * h] = csub<T>(b1, e3);
+            buf[a0] = cadd<T>(b0, d2);
+            buf[a2] = csub<T>(b0, d2);
+            buf[a1] = cadd<T>(b1, e3);
+            buf[a3] = csub<T>(b1, e3);
         }
         __syncthreads();
     }
@@ -90,22 +102,22 @@ __device__ void fft_lds(vec2<T> *buf, int nlines, int M, int logM, const vec2<T>
             const int t = b & (hm - 1);
             const int pos = t & (half - 1);
             const int i0 = ((t >> s) << (s + 1)) | pos;
-            vec2<T> w = tw[pos << tsh];
+            vec2<T> w = tw[lpos<PAD>(pos << tsh)];
             if (inverse) w.y = -w.y;
-            vec2<T> *Lb = buf + (size_t)line * M;
-            const vec2<T> a = Lb[i0], c = cmul<T>(w, Lb[i0 + half]);
-            Lb[i0] = cadd<T>(a, c);
-            Lb[i0 + half] = csub<T>(a, c);
+            const int a0 = lpos<PAD>(line * M + i0), a1 = lpos<PAD>(line * M + i0 + half);
+            const vec2<T> a = buf[a0], c = cmul<T>(w, buf[a1]);
+            buf[a0] = cadd<T>(a, c);
+            buf[a1] = csub<T>(a, c);
         }
         __syncthreads();
     }
 }
 
-// Split a packed forward FFT Z of two real sequences and apply the DCT post-twiddle:
-// returns (F_a(u), F_b(u)).
-template <typename T>
-__device__ __forceinline__ vec2<T> dct_post(const vec2<T> *line, int u, int M, vec2<T> ph) {
-    const vec2<T> Z = line[u], Zm = line[(M - u) & (M - 1)];
+// Split a packed forward FFT Z of two real sequences (the line at index lb of buf, laid out as
+// lpos<PAD>) and apply the DCT post-twiddle: returns (F_a(u), F_b(u)).
+template <typename T, bool PAD>
+__device__ __forceinline__ vec2<T> dct_post(const vec2<T> *buf, int lb, int u, int M, vec2<T> ph) {
+    const vec2<T> Z = buf[lpos<PAD>(lb + u)], Zm = buf[lpos<PAD>(lb + ((M - u) & (M - 1)))];
     const T var = (Z.x + Zm.x) * T(0.5), vai = (Z.y - Zm.y) * T(0.5);
     const T vbr = (Z.y + Zm.y) * T(0.5), vbi = -(Z.x - Zm.x) * T(0.5);
     return cmk<T>(ph.x * var + ph.y * vai, ph.x * vbr + ph.y * vbi);
@@ -136,6 +148,14 @@ struct Prefetch {
         for (int k = 0; k < K; ++k) {
             const int i = threadIdx.x + k * NT;
             if (i < n) s[i] = (S)r[k];
+        }
+    }
+    // into a padded array (element i at s[fpad(i)])
+    __device__ __forceinline__ void put_pad(V *s, int n) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = threadIdx.x + k * NT;
+            if (i < n) s[fpad(i)] = r[k];
         }
     }
 };
@@ -173,7 +193,8 @@ __device__ __forceinline__ int spec_block(int nb) {
 __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~size_t(15); }
 
 // ---- R1 ---------------------------------------------------------------------------------
-// lds: tw [M/2] | ph [M] | buf [lpb][M]
+// lds: tw [M/2] | ph [M] | buf [lpb][M] (not padded: here the padding's extra index arithmetic
+// cost more than the bank conflicts it removes)
 // A block takes 2 lpb consecutive rows (lpb complex lines), one bin per thread and round.
 constexpr int kRowsFwdThreads = 1024;
 
@@ -234,11 +255,11 @@ __global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nda, Slo
     ptw.put(s_tw, M / 2);
     pph.put(s_ph, M);
     __syncthreads();
-    fft_lds<T, NT>(buf, lpb, M, logM, s_tw, false);
+    fft_lds<T, NT, false>(buf, lpb, M, logM, s_tw, false);
     for (int idx = threadIdx.x; idx < lpb * M; idx += NT) {
         const int l = idx >> logM, u = idx & (M - 1);
         const size_t ra = g0 + (size_t)(2 * l) * M;
-        const vec2<T> F = dct_post<T>(buf + l * M, u, M, s_ph[u]);
+        const vec2<T> F = dct_post<T, false>(buf, l * M, u, M, s_ph[u]);
         t1[ra + u] = F.x;
         t1[ra + M + u] = F.y;
     }
@@ -249,13 +270,15 @@ __global__ __launch_bounds__(kRowsFwdThreads) void spec_rows_fwd(NetDev nda, Slo
 }
 
 // ---- C: two columns per block -------------------------------------------------------------
-// lds: tw [M/2] | ph [M] | den_y [M] | om_y [M] | acol [2][M] | inv [2][M] | work [2][M]
+// lds: tw [M/2, padded] | ph [M] | den_y [M] | om_y [M] | acol [2][M] | inv [2][M] |
+// work [2][M, padded]
 // (inv[h][v] = 1 / (d_x[u0 + h] + d_y[v]), 0 for the dropped (0, 0) term: every term of the
 // column shares these denominators, so each is divided once)
 template <typename T>
 __host__ __device__ inline size_t cols_lds(int M) {
-    return al16(sizeof(vec2<T>) * (M / 2)) + al16(sizeof(vec2<T>) * M) + 2 * al16(sizeof(T) * M) +
-           2 * al16(sizeof(T) * 2 * M) + al16(sizeof(vec2<T>) * 2 * M);
+    return al16(sizeof(vec2<T>) * fpad_n(M / 2)) + al16(sizeof(vec2<T>) * M) +
+           2 * al16(sizeof(T) * M) + 2 * al16(sizeof(T) * 2 * M) +
+           al16(sizeof(vec2<T>) * fpad_n(2 * M));
 }
 
 // C and R2 run 1024-thread blocks when a launch has at most one block per CU (a single slot:
@@ -272,7 +295,7 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nda, SlotArgs sa, SlotLay
     const int M = nd.my, logM = nd.logmy, mx = nd.mx;
     size_t o = 0;
     vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem + o);
-    o += al16(sizeof(vec2<T>) * (M / 2));
+    o += al16(sizeof(vec2<T>) * fpad_n(M / 2));
     vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + o);
     o += al16(sizeof(vec2<T>) * M);
     T *s_den = reinterpret_cast<T *>(smem + o);
@@ -283,7 +306,7 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nda, SlotArgs sa, SlotLay
     o += al16(sizeof(T) * 2 * M);
     T *inv = reinterpret_cast<T *>(smem + o);  // [2][M]
     o += al16(sizeof(T) * 2 * M);
-    vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M]
+    vec2<T> *work = reinterpret_cast<vec2<T> *>(smem + o);  // [2][M], padded
     const int bid = spec_block(nb);
     const int u0 = bid * 2;
     // every global load first: the two columns (as one complex line), the y tables and
@@ -307,20 +330,20 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nda, SlotArgs sa, SlotLay
 #pragma unroll
     for (int q = 0; q < 4; ++q) {  // Makhoul-reordered, bit-reversed
         const int k = threadIdx.x + q * NT;
-        if (k < M) work[brev(mperm(k, M), logM)] = col[q];
+        if (k < M) work[fpad(brev(mperm(k, M), logM))] = col[q];
     }
-    ptw.put(s_tw, M / 2);
+    ptw.put_pad(s_tw, M / 2);
     pph.put(s_ph, M);
     pden.put(s_den, M);
     pom.put(s_om, M);
     __syncthreads();
-    fft_lds<T, NT>(work, 1, M, logM, s_tw, false);
+    fft_lds<T, NT, true>(work, 1, M, logM, s_tw, false);
     const T norm = (T)(1.0 / ((double)nd.mx * nd.my));
     const T cu0 = u0 ? T(2) : T(1);  // u0 + 1 > 0 always
     const double mm = (double)nd.mx * nd.my;
     double e = 0.0;
     for (int v = threadIdx.x; v < M; v += NT) {
-        const vec2<T> F = dct_post<T>(work, v, M, s_ph[v]);
+        const vec2<T> F = dct_post<T, true>(work, 0, v, M, s_ph[v]);
         const T cv = v ? T(2) : T(1);
         const T a0 = cu0 * cv * norm * F.x, a1 = T(2) * cv * norm * F.y;
         acol[v] = a0;
@@ -349,15 +372,15 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nda, SlotArgs sa, SlotLay
         const T yp = v ? T(0.5) * Y(M - v) : T(0);
         const T yq = v ? T(0.5) * Y(v) : T(0);
         const vec2<T> VX = idct_pre<T>(xp, xq, s_ph[v]), VY = idct_pre<T>(yp, yq, s_ph[v]);
-        work[h * M + brev(v, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
+        work[fpad(h * M + brev(v, logM))] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
     }
     __syncthreads();
-    fft_lds<T, NT>(work, 2, M, logM, s_tw, true);
+    fft_lds<T, NT, true>(work, 2, M, logM, s_tw, true);
     T *bx = reinterpret_cast<T *>(base + L.bx);
     T *by = reinterpret_cast<T *>(base + L.by);
     for (int k = threadIdx.x; k < M; k += NT) {
         const int n = mperm(k, M);
-        const vec2<T> z0 = work[n], z1 = work[M + n];
+        const vec2<T> z0 = work[fpad(n)], z1 = work[fpad(M + n)];
         const T sg = (k & 1) ? T(-1) : T(1);
         *reinterpret_cast<vec2<T> *>(bx + (size_t)k * mx + u0) = cmk<T>(z0.x, z1.x);
         *reinterpret_cast<vec2<T> *>(by + (size_t)k * mx + u0) = cmk<T>(sg * z0.y, sg * z1.y);
@@ -374,18 +397,18 @@ __global__ __launch_bounds__(NT) void spec_cols(NetDev nda, SlotArgs sa, SlotLay
                 const T pq = v ? T(0.5) * P(M - v) : T(0);
                 V2v[h] = idct_pre<T>(pp, pq, s_ph[v]);
             }
-            work[brev(v, logM)] = cmk<T>(V2v[0].x - V2v[1].y, V2v[0].y + V2v[1].x);
+            work[fpad(brev(v, logM))] = cmk<T>(V2v[0].x - V2v[1].y, V2v[0].y + V2v[1].x);
         }
         __syncthreads();
-        fft_lds<T, NT>(work, 1, M, logM, s_tw, true);
+        fft_lds<T, NT, true>(work, 1, M, logM, s_tw, true);
         T *bp = reinterpret_cast<T *>(base + L.bp);
         for (int k = threadIdx.x; k < M; k += NT)
-            *reinterpret_cast<vec2<T> *>(bp + (size_t)k * mx + u0) = work[mperm(k, M)];
+            *reinterpret_cast<vec2<T> *>(bp + (size_t)k * mx + u0) = work[fpad(mperm(k, M))];
     }
 }
 
 // ---- R2 ---------------------------------------------------------------------------------
-// lds: tw [M/2] | ph [M] | stage [nst][2][M] | work [nst][M]
+// lds: tw [M/2, padded] | ph [M] | stage [nst][2][M] | work [nst][M, padded]
 template <typename T, int NT, bool RAG>
 __global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nda, SlotArgs sa, SlotLayout La,
                                                     int want_psi) {
@@ -399,7 +422,7 @@ __global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nda, SlotArgs sa, Slo
     const int nst = want_psi ? 3 : 2;
     size_t o = 0;
     vec2<T> *s_tw = reinterpret_cast<vec2<T> *>(smem + o);
-    o += al16(sizeof(vec2<T>) * (M / 2));
+    o += al16(sizeof(vec2<T>) * fpad_n(M / 2));
     vec2<T> *s_ph = reinterpret_cast<vec2<T> *>(smem + o);
     o += al16(sizeof(vec2<T>) * M);
     T *stage = reinterpret_cast<T *>(smem + o);  // [nst][2][M]
@@ -431,7 +454,7 @@ __global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nda, SlotArgs sa, Slo
             if (idx < nall) stage[idx] = r[q];
         }
     }
-    ptw.put(s_tw, M / 2);
+    ptw.put_pad(s_tw, M / 2);
     pph.put(s_ph, M);
     __syncthreads();
     const int nlines = want_psi ? 3 : 2;
@@ -444,28 +467,28 @@ __global__ __launch_bounds__(NT) void spec_rows_inv(NetDev nda, SlotArgs sa, Slo
         const T yp = u ? T(0.5) * sby[u] : sby[0];
         const T yq = u ? T(0.5) * sby[M - u] : T(0);
         const vec2<T> VX = idct_pre<T>(xp, xq, s_ph[u]), VY = idct_pre<T>(yp, yq, s_ph[u]);
-        work[r * M + brev(u, logM)] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
+        work[fpad(r * M + brev(u, logM))] = cmk<T>(VX.x - VY.y, VX.y + VY.x);
     }
     if (want_psi) {
         for (int u = threadIdx.x; u < M; u += NT) {
             const T *s0 = stage + 4 * M, *s1 = stage + 5 * M;
             const vec2<T> A = idct_pre<T>(u ? T(0.5) * s0[u] : s0[0], u ? T(0.5) * s0[M - u] : T(0), s_ph[u]);
             const vec2<T> B = idct_pre<T>(u ? T(0.5) * s1[u] : s1[0], u ? T(0.5) * s1[M - u] : T(0), s_ph[u]);
-            work[2 * M + brev(u, logM)] = cmk<T>(A.x - B.y, A.y + B.x);
+            work[fpad(2 * M + brev(u, logM))] = cmk<T>(A.x - B.y, A.y + B.x);
         }
     }
     __syncthreads();
-    fft_lds<T, NT>(work, nlines, M, logM, s_tw, true);
+    fft_lds<T, NT, true>(work, nlines, M, logM, s_tw, true);
     vec2<T> *exy = reinterpret_cast<vec2<T> *>(base + L.exy);
     T *psi = reinterpret_cast<T *>(base + L.psi);
     for (int idx = threadIdx.x; idx < 2 * M; idx += NT) {
         const int r = idx >> logM, j = idx & (M - 1);
         const int n = mperm(j, M);
-        const vec2<T> z = work[r * M + n];
+        const vec2<T> z = work[fpad(r * M + n)];
         const size_t oo = (size_t)(k0 + r) * M + j;
         exy[oo] = cmk<T>((j & 1) ? -z.x : z.x, z.y);
         if (want_psi) {
-            const vec2<T> zp = work[2 * M + n];
+            const vec2<T> zp = work[fpad(2 * M + n)];
             psi[oo] = r ? zp.y : zp.x;
         }
     }
@@ -480,8 +503,8 @@ static size_t rows_fwd_lds(const NetDev &nd) {
 }
 template <typename T>
 static size_t rows_inv_lds(const NetDev &nd, int nst) {
-    return al16(sizeof(vec2<T>) * (nd.mx / 2)) + al16(sizeof(vec2<T>) * nd.mx) +
-           al16(sizeof(T) * (size_t)nst * 2 * nd.mx) + sizeof(vec2<T>) * (size_t)nst * nd.mx;
+    return al16(sizeof(vec2<T>) * fpad_n(nd.mx / 2)) + al16(sizeof(vec2<T>) * nd.mx) +
+           al16(sizeof(T) * (size_t)nst * 2 * nd.mx) + sizeof(vec2<T>) * fpad_n((size_t)nst * nd.mx);
 }
 
 // 1024-thread C and R2 blocks while a launch has at most one block per CU, unless the
