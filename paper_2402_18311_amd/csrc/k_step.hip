@@ -48,6 +48,28 @@ __global__ __launch_bounds__(kFinBlock) void eval_finish_kernel(NetDev nda, Slot
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     double gm = 0.0;
     long long ov = 0;
+    if (nwl == 0 && ne == 0 && nov == 0) {
+        // The step's reductions alone (steady state above 1024 cell blocks): three arrays, so
+        // each thread keeps 12 elements of each in flight per round (one round up to 12,288
+        // partials).  The same elements in the same order as the general loop below.
+        constexpr int U = 12;
+        for (int i = threadIdx.x; i < nab; i += U * kFinBlock) {
+            double a[U], b[U], c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = i + u * kFinBlock;
+                a[u] = j < nab ? pa[j] : 0.0;
+                b[u] = j < nab ? pb[j] : 0.0;
+                c[u] = j < ng ? pg[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                v[2] += a[u];
+                v[3] += b[u];
+                gm = fmax(gm, c[u]);
+            }
+        }
+    } else
     for (int i = threadIdx.x; i < nmax; i += 4 * kFinBlock) {
         double a[4][5];
         long long o[4];
