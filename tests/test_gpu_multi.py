@@ -65,7 +65,9 @@ def test_shared_launches_match_each_slot_alone(hy, prec, closing, graph):
     """closing: one netlist takes the closing-reduction step form (as above 262,144 movable
     cells), which puts the whole shared launch in that form; else every slot takes the fused
     step.  graph: the shared launches replay steady blocks from a captured HIP graph (the
-    slots' rebuild intervals make a 24-iteration block), in calls long enough to replay."""
+    slots' rebuild intervals make a 24-iteration block), in calls long enough to replay.
+    The 'small' netlist iterated alone takes the non-temporal sweep, which launches that mix
+    netlists leave out: the same values either way."""
     nets = _NETS32 if prec == 32 else _NETS64
     built = {k: (make(), every) for k, (make, every) in nets.items()}
     stream = hy.OwnStream() if graph else None
@@ -78,6 +80,8 @@ def test_shared_launches_match_each_slot_alone(hy, prec, closing, graph):
                 pl.set_scatter_policy(every, every % 2 == 0)
                 if closing and k == "tiny" and where == "shared":
                     pl.set_tunable(hy.HP_TUNE_FUSED_STEP_PARTS, 0)
+                if k == "small" and where == "alone":  # hinted sweep alone, plain when shared
+                    pl.set_tunable(hy.HP_TUNE_NONTEMPORAL, 1)
                 # two slots of the first netlist, one of every other
                 ss = [pl.new_slot() for _ in range(2 if k == "small" or k == "tiny" else 1)]
                 for j, s in enumerate(ss):
