@@ -560,8 +560,8 @@ __device__ int64_t hpwl_block(const NetDev &nd, int net, const vec2<T> *__restri
 enum { MODE_WA = 0, MODE_HPWL = 1 };
 
 // Bucket b and bucket-local block index of sweep block bx.  Default order: bucket after bucket,
-// each one's blocks remapped so that XCD x (blocks bx with bx % 8 == x) walks one contiguous
-// eighth of it.  Interleaved order: the block-per-net bucket first, then on every XCD the
+// each padded bucket's blocks remapped so that XCD x (blocks bx with bx % 8 == x) walks one
+// contiguous eighth of it.  Interleaved order: the block-per-net bucket first, then on every XCD the
 // blocks of the padded buckets merged by their progress through their eighth (nd.sweep_map),
 // so all buckets sweep the same cell range at the same time.
 __device__ __forceinline__ void sweep_block(const NetDev &nd, const Buckets &bk, int bx, int &b,
@@ -575,7 +575,11 @@ __device__ __forceinline__ void sweep_block(const NetDev &nd, const Buckets &bk,
     }
     b = 0;
     while (b + 1 < bk.n && bx >= bk.blk0[b + 1]) ++b;
-    local = xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
+    // The block-per-net bucket is ordered by decreasing size: its blocks take the nets in grid
+    // order, so that consecutive (widest first) nets go to different XCDs and every XCD gets an
+    // even share of the work; in the padded buckets each XCD takes a contiguous eighth, whose
+    // nets gather a compact cell range.
+    local = bk.G[b] == 0 ? bx - bk.blk0[b] : xcd_remap(bx - bk.blk0[b], bk.nblk[b]);
 }
 
 // This lane's share of the exact HPWL of block-local index `local` of bucket b.
