@@ -188,7 +188,8 @@ BinGeom bin_geom(const hp_shape &s, const hp_die &d) {
     g.nty = d.my / ts;
     g.ntiles = g.ntx * g.nty;
     const int n = std::max(1, s.n_movable);
-    g.sort_cells = 2048 * ((n + 2048 * 512 - 1) / (2048 * 512));
+    // a multiple of 2048 cells, enough that there are at most kMaxSortBlocks blocks
+    g.sort_cells = 2048 * ((n + 2048 * kMaxSortBlocks - 1) / (2048 * kMaxSortBlocks));
     g.sort_blocks = (n + g.sort_cells - 1) / g.sort_cells;
     g.max_chunks = (n + kChunk - 1) / kChunk + g.ntiles;
     return g;

@@ -17,6 +17,8 @@ constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
 // blocks run alone for ~15 us; 768 to 1536 all cut the iteration by 1.4%, and 768 is the best
 // of them on 210 k cells (512 costs the placement pass more than it saves)
 constexpr int kChunk = 768;
+// counting blocks of a grouping at most (rows of the column scan, which covers this many)
+constexpr int kMaxSortBlocks = 512;
 constexpr int kRegroupEvery = 4; // evaluations between rebuilds of the scatter's tile order
 constexpr int kPairNets = 2;     // two-pin nets each lane sweeps (their loads issued together)
 constexpr int kBigHalo = 8;      // movable cells whose charge can span more than kBigHalo + 1

@@ -36,6 +36,7 @@ namespace hp {
 //    which the block places by, and the chunk starts and each chunk's tile and cell range,
 //    which each block writes for its share of the tiles.
 constexpr int kColTiles = 16, kColBands = kBlock / kColTiles, kColRows = 32;
+static_assert(kColBands * kColRows >= kMaxSortBlocks, "the column scan covers every counting block");
 template <bool RAG>
 __global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
     __shared__ int band[kColBands][kColTiles];
