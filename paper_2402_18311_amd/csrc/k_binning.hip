@@ -82,14 +82,17 @@ __global__ __launch_bounds__(kBlock) void bin_colscan_kernel(NetDev nda, SlotArg
     }
 }
 
-// tiles per thread of the placement pass's scan: the tile grid has at most 8192 tiles (the tile
-// side doubles until it does, or reaches the grid's short side, where at most 2048 / 8 remain)
-constexpr int kPlaceRun = 32;
-static_assert(kBlock * kPlaceRun >= 8192, "the placement pass's scan covers every tile");
-template <bool RAG>
-__global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
+// Threads of a placement block, NT: 1024 while a launch has at most two blocks per CU (one slot:
+// one block per counting block, at most kMaxSortBlocks, so its threads take few rounds of
+// cells), 256 for launches over many slots, where smaller blocks interleave better.  Tiles per
+// thread of its scan: the tile grid has at most 8192 tiles (the tile side doubles until it does,
+// or reaches the grid's short side, where at most 2048 / 8 remain).
+template <bool RAG, int NT>
+__global__ __launch_bounds__(NT) void bin_place_kernel(NetDev nda, SlotArgs sa, SlotLayout La) {
+    constexpr int kPlaceRun = 8192 / NT;
+    static_assert(NT * kPlaceRun >= 8192, "the placement pass's scan covers every tile");
     extern __shared__ int place_lds[];  // rank [ntiles], then the tile starts [ntiles]
-    __shared__ int ws[kBlock / 64][2];
+    __shared__ int ws[NT / 64][2];
     char *base = sa.base[blockIdx.y];
     const NetDev &nd = view_nd<RAG>(nda, base);
     const SlotLayout &L = view_L<RAG>(La, base);
@@ -102,12 +105,12 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs 
     // the tile scan: each thread a contiguous run of at most kPlaceRun tiles (ntiles <= 8192),
     // its totals loaded into registers in one round, its (cells, chunks) sums scanned over the
     // block
-    const int per = (T + kBlock - 1) / kBlock;
+    const int per = (T + NT - 1) / NT;
     const int t0 = min(T, (int)threadIdx.x * per), t1 = min(T, t0 + per);
     int v[kPlaceRun];
 #pragma unroll
     for (int k = 0; k < kPlaceRun; ++k) v[k] = (k < per && t0 + k < t1) ? tot[t0 + k] : 0;
-    for (int t = threadIdx.x; t < T; t += kBlock) rank[t] = 0;
+    for (int t = threadIdx.x; t < T; t += NT) rank[t] = 0;
     int sc = 0, sk = 0;
 #pragma unroll
     for (int k = 0; k < kPlaceRun; ++k) {
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs 
         oc += s;
         ok += nck;
     }
-    if (blk == nb - 1 && threadIdx.x == kBlock - 1) cstart[T] = ok;  // the chunk count
+    if (blk == nb - 1 && threadIdx.x == NT - 1) cstart[T] = ok;  // the chunk count
     __syncthreads();
     const int *tile = reinterpret_cast<const int *>(base + L.tile);
     const int *cnt = reinterpret_cast<const int *>(base + L.soff) + (size_t)blk * T;
@@ -159,17 +162,17 @@ __global__ __launch_bounds__(kBlock) void bin_place_kernel(NetDev nda, SlotArgs 
     const int i0 = blk * nd.sort_cells, i1 = min(nd.n_mov, i0 + nd.sort_cells);
     // four cells per thread and round: tiles, then ranks, then offsets, each step's accesses
     // all in flight together (indices clamped in range; only valid cells take a rank)
-    for (int i = i0 + threadIdx.x; i < i1; i += 4 * kBlock) {
+    for (int i = i0 + threadIdx.x; i < i1; i += 4 * NT) {
         int tt[4], r[4], o[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) tt[u] = tile[min(i + u * kBlock, i1 - 1)];
+        for (int u = 0; u < 4; ++u) tt[u] = tile[min(i + u * NT, i1 - 1)];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = i + u * kBlock < i1 ? atomicAdd(&rank[tt[u]], 1) : 0;
+        for (int u = 0; u < 4; ++u) r[u] = i + u * NT < i1 ? atomicAdd(&rank[tt[u]], 1) : 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) o[u] = hs[tt[u]] + cnt[tt[u]];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (i + u * kBlock < i1) sorted[o[u] + r[u]] = i + u * kBlock;
+            if (i + u * NT < i1) sorted[o[u] + r[u]] = i + u * NT;
     }
 }
 
@@ -197,8 +200,12 @@ hipError_t launch_regroup_tail(const NetDev &nd, const SlotArgs &sa, const SlotL
               dim3(kBlock), 0, st, nd, sa, L);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_place_kernel", bin_place_kernel<false>, dim3(nd.sort_blocks, sa.n), dim3(kBlock),
-              scatter_place_lds(nd), st, nd, sa, L);
+    if ((size_t)nd.sort_blocks * sa.n <= 2 * (size_t)nd.n_cu)
+        HP_LAUNCH("bin_place_kernel", (bin_place_kernel<false, 1024>), dim3(nd.sort_blocks, sa.n),
+                  dim3(1024), scatter_place_lds(nd), st, nd, sa, L);
+    else
+        HP_LAUNCH("bin_place_kernel", (bin_place_kernel<false, kBlock>), dim3(nd.sort_blocks, sa.n),
+                  dim3(kBlock), scatter_place_lds(nd), st, nd, sa, L);
     e = hipGetLastError();
     if (e != hipSuccess || !accum) return e;
     if (records)
@@ -221,7 +228,7 @@ hipError_t rag_regroup_tail(const SlotArgs &sa, int colscan_x, int place_x, int 
               0, st, nd0, sa, L0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    HP_LAUNCH("bin_place_kernel", bin_place_kernel<true>, dim3(place_x, sa.n), dim3(kBlock),
+    HP_LAUNCH("bin_place_kernel", (bin_place_kernel<true, kBlock>), dim3(place_x, sa.n), dim3(kBlock),
               place_lds, st, nd0, sa, L0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -429,6 +429,32 @@ def test_graph_block_follows_launch_settings(hy, orc):
     pl.close()
 
 
+def test_placement_widths_are_bit_identical(hy, orc):
+    """The grouping's placement pass runs 1024-thread blocks in a launch with at most two
+    blocks per CU and 256-thread blocks in a larger one.  600 k cells make 293 counting
+    blocks: two slots iterated in one call take the narrow blocks, one slot alone the wide
+    ones, and a slot of each, from the same start, stays bit-identical (every evaluation
+    rebuilds the grouping)."""
+    nl = netgen.make_small(600_000, 630_000, 128, seed=11, n_fixed=40)
+    pl = hy.Placer(nl, precision=32)
+    pl.set_scatter_policy(1, False)
+    gamma = 4 * nl.bin_w
+    a, b, c = pl.new_slot(), pl.new_slot(), pl.new_slot()
+    for s in (a, b, c):
+        pl.set_positions(s, nl.x0, nl.y0)
+        pl.set_schedule(s, 1e-4, 4.0, 200)
+    try:
+        for chunk in (1, 4, 7):
+            pl.iterate([a, b], gamma, chunk, hpwl=True)
+            pl.iterate(c, gamma, chunk, hpwl=True)
+            xa, ya = pl.positions(a)
+            xc, yc = pl.positions(c)
+            assert np.array_equal(xa, xc) and np.array_equal(ya, yc), chunk
+            assert pl.hpwl(a)[0] == pl.hpwl(c)[0]
+    finally:
+        pl.close()
+
+
 @pytest.mark.parametrize("case,prec", [("tiny", 64), ("small", 32)])
 def test_iterate_hpwl_last_matches_every(hy, orc, case, prec):
     """HPWL after the last iteration only: the same placement and the same final HPWL as the
